@@ -1,0 +1,189 @@
+/*
+ * swe_nh.h -- C ABI of the MI355X (gfx950) implementation of the per-time-step
+ * hot path of the locally adaptive non-hydrostatic shallow water model of
+ * Firdaus & Behrens ("Locally Adaptive Non-Hydrostatic Shallow Water
+ * Extension for Moving Bottom-Generated Waves").
+ *
+ * One step (Sec. 3 and Sec. 5 of the paper):
+ *   1. hydrostatic predictor: Heun (Eqs. 8-9) over a second-order
+ *      finite-volume operator with the Rusanov flux (Sec. 3.1), giving
+ *      Q~ = (h~, hu~, [hv~,] hw~);
+ *   2. criterion on Q~ against k_nh and enlargement of the marked area
+ *      (Sec. 5.1, 5.2), then compaction of the marked cells;
+ *   3. assembly of the elliptic system of Eqs. 12-17 on the marked cells
+ *      (zero Dirichlet data for the non-hydrostatic pressure outside them)
+ *      and its solution;
+ *   4. projection of hu (and hv) and hw with Eqs. 10-11; h = h~ (no mass
+ *      correction, Sec. 3.2).
+ *
+ * Memory: every array argument is a DEVICE pointer to contiguous FP64 (or
+ * uint8 for masks) memory owned by the caller, structure-of-arrays, x
+ * fastest; 2D arrays are [ny][nx].  The library owns no device memory: all
+ * scratch lives in a caller-provided workspace of swe_nh_workspace_bytes().
+ * Host pointers are marked "host".
+ *
+ * Streams and asynchrony: every call is enqueued on the stream given to
+ * swe_nh_init and returns without waiting, except the calls documented as
+ * synchronising.  Argument errors are returned immediately.  Numerical
+ * failures (dry cells, non-finite state, no convergence) are recorded on the
+ * device and returned by swe_nh_sync_stats().
+ *
+ * Errors: no exception crosses this interface; every call returns a
+ * swe_nh_status.  swe_nh_last_error() gives a message for the last failure of
+ * a context.  A context is not re-entrant: concurrent calls on one context
+ * are not allowed.
+ */
+#ifndef SWE_NH_H
+#define SWE_NH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SWE_NH_OK = 0,
+  SWE_NH_EINVAL = -1,   /* bad argument or configuration */
+  SWE_NH_ENOCONV = -2,  /* elliptic solve did not reach tol within max_iter */
+  SWE_NH_EDRY = -3,     /* a cell or reconstructed face depth <= 0 */
+  SWE_NH_ENAN = -4,     /* non-finite state on entry to a step */
+  SWE_NH_EHIP = -5,     /* HIP runtime error */
+  SWE_NH_ENOMEM = -6    /* workspace too small */
+} swe_nh_status;
+
+/* Adaptivity criteria of Sec. 5.1 (indicator > k_nh marks a cell), plus the
+ * global model (every cell) and the pure hydrostatic model (no cell).
+ * In 2D the indicators are |grad eta|, |(u, v)|, the Frobenius norm of
+ * grad(u, v) and |grad w|. */
+typedef enum {
+  SWE_NH_CRIT_ETA_D = 0,
+  SWE_NH_CRIT_ETA_X = 1,
+  SWE_NH_CRIT_U = 2,
+  SWE_NH_CRIT_U_X = 3,
+  SWE_NH_CRIT_W = 4,
+  SWE_NH_CRIT_W_X = 5,
+  SWE_NH_CRIT_GLOBAL = 6,
+  SWE_NH_CRIT_NONE = 7
+} swe_nh_criterion;
+
+/* Moving rigid body carried by the bottom: d(x, y, t) = d_s - B(x - X(t), y - y0),
+ * X(t) = x0 + dir * s(t).  Shapes: the quartic slide of Eq. 20 (amp = H_s,
+ * len = L_s, on |x - X| < L_s / 2) or a Gaussian mound amp exp(-r^2 / len^2).
+ * Laws s(t): fixed; constant velocity q[0]; sinusoidal ramp
+ * (q[0] / 2)(1 - cos(pi t / q[1])) then q[0]; the accelerate / coast /
+ * decelerate law of Eq. 21 with q = (a0, u_t, t1, t2, t3). */
+enum { SWE_NH_BODY_NONE = 0, SWE_NH_BODY_QUARTIC = 1, SWE_NH_BODY_GAUSS = 2 };
+enum { SWE_NH_LAW_FIXED = 0, SWE_NH_LAW_CONST_VEL = 1, SWE_NH_LAW_SIN_RAMP = 2,
+       SWE_NH_LAW_PIECEWISE = 3 };
+
+typedef struct {
+  int32_t kind;
+  int32_t law;
+  double amp, len, x0, y0, dir;
+  double q[5];
+} swe_nh_body;
+
+typedef struct {
+  int32_t dim;              /* 1 or 2 */
+  int32_t nx, ny;           /* 2D grid; ny ignored in 1D */
+  int32_t batch;            /* 1D: number of independent channels (>= 1) */
+  const int64_t* offsets;   /* host [batch + 1]: channel c owns packed cells
+                               offsets[c] .. offsets[c+1]-1; NULL when batch == 1
+                               (then the single channel has nx cells) */
+  double dx, dy;            /* cell sizes (m) */
+  double g, rho;            /* 9.81, 1000 */
+  double cfl;               /* > 0: dt = cfl dx / max(|u| + sqrt(g h)) per channel
+                               (2D: cfl / max(lx/dx + ly/dy)); <= 0: dt = dt_fixed */
+  double dt_fixed;
+  int32_t crit;             /* swe_nh_criterion */
+  double k_nh;              /* threshold, paper value 1e-3 */
+  int32_t enlarge;          /* cells added on each side of the marked area (paper: 1) */
+  int32_t first_global;     /* |w| and |w_x|: global model on the first step (Sec. 5.1.2) */
+  int32_t precision;        /* 0: FP64 solve; 1: FP32 inner solve + FP64 residual refinement */
+  double tol;               /* ||b - A p||_2 <= tol ||b||_2 (2D PCG, and 1D refinement) */
+  int32_t max_iter;         /* PCG iterations (2D) or refinement sweeps (precision 1) */
+  int32_t warm;             /* 2D: 0 zero guess, 1 previous p (the p array on entry) */
+  const double* depth_static;  /* device [cells]: static depth d_s */
+  const swe_nh_body* bodies;   /* host [batch] (1D) or [1] (2D) */
+} swe_nh_config;
+
+typedef struct {
+  int64_t n_active;         /* cells in the non-hydrostatic area of the last step */
+  int32_t iters;            /* PCG iterations (2D) / refinement sweeps of the last step */
+  int32_t status;           /* swe_nh_status of the last step(s) (first failure wins) */
+  double rel_res;           /* ||b - A p|| / ||b|| of the last solve (when computed) */
+  double dt;                /* time step of the last step (channel 0) */
+  double t;                 /* time after the last step (channel 0) */
+  int64_t steps;            /* steps taken since init */
+} swe_nh_stats;
+
+typedef struct swe_nh_ctx swe_nh_ctx;
+
+/* Bytes of device workspace needed for cfg (0 on invalid cfg). */
+size_t swe_nh_workspace_bytes(const swe_nh_config* cfg);
+
+/* Validate cfg, carve the caller's device workspace (>= workspace_bytes,
+ * 256-byte aligned), upload channel tables and set t = 0.  stream is a
+ * hipStream_t (NULL = the default stream).  The workspace must outlive the
+ * context.  Returns SWE_NH_EINVAL / SWE_NH_ENOMEM / SWE_NH_EHIP on failure. */
+int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t workspace_bytes, void* stream,
+                swe_nh_ctx** out);
+
+void swe_nh_destroy(swe_nh_ctx* ctx);
+const char* swe_nh_last_error(const swe_nh_ctx* ctx);
+
+/* Set / read the model time of every channel (host arrays [batch]; 2D: [1]).
+ * swe_nh_get_time synchronises the stream. */
+int swe_nh_set_time(swe_nh_ctx* ctx, const double* t_host);
+int swe_nh_get_time(swe_nh_ctx* ctx, double* t_host);
+
+/* Advance nsteps full steps in place: h, hu, hw (and hv in 2D; must be NULL
+ * in 1D) hold Q^n on entry and Q^{n+1} on return; p receives the NH
+ * pressure of the last step (0 outside the NH area) and, in 2D with
+ * warm = 1, is the initial guess.  mask (may be NULL) receives the NH area of
+ * the last step.  The step sequence is captured once into a hipGraph per
+ * distinct argument set and replayed. */
+int swe_nh_step(swe_nh_ctx* ctx, double* h, double* hu, double* hv, double* hw, double* p,
+                uint8_t* mask, int32_t nsteps);
+
+/* Synchronise the stream and read the statistics of the last step. */
+int swe_nh_sync_stats(swe_nh_ctx* ctx, swe_nh_stats* out);
+
+/* Stage entry points (same kernels as swe_nh_step), for callers that drive
+ * the stages themselves and for parity tests. */
+
+/* Hydrostatic predictor (Sec. 3.1): Q~ from Q^n over [t, t + dt] with the
+ * context's bottom law.  Outputs may not alias inputs. */
+int swe_nh_predict(swe_nh_ctx* ctx, const double* h, const double* hu, const double* hv,
+                   const double* hw, const double* t_host, const double* dt_host, double* ht,
+                   double* mt, double* nt, double* kt);
+
+/* Criterion and enlargement (Sec. 5.1, 5.2) on a predictor state at time t1
+ * (t_host[batch]); first_step selects the global first step of the |w|,
+ * |w_x| criteria.  mask_out: uint8 [cells]; n_active_host: total marked
+ * cells (synchronises when non-NULL). */
+int swe_nh_mask(swe_nh_ctx* ctx, const double* ht, const double* mt, const double* nt,
+                const double* kt, const double* t_host, int32_t first_step, uint8_t* mask_out,
+                int64_t* n_active_host);
+
+/* Elliptic system of Eqs. 12-17 on the cells with mask != 0 for the
+ * predictor state at t1 = t_host with step dt_host, solved for the NH
+ * pressure p (zero elsewhere).  In 2D p_inout is the initial guess when
+ * warm = 1.  iters / rel_res (host, may be NULL) synchronise. */
+int swe_nh_solve_pressure(swe_nh_ctx* ctx, const double* ht, const double* mt, const double* nt,
+                          const double* kt, const uint8_t* mask, const double* t_host,
+                          const double* dt_host, double* p_inout, int32_t* iters_host,
+                          double* rel_res_host);
+
+/* Projection (Eqs. 10-11): hu, hv, hw from the predictor state and p on the
+ * marked cells; unmarked cells copy the predictor values. */
+int swe_nh_correct(swe_nh_ctx* ctx, const double* ht, const double* mt, const double* nt,
+                   const double* kt, const uint8_t* mask, const double* p, const double* t_host,
+                   const double* dt_host, double* m_out, double* n_out, double* k_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

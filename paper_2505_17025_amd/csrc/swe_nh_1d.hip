@@ -1,0 +1,661 @@
+// swe_nh_1d.hip -- 1D kernels of the non-hydrostatic SWE step (gfx950).
+//
+// Layout: all channels packed back to back in one FP64 array per field; a
+// launch tile is TILE consecutive cells of one channel (tile table built on
+// the host).  Kernels never read across a channel end: the two ghost cells
+// on each side are reflections of the channel's own cells.
+//
+//   k_speed1d   max |u| + sqrt(g h) per channel (atomic max on the bit
+//               pattern, exact) and state checks -> dt (Sec. 3.1 CFL rule)
+//   k_pred1d    both Heun stages (Eqs. 8-9) of the hydrostatic FV operator
+//               fused in LDS with a 4-cell halo
+//   k_mask1d    criterion (Sec. 5.1) + enlargement (Sec. 5.2), tile counts
+//   k_scan      exclusive scan of tile counts (single block)
+//   k_compact1d packed list of marked cells (wave ballots)
+//   k_assemble1d / k_correct1d  elliptic system of Eqs. 12-17 and the
+//               projection of Eqs. 10-11 on the packed rows
+#include "swe_nh_common.h"
+#include "swe_nh_kernels.h"
+
+namespace swenh {
+
+// ---------------------------------------------------------------------------
+// wave speed and state check
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict__ h,
+                                                 const double* __restrict__ hu,
+                                                 const double* __restrict__ hw) {
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int end = min(tl.y + TILE, c.n);
+  double s = 0.0;
+  int flags = 0;
+  for (int i = tl.y + threadIdx.x; i < end; i += blockDim.x) {
+    const int64_t gi = c.off + i;
+    const double hh = h[gi], mm = hu[gi], kk = hw[gi];
+    if (!isfinite(hh) || !isfinite(mm) || !isfinite(kk)) {
+      flags |= ST_NAN;
+    } else if (!(hh > 0.0)) {
+      flags |= ST_DRY;
+    } else {
+      s = fmax(s, fabs(mm / hh) + sqrt(P.g * hh));
+    }
+  }
+  s = wave_max(s);
+  __shared__ double red[4];
+  __shared__ int fl;
+  if (threadIdx.x == 0) fl = 0;
+  __syncthreads();
+  if (flags) atomicOr(&fl, flags);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(&P.smax[tl.x], pos_bits(m));
+    if (fl) atomicOr(P.status, fl);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// hydrostatic predictor
+// ---------------------------------------------------------------------------
+struct Flux {
+  double Fh, FmL, FmR, Fk, hL, hR;
+  bool dry;
+};
+
+// Rusanov flux between hydrostatically reconstructed states (Audusse et al.
+// 2004 reconstruction; Rusanov solver as in Sec. 3.1)
+__device__ __forceinline__ Flux rusanov1d(double g, double eL, double mL, double kL, double dL,
+                                          double eR, double mR, double kR, double dR) {
+  Flux f;
+  const double hL = eL + dL, hR = eR + dR;
+  f.dry = !(hL > 0.0) || !(hR > 0.0);
+  const double uL = mL / hL, uR = mR / hR;
+  const double wL = kL / hL, wR = kR / hR;
+  const double db = fmin(dL, dR);
+  const double sL = fmax(0.0, eL + db), sR = fmax(0.0, eR + db);
+  const double lam = fmax(fabs(uL) + sqrt(g * sL), fabs(uR) + sqrt(g * sR));
+  const double qL = sL * uL, qR = sR * uR;
+  const double pL = 0.5 * g * sL * sL, pR = 0.5 * g * sR * sR;
+  f.Fh = 0.5 * (qL + qR) - 0.5 * lam * (sR - sL);
+  const double Fm = 0.5 * (qL * uL + pL + qR * uR + pR) - 0.5 * lam * (qR - qL);
+  f.FmL = Fm + 0.5 * g * (hL * hL - sL * sL);
+  f.FmR = Fm + 0.5 * g * (hR * hR - sR * sR);
+  f.Fk = 0.5 * (qL * wL + qR * wR) - 0.5 * lam * (sR * wR - sL * wL);
+  f.hL = hL;
+  f.hR = hR;
+  return f;
+}
+
+namespace {
+constexpr int HALO = 4;
+constexpr int WIN = TILE + 2 * HALO;
+
+struct PredSmem {
+  double e[WIN], m[WIN], k[WIN], d[WIN];  // working state of the current stage
+  double d1[WIN];                          // depth at the end of the step
+  double Fh[WIN], FmL[WIN], FmR[WIN], Fk[WIN], hL[WIN], hR[WIN];
+  double Lh[TILE + 4], Lm[TILE + 4], Lk[TILE + 4];  // stage-1 operator on tile +- 2
+  double h0[TILE + 4], m0[TILE + 4], k0[TILE + 4];  // Q^n on tile +- 2
+};
+
+// one stage of the FV operator on the window: faces f in [f0, f1) (face f
+// lies between window cells f-1 and f) and cells e in [c0, c1)
+__device__ __forceinline__ void stage_faces(PredSmem& S, double g, int f0, int f1, int lo_cell,
+                                            int hi_cell, int base, int* flags) {
+  for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
+    const int l = f - 1, r = f;
+    const double se_l = minmod(S.e[l] - S.e[l - 1], S.e[l + 1] - S.e[l]);
+    const double sm_l = minmod(S.m[l] - S.m[l - 1], S.m[l + 1] - S.m[l]);
+    const double sk_l = minmod(S.k[l] - S.k[l - 1], S.k[l + 1] - S.k[l]);
+    const double sd_l = minmod(S.d[l] - S.d[l - 1], S.d[l + 1] - S.d[l]);
+    const double se_r = minmod(S.e[r] - S.e[r - 1], S.e[r + 1] - S.e[r]);
+    const double sm_r = minmod(S.m[r] - S.m[r - 1], S.m[r + 1] - S.m[r]);
+    const double sk_r = minmod(S.k[r] - S.k[r - 1], S.k[r + 1] - S.k[r]);
+    const double sd_r = minmod(S.d[r] - S.d[r - 1], S.d[r + 1] - S.d[r]);
+    const Flux F = rusanov1d(g, S.e[l] + 0.5 * se_l, S.m[l] + 0.5 * sm_l, S.k[l] + 0.5 * sk_l,
+                             S.d[l] + 0.5 * sd_l, S.e[r] - 0.5 * se_r, S.m[r] - 0.5 * sm_r,
+                             S.k[r] - 0.5 * sk_r, S.d[r] - 0.5 * sd_r);
+    S.Fh[f] = F.Fh;
+    S.FmL[f] = F.FmL;
+    S.FmR[f] = F.FmR;
+    S.Fk[f] = F.Fk;
+    S.hL[f] = F.hL;
+    S.hR[f] = F.hR;
+    // only faces touching a channel cell of this stage's range count
+    const int il = base + l, ir = base + r;
+    const bool used = (il >= lo_cell && il < hi_cell) || (ir >= lo_cell && ir < hi_cell);
+    if (F.dry && used) *flags |= ST_DRY;
+  }
+}
+
+__device__ __forceinline__ void stage_cell(const PredSmem& S, double g, double idx, int e,
+                                           double& Lh, double& Lm, double& Lk) {
+  const double sd = minmod(S.d[e] - S.d[e - 1], S.d[e + 1] - S.d[e]);
+  Lh = -(S.Fh[e + 1] - S.Fh[e]) * idx;
+  Lm = -(S.FmL[e + 1] - S.FmR[e]) * idx + g * 0.5 * (S.hL[e + 1] + S.hR[e]) * sd * idx;
+  Lk = -(S.Fk[e + 1] - S.Fk[e]) * idx;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_pred1d(K1D P, const double* __restrict__ h,
+                                                const double* __restrict__ hu,
+                                                const double* __restrict__ hw,
+                                                double* __restrict__ ht, double* __restrict__ mt,
+                                                double* __restrict__ kt, const double* t_in,
+                                                const double* dt_in, int dt_from_speed) {
+  __shared__ PredSmem S;
+  __shared__ int sflags;
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int n = c.n, start = tl.y, base = start - HALO;  // window cell e <-> channel cell base+e
+  const int end = min(start + TILE, n);
+  const double t0 = t_in[tl.x];
+  double dt;
+  if (dt_from_speed) {
+    dt = (P.cfl > 0.0) ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[tl.x])
+                       : P.dt_fixed;
+    if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.dt[tl.x] = dt;
+  } else {
+    dt = dt_in[tl.x];
+  }
+  const double t1 = t0 + dt;
+  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t1);
+  const double idx = 1.0 / P.dx;
+  if (threadIdx.x == 0) sflags = 0;
+  int flags = 0;
+
+  // load Q^n on the window with reflected ghosts; depth at both stage times
+  for (int e = threadIdx.x; e < WIN; e += blockDim.x) {
+    const int i = min(base + e, n + HALO - 1);
+    const int s = reflect(i, n);
+    const int64_t gi = c.off + s;
+    const double sg = (s == i) ? 1.0 : -1.0;
+    const double x = (s + 0.5) * P.dx;
+    const double ds = P.ds[gi];
+    const double dA = ds - body_shape(c, x - M0.X, 0.0).B;
+    const double dB = ds - body_shape(c, x - M1.X, 0.0).B;
+    const double hh = h[gi];
+    S.e[e] = hh - dA;
+    S.m[e] = sg * hu[gi];
+    S.k[e] = hw[gi];
+    S.d[e] = dA;
+    S.d1[e] = dB;
+    if (e >= HALO - 2 && e < TILE + HALO + 2) {
+      S.h0[e - (HALO - 2)] = hh;
+      S.m0[e - (HALO - 2)] = S.m[e];
+      S.k0[e - (HALO - 2)] = S.k[e];
+    }
+  }
+  __syncthreads();
+
+  // stage 1 on the channel cells of window [2, WIN-2): faces [2, WIN-1)
+  const int lo1 = max(0, start - 2), hi1 = min(n, start + TILE + 2);
+  stage_faces(S, P.g, 2, WIN - 1, lo1, hi1, base, &flags);
+  __syncthreads();
+  for (int e = 2 + threadIdx.x; e < WIN - 2; e += blockDim.x) {
+    double a, b, q;
+    stage_cell(S, P.g, idx, e, a, b, q);
+    S.Lh[e - 2] = a;
+    S.Lm[e - 2] = b;
+    S.Lk[e - 2] = q;
+  }
+  __syncthreads();
+  // Q* = Q^n + dt L(Q^n, t^n) on channel cells; ghosts re-reflected from Q*
+  for (int e = 2 + threadIdx.x; e < WIN - 2; e += blockDim.x) {
+    const int i = base + e;
+    if (i >= 0 && i < n) {
+      const int j = e - 2;
+      S.e[e] = S.h0[j] + dt * S.Lh[j] - S.d1[e];
+      S.m[e] = S.m0[j] + dt * S.Lm[j];
+      S.k[e] = S.k0[j] + dt * S.Lk[j];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < WIN; e += blockDim.x) {
+    const int i = base + e;
+    if (i < 0 || i >= n) {
+      const int s = reflect(min(i, n + HALO - 1), n);
+      const int es = s - base;
+      double ev = 0.0, mv = 0.0, kv = 0.0;
+      if (es >= 2 && es < WIN - 2) {
+        ev = S.e[es];  // h is even and the ghost depth equals the reflected one
+        mv = -S.m[es];
+        kv = S.k[es];
+      }
+      S.e[e] = ev;
+      S.m[e] = mv;
+      S.k[e] = kv;
+    }
+    S.d[e] = S.d1[e];
+  }
+  __syncthreads();
+
+  // stage 2 on the tile cells: faces [HALO, HALO + TILE + 1)
+  stage_faces(S, P.g, HALO, HALO + TILE + 1, start, end, base, &flags);
+  __syncthreads();
+  for (int e = HALO + threadIdx.x; e < HALO + TILE; e += blockDim.x) {
+    const int i = base + e;
+    if (i >= end) continue;
+    double a, b, q;
+    stage_cell(S, P.g, idx, e, a, b, q);
+    const int j = e - 2;
+    const int64_t gi = c.off + i;
+    ht[gi] = S.h0[j] + 0.5 * dt * (S.Lh[j] + a);
+    mt[gi] = S.m0[j] + 0.5 * dt * (S.Lm[j] + b);
+    kt[gi] = S.k0[j] + 0.5 * dt * (S.Lk[j] + q);
+  }
+  if (flags) atomicOr(&sflags, flags);
+  __syncthreads();
+  if (threadIdx.x == 0 && sflags) atomicOr(P.status, sflags);
+}
+
+// ---------------------------------------------------------------------------
+// criterion, enlargement, tile counts
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int MAXE = 64;  // largest supported enlargement
+
+__device__ __forceinline__ double eta_at(const K1D& P, const Chan& c, const Motion& M,
+                                         const double* ht, int i) {
+  const int s = reflect(i, c.n);
+  const double x = (s + 0.5) * P.dx;
+  return ht[c.off + s] - (P.ds[c.off + s] - body_shape(c, x - M.X, 0.0).B);
+}
+
+// indicator of Sec. 5.1 at channel cell i (central differences, reflected ghosts)
+__device__ double indicator1d(const K1D& P, const Chan& c, const Motion& M, const double* ht,
+                              const double* mt, const double* kt, int i, int crit) {
+  const int n = c.n;
+  const int64_t o = c.off;
+  switch (crit) {
+    case SWE_NH_CRIT_ETA_D: {
+      const double x = (i + 0.5) * P.dx;
+      const double d = P.ds[o + i] - body_shape(c, x - M.X, 0.0).B;
+      return fabs((ht[o + i] - d) / d);
+    }
+    case SWE_NH_CRIT_ETA_X:
+      return fabs((eta_at(P, c, M, ht, i + 1) - eta_at(P, c, M, ht, i - 1)) / (2.0 * P.dx));
+    case SWE_NH_CRIT_U:
+      return fabs(mt[o + i] / ht[o + i]);
+    case SWE_NH_CRIT_U_X: {
+      const int l = reflect(i - 1, n), r = reflect(i + 1, n);
+      const double ul = (l == i - 1 ? 1.0 : -1.0) * mt[o + l] / ht[o + l];
+      const double ur = (r == i + 1 ? 1.0 : -1.0) * mt[o + r] / ht[o + r];
+      return fabs((ur - ul) / (2.0 * P.dx));
+    }
+    case SWE_NH_CRIT_W:
+      return fabs(kt[o + i] / ht[o + i]);
+    default: {
+      const int l = reflect(i - 1, n), r = reflect(i + 1, n);
+      return fabs((kt[o + r] / ht[o + r] - kt[o + l] / ht[o + l]) / (2.0 * P.dx));
+    }
+  }
+}
+}  // namespace
+
+// mode: 0 criterion, 1 every cell, 2 no cell.  When write_state != 0 the
+// step's defaults are written too: h = h~, hu = hu~, hw = hw~ everywhere and
+// p = 0 off the marked area (the projection then overwrites marked cells).
+__global__ void __launch_bounds__(256) k_mask1d(K1D P, const double* __restrict__ ht,
+                                                const double* __restrict__ mt,
+                                                const double* __restrict__ kt,
+                                                const double* t_in, const double* dt_in,
+                                                int mode_override, uint8_t* __restrict__ mask,
+                                                double* h, double* hu, double* hw, double* p,
+                                                int write_state) {
+  __shared__ uint8_t raw[TILE + 2 * MAXE];
+  __shared__ int cnt[4];
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int n = c.n, start = tl.y, end = min(start + TILE, n);
+  const int e = P.enlarge;
+  int mode = mode_override;
+  if (mode < 0) {  // step: decide from the criterion and the step counter
+    const bool wcrit = (P.crit == SWE_NH_CRIT_W || P.crit == SWE_NH_CRIT_W_X);
+    if (P.crit == SWE_NH_CRIT_GLOBAL || (wcrit && P.first_global && *P.step == 0))
+      mode = 1;
+    else if (P.crit == SWE_NH_CRIT_NONE)
+      mode = 2;
+    else
+      mode = 0;
+  }
+  if (mode == 0) {
+    const double t1 = t_in[tl.x] + dt_in[tl.x];
+    const Motion M = body_motion(c, t1);
+    for (int w = threadIdx.x; w < TILE + 2 * e; w += blockDim.x) {
+      const int i = start - e + w;
+      uint8_t r = 0;
+      if (i >= 0 && i < n) r = indicator1d(P, c, M, ht, mt, kt, i, P.crit) > P.k_nh;
+      raw[w] = r;
+    }
+    __syncthreads();
+  }
+  int local = 0;
+  for (int i = start + threadIdx.x; i < end; i += blockDim.x) {
+    uint8_t v;
+    if (mode == 1) {
+      v = 1;
+    } else if (mode == 2) {
+      v = 0;
+    } else {
+      v = 0;
+      const int w0 = i - start;  // raw index of cell i - e
+      for (int j = 0; j <= 2 * e; j++) v |= raw[w0 + j];
+    }
+    const int64_t gi = c.off + i;
+    mask[gi] = v;
+    local += v;
+    if (write_state) {
+      h[gi] = ht[gi];
+      hu[gi] = mt[gi];
+      hw[gi] = kt[gi];
+      if (!v) p[gi] = 0.0;
+    }
+  }
+  local = wave_sum_i(local);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) P.tile_cnt[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+// tile counts of a caller-supplied mask
+__global__ void __launch_bounds__(256) k_count1d(K1D P, const uint8_t* __restrict__ mask) {
+  __shared__ int cnt[4];
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int end = min(tl.y + TILE, c.n);
+  int local = 0;
+  for (int i = tl.y + threadIdx.x; i < end; i += blockDim.x) local += mask[c.off + i] ? 1 : 0;
+  local = wave_sum_i(local);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) P.tile_cnt[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+// exclusive scan of cnt[0..n) into off, total into *total (one block of 1024)
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int* __restrict__ off,
+                                               int n, int* total) {
+  __shared__ int part[1024];
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int b = threadIdx.x * per, e = min(b + per, n);
+  int s = 0;
+  for (int i = b; i < e; i++) s += cnt[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - s;
+  for (int i = b; i < e; i++) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (threadIdx.x == blockDim.x - 1) *total = part[threadIdx.x];
+}
+
+// packed list of marked cells in cell order
+__global__ void __launch_bounds__(256) k_compact1d(K1D P, const uint8_t* __restrict__ mask) {
+  __shared__ int wsum[4];
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int end = min(tl.y + TILE, c.n);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int base = P.tile_off[blockIdx.x];
+  for (int r0 = tl.y; r0 < end; r0 += blockDim.x) {
+    const int i = r0 + threadIdx.x;
+    const bool on = (i < end) && mask[c.off + i];
+    const unsigned long long bal = __ballot(on);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(bal);
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wv; w++) wbase += wsum[w];
+    if (on) {
+      const int k = base + wbase + pre;
+      P.act_cell[k] = (int)(c.off + i);
+      P.act_chan[k] = tl.x;
+    }
+    base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elliptic system on the packed rows
+// ---------------------------------------------------------------------------
+namespace {
+struct CellNH {
+  double D, al, phi;
+};
+struct FaceNH {
+  double K, a, b, qp, fd;
+};
+
+struct Local {
+  const K1D* P;
+  const Chan* c;
+  const double *ht, *mt, *kt;
+  Motion M;
+  double dt, dx;
+
+  __device__ double depth(int s) const {
+    const double x = (s + 0.5) * dx;
+    return P->ds[c->off + s] - body_shape(*c, x - M.X, 0.0).B;
+  }
+  // d_x, 4 + d_x^2 and phi (Eq. 5) at channel cell s (0 <= s < n)
+  __device__ CellNH cell(int s) const {
+    const int n = c->n;
+    const int l = reflect(s - 1, n), r = reflect(s + 1, n);
+    const double dl = depth(l), d0 = depth(s), dr = depth(r);
+    const double D = (dr - dl) / (2.0 * dx);
+    const double dxx = (dr - 2.0 * d0 + dl) / (dx * dx);
+    const int64_t o = c->off;
+    const double ex = ((ht[o + r] - dr) - (ht[o + l] - dl)) / (2.0 * dx);
+    const double hs = ht[o + s];
+    const double u = mt[o + s] / hs;
+    const double x = (s + 0.5) * dx;
+    const BedRate br = bed_rate(M, body_shape(*c, x - M.X, 0.0));
+    CellNH q;
+    q.D = D;
+    q.al = 4.0 + D * D;
+    q.phi = P->rho * hs / q.al * (P->g * D * ex - br.d_tt - 2.0 * u * br.d_xt - u * u * dxx);
+    return q;
+  }
+  // face f between cells f-1 and f (0 <= f <= n), given phi of both sides
+  __device__ FaceNH face(int f, double phil, double phir) const {
+    const int n = c->n;
+    const int l = reflect(f - 1, n), r = reflect(f, n);
+    const int64_t o = c->off;
+    const double hf = 0.5 * (ht[o + l] + ht[o + r]);
+    const double Df = (depth(r) - depth(l)) / dx;
+    const double hx = (ht[o + r] - ht[o + l]) / dx;
+    const double ml = (l == f - 1 ? 1.0 : -1.0) * mt[o + l];
+    const double mr = (r == f ? 1.0 : -1.0) * mt[o + r];
+    const double af = 4.0 + Df * Df;
+    const double s11 = (2.0 * hx - 3.0 * Df) / (2.0 * hf);
+    FaceNH q;
+    q.K = 4.0 * dt * hf / (P->rho * af);
+    q.a = -1.0 / dx + 0.5 * s11;
+    q.b = 1.0 / dx + 0.5 * s11;
+    q.fd = dt / P->rho * (0.5 * (phil + phir)) * Df;
+    q.qp = 0.5 * (ml + mr) + q.fd;
+    return q;
+  }
+};
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_assemble1d(K1D P, const double* __restrict__ ht,
+                                                    const double* __restrict__ mt,
+                                                    const double* __restrict__ kt,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const double* t_in, const double* dt_in,
+                                                    double* __restrict__ dg, double* __restrict__ up,
+                                                    double* __restrict__ rh) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *P.n_act) return;
+  const int gi = P.act_cell[k], ci = P.act_chan[k];
+  const Chan c = P.ch[ci];
+  const int i = (int)(gi - c.off), n = c.n;
+  Local L{&P, &c, ht, mt, kt, body_motion(c, t_in[ci] + dt_in[ci]), dt_in[ci], P.dx};
+  const CellNH cm = L.cell(reflect(i - 1, n)), c0 = L.cell(i), cp = L.cell(reflect(i + 1, n));
+  const FaceNH fl = L.face(i, cm.phi, c0.phi), fr = L.face(i + 1, c0.phi, cp.phi);
+  const double hs = ht[gi];
+  const double s22 = 3.0 * L.dt / (P.rho * hs);
+  const double xx = (i + 0.5) * P.dx;
+  const BedRate br = bed_rate(L.M, body_shape(c, xx - L.M.X, 0.0));
+  const double f2 = -2.0 * br.d_t - 2.0 * kt[gi] / hs - c0.D * mt[gi] / (2.0 * hs) -
+                    L.dt * c0.al * c0.phi / (2.0 * P.rho * hs);
+  dg[k] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
+  up[k] = (i + 1 < n && mask[gi + 1]) ? fr.K * fr.a * fr.b : 0.0;
+  rh[k] = f2 + fl.b * fl.qp + fr.a * fr.qp;
+}
+
+// projection on the packed rows: x = packed pressure
+__global__ void __launch_bounds__(256) k_correct1d(K1D P, const double* __restrict__ ht,
+                                                   const double* __restrict__ mt,
+                                                   const double* __restrict__ kt,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const double* t_in, const double* dt_in,
+                                                   const double* __restrict__ x, double* hu,
+                                                   double* hw, double* p) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *P.n_act) return;
+  const int gi = P.act_cell[k], ci = P.act_chan[k];
+  const Chan c = P.ch[ci];
+  const int i = (int)(gi - c.off), n = c.n;
+  Local L{&P, &c, ht, mt, kt, body_motion(c, t_in[ci] + dt_in[ci]), dt_in[ci], P.dx};
+  const CellNH cm = L.cell(reflect(i - 1, n)), c0 = L.cell(i), cp = L.cell(reflect(i + 1, n));
+  const FaceNH fl = L.face(i, cm.phi, c0.phi), fr = L.face(i + 1, c0.phi, cp.phi);
+  const double pc = x[k];
+  const double pl = (i > 0 && mask[gi - 1]) ? x[k - 1] : 0.0;
+  const double pr = (i + 1 < n && mask[gi + 1]) ? x[k + 1] : 0.0;
+  const double dql = fl.fd - fl.K * (fl.a * pl + fl.b * pc);
+  const double dqr = fr.fd - fr.K * (fr.a * pc + fr.b * pr);
+  const double dm = 0.5 * (dql + dqr);
+  const double Pb = 1.5 * pc - P.rho * c0.D * dm / (4.0 * L.dt) + c0.al * c0.phi / 4.0;
+  hu[gi] = mt[gi] + dm;
+  hw[gi] = kt[gi] + L.dt * Pb / P.rho;
+  if (p) p[gi] = pc;
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double* a, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+// p (packed rows) -> full array
+__global__ void k_gather_packed(const int* __restrict__ act_cell, const int* n_act,
+                                const double* __restrict__ full, double* __restrict__ packed) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < *n_act) packed[k] = full[act_cell[k]];
+}
+__global__ void k_scatter_packed(const int* __restrict__ act_cell, const int* n_act,
+                                 const double* __restrict__ packed, double* __restrict__ full) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < *n_act) full[act_cell[k]] = packed[k];
+}
+
+// end of a step: t += dt, speed reset, step counter
+__global__ void k_advance(K1D P, int nch) {
+  for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+    P.t[c] += P.dt[c];
+    P.smax[c] = 0ull;
+  }
+  if (threadIdx.x == 0) *P.step += 1;
+}
+
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+void launch_speed1d(const K1D& P, const double* h, const double* hu, const double* hw,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_speed1d, dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw);
+}
+void launch_pred1d(const K1D& P, const double* h, const double* hu, const double* hw, double* ht,
+                   double* mt, double* kt, const double* t_in, const double* dt_in,
+                   int dt_from_speed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pred1d, dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw, ht, mt, kt, t_in,
+                     dt_in, dt_from_speed);
+}
+void launch_mask1d(const K1D& P, const double* ht, const double* mt, const double* kt,
+                   const double* t_in, const double* dt_in, int mode_override, uint8_t* mask,
+                   double* h, double* hu, double* hw, double* p, int write_state, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask1d, dim3(P.ntiles), dim3(256), 0, s, P, ht, mt, kt, t_in, dt_in,
+                     mode_override, mask, h, hu, hw, p, write_state);
+}
+void launch_count1d(const K1D& P, const uint8_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_count1d, dim3(P.ntiles), dim3(256), 0, s, P, mask);
+}
+void launch_scan(const int* cnt, int* off, int n, int* total, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, off, n, total);
+}
+void launch_compact1d(const K1D& P, const uint8_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact1d, dim3(P.ntiles), dim3(256), 0, s, P, mask);
+}
+void launch_assemble1d(const K1D& P, int64_t max_rows, const double* ht, const double* mt,
+                       const double* kt, const uint8_t* mask, const double* t_in,
+                       const double* dt_in, double* dg, double* up, double* rh, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble1d, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s, P, ht, mt,
+                     kt, mask, t_in, dt_in, dg, up, rh);
+}
+void launch_correct1d(const K1D& P, int64_t max_rows, const double* ht, const double* mt,
+                      const double* kt, const uint8_t* mask, const double* t_in,
+                      const double* dt_in, const double* x, double* hu, double* hw, double* p,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_correct1d, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s, P, ht, mt,
+                     kt, mask, t_in, dt_in, x, hu, hw, p);
+}
+void launch_advance(const K1D& P, int nch, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, P, nch);
+}
+void launch_fill(double* a, int64_t n, double v, hipStream_t s) {
+  int b = blocks_for(n, 256);
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_fill_f64, dim3(b), dim3(256), 0, s, a, n, v);
+}
+__global__ void k_fill_i32(int* a, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+void launch_fill_i32(int* a, int64_t n, int v, hipStream_t s) {
+  int b = blocks_for(n, 256);
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_fill_i32, dim3(b), dim3(256), 0, s, a, n, v);
+}
+void launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
+  int g = blocks_for(n, 256);
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_copy_f64, dim3(g), dim3(256), 0, s, a, b, n);
+}
+void launch_gather_packed(const int* act_cell, const int* n_act, int64_t max_rows,
+                          const double* full, double* packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_packed, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s, act_cell,
+                     n_act, full, packed);
+}
+void launch_scatter_packed(const int* act_cell, const int* n_act, int64_t max_rows,
+                           const double* packed, double* full, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_packed, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s,
+                     act_cell, n_act, packed, full);
+}
+
+}  // namespace swenh

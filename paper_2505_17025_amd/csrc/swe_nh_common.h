@@ -1,0 +1,157 @@
+// swe_nh_common.h -- device-side types and helpers shared by the HIP kernels
+// of the non-hydrostatic SWE hot path (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swe_nh.h"
+
+namespace swenh {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// status bits accumulated on the device during a step
+enum : int32_t { ST_DRY = 1, ST_NAN = 2, ST_NOCONV = 4 };
+
+// one independent 1D channel (or the single 2D domain)
+struct Chan {
+  int64_t off;      // first packed cell
+  int32_t n;        // cells
+  int32_t kind;     // body shape
+  int32_t law;      // body travel law
+  int32_t pad;
+  double amp, len, x0, y0, dir;
+  double q[5];
+};
+
+// position, velocity and acceleration of the body centre along x
+struct Motion {
+  double X, V, A;
+};
+
+__device__ __forceinline__ Motion body_motion(const Chan& c, double t) {
+  double s = 0.0, v = 0.0, a = 0.0;
+  switch (c.law) {
+    case SWE_NH_LAW_CONST_VEL:
+      s = c.q[0] * t;
+      v = c.q[0];
+      break;
+    case SWE_NH_LAW_SIN_RAMP: {
+      // ramp of length q1 over the distance q0, half a cosine period
+      const double L = c.q[0], T = c.q[1];
+      if (t <= T) {
+        const double w = kPi / T;
+        double sn, cs;
+        sincos(w * t, &sn, &cs);
+        s = 0.5 * L * (1.0 - cs);
+        v = 0.5 * L * w * sn;
+        a = 0.5 * L * w * w * cs;
+      } else {
+        s = L;
+      }
+    } break;
+    case SWE_NH_LAW_PIECEWISE: {
+      // Eq. 21: accelerate (a0) to t1, coast at u_t to t2, decelerate to t3
+      const double a0 = c.q[0], ut = c.q[1], t1 = c.q[2], t2 = c.q[3], t3 = c.q[4];
+      const double s1 = 0.5 * a0 * t1 * t1;
+      if (t <= t1) {
+        s = 0.5 * a0 * t * t;
+        v = a0 * t;
+        a = a0;
+      } else if (t <= t2) {
+        s = s1 + ut * (t - t1);
+        v = ut;
+      } else if (t <= t3) {
+        const double r = t - t2;
+        s = s1 + ut * (t - t1) - 0.5 * a0 * r * r;
+        v = ut - a0 * r;
+        a = -a0;
+      } else {
+        const double r = t3 - t2;
+        s = s1 + ut * (t3 - t1) - 0.5 * a0 * r * r;
+      }
+    } break;
+    default:
+      break;
+  }
+  Motion m;
+  m.X = c.x0 + c.dir * s;
+  m.V = c.dir * v;
+  m.A = c.dir * a;
+  return m;
+}
+
+// body thickness B at (xi, zeta) relative to its centre, with dB/dxi,
+// d2B/dxi2 and d2B/dxi dzeta
+struct Shape {
+  double B, Bx, Bxx, Bxy;
+};
+
+__device__ __forceinline__ Shape body_shape(const Chan& c, double xi, double zeta) {
+  Shape s{0.0, 0.0, 0.0, 0.0};
+  if (c.kind == SWE_NH_BODY_QUARTIC) {
+    // Eq. 20 with z = 2 xi / L: B = H (1 - z^4) on |z| < 1
+    const double r = 2.0 / c.len;
+    const double z = xi * r;
+    if (fabs(xi) < 0.5 * c.len) {
+      const double z2 = z * z;
+      s.B = c.amp * (1.0 - z2 * z2);
+      s.Bx = -4.0 * c.amp * r * z2 * z;
+      s.Bxx = -12.0 * c.amp * r * r * z2;
+    }
+  } else if (c.kind == SWE_NH_BODY_GAUSS) {
+    const double iw2 = 1.0 / (c.len * c.len);
+    const double e = c.amp * exp(-(xi * xi + zeta * zeta) * iw2);
+    s.B = e;
+    s.Bx = -2.0 * xi * iw2 * e;
+    s.Bxx = (4.0 * xi * xi * iw2 * iw2 - 2.0 * iw2) * e;
+    s.Bxy = 4.0 * xi * zeta * iw2 * iw2 * e;
+  }
+  return s;
+}
+
+// time derivatives of the moving bottom d = d_s - B(x - X(t), y - y0)
+struct BedRate {
+  double d_t, d_tt, d_xt, d_yt;
+};
+
+__device__ __forceinline__ BedRate bed_rate(const Motion& m, const Shape& s) {
+  BedRate r;
+  r.d_t = m.V * s.Bx;
+  r.d_tt = m.A * s.Bx - m.V * m.V * s.Bxx;
+  r.d_xt = m.V * s.Bxx;
+  r.d_yt = m.V * s.Bxy;
+  return r;
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+// reflect a channel-local cell index into [0, n)
+__device__ __forceinline__ int reflect(int i, int n) {
+  return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+}
+
+// order-preserving bit pattern of a non-negative double (for atomicMax)
+__device__ __forceinline__ unsigned long long pos_bits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+
+// wave64 reductions
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace swenh

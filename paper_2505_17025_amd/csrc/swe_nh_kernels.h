@@ -1,0 +1,96 @@
+// swe_nh_kernels.h -- kernel parameter blocks and host-side launchers shared
+// between the kernel translation units and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swe_nh_common.h"
+
+namespace swenh {
+
+constexpr int TILE = 512;       // cells per block in the 1D stencil kernels
+constexpr int TRI_ROWS = 1024;  // rows per block in the tridiagonal solver
+constexpr int TRI_MAX_LEVELS = 6;
+
+// parameter block of the 1D kernels (passed by value)
+struct K1D {
+  const Chan* ch;          // [batch]
+  const int2* tiles;       // [ntiles] (channel, first cell)
+  const int* first_tile;   // [batch]
+  const double* ds;        // static depth [cells]
+  double dx, g, rho, cfl, dt_fixed, k_nh;
+  int crit, enlarge, first_global, ntiles;
+  double* t;               // [batch] time at the start of the step
+  double* dt;              // [batch] step of the current step
+  unsigned long long* smax;  // [batch] bit pattern of the max wave speed
+  int* status;             // ST_* bits
+  int* step;               // steps taken
+  int* tile_cnt;           // [ntiles]
+  int* tile_off;           // [ntiles]
+  int* n_act;              // marked cells
+  int* act_cell;           // [cells] packed row -> global cell
+  int* act_chan;           // [cells] packed row -> channel
+};
+
+// ---- 1D stencil / mask / projection ----
+void launch_speed1d(const K1D& P, const double* h, const double* hu, const double* hw,
+                    hipStream_t s);
+void launch_pred1d(const K1D& P, const double* h, const double* hu, const double* hw, double* ht,
+                   double* mt, double* kt, const double* t_in, const double* dt_in,
+                   int dt_from_speed, hipStream_t s);
+void launch_mask1d(const K1D& P, const double* ht, const double* mt, const double* kt,
+                   const double* t_in, const double* dt_in, int mode_override, uint8_t* mask,
+                   double* h, double* hu, double* hw, double* p, int write_state, hipStream_t s);
+void launch_count1d(const K1D& P, const uint8_t* mask, hipStream_t s);
+void launch_scan(const int* cnt, int* off, int n, int* total, hipStream_t s);
+void launch_compact1d(const K1D& P, const uint8_t* mask, hipStream_t s);
+void launch_assemble1d(const K1D& P, int64_t max_rows, const double* ht, const double* mt,
+                       const double* kt, const uint8_t* mask, const double* t_in,
+                       const double* dt_in, double* dg, double* up, double* rh, hipStream_t s);
+void launch_correct1d(const K1D& P, int64_t max_rows, const double* ht, const double* mt,
+                      const double* kt, const uint8_t* mask, const double* t_in,
+                      const double* dt_in, const double* x, double* hu, double* hw, double* p,
+                      hipStream_t s);
+void launch_advance(const K1D& P, int nch, hipStream_t s);
+void launch_fill(double* a, int64_t n, double v, hipStream_t s);
+void launch_fill_i32(int* a, int64_t n, int v, hipStream_t s);
+void launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
+void launch_gather_packed(const int* act_cell, const int* n_act, int64_t max_rows,
+                          const double* full, double* packed, hipStream_t s);
+void launch_scatter_packed(const int* act_cell, const int* n_act, int64_t max_rows,
+                           const double* packed, double* full, hipStream_t s);
+
+// ---- tridiagonal solver over a packed symmetric tridiagonal system ----
+// level l has n_l rows (device count); rows l+1 = 2 * ceil(n_l / TRI_ROWS)
+template <typename R>
+struct TriLevels {
+  int nlev;                          // number of levels (>= 1)
+  int64_t nmax[TRI_MAX_LEVELS];      // host bound on the rows of each level
+  R* dg[TRI_MAX_LEVELS];
+  R* up[TRI_MAX_LEVELS];
+  R* rh[TRI_MAX_LEVELS];
+  R* x[TRI_MAX_LEVELS];
+  int* n;                            // device [TRI_MAX_LEVELS]; n[0] is the caller's count
+};
+// solves level 0 (dg[0], up[0], rh[0], count *n0) into x[0]; conv (may be
+// NULL): skip everything when *conv != 0
+template <typename R>
+void launch_tri_solve(const TriLevels<R>& T, const int* n0, const int* conv, hipStream_t s);
+
+// ---- FP64 residual / FP32 refinement of the packed 1D system ----
+void launch_resid1d(const double* dg, const double* up, const double* rh, const double* x,
+                    const int* n, int64_t max_rows, float* r32, double* part, int with_b,
+                    double* part_b, const int* conv, hipStream_t s);
+void launch_resid_final(const double* part, const double* part_b, int nparts, int sweep,
+                        double tol, double* norms /*[0]=rr,[1]=bb*/, double* rel, int* iters,
+                        int* conv, int is_first, hipStream_t s);
+void launch_refine_update(const float* e, double* x, const int* n, int64_t max_rows, int first,
+                          const int* conv, hipStream_t s);
+void launch_cast_sys(const double* dg, const double* up, const double* rh, const int* n,
+                     int64_t max_rows, float* dg32, float* up32, float* rh32, hipStream_t s);
+void launch_flag_noconv(const int* conv, int* status, hipStream_t s);
+
+int resid_blocks(int64_t max_rows);
+
+}  // namespace swenh

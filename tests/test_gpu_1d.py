@@ -1,0 +1,290 @@
+"""GPU parity of the 1D HIP path against the FP64 oracle (through the C ABI).
+
+Stage tests feed both sides identical inputs; whole-step tests compare the
+state after several steps.  Bar: relative L2 error per field <= 1e-10 in
+FP64 (<= 1e-6 with the FP32 inner solve and FP64 refinement); masks and
+active counts bit-exact."""
+import numpy as np
+import pytest
+
+import oracle as O
+import swe_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17025_amd import swe_nh
+    return swe_nh
+
+
+DEV = "cuda:0"
+
+
+def dt(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(g, r):
+    g = g.detach().cpu().numpy() if hasattr(g, "detach") else np.asarray(g)
+    return np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300)
+
+
+def ens_small(lengths, seed=5):
+    rng = np.random.default_rng(seed)
+    chans = []
+    for j, n in enumerate(lengths):
+        c = S.random_case_1d(int(n), seed=seed * 100 + j, dx=0.05,
+                             body=S.Body(kind=S.BODY_QUARTIC, law=S.LAW_SIN_RAMP,
+                                         amp=float(rng.uniform(0.02, 0.08)),
+                                         length=float(rng.uniform(0.5, 2.0)),
+                                         x0=float(rng.uniform(0.2, 0.8)) * n * 0.05, dir=0.96,
+                                         q=(1.0, 0.7, 0, 0, 0)))
+        chans.append(c)
+    return S.Ensemble(chans)
+
+
+LENGTHS = [4, 5, 513, 1030, 2047, 3000]
+
+
+# ------------------------------------------------------------- stages ----
+
+def test_predictor_stage_parity(B):
+    ens = ens_small(LENGTHS)
+    ctx = B.context_1d(ens, crit=S.CRIT_GLOBAL)
+    ph = O.phys_struct()
+    t0 = [0.05 * (j + 1) for j in range(len(LENGTHS))]
+    dts = [2e-3 * (1 + 0.1 * j) for j in range(len(LENGTHS))]
+    N = int(ens.offsets[-1])
+    out = [torch.empty(N, dtype=torch.float64, device=DEV) for _ in range(3)]
+    ctx.predict(dt(ens.packed("h")), dt(ens.packed("hu")), None, dt(ens.packed("hw")), t0, dts,
+                out[0], out[1], None, out[2])
+    st = ctx.sync_stats()
+    assert st["status"] == 0
+    o = ens.offsets
+    for j, c in enumerate(ens.channels):
+        ref = O.predict_1d(c.ds, c.dx, c.body, ph, t0[j], dts[j], c.h, c.hu, c.hw)
+        for g, r in zip(out, ref):
+            assert rel(g[o[j]:o[j + 1]], r) <= 1e-13
+
+
+def _safe_knh(ind, k):
+    """move the threshold off any indicator value (decisions must not hinge on rounding)"""
+    while np.min(np.abs(ind - k)) <= 1e-9 * k:
+        k *= 1.0 + 1e-6
+    return k
+
+
+@pytest.mark.parametrize("crit", range(8))
+@pytest.mark.parametrize("e", [0, 1, 3])
+def test_mask_stage_bit_exact(B, crit, e):
+    ens = ens_small(LENGTHS, seed=7)
+    t1 = [0.3 + 0.01 * j for j in range(len(LENGTHS))]
+    k_nh = {0: 2e-2, 1: 0.05, 2: 2e-2, 3: 0.2, 4: 5e-3, 5: 5e-3}.get(crit, 1e-3)
+    if crit < 6:
+        inds = np.concatenate([O.indicator_1d(c.ds, c.dx, c.body, O.phys_struct(crit=crit), t1[j],
+                                              c.h, c.hu, c.hw) for j, c in enumerate(ens.channels)])
+        k_nh = _safe_knh(inds, k_nh)
+    ctx = B.context_1d(ens, crit=crit, k_nh=k_nh, enlarge=e)
+    N = int(ens.offsets[-1])
+    mask = torch.zeros(N, dtype=torch.uint8, device=DEV)
+    na = ctx.mask(dt(ens.packed("h")), dt(ens.packed("hu")), None, dt(ens.packed("hw")), t1, 0, mask)
+    ref = np.concatenate([O.mask_1d(c.ds, c.dx, c.body, O.phys_struct(crit=crit, k_nh=k_nh, enlarge=e),
+                                    t1[j], c.h, c.hu, c.hw)[0] for j, c in enumerate(ens.channels)])
+    assert np.array_equal(mask.cpu().numpy(), ref)
+    assert na == int(ref.sum())
+    if crit < 6:
+        assert 0 < na < N
+
+
+def _random_mask(lengths, seed, frac=0.6):
+    rng = np.random.default_rng(seed)
+    m = (rng.random(int(np.sum(lengths))) < frac).astype(np.uint8)
+    # long runs that span several solver blocks, and runs touching channel ends
+    m[100:2900] = 1
+    m[0] = 1
+    return m
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pressure_and_projection_stage_parity(B, precision):
+    lengths = [4, 517, 1500, 6000, 2200]
+    ens = ens_small(lengths, seed=9)
+    mask = _random_mask(lengths, 4)
+    mask[int(ens.offsets[3]) + 10:int(ens.offsets[3]) + 5000] = 1  # one run over ~5 blocks
+    N = int(ens.offsets[-1])
+    t0 = [0.2 + 0.01 * j for j in range(len(lengths))]
+    dts = [4e-3] * len(lengths)
+    ctx = B.context_1d(ens, crit=S.CRIT_ETA_D, precision=precision, tol=1e-12, max_iter=8)
+    h, hu, hw = dt(ens.packed("h")), dt(ens.packed("hu")), dt(ens.packed("hw"))
+    mk = torch.tensor(mask, device=DEV)
+    p = torch.full((N,), 7.0, dtype=torch.float64, device=DEV)
+    it, rr = ctx.solve_pressure(h, hu, None, hw, mk, t0, dts, p)
+    st = ctx.sync_stats()
+    assert st["status"] == 0
+    ph = O.phys_struct()
+    o = ens.offsets
+    pref, mref, kref = [], [], []
+    for j, c in enumerate(ens.channels):
+        mj = mask[o[j]:o[j + 1]]
+        t1 = t0[j] + dts[j]
+        dg, up, rh = O.nh_system_1d(c.ds, c.dx, c.body, ph, t1, dts[j], c.h, c.hu, c.hw, mj)
+        pj = O.tridiag_solve(dg, up, rh)
+        pref.append(pj)
+        mo, ko = O.nh_correct_1d(c.ds, c.dx, c.body, ph, t1, dts[j], c.h, c.hu, c.hw, mj, pj)
+        mref.append(mo)
+        kref.append(ko)
+    pref, mref, kref = map(np.concatenate, (pref, mref, kref))
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert rel(p, pref) <= tol
+    assert np.all(p.cpu().numpy()[mask == 0] == 0.0)
+    assert rr <= (1e-12 if precision == 1 else 1e-11)
+    if precision == 1:
+        assert 1 <= it <= 8
+    # projection from the oracle's pressure
+    mo, ko = torch.empty_like(h), torch.empty_like(h)
+    ctx.correct(h, hu, None, hw, mk, dt(pref), t0, dts, mo, None, ko)
+    assert rel(mo, mref) <= 1e-12
+    assert rel(ko - hw, kref - ens.packed("hw")) <= 1e-11
+
+
+# --------------------------------------------------------- whole steps ----
+
+def run_gpu(B, case_or_ens, nsteps, **kw):
+    ctx = B.context_1d(case_or_ens, **kw)
+    if hasattr(case_or_ens, "channels"):
+        ctx.set_time([c.t0 for c in case_or_ens.channels])
+        pk = case_or_ens.packed
+        h, hu, hw = dt(pk("h")), dt(pk("hu")), dt(pk("hw"))
+    else:
+        ctx.set_time(case_or_ens.t0)
+        h, hu, hw = dt(case_or_ens.h), dt(case_or_ens.hu), dt(case_or_ens.hw)
+    p = torch.zeros_like(h)
+    mask = torch.zeros(h.numel(), dtype=torch.uint8, device=DEV)
+    ctx.step(h, hu, None, hw, p, mask, nsteps=nsteps)
+    st = ctx.sync_stats()
+    return ctx, st, h, hu, hw, p, mask
+
+
+def phys_of(kw):
+    return O.phys_struct(crit=kw.get("crit", 6), k_nh=kw.get("k_nh", 1e-3),
+                         enlarge=kw.get("enlarge", 1), first_global=kw.get("first_global", 1))
+
+
+@pytest.mark.parametrize("crit", [S.CRIT_GLOBAL, S.CRIT_ETA_D, S.CRIT_U, S.CRIT_W, S.CRIT_NONE])
+def test_steps_parity_random(B, crit):
+    case = S.random_case_1d(3000, seed=21)
+    kw = dict(crit=crit, k_nh=5e-3, enlarge=1, cfl=0.45)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 20, **kw)
+    assert st["status"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(20)
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    assert st["n_active"] == ref.last_active
+    assert abs(st["t"] - ref.time) <= 1e-14 * ref.time
+    for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw)):
+        assert rel(g, r) <= 1e-10
+    if crit != S.CRIT_NONE:
+        assert rel(p, ref.p) <= 1e-10
+
+
+def test_solitary_wave_full_run_parity(B):
+    """1D solitary wave, h0 = 1, a = 0.2, 200 m, N = 2000, global, CFL 0.5, 1000 steps"""
+    case = S.solitary_case(n=2000, length=200.0, d=1.0, a=0.2)
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.5)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 1000, **kw)
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.5).step(1000)
+    assert st["status"] == 0 and st["n_active"] == 2000
+    for g, r in ((h - 1.0, ref.h - 1.0), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+    x = (np.arange(case.n) + 0.5) * case.dx
+    ex, _, _ = S.solitary_exact(x, st["t"], 0.2, 1.0, 50.0)
+    eta = h.cpu().numpy() - 1.0
+    assert np.sqrt(np.mean((eta - ex) ** 2)) / 0.2 < 5.4e-3
+    assert np.corrcoef(eta, ex)[0, 1] > 0.9997
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_slide_full_size_steps(B, precision):
+    """moving-bottom slide at its full size (N = 32768), adaptive |eta/d|, in the
+    launch configuration the benchmark times"""
+    case = S.slide_case(n=32768, dx=0.005)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=precision, tol=1e-12,
+              max_iter=8)
+    nsteps = 300
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, nsteps, **kw)
+    assert st["status"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.5).step(nsteps)
+    tol = 1e-10 if precision == 0 else 1e-6
+    assert st["n_active"] == ref.last_active > 0
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    d_end, *_ = O.forcing_1d(case.ds, case.dx, case.body, ref.time)
+    for g, r in ((h - dt(d_end), ref.h - d_end), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= tol
+
+
+def test_batched_ensemble_parity(B):
+    ens = S.ensemble_case(n_channels=6, n_min=600, n_max=5000, seed=3, dx=0.005)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 150, **kw)
+    assert st["status"] == 0
+    o = ens.offsets
+    tg = ctx.get_time()
+    total = 0
+    for j, c in enumerate(ens.channels):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.5).step(150)
+        sl = slice(o[j], o[j + 1])
+        assert abs(tg[j] - ref.time) <= 1e-13 * ref.time
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask)
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= 1e-10
+        if ref.last_active:
+            assert rel(p[sl], ref.p) <= 1e-10
+        total += ref.last_active
+    assert st["n_active"] == total
+
+
+def test_deterministic_and_graph_replay(B):
+    case = S.random_case_1d(5000, seed=2)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, cfl=0.4)
+    a = run_gpu(B, case, 30, **kw)
+    b = run_gpu(B, case, 30, **kw)
+    for x, y in zip(a[2:], b[2:]):
+        assert torch.equal(x, y)
+    # 30 single-step calls (graph replays) == one 30-step call
+    ctx = B.context_1d(case, **kw)
+    ctx.set_time(case.t0)
+    h, hu, hw = dt(case.h), dt(case.hu), dt(case.hw)
+    p = torch.zeros_like(h)
+    for _ in range(30):
+        ctx.step(h, hu, None, hw, p)
+    ctx.sync_stats()
+    assert torch.equal(h, a[2]) and torch.equal(hu, a[3]) and torch.equal(hw, a[4])
+
+
+def test_empty_area_and_status_codes(B):
+    case = S.random_case_1d(700, seed=1)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e6, cfl=0.4)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 5, **kw)
+    assert st["status"] == 0 and st["n_active"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.4).step(5)
+    assert rel(hu, ref.hu) <= 1e-12 and torch.count_nonzero(p) == 0
+    bad = S.Case1D(n=700, dx=case.dx, ds=case.ds, h=case.h.copy(), hu=case.hu, hw=case.hw,
+                   body=case.body, t0=case.t0)
+    bad.h[100] = -0.2
+    _, st, *_ = run_gpu(B, bad, 1, crit=S.CRIT_GLOBAL, cfl=0.0, dt_fixed=1e-4)
+    assert st["status"] == B.EDRY
+    bad.h[100] = np.nan
+    _, st, *_ = run_gpu(B, bad, 1, crit=S.CRIT_GLOBAL, cfl=0.4)
+    assert st["status"] == B.ENAN
+
+
+def test_refinement_reports_noconvergence(B):
+    case = S.slide_case(n=4096, dx=0.005)
+    _, st, *_ = run_gpu(B, case, 3, crit=S.CRIT_GLOBAL, cfl=0.5, precision=1, tol=1e-30,
+                        max_iter=2)
+    assert st["status"] == B.ENOCONV and st["iters"] == 2
