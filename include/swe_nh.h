@@ -183,6 +183,19 @@ int swe_nh_correct(swe_nh_ctx* ctx, const double* ht, const double* mt, const do
                    const double* kt, const uint8_t* mask, const double* p, const double* t_host,
                    const double* dt_host, double* m_out, double* n_out, double* k_out);
 
+/* Measurement: launch one stage kernel of the step nreps times back to back
+ * on the context's stream, with the launch configuration swe_nh_step uses,
+ * between two HIP events, and return the mean time per launch in
+ * microseconds (synchronises).  stage: 0 predictor, 1 criterion/mask,
+ * 2 elliptic solve (all solver launches of one solve), 3 projection.  The
+ * state arrays must hold a valid state of the context (for instance after
+ * swe_nh_step); stage 0 uses the time step of the last step and does not
+ * modify them (its output goes to the workspace).  Stages 1-3 reuse the
+ * workspace of the last step and may overwrite hu, hw (and hv) and p on the
+ * marked cells with the same values. */
+int swe_nh_time_stage(swe_nh_ctx* ctx, int32_t stage, int32_t nreps, double* h, double* hu,
+                      double* hv, double* hw, double* p, double* avg_us_host);
+
 #ifdef __cplusplus
 }
 #endif

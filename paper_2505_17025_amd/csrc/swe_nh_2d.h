@@ -34,4 +34,7 @@ void correct2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht
                const double* p, const double* t_in, const double* dt_in, double* m_out,
                double* n_out, double* k_out);
 
+void time_stage2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, int stage, double* h,
+                  double* hu, double* hv, double* hw, double* p);
+
 }  // namespace swenh

@@ -17,4 +17,6 @@ void solve_pressure2d(const swe_nh_config*, Ctx2D*, hipStream_t, const double*, 
 void correct2d(const swe_nh_config*, Ctx2D*, hipStream_t, const double*, const double*,
                const double*, const double*, const uint8_t*, const double*, const double*,
                const double*, double*, double*, double*) {}
+void time_stage2d(const swe_nh_config*, Ctx2D*, hipStream_t, int, double*, double*, double*,
+                  double*, double*) {}
 }  // namespace swenh

@@ -598,4 +598,40 @@ int swe_nh_correct(swe_nh_ctx* c, const double* ht, const double* mt, const doub
   return after_launch(c);
 }
 
+int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, double* hu,
+                      double* hv, double* hw, double* p, double* avg_us_host) {
+  if (!c || !h || !hu || !hw || !p || !avg_us_host || nreps < 1 || stage < 0 || stage > 3)
+    return fail(c, SWE_NH_EINVAL, "bad arguments");
+  if ((c->cfg.dim == 1) != (hv == nullptr)) return fail(c, SWE_NH_EINVAL, "hv must be NULL iff dim == 1");
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipEventRecord(e0, s));
+  for (int r = 0; r < nreps; r++) {
+    if (c->cfg.dim == 1) {
+      K1D& P = c->k1;
+      uint8_t* M = c->mask_ws;
+      switch (stage) {
+        case 0: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s); break;
+        case 1: launch_mask1d(P, c->ht, c->mt, c->kt, P.t, P.dt, 0, M, nullptr, nullptr, nullptr,
+                              nullptr, 0, s); break;
+        case 2: solve1d(c, s, 0); break;
+        default: launch_correct1d(P, c->ncells, c->ht, c->mt, c->kt, M, P.t, P.dt, c->T64.x[0],
+                                  hu, hw, p, s);
+      }
+    } else {
+      time_stage2d(&c->cfg, &c->c2, s, stage, h, hu, hv, hw, p);
+    }
+  }
+  HIPCHK(c, hipEventRecord(e1, s));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_us_host = 1000.0 * ms / nreps;
+  return after_launch(c);
+}
+
 }  // extern "C"

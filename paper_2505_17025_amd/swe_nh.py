@@ -73,7 +73,8 @@ def _load():
                                           vp, C.POINTER(i32), C.POINTER(dbl)]
     lib.swe_nh_correct.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp,
                                    vp, vp]
-    for name in ("swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
+    lib.swe_nh_time_stage.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, C.POINTER(dbl)]
+    for name in ("swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
                  "swe_nh_sync_stats", "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure",
                  "swe_nh_correct"):
         getattr(lib, name).restype = C.c_int
@@ -83,7 +84,8 @@ def _load():
 LIB = _load()
 EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_last_error",
             "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step", "swe_nh_sync_stats",
-            "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct"]
+            "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct",
+            "swe_nh_time_stage"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -178,6 +180,13 @@ class Context:
         st = swe_nh_stats()
         self._check(LIB.swe_nh_sync_stats(self.ctx, C.byref(st)), "swe_nh_sync_stats")
         return {k: getattr(st, k) for k, _ in swe_nh_stats._fields_}
+
+    def time_stage(self, stage, nreps, h, hu, hv, hw, p):
+        us = C.c_double()
+        self._check(LIB.swe_nh_time_stage(self.ctx, int(stage), int(nreps), _ptr(h), _ptr(hu),
+                                          _ptr(hv), _ptr(hw), _ptr(p), C.byref(us)),
+                    "swe_nh_time_stage")
+        return us.value
 
     # ---- stages ----
     def _times(self, t):
