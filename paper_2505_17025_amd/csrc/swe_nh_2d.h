@@ -10,10 +10,39 @@
 
 namespace swenh {
 
+constexpr int TX2 = 32;  // tile width (cells along x) of the 2D kernels
+constexpr int TY2 = 16;  // tile height
+
 struct Ctx2D {
-  int* n_act = nullptr;
+  int nx = 0, ny = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
+  int grid_pcg = 0;          // blocks of the persistent PCG kernel
+  // predictor output
+  double *ht = nullptr, *mt = nullptr, *nt = nullptr, *kt = nullptr;
+  uint8_t* mask_ws = nullptr;
+  // tiles
+  int* tile_cnt = nullptr;   // marked cells per tile
+  int* tile_list = nullptr;  // active tiles
+  int* n_tiles_act = nullptr;
+  int* n_act = nullptr;      // marked cells
+  // operator (FP64 and FP32 copies), neighbour flags, right-hand side, solution
+  double *dg = nullptr, *ce = nullptr, *cn = nullptr, *b = nullptr, *x = nullptr;
+  float *dg32 = nullptr, *ce32 = nullptr, *cn32 = nullptr;
+  uint8_t* nb = nullptr;
+  // inner Krylov vectors: FP32 (precision 1) or FP64 (precision 0)
+  float *r = nullptr, *z = nullptr, *pa = nullptr, *pb = nullptr, *q = nullptr, *e = nullptr;
+  double *r64 = nullptr, *z64 = nullptr, *pa64 = nullptr, *pb64 = nullptr, *q64 = nullptr,
+         *e64 = nullptr;
+  double* part = nullptr;    // [grid_pcg * 4] block partial sums
+  unsigned* bar = nullptr;   // grid barrier: [grid_pcg] arrival flags + release word
   int* iters = nullptr;
   double* rel = nullptr;
+  // shared scalars from the 1D block (time, dt, speed, status, step)
+  double* t = nullptr;
+  double* dt = nullptr;
+  unsigned long long* smax = nullptr;
+  int* status = nullptr;
+  int* step = nullptr;
+  const Chan* ch = nullptr;
 };
 
 void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x);
@@ -25,7 +54,7 @@ void launch_pred2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const 
                          const double* dt_in, double* ht, double* mt, double* nt, double* kt);
 void launch_mask2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
                          const double* mt, const double* nt, const double* kt,
-                         const double* t_in, int mode, uint8_t* mask);
+                         const double* t_in, const double* dt_in, int mode, uint8_t* mask);
 void solve_pressure2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
                       const double* mt, const double* nt, const double* kt, const uint8_t* mask,
                       const double* t_in, const double* dt_in, double* p);
@@ -33,7 +62,6 @@ void correct2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht
                const double* mt, const double* nt, const double* kt, const uint8_t* mask,
                const double* p, const double* t_in, const double* dt_in, double* m_out,
                double* n_out, double* k_out);
-
 void time_stage2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, int stage, double* h,
                   double* hu, double* hv, double* hw, double* p);
 

@@ -1,22 +1,1297 @@
-// swe_nh_2d.hip -- 2D path (placeholder until the 2D kernels land)
+// swe_nh_2d.hip -- 2D kernels of the non-hydrostatic SWE step (gfx950).
+//
+// Grid [ny][nx], x fastest, tiles of TX2 x TY2 cells (one block of 256
+// threads per tile).  Walls on all four sides: reflected ghosts (the normal
+// momentum changes sign), zero Dirichlet data for the NH pressure.
+//
+//   k_speed2d      max (|u| + c)/dx + (|v| + c)/dy and state checks -> dt
+//   k_pred2d       both Heun stages of the unsplit hydrostatic FV operator in
+//                  LDS (4-cell halo); face fluxes computed once per direction
+//   k_mask2d       criterion + (2e+1)^2 box enlargement, tile counts
+//   k_tiles2d      list of tiles holding marked cells
+//   k_assemble2d   5-point operator of the elliptic system (FP64 + FP32 copy)
+//   k_pcg2d<R>     persistent preconditioned CG (Jacobi) in precision R with
+//                  FP64 residuals and FP64 refinement of the solution,
+//                  deterministic fixed-order dot products, flag-array grid
+//                  barrier with bounded waits
+//   k_correct2d    projection of hu, hv and hw on the marked cells
 #include "swe_nh_2d.h"
+#include "swe_nh_common.h"
 
 namespace swenh {
-void plan2d(const swe_nh_config*, char*, size_t*, Ctx2D*) {}
-int init2d(const swe_nh_config*, Ctx2D*, const K1D&, hipStream_t) { return SWE_NH_EINVAL; }
-void enqueue_step2d(const swe_nh_config*, Ctx2D*, hipStream_t, double*, double*, double*, double*,
-                    double*, uint8_t*) {}
-void launch_pred2d_stage(const swe_nh_config*, Ctx2D*, hipStream_t, const double*, const double*,
-                         const double*, const double*, const double*, const double*, double*,
-                         double*, double*, double*) {}
-void launch_mask2d_stage(const swe_nh_config*, Ctx2D*, hipStream_t, const double*, const double*,
-                         const double*, const double*, const double*, int, uint8_t*) {}
-void solve_pressure2d(const swe_nh_config*, Ctx2D*, hipStream_t, const double*, const double*,
-                      const double*, const double*, const uint8_t*, const double*, const double*,
-                      double*) {}
-void correct2d(const swe_nh_config*, Ctx2D*, hipStream_t, const double*, const double*,
-               const double*, const double*, const uint8_t*, const double*, const double*,
-               const double*, double*, double*, double*) {}
-void time_stage2d(const swe_nh_config*, Ctx2D*, hipStream_t, int, double*, double*, double*,
-                  double*, double*) {}
+
+namespace {
+
+constexpr int NT2 = 256;
+constexpr int H2 = 4;
+constexpr int WX = TX2 + 2 * H2, WY = TY2 + 2 * H2, WN = WX * WY;
+constexpr int R1X = TX2 + 4, R1Y = TY2 + 4, R1N = R1X * R1Y;
+constexpr int NFACE = ((R1X + 1) * R1Y > R1X * (R1Y + 1)) ? (R1X + 1) * R1Y : R1X * (R1Y + 1);
+constexpr int QMAX = (R1N + NT2 - 1) / NT2;
+constexpr int TN = TX2 * TY2;
+constexpr int MAXE2 = 64;
+
+struct G2 {
+  int nx, ny, tiles_x;
+  double dx, dy, g, rho, cfl, dt_fixed, k_nh;
+  int crit, enlarge, first_global;
+  const double* ds;
+  const Chan* ch;
+  double* t;
+  double* dt;
+  unsigned long long* smax;
+  int* status;
+  int* step;
+};
+
+G2 make_g2(const swe_nh_config* c, const Ctx2D* x) {
+  G2 g;
+  g.nx = c->nx;
+  g.ny = c->ny;
+  g.tiles_x = x->tiles_x;
+  g.dx = c->dx;
+  g.dy = c->dy;
+  g.g = c->g;
+  g.rho = c->rho;
+  g.cfl = c->cfl;
+  g.dt_fixed = c->dt_fixed;
+  g.k_nh = c->k_nh;
+  g.crit = c->crit;
+  g.enlarge = c->enlarge;
+  g.first_global = c->first_global;
+  g.ds = c->depth_static;
+  g.ch = x->ch;
+  g.t = x->t;
+  g.dt = x->dt;
+  g.smax = x->smax;
+  g.status = x->status;
+  g.step = x->step;
+  return g;
+}
+
+__device__ __forceinline__ double depth2(const G2& G, const Chan& c, const Motion& M, int i,
+                                         int j) {
+  const double x = (i + 0.5) * G.dx, y = (j + 0.5) * G.dy;
+  return G.ds[(int64_t)j * G.nx + i] - body_shape(c, x - M.X, y - c.y0).B;
+}
+
+// ---------------------------------------------------------------------------
+// wave speed
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT2) k_speed2d(G2 G, const double* __restrict__ h,
+                                                 const double* __restrict__ hu,
+                                                 const double* __restrict__ hv,
+                                                 const double* __restrict__ hw) {
+  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
+  double s = 0.0;
+  int flags = 0;
+  for (int c = threadIdx.x; c < TN; c += NT2) {
+    const int i = i0 + c % TX2, j = j0 + c / TX2;
+    if (i >= G.nx || j >= G.ny) continue;
+    const int64_t o = (int64_t)j * G.nx + i;
+    const double hh = h[o], m = hu[o], n = hv[o], k = hw[o];
+    if (!isfinite(hh) || !isfinite(m) || !isfinite(n) || !isfinite(k)) {
+      flags |= ST_NAN;
+    } else if (!(hh > 0.0)) {
+      flags |= ST_DRY;
+    } else {
+      const double a = sqrt(G.g * hh);
+      s = fmax(s, (fabs(m / hh) + a) / G.dx + (fabs(n / hh) + a) / G.dy);
+    }
+  }
+  s = wave_max(s);
+  __shared__ double red[NT2 / 64];
+  __shared__ int fl;
+  if (threadIdx.x == 0) fl = 0;
+  __syncthreads();
+  if (flags) atomicOr(&fl, flags);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < NT2 / 64; w++) m = fmax(m, red[w]);
+    atomicMax(G.smax, pos_bits(m));
+    if (fl) atomicOr(G.status, fl);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// predictor
+// ---------------------------------------------------------------------------
+struct Flux2 {
+  double Fh, FmL, FmR, Ft1, Ft2;
+  bool dry;
+};
+
+// Rusanov flux across a face with normal momentum m and tangential
+// momenta a, b, hydrostatic reconstruction of the bed (Audusse et al. 2004)
+__device__ __forceinline__ Flux2 rusanov2d(double g, double eL, double mL, double aL, double bL,
+                                           double dL, double eR, double mR, double aR, double bR,
+                                           double dR) {
+  Flux2 f;
+  const double hL = eL + dL, hR = eR + dR;
+  f.dry = !(hL > 0.0) || !(hR > 0.0);
+  const double uL = mL / hL, uR = mR / hR;
+  const double vL = aL / hL, vR = aR / hR;
+  const double wL = bL / hL, wR = bR / hR;
+  const double db = fmin(dL, dR);
+  const double sL = fmax(0.0, eL + db), sR = fmax(0.0, eR + db);
+  const double lam = fmax(fabs(uL) + sqrt(g * sL), fabs(uR) + sqrt(g * sR));
+  const double qL = sL * uL, qR = sR * uR;
+  f.Fh = 0.5 * (qL + qR) - 0.5 * lam * (sR - sL);
+  const double Fm = 0.5 * (qL * uL + 0.5 * g * sL * sL + qR * uR + 0.5 * g * sR * sR) -
+                    0.5 * lam * (qR - qL);
+  f.FmL = Fm + 0.5 * g * (hL * hL - sL * sL);
+  f.FmR = Fm + 0.5 * g * (hR * hR - sR * sR);
+  f.Ft1 = 0.5 * (qL * vL + qR * vR) - 0.5 * lam * (sR * vR - sL * vL);
+  f.Ft2 = 0.5 * (qL * wL + qR * wR) - 0.5 * lam * (sR * wR - sL * wL);
+  return f;
+}
+
+struct P2 {
+  double e[WN], m[WN], n[WN], k[WN], d0[WN], d1[WN];
+  double F0[NFACE], F1[NFACE], F2[NFACE], F3[NFACE], F4[NFACE];
+};
+
+__device__ __forceinline__ int W(int i, int j) { return j * WX + i; }
+
+// face of the window between cells wl and wr (step s: 1 along x, WX along y)
+__device__ __forceinline__ Flux2 face2d(const P2& S, const double* d, double g, int wl, int wr,
+                                        int s, bool xdir) {
+  const double* nm = xdir ? S.m : S.n;  // normal momentum
+  const double* t1 = xdir ? S.n : S.m;  // tangential momentum
+  const double sel = minmod(S.e[wl] - S.e[wl - s], S.e[wl + s] - S.e[wl]);
+  const double sml = minmod(nm[wl] - nm[wl - s], nm[wl + s] - nm[wl]);
+  const double sal = minmod(t1[wl] - t1[wl - s], t1[wl + s] - t1[wl]);
+  const double skl = minmod(S.k[wl] - S.k[wl - s], S.k[wl + s] - S.k[wl]);
+  const double sdl = minmod(d[wl] - d[wl - s], d[wl + s] - d[wl]);
+  const double ser = minmod(S.e[wr] - S.e[wr - s], S.e[wr + s] - S.e[wr]);
+  const double smr = minmod(nm[wr] - nm[wr - s], nm[wr + s] - nm[wr]);
+  const double sar = minmod(t1[wr] - t1[wr - s], t1[wr + s] - t1[wr]);
+  const double skr = minmod(S.k[wr] - S.k[wr - s], S.k[wr + s] - S.k[wr]);
+  const double sdr = minmod(d[wr] - d[wr - s], d[wr + s] - d[wr]);
+  return rusanov2d(g, S.e[wl] + 0.5 * sel, nm[wl] + 0.5 * sml, t1[wl] + 0.5 * sal,
+                   S.k[wl] + 0.5 * skl, d[wl] + 0.5 * sdl, S.e[wr] - 0.5 * ser, nm[wr] - 0.5 * smr,
+                   t1[wr] - 0.5 * sar, S.k[wr] - 0.5 * skr, d[wr] - 0.5 * sdr);
+}
+
+// centred bed source g (h-_{+} + h+_{-}) / 2 * slope(d) / dx of a cell along one direction
+__device__ __forceinline__ double bed_src(const P2& S, const double* d, double g, int w, int s,
+                                          double inv) {
+  const double se = minmod(S.e[w] - S.e[w - s], S.e[w + s] - S.e[w]);
+  const double sd = minmod(d[w] - d[w - s], d[w + s] - d[w]);
+  const double hp = (S.e[w] + 0.5 * se) + (d[w] + 0.5 * sd);
+  const double hm = (S.e[w] - 0.5 * se) + (d[w] - 0.5 * sd);
+  return g * 0.5 * (hp + hm) * sd * inv;
+}
+
+// L of one stage on the region of RXs x RYs cells at window offset O; the
+// thread's cells are region cells r = threadIdx.x + NT2 q (stage 1 layout);
+// only cells with `want` set are evaluated.
+template <int RXs, int RYs, int O>
+__device__ void stage2d(P2& S, const double* d, const G2& G, int i0, int j0, double (&L)[QMAX][4],
+                        int* flags) {
+  const double idx = 1.0 / G.dx, idy = 1.0 / G.dy;
+  const int wi0 = i0 - H2, wj0 = j0 - H2;  // domain coords of window cell (0, 0)
+  auto dom = [&](int wi, int wj) {
+    const int i = wi0 + wi, j = wj0 + wj;
+    return i >= 0 && i < G.nx && j >= 0 && j < G.ny;
+  };
+  auto inreg = [&](int wi, int wj) {
+    return wi >= O && wi < O + RXs && wj >= O && wj < O + RYs;
+  };
+  // x-faces
+  for (int f = threadIdx.x; f < (RXs + 1) * RYs; f += NT2) {
+    const int fi = f % (RXs + 1), rj = f / (RXs + 1);
+    const int wl = W(O + fi - 1, O + rj), wr = wl + 1;
+    const Flux2 F = face2d(S, d, G.g, wl, wr, 1, true);
+    S.F0[f] = F.Fh;
+    S.F1[f] = F.FmL;
+    S.F2[f] = F.FmR;
+    S.F3[f] = F.Ft1;
+    S.F4[f] = F.Ft2;
+    const bool used = (inreg(O + fi - 1, O + rj) && dom(O + fi - 1, O + rj)) ||
+                      (inreg(O + fi, O + rj) && dom(O + fi, O + rj));
+    if (F.dry && used) *flags |= ST_DRY;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < QMAX; q++) {
+    const int r = threadIdx.x + NT2 * q;
+    if (r >= R1N) break;
+    const int wi = 2 + r % R1X, wj = 2 + r / R1X;  // stage-1 layout
+    if (!inreg(wi, wj)) continue;
+    const int ri = wi - O, rj = wj - O;
+    const int fl = rj * (RXs + 1) + ri, fr = fl + 1;
+    const int w = W(wi, wj);
+    L[q][0] = -(S.F0[fr] - S.F0[fl]) * idx;
+    L[q][1] = -(S.F1[fr] - S.F2[fl]) * idx + bed_src(S, d, G.g, w, 1, idx);
+    L[q][2] = -(S.F3[fr] - S.F3[fl]) * idx;
+    L[q][3] = -(S.F4[fr] - S.F4[fl]) * idx;
+  }
+  __syncthreads();
+  // y-faces: normal momentum hv, tangential hu
+  for (int f = threadIdx.x; f < RXs * (RYs + 1); f += NT2) {
+    const int ri = f % RXs, fj = f / RXs;
+    const int wl = W(O + ri, O + fj - 1), wr = wl + WX;
+    const Flux2 F = face2d(S, d, G.g, wl, wr, WX, false);
+    S.F0[f] = F.Fh;
+    S.F1[f] = F.FmL;
+    S.F2[f] = F.FmR;
+    S.F3[f] = F.Ft1;
+    S.F4[f] = F.Ft2;
+    const bool used = (inreg(O + ri, O + fj - 1) && dom(O + ri, O + fj - 1)) ||
+                      (inreg(O + ri, O + fj) && dom(O + ri, O + fj));
+    if (F.dry && used) *flags |= ST_DRY;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < QMAX; q++) {
+    const int r = threadIdx.x + NT2 * q;
+    if (r >= R1N) break;
+    const int wi = 2 + r % R1X, wj = 2 + r / R1X;
+    if (!inreg(wi, wj)) continue;
+    const int ri = wi - O, rj = wj - O;
+    const int fs = rj * RXs + ri, fn = fs + RXs;
+    const int w = W(wi, wj);
+    L[q][0] += -(S.F0[fn] - S.F0[fs]) * idy;
+    L[q][2] += -(S.F1[fn] - S.F2[fs]) * idy + bed_src(S, d, G.g, w, WX, idy);
+    L[q][1] += -(S.F3[fn] - S.F3[fs]) * idy;
+    L[q][3] += -(S.F4[fn] - S.F4[fs]) * idy;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT2) k_pred2d(G2 G, const double* __restrict__ h,
+                                                const double* __restrict__ hu,
+                                                const double* __restrict__ hv,
+                                                const double* __restrict__ hw,
+                                                double* __restrict__ ht, double* __restrict__ mt,
+                                                double* __restrict__ nt, double* __restrict__ kt,
+                                                const double* t_in, const double* dt_in,
+                                                int dt_from_speed) {
+  __shared__ P2 S;
+  __shared__ int sflags;
+  const Chan c = G.ch[0];
+  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
+  const int wi0 = i0 - H2, wj0 = j0 - H2;
+  const double t0 = t_in[0];
+  double dt;
+  if (dt_from_speed) {
+    dt = (G.cfl > 0.0) ? G.cfl / __longlong_as_double((long long)*G.smax) : G.dt_fixed;
+    if (blockIdx.x == 0 && threadIdx.x == 0) G.dt[0] = dt;
+  } else {
+    dt = dt_in[0];
+  }
+  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t0 + dt);
+  if (threadIdx.x == 0) sflags = 0;
+  int flags = 0;
+  for (int w = threadIdx.x; w < WN; w += NT2) {
+    const int ii = wi0 + w % WX, jj = wj0 + w / WX;
+    const int si = reflect(min(max(ii, -H2), G.nx + H2 - 1), G.nx);
+    const int sj = reflect(min(max(jj, -H2), G.ny + H2 - 1), G.ny);
+    const int64_t o = (int64_t)sj * G.nx + si;
+    const double a0 = depth2(G, c, M0, si, sj), a1 = depth2(G, c, M1, si, sj);
+    S.e[w] = h[o] - a0;
+    S.m[w] = (si == ii ? 1.0 : -1.0) * hu[o];
+    S.n[w] = (sj == jj ? 1.0 : -1.0) * hv[o];
+    S.k[w] = hw[o];
+    S.d0[w] = a0;
+    S.d1[w] = a1;
+  }
+  __syncthreads();
+  double Qn[QMAX][4], L1[QMAX][4], L2[QMAX][4];
+#pragma unroll
+  for (int q = 0; q < QMAX; q++)
+#pragma unroll
+    for (int v = 0; v < 4; v++) Qn[q][v] = L1[q][v] = L2[q][v] = 0.0;
+  stage2d<R1X, R1Y, 2>(S, S.d0, G, i0, j0, L1, &flags);
+  // Q* = Q^n + dt L(Q^n) on the stage-1 region, then ghosts reflected from Q*
+#pragma unroll
+  for (int q = 0; q < QMAX; q++) {
+    const int r = threadIdx.x + NT2 * q;
+    if (r >= R1N) break;
+    const int wi = 2 + r % R1X, wj = 2 + r / R1X, w = W(wi, wj);
+    const int i = wi0 + wi, j = wj0 + wj;
+    if (i < 0 || i >= G.nx || j < 0 || j >= G.ny) continue;
+    Qn[q][0] = S.e[w] + S.d0[w];
+    Qn[q][1] = S.m[w];
+    Qn[q][2] = S.n[w];
+    Qn[q][3] = S.k[w];
+    S.e[w] = Qn[q][0] + dt * L1[q][0] - S.d1[w];
+    S.m[w] = Qn[q][1] + dt * L1[q][1];
+    S.n[w] = Qn[q][2] + dt * L1[q][2];
+    S.k[w] = Qn[q][3] + dt * L1[q][3];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R1N; r += NT2) {
+    const int wi = 2 + r % R1X, wj = 2 + r / R1X, w = W(wi, wj);
+    const int i = wi0 + wi, j = wj0 + wj;
+    if (i >= 0 && i < G.nx && j >= 0 && j < G.ny) continue;
+    const int si = reflect(min(max(i, -H2), G.nx + H2 - 1), G.nx);
+    const int sj = reflect(min(max(j, -H2), G.ny + H2 - 1), G.ny);
+    const int swi = si - wi0, swj = sj - wj0;
+    double ev = 0.0, mv = 0.0, nv = 0.0, kv = 0.0;
+    if (swi >= 2 && swi < 2 + R1X && swj >= 2 && swj < 2 + R1Y) {
+      const int sw = W(swi, swj);
+      ev = S.e[sw];
+      mv = (si == i ? 1.0 : -1.0) * S.m[sw];
+      nv = (sj == j ? 1.0 : -1.0) * S.n[sw];
+      kv = S.k[sw];
+    }
+    S.e[w] = ev;
+    S.m[w] = mv;
+    S.n[w] = nv;
+    S.k[w] = kv;
+  }
+  __syncthreads();
+  stage2d<TX2, TY2, H2>(S, S.d1, G, i0, j0, L2, &flags);
+#pragma unroll
+  for (int q = 0; q < QMAX; q++) {
+    const int r = threadIdx.x + NT2 * q;
+    if (r >= R1N) break;
+    const int wi = 2 + r % R1X, wj = 2 + r / R1X;
+    if (wi < H2 || wi >= H2 + TX2 || wj < H2 || wj >= H2 + TY2) continue;
+    const int i = wi0 + wi, j = wj0 + wj;
+    if (i >= G.nx || j >= G.ny) continue;
+    const int64_t o = (int64_t)j * G.nx + i;
+    ht[o] = Qn[q][0] + 0.5 * dt * (L1[q][0] + L2[q][0]);
+    mt[o] = Qn[q][1] + 0.5 * dt * (L1[q][1] + L2[q][1]);
+    nt[o] = Qn[q][2] + 0.5 * dt * (L1[q][2] + L2[q][2]);
+    kt[o] = Qn[q][3] + 0.5 * dt * (L1[q][3] + L2[q][3]);
+  }
+  if (flags) atomicOr(&sflags, flags);
+  __syncthreads();
+  if (threadIdx.x == 0 && sflags) atomicOr(G.status, sflags);
+}
+
+// ---------------------------------------------------------------------------
+// criterion and enlargement
+// ---------------------------------------------------------------------------
+__device__ double indicator2d(const G2& G, const Chan& c, const Motion& M, const double* ht,
+                              const double* mt, const double* nt, const double* kt, int i, int j) {
+  const int nx = G.nx, ny = G.ny;
+  const int il = reflect(i - 1, nx), ir = reflect(i + 1, nx);
+  const int jl = reflect(j - 1, ny), jr = reflect(j + 1, ny);
+  const double sxl = (il == i - 1) ? 1.0 : -1.0, sxr = (ir == i + 1) ? 1.0 : -1.0;
+  const double syl = (jl == j - 1) ? 1.0 : -1.0, syr = (jr == j + 1) ? 1.0 : -1.0;
+  auto O = [&](int a, int b) { return (int64_t)b * nx + a; };
+  const int64_t o = O(i, j);
+  switch (G.crit) {
+    case SWE_NH_CRIT_ETA_D: {
+      const double d = depth2(G, c, M, i, j);
+      return fabs((ht[o] - d) / d);
+    }
+    case SWE_NH_CRIT_ETA_X: {
+      const double ex = ((ht[O(ir, j)] - depth2(G, c, M, ir, j)) -
+                         (ht[O(il, j)] - depth2(G, c, M, il, j))) / (2.0 * G.dx);
+      const double ey = ((ht[O(i, jr)] - depth2(G, c, M, i, jr)) -
+                         (ht[O(i, jl)] - depth2(G, c, M, i, jl))) / (2.0 * G.dy);
+      return sqrt(ex * ex + ey * ey);
+    }
+    case SWE_NH_CRIT_U: {
+      const double u = mt[o] / ht[o], v = nt[o] / ht[o];
+      return sqrt(u * u + v * v);
+    }
+    case SWE_NH_CRIT_U_X: {
+      const double ux = (sxr * mt[O(ir, j)] / ht[O(ir, j)] - sxl * mt[O(il, j)] / ht[O(il, j)]) /
+                        (2.0 * G.dx);
+      const double uy = (mt[O(i, jr)] / ht[O(i, jr)] - mt[O(i, jl)] / ht[O(i, jl)]) / (2.0 * G.dy);
+      const double vx = (nt[O(ir, j)] / ht[O(ir, j)] - nt[O(il, j)] / ht[O(il, j)]) / (2.0 * G.dx);
+      const double vy = (syr * nt[O(i, jr)] / ht[O(i, jr)] - syl * nt[O(i, jl)] / ht[O(i, jl)]) /
+                        (2.0 * G.dy);
+      return sqrt(ux * ux + uy * uy + vx * vx + vy * vy);
+    }
+    case SWE_NH_CRIT_W:
+      return fabs(kt[o] / ht[o]);
+    default: {
+      const double wx = (kt[O(ir, j)] / ht[O(ir, j)] - kt[O(il, j)] / ht[O(il, j)]) / (2.0 * G.dx);
+      const double wy = (kt[O(i, jr)] / ht[O(i, jr)] - kt[O(i, jl)] / ht[O(i, jl)]) / (2.0 * G.dy);
+      return sqrt(wx * wx + wy * wy);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(NT2) k_mask2d(G2 G, const double* __restrict__ ht,
+                                                const double* __restrict__ mt,
+                                                const double* __restrict__ nt,
+                                                const double* __restrict__ kt, const double* t_in,
+                                                const double* dt_in, int mode_override,
+                                                uint8_t* __restrict__ mask, int* tile_cnt,
+                                                double* h, double* hu, double* hv, double* hw,
+                                                double* p, int write_state) {
+  __shared__ uint8_t raw[(TX2 + 2 * MAXE2) * (TY2 + 2 * MAXE2)];
+  __shared__ uint8_t rowor[TX2 * (TY2 + 2 * MAXE2)];
+  __shared__ int cnt[NT2 / 64];
+  const Chan c = G.ch[0];
+  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
+  const int e = G.enlarge;
+  int mode = mode_override;
+  if (mode < 0) {
+    const bool wcrit = (G.crit == SWE_NH_CRIT_W || G.crit == SWE_NH_CRIT_W_X);
+    if (G.crit == SWE_NH_CRIT_GLOBAL || (wcrit && G.first_global && *G.step == 0))
+      mode = 1;
+    else if (G.crit == SWE_NH_CRIT_NONE)
+      mode = 2;
+    else
+      mode = 0;
+  }
+  const int RW = TX2 + 2 * e, RH = TY2 + 2 * e;
+  if (mode == 0) {
+    const Motion M = body_motion(c, t_in[0] + dt_in[0]);
+    for (int w = threadIdx.x; w < RW * RH; w += NT2) {
+      const int i = i0 - e + w % RW, j = j0 - e + w / RW;
+      uint8_t r = 0;
+      if (i >= 0 && i < G.nx && j >= 0 && j < G.ny)
+        r = indicator2d(G, c, M, ht, mt, nt, kt, i, j) > G.k_nh;
+      raw[w] = r;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < TX2 * RH; w += NT2) {
+      const int ti = w % TX2, rj = w / TX2;
+      uint8_t v = 0;
+      for (int a = 0; a <= 2 * e; a++) v |= raw[rj * RW + ti + a];
+      rowor[w] = v;
+    }
+    __syncthreads();
+  }
+  int local = 0;
+  for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+    const int ti = cc % TX2, tj = cc / TX2;
+    const int i = i0 + ti, j = j0 + tj;
+    if (i >= G.nx || j >= G.ny) continue;
+    uint8_t v;
+    if (mode == 1) {
+      v = 1;
+    } else if (mode == 2) {
+      v = 0;
+    } else {
+      v = 0;
+      for (int a = 0; a <= 2 * e; a++) v |= rowor[(tj + a) * TX2 + ti];
+    }
+    const int64_t o = (int64_t)j * G.nx + i;
+    mask[o] = v;
+    local += v;
+    if (write_state) {
+      h[o] = ht[o];
+      hu[o] = mt[o];
+      hv[o] = nt[o];
+      hw[o] = kt[o];
+      if (!v) p[o] = 0.0;
+    }
+  }
+  local = wave_sum_i(local);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < NT2 / 64; w++) s += cnt[w];
+    tile_cnt[blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(NT2) k_count2d(G2 G, const uint8_t* __restrict__ mask,
+                                                 int* tile_cnt) {
+  __shared__ int cnt[NT2 / 64];
+  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
+  int local = 0;
+  for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+    const int i = i0 + cc % TX2, j = j0 + cc / TX2;
+    if (i < G.nx && j < G.ny) local += mask[(int64_t)j * G.nx + i] ? 1 : 0;
+  }
+  local = wave_sum_i(local);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < NT2 / 64; w++) s += cnt[w];
+    tile_cnt[blockIdx.x] = s;
+  }
+}
+
+// list of tiles holding marked cells, in tile order; total marked cells
+__global__ void __launch_bounds__(1024) k_tiles2d(const int* __restrict__ tile_cnt, int ntiles,
+                                                  int* __restrict__ tile_list, int* n_list,
+                                                  int* n_cells) {
+  __shared__ int part[1024];
+  __shared__ long long cells[1024];
+  const int per = (ntiles + 1023) / 1024;
+  const int b = threadIdx.x * per, e = min(b + per, ntiles);
+  int s = 0;
+  long long cs = 0;
+  for (int i = b; i < e; i++) {
+    s += tile_cnt[i] > 0;
+    cs += tile_cnt[i];
+  }
+  part[threadIdx.x] = s;
+  cells[threadIdx.x] = cs;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    const long long w = threadIdx.x >= (unsigned)o ? cells[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    cells[threadIdx.x] += w;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - s;
+  for (int i = b; i < e; i++)
+    if (tile_cnt[i] > 0) tile_list[run++] = i;
+  if (threadIdx.x == 1023) {
+    *n_list = part[1023];
+    *n_cells = (int)cells[1023];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elliptic system (Eqs. 12-17 on the 2D grid, the diagonal part of
+// S12^{-1} = (dt h / rho)(I - grad d grad d^T / alpha) on each face)
+// ---------------------------------------------------------------------------
+constexpr int RGX = TX2 + 2, RGY = TY2 + 2, RGN = RGX * RGY;
+
+struct Ring {
+  double h[RGN], m[RGN], n[RGN], d[RGN], Dx[RGN], Dy[RGN], phi[RGN];
+};
+
+struct Face2 {
+  double K, a, b, qp, fd;
+};
+
+// fills the ring (tile +- 1) with the quantities the faces need
+__device__ void fill_ring(Ring& R, const G2& G, const Chan& c, const Motion& M, const double* ht,
+                          const double* mt, const double* nt, int i0, int j0) {
+  const int nx = G.nx, ny = G.ny;
+  for (int w = threadIdx.x; w < RGN; w += NT2) {
+    const int ii = i0 - 1 + w % RGX, jj = j0 - 1 + w / RGX;
+    const int i = reflect(min(max(ii, -1), nx), nx), j = reflect(min(max(jj, -1), ny), ny);
+    auto O = [&](int a, int b) { return (int64_t)b * nx + a; };
+    const int il = reflect(i - 1, nx), ir = reflect(i + 1, nx);
+    const int jl = reflect(j - 1, ny), jr = reflect(j + 1, ny);
+    const double d = depth2(G, c, M, i, j);
+    const double dw = depth2(G, c, M, il, j), de = depth2(G, c, M, ir, j);
+    const double ds_ = depth2(G, c, M, i, jl), dn = depth2(G, c, M, i, jr);
+    const double Dx = (de - dw) / (2.0 * G.dx), Dy = (dn - ds_) / (2.0 * G.dy);
+    const double dxx = (de - 2.0 * d + dw) / (G.dx * G.dx);
+    const double dyy = (dn - 2.0 * d + ds_) / (G.dy * G.dy);
+    const double dxy = (depth2(G, c, M, ir, jr) - depth2(G, c, M, ir, jl) -
+                        depth2(G, c, M, il, jr) + depth2(G, c, M, il, jl)) /
+                       (4.0 * G.dx * G.dy);
+    const int64_t o = O(i, j);
+    const double hs = ht[o];
+    const double ex = ((ht[O(ir, j)] - de) - (ht[O(il, j)] - dw)) / (2.0 * G.dx);
+    const double ey = ((ht[O(i, jr)] - dn) - (ht[O(i, jl)] - ds_)) / (2.0 * G.dy);
+    const double u = mt[o] / hs, v = nt[o] / hs;
+    const double x = (i + 0.5) * G.dx, y = (j + 0.5) * G.dy;
+    const BedRate br = bed_rate(M, body_shape(c, x - M.X, y - c.y0));
+    const double al = 4.0 + Dx * Dx + Dy * Dy;
+    R.h[w] = hs;
+    R.m[w] = (i == ii ? 1.0 : -1.0) * mt[o];
+    R.n[w] = (j == jj ? 1.0 : -1.0) * nt[o];
+    R.d[w] = d;
+    R.Dx[w] = Dx;
+    R.Dy[w] = Dy;
+    R.phi[w] = G.rho * hs / al *
+               (G.g * (Dx * ex + Dy * ey) - br.d_tt - 2.0 * (u * br.d_xt + v * br.d_yt) -
+                (u * u * dxx + 2.0 * u * v * dxy + v * v * dyy));
+  }
+}
+
+// face between ring cells l and r; xdir selects the normal
+__device__ __forceinline__ Face2 face_coef(const Ring& R, const G2& G, double dt, int l, int r,
+                                           bool xdir) {
+  const double del = xdir ? G.dx : G.dy;
+  const double hf = 0.5 * (R.h[l] + R.h[r]);
+  const double Dn = (R.d[r] - R.d[l]) / del;
+  const double Dt = xdir ? 0.5 * (R.Dy[l] + R.Dy[r]) : 0.5 * (R.Dx[l] + R.Dx[r]);
+  const double hn = (R.h[r] - R.h[l]) / del;
+  const double qf = xdir ? 0.5 * (R.m[l] + R.m[r]) : 0.5 * (R.n[l] + R.n[r]);
+  const double af = 4.0 + Dn * Dn + Dt * Dt;
+  const double s11 = (2.0 * hn - 3.0 * Dn) / (2.0 * hf);
+  Face2 f;
+  f.K = dt * hf / G.rho * (1.0 - Dn * Dn / af);
+  f.a = -1.0 / del + 0.5 * s11;
+  f.b = 1.0 / del + 0.5 * s11;
+  f.fd = dt / G.rho * (0.5 * (R.phi[l] + R.phi[r])) * Dn;
+  f.qp = qf + f.fd;
+  return f;
+}
+
+enum : uint8_t { NB_W = 1, NB_E = 2, NB_S = 4, NB_N = 8, NB_SELF = 16 };
+
+__device__ __forceinline__ uint8_t nbr_flags(const G2& G, const uint8_t* mask, int i, int j) {
+  const int64_t o = (int64_t)j * G.nx + i;
+  uint8_t f = mask[o] ? NB_SELF : 0;
+  if (!f) return 0;
+  if (i > 0 && mask[o - 1]) f |= NB_W;
+  if (i + 1 < G.nx && mask[o + 1]) f |= NB_E;
+  if (j > 0 && mask[o - G.nx]) f |= NB_S;
+  if (j + 1 < G.ny && mask[o + G.nx]) f |= NB_N;
+  return f;
+}
+
+struct Sys2 {
+  double *dg, *ce, *cn, *b, *x;
+  float *dg32, *ce32, *cn32;
+  uint8_t* nb;
+};
+
+__global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restrict__ ht,
+                                                    const double* __restrict__ mt,
+                                                    const double* __restrict__ nt,
+                                                    const double* __restrict__ kt,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const int* tile_list, const int* n_list,
+                                                    const double* t_in, const double* dt_in,
+                                                    Sys2 Y, const double* p_prev, int warm) {
+  if ((int)blockIdx.x >= *n_list) return;
+  __shared__ Ring R;
+  const int tile = tile_list[blockIdx.x];
+  const int i0 = (tile % G.tiles_x) * TX2, j0 = (tile / G.tiles_x) * TY2;
+  const Chan c = G.ch[0];
+  const double dt = dt_in[0];
+  const Motion M = body_motion(c, t_in[0] + dt);
+  fill_ring(R, G, c, M, ht, mt, nt, i0, j0);
+  __syncthreads();
+  for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+    const int ti = cc % TX2, tj = cc / TX2;
+    const int i = i0 + ti, j = j0 + tj;
+    if (i >= G.nx || j >= G.ny) continue;
+    const int64_t o = (int64_t)j * G.nx + i;
+    const uint8_t nb = nbr_flags(G, mask, i, j);
+    Y.nb[o] = nb;
+    if (!(nb & NB_SELF)) {
+      Y.dg[o] = 1.0;
+      Y.ce[o] = 0.0;
+      Y.cn[o] = 0.0;
+      Y.b[o] = 0.0;
+      Y.x[o] = 0.0;
+      Y.dg32[o] = 1.0f;
+      Y.ce32[o] = 0.0f;
+      Y.cn32[o] = 0.0f;
+      continue;
+    }
+    const int w = (tj + 1) * RGX + (ti + 1);
+    const Face2 fw = face_coef(R, G, dt, w - 1, w, true), fe = face_coef(R, G, dt, w, w + 1, true);
+    const Face2 fs = face_coef(R, G, dt, w - RGX, w, false);
+    const Face2 fn = face_coef(R, G, dt, w, w + RGX, false);
+    const double hs = R.h[w];
+    const double x = (i + 0.5) * G.dx, y = (j + 0.5) * G.dy;
+    const BedRate br = bed_rate(M, body_shape(c, x - M.X, y - c.y0));
+    const double al = 4.0 + R.Dx[w] * R.Dx[w] + R.Dy[w] * R.Dy[w];
+    const double s22 = 3.0 * dt / (G.rho * hs);
+    const double f2 = -2.0 * br.d_t - 2.0 * kt[o] / hs -
+                      (R.Dx[w] * mt[o] + R.Dy[w] * nt[o]) / (2.0 * hs) -
+                      dt * al * R.phi[w] / (2.0 * G.rho * hs);
+    const double dg = s22 + fw.K * fw.b * fw.b + fe.K * fe.a * fe.a + fs.K * fs.b * fs.b +
+                      fn.K * fn.a * fn.a;
+    const double ce = (nb & NB_E) ? fe.K * fe.a * fe.b : 0.0;
+    const double cn = (nb & NB_N) ? fn.K * fn.a * fn.b : 0.0;
+    Y.dg[o] = dg;
+    Y.ce[o] = ce;
+    Y.cn[o] = cn;
+    Y.b[o] = f2 + fw.b * fw.qp + fe.a * fe.qp + fs.b * fs.qp + fn.a * fn.qp;
+    Y.dg32[o] = (float)dg;
+    Y.ce32[o] = (float)ce;
+    Y.cn32[o] = (float)cn;
+    Y.x[o] = warm ? p_prev[o] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// persistent PCG with FP64 refinement
+// ---------------------------------------------------------------------------
+// bounded waits: a wait longer than this aborts the solve (status bit) so that
+// the kernel always ends; wall_clock64 ticks at 100 MHz
+constexpr unsigned long long WAIT_TICKS = 50000000ull;
+
+struct Bar {
+  unsigned* flags;  // [G] arrival epochs, [G] = release epoch
+  int* status;
+};
+
+__device__ __forceinline__ bool aborted(const Bar& B) {
+  return (__hip_atomic_load(B.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_ABORT) != 0;
+}
+
+// waits until *w >= epoch; false when the wait timed out or another block aborted
+__device__ bool wait_epoch(const Bar& B, unsigned* w, unsigned epoch) {
+  const unsigned long long t0 = wall_clock64();
+  while (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    if (aborted(B)) return false;
+    if (wall_clock64() - t0 > WAIT_TICKS) {
+      atomicOr(B.status, ST_ABORT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// grid-wide barrier over co-resident blocks: each block raises its own flag,
+// block 0 waits for all flags and releases everyone.  Returns false (in every
+// thread of the block) when the solve was aborted.
+__device__ bool grid_sync(const Bar& B, unsigned epoch) {
+  const int G = gridDim.x;
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __threadfence();
+    __hip_atomic_store(&B.flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int b = threadIdx.x; b < G; b += blockDim.x)
+      if (!wait_epoch(B, &B.flags[b], epoch)) ok = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_store(&B.flags[G], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    if (!wait_epoch(B, &B.flags[G], epoch)) ok = 0;
+  }
+  __syncthreads();
+  __threadfence();
+  const bool r = ok != 0 && !aborted(B);
+  __syncthreads();
+  return r;
+}
+
+// block partial sums (fixed order) of NV values -> part[slot + v][blockIdx]
+template <int NV>
+__device__ void block_partials(double (&v)[NV], double* part, int slot) {
+  __shared__ double sh[NV][NT2 / 64];
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const double s = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      double s = 0.0;
+      for (int w = 0; w < NT2 / 64; w++) s += sh[k][w];
+      part[(int64_t)(slot + k) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// the same fixed-order total of the partials in every block
+__device__ double grid_total(const double* part, int slot) {
+  __shared__ double tot;
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 64)
+      s += __hip_atomic_load(&part[(int64_t)slot * gridDim.x + b], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    s = wave_sum(s);
+    if (threadIdx.x == 0) tot = s;
+  }
+  __syncthreads();
+  const double r = tot;
+  __syncthreads();
+  return r;
+}
+
+template <typename R>
+struct PcgArgs {
+  int nx, ny, tiles_x;
+  const int* tile_list;
+  const int* n_list;
+  const uint8_t* nb;
+  const double *dg, *ce, *cn, *b;
+  double* x;
+  const R *dgR, *ceR, *cnR;
+  R *r, *z, *pa, *pb, *q, *e;
+  double* part;
+  Bar bar;
+  int* iters;
+  double* rel;
+  double tol, tol_in;
+  int max_iter;
+};
+
+template <typename T, typename V>
+__device__ __forceinline__ V apply5(const T* dg, const T* ce, const T* cn, const V* v, uint8_t nb,
+                                    int64_t o, int nx) {
+  V a = (V)dg[o] * v[o];
+  if (nb & NB_E) a += (V)ce[o] * v[o + 1];
+  if (nb & NB_W) a += (V)ce[o - 1] * v[o - 1];
+  if (nb & NB_N) a += (V)cn[o] * v[o + nx];
+  if (nb & NB_S) a += (V)cn[o - nx] * v[o - nx];
+  return a;
+}
+
+// loops over this block's active tiles and calls f(o, nb) for each marked cell
+template <typename F>
+__device__ __forceinline__ void for_cells(int nx, int ny, int tiles_x, const int* tile_list,
+                                          int nlist, const uint8_t* nbf, F f) {
+  for (int t = blockIdx.x; t < nlist; t += gridDim.x) {
+    const int tile = tile_list[t];
+    const int i0 = (tile % tiles_x) * TX2, j0 = (tile / tiles_x) * TY2;
+    for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+      const int i = i0 + cc % TX2, j = j0 + cc / TX2;
+      if (i >= nx || j >= ny) continue;
+      const int64_t o = (int64_t)j * nx + i;
+      const uint8_t nb = nbf[o];
+      if (nb & NB_SELF) f(o, nb);
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
+  const int nlist = *A.n_list;
+  const int nx = A.nx;
+  unsigned epoch = 0;
+  double bb = 0.0, rr = 0.0;
+  int total = 0, sweep = 0;
+  bool done = false;
+  for (;;) {
+    // FP64 residual of the current solution
+    {
+      double v[2] = {0.0, 0.0};
+      for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
+        const double rv = A.b[o] - apply5<double, double>(A.dg, A.ce, A.cn, A.x, nb, o, nx);
+        A.r[o] = (R)rv;
+        v[0] += rv * rv;
+        if (sweep == 0) v[1] += A.b[o] * A.b[o];
+      });
+      block_partials<2>(v, A.part, 0);
+      if (!grid_sync(A.bar, ++epoch)) return;
+      rr = grid_total(A.part, 0);
+      if (sweep == 0) bb = grid_total(A.part, 1);
+    }
+    const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    if (rel <= A.tol) {
+      done = true;
+      if (blockIdx.x == 0 && threadIdx.x == 0) *A.rel = rel;
+      break;
+    }
+    if (total >= A.max_iter) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *A.rel = rel;
+        atomicOr(A.bar.status, ST_NOCONV);
+      }
+      break;
+    }
+    // inner PCG on A_R e = r (Jacobi), stopped at ||r_k|| <= tol_abs
+    const double tol_abs = (sizeof(R) == 4) ? A.tol_in * sqrt(rr) : 0.5 * A.tol * sqrt(bb);
+    double rz;
+    {
+      double v[1] = {0.0};
+      for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
+        const R zz = A.r[o] / A.dgR[o];
+        A.z[o] = zz;
+        A.e[o] = R(0);
+        v[0] += (double)A.r[o] * (double)zz;
+      });
+      block_partials<1>(v, A.part, 0);
+      if (!grid_sync(A.bar, ++epoch)) return;
+      rz = grid_total(A.part, 0);
+    }
+    R* pold = A.pa;
+    R* pnew = A.pb;
+    double beta = 0.0;
+    for (int it = 0;; it++) {
+      // p = z + beta p_old (first: p = z), q = A p, p.q
+      {
+        double v[1] = {0.0};
+        const R bt = (R)beta;
+        for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
+          auto pv = [&](int64_t u) { return it == 0 ? A.z[u] : A.z[u] + bt * pold[u]; };
+          const R pc = pv(o);
+          R a = A.dgR[o] * pc;
+          if (nb & NB_E) a += A.ceR[o] * pv(o + 1);
+          if (nb & NB_W) a += A.ceR[o - 1] * pv(o - 1);
+          if (nb & NB_N) a += A.cnR[o] * pv(o + nx);
+          if (nb & NB_S) a += A.cnR[o - nx] * pv(o - nx);
+          pnew[o] = pc;
+          A.q[o] = a;
+          v[0] += (double)pc * (double)a;
+        });
+        block_partials<1>(v, A.part, 0);
+        if (!grid_sync(A.bar, ++epoch)) return;
+      }
+      const double pq = grid_total(A.part, 0);
+      const R alpha = (R)(pq != 0.0 ? rz / pq : 0.0);
+      double rz_new, rr_in;
+      {
+        double v[2] = {0.0, 0.0};
+        for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
+          A.e[o] += alpha * pnew[o];
+          const R rv = A.r[o] - alpha * A.q[o];
+          A.r[o] = rv;
+          const R zz = rv / A.dgR[o];
+          A.z[o] = zz;
+          v[0] += (double)rv * (double)zz;
+          v[1] += (double)rv * (double)rv;
+        });
+        block_partials<2>(v, A.part, 0);
+        if (!grid_sync(A.bar, ++epoch)) return;
+        rz_new = grid_total(A.part, 0);
+        rr_in = grid_total(A.part, 1);
+      }
+      total++;
+      if (sqrt(rr_in) <= tol_abs || total >= A.max_iter || !(rz_new == rz_new)) break;
+      beta = rz_new / rz;
+      rz = rz_new;
+      R* tmp = pold;
+      pold = pnew;
+      pnew = tmp;
+    }
+    // x += e (FP64)
+    for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb,
+              [&](int64_t o, uint8_t nb) { A.x[o] += (double)A.e[o]; });
+    if (!grid_sync(A.bar, ++epoch)) return;
+    sweep++;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
+  (void)done;
+}
+
+__global__ void k_bar_reset(unsigned* flags, int n) {
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) flags[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// projection
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT2) k_correct2d(G2 G, const double* __restrict__ ht,
+                                                   const double* __restrict__ mt,
+                                                   const double* __restrict__ nt,
+                                                   const double* __restrict__ kt,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const int* tile_list, const int* n_list,
+                                                   const double* t_in, const double* dt_in,
+                                                   const double* __restrict__ x, double* hu,
+                                                   double* hv, double* hw, double* p) {
+  if ((int)blockIdx.x >= *n_list) return;
+  __shared__ Ring R;
+  const int tile = tile_list[blockIdx.x];
+  const int i0 = (tile % G.tiles_x) * TX2, j0 = (tile / G.tiles_x) * TY2;
+  const Chan c = G.ch[0];
+  const double dt = dt_in[0];
+  const Motion M = body_motion(c, t_in[0] + dt);
+  fill_ring(R, G, c, M, ht, mt, nt, i0, j0);
+  __syncthreads();
+  const int nx = G.nx;
+  for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+    const int ti = cc % TX2, tj = cc / TX2;
+    const int i = i0 + ti, j = j0 + tj;
+    if (i >= G.nx || j >= G.ny) continue;
+    const int64_t o = (int64_t)j * nx + i;
+    if (!mask[o]) continue;
+    auto pv = [&](int a, int b) -> double {
+      if (a < 0 || a >= G.nx || b < 0 || b >= G.ny) return 0.0;
+      const int64_t u = (int64_t)b * nx + a;
+      return mask[u] ? x[u] : 0.0;
+    };
+    const int w = (tj + 1) * RGX + (ti + 1);
+    const Face2 fw = face_coef(R, G, dt, w - 1, w, true), fe = face_coef(R, G, dt, w, w + 1, true);
+    const Face2 fs = face_coef(R, G, dt, w - RGX, w, false);
+    const Face2 fn = face_coef(R, G, dt, w, w + RGX, false);
+    const double pc = x[o];
+    const double dqw = fw.fd - fw.K * (fw.a * pv(i - 1, j) + fw.b * pc);
+    const double dqe = fe.fd - fe.K * (fe.a * pc + fe.b * pv(i + 1, j));
+    const double dqs = fs.fd - fs.K * (fs.a * pv(i, j - 1) + fs.b * pc);
+    const double dqn = fn.fd - fn.K * (fn.a * pc + fn.b * pv(i, j + 1));
+    const double dm = 0.5 * (dqw + dqe), dn = 0.5 * (dqs + dqn);
+    const double al = 4.0 + R.Dx[w] * R.Dx[w] + R.Dy[w] * R.Dy[w];
+    const double Pb = 1.5 * pc - G.rho * (R.Dx[w] * dm + R.Dy[w] * dn) / (4.0 * dt) +
+                      al * R.phi[w] / 4.0;
+    hu[o] = mt[o] + dm;
+    hv[o] = nt[o] + dn;
+    hw[o] = kt[o] + dt * Pb / G.rho;
+    if (p) p[o] = pc;
+  }
+}
+
+__global__ void k_advance2d(double* t, double* dt, unsigned long long* smax, int* step) {
+  if (threadIdx.x == 0) {
+    t[0] += dt[0];
+    smax[0] = 0ull;
+    *step += 1;
+  }
+}
+
+
+Sys2 sys_of(Ctx2D* x) {
+  Sys2 Y;
+  Y.dg = x->dg;
+  Y.ce = x->ce;
+  Y.cn = x->cn;
+  Y.b = x->b;
+  Y.x = x->x;
+  Y.dg32 = x->dg32;
+  Y.ce32 = x->ce32;
+  Y.cn32 = x->cn32;
+  Y.nb = x->nb;
+  return Y;
+}
+
+template <typename R>
+PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
+  PcgArgs<R> A;
+  A.nx = x->nx;
+  A.ny = x->ny;
+  A.tiles_x = x->tiles_x;
+  A.tile_list = x->tile_list;
+  A.n_list = x->n_tiles_act;
+  A.nb = x->nb;
+  A.dg = x->dg;
+  A.ce = x->ce;
+  A.cn = x->cn;
+  A.b = x->b;
+  A.x = x->x;
+  A.part = x->part;
+  A.bar.flags = x->bar;
+  A.bar.status = x->status;
+  A.iters = x->iters;
+  A.rel = x->rel;
+  A.tol = c->tol;
+  A.max_iter = c->max_iter;
+  return A;
+}
+
+PcgArgs<float> pcg_args32(const swe_nh_config* c, Ctx2D* x) {
+  PcgArgs<float> A = pcg_common<float>(c, x);
+  A.dgR = x->dg32;
+  A.ceR = x->ce32;
+  A.cnR = x->cn32;
+  A.r = x->r;
+  A.z = x->z;
+  A.pa = x->pa;
+  A.pb = x->pb;
+  A.q = x->q;
+  A.e = x->e;
+  A.tol_in = 1e-4;  // each FP32 solve reduces the FP64 residual by this factor
+  return A;
+}
+
+PcgArgs<double> pcg_args64(const swe_nh_config* c, Ctx2D* x) {
+  PcgArgs<double> A = pcg_common<double>(c, x);
+  A.dgR = x->dg;
+  A.ceR = x->ce;
+  A.cnR = x->cn;
+  A.r = x->r64;
+  A.z = x->z64;
+  A.pa = x->pa64;
+  A.pb = x->pb64;
+  A.q = x->q64;
+  A.e = x->e64;
+  A.tol_in = 0.0;
+  return A;
+}
+
+__global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __restrict__ mask,
+                                double* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = mask[i] ? x[i] : 0.0;
+}
+
+void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(256), 0, s, x->bar, x->grid_pcg);
+  if (c->precision == 1)
+    hipLaunchKernelGGL(k_pcg2d<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, pcg_args32(c, x));
+  else
+    hipLaunchKernelGGL(k_pcg2d<double>, dim3(x->grid_pcg), dim3(NT2), 0, s, pcg_args64(c, x));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host entry points
+// ---------------------------------------------------------------------------
+void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
+  auto take = [&](size_t bytes) -> char* {
+    *off = (*off + 255) & ~size_t(255);
+    char* p = base ? base + *off : nullptr;
+    *off += bytes ? bytes : 1;
+    return p;
+  };
+  const int64_t N = (int64_t)c->nx * c->ny;
+  x->nx = c->nx;
+  x->ny = c->ny;
+  x->tiles_x = (c->nx + TX2 - 1) / TX2;
+  x->tiles_y = (c->ny + TY2 - 1) / TY2;
+  x->ntiles = x->tiles_x * x->tiles_y;
+  x->grid_pcg = x->ntiles < 512 ? x->ntiles : 512;
+  x->ht = (double*)take(8 * N);
+  x->mt = (double*)take(8 * N);
+  x->nt = (double*)take(8 * N);
+  x->kt = (double*)take(8 * N);
+  x->mask_ws = (uint8_t*)take(N);
+  x->tile_cnt = (int*)take(4 * x->ntiles);
+  x->tile_list = (int*)take(4 * x->ntiles);
+  x->n_tiles_act = (int*)take(4);
+  x->n_act = (int*)take(4);
+  x->dg = (double*)take(8 * N);
+  x->ce = (double*)take(8 * N);
+  x->cn = (double*)take(8 * N);
+  x->b = (double*)take(8 * N);
+  x->x = (double*)take(8 * N);
+  x->nb = (uint8_t*)take(N);
+  x->dg32 = (float*)take(4 * N);
+  x->ce32 = (float*)take(4 * N);
+  x->cn32 = (float*)take(4 * N);
+  if (c->precision == 1) {
+    x->r = (float*)take(4 * N);
+    x->z = (float*)take(4 * N);
+    x->pa = (float*)take(4 * N);
+    x->pb = (float*)take(4 * N);
+    x->q = (float*)take(4 * N);
+    x->e = (float*)take(4 * N);
+  } else {
+    x->r64 = (double*)take(8 * N);
+    x->z64 = (double*)take(8 * N);
+    x->pa64 = (double*)take(8 * N);
+    x->pb64 = (double*)take(8 * N);
+    x->q64 = (double*)take(8 * N);
+    x->e64 = (double*)take(8 * N);
+  }
+  x->part = (double*)take(8 * 4 * (size_t)x->grid_pcg);
+  x->bar = (unsigned*)take(4 * ((size_t)x->grid_pcg + 1));
+  x->iters = (int*)take(4);
+  x->rel = (double*)take(8);
+}
+
+int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
+  x->t = k1.t;
+  x->dt = k1.dt;
+  x->smax = k1.smax;
+  x->status = k1.status;
+  x->step = k1.step;
+  x->ch = k1.ch;
+  // the persistent solver needs all its blocks resident at once
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SWE_NH_EHIP;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SWE_NH_EHIP;
+  hipError_t e = c->precision == 1
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg2d<float>, NT2, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg2d<double>, NT2, 0);
+  if (e != hipSuccess || per_cu < 1) return SWE_NH_EHIP;
+  const int cap = cus * per_cu;
+  if (x->grid_pcg > cap) x->grid_pcg = cap;
+  int zi[2] = {0, 0};
+  if (hipMemcpy(x->n_tiles_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  if (hipMemcpy(x->n_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  if (hipMemcpy(x->iters, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  (void)s;
+  return SWE_NH_OK;
+}
+
+static void enqueue_nh2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
+                         const double* mt, const double* nt, const double* kt,
+                         const uint8_t* mask, const double* t_in, const double* dt_in,
+                         const double* p_prev, double* hu, double* hv, double* hw, double* p) {
+  const G2 G = make_g2(c, x);
+  hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
+                     x->n_tiles_act, x->n_act);
+  hipLaunchKernelGGL(k_assemble2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
+                     x->tile_list, x->n_tiles_act, t_in, dt_in, sys_of(x), p_prev,
+                     (int)(c->warm && p_prev));
+  launch_solve2d(c, x, s);
+  if (hu)
+    hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
+                       x->tile_list, x->n_tiles_act, t_in, dt_in, x->x, hu, hv, hw, p);
+}
+
+void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, double* hu,
+                    double* hv, double* hw, double* p, uint8_t* mask) {
+  const G2 G = make_g2(c, x);
+  uint8_t* M = mask ? mask : x->mask_ws;
+  hipLaunchKernelGGL(k_speed2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw);
+  hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw, x->ht, x->mt,
+                     x->nt, x->kt, (const double*)x->t, (const double*)x->dt, 1);
+  // the mask pass clears p only off the new marked area: p keeps the previous
+  // pressure where it is needed as the initial guess
+  hipLaunchKernelGGL(k_mask2d, dim3(x->ntiles), dim3(NT2), 0, s, G, x->ht, x->mt, x->nt, x->kt,
+                     (const double*)x->t, (const double*)x->dt, -1, M, x->tile_cnt, h, hu, hv,
+                     hw, p, 1);
+  if (c->crit != SWE_NH_CRIT_NONE) {
+    enqueue_nh2d(c, x, s, x->ht, x->mt, x->nt, x->kt, M, x->t, x->dt, c->warm ? p : nullptr, hu,
+                 hv, hw, p);
+  } else {
+    hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
+                       x->n_tiles_act, x->n_act);
+  }
+  hipLaunchKernelGGL(k_advance2d, dim3(1), dim3(64), 0, s, x->t, x->dt, x->smax, x->step);
+}
+
+void launch_pred2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,
+                         const double* hu, const double* hv, const double* hw, const double* t_in,
+                         const double* dt_in, double* ht, double* mt, double* nt, double* kt) {
+  hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, make_g2(c, x), h, hu, hv, hw, ht,
+                     mt, nt, kt, t_in, dt_in, 0);
+}
+
+void launch_mask2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
+                         const double* mt, const double* nt, const double* kt,
+                         const double* t_in, const double* dt_in, int mode, uint8_t* mask) {
+  const G2 G = make_g2(c, x);
+  hipLaunchKernelGGL(k_mask2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, t_in,
+                     dt_in, mode, mask, x->tile_cnt, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     0);
+  hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
+                     x->n_tiles_act, x->n_act);
+}
+
+void solve_pressure2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
+                      const double* mt, const double* nt, const double* kt, const uint8_t* mask,
+                      const double* t_in, const double* dt_in, double* p) {
+  const G2 G = make_g2(c, x);
+  const int64_t N = (int64_t)x->nx * x->ny;
+  hipLaunchKernelGGL(k_count2d, dim3(x->ntiles), dim3(NT2), 0, s, G, mask, x->tile_cnt);
+  enqueue_nh2d(c, x, s, ht, mt, nt, kt, mask, t_in, dt_in, c->warm ? p : nullptr, nullptr,
+               nullptr, nullptr, nullptr);
+  // p = x on the marked cells, 0 elsewhere
+  hipLaunchKernelGGL(k_copy_masked2d, dim3(2048), dim3(256), 0, s, (const double*)x->x, mask, p,
+                     N);
+}
+
+void correct2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
+               const double* mt, const double* nt, const double* kt, const uint8_t* mask,
+               const double* p, const double* t_in, const double* dt_in, double* m_out,
+               double* n_out, double* k_out) {
+  const G2 G = make_g2(c, x);
+  const int64_t N = (int64_t)x->nx * x->ny;
+  hipLaunchKernelGGL(k_count2d, dim3(x->ntiles), dim3(NT2), 0, s, G, mask, x->tile_cnt);
+  hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
+                     x->n_tiles_act, x->n_act);
+  launch_copy(mt, m_out, N, s);
+  launch_copy(nt, n_out, N, s);
+  launch_copy(kt, k_out, N, s);
+  hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
+                     x->tile_list, x->n_tiles_act, t_in, dt_in, p, m_out, n_out, k_out, nullptr);
+}
+
+void time_stage2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, int stage, double* h,
+                  double* hu, double* hv, double* hw, double* p) {
+  const G2 G = make_g2(c, x);
+  switch (stage) {
+    case 0:
+      hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw, x->ht,
+                         x->mt, x->nt, x->kt, (const double*)x->t, (const double*)x->dt, 0);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_mask2d, dim3(x->ntiles), dim3(NT2), 0, s, G, x->ht, x->mt, x->nt, x->kt,
+                         (const double*)x->t, (const double*)x->dt, 0, x->mask_ws, x->tile_cnt,
+                         nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+      break;
+    case 2:
+      launch_solve2d(c, x, s);
+      break;
+    default:
+      hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, x->ht, x->mt, x->nt,
+                         x->kt, x->mask_ws, x->tile_list, x->n_tiles_act, (const double*)x->t,
+                         (const double*)x->dt, x->x, hu, hv, hw, p);
+  }
+}
+
 }  // namespace swenh

@@ -282,6 +282,7 @@ int reset_status(swe_nh_ctx* c) {
 int status_code(int bits) {
   if (bits & ST_NAN) return SWE_NH_ENAN;
   if (bits & ST_DRY) return SWE_NH_EDRY;
+  if (bits & ST_ABORT) return SWE_NH_EHIP;  // a device-side wait timed out
   if (bits & ST_NOCONV) return SWE_NH_ENOCONV;
   return SWE_NH_OK;
 }
@@ -383,11 +384,12 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   INIT_COPY(c->n_act, zi, sizeof(int));
   INIT_COPY(c->conv, zi, sizeof(int));
   INIT_COPY(c->iters, zi, sizeof(int));
-  INIT_COPY(c->T64.n, zi, sizeof(int) * TRI_MAX_LEVELS);
+  if (cfg->dim == 1) INIT_COPY(c->T64.n, zi, sizeof(int) * TRI_MAX_LEVELS);
   if (cfg->precision == 1 && cfg->dim == 1) INIT_COPY(c->T32.n, zi, sizeof(int) * TRI_MAX_LEVELS);
 #undef INIT_COPY
   if (rc == SWE_NH_OK && cfg->dim == 2) rc = init2d(&c->cfg, &c->c2, c->k1, c->stream);
   if (rc != SWE_NH_OK) {
+    (void)hipGetLastError();  // do not leave a failed call behind for the caller's next check
     hipStreamDestroy(c->cap);
     delete c;
     return rc;
@@ -515,7 +517,8 @@ int swe_nh_mask(swe_nh_ctx* c, const double* ht, const double* mt, const double*
     launch_scan(c->k1.tile_cnt, c->k1.tile_off, c->k1.ntiles, c->n_act, c->stream);
     nact = c->n_act;
   } else {
-    launch_mask2d_stage(&c->cfg, &c->c2, c->stream, ht, mt, nt, kt, c->stage_t, mode, mask_out);
+    launch_mask2d_stage(&c->cfg, &c->c2, c->stream, ht, mt, nt, kt, c->stage_t, c->stage_dt, mode,
+                        mask_out);
     nact = c->c2.n_act;
   }
   rc = after_launch(c);

@@ -12,7 +12,7 @@ namespace swenh {
 constexpr double kPi = 3.14159265358979323846;
 
 // status bits accumulated on the device during a step
-enum : int32_t { ST_DRY = 1, ST_NAN = 2, ST_NOCONV = 4 };
+enum : int32_t { ST_DRY = 1, ST_NAN = 2, ST_NOCONV = 4, ST_ABORT = 8 };
 
 // one independent 1D channel (or the single 2D domain)
 struct Chan {

@@ -1,0 +1,206 @@
+"""GPU parity of the 2D HIP path against the FP64 oracle (through the C ABI).
+
+Stage tests feed both sides the same inputs.  The elliptic solves are
+iterative on both sides: they agree to about cond(A) * tol, so the GPU solves
+to a tolerance tight enough for the FP64 bar (relative L2 <= 1e-10) and the
+FP32 + FP64-refinement bar (<= 1e-6).  At the full 2048 x 2048 size the
+predictor and the mask are compared cell by cell and the solve is checked by
+the oracle's own residual of the GPU pressure."""
+import numpy as np
+import pytest
+
+import oracle as O
+import swe_inputs as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17025_amd import swe_nh
+    return swe_nh
+
+
+def dt_(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(g, r):
+    g = g.detach().cpu().numpy() if hasattr(g, "detach") else np.asarray(g)
+    return np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300)
+
+
+def case(nx=70, ny=37, seed=3):
+    return S.random_case_2d(nx, ny, seed=seed, dx=0.5, dy=0.4)
+
+
+def test_predictor_stage_parity(B):
+    c = case()
+    ctx = B.context_2d(c, crit=S.CRIT_GLOBAL, tol=1e-12, max_iter=2000)
+    out = [torch.empty((c.ny, c.nx), dtype=torch.float64, device=DEV) for _ in range(4)]
+    t0, dt = 0.13, 0.02
+    ctx.predict(dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw), t0, dt, *out)
+    assert ctx.sync_stats()["status"] == 0
+    ref = O.predict_2d(c.ds, c.dx, c.dy, c.body, O.phys_struct(), t0, dt, c.h, c.hu, c.hv, c.hw)
+    for g, r in zip(out, ref):
+        assert rel(g, r) <= 1e-13
+
+
+def _safe_knh(ind, k):
+    while np.min(np.abs(ind - k)) <= 1e-9 * k:
+        k *= 1.0 + 1e-6
+    return k
+
+
+@pytest.mark.parametrize("crit", range(8))
+@pytest.mark.parametrize("e", [0, 1, 3])
+def test_mask_stage_bit_exact(B, crit, e):
+    c = case(seed=5)
+    t1 = 0.4
+    ind = O.indicator_2d(c.ds, c.dx, c.dy, c.body, O.phys_struct(crit=min(crit, 5)), t1, c.h, c.hu,
+                         c.hv, c.hw)
+    k = float(np.percentile(ind, 80)) if crit < 6 else 1e-3
+    if crit < 6:
+        k = _safe_knh(ind, k)
+    ctx = B.context_2d(c, crit=crit, k_nh=k, enlarge=e, tol=1e-10, max_iter=100)
+    m = torch.zeros((c.ny, c.nx), dtype=torch.uint8, device=DEV)
+    na = ctx.mask(dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw), t1, 0, m)
+    ref, cnt = O.mask_2d(c.ds, c.dx, c.dy, c.body, O.phys_struct(crit=crit, k_nh=k, enlarge=e), t1,
+                         c.h, c.hu, c.hv, c.hw)
+    assert np.array_equal(m.cpu().numpy(), ref)
+    assert na == cnt
+
+
+def _mask(c, seed):
+    rng = np.random.default_rng(seed)
+    m = (rng.random((c.ny, c.nx)) < 0.2).astype(np.uint8)
+    m[5:30, 10:60] = 1
+    m[0:4, 0:6] = 1   # a patch at the corner walls
+    m[20, :] = 1      # a row spanning every tile column
+    return m
+
+
+@pytest.mark.parametrize("precision,tol,bar", [(0, 1e-13, 1e-10), (1, 1e-10, 1e-6)])
+def test_pressure_and_projection_stage_parity(B, precision, tol, bar):
+    c = case(seed=7)
+    m = _mask(c, 1)
+    t0, dt = 0.2, 0.01
+    ctx = B.context_2d(c, crit=S.CRIT_ETA_D, precision=precision, tol=tol, max_iter=20000, warm=0)
+    p = torch.full((c.ny, c.nx), 3.0, dtype=torch.float64, device=DEV)
+    args = (dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw))
+    it, rr = ctx.solve_pressure(*args, torch.tensor(m, device=DEV), t0, dt, p)
+    st = ctx.sync_stats()
+    assert st["status"] == 0, st
+    assert rr <= tol and it > 0
+    ph = O.phys_struct()
+    cell, xf, yf = O.nh_coeffs_2d(c.ds, c.dx, c.dy, c.body, ph, t0 + dt, dt, c.h, c.hu, c.hv, c.hw)
+    rhs = O.nh_rhs_2d(cell, xf, yf, m)
+    pref, _, _ = O.cg_2d(cell, xf, yf, m, rhs, tol=1e-14)
+    assert rel(p, pref) <= bar
+    assert np.all(p.cpu().numpy()[m == 0] == 0.0)
+    mref, nref, kref = O.nh_correct_2d(cell, xf, yf, dt, 1000.0, c.hu, c.hv, c.hw, m, pref)
+    outs = [torch.empty_like(args[0]) for _ in range(3)]
+    ctx.correct(*args, torch.tensor(m, device=DEV), dt_(pref), t0, dt, *outs)
+    assert ctx.sync_stats()["status"] == 0
+    assert rel(outs[0], mref) <= 1e-12
+    assert rel(outs[1], nref) <= 1e-12
+    assert rel(outs[2] - args[3], kref - c.hw) <= 1e-11
+
+
+def run2d(B, c, nsteps, **kw):
+    ctx = B.context_2d(c, **kw)
+    ctx.set_time(c.t0)
+    h, hu, hv, hw = dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw)
+    p = torch.zeros_like(h)
+    m = torch.zeros((c.ny, c.nx), dtype=torch.uint8, device=DEV)
+    ctx.step(h, hu, hv, hw, p, m, nsteps=nsteps)
+    return ctx, ctx.sync_stats(), h, hu, hv, hw, p, m
+
+
+@pytest.mark.parametrize("crit", [S.CRIT_GLOBAL, S.CRIT_ETA_D, S.CRIT_NONE])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_steps_parity(B, crit, precision):
+    c = case(nx=66, ny=50, seed=11)
+    tol = 1e-13 if precision == 0 else 1e-11
+    kw = dict(crit=crit, k_nh=4e-3, enlarge=1, cfl=0.4, precision=precision, tol=tol,
+              max_iter=20000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 8, **kw)
+    assert st["status"] == 0, st
+    ref = O.Sim2D(c, O.phys_struct(crit=crit, k_nh=4e-3, enlarge=1, tol=1e-14), cfl=0.4).step(8)
+    assert np.array_equal(m.cpu().numpy(), ref.mask)
+    assert st["n_active"] == ref.last_active
+    bar = 1e-10 if precision == 0 else 1e-6
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw)):
+        assert rel(g, r) <= bar
+    if crit != S.CRIT_NONE:
+        assert rel(p, ref.p) <= bar
+
+
+def test_shelf_reduced_fp32_refinement(B):
+    """the 2D shelf with a moving mound, reduced to 256 x 256 (same dx, depth
+    statistics and mound), adaptive |eta/d|, FP32 PCG + FP64 refinement"""
+    c = S.shelf_case_2d(nx=256, ny=256, x0=60.0, y0=128.0, amp=3.0, width=60.0 / 4)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1, tol=1e-10,
+              max_iter=20000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 20, **kw)
+    assert st["status"] == 0, st
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, tol=1e-13),
+                  cfl=0.5).step(20)
+    assert np.array_equal(m.cpu().numpy(), ref.mask) and ref.last_active > 0
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-6
+
+
+def test_full_size_shelf_properties(B):
+    """2048 x 2048 shelf, in the benchmark's launch configuration: predictor
+    and mask cell by cell against the oracle, the pressure through the
+    oracle's residual, mass conservation"""
+    c = S.shelf_case_2d()
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1, tol=1e-10,
+              max_iter=20000, warm=1)
+    ctx = B.context_2d(c, **kw)
+    ctx.set_time(c.t0)
+    h, hu, hv, hw = dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw)
+    p = torch.zeros_like(h)
+    m = torch.zeros((c.ny, c.nx), dtype=torch.uint8, device=DEV)
+    ctx.step(h, hu, hv, hw, p, m, nsteps=30)
+    st = ctx.sync_stats()
+    assert st["status"] == 0, st
+    t = float(ctx.get_time()[0])
+    # one more step driven stage by stage from the same state
+    hs, hus, hvs, hws = (a.cpu().numpy() for a in (h, hu, hv, hw))
+    mass0 = hs.sum()
+    dtv = 0.5 / O.max_rate_2d(hs, hus, hvs, c.dx, c.dy)
+    outs = [torch.empty_like(h) for _ in range(4)]
+    ctx.predict(h, hu, hv, hw, t, dtv, *outs)
+    ref = O.predict_2d(c.ds, c.dx, c.dy, c.body, O.phys_struct(), t, dtv, hs, hus, hvs, hws)
+    for g, r in zip(outs, ref):
+        assert rel(g, r) <= 1e-13
+    ht, mt, nt, kt = ref
+    ph = O.phys_struct(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1)
+    mref, cnt = O.mask_2d(c.ds, c.dx, c.dy, c.body, ph, t + dtv, ht, mt, nt, kt)
+    mg = torch.zeros_like(m)
+    na = ctx.mask(*[dt_(a) for a in ref], t + dtv, 0, mg)
+    assert na == cnt > 0 and np.array_equal(mg.cpu().numpy(), mref)
+    pg = torch.zeros_like(h)
+    it, rr = ctx.solve_pressure(*[dt_(a) for a in ref], mg, t, dtv, pg)
+    assert rr <= 1e-10
+    cell, xf, yf = O.nh_coeffs_2d(c.ds, c.dx, c.dy, c.body, ph, t + dtv, dtv, ht, mt, nt, kt)
+    rhs = O.nh_rhs_2d(cell, xf, yf, mref)
+    r = rhs - O.nh_apply_2d(cell, xf, yf, mref, pg.cpu().numpy())
+    assert np.linalg.norm(r[mref == 1]) <= 1.01e-10 * np.linalg.norm(rhs[mref == 1])
+    assert abs(hs.sum() - c.h.sum()) <= 1e-12 * c.h.sum()
+    assert abs(mass0 - c.h.sum()) <= 1e-12 * c.h.sum()
+
+
+def test_deterministic_2d(B):
+    c = case(nx=80, ny=64, seed=2)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=4e-3, cfl=0.4, precision=1, tol=1e-10, max_iter=5000)
+    a = run2d(B, c, 5, **kw)
+    b = run2d(B, c, 5, **kw)
+    for x, y in zip(a[2:], b[2:]):
+        assert torch.equal(x, y)
