@@ -104,7 +104,8 @@ typedef struct {
   int32_t precision;        /* 0: FP64 solve; 1: FP32 inner solve + FP64 residual refinement */
   double tol;               /* ||b - A p||_2 <= tol ||b||_2 (2D PCG, and 1D refinement) */
   int32_t max_iter;         /* PCG iterations (2D) or refinement sweeps (precision 1) */
-  int32_t warm;             /* 2D: 0 zero guess, 1 previous p (the p array on entry) */
+  int32_t warm;             /* 2D initial guess: 0 zero, 1 previous p (the p array on
+                               entry), 2 the warm-start network */
   const double* depth_static;  /* device [cells]: static depth d_s */
   const swe_nh_body* bodies;   /* host [batch] (1D) or [1] (2D) */
 } swe_nh_config;
@@ -182,6 +183,56 @@ int swe_nh_solve_pressure(swe_nh_ctx* ctx, const double* ht, const double* mt, c
 int swe_nh_correct(swe_nh_ctx* ctx, const double* ht, const double* mt, const double* nt,
                    const double* kt, const uint8_t* mask, const double* p, const double* t_host,
                    const double* dt_host, double* m_out, double* n_out, double* k_out);
+
+/* ---- learned warm start of the 2D pressure solve ----
+ * A fixed convolutional network (six 3x3 layers, channels 16 -> 32 -> 32 ->
+ * 32 -> 32 -> 32 -> 1, ReLU between layers, zero padding; 5 input features,
+ * the other 11 input channels zero) maps the predictor state to a guess of
+ * the non-hydrostatic pressure.  It is not part of the paper's method: the
+ * PCG still iterates to the same tolerance from the guess, so the guess only
+ * changes the iteration count.  Parameters are one FP32 vector: per layer
+ * the weights [Cout][3][3][Cin] then the Cout biases.  Activations are BF16
+ * NHWC; products accumulate in FP32 on the matrix cores.  Images must have a
+ * height and width that are multiples of 16. */
+size_t swe_nh_cnn_param_count(void);
+
+/* Device workspace for a batch of n images of h x w (0 if the shape is not supported). */
+size_t swe_nh_cnn_workspace_bytes(int32_t n, int32_t h, int32_t w);
+
+/* out[n][h][w] (FP32) = network(x), x: BF16 NHWC [n][h][w][16]; keeps the
+ * activations in ws for a following swe_nh_cnn_backward. */
+int swe_nh_cnn_forward(const float* params, const uint16_t* x, int32_t n, int32_t h, int32_t w,
+                       float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* grad (parameter-shaped, FP32) = d(sum(out * dout)) / d(params) for the
+ * batch of the last swe_nh_cnn_forward on the same workspace. */
+int swe_nh_cnn_backward(const float* params, const uint16_t* x, const float* dout, int32_t n,
+                        int32_t h, int32_t w, float* grad, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Weighted mean squared error: *loss = sum wt (out - target)^2 / sum wt
+ * (device scalar), dout = its gradient with respect to out. */
+int swe_nh_cnn_mse(const float* out, const float* target, const float* weight, int32_t n,
+                   int32_t h, int32_t w, float* dout, float* loss, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* One Adam step (Kingma & Ba 2015) on FP32 parameters; step counts from 1. */
+int swe_nh_cnn_adam(float* params, float* m, float* v, const float* grad, int64_t count,
+                    int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Network input of a 2D predictor state at time t1_host: BF16 NHWC
+ * [ny][nx][16] with eta / s0, hu / s1, hv / s2, -d_t / s3 and the mask, the
+ * other channels 0 (scales_host: the four s_k > 0). */
+int swe_nh_features(swe_nh_ctx* ctx, const double* ht, const double* mt, const double* nt,
+                    const uint8_t* mask, const double* t1_host, const double* scales_host,
+                    uint16_t* out);
+
+/* Use the network (device parameters, kept by reference) as the initial
+ * guess of the 2D pressure solve of swe_nh_step when the context was
+ * created with warm = 2: inputs scaled as in swe_nh_features, guess =
+ * p_scale * network output on the marked cells (Pa). */
+int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double* scales_host,
+                              double p_scale);
 
 /* Measurement: launch one stage kernel of the step nreps times back to back
  * on the context's stream, with the launch configuration swe_nh_step uses,

@@ -36,6 +36,14 @@ struct Ctx2D {
   unsigned* bar = nullptr;   // grid barrier: [grid_pcg] arrival flags + release word
   int* iters = nullptr;
   double* rel = nullptr;
+  // learned warm start (warm = 2)
+  char* cnn_ws = nullptr;
+  size_t cnn_bytes = 0;
+  uint16_t* feat = nullptr;
+  double* guess = nullptr;
+  const float* net = nullptr;
+  double fscale[4] = {1.0, 1.0, 1.0, 1.0};  // input scales of eta, hu, hv, -d_t
+  double p_scale = 1.0;
   // shared scalars from the 1D block (time, dt, speed, status, step)
   double* t = nullptr;
   double* dt = nullptr;

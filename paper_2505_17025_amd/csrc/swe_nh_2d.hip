@@ -16,6 +16,7 @@
 //                  barrier with bounded waits
 //   k_correct2d    projection of hu, hv and hw on the marked cells
 #include "swe_nh_2d.h"
+#include "swe_nh_cnn.h"
 #include "swe_nh_common.h"
 
 namespace swenh {
@@ -713,31 +714,36 @@ __device__ __forceinline__ bool aborted(const Bar& B) {
   return (__hip_atomic_load(B.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_ABORT) != 0;
 }
 
-// waits until *w >= epoch; false when the wait timed out or another block aborted
+// waits until *w >= epoch (relaxed polls, no cache maintenance per poll);
+// false when the wait timed out or another block aborted
 __device__ bool wait_epoch(const Bar& B, unsigned* w, unsigned epoch) {
   const unsigned long long t0 = wall_clock64();
-  while (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-    if (aborted(B)) return false;
-    if (wall_clock64() - t0 > WAIT_TICKS) {
-      atomicOr(B.status, ST_ABORT);
-      return false;
+  unsigned polls = 0;
+  while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    if ((++polls & 255u) == 0u) {
+      if (aborted(B)) return false;
+      if (wall_clock64() - t0 > WAIT_TICKS) {
+        atomicOr(B.status, ST_ABORT);
+        return false;
+      }
     }
     __builtin_amdgcn_s_sleep(1);
   }
   return true;
 }
 
-// grid-wide barrier over co-resident blocks: each block raises its own flag,
-// block 0 waits for all flags and releases everyone.  Returns false (in every
-// thread of the block) when the solve was aborted.
+// grid-wide barrier over co-resident blocks: each block raises its own flag
+// (release), block 0 waits for all flags and raises the release word, every
+// block waits for it (acquire).  Returns false in every thread of the block
+// when the solve was aborted.
 __device__ bool grid_sync(const Bar& B, unsigned epoch) {
   const int G = gridDim.x;
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    __threadfence();
-    __hip_atomic_store(&B.flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&B.flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (blockIdx.x == 0) {
@@ -745,15 +751,15 @@ __device__ bool grid_sync(const Bar& B, unsigned epoch) {
       if (!wait_epoch(B, &B.flags[b], epoch)) ok = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-      __threadfence();
-      __hip_atomic_store(&B.flags[G], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_store(&B.flags[G], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else if (threadIdx.x == 0) {
     if (!wait_epoch(B, &B.flags[G], epoch)) ok = 0;
   }
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
-  __threadfence();
-  const bool r = ok != 0 && !aborted(B);
+  const bool r = ok != 0;
   __syncthreads();
   return r;
 }
@@ -779,21 +785,34 @@ __device__ void block_partials(double (&v)[NV], double* part, int slot) {
   __syncthreads();
 }
 
-// the same fixed-order total of the partials in every block
-__device__ double grid_total(const double* part, int slot) {
-  __shared__ double tot;
-  if (threadIdx.x < 64) {
+// the same fixed-order totals of the partial sums in every block
+template <int NV>
+__device__ void grid_totals(const double* part, double (&tot)[NV]) {
+  __shared__ double sh[NV][NT2 / 64];
+  const int G = gridDim.x;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += 64)
-      s += __hip_atomic_load(&part[(int64_t)slot * gridDim.x + b], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    for (int b = threadIdx.x; b < G; b += NT2)
+      s += __hip_atomic_load(&part[(int64_t)k * G + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s = wave_sum(s);
-    if (threadIdx.x == 0) tot = s;
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
   }
   __syncthreads();
-  const double r = tot;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    double s = 0.0;
+    for (int w = 0; w < NT2 / 64; w++) s += sh[k][w];
+    tot[k] = s;
+  }
   __syncthreads();
-  return r;
+}
+
+// partial sums of the phase that ends with barrier `epoch`: two buffers, so
+// that a block already writing the next phase's partials cannot overwrite
+// values another block is still reading
+__device__ __forceinline__ double* part_buf(double* part, unsigned epoch) {
+  return part + (epoch & 1u) * 4 * gridDim.x;
 }
 
 template <typename R>
@@ -860,10 +879,12 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
         v[0] += rv * rv;
         if (sweep == 0) v[1] += A.b[o] * A.b[o];
       });
-      block_partials<2>(v, A.part, 0);
+      block_partials<2>(v, part_buf(A.part, epoch + 1), 0);
       if (!grid_sync(A.bar, ++epoch)) return;
-      rr = grid_total(A.part, 0);
-      if (sweep == 0) bb = grid_total(A.part, 1);
+      double tt[2];
+      grid_totals<2>(part_buf(A.part, epoch), tt);
+      rr = tt[0];
+      if (sweep == 0) bb = tt[1];
     }
     const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     if (rel <= A.tol) {
@@ -879,7 +900,10 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
       break;
     }
     // inner PCG on A_R e = r (Jacobi), stopped at ||r_k|| <= tol_abs
-    const double tol_abs = (sizeof(R) == 4) ? A.tol_in * sqrt(rr) : 0.5 * A.tol * sqrt(bb);
+    // FP32: reduce the residual by tol_in (what FP32 can deliver) but never
+    // further than the outer target; FP64: straight to the outer target
+    const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
+                                            : 0.5 * A.tol * sqrt(bb);
     double rz;
     {
       double v[1] = {0.0};
@@ -889,9 +913,11 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
         A.e[o] = R(0);
         v[0] += (double)A.r[o] * (double)zz;
       });
-      block_partials<1>(v, A.part, 0);
+      block_partials<1>(v, part_buf(A.part, epoch + 1), 0);
       if (!grid_sync(A.bar, ++epoch)) return;
-      rz = grid_total(A.part, 0);
+      double tt[1];
+      grid_totals<1>(part_buf(A.part, epoch), tt);
+      rz = tt[0];
     }
     R* pold = A.pa;
     R* pnew = A.pb;
@@ -913,10 +939,12 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
           A.q[o] = a;
           v[0] += (double)pc * (double)a;
         });
-        block_partials<1>(v, A.part, 0);
+        block_partials<1>(v, part_buf(A.part, epoch + 1), 0);
         if (!grid_sync(A.bar, ++epoch)) return;
       }
-      const double pq = grid_total(A.part, 0);
+      double tq[1];
+      grid_totals<1>(part_buf(A.part, epoch), tq);
+      const double pq = tq[0];
       const R alpha = (R)(pq != 0.0 ? rz / pq : 0.0);
       double rz_new, rr_in;
       {
@@ -930,10 +958,12 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
           v[0] += (double)rv * (double)zz;
           v[1] += (double)rv * (double)rv;
         });
-        block_partials<2>(v, A.part, 0);
+        block_partials<2>(v, part_buf(A.part, epoch + 1), 0);
         if (!grid_sync(A.bar, ++epoch)) return;
-        rz_new = grid_total(A.part, 0);
-        rr_in = grid_total(A.part, 1);
+        double tt[2];
+        grid_totals<2>(part_buf(A.part, epoch), tt);
+        rz_new = tt[0];
+        rr_in = tt[1];
       }
       total++;
       if (sqrt(rr_in) <= tol_abs || total >= A.max_iter || !(rz_new == rz_new)) break;
@@ -1120,7 +1150,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->tiles_x = (c->nx + TX2 - 1) / TX2;
   x->tiles_y = (c->ny + TY2 - 1) / TY2;
   x->ntiles = x->tiles_x * x->tiles_y;
-  x->grid_pcg = x->ntiles < 512 ? x->ntiles : 512;
+  x->grid_pcg = x->ntiles < 256 ? x->ntiles : 256;
   x->ht = (double*)take(8 * N);
   x->mt = (double*)take(8 * N);
   x->nt = (double*)take(8 * N);
@@ -1154,13 +1184,20 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
     x->q64 = (double*)take(8 * N);
     x->e64 = (double*)take(8 * N);
   }
-  x->part = (double*)take(8 * 4 * (size_t)x->grid_pcg);
+  x->part = (double*)take(8 * 2 * 4 * (size_t)x->grid_pcg);
   x->bar = (unsigned*)take(4 * ((size_t)x->grid_pcg + 1));
   x->iters = (int*)take(4);
   x->rel = (double*)take(8);
+  if (c->warm == 2) {
+    x->cnn_bytes = cnn_layout(1, c->ny, c->nx).bytes;
+    x->cnn_ws = take(x->cnn_bytes);
+    x->feat = (uint16_t*)take(2 * 16 * N);
+    x->guess = (double*)take(8 * N);
+  }
 }
 
 int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
+  if (c->warm == 2 && (c->nx % 16 || c->ny % 16)) return SWE_NH_EINVAL;
   x->t = k1.t;
   x->dt = k1.dt;
   x->smax = k1.smax;
@@ -1195,7 +1232,7 @@ static void enqueue_nh2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const 
                      x->n_tiles_act, x->n_act);
   hipLaunchKernelGGL(k_assemble2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
                      x->tile_list, x->n_tiles_act, t_in, dt_in, sys_of(x), p_prev,
-                     (int)(c->warm && p_prev));
+                     (int)(p_prev != nullptr));
   launch_solve2d(c, x, s);
   if (hu)
     hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
@@ -1215,8 +1252,20 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
                      (const double*)x->t, (const double*)x->dt, -1, M, x->tile_cnt, h, hu, hv,
                      hw, p, 1);
   if (c->crit != SWE_NH_CRIT_NONE) {
-    enqueue_nh2d(c, x, s, x->ht, x->mt, x->nt, x->kt, M, x->t, x->dt, c->warm ? p : nullptr, hu,
-                 hv, hw, p);
+    const double* guess = c->warm == 1 ? p : nullptr;
+    if (c->warm == 2 && x->net) {
+      const int64_t N = (int64_t)x->nx * x->ny;
+      const CnnLayout L = cnn_layout(1, x->ny, x->nx);
+      cnn_features(x->ch, c->depth_static, x->nx, x->ny, c->dx, c->dy, x->fscale, x->t, x->dt,
+                   x->ht, x->mt, x->nt, M, x->feat, s);
+      cnn_pack_weights(x->net, x->cnn_ws, L, false, s);
+      cnn_forward(x->net, x->feat, 1, x->ny, x->nx, x->cnn_ws, L,
+                  reinterpret_cast<float*>(x->cnn_ws + L.out), s);
+      cnn_scale_guess(reinterpret_cast<const float*>(x->cnn_ws + L.out), M, N, x->p_scale,
+                      x->guess, s);
+      guess = x->guess;
+    }
+    enqueue_nh2d(c, x, s, x->ht, x->mt, x->nt, x->kt, M, x->t, x->dt, guess, hu, hv, hw, p);
   } else {
     hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
                        x->n_tiles_act, x->n_act);
@@ -1248,7 +1297,7 @@ void solve_pressure2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const dou
   const G2 G = make_g2(c, x);
   const int64_t N = (int64_t)x->nx * x->ny;
   hipLaunchKernelGGL(k_count2d, dim3(x->ntiles), dim3(NT2), 0, s, G, mask, x->tile_cnt);
-  enqueue_nh2d(c, x, s, ht, mt, nt, kt, mask, t_in, dt_in, c->warm ? p : nullptr, nullptr,
+  enqueue_nh2d(c, x, s, ht, mt, nt, kt, mask, t_in, dt_in, c->warm == 1 ? p : nullptr, nullptr,
                nullptr, nullptr, nullptr);
   // p = x on the marked cells, 0 elsewhere
   hipLaunchKernelGGL(k_copy_masked2d, dim3(2048), dim3(256), 0, s, (const double*)x->x, mask, p,

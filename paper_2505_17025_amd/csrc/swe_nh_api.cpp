@@ -11,6 +11,7 @@
 
 #include "swe_nh.h"
 #include "swe_nh_2d.h"
+#include "swe_nh_cnn.h"
 #include "swe_nh_kernels.h"
 
 using namespace swenh;
@@ -599,6 +600,39 @@ int swe_nh_correct(swe_nh_ctx* c, const double* ht, const double* mt, const doub
               k_out);
   }
   return after_launch(c);
+}
+
+int swe_nh_features(swe_nh_ctx* c, const double* ht, const double* mt, const double* nt,
+                    const uint8_t* mask, const double* t1_host, const double* scales_host,
+                    uint16_t* out) {
+  if (!c || !ht || !mt || !nt || !mask || !t1_host || !scales_host || !out)
+    return fail(c, SWE_NH_EINVAL, "bad arguments");
+  for (int k = 0; k < 4; k++)
+    if (!(scales_host[k] > 0.0)) return fail(c, SWE_NH_EINVAL, "feature scales must be > 0");
+  if (c->cfg.dim != 2) return fail(c, SWE_NH_EINVAL, "features are defined on the 2D grid");
+  int rc = upload_stage_times(c, t1_host, nullptr);
+  if (rc) return rc;
+  cnn_features(c->k1.ch, c->cfg.depth_static, c->cfg.nx, c->cfg.ny, c->cfg.dx, c->cfg.dy,
+               scales_host, c->stage_t, c->stage_dt, ht, mt, nt, mask, out, c->stream);
+  return after_launch(c);
+}
+
+int swe_nh_set_warm_start_net(swe_nh_ctx* c, const float* params, const double* scales_host,
+                              double p_scale) {
+  if (!c || !params || !scales_host || !(p_scale > 0.0))
+    return fail(c, SWE_NH_EINVAL, "bad arguments");
+  for (int k = 0; k < 4; k++)
+    if (!(scales_host[k] > 0.0)) return fail(c, SWE_NH_EINVAL, "feature scales must be > 0");
+  if (c->cfg.dim != 2 || c->cfg.warm != 2)
+    return fail(c, SWE_NH_EINVAL, "the network guess needs a 2D context created with warm = 2");
+  c->c2.net = params;
+  for (int k = 0; k < 4; k++) c->c2.fscale[k] = scales_host[k];
+  c->c2.p_scale = p_scale;
+  if (c->gexec) {  // the captured step must pick up the network
+    hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  return SWE_NH_OK;
 }
 
 int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, double* hu,

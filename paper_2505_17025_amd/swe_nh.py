@@ -74,7 +74,19 @@ def _load():
     lib.swe_nh_correct.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp,
                                    vp, vp]
     lib.swe_nh_time_stage.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, C.POINTER(dbl)]
-    for name in ("swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
+    lib.swe_nh_cnn_param_count.restype = C.c_size_t
+    lib.swe_nh_cnn_param_count.argtypes = []
+    lib.swe_nh_cnn_workspace_bytes.restype = C.c_size_t
+    lib.swe_nh_cnn_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.swe_nh_cnn_forward.argtypes = [vp, vp, i32, i32, i32, vp, vp, C.c_size_t, vp]
+    lib.swe_nh_cnn_backward.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, C.c_size_t, vp]
+    lib.swe_nh_cnn_mse.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, C.c_size_t, vp]
+    lib.swe_nh_cnn_adam.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float,
+                                    C.c_float, vp]
+    lib.swe_nh_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
+    lib.swe_nh_set_warm_start_net.argtypes = [vp, vp, C.POINTER(dbl), dbl]
+    for name in ("swe_nh_cnn_forward", "swe_nh_cnn_backward", "swe_nh_cnn_mse", "swe_nh_cnn_adam",
+                 "swe_nh_features", "swe_nh_set_warm_start_net", "swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
                  "swe_nh_sync_stats", "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure",
                  "swe_nh_correct"):
         getattr(lib, name).restype = C.c_int
@@ -85,7 +97,9 @@ LIB = _load()
 EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_last_error",
             "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step", "swe_nh_sync_stats",
             "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct",
-            "swe_nh_time_stage"]
+            "swe_nh_time_stage", "swe_nh_cnn_param_count", "swe_nh_cnn_workspace_bytes",
+            "swe_nh_cnn_forward", "swe_nh_cnn_backward", "swe_nh_cnn_mse", "swe_nh_cnn_adam",
+            "swe_nh_features", "swe_nh_set_warm_start_net"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -153,8 +167,11 @@ class Context:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            LIB.swe_nh_destroy(ctx)
+        if ctx and LIB is not None:
+            try:
+                LIB.swe_nh_destroy(ctx)
+            except Exception:
+                pass
             self.ctx = None
 
     def _check(self, rc, where):
@@ -187,6 +204,16 @@ class Context:
                                           _ptr(hv), _ptr(hw), _ptr(p), C.byref(us)),
                     "swe_nh_time_stage")
         return us.value
+
+    def features(self, ht, mt, nt, mask, t1, scales, out):
+        self._check(LIB.swe_nh_features(self.ctx, _ptr(ht), _ptr(mt), _ptr(nt), _ptr(mask),
+                                        self._times(t1), _darr(scales), _ptr(out)),
+                    "swe_nh_features")
+
+    def set_warm_start_net(self, params, scales, p_scale):
+        self._net = params  # the library keeps the pointer
+        self._check(LIB.swe_nh_set_warm_start_net(self.ctx, _ptr(params), _darr(scales),
+                                                  float(p_scale)), "swe_nh_set_warm_start_net")
 
     # ---- stages ----
     def _times(self, t):
@@ -233,3 +260,48 @@ def context_1d(case_or_ensemble, **kw) -> Context:
 def context_2d(case, **kw) -> Context:
     return Context(dim=2, nx=case.nx, ny=case.ny, dx=case.dx, dy=case.dy,
                    depth_static=torch.from_numpy(np.asarray(case.ds)), bodies=[case.body], **kw)
+
+
+class Net:
+    """the warm-start network's kernels on caller-owned device buffers"""
+
+    def __init__(self, n, h, w, device="cuda"):
+        self.n, self.h, self.w = n, h, w
+        nb = LIB.swe_nh_cnn_workspace_bytes(n, h, w)
+        if nb == 0:
+            raise SweNhError(EINVAL, "swe_nh_cnn_workspace_bytes", f"shape {n}x{h}x{w}")
+        self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        self.wsp = (self.ws.data_ptr() + 255) // 256 * 256
+        self.nbytes = nb
+        self.stream = torch.cuda.current_stream(torch.device(device)).cuda_stream
+
+    @staticmethod
+    def param_count():
+        return int(LIB.swe_nh_cnn_param_count())
+
+    def _ok(self, rc, where):
+        if rc != OK:
+            raise SweNhError(rc, where)
+
+    def forward(self, params, x, out):
+        self._ok(LIB.swe_nh_cnn_forward(_ptr(params), _ptr(x), self.n, self.h, self.w, _ptr(out),
+                                        C.c_void_p(self.wsp), C.c_size_t(self.nbytes),
+                                        C.c_void_p(self.stream)), "swe_nh_cnn_forward")
+
+    def backward(self, params, x, dout, grad):
+        self._ok(LIB.swe_nh_cnn_backward(_ptr(params), _ptr(x), _ptr(dout), self.n, self.h,
+                                         self.w, _ptr(grad), C.c_void_p(self.wsp),
+                                         C.c_size_t(self.nbytes), C.c_void_p(self.stream)),
+                 "swe_nh_cnn_backward")
+
+    def mse(self, out, target, weight, dout, loss):
+        self._ok(LIB.swe_nh_cnn_mse(_ptr(out), _ptr(target), _ptr(weight), self.n, self.h, self.w,
+                                    _ptr(dout), _ptr(loss), C.c_void_p(self.wsp),
+                                    C.c_size_t(self.nbytes), C.c_void_p(self.stream)),
+                 "swe_nh_cnn_mse")
+
+    def adam(self, params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._ok(LIB.swe_nh_cnn_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                                     int(params.numel()), int(step), float(lr), float(beta1),
+                                     float(beta2), float(eps), C.c_void_p(self.stream)),
+                 "swe_nh_cnn_adam")

@@ -279,3 +279,17 @@ def random_case_2d(nx, ny, seed, dx=0.5, dy=0.5, h0=2.0, amp=0.05, mom=0.05, ver
         body = Body(kind=BODY_GAUSS, law=LAW_CONST_VEL, amp=0.05 * h0, length=4 * dx,
                     x0=0.4 * nx * dx, y0=0.5 * ny * dy, dir=1.0, q=(1.0, 0, 0, 0, 0))
     return Case2D(nx=nx, ny=ny, dx=dx, dy=dy, ds=ds, h=h, hu=hu, hv=hv, hw=hw, body=body, t0=0.05)
+
+
+def warm_start_case_2d(seed, n=1024, dx=2.0, h0=50.0) -> Case2D:
+    """2D slide scenario for the learned warm start: the shelf of the 2D
+    benchmark (50 m, Gaussian-correlated perturbation with std 2 m and
+    correlation length 40 m) on an n x n grid of spacing dx, with a Gaussian
+    mound (3 m, e-folding width 60 m, 8 m/s) whose start position and the
+    bathymetry vary with the seed"""
+    rng = np.random.default_rng(seed)
+    L = n * dx
+    x0 = float(rng.uniform(0.15, 0.35)) * L
+    y0 = float(rng.uniform(0.35, 0.65)) * L
+    return shelf_case_2d(nx=n, ny=n, dx=dx, dy=dx, h0=h0, sigma=2.0, ell=40.0, seed=seed,
+                         amp=3.0, width=60.0, x0=x0, y0=y0, speed=8.0)
