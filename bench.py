@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="slide1d", choices=["slide1d", "ensemble1d", "shelf2d"])
+    ap.add_argument("--workload", default="slide1d",
+                    choices=["slide1d", "ensemble1d", "shelf2d", "learned2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     return ap.parse_args()
@@ -197,11 +198,77 @@ def main():
                           "global_cell_steps_per_s": g["cell_steps_per_s"],
                           "n_active_last": res["n_active_last"]}}
         print(json.dumps(line), flush=True)
+    elif args.workload == "learned2d":
+        steps = args.steps or 20
+        warmup = args.warmup if args.warmup is not None else 30
+        print(json.dumps(run_learned(B, torch, S, steps, warmup)), flush=True)
     elif args.workload == "shelf2d":
         steps = args.steps or 50
         warmup = args.warmup if args.warmup is not None else 40
         res = run_2d(B, torch, S, steps, warmup)
         print(json.dumps(res), flush=True)
+
+
+def run_learned(B, torch, S, steps, warmup, n=1024, dx=4.0):
+    """learned warm start: train on the solver's own runs (seeds 17027-17030),
+    then time full steps of a held-out seed with the zero guess, the previous
+    step's pressure and the network's guess at the same tolerance"""
+    from paper_2505_17025_amd import warm_start as W
+    mk = lambda s: S.warm_start_case_2d(s, n=n, dx=dx)
+    t0 = time.perf_counter()
+    sc = W.estimate_scales(mk(17027), 60, 20)
+    X, P, M = W.dataset([17027, 17028, 17029, 17030], sc, nsteps=150, every=10, crops_per=16,
+                        make_case=mk)
+    params, ps, losses = W.train(X, P, M, iters=2000, batch=16, lr=2e-3, log_every=200)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("trained in", round(t_train, 1), "s on", tuple(X.shape), "losses", losses)
+    case = mk(17099)
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    out = {}
+    for name, warm in (("zero", 0), ("previous", 1), ("learned", 2)):
+        ctx = B.context_2d(case, crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1,
+                           tol=1e-8, max_iter=100000, warm=warm)
+        if warm == 2:
+            ctx.set_warm_start_net(params, sc, ps)
+        ctx.set_time(0.0)
+        h, hu, hv, hw = f(case.h), f(case.hu), f(case.hv), f(case.hw)
+        p = torch.zeros_like(h)
+        ctx.step(h, hu, hv, hw, p, nsteps=warmup)
+        st = ctx.sync_stats()
+        if st["status"] != 0:
+            raise RuntimeError(f"{name}: warmup status {st}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            ctx.step(h, hu, hv, hw, p)
+            st = ctx.sync_stats()
+            if st["status"] != 0:
+                raise RuntimeError(f"{name}: step status {st}")
+            its += st["iters"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out[name] = {"cell_steps_per_s": n * n * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "pcg_iters_per_step": its / steps, "n_active_last": st["n_active"]}
+        log(name, json.dumps(out[name]))
+    ev = W.evaluate(params, ps, sc, case, 150, 10)
+    res = out["learned"]
+    return {"metric": METRIC, "value": res["cell_steps_per_s"], "unit": "cell-steps/s",
+            "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": res["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"2D {n}x{n} slide, dx={dx} m, 50 m shelf + correlated "
+                                   "perturbation, Gaussian mound 3 m / 60 m at 8 m/s, adaptive "
+                                   "|eta/d|, FP32 PCG + FP64 refinement to tol 1e-8, learned "
+                                   "warm start (6x3x3 conv, 32 ch, BF16 MFMA)",
+                       "cells": n * n},
+            "roofline": None, "cpu_baseline": None,
+            "extra": {"zero_guess": out["zero"], "previous_step_guess": out["previous"],
+                      "learned_guess": out["learned"], "train_seconds": t_train,
+                      "train_loss": losses, "heldout_pcg_iters": {k: float(np.mean(v))
+                                                                  for k, v in ev.items()}}}
 
 
 def run_2d(B, torch, S, steps, warmup):

@@ -106,6 +106,8 @@ typedef struct {
   int32_t max_iter;         /* PCG iterations (2D) or refinement sweeps (precision 1) */
   int32_t warm;             /* 2D initial guess: 0 zero, 1 previous p (the p array on
                                entry), 2 the warm-start network */
+  int32_t tile1d;           /* 1D cells per block of the stencil kernels: 128, 256, 512,
+                               or 0 for the built-in choice */
   const double* depth_static;  /* device [cells]: static depth d_s */
   const swe_nh_body* bodies;   /* host [batch] (1D) or [1] (2D) */
 } swe_nh_config;

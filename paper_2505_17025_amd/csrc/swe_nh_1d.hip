@@ -1,7 +1,7 @@
 // swe_nh_1d.hip -- 1D kernels of the non-hydrostatic SWE step (gfx950).
 //
 // Layout: all channels packed back to back in one FP64 array per field; a
-// launch tile is TILE consecutive cells of one channel (tile table built on
+// launch tile is 128, 256 or 512 consecutive cells of one channel (tile table built on
 // the host).  Kernels never read across a channel end: the two ghost cells
 // on each side are reflections of the channel's own cells.
 //
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict
                                                  const double* __restrict__ hw) {
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
-  const int end = min(tl.y + TILE, c.n);
+  const int end = min(tl.y + P.tile, c.n);
   double s = 0.0;
   int flags = 0;
   for (int i = tl.y + threadIdx.x; i < end; i += blockDim.x) {
@@ -90,33 +90,34 @@ __device__ __forceinline__ Flux rusanov1d(double g, double eL, double mL, double
 
 namespace {
 constexpr int HALO = 4;
-constexpr int WIN = TILE + 2 * HALO;
 
+// LDS of the fused predictor for a tile of T cells (window of T + 8)
+template <int T>
 struct PredSmem {
-  double e[WIN], m[WIN], k[WIN], d[WIN];  // working state of the current stage
-  double d1[WIN];                          // depth at the end of the step
-  double Fh[WIN], FmL[WIN], FmR[WIN], Fk[WIN], hL[WIN], hR[WIN];
-  double Lh[TILE + 4], Lm[TILE + 4], Lk[TILE + 4];  // stage-1 operator on tile +- 2
-  double h0[TILE + 4], m0[TILE + 4], k0[TILE + 4];  // Q^n on tile +- 2
+  static constexpr int WIN = T + 2 * HALO;
+  double e[WIN], m[WIN], k[WIN], d0[WIN], d1[WIN];  // working state, depth at t^n and t^n+1
+  double Fh[WIN], FmL[WIN], FmR[WIN], Fk[WIN], hL[WIN], hR[WIN];  // face fluxes
 };
 
-// one stage of the FV operator on the window: faces f in [f0, f1) (face f
-// lies between window cells f-1 and f) and cells e in [c0, c1)
-__device__ __forceinline__ void stage_faces(PredSmem& S, double g, int f0, int f1, int lo_cell,
-                                            int hi_cell, int base, int* flags) {
+// face fluxes of one stage for faces f in [f0, f1) (face f between window
+// cells f-1 and f); d: depth of the stage
+template <int T>
+__device__ __forceinline__ void stage_faces(PredSmem<T>& S, const double* d, double g, int f0,
+                                            int f1, int lo_cell, int hi_cell, int base,
+                                            int* flags) {
   for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
     const int l = f - 1, r = f;
     const double se_l = minmod(S.e[l] - S.e[l - 1], S.e[l + 1] - S.e[l]);
     const double sm_l = minmod(S.m[l] - S.m[l - 1], S.m[l + 1] - S.m[l]);
     const double sk_l = minmod(S.k[l] - S.k[l - 1], S.k[l + 1] - S.k[l]);
-    const double sd_l = minmod(S.d[l] - S.d[l - 1], S.d[l + 1] - S.d[l]);
+    const double sd_l = minmod(d[l] - d[l - 1], d[l + 1] - d[l]);
     const double se_r = minmod(S.e[r] - S.e[r - 1], S.e[r + 1] - S.e[r]);
     const double sm_r = minmod(S.m[r] - S.m[r - 1], S.m[r + 1] - S.m[r]);
     const double sk_r = minmod(S.k[r] - S.k[r - 1], S.k[r + 1] - S.k[r]);
-    const double sd_r = minmod(S.d[r] - S.d[r - 1], S.d[r + 1] - S.d[r]);
+    const double sd_r = minmod(d[r] - d[r - 1], d[r + 1] - d[r]);
     const Flux F = rusanov1d(g, S.e[l] + 0.5 * se_l, S.m[l] + 0.5 * sm_l, S.k[l] + 0.5 * sk_l,
-                             S.d[l] + 0.5 * sd_l, S.e[r] - 0.5 * se_r, S.m[r] - 0.5 * sm_r,
-                             S.k[r] - 0.5 * sk_r, S.d[r] - 0.5 * sd_r);
+                             d[l] + 0.5 * sd_l, S.e[r] - 0.5 * se_r, S.m[r] - 0.5 * sm_r,
+                             S.k[r] - 0.5 * sk_r, d[r] - 0.5 * sd_r);
     S.Fh[f] = F.Fh;
     S.FmL[f] = F.FmL;
     S.FmR[f] = F.FmR;
@@ -130,27 +131,36 @@ __device__ __forceinline__ void stage_faces(PredSmem& S, double g, int f0, int f
   }
 }
 
-__device__ __forceinline__ void stage_cell(const PredSmem& S, double g, double idx, int e,
-                                           double& Lh, double& Lm, double& Lk) {
-  const double sd = minmod(S.d[e] - S.d[e - 1], S.d[e + 1] - S.d[e]);
+template <int T>
+__device__ __forceinline__ void stage_cell(const PredSmem<T>& S, const double* d, double g,
+                                           double idx, int e, double& Lh, double& Lm,
+                                           double& Lk) {
+  const double sd = minmod(d[e] - d[e - 1], d[e + 1] - d[e]);
   Lh = -(S.Fh[e + 1] - S.Fh[e]) * idx;
   Lm = -(S.FmL[e + 1] - S.FmR[e]) * idx + g * 0.5 * (S.hL[e + 1] + S.hR[e]) * sd * idx;
   Lk = -(S.Fk[e + 1] - S.Fk[e]) * idx;
 }
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_pred1d(K1D P, const double* __restrict__ h,
-                                                const double* __restrict__ hu,
-                                                const double* __restrict__ hw,
-                                                double* __restrict__ ht, double* __restrict__ mt,
-                                                double* __restrict__ kt, const double* t_in,
-                                                const double* dt_in, int dt_from_speed) {
-  __shared__ PredSmem S;
+// Both Heun stages for a tile of T cells.  Thread t owns the window cells
+// e = 2 + t + NT q of the stage-1 range [2, T + 6): their Q^n and stage-1
+// operator stay in registers for the final combination on the tile cells.
+template <int T, int NT>
+__global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__ h,
+                                               const double* __restrict__ hu,
+                                               const double* __restrict__ hw,
+                                               double* __restrict__ ht, double* __restrict__ mt,
+                                               double* __restrict__ kt, const double* t_in,
+                                               const double* dt_in, int dt_from_speed) {
+  constexpr int WIN = T + 2 * HALO;
+  constexpr int R1 = T + 4;                 // stage-1 cells: window [2, T + 6)
+  constexpr int Q = (R1 + NT - 1) / NT;
+  __shared__ PredSmem<T> S;
   __shared__ int sflags;
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, base = start - HALO;  // window cell e <-> channel cell base+e
-  const int end = min(start + TILE, n);
+  const int end = min(start + T, n);
   const double t0 = t_in[tl.x];
   double dt;
   if (dt_from_speed) {
@@ -167,84 +177,83 @@ __global__ void __launch_bounds__(256) k_pred1d(K1D P, const double* __restrict_
   int flags = 0;
 
   // load Q^n on the window with reflected ghosts; depth at both stage times
-  for (int e = threadIdx.x; e < WIN; e += blockDim.x) {
+  for (int e = threadIdx.x; e < WIN; e += NT) {
     const int i = min(base + e, n + HALO - 1);
     const int s = reflect(i, n);
     const int64_t gi = c.off + s;
-    const double sg = (s == i) ? 1.0 : -1.0;
     const double x = (s + 0.5) * P.dx;
     const double ds = P.ds[gi];
     const double dA = ds - body_shape(c, x - M0.X, 0.0).B;
-    const double dB = ds - body_shape(c, x - M1.X, 0.0).B;
-    const double hh = h[gi];
-    S.e[e] = hh - dA;
-    S.m[e] = sg * hu[gi];
+    S.e[e] = h[gi] - dA;
+    S.m[e] = (s == i ? 1.0 : -1.0) * hu[gi];
     S.k[e] = hw[gi];
-    S.d[e] = dA;
-    S.d1[e] = dB;
-    if (e >= HALO - 2 && e < TILE + HALO + 2) {
-      S.h0[e - (HALO - 2)] = hh;
-      S.m0[e - (HALO - 2)] = S.m[e];
-      S.k0[e - (HALO - 2)] = S.k[e];
-    }
+    S.d0[e] = dA;
+    S.d1[e] = ds - body_shape(c, x - M1.X, 0.0).B;
   }
   __syncthreads();
 
-  // stage 1 on the channel cells of window [2, WIN-2): faces [2, WIN-1)
-  const int lo1 = max(0, start - 2), hi1 = min(n, start + TILE + 2);
-  stage_faces(S, P.g, 2, WIN - 1, lo1, hi1, base, &flags);
+  double Qn[Q][3], L1[Q][3];
+  // stage 1: faces [2, WIN - 1), cells [2, WIN - 2)
+  const int lo1 = max(0, start - 2), hi1 = min(n, start + T + 2);
+  stage_faces<T>(S, S.d0, P.g, 2, WIN - 1, lo1, hi1, base, &flags);
   __syncthreads();
-  for (int e = 2 + threadIdx.x; e < WIN - 2; e += blockDim.x) {
-    double a, b, q;
-    stage_cell(S, P.g, idx, e, a, b, q);
-    S.Lh[e - 2] = a;
-    S.Lm[e - 2] = b;
-    S.Lk[e - 2] = q;
-  }
-  __syncthreads();
-  // Q* = Q^n + dt L(Q^n, t^n) on channel cells; ghosts re-reflected from Q*
-  for (int e = 2 + threadIdx.x; e < WIN - 2; e += blockDim.x) {
-    const int i = base + e;
-    if (i >= 0 && i < n) {
-      const int j = e - 2;
-      S.e[e] = S.h0[j] + dt * S.Lh[j] - S.d1[e];
-      S.m[e] = S.m0[j] + dt * S.Lm[j];
-      S.k[e] = S.k0[j] + dt * S.Lk[j];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int e = 2 + threadIdx.x + NT * q;
+    Qn[q][0] = Qn[q][1] = Qn[q][2] = 0.0;
+    L1[q][0] = L1[q][1] = L1[q][2] = 0.0;
+    if (e < WIN - 2) {
+      stage_cell<T>(S, S.d0, P.g, idx, e, L1[q][0], L1[q][1], L1[q][2]);
+      Qn[q][0] = S.e[e] + S.d0[e];
+      Qn[q][1] = S.m[e];
+      Qn[q][2] = S.k[e];
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < WIN; e += blockDim.x) {
+  // Q* = Q^n + dt L(Q^n, t^n) on the channel cells of the range
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int e = 2 + threadIdx.x + NT * q;
     const int i = base + e;
-    if (i < 0 || i >= n) {
-      const int s = reflect(min(i, n + HALO - 1), n);
-      const int es = s - base;
-      double ev = 0.0, mv = 0.0, kv = 0.0;
-      if (es >= 2 && es < WIN - 2) {
-        ev = S.e[es];  // h is even and the ghost depth equals the reflected one
-        mv = -S.m[es];
-        kv = S.k[es];
-      }
-      S.e[e] = ev;
-      S.m[e] = mv;
-      S.k[e] = kv;
+    if (e < WIN - 2 && i >= 0 && i < n) {
+      S.e[e] = Qn[q][0] + dt * L1[q][0] - S.d1[e];
+      S.m[e] = Qn[q][1] + dt * L1[q][1];
+      S.k[e] = Qn[q][2] + dt * L1[q][2];
     }
-    S.d[e] = S.d1[e];
+  }
+  __syncthreads();
+  // ghosts of Q*: reflections of channel cells (h and hw even, hu odd)
+  for (int e = threadIdx.x; e < WIN; e += NT) {
+    const int i = base + e;
+    if (i >= 0 && i < n) continue;
+    const int s = reflect(min(i, n + HALO - 1), n);
+    const int es = s - base;
+    double ev = 0.0, mv = 0.0, kv = 0.0;
+    if (es >= 2 && es < WIN - 2) {
+      ev = S.e[es];
+      mv = -S.m[es];
+      kv = S.k[es];
+    }
+    S.e[e] = ev;
+    S.m[e] = mv;
+    S.k[e] = kv;
   }
   __syncthreads();
 
-  // stage 2 on the tile cells: faces [HALO, HALO + TILE + 1)
-  stage_faces(S, P.g, HALO, HALO + TILE + 1, start, end, base, &flags);
+  // stage 2 on the tile cells: faces [HALO, HALO + T + 1)
+  stage_faces<T>(S, S.d1, P.g, HALO, HALO + T + 1, start, end, base, &flags);
   __syncthreads();
-  for (int e = HALO + threadIdx.x; e < HALO + TILE; e += blockDim.x) {
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int e = 2 + threadIdx.x + NT * q;
     const int i = base + e;
-    if (i >= end) continue;
-    double a, b, q;
-    stage_cell(S, P.g, idx, e, a, b, q);
-    const int j = e - 2;
+    if (e < HALO || e >= HALO + T || i >= end) continue;
+    double a, b, k2;
+    stage_cell<T>(S, S.d1, P.g, idx, e, a, b, k2);
     const int64_t gi = c.off + i;
-    ht[gi] = S.h0[j] + 0.5 * dt * (S.Lh[j] + a);
-    mt[gi] = S.m0[j] + 0.5 * dt * (S.Lm[j] + b);
-    kt[gi] = S.k0[j] + 0.5 * dt * (S.Lk[j] + q);
+    ht[gi] = Qn[q][0] + 0.5 * dt * (L1[q][0] + a);
+    mt[gi] = Qn[q][1] + 0.5 * dt * (L1[q][1] + b);
+    kt[gi] = Qn[q][2] + 0.5 * dt * (L1[q][2] + k2);
   }
   if (flags) atomicOr(&sflags, flags);
   __syncthreads();
@@ -305,11 +314,11 @@ __global__ void __launch_bounds__(256) k_mask1d(K1D P, const double* __restrict_
                                                 int mode_override, uint8_t* __restrict__ mask,
                                                 double* h, double* hu, double* hw, double* p,
                                                 int write_state) {
-  __shared__ uint8_t raw[TILE + 2 * MAXE];
+  __shared__ uint8_t raw[TILE_MAX + 2 * MAXE];
   __shared__ int cnt[4];
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
-  const int n = c.n, start = tl.y, end = min(start + TILE, n);
+  const int n = c.n, start = tl.y, end = min(start + P.tile, n);
   const int e = P.enlarge;
   int mode = mode_override;
   if (mode < 0) {  // step: decide from the criterion and the step counter
@@ -324,7 +333,7 @@ __global__ void __launch_bounds__(256) k_mask1d(K1D P, const double* __restrict_
   if (mode == 0) {
     const double t1 = t_in[tl.x] + dt_in[tl.x];
     const Motion M = body_motion(c, t1);
-    for (int w = threadIdx.x; w < TILE + 2 * e; w += blockDim.x) {
+    for (int w = threadIdx.x; w < P.tile + 2 * e; w += blockDim.x) {
       const int i = start - e + w;
       uint8_t r = 0;
       if (i >= 0 && i < n) r = indicator1d(P, c, M, ht, mt, kt, i, P.crit) > P.k_nh;
@@ -365,7 +374,7 @@ __global__ void __launch_bounds__(256) k_count1d(K1D P, const uint8_t* __restric
   __shared__ int cnt[4];
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
-  const int end = min(tl.y + TILE, c.n);
+  const int end = min(tl.y + P.tile, c.n);
   int local = 0;
   for (int i = tl.y + threadIdx.x; i < end; i += blockDim.x) local += mask[c.off + i] ? 1 : 0;
   local = wave_sum_i(local);
@@ -403,7 +412,7 @@ __global__ void __launch_bounds__(256) k_compact1d(K1D P, const uint8_t* __restr
   __shared__ int wsum[4];
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
-  const int end = min(tl.y + TILE, c.n);
+  const int end = min(tl.y + P.tile, c.n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int base = P.tile_off[blockIdx.x];
   for (int r0 = tl.y; r0 < end; r0 += blockDim.x) {
@@ -590,8 +599,15 @@ void launch_speed1d(const K1D& P, const double* h, const double* hu, const doubl
 void launch_pred1d(const K1D& P, const double* h, const double* hu, const double* hw, double* ht,
                    double* mt, double* kt, const double* t_in, const double* dt_in,
                    int dt_from_speed, hipStream_t s) {
-  hipLaunchKernelGGL(k_pred1d, dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw, ht, mt, kt, t_in,
-                     dt_in, dt_from_speed);
+  if (P.tile == 128)
+    hipLaunchKernelGGL((k_pred1d<128, 128>), dim3(P.ntiles), dim3(128), 0, s, P, h, hu, hw, ht, mt,
+                       kt, t_in, dt_in, dt_from_speed);
+  else if (P.tile == 256)
+    hipLaunchKernelGGL((k_pred1d<256, 256>), dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw, ht, mt,
+                       kt, t_in, dt_in, dt_from_speed);
+  else
+    hipLaunchKernelGGL((k_pred1d<512, 256>), dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw, ht, mt,
+                       kt, t_in, dt_in, dt_from_speed);
 }
 void launch_mask1d(const K1D& P, const double* ht, const double* mt, const double* kt,
                    const double* t_in, const double* dt_in, int mode_override, uint8_t* mask,

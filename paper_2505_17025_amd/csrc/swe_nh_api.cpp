@@ -96,6 +96,8 @@ int check_config(const swe_nh_config* c, std::string* why) {
   if (!(c->cfl > 0.0) && !(c->dt_fixed > 0.0)) return bad("need cfl > 0 or dt_fixed > 0");
   if (c->crit < 0 || c->crit > SWE_NH_CRIT_NONE) return bad("unknown criterion");
   if (c->enlarge < 0 || c->enlarge > 64) return bad("enlarge must be in [0, 64]");
+  if (c->tile1d != 0 && c->tile1d != 128 && c->tile1d != 256 && c->tile1d != 512)
+    return bad("tile1d must be 0, 128, 256 or 512");
   if (c->precision != 0 && c->precision != 1) return bad("precision must be 0 or 1");
   if (!c->depth_static) return bad("depth_static is required");
   if (!c->bodies) return bad("bodies is required");
@@ -126,12 +128,21 @@ int64_t total_cells(const swe_nh_config* c) {
 
 int n_channels(const swe_nh_config* c) { return c->dim == 2 ? 1 : c->batch; }
 
+// 1D tile size: the configured one, else 128 cells when tiles of 512 would
+// leave most of the 256 compute units idle
+int tile_of(const swe_nh_config* c) {
+  if (c->tile1d == 128 || c->tile1d == 256 || c->tile1d == 512) return c->tile1d;
+  const int64_t N = c->dim == 2 ? (int64_t)c->nx * c->ny : (c->offsets ? c->offsets[c->batch] : c->nx);
+  return N <= 256 * 512 ? 128 : 512;
+}
+
 void tile_table(const swe_nh_config* c, std::vector<int2>* tiles, std::vector<int>* first) {
   const int nch = n_channels(c);
+  const int T = tile_of(c);
   for (int b = 0; b < nch; b++) {
     const int64_t n = c->offsets ? c->offsets[b + 1] - c->offsets[b] : c->nx;
     first->push_back((int)tiles->size());
-    for (int64_t s = 0; s < n; s += TILE) tiles->push_back(make_int2(b, (int)s));
+    for (int64_t s = 0; s < n; s += T) tiles->push_back(make_int2(b, (int)s));
   }
 }
 
@@ -364,6 +375,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.enlarge = cfg->enlarge;
   P.first_global = cfg->first_global;
   P.ntiles = (int)c->tiles.size();
+  P.tile = tile_of(cfg);
   std::vector<double> zeros(c->nch, 0.0);
   std::vector<unsigned long long> zu(c->nch, 0ull);
   int zi[TRI_MAX_LEVELS * 2] = {0};

@@ -9,7 +9,7 @@
 
 namespace swenh {
 
-constexpr int TILE = 512;       // cells per block in the 1D stencil kernels
+constexpr int TILE_MAX = 512;   // largest 1D tile (cells per block of the stencil kernels)
 constexpr int TRI_ROWS = 1024;  // rows per block in the tridiagonal solver
 constexpr int TRI_MAX_LEVELS = 6;
 
@@ -21,6 +21,7 @@ struct K1D {
   const double* ds;        // static depth [cells]
   double dx, g, rho, cfl, dt_fixed, k_nh;
   int crit, enlarge, first_global, ntiles;
+  int tile;                // cells per 1D tile: 128, 256 or 512
   double* t;               // [batch] time at the start of the step
   double* dt;              // [batch] step of the current step
   unsigned long long* smax;  // [batch] bit pattern of the max wave speed

@@ -1,0 +1,53 @@
+"""What the trained warm-start network gains: trained on the GPU by the
+project's kernels on pressure fields the solver produced, its guess on a
+held-out run must be closer to the converged pressure than the zero guess,
+and the PCG to the same tolerance must not need more iterations from it
+than from zero. The converged pressures are checked against the FP64
+oracle's own system first, so the target is independent of the network.
+
+The residual of the guess is not the bar: the operator weighs the error's
+finest scales by about 1/dx^2, so a guess that is close in value can still
+have a residual above that of the zero guess."""
+import numpy as np
+import pytest
+
+import oracle as O
+import swe_inputs as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_trained_network_beats_the_zero_guess():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17025_amd import warm_start as W
+    mk = lambda s: S.warm_start_case_2d(s, n=256, dx=4.0)
+    sc = W.estimate_scales(mk(31), 60, 20)
+    X, P, M = W.dataset([32, 33, 34], sc, nsteps=100, every=10, crops_per=16, size=64,
+                        make_case=mk)
+    params, ps, losses = W.train(X, P, M, iters=1500, batch=16, lr=2e-3, log_every=150)
+    print("losses", losses)
+    assert losses[-1] < 0.25 * losses[0], losses
+    case = mk(77)
+    errs, rres = [], []
+    for f, pc, m, (ctx, t, dt, ht, mt, nt, kt, p) in W.snapshots(case, 100, 25, sc):
+        mk_ = m.cpu().numpy()
+        sel = mk_ == 1
+        st = [a.cpu().numpy() for a in (ht, mt, nt, kt)]
+        cell, xf, yf = O.nh_coeffs_2d(case.ds, case.dx, case.dy, case.body, O.phys_struct(),
+                                      t + dt, dt, *st)
+        rhs = O.nh_rhs_2d(cell, xf, yf, mk_)
+        ps_ = pc.double().cpu().numpy()
+        # the converged pressure solves the oracle's system (FP32 copy: 1e-6)
+        r = rhs - O.nh_apply_2d(cell, xf, yf, mk_, ps_)
+        assert np.linalg.norm(r[sel]) <= 1e-5 * np.linalg.norm(rhs[sel])
+        g = W.guess(params, ps, f, m).cpu().numpy()
+        errs.append(np.linalg.norm((g - ps_)[sel]) / np.linalg.norm(ps_[sel]))
+        r = rhs - O.nh_apply_2d(cell, xf, yf, mk_, g)
+        rres.append(np.linalg.norm(r[sel]) / np.linalg.norm(rhs[sel]))
+    print("guess error", errs, "guess residual", rres)
+    assert len(errs) >= 2 and max(errs) < 0.7, errs
+    ev = W.evaluate(params, ps, sc, case, 100, 25)
+    print("iterations", ev)
+    assert np.mean(ev["learned"]) <= np.mean(ev["zero"]) * 1.02, ev
