@@ -28,12 +28,12 @@ struct Ctx2D {
   double *dg = nullptr, *ce = nullptr, *cn = nullptr, *b = nullptr, *x = nullptr;
   float *dg32 = nullptr, *ce32 = nullptr, *cn32 = nullptr;
   uint8_t* nb = nullptr;
-  // inner Krylov vectors: FP32 (precision 1) or FP64 (precision 0)
-  float *r = nullptr, *z = nullptr, *pa = nullptr, *pb = nullptr, *q = nullptr, *e = nullptr;
-  double *r64 = nullptr, *z64 = nullptr, *pa64 = nullptr, *pb64 = nullptr, *q64 = nullptr,
-         *e64 = nullptr;
-  double* part = nullptr;    // [grid_pcg * 4] block partial sums
-  unsigned* bar = nullptr;   // grid barrier: [grid_pcg] arrival flags + release word
+  // inner Krylov vectors, FP32 (precision 1) or FP64 (precision 0):
+  // r[2], w[2], s[2] (double-buffered by iteration parity), p, e
+  float* v32[8] = {};
+  double* v64[8] = {};
+  double* part = nullptr;    // [2][4][PCG_GMAX] block partial sums
+  unsigned long long* bar = nullptr;  // grid barrier arrival counter
   int* iters = nullptr;
   double* rel = nullptr;
   // learned warm start (warm = 2)

@@ -10,10 +10,11 @@
 //   k_mask2d       criterion + (2e+1)^2 box enlargement, tile counts
 //   k_tiles2d      list of tiles holding marked cells
 //   k_assemble2d   5-point operator of the elliptic system (FP64 + FP32 copy)
-//   k_pcg2d<R>     persistent preconditioned CG (Jacobi) in precision R with
+//   k_pcg2d<R>     persistent Jacobi-preconditioned CG (Chronopoulos-Gear
+//                  form) in precision R with
 //                  FP64 residuals and FP64 refinement of the solution,
-//                  deterministic fixed-order dot products, flag-array grid
-//                  barrier with bounded waits
+//                  deterministic fixed-order dot products, one grid
+//                  barrier (arrival counter, bounded waits) per iteration
 //   k_correct2d    projection of hu, hv and hw on the marked cells
 #include "swe_nh_2d.h"
 #include "swe_nh_cnn.h"
@@ -701,12 +702,23 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
 // ---------------------------------------------------------------------------
 // persistent PCG with FP64 refinement
 // ---------------------------------------------------------------------------
-// bounded waits: a wait longer than this aborts the solve (status bit) so that
-// the kernel always ends; wall_clock64 ticks at 100 MHz
+// The inner solve is CG in the Chronopoulos-Gear form (one global reduction
+// per iteration: (r,u), (w,u) and (r,r) together, with w = A u).  Each
+// iteration is one pass over the block's cells followed by one grid barrier:
+// the SpMV w' = A u' needs u' = M^-1 r' at the four neighbours, and a
+// neighbour's u' is recomputed from that neighbour's r, w and s of the
+// previous iteration (double-buffered by iteration parity, so that no block
+// overwrites a value another block may still read).  The recomputation uses
+// the same fused operations as the owner's own update, so both give the same
+// bits.
+//
+// Bounded waits: a wait longer than WAIT_TICKS aborts the solve (status bit)
+// so that the kernel always ends; wall_clock64 ticks at 100 MHz.
 constexpr unsigned long long WAIT_TICKS = 50000000ull;
+constexpr int PCG_GMAX = 1024;  // most blocks of the persistent solver
 
 struct Bar {
-  unsigned* flags;  // [G] arrival epochs, [G] = release epoch
+  unsigned long long* count;  // arrivals, increasing over the whole solve
   int* status;
 };
 
@@ -714,12 +726,12 @@ __device__ __forceinline__ bool aborted(const Bar& B) {
   return (__hip_atomic_load(B.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_ABORT) != 0;
 }
 
-// waits until *w >= epoch (relaxed polls, no cache maintenance per poll);
-// false when the wait timed out or another block aborted
-__device__ bool wait_epoch(const Bar& B, unsigned* w, unsigned epoch) {
+// waits until *B.count >= target (relaxed polls, no cache maintenance per
+// poll); false when the wait timed out or another block aborted
+__device__ bool wait_count(const Bar& B, unsigned long long target) {
   const unsigned long long t0 = wall_clock64();
   unsigned polls = 0;
-  while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+  while (__hip_atomic_load(B.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if ((++polls & 255u) == 0u) {
       if (aborted(B)) return false;
       if (wall_clock64() - t0 > WAIT_TICKS) {
@@ -732,41 +744,26 @@ __device__ bool wait_epoch(const Bar& B, unsigned* w, unsigned epoch) {
   return true;
 }
 
-// grid-wide barrier over co-resident blocks: each block raises its own flag
-// (release), block 0 waits for all flags and raises the release word, every
-// block waits for it (acquire).  Returns false in every thread of the block
-// when the solve was aborted.
-__device__ bool grid_sync(const Bar& B, unsigned epoch) {
-  const int G = gridDim.x;
+// grid-wide barrier over the G co-resident blocks of the solve: one arrival
+// counter (release on arrival, acquire after the wait).  Barrier number k
+// (1, 2, ...) completes when the counter reaches k G.  Returns false in every
+// thread of the block when the solve was aborted.
+__device__ bool grid_sync(const Bar& B, unsigned k, int G) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    ok = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&B.flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(B.count, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = wait_count(B, (unsigned long long)k * (unsigned long long)G) ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int b = threadIdx.x; b < G; b += blockDim.x)
-      if (!wait_epoch(B, &B.flags[b], epoch)) ok = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      __hip_atomic_store(&B.flags[G], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (threadIdx.x == 0) {
-    if (!wait_epoch(B, &B.flags[G], epoch)) ok = 0;
-  }
-  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  __syncthreads();
-  const bool r = ok != 0;
-  __syncthreads();
-  return r;
+  return ok != 0;
 }
 
-// block partial sums (fixed order) of NV values -> part[slot + v][blockIdx]
+// block partial sums (fixed order) of NV values -> part[v][vb]
 template <int NV>
-__device__ void block_partials(double (&v)[NV], double* part, int slot) {
+__device__ void block_partials(double (&v)[NV], double* part, int vb, int G) {
   __shared__ double sh[NV][NT2 / 64];
 #pragma unroll
   for (int k = 0; k < NV; k++) {
@@ -779,17 +776,15 @@ __device__ void block_partials(double (&v)[NV], double* part, int slot) {
     for (int k = 0; k < NV; k++) {
       double s = 0.0;
       for (int w = 0; w < NT2 / 64; w++) s += sh[k][w];
-      part[(int64_t)(slot + k) * gridDim.x + blockIdx.x] = s;
+      part[(int64_t)k * G + vb] = s;
     }
   }
-  __syncthreads();
 }
 
-// the same fixed-order totals of the partial sums in every block
+// the same fixed-order totals of the G partial sums in every block
 template <int NV>
-__device__ void grid_totals(const double* part, double (&tot)[NV]) {
+__device__ void grid_totals(const double* part, int G, double (&tot)[NV]) {
   __shared__ double sh[NV][NT2 / 64];
-  const int G = gridDim.x;
 #pragma unroll
   for (int k = 0; k < NV; k++) {
     double s = 0.0;
@@ -805,14 +800,13 @@ __device__ void grid_totals(const double* part, double (&tot)[NV]) {
     for (int w = 0; w < NT2 / 64; w++) s += sh[k][w];
     tot[k] = s;
   }
-  __syncthreads();
 }
 
-// partial sums of the phase that ends with barrier `epoch`: two buffers, so
-// that a block already writing the next phase's partials cannot overwrite
-// values another block is still reading
-__device__ __forceinline__ double* part_buf(double* part, unsigned epoch) {
-  return part + (epoch & 1u) * 4 * gridDim.x;
+// partial sums of the phase that ends with barrier k: two buffers, so that a
+// block already writing the next phase's partials cannot overwrite values
+// another block is still reading
+__device__ __forceinline__ double* part_buf(double* part, unsigned k) {
+  return part + (k & 1u) * 4 * PCG_GMAX;
 }
 
 template <typename R>
@@ -824,7 +818,7 @@ struct PcgArgs {
   const double *dg, *ce, *cn, *b;
   double* x;
   const R *dgR, *ceR, *cnR;
-  R *r, *z, *pa, *pb, *q, *e;
+  R *r[2], *w[2], *s[2], *p, *e;
   double* part;
   Bar bar;
   int* iters;
@@ -844,11 +838,30 @@ __device__ __forceinline__ V apply5(const T* dg, const T* ce, const T* cn, const
   return a;
 }
 
-// loops over this block's active tiles and calls f(o, nb) for each marked cell
+// Block-to-tile map of the solver: the G participating blocks take
+// contiguous, equal shares of the active-tile list, ordered so that the
+// blocks of one XCD (blocks are dispatched round-robin over the 8 XCDs) hold
+// neighbouring shares.
+struct Share {
+  int vb;      // position of this block among the G shares
+  int t0, t1;  // active-list range [t0, t1)
+};
+
+__device__ __forceinline__ Share share_of(int G, int nlist) {
+  const int b = blockIdx.x, x = b & 7, l = b >> 3;
+  const int vb = x * (G >> 3) + min(x, G & 7) + l;
+  Share S;
+  S.vb = vb;
+  S.t0 = (int)(((int64_t)nlist * vb) / G);
+  S.t1 = (int)(((int64_t)nlist * (vb + 1)) / G);
+  return S;
+}
+
+// calls f(o, nb) for each marked cell of the block's share
 template <typename F>
 __device__ __forceinline__ void for_cells(int nx, int ny, int tiles_x, const int* tile_list,
-                                          int nlist, const uint8_t* nbf, F f) {
-  for (int t = blockIdx.x; t < nlist; t += gridDim.x) {
+                                          const Share& S, const uint8_t* nbf, F f) {
+  for (int t = S.t0; t < S.t1; t++) {
     const int tile = tile_list[t];
     const int i0 = (tile % tiles_x) * TX2, j0 = (tile / tiles_x) * TY2;
     for (int cc = threadIdx.x; cc < TN; cc += NT2) {
@@ -861,34 +874,45 @@ __device__ __forceinline__ void for_cells(int nx, int ny, int tiles_x, const int
   }
 }
 
+// u' = M^-1 (r - alpha (w + beta s_old)) at cell j from the previous
+// iteration's r, w (buffer cur) and s (buffer cur ^ 1)
+template <typename R>
+__device__ __forceinline__ R u_next(const PcgArgs<R>& A, int64_t j, int cur, bool first, R alpha,
+                                    R beta) {
+  const R wj = A.w[cur][j];
+  const R sj = first ? wj : fma(beta, A.s[cur ^ 1][j], wj);
+  return fma(-alpha, sj, A.r[cur][j]) / A.dgR[j];
+}
+
 template <typename R>
 __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
   const int nlist = *A.n_list;
+  const int G = max(1, min((int)gridDim.x, nlist));
+  if ((int)blockIdx.x >= G) return;
+  const Share S = share_of(G, nlist);
   const int nx = A.nx;
-  unsigned epoch = 0;
+  unsigned k = 0;  // barriers passed
   double bb = 0.0, rr = 0.0;
   int total = 0, sweep = 0;
-  bool done = false;
   for (;;) {
-    // FP64 residual of the current solution
+    // FP64 residual of the current solution -> r[0] in precision R
     {
       double v[2] = {0.0, 0.0};
-      for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
+      for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb, [&](int64_t o, uint8_t nb) {
         const double rv = A.b[o] - apply5<double, double>(A.dg, A.ce, A.cn, A.x, nb, o, nx);
-        A.r[o] = (R)rv;
+        A.r[0][o] = (R)rv;
         v[0] += rv * rv;
         if (sweep == 0) v[1] += A.b[o] * A.b[o];
       });
-      block_partials<2>(v, part_buf(A.part, epoch + 1), 0);
-      if (!grid_sync(A.bar, ++epoch)) return;
+      block_partials<2>(v, part_buf(A.part, k + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++k, G)) return;
       double tt[2];
-      grid_totals<2>(part_buf(A.part, epoch), tt);
+      grid_totals<2>(part_buf(A.part, k), G, tt);
       rr = tt[0];
       if (sweep == 0) bb = tt[1];
     }
     const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     if (rel <= A.tol) {
-      done = true;
       if (blockIdx.x == 0 && threadIdx.x == 0) *A.rel = rel;
       break;
     }
@@ -899,92 +923,87 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
       }
       break;
     }
-    // inner PCG on A_R e = r (Jacobi), stopped at ||r_k|| <= tol_abs
-    // FP32: reduce the residual by tol_in (what FP32 can deliver) but never
-    // further than the outer target; FP64: straight to the outer target
+    // inner solve of A_R e = r stopped at ||r_k|| <= tol_abs.  FP32 reduces
+    // the residual by tol_in (what FP32 can deliver) but never further than
+    // the outer target; FP64 goes straight to the outer target.
     const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
                                             : 0.5 * A.tol * sqrt(bb);
-    double rz;
+    // u0 = M^-1 r0, w0 = A u0, e = 0; gamma = (r0, u0), delta = (w0, u0)
+    double gam, del;
     {
-      double v[1] = {0.0};
-      for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
-        const R zz = A.r[o] / A.dgR[o];
-        A.z[o] = zz;
+      double v[2] = {0.0, 0.0};
+      for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb, [&](int64_t o, uint8_t nb) {
+        auto u0 = [&](int64_t j) { return A.r[0][j] / A.dgR[j]; };
+        const R uc = u0(o);
+        R a = A.dgR[o] * uc;
+        if (nb & NB_E) a += A.ceR[o] * u0(o + 1);
+        if (nb & NB_W) a += A.ceR[o - 1] * u0(o - 1);
+        if (nb & NB_N) a += A.cnR[o] * u0(o + nx);
+        if (nb & NB_S) a += A.cnR[o - nx] * u0(o - nx);
+        A.w[0][o] = a;
         A.e[o] = R(0);
-        v[0] += (double)A.r[o] * (double)zz;
+        v[0] += (double)A.r[0][o] * (double)uc;
+        v[1] += (double)a * (double)uc;
       });
-      block_partials<1>(v, part_buf(A.part, epoch + 1), 0);
-      if (!grid_sync(A.bar, ++epoch)) return;
-      double tt[1];
-      grid_totals<1>(part_buf(A.part, epoch), tt);
-      rz = tt[0];
+      block_partials<2>(v, part_buf(A.part, k + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++k, G)) return;
+      double tt[2];
+      grid_totals<2>(part_buf(A.part, k), G, tt);
+      gam = tt[0];
+      del = tt[1];
     }
-    R* pold = A.pa;
-    R* pnew = A.pb;
-    double beta = 0.0;
+    double alpha = del != 0.0 ? gam / del : 0.0, beta = 0.0;
     for (int it = 0;; it++) {
-      // p = z + beta p_old (first: p = z), q = A p, p.q
-      {
-        double v[1] = {0.0};
-        const R bt = (R)beta;
-        for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
-          auto pv = [&](int64_t u) { return it == 0 ? A.z[u] : A.z[u] + bt * pold[u]; };
-          const R pc = pv(o);
-          R a = A.dgR[o] * pc;
-          if (nb & NB_E) a += A.ceR[o] * pv(o + 1);
-          if (nb & NB_W) a += A.ceR[o - 1] * pv(o - 1);
-          if (nb & NB_N) a += A.cnR[o] * pv(o + nx);
-          if (nb & NB_S) a += A.cnR[o - nx] * pv(o - nx);
-          pnew[o] = pc;
-          A.q[o] = a;
-          v[0] += (double)pc * (double)a;
-        });
-        block_partials<1>(v, part_buf(A.part, epoch + 1), 0);
-        if (!grid_sync(A.bar, ++epoch)) return;
-      }
-      double tq[1];
-      grid_totals<1>(part_buf(A.part, epoch), tq);
-      const double pq = tq[0];
-      const R alpha = (R)(pq != 0.0 ? rz / pq : 0.0);
-      double rz_new, rr_in;
-      {
-        double v[2] = {0.0, 0.0};
-        for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb, [&](int64_t o, uint8_t nb) {
-          A.e[o] += alpha * pnew[o];
-          const R rv = A.r[o] - alpha * A.q[o];
-          A.r[o] = rv;
-          const R zz = rv / A.dgR[o];
-          A.z[o] = zz;
-          v[0] += (double)rv * (double)zz;
-          v[1] += (double)rv * (double)rv;
-        });
-        block_partials<2>(v, part_buf(A.part, epoch + 1), 0);
-        if (!grid_sync(A.bar, ++epoch)) return;
-        double tt[2];
-        grid_totals<2>(part_buf(A.part, epoch), tt);
-        rz_new = tt[0];
-        rr_in = tt[1];
-      }
+      const int cur = it & 1;
+      const bool first = it == 0;
+      const R al = (R)alpha, bt = (R)beta;
+      double v[3] = {0.0, 0.0, 0.0};
+      for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb, [&](int64_t o, uint8_t nb) {
+        const R ri = A.r[cur][o], wi = A.w[cur][o], D = A.dgR[o];
+        const R ui = ri / D;
+        const R pv = first ? ui : fma(bt, A.p[o], ui);
+        const R sv = first ? wi : fma(bt, A.s[cur ^ 1][o], wi);
+        A.p[o] = pv;
+        A.s[cur][o] = sv;
+        A.e[o] = fma(al, pv, A.e[o]);
+        const R r1 = fma(-al, sv, ri);
+        const R u1 = r1 / D;
+        R a = D * u1;
+        if (nb & NB_E) a += A.ceR[o] * u_next(A, o + 1, cur, first, al, bt);
+        if (nb & NB_W) a += A.ceR[o - 1] * u_next(A, o - 1, cur, first, al, bt);
+        if (nb & NB_N) a += A.cnR[o] * u_next(A, o + nx, cur, first, al, bt);
+        if (nb & NB_S) a += A.cnR[o - nx] * u_next(A, o - nx, cur, first, al, bt);
+        A.r[cur ^ 1][o] = r1;
+        A.w[cur ^ 1][o] = a;
+        v[0] += (double)r1 * (double)u1;
+        v[1] += (double)a * (double)u1;
+        v[2] += (double)r1 * (double)r1;
+      });
+      block_partials<3>(v, part_buf(A.part, k + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++k, G)) return;
+      double tt[3];
+      grid_totals<3>(part_buf(A.part, k), G, tt);
       total++;
-      if (sqrt(rr_in) <= tol_abs || total >= A.max_iter || !(rz_new == rz_new)) break;
-      beta = rz_new / rz;
-      rz = rz_new;
-      R* tmp = pold;
-      pold = pnew;
-      pnew = tmp;
+      const double gn = tt[0], dn = tt[1], rn = tt[2];
+      if (sqrt(rn) <= tol_abs || total >= A.max_iter || !(gn == gn) || gam == 0.0) break;
+      const double bn = gn / gam;
+      const double den = dn - bn * gn / alpha;
+      if (!(den != 0.0)) break;
+      beta = bn;
+      alpha = gn / den;
+      gam = gn;
     }
     // x += e (FP64)
-    for_cells(nx, A.ny, A.tiles_x, A.tile_list, nlist, A.nb,
+    for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb,
               [&](int64_t o, uint8_t nb) { A.x[o] += (double)A.e[o]; });
-    if (!grid_sync(A.bar, ++epoch)) return;
+    if (!grid_sync(A.bar, ++k, G)) return;
     sweep++;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
-  (void)done;
 }
 
-__global__ void k_bar_reset(unsigned* flags, int n) {
-  for (int i = threadIdx.x; i <= n; i += blockDim.x) flags[i] = 0u;
+__global__ void k_bar_reset(unsigned long long* count) {
+  if (threadIdx.x == 0) *count = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -1078,7 +1097,7 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.b = x->b;
   A.x = x->x;
   A.part = x->part;
-  A.bar.flags = x->bar;
+  A.bar.count = x->bar;
   A.bar.status = x->status;
   A.iters = x->iters;
   A.rel = x->rel;
@@ -1087,17 +1106,24 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   return A;
 }
 
+template <typename R>
+void set_vectors(PcgArgs<R>& A, R* const* v) {
+  A.r[0] = v[0];
+  A.r[1] = v[1];
+  A.w[0] = v[2];
+  A.w[1] = v[3];
+  A.s[0] = v[4];
+  A.s[1] = v[5];
+  A.p = v[6];
+  A.e = v[7];
+}
+
 PcgArgs<float> pcg_args32(const swe_nh_config* c, Ctx2D* x) {
   PcgArgs<float> A = pcg_common<float>(c, x);
   A.dgR = x->dg32;
   A.ceR = x->ce32;
   A.cnR = x->cn32;
-  A.r = x->r;
-  A.z = x->z;
-  A.pa = x->pa;
-  A.pb = x->pb;
-  A.q = x->q;
-  A.e = x->e;
+  set_vectors(A, x->v32);
   A.tol_in = 1e-4;  // each FP32 solve reduces the FP64 residual by this factor
   return A;
 }
@@ -1107,12 +1133,7 @@ PcgArgs<double> pcg_args64(const swe_nh_config* c, Ctx2D* x) {
   A.dgR = x->dg;
   A.ceR = x->ce;
   A.cnR = x->cn;
-  A.r = x->r64;
-  A.z = x->z64;
-  A.pa = x->pa64;
-  A.pb = x->pb64;
-  A.q = x->q64;
-  A.e = x->e64;
+  set_vectors(A, x->v64);
   A.tol_in = 0.0;
   return A;
 }
@@ -1125,7 +1146,7 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
 }
 
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(256), 0, s, x->bar, x->grid_pcg);
+  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, x->bar);
   if (c->precision == 1)
     hipLaunchKernelGGL(k_pcg2d<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, pcg_args32(c, x));
   else
@@ -1150,7 +1171,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->tiles_x = (c->nx + TX2 - 1) / TX2;
   x->tiles_y = (c->ny + TY2 - 1) / TY2;
   x->ntiles = x->tiles_x * x->tiles_y;
-  x->grid_pcg = x->ntiles < 256 ? x->ntiles : 256;
+  x->grid_pcg = x->ntiles < PCG_GMAX ? x->ntiles : PCG_GMAX;
   x->ht = (double*)take(8 * N);
   x->mt = (double*)take(8 * N);
   x->nt = (double*)take(8 * N);
@@ -1169,23 +1190,14 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->dg32 = (float*)take(4 * N);
   x->ce32 = (float*)take(4 * N);
   x->cn32 = (float*)take(4 * N);
-  if (c->precision == 1) {
-    x->r = (float*)take(4 * N);
-    x->z = (float*)take(4 * N);
-    x->pa = (float*)take(4 * N);
-    x->pb = (float*)take(4 * N);
-    x->q = (float*)take(4 * N);
-    x->e = (float*)take(4 * N);
-  } else {
-    x->r64 = (double*)take(8 * N);
-    x->z64 = (double*)take(8 * N);
-    x->pa64 = (double*)take(8 * N);
-    x->pb64 = (double*)take(8 * N);
-    x->q64 = (double*)take(8 * N);
-    x->e64 = (double*)take(8 * N);
+  for (int k = 0; k < 8; k++) {
+    if (c->precision == 1)
+      x->v32[k] = (float*)take(4 * N);
+    else
+      x->v64[k] = (double*)take(8 * N);
   }
-  x->part = (double*)take(8 * 2 * 4 * (size_t)x->grid_pcg);
-  x->bar = (unsigned*)take(4 * ((size_t)x->grid_pcg + 1));
+  x->part = (double*)take(8 * 2 * 4 * (size_t)PCG_GMAX);
+  x->bar = (unsigned long long*)take(8);
   x->iters = (int*)take(4);
   x->rel = (double*)take(8);
   if (c->warm == 2) {
