@@ -51,7 +51,8 @@ __global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict
   __syncthreads();
   if (threadIdx.x == 0) {
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    atomicMax(&P.smax[tl.x], pos_bits(m));
+    const int par = P.fused ? (*P.step & 1) : 0;
+    atomicMax(&P.smax[par * P.nch + tl.x], pos_bits(m));
     if (fl) atomicOr(P.status, fl);
   }
 }
@@ -164,9 +165,16 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
   const double t0 = t_in[tl.x];
   double dt;
   if (dt_from_speed) {
-    dt = (P.cfl > 0.0) ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[tl.x])
-                       : P.dt_fixed;
-    if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.dt[tl.x] = dt;
+    // fused step: the speed of Q^n is in buffer (step & 1); the other buffer
+    // collects the speed of Q^{n+1} during this step and is cleared here
+    const int par = P.fused ? (*P.step & 1) : 0;
+    const unsigned long long sm = P.smax[par * P.nch + tl.x];
+    dt = (P.cfl > 0.0) ? P.cfl * P.dx / __longlong_as_double((long long)sm) : P.dt_fixed;
+    if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) {
+      P.dt[tl.x] = dt;
+      if (P.fused) P.smax[(par ^ 1) * P.nch + tl.x] = 0ull;
+    }
+    if (P.fused && blockIdx.x == 0 && threadIdx.x == 0) *P.n_act = 0;
   } else {
     dt = dt_in[tl.x];
   }
@@ -553,6 +561,406 @@ __global__ void __launch_bounds__(256) k_correct1d(K1D P, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
+// tile-fused FP64 step: criterion + assembly + tile Schur reduction, level-1
+// system, projection
+// ---------------------------------------------------------------------------
+// The marked rows of a tile are consecutive rows of the packed system in cell
+// order.  The tile eliminates its interior rows (pinned first and last row,
+// parallel cyclic reduction for three right-hand sides), which leaves two
+// rows per tile: the level-1 system, tridiagonal over all tiles of all
+// channels.  Its solution gives every row as x = z + u x_first + v x_last.
+// A tile with one marked row keeps it as the first row, or as the last row
+// when it couples to the next tile.  Tiles without marked rows give identity
+// rows.
+namespace {
+
+// checks one cell of the final state and folds its wave speed into s
+__device__ __forceinline__ void final_state(double g, double hh, double mm, double kk, double& s,
+                                            int& flags) {
+  if (!isfinite(hh) || !isfinite(mm) || !isfinite(kk)) {
+    flags |= ST_NAN;
+  } else if (!(hh > 0.0)) {
+    flags |= ST_DRY;
+  } else {
+    s = fmax(s, fabs(mm / hh) + sqrt(g * hh));
+  }
+}
+
+// block max of s and OR of flags -> next step's speed buffer and status
+template <int NT>
+__device__ void flush_speed(const K1D& P, int chan, int par, double s, int flags) {
+  __shared__ double red[NT / 64];
+  __shared__ int fl;
+  if (threadIdx.x == 0) fl = 0;
+  s = wave_max(s);
+  __syncthreads();
+  if (flags) atomicOr(&fl, flags);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < NT / 64; w++) m = fmax(m, red[w]);
+    atomicMax(&P.smax[(par ^ 1) * P.nch + chan], pos_bits(m));
+    if (fl) atomicOr(P.status, fl);
+  }
+}
+
+// rank (in cell order) of the marked cells of a tile: thread t handles the
+// tile cells k = 1 + t + NT q; rank[q] is valid where the cell is marked.
+// Returns the number of marked cells.
+template <int T, int NT, typename On>
+__device__ int tile_ranks(On on_of, int (&rank)[T / NT], bool (&on)[T / NT]) {
+  __shared__ int wcnt[NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int base = 0;
+#pragma unroll
+  for (int q = 0; q < T / NT; q++) {
+    on[q] = on_of(1 + (int)threadIdx.x + NT * q);
+    const unsigned long long bal = __ballot(on[q]);
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int wb = 0, tot = 0;
+    for (int w = 0; w < NT / 64; w++) {
+      if (w < wv) wb += wcnt[w];
+      tot += wcnt[w];
+    }
+    rank[q] = base + wb + __popcll(bal & ((1ull << lane) - 1ull));
+    base += tot;
+    __syncthreads();
+  }
+  return base;
+}
+
+template <int T, int NT>
+struct NhSmem {
+  static constexpr int RW = 2 * NT;  // rows of the in-LDS system (>= T)
+  uint8_t raw[T + 2 + 2 * MAXE];
+  uint8_t mk[T + 2];
+  CellNH cq[T + 2];  // cells start-1 .. end (reflected at walls)
+  FaceNH fq[T + 1];  // faces start .. end
+  double a[RW], b[RW], c[RW], d[3][RW];
+};
+
+// parallel cyclic reduction of the first m rows (rows m..RW are identity)
+template <int T, int NT>
+__device__ void pcr_rows(NhSmem<T, NT>& S, int m) {
+  constexpr int RW = NhSmem<T, NT>::RW;
+  const int t = threadIdx.x;
+  for (int s = 1; s < m; s <<= 1) {
+    double na[2], nb[2], nc[2], nd[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const int i = 2 * t + j;
+      const int im = i - s, ip = i + s;
+      double bi = S.b[i], ai = 0.0, ci = 0.0;
+      double di[3] = {S.d[0][i], S.d[1][i], S.d[2][i]};
+      if (im >= 0) {
+        const double k1 = S.a[i] / S.b[im];
+        ai = -S.a[im] * k1;
+        bi -= S.c[im] * k1;
+#pragma unroll
+        for (int r = 0; r < 3; r++) di[r] -= S.d[r][im] * k1;
+      }
+      if (ip < RW) {
+        const double k2 = S.c[i] / S.b[ip];
+        ci = -S.c[ip] * k2;
+        bi -= S.a[ip] * k2;
+#pragma unroll
+        for (int r = 0; r < 3; r++) di[r] -= S.d[r][ip] * k2;
+      }
+      na[j] = ai;
+      nb[j] = bi;
+      nc[j] = ci;
+#pragma unroll
+      for (int r = 0; r < 3; r++) nd[j][r] = di[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const int i = 2 * t + j;
+      S.a[i] = na[j];
+      S.b[i] = nb[j];
+      S.c[i] = nc[j];
+#pragma unroll
+      for (int r = 0; r < 3; r++) S.d[r][i] = nd[j][r];
+    }
+    __syncthreads();
+  }
+}
+}  // namespace
+
+// criterion, step defaults, speed of the unmarked final state, assembly of
+// the tile's marked rows and their reduction to the two level-1 rows
+template <int T, int NT>
+__global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restrict__ ht,
+                                                  const double* __restrict__ mt,
+                                                  const double* __restrict__ kt,
+                                                  uint8_t* __restrict__ mask, double* h, double* hu,
+                                                  double* hw, double* p) {
+  constexpr int RW = NhSmem<T, NT>::RW;
+  __shared__ NhSmem<T, NT> S;
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
+  const int e = P.enlarge;
+  const int step = *P.step, par = step & 1;
+  const double dt = P.dt[tl.x], t1 = P.t[tl.x] + dt;
+  int mode;
+  {
+    const bool wcrit = (P.crit == SWE_NH_CRIT_W || P.crit == SWE_NH_CRIT_W_X);
+    if (P.crit == SWE_NH_CRIT_GLOBAL || (wcrit && P.first_global && step == 0))
+      mode = 1;
+    else if (P.crit == SWE_NH_CRIT_NONE)
+      mode = 2;
+    else
+      mode = 0;
+  }
+  const Motion M = body_motion(c, t1);
+  // indicator on cells start-1-e .. end+e, mask on cells start-1 .. end
+  if (mode == 0) {
+    for (int w = threadIdx.x; w < len + 2 + 2 * e; w += NT) {
+      const int i = start - 1 - e + w;
+      uint8_t r = 0;
+      if (i >= 0 && i < n) r = indicator1d(P, c, M, ht, mt, kt, i, P.crit) > P.k_nh;
+      S.raw[w] = r;
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < len + 2; k += NT) {
+    const int i = start - 1 + k;
+    uint8_t v = 0;
+    if (i >= 0 && i < n) {
+      if (mode == 1) {
+        v = 1;
+      } else if (mode == 0) {
+        for (int j = 0; j <= 2 * e; j++) v |= S.raw[k + j];
+      }
+    }
+    S.mk[k] = v;
+  }
+  __syncthreads();
+  // tile cells: mask, defaults h = h~, hu = hu~, hw = hw~ (p = 0 off the
+  // marked area), final-state speed where no projection follows
+  double smax = 0.0;
+  int flags = 0;
+#pragma unroll
+  for (int q = 0; q < T / NT; q++) {
+    const int k = 1 + threadIdx.x + NT * q;
+    if (k > len) continue;
+    const int64_t gi = c.off + start + k - 1;
+    const bool on = S.mk[k] != 0;
+    const double hh = ht[gi], mm = mt[gi], kk = kt[gi];
+    mask[gi] = on;
+    h[gi] = hh;
+    hu[gi] = mm;
+    hw[gi] = kk;
+    if (!on) {
+      p[gi] = 0.0;
+      final_state(P.g, hh, mm, kk, smax, flags);
+    }
+  }
+  flush_speed<NT>(P, tl.x, par, smax, flags);
+  int rank[T / NT];
+  bool on[T / NT];
+  const int m =
+      tile_ranks<T, NT>([&](int k) { return k <= len && S.mk[k] != 0; }, rank, on);
+  const int F = 2 * blockIdx.x, L = F + 1;
+  if (threadIdx.x == 0) {
+    P.tile_cnt[blockIdx.x] = m;
+    if (m) atomicAdd(P.n_act, m);
+  }
+  if (m == 0) {
+    if (threadIdx.x == 0) {
+      P.dg1[F] = 1.0;
+      P.up1[F] = 0.0;
+      P.rh1[F] = 0.0;
+      P.dg1[L] = 1.0;
+      P.up1[L] = 0.0;
+      P.rh1[L] = 0.0;
+    }
+    return;
+  }
+  // cell and face quantities of the elliptic system (Eqs. 10-17) at t^{n+1}
+  Local Lc{&P, &c, ht, mt, kt, M, dt, P.dx};
+  for (int k = threadIdx.x; k < len + 2; k += NT) S.cq[k] = Lc.cell(reflect(start - 1 + k, n));
+  __syncthreads();
+  for (int f = threadIdx.x; f <= len; f += NT)
+    S.fq[f] = Lc.face(start + f, S.cq[f].phi, S.cq[f + 1].phi);
+  for (int j = m + threadIdx.x; j < RW; j += NT) {
+    S.a[j] = 0.0;
+    S.b[j] = 1.0;
+    S.c[j] = 0.0;
+    S.d[0][j] = 0.0;
+  }
+  __syncthreads();
+  const int64_t zs = (int64_t)P.ntiles * T;  // stride of the zw planes
+  const int64_t pb = (int64_t)blockIdx.x * T;
+#pragma unroll
+  for (int q = 0; q < T / NT; q++) {
+    if (!on[q]) continue;
+    const int k = 1 + threadIdx.x + NT * q, j = rank[q];
+    const int i = start + k - 1;
+    const int64_t gi = c.off + i;
+    const FaceNH fl = S.fq[k - 1], fr = S.fq[k];
+    const CellNH c0 = S.cq[k];
+    const double hs = ht[gi];
+    const double s22 = 3.0 * dt / (P.rho * hs);
+    const BedRate br = bed_rate(M, body_shape(c, (i + 0.5) * P.dx - M.X, 0.0));
+    const double f2 = -2.0 * br.d_t - 2.0 * kt[gi] / hs - c0.D * mt[gi] / (2.0 * hs) -
+                      dt * c0.al * c0.phi / (2.0 * P.rho * hs);
+    S.a[j] = (i > 0 && S.mk[k - 1]) ? fl.K * fl.a * fl.b : 0.0;
+    S.b[j] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
+    S.c[j] = (i + 1 < n && S.mk[k + 1]) ? fr.K * fr.a * fr.b : 0.0;
+    S.d[0][j] = f2 + fl.b * fl.qp + fr.a * fr.qp;
+    double* z = P.zw + pb + j;
+    z[ZW_KL * zs] = fl.K;
+    z[ZW_AL * zs] = fl.a;
+    z[ZW_BL * zs] = fl.b;
+    z[ZW_FL * zs] = fl.fd;
+    z[ZW_KR * zs] = fr.K;
+    z[ZW_AR * zs] = fr.a;
+    z[ZW_BR * zs] = fr.b;
+    z[ZW_FR * zs] = fr.fd;
+    z[ZW_D * zs] = c0.D;
+    z[ZW_P * zs] = c0.al * c0.phi / 4.0;
+  }
+  __syncthreads();
+  if (m == 1) {
+    if (threadIdx.x == 0) {
+      const bool asL = S.c[0] != 0.0;  // couples to the next tile's first row
+      P.dg1[F] = asL ? 1.0 : S.b[0];
+      P.up1[F] = 0.0;
+      P.rh1[F] = asL ? 0.0 : S.d[0][0];
+      P.dg1[L] = asL ? S.b[0] : 1.0;
+      P.up1[L] = asL ? S.c[0] : 0.0;
+      P.rh1[L] = asL ? S.d[0][0] : 0.0;
+      P.zw[pb + ZW_Z * zs] = 0.0;
+      P.zw[pb + ZW_U * zs] = asL ? 0.0 : 1.0;
+      P.zw[pb + ZW_V * zs] = asL ? 1.0 : 0.0;
+    }
+    return;
+  }
+  // keep the end rows, then pin them: x_first and x_last become parameters
+  const double b0 = S.b[0], c0 = S.c[0], d0 = S.d[0][0];
+  const double aL = S.a[m - 1], bL = S.b[m - 1], cL = S.c[m - 1], dL = S.d[0][m - 1];
+  __syncthreads();
+  for (int j = threadIdx.x; j < RW; j += NT) {
+    const bool first = j == 0, last = j == m - 1;
+    if (first || last) {
+      S.a[j] = 0.0;
+      S.c[j] = 0.0;
+      S.b[j] = 1.0;
+      S.d[0][j] = 0.0;
+    }
+    S.d[1][j] = first ? 1.0 : 0.0;
+    S.d[2][j] = last ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  pcr_rows<T, NT>(S, m);
+  for (int j = threadIdx.x; j < m; j += NT) {
+    const double ib = 1.0 / S.b[j];
+    P.zw[pb + j + ZW_Z * zs] = S.d[0][j] * ib;
+    P.zw[pb + j + ZW_U * zs] = S.d[1][j] * ib;
+    P.zw[pb + j + ZW_V * zs] = S.d[2][j] * ib;
+  }
+  if (threadIdx.x == 0) {
+    const double z1 = S.d[0][1] / S.b[1], u1 = S.d[1][1] / S.b[1], v1 = S.d[2][1] / S.b[1];
+    const double zL = S.d[0][m - 2] / S.b[m - 2], vL = S.d[2][m - 2] / S.b[m - 2];
+    P.dg1[F] = b0 + c0 * u1;
+    P.up1[F] = c0 * v1;
+    P.rh1[F] = d0 - c0 * z1;
+    P.dg1[L] = bL + aL * vL;
+    P.up1[L] = cL;
+    P.rh1[L] = dL - aL * zL;
+  }
+}
+
+// projection of the marked cells from the level-1 solution, speed of their
+// final state; the last block to finish advances t and the step counter
+// (advance = 0: stage timing, the step does not advance)
+template <int T, int NT>
+__global__ void __launch_bounds__(NT) k_nh1d_apply(K1D P, const double* __restrict__ ht,
+                                                   const double* __restrict__ mt,
+                                                   const double* __restrict__ kt,
+                                                   const uint8_t* __restrict__ mask, double* hu,
+                                                   double* hw, double* p, int advance) {
+  __shared__ double xs[T + 2];
+  __shared__ int last;
+  const int2 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];
+  const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
+  const int par = *P.step & 1;
+  const double dt = P.dt[tl.x];
+  const int m = P.tile_cnt[blockIdx.x];
+  double smax = 0.0;
+  int flags = 0;
+  if (m > 0) {
+    int rank[T / NT];
+    bool on[T / NT];
+    const int64_t m0 = c.off + start - 1;  // mask[m0 + k]: tile-local cell k
+    tile_ranks<T, NT>([&](int k) { return k <= len && mask[m0 + k] != 0; }, rank, on);
+    const int64_t zs = (int64_t)P.ntiles * T;
+    const int64_t pb = (int64_t)blockIdx.x * T;
+    const double xF = P.x1[2 * blockIdx.x], xL = P.x1[2 * blockIdx.x + 1];
+#pragma unroll
+    for (int q = 0; q < T / NT; q++) {
+      const int k = 1 + threadIdx.x + NT * q;
+      if (k > len) continue;
+      double x = 0.0;
+      if (on[q]) {
+        const double* z = P.zw + pb + rank[q];
+        x = z[ZW_Z * zs] + z[ZW_U * zs] * xF + z[ZW_V * zs] * xL;
+      }
+      xs[k] = x;
+    }
+    if (threadIdx.x == 0) {
+      xs[0] = (start > 0 && mask[m0]) ? P.x1[2 * blockIdx.x - 1] : 0.0;
+      xs[len + 1] = (end < n && mask[m0 + len + 1]) ? P.x1[2 * blockIdx.x + 2] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < T / NT; q++) {
+      if (!on[q]) continue;
+      const int k = 1 + threadIdx.x + NT * q;
+      const int64_t gi = c.off + start + k - 1;
+      const double* z = P.zw + pb + rank[q];
+      const double pc = xs[k], pl = xs[k - 1], pr = xs[k + 1];
+      const double dql = z[ZW_FL * zs] - z[ZW_KL * zs] * (z[ZW_AL * zs] * pl + z[ZW_BL * zs] * pc);
+      const double dqr = z[ZW_FR * zs] - z[ZW_KR * zs] * (z[ZW_AR * zs] * pc + z[ZW_BR * zs] * pr);
+      const double dm = 0.5 * (dql + dqr);
+      const double Pb = 1.5 * pc - P.rho * z[ZW_D * zs] * dm / (4.0 * dt) + z[ZW_P * zs];
+      const double hn = ht[gi], mn = mt[gi] + dm, kn = kt[gi] + dt * Pb / P.rho;
+      hu[gi] = mn;
+      hw[gi] = kn;
+      p[gi] = pc;
+      final_state(P.g, hn, mn, kn, smax, flags);
+    }
+  }
+  flush_speed<NT>(P, tl.x, par, smax, flags);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = __hip_atomic_fetch_add(P.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    if (advance)
+      for (int ch = threadIdx.x; ch < P.nch; ch += NT) P.t[ch] += P.dt[ch];
+    if (threadIdx.x == 0) {
+      if (advance) *P.step += 1;
+      *P.done = 0;
+    }
+  }
+}
+
+// prologue of a run of steps: speed of the caller's state into buffer
+// (step & 1) after clearing it
+__global__ void k_smax_clear(K1D P) {
+  const int par = *P.step & 1;
+  for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) P.smax[par * P.nch + ch] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
 __global__ void k_fill_f64(double* a, int64_t n, double v) {
@@ -672,6 +1080,42 @@ void launch_scatter_packed(const int* act_cell, const int* n_act, int64_t max_ro
                            const double* packed, double* full, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter_packed, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s,
                      act_cell, n_act, packed, full);
+}
+
+template <int T, int NT>
+static void launch_fused_pair(const K1D& P, const double* ht, const double* mt, const double* kt,
+                              uint8_t* mask, double* h, double* hu, double* hw, double* p,
+                              bool tile_pass, int advance, hipStream_t s) {
+  if (tile_pass)
+    hipLaunchKernelGGL((k_nh1d_tile<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, ht, mt, kt, mask,
+                       h, hu, hw, p);
+  else
+    hipLaunchKernelGGL((k_nh1d_apply<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, ht, mt, kt,
+                       (const uint8_t*)mask, hu, hw, p, advance);
+}
+static void launch_fused(const K1D& P, const double* ht, const double* mt, const double* kt,
+                         uint8_t* mask, double* h, double* hu, double* hw, double* p,
+                         bool tile_pass, int advance, hipStream_t s) {
+  if (P.tile == 128)
+    launch_fused_pair<128, 128>(P, ht, mt, kt, mask, h, hu, hw, p, tile_pass, advance, s);
+  else if (P.tile == 256)
+    launch_fused_pair<256, 256>(P, ht, mt, kt, mask, h, hu, hw, p, tile_pass, advance, s);
+  else
+    launch_fused_pair<512, 256>(P, ht, mt, kt, mask, h, hu, hw, p, tile_pass, advance, s);
+}
+void launch_nh1d_tile(const K1D& P, const double* ht, const double* mt, const double* kt,
+                      uint8_t* mask, double* h, double* hu, double* hw, double* p, hipStream_t s) {
+  launch_fused(P, ht, mt, kt, mask, h, hu, hw, p, true, 1, s);
+}
+void launch_nh1d_apply(const K1D& P, const double* ht, const double* mt, const double* kt,
+                       const uint8_t* mask, double* hu, double* hw, double* p, int advance,
+                       hipStream_t s) {
+  launch_fused(P, ht, mt, kt, const_cast<uint8_t*>(mask), nullptr, hu, hw, p, false, advance, s);
+}
+void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_smax_clear, dim3(1), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_speed1d, dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw);
 }
 
 }  // namespace swenh

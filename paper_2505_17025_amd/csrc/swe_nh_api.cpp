@@ -62,6 +62,8 @@ struct swe_nh_ctx {
   uint8_t* mask_ws = nullptr;
   TriLevels<double> T64{};
   TriLevels<float> T32{};
+  TriLevels<double> T1{};  // level-1 system of the tile-fused step
+  int* n1 = nullptr;       // its row count (2 per tile)
   // 2D
   Ctx2D c2{};
   // graph of one step
@@ -181,7 +183,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   P.first_tile = cv.take<int>(nch);
   P.t = cv.take<double>(nch);
   P.dt = cv.take<double>(nch);
-  P.smax = cv.take<unsigned long long>(nch);
+  P.smax = cv.take<unsigned long long>(2 * (size_t)nch);
   x->stage_t = cv.take<double>(nch);
   x->stage_dt = cv.take<double>(nch);
   x->status = cv.take<int>(1);
@@ -193,6 +195,9 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   x->rel = cv.take<double>(1);
   int* nbuf64 = cv.take<int>(TRI_MAX_LEVELS);
   int* nbuf32 = cv.take<int>(TRI_MAX_LEVELS);
+  int* nbuf1 = cv.take<int>(TRI_MAX_LEVELS);
+  P.done = cv.take<int>(1);
+  x->n1 = cv.take<int>(1);
   if (c->dim == 1) {
     P.tile_cnt = cv.take<int>(ntiles);
     P.tile_off = cv.take<int>(ntiles);
@@ -204,6 +209,14 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
     x->mask_ws = cv.take<uint8_t>(N);
     plan_levels(&x->T64, N, cv, nbuf64);
     if (c->precision == 1) plan_levels(&x->T32, N, cv, nbuf32);
+    if (c->precision == 0) {  // tile-fused step
+      plan_levels(&x->T1, 2 * (int64_t)ntiles, cv, nbuf1);
+      P.zw = cv.take<double>((size_t)ZW_N * ntiles * tile_of(c));
+      P.dg1 = x->T1.dg[0];
+      P.up1 = x->T1.up[0];
+      P.rh1 = x->T1.rh[0];
+      P.x1 = x->T1.x[0];
+    }
     x->nparts = resid_blocks(N);
     x->part = cv.take<double>(x->nparts);
     x->part_b = cv.take<double>(x->nparts);
@@ -262,6 +275,16 @@ void enqueue_step1d(swe_nh_ctx* c, hipStream_t s, double* h, double* hu, double*
   K1D& P = c->k1;
   uint8_t* M = mask ? mask : c->mask_ws;
   const int64_t N = c->ncells;
+  if (P.fused) {
+    // predictor; criterion + assembly + tile reduction; level-1 solve;
+    // projection + next speed + advance (the speed of the caller's state is
+    // computed once per call, before the first step)
+    launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 1, s);
+    launch_nh1d_tile(P, c->ht, c->mt, c->kt, M, h, hu, hw, p, s);
+    launch_tri_solve(c->T1, c->n1, nullptr, s);
+    launch_nh1d_apply(P, c->ht, c->mt, c->kt, M, hu, hw, p, 1, s);
+    return;
+  }
   launch_speed1d(P, h, hu, hw, s);
   launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 1, s);
   launch_mask1d(P, c->ht, c->mt, c->kt, P.t, P.dt, -1, M, h, hu, hw, p, 1, s);
@@ -376,6 +399,9 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.first_global = cfg->first_global;
   P.ntiles = (int)c->tiles.size();
   P.tile = tile_of(cfg);
+  P.nch = c->nch;
+  P.fused = (cfg->dim == 1 && cfg->precision == 0) ? 1 : 0;
+  const int n1 = 2 * P.ntiles;
   std::vector<double> zeros(c->nch, 0.0);
   std::vector<unsigned long long> zu(c->nch, 0ull);
   int zi[TRI_MAX_LEVELS * 2] = {0};
@@ -392,6 +418,12 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   INIT_COPY(P.t, zeros.data(), sizeof(double) * c->nch);
   INIT_COPY(P.dt, zeros.data(), sizeof(double) * c->nch);
   INIT_COPY(P.smax, zu.data(), sizeof(unsigned long long) * c->nch);
+  INIT_COPY(P.smax + c->nch, zu.data(), sizeof(unsigned long long) * c->nch);
+  INIT_COPY(P.done, zi, sizeof(int));
+  if (P.fused) {
+    INIT_COPY(c->n1, &n1, sizeof(int));
+    INIT_COPY(c->T1.n, zi, sizeof(int) * TRI_MAX_LEVELS);
+  }
   INIT_COPY(c->status, zi, sizeof(int));
   INIT_COPY(c->step, zi, sizeof(int));
   INIT_COPY(c->n_act, zi, sizeof(int));
@@ -465,6 +497,11 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
     hipGraphDestroy(g);
     if (e3 != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("instantiate: ") + hipGetErrorString(e3));
     for (int i = 0; i < 6; i++) c->gkey[i] = key[i];
+  }
+  if (c->k1.fused && nsteps > 0) {
+    launch_speed_prologue(c->k1, h, hu, hw, c->stream);
+    int rc = after_launch(c);
+    if (rc) return rc;
   }
   for (int i = 0; i < nsteps; i++) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
   c->steps_taken += nsteps;
@@ -661,6 +698,18 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
     if (c->cfg.dim == 1) {
       K1D& P = c->k1;
       uint8_t* M = c->mask_ws;
+      if (P.fused) {
+        // the fused kernels write into workspace scratch (level-0 arrays of
+        // the packed solver, unused by this path), never the caller's state
+        double *s0 = c->T64.dg[0], *s1 = c->T64.up[0], *s2 = c->T64.rh[0], *s3 = c->T64.x[0];
+        switch (stage) {
+          case 0: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s); break;
+          case 1: launch_nh1d_tile(P, c->ht, c->mt, c->kt, M, s0, s1, s2, s3, s); break;
+          case 2: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
+          default: launch_nh1d_apply(P, c->ht, c->mt, c->kt, M, s0, s1, s3, 0, s);
+        }
+        continue;
+      }
       switch (stage) {
         case 0: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s); break;
         case 1: launch_mask1d(P, c->ht, c->mt, c->kt, P.t, P.dt, 0, M, nullptr, nullptr, nullptr,

@@ -32,7 +32,18 @@ struct K1D {
   int* n_act;              // marked cells
   int* act_cell;           // [cells] packed row -> global cell
   int* act_chan;           // [cells] packed row -> channel
+  // tile-fused step (FP64): smax is then [2][batch], selected by step parity
+  int fused;
+  int nch;
+  int* done;               // blocks of the projection kernel finished this step
+  double* zw;              // [ZW_N][ntiles * tile] per marked row, tile-padded
+  double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
+  const double* x1;        // level-1 solution
 };
+
+// per marked row of the tile-fused step: solution basis of the tile's
+// interior system (x = z + u x_first + v x_last) and the projection data
+enum { ZW_Z, ZW_U, ZW_V, ZW_KL, ZW_AL, ZW_BL, ZW_FL, ZW_KR, ZW_AR, ZW_BR, ZW_FR, ZW_D, ZW_P, ZW_N };
 
 // ---- 1D stencil / mask / projection ----
 void launch_speed1d(const K1D& P, const double* h, const double* hu, const double* hw,
@@ -54,6 +65,15 @@ void launch_correct1d(const K1D& P, int64_t max_rows, const double* ht, const do
                       const double* dt_in, const double* x, double* hu, double* hw, double* p,
                       hipStream_t s);
 void launch_advance(const K1D& P, int nch, hipStream_t s);
+// tile-fused step: criterion + assembly + tile Schur reduction, and the
+// projection from the level-1 solution (plus next-step speed and advance)
+void launch_nh1d_tile(const K1D& P, const double* ht, const double* mt, const double* kt,
+                      uint8_t* mask, double* h, double* hu, double* hw, double* p, hipStream_t s);
+void launch_nh1d_apply(const K1D& P, const double* ht, const double* mt, const double* kt,
+                       const uint8_t* mask, double* hu, double* hw, double* p, int advance,
+                       hipStream_t s);
+void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
+                           hipStream_t s);
 void launch_fill(double* a, int64_t n, double v, hipStream_t s);
 void launch_fill_i32(int* a, int64_t n, int v, hipStream_t s);
 void launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
