@@ -60,6 +60,22 @@ def pmc_traffic(kernel_file, src_file):
     return float(t.group(1)) if t else None
 
 
+def tune_tile(B, torch, case, kw, nsteps, warmup):
+    """tile1d picked by the launch-shape autotuner on this workload"""
+    from paper_2505_17025_amd import autotune
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    if hasattr(case, "channels"):
+        state = (f(case.packed("h")), f(case.packed("hu")), f(case.packed("hw")))
+        t0 = [c.t0 for c in case.channels]
+    else:
+        state = (f(case.h), f(case.hu), f(case.hw))
+        t0 = case.t0
+    tile, times = autotune.tune_1d(case, kw, state, t0, nsteps=nsteps, warmup=warmup)
+    log(f"autotune tile1d: {tile} ({ {k: round(v * 1e6, 2) for k, v in times.items()} } us/step)")
+    return tile, {str(k): v * 1e6 for k, v in times.items()}
+
+
 def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000):
     dev = torch.device("cuda:0")
     f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -89,10 +105,31 @@ def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000):
            "n_active_last": int(st["n_active"]), "t_end": st["t"], "iters_last": st["iters"],
            "cells": ncell}
     if reps_stage:
-        out["stage_us"] = {name: ctx.time_stage(i, reps_stage if i != 2 else max(1, reps_stage // 4),
-                                                h, hu, None, hw, p)
-                           for i, name in enumerate(["predictor", "mask", "solve", "projection"])}
+        if kw.get("precision", 0) == 0:  # fused step: its kernels one by one
+            names = ["step_kernel", "level1_solve", "projection", "predictor_alone"]
+            reps = [reps_stage] * 4
+        else:
+            names = ["predictor", "mask", "solve", "projection"]
+            reps = [reps_stage, reps_stage, max(1, reps_stage // 4), reps_stage]
+        out["stage_us"] = {nm: ctx.time_stage(i, r, h, hu, None, hw, p)
+                           for i, (nm, r) in enumerate(zip(names, reps))}
     return out
+
+
+STEP1D_BYTES = 65.0  # per cell: read h, hu, hw, d_s; write h, hu, hw, p (FP64) and the mask byte
+
+
+def step_roofline(ncell, stage_us, pmc_file):
+    """roofline of the fused 1D step kernel (the dominant kernel of the FP64 1D path)"""
+    us = stage_us["step_kernel"]
+    per_launch = ncell * STEP1D_BYTES
+    achieved = per_launch / (us * 1e-6) / 1e9
+    return {"kernel": "k_step1d", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pmc_traffic(pmc_file, "paper_2505_17025_amd/csrc/swe_nh_1d.hip")
+            if pmc_file else None,
+            "avg_launch_us": us, "bytes_per_launch": per_launch,
+            "bytes_per_cell": STEP1D_BYTES, "stage_us": stage_us}
 
 
 def cpu_baseline_1d(case, kw, nsteps):
@@ -125,6 +162,8 @@ def main():
         warmup = args.warmup if args.warmup is not None else 200
         case = S.slide_case(n=32768, dx=0.005)
         kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=0)
+        tile, tune_us = tune_tile(B, torch, case, kw, 400, 100)
+        kw["tile1d"] = tile
         log(f"slide1d: {case.n} cells, {warmup} warmup + {steps} timed steps")
         res = run_1d(B, torch, case, kw, steps, warmup)
         log("adaptive fp64:", json.dumps(res))
@@ -143,15 +182,7 @@ def main():
                      "paper_context": "paper: adaptive saves more than 50% of the global time "
                                       "(t_local/t_global 0.07-0.40 with |eta/d| + 1-cell "
                                       "enlargement), hardware not stated"}
-        per_launch_bytes = case.n * 56.0  # read h, hu, hw, d_s; write h~, hu~, hw~ (FP64)
-        pred_us = res["stage_us"]["predictor"]
-        achieved = per_launch_bytes / (pred_us * 1e-6) / 1e9
-        roof = {"kernel": "k_pred1d", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": pmc_traffic("pred1d_slide32768_pmc.txt",
-                                       "paper_2505_17025_amd/csrc/swe_nh_1d.hip"),
-                "avg_launch_us": pred_us, "bytes_per_launch": per_launch_bytes,
-                "stage_us": res["stage_us"]}
+        roof = step_roofline(case.n, res["stage_us"], "step1d_slide32768_pmc.txt")
         cpu = None
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
@@ -164,7 +195,8 @@ def main():
                                        "15 deg slope into h0=0.4 m, sinusoidal-ramp displacement, "
                                        "N=32768, dx=0.005 m, adaptive |eta/d|>1e-3 + 1-cell "
                                        "enlargement, FP64 direct solve, CFL 0.5",
-                           "cells": case.n, "criterion": "eta_d", "k_nh": 1e-3, "enlarge": 1},
+                           "cells": case.n, "criterion": "eta_d", "k_nh": 1e-3, "enlarge": 1,
+                           "tile1d": tile, "autotune_us_per_step": tune_us},
                 "roofline": roof, "cpu_baseline": cpu, "extra": extra}
         print(json.dumps(line), flush=True)
     elif args.workload == "ensemble1d":
@@ -174,13 +206,16 @@ def main():
         kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1, tol=1e-12,
                   max_iter=6)
         log(f"ensemble1d: 512 channels, {int(ens.offsets[-1])} cells")
+        tile, tune_us = tune_tile(B, torch, ens, dict(kw, precision=0), 30, 5)
+        kw["tile1d"] = tile
         res = run_1d(B, torch, ens, kw, steps, warmup, reps_stage=50)
         log("adaptive fp32+refine:", json.dumps(res))
-        r64 = run_1d(B, torch, ens, dict(kw, precision=0), steps, warmup, reps_stage=0)
+        r64 = run_1d(B, torch, ens, dict(kw, precision=0), steps, warmup, reps_stage=50)
         g = run_1d(B, torch, ens, dict(kw, crit=S.CRIT_GLOBAL), steps, warmup, reps_stage=0)
         ncell = res["cells"]
         pred_us = res["stage_us"]["predictor"]
         achieved = ncell * 56.0 / (pred_us * 1e-6) / 1e9
+        r64s = r64.get("stage_us")
         line = {"metric": METRIC, "value": res["cell_steps_per_s"], "unit": "cell-steps/s",
                 "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": res["ms_per_step"],
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -188,13 +223,15 @@ def main():
                 "config": {"workload": "512 independent 1D slide channels, lengths U{4096..65536}, "
                                        "slide length/height/slope from seeded uniform ranges, "
                                        "adaptive |eta/d|, FP32 solve + FP64 refinement, one "
-                                       "hipGraph per step", "cells": ncell},
+                                       "hipGraph per step", "cells": ncell, "tile1d": tile,
+                           "autotune_us_per_step": tune_us},
                 "roofline": {"kernel": "k_pred1d", "bound": "hbm", "achieved": achieved,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                              "traffic": None, "avg_launch_us": pred_us,
                              "bytes_per_launch": ncell * 56.0, "stage_us": res["stage_us"]},
                 "cpu_baseline": None,
                 "extra": {"fp64_cell_steps_per_s": r64["cell_steps_per_s"],
+                          "fp64_roofline": step_roofline(ncell, r64s, None),
                           "global_cell_steps_per_s": g["cell_steps_per_s"],
                           "n_active_last": res["n_active_last"]}}
         print(json.dumps(line), flush=True)

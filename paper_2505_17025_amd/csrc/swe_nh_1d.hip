@@ -561,9 +561,15 @@ __global__ void __launch_bounds__(256) k_correct1d(K1D P, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// tile-fused FP64 step: criterion + assembly + tile Schur reduction, level-1
-// system, projection
+// fused FP64 step
 // ---------------------------------------------------------------------------
+// One kernel per tile runs both Heun stages on an LDS window that extends the
+// tile by e + 2 cells on each side (e = enlargement), so that the criterion,
+// its enlargement and the elliptic coefficients of the tile's cells and faces
+// all read Q~ from LDS; Q~ never goes to HBM.  The new state goes to a second
+// buffer (the caller's arrays and the workspace alternate), because
+// neighbouring tiles still read Q^n.
+//
 // The marked rows of a tile are consecutive rows of the packed system in cell
 // order.  The tile eliminates its interior rows (pinned first and last row,
 // parallel cyclic reduction for three right-hand sides), which leaves two
@@ -573,6 +579,9 @@ __global__ void __launch_bounds__(256) k_correct1d(K1D P, const double* __restri
 // when it couples to the next tile.  Tiles without marked rows give identity
 // rows.
 namespace {
+constexpr int EMAXF = 8;          // largest enlargement of the fused step
+constexpr int HMAXF = EMAXF + 2;  // Q~ beyond the tile: criterion stencil + enlargement
+constexpr int L1MAX = 512;        // level-1 rows solved inside the projection kernel
 
 // checks one cell of the final state and folds its wave speed into s
 __device__ __forceinline__ void final_state(double g, double hh, double mm, double kk, double& s,
@@ -632,41 +641,164 @@ __device__ int tile_ranks(On on_of, int (&rank)[T / NT], bool (&on)[T / NT]) {
 }
 
 template <int T, int NT>
-struct NhSmem {
-  static constexpr int RW = 2 * NT;  // rows of the in-LDS system (>= T)
-  uint8_t raw[T + 2 + 2 * MAXE];
+struct StepSmem {
+  static constexpr int WMAX = T + 2 * (4 + HMAXF);  // predictor window
+  static constexpr int RW = T > NT ? T : NT;        // rows of the in-LDS tile system
+  // eta (then h~ after the predictor), hu, hw; depth at t^n and t^{n+1}
+  double e[WMAX], m[WMAX], k[WMAX], d0[WMAX], d1[WMAX];
+  union {
+    struct {
+      double Fh[WMAX], FmL[WMAX], FmR[WMAX], Fk[WMAX], hL[WMAX], hR[WMAX];
+    } f;  // face fluxes of a predictor stage
+    struct {
+      CellNH cq[T + 2];  // cells start-1 .. end
+      FaceNH fq[T + 1];  // faces start .. end
+    } q;
+    struct {
+      double a[RW], b[RW], c[RW], d[3][RW];
+    } s;  // tile system
+  } u;
+  uint8_t raw[T + 2 + 2 * EMAXF];
   uint8_t mk[T + 2];
-  CellNH cq[T + 2];  // cells start-1 .. end (reflected at walls)
-  FaceNH fq[T + 1];  // faces start .. end
-  double a[RW], b[RW], c[RW], d[3][RW];
 };
 
-// parallel cyclic reduction of the first m rows (rows m..RW are identity)
+// face fluxes of one predictor stage on faces [f0, f1) of the window (face f
+// between window cells f-1 and f); dry faces touching channel cells of
+// [lo_cell, hi_cell) raise the flag
+template <typename SM>
+__device__ __forceinline__ void step_faces(SM& S, const double* d, double g, int f0, int f1,
+                                           int lo_cell, int hi_cell, int base, int& flags) {
+  for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
+    const int l = f - 1, r = f;
+    const double se_l = minmod(S.e[l] - S.e[l - 1], S.e[l + 1] - S.e[l]);
+    const double sm_l = minmod(S.m[l] - S.m[l - 1], S.m[l + 1] - S.m[l]);
+    const double sk_l = minmod(S.k[l] - S.k[l - 1], S.k[l + 1] - S.k[l]);
+    const double sd_l = minmod(d[l] - d[l - 1], d[l + 1] - d[l]);
+    const double se_r = minmod(S.e[r] - S.e[r - 1], S.e[r + 1] - S.e[r]);
+    const double sm_r = minmod(S.m[r] - S.m[r - 1], S.m[r + 1] - S.m[r]);
+    const double sk_r = minmod(S.k[r] - S.k[r - 1], S.k[r + 1] - S.k[r]);
+    const double sd_r = minmod(d[r] - d[r - 1], d[r + 1] - d[r]);
+    const Flux F = rusanov1d(g, S.e[l] + 0.5 * se_l, S.m[l] + 0.5 * sm_l, S.k[l] + 0.5 * sk_l,
+                             d[l] + 0.5 * sd_l, S.e[r] - 0.5 * se_r, S.m[r] - 0.5 * sm_r,
+                             S.k[r] - 0.5 * sk_r, d[r] - 0.5 * sd_r);
+    S.u.f.Fh[f] = F.Fh;
+    S.u.f.FmL[f] = F.FmL;
+    S.u.f.FmR[f] = F.FmR;
+    S.u.f.Fk[f] = F.Fk;
+    S.u.f.hL[f] = F.hL;
+    S.u.f.hR[f] = F.hR;
+    const int il = base + l, ir = base + r;
+    const bool used = (il >= lo_cell && il < hi_cell) || (ir >= lo_cell && ir < hi_cell);
+    if (F.dry && used) flags |= ST_DRY;
+  }
+}
+
+template <typename SM>
+__device__ __forceinline__ void step_cell(const SM& S, const double* d, double g, double idx,
+                                          int e, double& Lh, double& Lm, double& Lk) {
+  const double sd = minmod(d[e] - d[e - 1], d[e + 1] - d[e]);
+  Lh = -(S.u.f.Fh[e + 1] - S.u.f.Fh[e]) * idx;
+  Lm = -(S.u.f.FmL[e + 1] - S.u.f.FmR[e]) * idx +
+       g * 0.5 * (S.u.f.hL[e + 1] + S.u.f.hR[e]) * sd * idx;
+  Lk = -(S.u.f.Fk[e + 1] - S.u.f.Fk[e]) * idx;
+}
+
+// Q~ and the depth at t^{n+1} of channel cells, read from the window
+struct WinQ {
+  const double *h, *m, *k, *d;  // window arrays
+  int lo, n;
+  double dx;
+  __device__ double H(int i) const { return h[reflect(i, n) - lo]; }
+  __device__ double D(int i) const { return d[reflect(i, n) - lo]; }
+  // momentum of cell i, odd under the wall reflection
+  __device__ double Mo(int i) const {
+    const int s = reflect(i, n);
+    return (s == i ? 1.0 : -1.0) * m[s - lo];
+  }
+  __device__ double K(int i) const { return k[reflect(i, n) - lo]; }
+};
+
+// criterion of Sec. 5.1 at channel cell i from the window
+__device__ double indicator_win(const WinQ& Q, int i, int crit) {
+  switch (crit) {
+    case SWE_NH_CRIT_ETA_D: {
+      const double d = Q.D(i);
+      return fabs((Q.H(i) - d) / d);
+    }
+    case SWE_NH_CRIT_ETA_X:
+      return fabs(((Q.H(i + 1) - Q.D(i + 1)) - (Q.H(i - 1) - Q.D(i - 1))) / (2.0 * Q.dx));
+    case SWE_NH_CRIT_U:
+      return fabs(Q.Mo(i) / Q.H(i));
+    case SWE_NH_CRIT_U_X:
+      return fabs((Q.Mo(i + 1) / Q.H(i + 1) - Q.Mo(i - 1) / Q.H(i - 1)) / (2.0 * Q.dx));
+    case SWE_NH_CRIT_W:
+      return fabs(Q.K(i) / Q.H(i));
+    default:  // SWE_NH_CRIT_W_X
+      return fabs((Q.K(i + 1) / Q.H(i + 1) - Q.K(i - 1) / Q.H(i - 1)) / (2.0 * Q.dx));
+  }
+}
+
+// d_x, 4 + d_x^2 and phi (Eq. 5) at channel cell s from the window
+__device__ CellNH cell_win(const WinQ& Q, const K1D& P, const Chan& c, const Motion& M, int s) {
+  const double dl = Q.D(s - 1), d0 = Q.D(s), dr = Q.D(s + 1);
+  const double D = (dr - dl) / (2.0 * Q.dx);
+  const double dxx = (dr - 2.0 * d0 + dl) / (Q.dx * Q.dx);
+  const double ex = ((Q.H(s + 1) - dr) - (Q.H(s - 1) - dl)) / (2.0 * Q.dx);
+  const double hs = Q.H(s);
+  const double u = Q.Mo(s) / hs;
+  const BedRate br = bed_rate(M, body_shape(c, (s + 0.5) * Q.dx - M.X, 0.0));
+  CellNH q;
+  q.D = D;
+  q.al = 4.0 + D * D;
+  q.phi = P.rho * hs / q.al * (P.g * D * ex - br.d_tt - 2.0 * u * br.d_xt - u * u * dxx);
+  return q;
+}
+
+// face f between cells f-1 and f (0 <= f <= n) from the window
+__device__ FaceNH face_win(const WinQ& Q, const K1D& P, double dt, int f, double phil,
+                           double phir) {
+  const double hl = Q.H(f - 1), hr = Q.H(f);
+  const double hf = 0.5 * (hl + hr);
+  const double Df = (Q.D(f) - Q.D(f - 1)) / Q.dx;
+  const double hx = (hr - hl) / Q.dx;
+  const double af = 4.0 + Df * Df;
+  const double s11 = (2.0 * hx - 3.0 * Df) / (2.0 * hf);
+  FaceNH q;
+  q.K = 4.0 * dt * hf / (P.rho * af);
+  q.a = -1.0 / Q.dx + 0.5 * s11;
+  q.b = 1.0 / Q.dx + 0.5 * s11;
+  q.fd = dt / P.rho * (0.5 * (phil + phir)) * Df;
+  q.qp = 0.5 * (Q.Mo(f - 1) + Q.Mo(f)) + q.fd;
+  return q;
+}
+
+// parallel cyclic reduction of the first m rows of the tile system (rows
+// m..RW are identity), three right-hand sides
 template <int T, int NT>
-__device__ void pcr_rows(NhSmem<T, NT>& S, int m) {
-  constexpr int RW = NhSmem<T, NT>::RW;
-  const int t = threadIdx.x;
+__device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
+  constexpr int RW = StepSmem<T, NT>::RW, RPT = RW / NT;
+  auto& Y = S.u.s;
   for (int s = 1; s < m; s <<= 1) {
-    double na[2], nb[2], nc[2], nd[2][3];
+    double na[RPT], nb[RPT], nc[RPT], nd[RPT][3];
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-      const int i = 2 * t + j;
+    for (int j = 0; j < RPT; j++) {
+      const int i = RPT * threadIdx.x + j;
       const int im = i - s, ip = i + s;
-      double bi = S.b[i], ai = 0.0, ci = 0.0;
-      double di[3] = {S.d[0][i], S.d[1][i], S.d[2][i]};
+      double bi = Y.b[i], ai = 0.0, ci = 0.0;
+      double di[3] = {Y.d[0][i], Y.d[1][i], Y.d[2][i]};
       if (im >= 0) {
-        const double k1 = S.a[i] / S.b[im];
-        ai = -S.a[im] * k1;
-        bi -= S.c[im] * k1;
+        const double k1 = Y.a[i] / Y.b[im];
+        ai = -Y.a[im] * k1;
+        bi -= Y.c[im] * k1;
 #pragma unroll
-        for (int r = 0; r < 3; r++) di[r] -= S.d[r][im] * k1;
+        for (int r = 0; r < 3; r++) di[r] -= Y.d[r][im] * k1;
       }
       if (ip < RW) {
-        const double k2 = S.c[i] / S.b[ip];
-        ci = -S.c[ip] * k2;
-        bi -= S.a[ip] * k2;
+        const double k2 = Y.c[i] / Y.b[ip];
+        ci = -Y.c[ip] * k2;
+        bi -= Y.a[ip] * k2;
 #pragma unroll
-        for (int r = 0; r < 3; r++) di[r] -= S.d[r][ip] * k2;
+        for (int r = 0; r < 3; r++) di[r] -= Y.d[r][ip] * k2;
       }
       na[j] = ai;
       nb[j] = bi;
@@ -676,35 +808,140 @@ __device__ void pcr_rows(NhSmem<T, NT>& S, int m) {
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-      const int i = 2 * t + j;
-      S.a[i] = na[j];
-      S.b[i] = nb[j];
-      S.c[i] = nc[j];
+    for (int j = 0; j < RPT; j++) {
+      const int i = RPT * threadIdx.x + j;
+      Y.a[i] = na[j];
+      Y.b[i] = nb[j];
+      Y.c[i] = nc[j];
 #pragma unroll
-      for (int r = 0; r < 3; r++) S.d[r][i] = nd[j][r];
+      for (int r = 0; r < 3; r++) Y.d[r][i] = nd[j][r];
     }
     __syncthreads();
   }
 }
 }  // namespace
 
-// criterion, step defaults, speed of the unmarked final state, assembly of
-// the tile's marked rows and their reduction to the two level-1 rows
+// Whole step of a tile up to the level-1 rows: dt from the speed of Q^n, both
+// Heun stages (Eqs. 8-9), criterion and enlargement (Secs. 5.1-5.2), the new
+// state's defaults (h = h~, hu = hu~, hw = hw~, p = 0 off the marked area),
+// the speed of the unmarked cells' new state, assembly of the marked rows
+// (Eqs. 10-17) and their reduction to the two level-1 rows.
 template <int T, int NT>
-__global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restrict__ ht,
-                                                  const double* __restrict__ mt,
-                                                  const double* __restrict__ kt,
-                                                  uint8_t* __restrict__ mask, double* h, double* hu,
-                                                  double* hw, double* p) {
-  constexpr int RW = NhSmem<T, NT>::RW;
-  __shared__ NhSmem<T, NT> S;
+__global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__ h,
+                                               const double* __restrict__ hu,
+                                               const double* __restrict__ hw,
+                                               double* __restrict__ hn, double* __restrict__ hun,
+                                               double* __restrict__ hwn, uint8_t* __restrict__ mask,
+                                               double* __restrict__ p) {
+  using SM = StepSmem<T, NT>;
+  constexpr int WMAX = SM::WMAX, RW = SM::RW;
+  constexpr int Q = (WMAX - 4 + NT - 1) / NT;  // window cells per thread
+  __shared__ SM S;
+  __shared__ int sflags;
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
-  const int e = P.enlarge;
   const int step = *P.step, par = step & 1;
-  const double dt = P.dt[tl.x], t1 = P.t[tl.x] + dt;
+  const double dt =
+      (P.cfl > 0.0)
+          ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[par * P.nch + tl.x])
+          : P.dt_fixed;
+  if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.dt[tl.x] = dt;
+  const int ee = P.enlarge, HL = 6 + ee, W = T + 2 * HL;
+  const int lo = start - HL;  // window cell w <-> channel cell lo + w
+  const double t0 = P.t[tl.x], t1 = t0 + dt;
+  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t1);
+  const double idx = 1.0 / P.dx;
+  if (threadIdx.x == 0) sflags = 0;
+  int flags = 0;
+
+  // ---- predictor ----
+  for (int w = threadIdx.x; w < W; w += NT) {
+    const int i = lo + w;
+    const int s = reflect(max(-n, min(i, 2 * n - 1)), n);
+    const int64_t gi = c.off + s;
+    const double x = (s + 0.5) * P.dx;
+    const double ds = P.ds[gi];
+    const double dA = ds - body_shape(c, x - M0.X, 0.0).B;
+    S.e[w] = h[gi] - dA;
+    S.m[w] = (s == i ? 1.0 : -1.0) * hu[gi];
+    S.k[w] = hw[gi];
+    S.d0[w] = dA;
+    S.d1[w] = ds - body_shape(c, x - M1.X, 0.0).B;
+  }
+  __syncthreads();
+  double Qn[Q][3], L1[Q][3];
+  step_faces(S, S.d0, P.g, 2, W - 1, max(0, start - 2), min(n, start + T + 2), lo, flags);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int e = 2 + threadIdx.x + NT * q;
+    Qn[q][0] = Qn[q][1] = Qn[q][2] = 0.0;
+    L1[q][0] = L1[q][1] = L1[q][2] = 0.0;
+    if (e < W - 2) {
+      step_cell(S, S.d0, P.g, idx, e, L1[q][0], L1[q][1], L1[q][2]);
+      Qn[q][0] = S.e[e] + S.d0[e];
+      Qn[q][1] = S.m[e];
+      Qn[q][2] = S.k[e];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; q++) {  // Q* on the channel cells
+    const int e = 2 + threadIdx.x + NT * q;
+    const int i = lo + e;
+    if (e < W - 2 && i >= 0 && i < n) {
+      S.e[e] = Qn[q][0] + dt * L1[q][0] - S.d1[e];
+      S.m[e] = Qn[q][1] + dt * L1[q][1];
+      S.k[e] = Qn[q][2] + dt * L1[q][2];
+    }
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < W; w += NT) {  // ghosts of Q*: reflections
+    const int i = lo + w;
+    if (i >= 0 && i < n) continue;
+    const int es = reflect(max(-n, min(i, 2 * n - 1)), n) - lo;
+    double ev = 0.0, mv = 0.0, kv = 0.0;
+    if (es >= 2 && es < W - 2) {
+      ev = S.e[es];
+      mv = -S.m[es];
+      kv = S.k[es];
+    }
+    S.e[w] = ev;
+    S.m[w] = mv;
+    S.k[w] = kv;
+  }
+  __syncthreads();
+  // stage 2 on window cells [4, W - 4): the tile and e + 2 cells beyond
+  step_faces(S, S.d1, P.g, 4, W - 3, start, end, lo, flags);
+  __syncthreads();
+  double Qt[Q][3];
+#pragma unroll
+  for (int q = 0; q < Q; q++) {
+    const int e = 2 + threadIdx.x + NT * q;
+    Qt[q][0] = Qt[q][1] = Qt[q][2] = 0.0;
+    if (e < 4 || e >= W - 4) continue;
+    double a, b, k2;
+    step_cell(S, S.d1, P.g, idx, e, a, b, k2);
+    Qt[q][0] = Qn[q][0] + 0.5 * dt * (L1[q][0] + a);
+    Qt[q][1] = Qn[q][1] + 0.5 * dt * (L1[q][1] + b);
+    Qt[q][2] = Qn[q][2] + 0.5 * dt * (L1[q][2] + k2);
+  }
+  if (flags) atomicOr(&sflags, flags);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; q++) {  // the window now holds h~, hu~, hw~
+    const int e = 2 + threadIdx.x + NT * q;
+    if (e < 4 || e >= W - 4) continue;
+    S.e[e] = Qt[q][0];
+    S.m[e] = Qt[q][1];
+    S.k[e] = Qt[q][2];
+  }
+  if (threadIdx.x == 0 && sflags) atomicOr(P.status, sflags);
+  __syncthreads();
+
+  // ---- criterion, enlargement ----
+  const WinQ QW{S.e, S.m, S.k, S.d1, lo, n, P.dx};
   int mode;
   {
     const bool wcrit = (P.crit == SWE_NH_CRIT_W || P.crit == SWE_NH_CRIT_W_X);
@@ -715,13 +952,11 @@ __global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restric
     else
       mode = 0;
   }
-  const Motion M = body_motion(c, t1);
-  // indicator on cells start-1-e .. end+e, mask on cells start-1 .. end
   if (mode == 0) {
-    for (int w = threadIdx.x; w < len + 2 + 2 * e; w += NT) {
-      const int i = start - 1 - e + w;
+    for (int w = threadIdx.x; w < len + 2 + 2 * ee; w += NT) {
+      const int i = start - 1 - ee + w;
       uint8_t r = 0;
-      if (i >= 0 && i < n) r = indicator1d(P, c, M, ht, mt, kt, i, P.crit) > P.k_nh;
+      if (i >= 0 && i < n) r = indicator_win(QW, i, P.crit) > P.k_nh;
       S.raw[w] = r;
     }
     __syncthreads();
@@ -733,41 +968,40 @@ __global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restric
       if (mode == 1) {
         v = 1;
       } else if (mode == 0) {
-        for (int j = 0; j <= 2 * e; j++) v |= S.raw[k + j];
+        for (int j = 0; j <= 2 * ee; j++) v |= S.raw[k + j];
       }
     }
     S.mk[k] = v;
   }
   __syncthreads();
-  // tile cells: mask, defaults h = h~, hu = hu~, hw = hw~ (p = 0 off the
-  // marked area), final-state speed where no projection follows
+  // ---- new state defaults, speed where no projection follows ----
   double smax = 0.0;
-  int flags = 0;
+  int fl2 = 0;
 #pragma unroll
   for (int q = 0; q < T / NT; q++) {
     const int k = 1 + threadIdx.x + NT * q;
     if (k > len) continue;
-    const int64_t gi = c.off + start + k - 1;
+    const int i = start + k - 1, w = i - lo;
+    const int64_t gi = c.off + i;
     const bool on = S.mk[k] != 0;
-    const double hh = ht[gi], mm = mt[gi], kk = kt[gi];
+    const double hh = S.e[w], mm = S.m[w], kk = S.k[w];
     mask[gi] = on;
-    h[gi] = hh;
-    hu[gi] = mm;
-    hw[gi] = kk;
+    hn[gi] = hh;
+    hun[gi] = mm;
+    hwn[gi] = kk;
     if (!on) {
       p[gi] = 0.0;
-      final_state(P.g, hh, mm, kk, smax, flags);
+      final_state(P.g, hh, mm, kk, smax, fl2);
     }
   }
-  flush_speed<NT>(P, tl.x, par, smax, flags);
+  flush_speed<NT>(P, tl.x, par, smax, fl2);
   int rank[T / NT];
   bool on[T / NT];
-  const int m =
-      tile_ranks<T, NT>([&](int k) { return k <= len && S.mk[k] != 0; }, rank, on);
+  const int m = tile_ranks<T, NT>([&](int k) { return k <= len && S.mk[k] != 0; }, rank, on);
   const int F = 2 * blockIdx.x, L = F + 1;
   if (threadIdx.x == 0) {
     P.tile_cnt[blockIdx.x] = m;
-    if (m) atomicAdd(P.n_act, m);
+    if (m) atomicAdd(P.n_acc, m);
   }
   if (m == 0) {
     if (threadIdx.x == 0) {
@@ -780,39 +1014,33 @@ __global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restric
     }
     return;
   }
-  // cell and face quantities of the elliptic system (Eqs. 10-17) at t^{n+1}
-  Local Lc{&P, &c, ht, mt, kt, M, dt, P.dx};
-  for (int k = threadIdx.x; k < len + 2; k += NT) S.cq[k] = Lc.cell(reflect(start - 1 + k, n));
+  // ---- elliptic rows of the marked cells (Eqs. 10-17 at t^{n+1}) ----
+  for (int k = threadIdx.x; k < len + 2; k += NT)
+    S.u.q.cq[k] = cell_win(QW, P, c, M1, reflect(start - 1 + k, n));
   __syncthreads();
   for (int f = threadIdx.x; f <= len; f += NT)
-    S.fq[f] = Lc.face(start + f, S.cq[f].phi, S.cq[f + 1].phi);
-  for (int j = m + threadIdx.x; j < RW; j += NT) {
-    S.a[j] = 0.0;
-    S.b[j] = 1.0;
-    S.c[j] = 0.0;
-    S.d[0][j] = 0.0;
-  }
+    S.u.q.fq[f] = face_win(QW, P, dt, start + f, S.u.q.cq[f].phi, S.u.q.cq[f + 1].phi);
   __syncthreads();
   const int64_t zs = (int64_t)P.ntiles * T;  // stride of the zw planes
   const int64_t pb = (int64_t)blockIdx.x * T;
+  double ra[T / NT], rb[T / NT], rc[T / NT], rd[T / NT];
 #pragma unroll
   for (int q = 0; q < T / NT; q++) {
     if (!on[q]) continue;
-    const int k = 1 + threadIdx.x + NT * q, j = rank[q];
-    const int i = start + k - 1;
-    const int64_t gi = c.off + i;
-    const FaceNH fl = S.fq[k - 1], fr = S.fq[k];
-    const CellNH c0 = S.cq[k];
-    const double hs = ht[gi];
+    const int k = 1 + threadIdx.x + NT * q;
+    const int i = start + k - 1, w = i - lo;
+    const FaceNH fl = S.u.q.fq[k - 1], fr = S.u.q.fq[k];
+    const CellNH c0 = S.u.q.cq[k];
+    const double hs = S.e[w], ms = S.m[w], ks = S.k[w];
     const double s22 = 3.0 * dt / (P.rho * hs);
-    const BedRate br = bed_rate(M, body_shape(c, (i + 0.5) * P.dx - M.X, 0.0));
-    const double f2 = -2.0 * br.d_t - 2.0 * kt[gi] / hs - c0.D * mt[gi] / (2.0 * hs) -
+    const BedRate br = bed_rate(M1, body_shape(c, (i + 0.5) * P.dx - M1.X, 0.0));
+    const double f2 = -2.0 * br.d_t - 2.0 * ks / hs - c0.D * ms / (2.0 * hs) -
                       dt * c0.al * c0.phi / (2.0 * P.rho * hs);
-    S.a[j] = (i > 0 && S.mk[k - 1]) ? fl.K * fl.a * fl.b : 0.0;
-    S.b[j] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
-    S.c[j] = (i + 1 < n && S.mk[k + 1]) ? fr.K * fr.a * fr.b : 0.0;
-    S.d[0][j] = f2 + fl.b * fl.qp + fr.a * fr.qp;
-    double* z = P.zw + pb + j;
+    ra[q] = (i > 0 && S.mk[k - 1]) ? fl.K * fl.a * fl.b : 0.0;
+    rb[q] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
+    rc[q] = (i + 1 < n && S.mk[k + 1]) ? fr.K * fr.a * fr.b : 0.0;
+    rd[q] = f2 + fl.b * fl.qp + fr.a * fr.qp;
+    double* z = P.zw + pb + rank[q];
     z[ZW_KL * zs] = fl.K;
     z[ZW_AL * zs] = fl.a;
     z[ZW_BL * zs] = fl.b;
@@ -823,17 +1051,38 @@ __global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restric
     z[ZW_FR * zs] = fr.fd;
     z[ZW_D * zs] = c0.D;
     z[ZW_P * zs] = c0.al * c0.phi / 4.0;
+    z[ZW_HT * zs] = hs;
+    z[ZW_MT * zs] = ms;
+    z[ZW_KT * zs] = ks;
+  }
+  __syncthreads();  // cq, fq dead: the tile system takes their place
+  auto& Y = S.u.s;
+  for (int j = threadIdx.x; j < RW; j += NT) {
+    Y.a[j] = 0.0;
+    Y.b[j] = 1.0;
+    Y.c[j] = 0.0;
+    Y.d[0][j] = 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < T / NT; q++) {
+    if (!on[q]) continue;
+    const int j = rank[q];
+    Y.a[j] = ra[q];
+    Y.b[j] = rb[q];
+    Y.c[j] = rc[q];
+    Y.d[0][j] = rd[q];
   }
   __syncthreads();
   if (m == 1) {
     if (threadIdx.x == 0) {
-      const bool asL = S.c[0] != 0.0;  // couples to the next tile's first row
-      P.dg1[F] = asL ? 1.0 : S.b[0];
+      const bool asL = Y.c[0] != 0.0;  // couples to the next tile's first row
+      P.dg1[F] = asL ? 1.0 : Y.b[0];
       P.up1[F] = 0.0;
-      P.rh1[F] = asL ? 0.0 : S.d[0][0];
-      P.dg1[L] = asL ? S.b[0] : 1.0;
-      P.up1[L] = asL ? S.c[0] : 0.0;
-      P.rh1[L] = asL ? S.d[0][0] : 0.0;
+      P.rh1[F] = asL ? 0.0 : Y.d[0][0];
+      P.dg1[L] = asL ? Y.b[0] : 1.0;
+      P.up1[L] = asL ? Y.c[0] : 0.0;
+      P.rh1[L] = asL ? Y.d[0][0] : 0.0;
       P.zw[pb + ZW_Z * zs] = 0.0;
       P.zw[pb + ZW_U * zs] = asL ? 0.0 : 1.0;
       P.zw[pb + ZW_V * zs] = asL ? 1.0 : 0.0;
@@ -841,31 +1090,31 @@ __global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restric
     return;
   }
   // keep the end rows, then pin them: x_first and x_last become parameters
-  const double b0 = S.b[0], c0 = S.c[0], d0 = S.d[0][0];
-  const double aL = S.a[m - 1], bL = S.b[m - 1], cL = S.c[m - 1], dL = S.d[0][m - 1];
+  const double b0 = Y.b[0], c0 = Y.c[0], d0 = Y.d[0][0];
+  const double aL = Y.a[m - 1], bL = Y.b[m - 1], cL = Y.c[m - 1], dL = Y.d[0][m - 1];
   __syncthreads();
   for (int j = threadIdx.x; j < RW; j += NT) {
     const bool first = j == 0, last = j == m - 1;
     if (first || last) {
-      S.a[j] = 0.0;
-      S.c[j] = 0.0;
-      S.b[j] = 1.0;
-      S.d[0][j] = 0.0;
+      Y.a[j] = 0.0;
+      Y.c[j] = 0.0;
+      Y.b[j] = 1.0;
+      Y.d[0][j] = 0.0;
     }
-    S.d[1][j] = first ? 1.0 : 0.0;
-    S.d[2][j] = last ? 1.0 : 0.0;
+    Y.d[1][j] = first ? 1.0 : 0.0;
+    Y.d[2][j] = last ? 1.0 : 0.0;
   }
   __syncthreads();
-  pcr_rows<T, NT>(S, m);
+  pcr_tile<T, NT>(S, m);
   for (int j = threadIdx.x; j < m; j += NT) {
-    const double ib = 1.0 / S.b[j];
-    P.zw[pb + j + ZW_Z * zs] = S.d[0][j] * ib;
-    P.zw[pb + j + ZW_U * zs] = S.d[1][j] * ib;
-    P.zw[pb + j + ZW_V * zs] = S.d[2][j] * ib;
+    const double ib = 1.0 / Y.b[j];
+    P.zw[pb + j + ZW_Z * zs] = Y.d[0][j] * ib;
+    P.zw[pb + j + ZW_U * zs] = Y.d[1][j] * ib;
+    P.zw[pb + j + ZW_V * zs] = Y.d[2][j] * ib;
   }
   if (threadIdx.x == 0) {
-    const double z1 = S.d[0][1] / S.b[1], u1 = S.d[1][1] / S.b[1], v1 = S.d[2][1] / S.b[1];
-    const double zL = S.d[0][m - 2] / S.b[m - 2], vL = S.d[2][m - 2] / S.b[m - 2];
+    const double z1 = Y.d[0][1] / Y.b[1], u1 = Y.d[1][1] / Y.b[1], v1 = Y.d[2][1] / Y.b[1];
+    const double zL = Y.d[0][m - 2] / Y.b[m - 2], vL = Y.d[2][m - 2] / Y.b[m - 2];
     P.dg1[F] = b0 + c0 * u1;
     P.up1[F] = c0 * v1;
     P.rh1[F] = d0 - c0 * z1;
@@ -875,16 +1124,37 @@ __global__ void __launch_bounds__(NT) k_nh1d_tile(K1D P, const double* __restric
   }
 }
 
-// projection of the marked cells from the level-1 solution, speed of their
-// final state; the last block to finish advances t and the step counter
-// (advance = 0: stage timing, the step does not advance)
-template <int T, int NT>
-__global__ void __launch_bounds__(NT) k_nh1d_apply(K1D P, const double* __restrict__ ht,
-                                                   const double* __restrict__ mt,
-                                                   const double* __restrict__ kt,
-                                                   const uint8_t* __restrict__ mask, double* hu,
-                                                   double* hw, double* p, int advance) {
+namespace {
+// t += dt, step + 1, publish the marked-cell count, clear the speed buffer
+// this step read (it collects the speed of the step after next)
+__device__ void finish_step(const K1D& P, int par) {
+  for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) {
+    P.t[ch] += P.dt[ch];
+    P.smax[par * P.nch + ch] = 0ull;
+  }
+  if (threadIdx.x == 0) {
+    *P.step += 1;
+    *P.n_act = *P.n_acc;
+    *P.n_acc = 0;
+  }
+}
+}  // namespace
+
+// Projection of the marked cells (a6) from the level-1 solution -- solved
+// here, redundantly by every tile that needs it, when it has at most L1MAX
+// rows (L1LOCAL), else read from P.x1 -- and the speed of their new state.
+// fin = 1: the last block to finish ends the step (advances t and the step
+// counter, publishes the marked-cell count, clears the speed buffer this
+// step read); fin = 2: k_finish1d does that; fin = 0: stage timing.
+template <int T, int NT, bool L1LOCAL>
+__global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict__ mask,
+                                                double* hun, double* hwn, double* p,
+                                                int fin) {
+  constexpr int L1 = L1LOCAL ? L1MAX : 1, RPT = L1LOCAL ? L1MAX / NT : 1;
   __shared__ double xs[T + 2];
+  __shared__ double la[L1], lb[L1], lc[L1], ld[L1];
+  __shared__ int tpos[(L1 + 1) / 2], tlist[(L1 + 1) / 2];  // tile <-> compact level-1 tile
+  __shared__ int wc[NT / 64];
   __shared__ int last;
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
@@ -895,13 +1165,102 @@ __global__ void __launch_bounds__(NT) k_nh1d_apply(K1D P, const double* __restri
   double smax = 0.0;
   int flags = 0;
   if (m > 0) {
+    // level-1 solution of row j (= 2 tile + 0 first / 1 last)
+    auto x1 = [&](int j) {
+      if (!L1LOCAL) return P.x1[j];
+      const int r = 2 * tpos[j >> 1] + (j & 1);
+      return ld[r] / lb[r];
+    };
+    if (L1LOCAL) {
+      // Level-1 system restricted to the marked tiles (an unmarked tile's two
+      // identity rows are decoupled from everything), in tile order; solved
+      // by parallel cyclic reduction.
+      int base = 0;
+      for (int t0 = 0; t0 < P.ntiles; t0 += NT) {
+        const int t = t0 + threadIdx.x;
+        const bool mt = t < P.ntiles && P.tile_cnt[t] > 0;
+        const unsigned long long bal = __ballot(mt);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) wc[wv] = __popcll(bal);
+        __syncthreads();
+        int wb = 0, tot = 0;
+        for (int w = 0; w < NT / 64; w++) {
+          if (w < wv) wb += wc[w];
+          tot += wc[w];
+        }
+        const int r = base + wb + __popcll(bal & ((1ull << lane) - 1ull));
+        if (t < P.ntiles) tpos[t] = mt ? r : -1;
+        if (mt) tlist[r] = t;
+        base += tot;
+        __syncthreads();
+      }
+      const int n1 = 2 * base;
+      // coupling of compact row j to row j + 1
+      auto up_c = [&](int j) {
+        const int t = tlist[j >> 1];
+        if ((j & 1) == 0) return P.up1[2 * t];
+        return (j + 1 < n1 && tlist[(j >> 1) + 1] == t + 1) ? P.up1[2 * t + 1] : 0.0;
+      };
+      for (int j = threadIdx.x; j < L1; j += NT) {
+        if (j < n1) {
+          const int g = 2 * tlist[j >> 1] + (j & 1);
+          la[j] = j > 0 ? up_c(j - 1) : 0.0;
+          lb[j] = P.dg1[g];
+          lc[j] = up_c(j);
+          ld[j] = P.rh1[g];
+        } else {
+          la[j] = 0.0;
+          lb[j] = 1.0;
+          lc[j] = 0.0;
+          ld[j] = 0.0;
+        }
+      }
+      __syncthreads();
+      for (int s = 1; s < n1; s <<= 1) {
+        double na[RPT], nb[RPT], nc[RPT], nd[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; r++) {
+          const int i = threadIdx.x + NT * r;
+          if (i >= n1) continue;
+          const int im = i - s, ip = i + s;
+          double ai = 0.0, bi = lb[i], ci = 0.0, di = ld[i];
+          if (im >= 0) {
+            const double k1 = la[i] / lb[im];
+            ai = -la[im] * k1;
+            bi -= lc[im] * k1;
+            di -= ld[im] * k1;
+          }
+          if (ip < L1) {
+            const double k2 = lc[i] / lb[ip];
+            ci = -lc[ip] * k2;
+            bi -= la[ip] * k2;
+            di -= ld[ip] * k2;
+          }
+          na[r] = ai;
+          nb[r] = bi;
+          nc[r] = ci;
+          nd[r] = di;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPT; r++) {
+          const int i = threadIdx.x + NT * r;
+          if (i >= n1) continue;
+          la[i] = na[r];
+          lb[i] = nb[r];
+          lc[i] = nc[r];
+          ld[i] = nd[r];
+        }
+        __syncthreads();
+      }
+    }
     int rank[T / NT];
     bool on[T / NT];
     const int64_t m0 = c.off + start - 1;  // mask[m0 + k]: tile-local cell k
     tile_ranks<T, NT>([&](int k) { return k <= len && mask[m0 + k] != 0; }, rank, on);
     const int64_t zs = (int64_t)P.ntiles * T;
     const int64_t pb = (int64_t)blockIdx.x * T;
-    const double xF = P.x1[2 * blockIdx.x], xL = P.x1[2 * blockIdx.x + 1];
+    const double xF = x1(2 * blockIdx.x), xL = x1(2 * blockIdx.x + 1);
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
       const int k = 1 + threadIdx.x + NT * q;
@@ -914,8 +1273,8 @@ __global__ void __launch_bounds__(NT) k_nh1d_apply(K1D P, const double* __restri
       xs[k] = x;
     }
     if (threadIdx.x == 0) {
-      xs[0] = (start > 0 && mask[m0]) ? P.x1[2 * blockIdx.x - 1] : 0.0;
-      xs[len + 1] = (end < n && mask[m0 + len + 1]) ? P.x1[2 * blockIdx.x + 2] : 0.0;
+      xs[0] = (start > 0 && mask[m0]) ? x1(2 * blockIdx.x - 1) : 0.0;
+      xs[len + 1] = (end < n && mask[m0 + len + 1]) ? x1(2 * blockIdx.x + 2) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -929,14 +1288,16 @@ __global__ void __launch_bounds__(NT) k_nh1d_apply(K1D P, const double* __restri
       const double dqr = z[ZW_FR * zs] - z[ZW_KR * zs] * (z[ZW_AR * zs] * pc + z[ZW_BR * zs] * pr);
       const double dm = 0.5 * (dql + dqr);
       const double Pb = 1.5 * pc - P.rho * z[ZW_D * zs] * dm / (4.0 * dt) + z[ZW_P * zs];
-      const double hn = ht[gi], mn = mt[gi] + dm, kn = kt[gi] + dt * Pb / P.rho;
-      hu[gi] = mn;
-      hw[gi] = kn;
+      const double hh = z[ZW_HT * zs];
+      const double mn = z[ZW_MT * zs] + dm, kn = z[ZW_KT * zs] + dt * Pb / P.rho;
+      hun[gi] = mn;
+      hwn[gi] = kn;
       p[gi] = pc;
-      final_state(P.g, hn, mn, kn, smax, flags);
+      final_state(P.g, hh, mn, kn, smax, flags);
     }
   }
   flush_speed<NT>(P, tl.x, par, smax, flags);
+  if (fin != 1) return;
   __syncthreads();
   if (threadIdx.x == 0) {
     const int prev = __hip_atomic_fetch_add(P.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -944,14 +1305,13 @@ __global__ void __launch_bounds__(NT) k_nh1d_apply(K1D P, const double* __restri
   }
   __syncthreads();
   if (last) {
-    if (advance)
-      for (int ch = threadIdx.x; ch < P.nch; ch += NT) P.t[ch] += P.dt[ch];
-    if (threadIdx.x == 0) {
-      if (advance) *P.step += 1;
-      *P.done = 0;
-    }
+    finish_step(P, par);
+    if (threadIdx.x == 0) *P.done = 0;
   }
 }
+
+// end of the step for grids too large for the arrival counter
+__global__ void k_finish1d(K1D P) { finish_step(P, *P.step & 1); }
 
 // prologue of a run of steps: speed of the caller's state into buffer
 // (step & 1) after clearing it
@@ -1083,35 +1443,46 @@ void launch_scatter_packed(const int* act_cell, const int* n_act, int64_t max_ro
 }
 
 template <int T, int NT>
-static void launch_fused_pair(const K1D& P, const double* ht, const double* mt, const double* kt,
-                              uint8_t* mask, double* h, double* hu, double* hw, double* p,
-                              bool tile_pass, int advance, hipStream_t s) {
-  if (tile_pass)
-    hipLaunchKernelGGL((k_nh1d_tile<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, ht, mt, kt, mask,
-                       h, hu, hw, p);
-  else
-    hipLaunchKernelGGL((k_nh1d_apply<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, ht, mt, kt,
-                       (const uint8_t*)mask, hu, hw, p, advance);
+static void launch_step_t(const K1D& P, const double* h, const double* hu, const double* hw,
+                          double* hn, double* hun, double* hwn, uint8_t* mask, double* p,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_step1d<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn, hun, hwn,
+                     mask, p);
 }
-static void launch_fused(const K1D& P, const double* ht, const double* mt, const double* kt,
-                         uint8_t* mask, double* h, double* hu, double* hw, double* p,
-                         bool tile_pass, int advance, hipStream_t s) {
+void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
+                   double* hun, double* hwn, uint8_t* mask, double* p, hipStream_t s) {
   if (P.tile == 128)
-    launch_fused_pair<128, 128>(P, ht, mt, kt, mask, h, hu, hw, p, tile_pass, advance, s);
+    launch_step_t<128, 128>(P, h, hu, hw, hn, hun, hwn, mask, p, s);
   else if (P.tile == 256)
-    launch_fused_pair<256, 256>(P, ht, mt, kt, mask, h, hu, hw, p, tile_pass, advance, s);
+    launch_step_t<256, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, s);
   else
-    launch_fused_pair<512, 256>(P, ht, mt, kt, mask, h, hu, hw, p, tile_pass, advance, s);
+    launch_step_t<512, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, s);
 }
-void launch_nh1d_tile(const K1D& P, const double* ht, const double* mt, const double* kt,
-                      uint8_t* mask, double* h, double* hu, double* hw, double* p, hipStream_t s) {
-  launch_fused(P, ht, mt, kt, mask, h, hu, hw, p, true, 1, s);
+constexpr int FIN_INLINE_MAX = 2048;  // largest grid that ends the step with a counter
+
+template <int T, int NT>
+static void launch_apply_t(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
+                           int fin, hipStream_t s) {
+  if (2 * P.ntiles <= L1MAX)
+    hipLaunchKernelGGL((k_apply1d<T, NT, true>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun, hwn,
+                       p, fin);
+  else
+    hipLaunchKernelGGL((k_apply1d<T, NT, false>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun,
+                       hwn, p, fin);
 }
-void launch_nh1d_apply(const K1D& P, const double* ht, const double* mt, const double* kt,
-                       const uint8_t* mask, double* hu, double* hw, double* p, int advance,
-                       hipStream_t s) {
-  launch_fused(P, ht, mt, kt, const_cast<uint8_t*>(mask), nullptr, hu, hw, p, false, advance, s);
+void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
+                    int advance, hipStream_t s) {
+  const int fin = !advance ? 0 : (P.ntiles <= FIN_INLINE_MAX ? 1 : 2);
+  if (P.tile == 128)
+    launch_apply_t<128, 128>(P, mask, hun, hwn, p, fin, s);
+  else if (P.tile == 256)
+    launch_apply_t<256, 256>(P, mask, hun, hwn, p, fin, s);
+  else
+    launch_apply_t<512, 256>(P, mask, hun, hwn, p, fin, s);
+  if (fin == 2) hipLaunchKernelGGL(k_finish1d, dim3(1), dim3(256), 0, s, P);
 }
+bool level1_local(const K1D& P) { return 2 * P.ntiles <= L1MAX; }
+int fused_max_enlarge() { return EMAXF; }
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_smax_clear, dim3(1), dim3(256), 0, s, P);

@@ -66,8 +66,9 @@ struct swe_nh_ctx {
   int* n1 = nullptr;       // its row count (2 per tile)
   // 2D
   Ctx2D c2{};
-  // graph of one step
+  // graph of one step (fused 1D path: two, alternating the state buffers)
   hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec2 = nullptr;
   const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t steps_taken = 0;
 };
@@ -197,6 +198,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   int* nbuf32 = cv.take<int>(TRI_MAX_LEVELS);
   int* nbuf1 = cv.take<int>(TRI_MAX_LEVELS);
   P.done = cv.take<int>(1);
+  P.n_acc = cv.take<int>(1);
   x->n1 = cv.take<int>(1);
   if (c->dim == 1) {
     P.tile_cnt = cv.take<int>(ntiles);
@@ -209,7 +211,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
     x->mask_ws = cv.take<uint8_t>(N);
     plan_levels(&x->T64, N, cv, nbuf64);
     if (c->precision == 1) plan_levels(&x->T32, N, cv, nbuf32);
-    if (c->precision == 0) {  // tile-fused step
+    if (c->precision == 0 && c->enlarge <= fused_max_enlarge()) {  // fused step
       plan_levels(&x->T1, 2 * (int64_t)ntiles, cv, nbuf1);
       P.zw = cv.take<double>((size_t)ZW_N * ntiles * tile_of(c));
       P.dg1 = x->T1.dg[0];
@@ -270,21 +272,23 @@ void solve1d(swe_nh_ctx* c, hipStream_t s, int with_residual) {
   launch_flag_noconv(c->conv, c->status, s);
 }
 
+// fused FP64 step from (h, hu, hw) into (hn, hun, hwn)
+void enqueue_fused1d(swe_nh_ctx* c, hipStream_t s, const double* h, const double* hu,
+                     const double* hw, double* hn, double* hun, double* hwn, double* p,
+                     uint8_t* mask) {
+  K1D& P = c->k1;
+  uint8_t* M = mask ? mask : c->mask_ws;
+  launch_step1d(P, h, hu, hw, hn, hun, hwn, M, p, s);
+  if (!level1_local(P)) launch_tri_solve(c->T1, c->n1, nullptr, s);
+  launch_apply1d(P, M, hun, hwn, p, 1, s);
+}
+
 void enqueue_step1d(swe_nh_ctx* c, hipStream_t s, double* h, double* hu, double* hw, double* p,
                     uint8_t* mask) {
   K1D& P = c->k1;
   uint8_t* M = mask ? mask : c->mask_ws;
   const int64_t N = c->ncells;
-  if (P.fused) {
-    // predictor; criterion + assembly + tile reduction; level-1 solve;
-    // projection + next speed + advance (the speed of the caller's state is
-    // computed once per call, before the first step)
-    launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 1, s);
-    launch_nh1d_tile(P, c->ht, c->mt, c->kt, M, h, hu, hw, p, s);
-    launch_tri_solve(c->T1, c->n1, nullptr, s);
-    launch_nh1d_apply(P, c->ht, c->mt, c->kt, M, hu, hw, p, 1, s);
-    return;
-  }
+
   launch_speed1d(P, h, hu, hw, s);
   launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 1, s);
   launch_mask1d(P, c->ht, c->mt, c->kt, P.t, P.dt, -1, M, h, hu, hw, p, 1, s);
@@ -325,6 +329,25 @@ int status_code(int bits) {
 int after_launch(swe_nh_ctx* c) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("launch: ") + hipGetErrorString(e));
+  return SWE_NH_OK;
+}
+
+// captures the work enqueued by f on the private stream into an executable graph
+template <typename F>
+int capture_graph(swe_nh_ctx* c, F f, hipGraphExec_t* out) {
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+  f(c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(c, SWE_NH_EHIP,
+                std::string("capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("instantiate: ") + hipGetErrorString(e3));
   return SWE_NH_OK;
 }
 
@@ -400,7 +423,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.ntiles = (int)c->tiles.size();
   P.tile = tile_of(cfg);
   P.nch = c->nch;
-  P.fused = (cfg->dim == 1 && cfg->precision == 0) ? 1 : 0;
+  P.fused = (cfg->dim == 1 && cfg->precision == 0 && cfg->enlarge <= fused_max_enlarge()) ? 1 : 0;
   const int n1 = 2 * P.ntiles;
   std::vector<double> zeros(c->nch, 0.0);
   std::vector<unsigned long long> zu(c->nch, 0ull);
@@ -420,6 +443,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   INIT_COPY(P.smax, zu.data(), sizeof(unsigned long long) * c->nch);
   INIT_COPY(P.smax + c->nch, zu.data(), sizeof(unsigned long long) * c->nch);
   INIT_COPY(P.done, zi, sizeof(int));
+  INIT_COPY(P.n_acc, zi, sizeof(int));
   if (P.fused) {
     INIT_COPY(c->n1, &n1, sizeof(int));
     INIT_COPY(c->T1.n, zi, sizeof(int) * TRI_MAX_LEVELS);
@@ -446,6 +470,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
 void swe_nh_destroy(swe_nh_ctx* c) {
   if (!c) return;
   if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->gexec2) hipGraphExecDestroy(c->gexec2);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
@@ -472,38 +497,58 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
                 uint8_t* mask, int32_t nsteps) {
   if (!c || !h || !hu || !hw || !p || nsteps < 0) return fail(c, SWE_NH_EINVAL, "bad arguments");
   if ((c->cfg.dim == 1) != (hv == nullptr)) return fail(c, SWE_NH_EINVAL, "hv must be NULL iff dim == 1");
+  const bool fused = c->cfg.dim == 1 && c->k1.fused;
   const void* key[6] = {h, hu, hv, hw, p, mask};
   bool same = c->gexec != nullptr;
   for (int i = 0; i < 6 && same; i++) same = (key[i] == c->gkey[i]);
   if (!same) {
-    if (c->gexec) {
-      hipGraphExecDestroy(c->gexec);
-      c->gexec = nullptr;
+    for (hipGraphExec_t* g : {&c->gexec, &c->gexec2})
+      if (*g) {
+        hipGraphExecDestroy(*g);
+        *g = nullptr;
+      }
+    int rc;
+    if (fused) {
+      // even steps: caller arrays -> workspace; odd steps: back
+      rc = capture_graph(c, [&](hipStream_t s) {
+        enqueue_fused1d(c, s, h, hu, hw, c->ht, c->mt, c->kt, p, mask);
+      }, &c->gexec);
+      if (rc == SWE_NH_OK)
+        rc = capture_graph(c, [&](hipStream_t s) {
+          enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask);
+        }, &c->gexec2);
+    } else {
+      rc = capture_graph(c, [&](hipStream_t s) {
+        if (c->cfg.dim == 1)
+          enqueue_step1d(c, s, h, hu, hw, p, mask);
+        else
+          enqueue_step2d(&c->cfg, &c->c2, s, h, hu, hv, hw, p, mask);
+      }, &c->gexec);
     }
-    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
-    if (c->cfg.dim == 1)
-      enqueue_step1d(c, c->cap, h, hu, hw, p, mask);
-    else
-      enqueue_step2d(&c->cfg, &c->c2, c->cap, h, hu, hv, hw, p, mask);
-    hipGraph_t g = nullptr;
-    hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-      if (g) hipGraphDestroy(g);
-      return fail(c, SWE_NH_EHIP, std::string("capture: ") +
-                                      hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    if (rc != SWE_NH_OK) {
+      for (hipGraphExec_t* g : {&c->gexec, &c->gexec2})
+        if (*g) {
+          hipGraphExecDestroy(*g);
+          *g = nullptr;
+        }
+      return rc;
     }
-    hipError_t e3 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e3 != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("instantiate: ") + hipGetErrorString(e3));
     for (int i = 0; i < 6; i++) c->gkey[i] = key[i];
   }
-  if (c->k1.fused && nsteps > 0) {
+  if (fused && nsteps > 0) {
     launch_speed_prologue(c->k1, h, hu, hw, c->stream);
     int rc = after_launch(c);
     if (rc) return rc;
   }
-  for (int i = 0; i < nsteps; i++) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  for (int i = 0; i < nsteps; i++)
+    HIPCHK(c, hipGraphLaunch((fused && (i & 1)) ? c->gexec2 : c->gexec, c->stream));
+  if (fused && (nsteps & 1)) {  // the last step wrote the workspace copy
+    launch_copy(c->ht, h, c->ncells, c->stream);
+    launch_copy(c->mt, hu, c->ncells, c->stream);
+    launch_copy(c->kt, hw, c->ncells, c->stream);
+    int rc = after_launch(c);
+    if (rc) return rc;
+  }
   c->steps_taken += nsteps;
   return SWE_NH_OK;
 }
@@ -677,10 +722,11 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* c, const float* params, const double* 
   c->c2.net = params;
   for (int k = 0; k < 4; k++) c->c2.fscale[k] = scales_host[k];
   c->c2.p_scale = p_scale;
-  if (c->gexec) {  // the captured step must pick up the network
-    hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-  }
+  for (hipGraphExec_t* g : {&c->gexec, &c->gexec2})  // the captured step must pick up the network
+    if (*g) {
+      hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
   return SWE_NH_OK;
 }
 
@@ -699,14 +745,16 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
       K1D& P = c->k1;
       uint8_t* M = c->mask_ws;
       if (P.fused) {
-        // the fused kernels write into workspace scratch (level-0 arrays of
-        // the packed solver, unused by this path), never the caller's state
+        // stage 0: the fused step kernel, 1: level-1 solve, 2: projection,
+        // 3: the stand-alone predictor.  Outputs go to workspace scratch
+        // (level-0 arrays of the packed solver, unused by this path), never
+        // the caller's state; nothing advances.
         double *s0 = c->T64.dg[0], *s1 = c->T64.up[0], *s2 = c->T64.rh[0], *s3 = c->T64.x[0];
         switch (stage) {
-          case 0: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s); break;
-          case 1: launch_nh1d_tile(P, c->ht, c->mt, c->kt, M, s0, s1, s2, s3, s); break;
-          case 2: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
-          default: launch_nh1d_apply(P, c->ht, c->mt, c->kt, M, s0, s1, s3, 0, s);
+          case 0: launch_step1d(P, h, hu, hw, s0, s1, s2, M, s3, s); break;
+          case 1: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
+          case 2: launch_apply1d(P, M, s1, s2, s3, 0, s); break;
+          default: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s);
         }
         continue;
       }

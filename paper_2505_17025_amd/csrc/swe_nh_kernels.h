@@ -36,6 +36,7 @@ struct K1D {
   int fused;
   int nch;
   int* done;               // blocks of the projection kernel finished this step
+  int* n_acc;              // marked cells counted during the step (published at its end)
   double* zw;              // [ZW_N][ntiles * tile] per marked row, tile-padded
   double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
   const double* x1;        // level-1 solution
@@ -43,7 +44,14 @@ struct K1D {
 
 // per marked row of the tile-fused step: solution basis of the tile's
 // interior system (x = z + u x_first + v x_last) and the projection data
-enum { ZW_Z, ZW_U, ZW_V, ZW_KL, ZW_AL, ZW_BL, ZW_FL, ZW_KR, ZW_AR, ZW_BR, ZW_FR, ZW_D, ZW_P, ZW_N };
+enum {
+  ZW_Z, ZW_U, ZW_V,                  // x = z + u x_first + v x_last
+  ZW_KL, ZW_AL, ZW_BL, ZW_FL,        // left face: K, a, b, (dt / rho) phi d_x
+  ZW_KR, ZW_AR, ZW_BR, ZW_FR,        // right face
+  ZW_D, ZW_P,                        // cell: d_x, (4 + d_x^2) phi / 4
+  ZW_HT, ZW_MT, ZW_KT,               // h~, hu~, hw~
+  ZW_N
+};
 
 // ---- 1D stencil / mask / projection ----
 void launch_speed1d(const K1D& P, const double* h, const double* hu, const double* hw,
@@ -65,13 +73,15 @@ void launch_correct1d(const K1D& P, int64_t max_rows, const double* ht, const do
                       const double* dt_in, const double* x, double* hu, double* hw, double* p,
                       hipStream_t s);
 void launch_advance(const K1D& P, int nch, hipStream_t s);
-// tile-fused step: criterion + assembly + tile Schur reduction, and the
+// fused FP64 step: predictor + criterion + assembly + tile reduction from the
+// state (h, hu, hw) into a second state buffer (hn, hun, hwn), and the
 // projection from the level-1 solution (plus next-step speed and advance)
-void launch_nh1d_tile(const K1D& P, const double* ht, const double* mt, const double* kt,
-                      uint8_t* mask, double* h, double* hu, double* hw, double* p, hipStream_t s);
-void launch_nh1d_apply(const K1D& P, const double* ht, const double* mt, const double* kt,
-                       const uint8_t* mask, double* hu, double* hw, double* p, int advance,
-                       hipStream_t s);
+void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
+                   double* hun, double* hwn, uint8_t* mask, double* p, hipStream_t s);
+void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
+                    int advance, hipStream_t s);
+bool level1_local(const K1D& P);  // the projection kernel solves the level-1 system itself
+int fused_max_enlarge();
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
                            hipStream_t s);
 void launch_fill(double* a, int64_t n, double v, hipStream_t s);

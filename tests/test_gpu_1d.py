@@ -288,3 +288,58 @@ def test_refinement_reports_noconvergence(B):
     _, st, *_ = run_gpu(B, case, 3, crit=S.CRIT_GLOBAL, cfl=0.5, precision=1, tol=1e-30,
                         max_iter=2)
     assert st["status"] == B.ENOCONV and st["iters"] == 2
+
+
+# ------------------------------------------------- fused FP64 step paths ----
+
+@pytest.mark.parametrize("tile", [128, 256, 512])
+@pytest.mark.parametrize("nsteps", [15, 16])
+def test_fused_step_tiles(B, tile, nsteps):
+    """every tile size of the fused step on ragged channels (channel ends
+    inside and at tile ends, 4-cell channels); odd step counts end in the
+    workspace copy of the state"""
+    ens = ens_small(LENGTHS + [tile, tile + 1, 2 * tile - 1], seed=8)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=1, cfl=0.45, tile1d=tile)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, nsteps, **kw)
+    assert st["status"] == 0
+    o = ens.offsets
+    total = 0
+    for j, c in enumerate(ens.channels):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.45).step(nsteps)
+        sl = slice(o[j], o[j + 1])
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), j
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= 1e-10, j
+        if ref.last_active:
+            assert rel(p[sl], ref.p) <= 1e-10, j
+        total += ref.last_active
+    assert st["n_active"] == total > 0
+
+
+@pytest.mark.parametrize("n", [70000, 300000])
+def test_fused_step_large_grids(B, n):
+    """level-1 system beyond the projection kernel's own solve (> 256 tiles)
+    and the step end by a separate kernel (> 2048 tiles)"""
+    case = S.random_case_1d(n, seed=31, dx=0.05)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=3e-3, enlarge=2, cfl=0.45, tile1d=128)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 5, **kw)
+    assert st["status"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(5)
+    assert st["n_active"] == ref.last_active > 0
+    assert abs(st["t"] - ref.time) <= 1e-14 * ref.time
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+
+
+def test_wide_enlargement_uses_the_unfused_step(B):
+    """an enlargement wider than the fused window (e > 8) runs the unfused
+    FP64 kernels; same results as the oracle"""
+    case = S.random_case_1d(3000, seed=23)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=5e-3, enlarge=12, cfl=0.45)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 12, **kw)
+    assert st["status"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(12)
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
