@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="slide1d",
-                    choices=["slide1d", "ensemble1d", "shelf2d", "learned2d"])
+                    choices=["slide1d", "ensemble1d", "shelf2d", "learned2d", "copycal"])
+    ap.add_argument("--tile1d", type=int, default=0,
+                    help="1D tile (128, 256 or 512); 0: pick with the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     return ap.parse_args()
@@ -162,7 +164,8 @@ def main():
         warmup = args.warmup if args.warmup is not None else 200
         case = S.slide_case(n=32768, dx=0.005)
         kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=0)
-        tile, tune_us = tune_tile(B, torch, case, kw, 400, 100)
+        tile, tune_us = (args.tile1d, None) if args.tile1d else tune_tile(B, torch, case, kw, 400,
+                                                                           100)
         kw["tile1d"] = tile
         log(f"slide1d: {case.n} cells, {warmup} warmup + {steps} timed steps")
         res = run_1d(B, torch, case, kw, steps, warmup)
@@ -206,7 +209,8 @@ def main():
         kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1, tol=1e-12,
                   max_iter=6)
         log(f"ensemble1d: 512 channels, {int(ens.offsets[-1])} cells")
-        tile, tune_us = tune_tile(B, torch, ens, dict(kw, precision=0), 30, 5)
+        tile, tune_us = (args.tile1d, None) if args.tile1d else tune_tile(
+            B, torch, ens, dict(kw, precision=0), 30, 5)
         kw["tile1d"] = tile
         res = run_1d(B, torch, ens, kw, steps, warmup, reps_stage=50)
         log("adaptive fp32+refine:", json.dumps(res))
@@ -235,6 +239,22 @@ def main():
                           "global_cell_steps_per_s": g["cell_steps_per_s"],
                           "n_active_last": res["n_active_last"]}}
         print(json.dumps(line), flush=True)
+    elif args.workload == "copycal":
+        # plain device copy of known size: the HBM counters of a profiled run
+        # of it give the scale of FETCH_SIZE / WRITE_SIZE
+        n = 1 << 25  # 32 Mi FP64 = 256 MiB each way
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        reps = args.steps or 10
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"workload": "copycal", "bytes_read_per_copy": 8 * n,
+                          "bytes_written_per_copy": 8 * n, "copies": reps,
+                          "GBps": 2 * 8 * n * reps / el / 1e9}), flush=True)
     elif args.workload == "learned2d":
         steps = args.steps or 20
         warmup = args.warmup if args.warmup is not None else 30

@@ -33,6 +33,8 @@ struct Carve {
 
 }  // namespace
 
+constexpr int GSTEPS = 8;  // steps per graph launch on the fused 1D path (even)
+
 struct swe_nh_ctx {
   swe_nh_config cfg{};
   std::vector<int64_t> offsets;
@@ -69,6 +71,7 @@ struct swe_nh_ctx {
   // graph of one step (fused 1D path: two, alternating the state buffers)
   hipGraphExec_t gexec = nullptr;
   hipGraphExec_t gexec2 = nullptr;
+  hipGraphExec_t gexecN = nullptr;  // fused 1D path: GSTEPS steps in one graph
   const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t steps_taken = 0;
 };
@@ -471,6 +474,7 @@ void swe_nh_destroy(swe_nh_ctx* c) {
   if (!c) return;
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->gexec2) hipGraphExecDestroy(c->gexec2);
+  if (c->gexecN) hipGraphExecDestroy(c->gexecN);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
@@ -502,7 +506,7 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
   bool same = c->gexec != nullptr;
   for (int i = 0; i < 6 && same; i++) same = (key[i] == c->gkey[i]);
   if (!same) {
-    for (hipGraphExec_t* g : {&c->gexec, &c->gexec2})
+    for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})
       if (*g) {
         hipGraphExecDestroy(*g);
         *g = nullptr;
@@ -517,6 +521,15 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
         rc = capture_graph(c, [&](hipStream_t s) {
           enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask);
         }, &c->gexec2);
+      // GSTEPS (even) steps per launch: the host's per-launch cost is paid
+      // once for all of them; starts and ends in the caller's arrays
+      if (rc == SWE_NH_OK)
+        rc = capture_graph(c, [&](hipStream_t s) {
+          for (int k = 0; k < GSTEPS; k += 2) {
+            enqueue_fused1d(c, s, h, hu, hw, c->ht, c->mt, c->kt, p, mask);
+            enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask);
+          }
+        }, &c->gexecN);
     } else {
       rc = capture_graph(c, [&](hipStream_t s) {
         if (c->cfg.dim == 1)
@@ -526,7 +539,7 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
       }, &c->gexec);
     }
     if (rc != SWE_NH_OK) {
-      for (hipGraphExec_t* g : {&c->gexec, &c->gexec2})
+      for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})
         if (*g) {
           hipGraphExecDestroy(*g);
           *g = nullptr;
@@ -540,7 +553,10 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
     int rc = after_launch(c);
     if (rc) return rc;
   }
-  for (int i = 0; i < nsteps; i++)
+  int i = 0;
+  if (fused)
+    for (; i + GSTEPS <= nsteps; i += GSTEPS) HIPCHK(c, hipGraphLaunch(c->gexecN, c->stream));
+  for (; i < nsteps; i++)
     HIPCHK(c, hipGraphLaunch((fused && (i & 1)) ? c->gexec2 : c->gexec, c->stream));
   if (fused && (nsteps & 1)) {  // the last step wrote the workspace copy
     launch_copy(c->ht, h, c->ncells, c->stream);
@@ -722,7 +738,7 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* c, const float* params, const double* 
   c->c2.net = params;
   for (int k = 0; k < 4; k++) c->c2.fscale[k] = scales_host[k];
   c->c2.p_scale = p_scale;
-  for (hipGraphExec_t* g : {&c->gexec, &c->gexec2})  // the captured step must pick up the network
+  for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})  // the step must pick up the network
     if (*g) {
       hipGraphExecDestroy(*g);
       *g = nullptr;
