@@ -29,9 +29,10 @@ struct Ctx2D {
   float *dg32 = nullptr, *ce32 = nullptr, *cn32 = nullptr;
   uint8_t* nb = nullptr;
   // inner Krylov vectors, FP32 (precision 1) or FP64 (precision 0):
-  // r[2], w[2], s[2] (double-buffered by iteration parity), p, e
-  float* v32[8] = {};
-  double* v64[8] = {};
+  // r, u = M^-1 r, w = A u, p, s, e
+  float* v32[6] = {};
+  double* v64[6] = {};
+  unsigned* tflag = nullptr;  // per tile: neighbour-sync stamp
   double* part = nullptr;    // [2][4][PCG_GMAX] block partial sums
   unsigned long long* bar = nullptr;  // grid barrier arrival counter
   int* iters = nullptr;

@@ -10,11 +10,12 @@
 //   k_mask2d       criterion + (2e+1)^2 box enlargement, tile counts
 //   k_tiles2d      list of tiles holding marked cells
 //   k_assemble2d   5-point operator of the elliptic system (FP64 + FP32 copy)
-//   k_pcg2d<R>     persistent Jacobi-preconditioned CG (Chronopoulos-Gear
-//                  form) in precision R with
+//   k_pcg2d<R>     persistent CG (Chronopoulos-Gear form) preconditioned by
+//                  tile-block symmetric red-black SOR, in precision R with
 //                  FP64 residuals and FP64 refinement of the solution,
-//                  deterministic fixed-order dot products, one grid
-//                  barrier (arrival counter, bounded waits) per iteration
+//                  deterministic fixed-order dot products, per iteration
+//                  one neighbour-tile sync and one grid barrier (arrival
+//                  counter), all waits bounded
 //   k_correct2d    projection of hu, hv and hw on the marked cells
 #include "swe_nh_2d.h"
 #include "swe_nh_cnn.h"
@@ -703,14 +704,9 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
 // persistent PCG with FP64 refinement
 // ---------------------------------------------------------------------------
 // The inner solve is CG in the Chronopoulos-Gear form (one global reduction
-// per iteration: (r,u), (w,u) and (r,r) together, with w = A u).  Each
-// iteration is one pass over the block's cells followed by one grid barrier:
-// the SpMV w' = A u' needs u' = M^-1 r' at the four neighbours, and a
-// neighbour's u' is recomputed from that neighbour's r, w and s of the
-// previous iteration (double-buffered by iteration parity, so that no block
-// overwrites a value another block may still read).  The recomputation uses
-// the same fused operations as the owner's own update, so both give the same
-// bits.
+// per iteration: (r,u), (w,u) and (r,r) together, with w = A u) with a
+// tile-block preconditioner (symmetric red-black SOR on each tile's own block
+// of A); see k_pcg2d.
 //
 // Bounded waits: a wait longer than WAIT_TICKS aborts the solve (status bit)
 // so that the kernel always ends; wall_clock64 ticks at 100 MHz.
@@ -811,14 +807,16 @@ __device__ __forceinline__ double* part_buf(double* part, unsigned k) {
 
 template <typename R>
 struct PcgArgs {
-  int nx, ny, tiles_x;
+  int nx, ny, tiles_x, tiles_y;
   const int* tile_list;
   const int* n_list;
+  const int* tile_cnt;  // marked cells per tile (0: the tile holds no unknowns)
   const uint8_t* nb;
   const double *dg, *ce, *cn, *b;
   double* x;
   const R *dgR, *ceR, *cnR;
-  R *r[2], *w[2], *s[2], *p, *e;
+  R *r, *u, *w, *p, *s, *e;
+  unsigned* tflag;  // per tile: last neighbour-sync stamp passed
   double* part;
   Bar bar;
   int* iters;
@@ -874,33 +872,153 @@ __device__ __forceinline__ void for_cells(int nx, int ny, int tiles_x, const int
   }
 }
 
-// u' = M^-1 (r - alpha (w + beta s_old)) at cell j from the previous
-// iteration's r, w (buffer cur) and s (buffer cur ^ 1)
-template <typename R>
-__device__ __forceinline__ R u_next(const PcgArgs<R>& A, int64_t j, int cur, bool first, R alpha,
-                                    R beta) {
-  const R wj = A.w[cur][j];
-  const R sj = first ? wj : fma(beta, A.s[cur ^ 1][j], wj);
-  return fma(-alpha, sj, A.r[cur][j]) / A.dgR[j];
-}
+// Preconditioner: per active tile, symmetric red-black SOR on the tile's own
+// block of A (couplings that leave the tile dropped), from zero: half-sweeps
+// red, black, ..., red (GS_HALF of them, a palindrome, so the preconditioner
+// is symmetric), over-relaxation GS_OMEGA.  Thread t owns the tile cells 2t
+// and 2t + 1 (row-major), one of each colour.
+constexpr int GS_HALF = 7;
+constexpr double GS_OMEGA = 1.5;
 
 template <typename R>
+struct TileCells {
+  int64_t o[2];
+  uint8_t nb[2];  // neighbour flags restricted to the tile (NB_SELF: a cell of the system)
+  int li[2], lj[2];
+};
+
+template <typename R>
+__device__ __forceinline__ TileCells<R> tile_cells(const PcgArgs<R>& A, int tile) {
+  TileCells<R> C;
+  const int i0 = (tile % A.tiles_x) * TX2, j0 = (tile / A.tiles_x) * TY2;
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const int cc = 2 * threadIdx.x + q;
+    const int li = cc % TX2, lj = cc / TX2;
+    const int i = i0 + li, j = j0 + lj;
+    C.li[q] = li;
+    C.lj[q] = lj;
+    C.o[q] = (int64_t)min(j, A.ny - 1) * A.nx + min(i, A.nx - 1);
+    uint8_t f = 0;
+    if (i < A.nx && j < A.ny) {
+      f = A.nb[C.o[q]];
+      if (li == TX2 - 1) f &= ~NB_E;
+      if (li == 0) f &= ~NB_W;
+      if (lj == TY2 - 1) f &= ~NB_N;
+      if (lj == 0) f &= ~NB_S;
+    }
+    C.nb[q] = f;
+  }
+  return C;
+}
+
+// u = M^-1 r on one tile; rc[q]: r of the thread's cells (0 off the system);
+// z: LDS [TY2][TX2]; result in z
+template <typename R>
+__device__ void tile_precond(const PcgArgs<R>& A, const TileCells<R>& C, const R (&rc)[2],
+                             R (*z)[TX2]) {
+  R dg[2], cE[2], cW[2], cN[2], cS[2];
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const int64_t o = C.o[q];
+    const uint8_t f = C.nb[q];
+    dg[q] = (f & NB_SELF) ? A.dgR[o] : R(1);
+    cE[q] = (f & NB_E) ? A.ceR[o] : R(0);
+    cW[q] = (f & NB_W) ? A.ceR[o - 1] : R(0);
+    cN[q] = (f & NB_N) ? A.cnR[o] : R(0);
+    cS[q] = (f & NB_S) ? A.cnR[o - A.nx] : R(0);
+    z[C.lj[q]][C.li[q]] = R(0);
+  }
+  __syncthreads();
+  const R om = (R)GS_OMEGA;
+  for (int hs = 0; hs < GS_HALF; hs++) {
+    const int colour = hs & 1;  // 0: red ((i + j) even) first and last
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int li = C.li[q], lj = C.lj[q];
+      if (((li + lj) & 1) != colour || !(C.nb[q] & NB_SELF)) continue;
+      R a = rc[q];
+      if (C.nb[q] & NB_E) a -= cE[q] * z[lj][li + 1];
+      if (C.nb[q] & NB_W) a -= cW[q] * z[lj][li - 1];
+      if (C.nb[q] & NB_N) a -= cN[q] * z[lj + 1][li];
+      if (C.nb[q] & NB_S) a -= cS[q] * z[lj - 1][li];
+      z[lj][li] = (R(1) - om) * z[lj][li] + om * a / dg[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Neighbour sync: every block stamps its tiles, then waits until the four
+// face neighbours of each of its tiles that hold unknowns carry the stamp.
+template <typename R>
+__device__ bool neighbour_sync(const PcgArgs<R>& A, const Share& S, unsigned stamp) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (int t = S.t0; t < S.t1; t++)
+      __hip_atomic_store(&A.tflag[A.tile_list[t]], stamp, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 4 * (S.t1 - S.t0); q += NT2) {
+    const int tile = A.tile_list[S.t0 + (q >> 2)];
+    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+    int nx_ = tx, ny_ = ty;
+    switch (q & 3) {
+      case 0: nx_ = tx + 1; break;
+      case 1: nx_ = tx - 1; break;
+      case 2: ny_ = ty + 1; break;
+      default: ny_ = ty - 1;
+    }
+    if (nx_ < 0 || nx_ >= A.tiles_x || ny_ < 0 || ny_ >= A.tiles_y) continue;
+    const int nt = ny_ * A.tiles_x + nx_;
+    if (A.tile_cnt[nt] == 0) continue;
+    const unsigned long long t0 = wall_clock64();
+    unsigned polls = 0;
+    while (__hip_atomic_load(&A.tflag[nt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < stamp) {
+      if ((++polls & 255u) == 0u) {
+        if (aborted(A.bar) || wall_clock64() - t0 > WAIT_TICKS) {
+          atomicOr(A.bar.status, ST_ABORT);
+          ok = 0;
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return ok != 0;
+}
+
+// Persistent preconditioned CG, Chronopoulos-Gear form (u = M^-1 r, w = A u;
+// one grid reduction of (r,u), (w,u), (r,r) per iteration).  Each iteration:
+// phase 1 (recurrences of p, s, e, r on the block's cells, then u = M^-1 r on
+// its tiles), a neighbour-tile sync (w needs the neighbours' u), phase 2
+// (w = A u), one grid barrier.  The inner solve runs in precision R; the
+// outer loop refines the FP64 solution with FP64 residuals.
+template <typename R>
 __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
+  __shared__ R zt[TY2][TX2];
   const int nlist = *A.n_list;
   const int G = max(1, min((int)gridDim.x, nlist));
   if ((int)blockIdx.x >= G) return;
   const Share S = share_of(G, nlist);
   const int nx = A.nx;
-  unsigned k = 0;  // barriers passed
+  unsigned k = 0;      // grid barriers passed
+  unsigned stamp = 0;  // neighbour syncs passed
   double bb = 0.0, rr = 0.0;
   int total = 0, sweep = 0;
   for (;;) {
-    // FP64 residual of the current solution -> r[0] in precision R
+    // FP64 residual of the current solution -> r in precision R
     {
       double v[2] = {0.0, 0.0};
       for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb, [&](int64_t o, uint8_t nb) {
         const double rv = A.b[o] - apply5<double, double>(A.dg, A.ce, A.cn, A.x, nb, o, nx);
-        A.r[0][o] = (R)rv;
+        A.r[o] = (R)rv;
         v[0] += rv * rv;
         if (sweep == 0) v[1] += A.b[o] * A.b[o];
       });
@@ -928,69 +1046,69 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
     // the outer target; FP64 goes straight to the outer target.
     const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
                                             : 0.5 * A.tol * sqrt(bb);
-    // u0 = M^-1 r0, w0 = A u0, e = 0; gamma = (r0, u0), delta = (w0, u0)
-    double gam, del;
-    {
-      double v[2] = {0.0, 0.0};
-      for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb, [&](int64_t o, uint8_t nb) {
-        auto u0 = [&](int64_t j) { return A.r[0][j] / A.dgR[j]; };
-        const R uc = u0(o);
-        R a = A.dgR[o] * uc;
-        if (nb & NB_E) a += A.ceR[o] * u0(o + 1);
-        if (nb & NB_W) a += A.ceR[o - 1] * u0(o - 1);
-        if (nb & NB_N) a += A.cnR[o] * u0(o + nx);
-        if (nb & NB_S) a += A.cnR[o - nx] * u0(o - nx);
-        A.w[0][o] = a;
-        A.e[o] = R(0);
-        v[0] += (double)A.r[0][o] * (double)uc;
-        v[1] += (double)a * (double)uc;
-      });
-      block_partials<2>(v, part_buf(A.part, k + 1), S.vb, G);
-      if (!grid_sync(A.bar, ++k, G)) return;
-      double tt[2];
-      grid_totals<2>(part_buf(A.part, k), G, tt);
-      gam = tt[0];
-      del = tt[1];
-    }
-    double alpha = del != 0.0 ? gam / del : 0.0, beta = 0.0;
+    double gam = 0.0, alpha = 0.0, beta = 0.0;
     for (int it = 0;; it++) {
-      const int cur = it & 1;
-      const bool first = it == 0;
       const R al = (R)alpha, bt = (R)beta;
-      double v[3] = {0.0, 0.0, 0.0};
+      double v[3] = {0.0, 0.0, 0.0};  // (r,u), (r,r), (w,u)
+      // phase 1
+      for (int t = S.t0; t < S.t1; t++) {
+        const TileCells<R> C = tile_cells(A, A.tile_list[t]);
+        R rc[2];
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+          rc[q] = R(0);
+          if (!(C.nb[q] & NB_SELF)) continue;
+          const int64_t o = C.o[q];
+          if (it == 0) {
+            A.e[o] = R(0);
+            rc[q] = A.r[o];
+          } else {
+            const R pv = it == 1 ? A.u[o] : fma(bt, A.p[o], A.u[o]);
+            const R sv = it == 1 ? A.w[o] : fma(bt, A.s[o], A.w[o]);
+            A.p[o] = pv;
+            A.s[o] = sv;
+            A.e[o] = fma(al, pv, A.e[o]);
+            rc[q] = fma(-al, sv, A.r[o]);
+            A.r[o] = rc[q];
+          }
+        }
+        tile_precond(A, C, rc, zt);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+          if (!(C.nb[q] & NB_SELF)) continue;
+          const R uv = zt[C.lj[q]][C.li[q]];
+          A.u[C.o[q]] = uv;
+          v[0] += (double)rc[q] * (double)uv;
+          v[1] += (double)rc[q] * (double)rc[q];
+        }
+        __syncthreads();  // zt is reused by the next tile
+      }
+      if (!neighbour_sync(A, S, ++stamp)) return;
+      // phase 2: w = A u
       for_cells(nx, A.ny, A.tiles_x, A.tile_list, S, A.nb, [&](int64_t o, uint8_t nb) {
-        const R ri = A.r[cur][o], wi = A.w[cur][o], D = A.dgR[o];
-        const R ui = ri / D;
-        const R pv = first ? ui : fma(bt, A.p[o], ui);
-        const R sv = first ? wi : fma(bt, A.s[cur ^ 1][o], wi);
-        A.p[o] = pv;
-        A.s[cur][o] = sv;
-        A.e[o] = fma(al, pv, A.e[o]);
-        const R r1 = fma(-al, sv, ri);
-        const R u1 = r1 / D;
-        R a = D * u1;
-        if (nb & NB_E) a += A.ceR[o] * u_next(A, o + 1, cur, first, al, bt);
-        if (nb & NB_W) a += A.ceR[o - 1] * u_next(A, o - 1, cur, first, al, bt);
-        if (nb & NB_N) a += A.cnR[o] * u_next(A, o + nx, cur, first, al, bt);
-        if (nb & NB_S) a += A.cnR[o - nx] * u_next(A, o - nx, cur, first, al, bt);
-        A.r[cur ^ 1][o] = r1;
-        A.w[cur ^ 1][o] = a;
-        v[0] += (double)r1 * (double)u1;
-        v[1] += (double)a * (double)u1;
-        v[2] += (double)r1 * (double)r1;
+        const R a = apply5<R, R>(A.dgR, A.ceR, A.cnR, A.u, nb, o, nx);
+        A.w[o] = a;
+        v[2] += (double)a * (double)A.u[o];
       });
       block_partials<3>(v, part_buf(A.part, k + 1), S.vb, G);
       if (!grid_sync(A.bar, ++k, G)) return;
       double tt[3];
       grid_totals<3>(part_buf(A.part, k), G, tt);
-      total++;
-      const double gn = tt[0], dn = tt[1], rn = tt[2];
-      if (sqrt(rn) <= tol_abs || total >= A.max_iter || !(gn == gn) || gam == 0.0) break;
-      const double bn = gn / gam;
-      const double den = dn - bn * gn / alpha;
-      if (!(den != 0.0)) break;
-      beta = bn;
-      alpha = gn / den;
+      const double gn = tt[0], rn = tt[1], dn = tt[2];
+      if (it > 0) {
+        total++;
+        if (sqrt(rn) <= tol_abs || total >= A.max_iter || !(gn == gn)) break;
+      }
+      if (it == 0) {
+        alpha = dn != 0.0 ? gn / dn : 0.0;
+        beta = 0.0;
+      } else {
+        const double bn = gam != 0.0 ? gn / gam : 0.0;
+        const double den = dn - bn * gn / alpha;
+        if (!(den != 0.0)) break;
+        beta = bn;
+        alpha = gn / den;
+      }
       gam = gn;
     }
     // x += e (FP64)
@@ -1002,8 +1120,10 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
 }
 
-__global__ void k_bar_reset(unsigned long long* count) {
-  if (threadIdx.x == 0) *count = 0ull;
+__global__ void k_bar_reset(unsigned long long* count, unsigned* tflag, int ntiles) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0ull;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
+    tflag[t] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,8 +1208,11 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.nx = x->nx;
   A.ny = x->ny;
   A.tiles_x = x->tiles_x;
+  A.tiles_y = x->tiles_y;
   A.tile_list = x->tile_list;
   A.n_list = x->n_tiles_act;
+  A.tile_cnt = x->tile_cnt;
+  A.tflag = x->tflag;
   A.nb = x->nb;
   A.dg = x->dg;
   A.ce = x->ce;
@@ -1108,14 +1231,12 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
 
 template <typename R>
 void set_vectors(PcgArgs<R>& A, R* const* v) {
-  A.r[0] = v[0];
-  A.r[1] = v[1];
-  A.w[0] = v[2];
-  A.w[1] = v[3];
-  A.s[0] = v[4];
-  A.s[1] = v[5];
-  A.p = v[6];
-  A.e = v[7];
+  A.r = v[0];
+  A.u = v[1];
+  A.w = v[2];
+  A.p = v[3];
+  A.s = v[4];
+  A.e = v[5];
 }
 
 PcgArgs<float> pcg_args32(const swe_nh_config* c, Ctx2D* x) {
@@ -1146,7 +1267,8 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
 }
 
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, x->bar);
+  hipLaunchKernelGGL(k_bar_reset, dim3((x->ntiles + 255) / 256), dim3(256), 0, s, x->bar, x->tflag,
+                     x->ntiles);
   if (c->precision == 1)
     hipLaunchKernelGGL(k_pcg2d<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, pcg_args32(c, x));
   else
@@ -1190,7 +1312,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->dg32 = (float*)take(4 * N);
   x->ce32 = (float*)take(4 * N);
   x->cn32 = (float*)take(4 * N);
-  for (int k = 0; k < 8; k++) {
+  for (int k = 0; k < 6; k++) {
     if (c->precision == 1)
       x->v32[k] = (float*)take(4 * N);
     else
@@ -1198,6 +1320,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   }
   x->part = (double*)take(8 * 2 * 4 * (size_t)PCG_GMAX);
   x->bar = (unsigned long long*)take(8);
+  x->tflag = (unsigned*)take(4 * (size_t)x->ntiles);
   x->iters = (int*)take(4);
   x->rel = (double*)take(8);
   if (c->warm == 2) {
