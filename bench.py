@@ -336,9 +336,10 @@ def run_2d(B, torch, S, steps, warmup):
     for name, kw in (("adaptive_fp32", dict(crit=S.CRIT_ETA_D, precision=1)),
                      ("adaptive_fp64", dict(crit=S.CRIT_ETA_D, precision=0)),
                      ("global_fp32", dict(crit=S.CRIT_GLOBAL, precision=1))):
-        ctx = B.context_2d(c, k_nh=1e-3, enlarge=1, cfl=0.5, tol=1e-10, max_iter=50000, warm=1,
+        ctx = B.context_2d(c, k_nh=1e-3, enlarge=1, cfl=0.5, tol=1e-10, max_iter=5000, warm=1,
                            **kw)
         ctx.set_time(0.0)
+        log(f"{name}: {warmup} warmup + {steps} timed steps")
         h, hu, hv, hw = f(c.h), f(c.hu), f(c.hv), f(c.hw)
         p = torch.zeros_like(h)
         ctx.step(h, hu, hv, hw, p, nsteps=warmup)

@@ -12,6 +12,7 @@ namespace swenh {
 
 constexpr int TX2 = 32;  // tile width (cells along x) of the 2D kernels
 constexpr int TY2 = 16;  // tile height
+constexpr int PCG_NVEC = 10;  // inner vectors of the 2D solver
 
 struct Ctx2D {
   int nx = 0, ny = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
@@ -29,9 +30,9 @@ struct Ctx2D {
   float *dg32 = nullptr, *ce32 = nullptr, *cn32 = nullptr;
   uint8_t* nb = nullptr;
   // inner Krylov vectors, FP32 (precision 1) or FP64 (precision 0):
-  // r, u = M^-1 r, w = A u, p, s, e
-  float* v32[6] = {};
-  double* v64[6] = {};
+  // r, u, w, z, q, s, p, e, m[2] of the pipelined CG
+  float* v32[PCG_NVEC] = {};
+  double* v64[PCG_NVEC] = {};
   unsigned* tflag = nullptr;  // per tile: neighbour-sync stamp
   double* part = nullptr;    // [2][4][PCG_GMAX] block partial sums
   unsigned long long* bar = nullptr;  // grid barrier arrival counter

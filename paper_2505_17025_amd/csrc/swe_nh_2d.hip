@@ -10,12 +10,12 @@
 //   k_mask2d       criterion + (2e+1)^2 box enlargement, tile counts
 //   k_tiles2d      list of tiles holding marked cells
 //   k_assemble2d   5-point operator of the elliptic system (FP64 + FP32 copy)
-//   k_pcg2d<R>     persistent CG (Chronopoulos-Gear form) preconditioned by
-//                  tile-block symmetric red-black SOR, in precision R with
+//   k_pcg2d<R>     persistent CG preconditioned by tile-block symmetric
+//                  red-black SOR (pipelined form when each block owns one
+//                  tile, Chronopoulos-Gear otherwise), in precision R with
 //                  FP64 residuals and FP64 refinement of the solution,
-//                  deterministic fixed-order dot products, per iteration
-//                  one neighbour-tile sync and one grid barrier (arrival
-//                  counter), all waits bounded
+//                  deterministic fixed-order dot products, arrival-counter
+//                  grid barrier, bounded waits
 //   k_correct2d    projection of hu, hv and hw on the marked cells
 #include "swe_nh_2d.h"
 #include "swe_nh_cnn.h"
@@ -703,10 +703,8 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
 // ---------------------------------------------------------------------------
 // persistent PCG with FP64 refinement
 // ---------------------------------------------------------------------------
-// The inner solve is CG in the Chronopoulos-Gear form (one global reduction
-// per iteration: (r,u), (w,u) and (r,r) together, with w = A u) with a
-// tile-block preconditioner (symmetric red-black SOR on each tile's own block
-// of A); see k_pcg2d.
+// The inner solve is pipelined CG with a tile-block preconditioner
+// (symmetric red-black SOR on each tile's own block of A); see k_pcg2d.
 //
 // Bounded waits: a wait longer than WAIT_TICKS aborts the solve (status bit)
 // so that the kernel always ends; wall_clock64 ticks at 100 MHz.
@@ -815,8 +813,9 @@ struct PcgArgs {
   const double *dg, *ce, *cn, *b;
   double* x;
   const R *dgR, *ceR, *cnR;
-  R *r, *u, *w, *p, *s, *e;
-  unsigned* tflag;  // per tile: last neighbour-sync stamp passed
+  R *r, *u, *w, *z, *q, *s, *p, *e;
+  R* m[2];          // M^-1 w, double-buffered by pass parity (pipelined form)
+  unsigned* tflag;  // per tile: last neighbour-sync stamp passed (Chronopoulos-Gear form)
   double* part;
   Bar bar;
   int* iters;
@@ -912,23 +911,36 @@ __device__ __forceinline__ TileCells<R> tile_cells(const PcgArgs<R>& A, int tile
   return C;
 }
 
-// u = M^-1 r on one tile; rc[q]: r of the thread's cells (0 off the system);
-// z: LDS [TY2][TX2]; result in z
+// the tile's own block of A at the thread's cells (couplings that leave the
+// tile dropped)
 template <typename R>
-__device__ void tile_precond(const PcgArgs<R>& A, const TileCells<R>& C, const R (&rc)[2],
-                             R (*z)[TX2]) {
+struct TileOp {
   R dg[2], cE[2], cW[2], cN[2], cS[2];
+};
+
+template <typename R>
+__device__ __forceinline__ TileOp<R> tile_op(const PcgArgs<R>& A, const TileCells<R>& C) {
+  TileOp<R> T;
 #pragma unroll
   for (int q = 0; q < 2; q++) {
     const int64_t o = C.o[q];
     const uint8_t f = C.nb[q];
-    dg[q] = (f & NB_SELF) ? A.dgR[o] : R(1);
-    cE[q] = (f & NB_E) ? A.ceR[o] : R(0);
-    cW[q] = (f & NB_W) ? A.ceR[o - 1] : R(0);
-    cN[q] = (f & NB_N) ? A.cnR[o] : R(0);
-    cS[q] = (f & NB_S) ? A.cnR[o - A.nx] : R(0);
-    z[C.lj[q]][C.li[q]] = R(0);
+    T.dg[q] = (f & NB_SELF) ? A.dgR[o] : R(1);
+    T.cE[q] = (f & NB_E) ? A.ceR[o] : R(0);
+    T.cW[q] = (f & NB_W) ? A.ceR[o - 1] : R(0);
+    T.cN[q] = (f & NB_N) ? A.cnR[o] : R(0);
+    T.cS[q] = (f & NB_S) ? A.cnR[o - A.nx] : R(0);
   }
+  return T;
+}
+
+// u = M^-1 r on one tile; rc[q]: r of the thread's cells (0 off the system);
+// z: LDS [TY2][TX2]; result in z (all threads synchronised on return)
+template <typename R>
+__device__ void tile_precond(const TileCells<R>& C, const TileOp<R>& T, const R (&rc)[2],
+                             R (*z)[TX2]) {
+#pragma unroll
+  for (int q = 0; q < 2; q++) z[C.lj[q]][C.li[q]] = R(0);
   __syncthreads();
   const R om = (R)GS_OMEGA;
   for (int hs = 0; hs < GS_HALF; hs++) {
@@ -938,15 +950,76 @@ __device__ void tile_precond(const PcgArgs<R>& A, const TileCells<R>& C, const R
       const int li = C.li[q], lj = C.lj[q];
       if (((li + lj) & 1) != colour || !(C.nb[q] & NB_SELF)) continue;
       R a = rc[q];
-      if (C.nb[q] & NB_E) a -= cE[q] * z[lj][li + 1];
-      if (C.nb[q] & NB_W) a -= cW[q] * z[lj][li - 1];
-      if (C.nb[q] & NB_N) a -= cN[q] * z[lj + 1][li];
-      if (C.nb[q] & NB_S) a -= cS[q] * z[lj - 1][li];
-      z[lj][li] = (R(1) - om) * z[lj][li] + om * a / dg[q];
+      if (C.nb[q] & NB_E) a -= T.cE[q] * z[lj][li + 1];
+      if (C.nb[q] & NB_W) a -= T.cW[q] * z[lj][li - 1];
+      if (C.nb[q] & NB_N) a -= T.cN[q] * z[lj + 1][li];
+      if (C.nb[q] & NB_S) a -= T.cS[q] * z[lj - 1][li];
+      z[lj][li] = (R(1) - om) * z[lj][li] + om * a / T.dg[q];
     }
     __syncthreads();
   }
 }
+
+// The full operator at the thread's cells (couplings across tile edges kept)
+template <typename R>
+struct FullOp {
+  uint8_t nf[2];
+  R dg[2], cE[2], cW[2], cN[2], cS[2];
+};
+
+template <typename R>
+__device__ __forceinline__ FullOp<R> full_op(const PcgArgs<R>& A, const TileCells<R>& C) {
+  FullOp<R> F;
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const int64_t o = C.o[q];
+    const uint8_t f = (C.nb[q] & NB_SELF) ? A.nb[o] : 0;
+    F.nf[q] = f;
+    F.dg[q] = (f & NB_SELF) ? A.dgR[o] : R(1);
+    F.cE[q] = (f & NB_E) ? A.ceR[o] : R(0);
+    F.cW[q] = (f & NB_W) ? A.ceR[o - 1] : R(0);
+    F.cN[q] = (f & NB_N) ? A.cnR[o] : R(0);
+    F.cS[q] = (f & NB_S) ? A.cnR[o - A.nx] : R(0);
+  }
+  return F;
+}
+
+// its restriction to the tile's own block
+template <typename R>
+__device__ __forceinline__ TileOp<R> restrict_op(const FullOp<R>& F, const TileCells<R>& C) {
+  TileOp<R> T;
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    T.dg[q] = F.dg[q];
+    T.cE[q] = (C.nb[q] & NB_E) ? F.cE[q] : R(0);
+    T.cW[q] = (C.nb[q] & NB_W) ? F.cW[q] : R(0);
+    T.cN[q] = (C.nb[q] & NB_N) ? F.cN[q] : R(0);
+    T.cS[q] = (C.nb[q] & NB_S) ? F.cS[q] : R(0);
+  }
+  return T;
+}
+
+// (A v) at the thread's cell q: v of the tile from LDS (lds) or memory, v
+// across the tile edges from memory
+template <typename R>
+__device__ __forceinline__ R apply_at(const FullOp<R>& F, const TileCells<R>& C, int q, const R* v,
+                                      const R (*zt)[TX2], bool lds, int nx) {
+  const int64_t o = C.o[q];
+  const int li = C.li[q], lj = C.lj[q];
+  const uint8_t f = F.nf[q];
+  R a = F.dg[q] * (lds ? zt[lj][li] : v[o]);
+  if (f & NB_E) a += F.cE[q] * ((lds && li + 1 < TX2) ? zt[lj][li + 1] : v[o + 1]);
+  if (f & NB_W) a += F.cW[q] * ((lds && li > 0) ? zt[lj][li - 1] : v[o - 1]);
+  if (f & NB_N) a += F.cN[q] * ((lds && lj + 1 < TY2) ? zt[lj + 1][li] : v[o + nx]);
+  if (f & NB_S) a += F.cS[q] * ((lds && lj > 0) ? zt[lj - 1][li] : v[o - nx]);
+  return a;
+}
+
+// inner vectors of the thread's two cells
+template <typename R>
+struct Cells {
+  R r[2], u[2], w[2], z[2], q[2], s[2], p[2], e[2];
+};
 
 // Neighbour sync: every block stamps its tiles, then waits until the four
 // face neighbours of each of its tiles that hold unknowns carry the stamp.
@@ -994,19 +1067,13 @@ __device__ bool neighbour_sync(const PcgArgs<R>& A, const Share& S, unsigned sta
   return ok != 0;
 }
 
-// Persistent preconditioned CG, Chronopoulos-Gear form (u = M^-1 r, w = A u;
-// one grid reduction of (r,u), (w,u), (r,r) per iteration).  Each iteration:
-// phase 1 (recurrences of p, s, e, r on the block's cells, then u = M^-1 r on
-// its tiles), a neighbour-tile sync (w needs the neighbours' u), phase 2
-// (w = A u), one grid barrier.  The inner solve runs in precision R; the
-// outer loop refines the FP64 solution with FP64 residuals.
+// Preconditioned CG in the Chronopoulos-Gear form (u = M^-1 r, w = A u; one
+// grid reduction of (r,u), (w,u), (r,r) per iteration) for blocks that own
+// several tiles: vectors in memory.  Each iteration: phase 1 (recurrences of
+// p, s, e, r, then u = M^-1 r on the block's tiles), a neighbour-tile sync
+// (w needs the neighbours' u), phase 2 (w = A u), one grid barrier.
 template <typename R>
-__global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
-  __shared__ R zt[TY2][TX2];
-  const int nlist = *A.n_list;
-  const int G = max(1, min((int)gridDim.x, nlist));
-  if ((int)blockIdx.x >= G) return;
-  const Share S = share_of(G, nlist);
+__device__ void pcg_cg(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2]) {
   const int nx = A.nx;
   unsigned k = 0;      // grid barriers passed
   unsigned stamp = 0;  // neighbour syncs passed
@@ -1072,7 +1139,7 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
             A.r[o] = rc[q];
           }
         }
-        tile_precond(A, C, rc, zt);
+        tile_precond(C, tile_op(A, C), rc, zt);
 #pragma unroll
         for (int q = 0; q < 2; q++) {
           if (!(C.nb[q] & NB_SELF)) continue;
@@ -1119,6 +1186,165 @@ __global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
 }
+
+
+// Preconditioned CG in the pipelined form of Ghysels and Vanroose (2014)
+// for blocks that own one tile each: per iteration one pass and one grid
+// barrier, which both completes the reduction of (r,u), (w,u), (r,r) and
+// publishes m = M^-1 w (tile-local) for the neighbours' n = A m of the next
+// pass (m double-buffered by pass parity).  The vectors stay in registers and
+// the tile's m stays in LDS for the whole solve.
+template <typename R>
+__device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2]) {
+  const int nx = A.nx;
+  const TileCells<R> C = tile_cells(A, A.tile_list[S.t0]);
+  const FullOp<R> F = full_op(A, C);
+  const TileOp<R> T = restrict_op(F, C);
+  Cells<R> X{};
+  unsigned k = 0;  // grid barriers passed
+  double bb = 0.0, rr = 0.0;
+  int total = 0, sweep = 0;
+  for (;;) {
+    // FP64 residual of the current solution -> r_0 (precision R), u_0 = M^-1 r_0
+    {
+      double v[2] = {0.0, 0.0};
+      R rc[2];
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        rc[q] = R(0);
+        if (!(F.nf[q] & NB_SELF)) continue;
+        const int64_t o = C.o[q];
+        const double rv = A.b[o] - apply5<double, double>(A.dg, A.ce, A.cn, A.x, F.nf[q], o, nx);
+        rc[q] = (R)rv;
+        X.r[q] = rc[q];
+        X.e[q] = R(0);
+        v[0] += rv * rv;
+        if (sweep == 0) v[1] += A.b[o] * A.b[o];
+      }
+      tile_precond(C, T, rc, zt);
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        if (!(F.nf[q] & NB_SELF)) continue;
+        X.u[q] = zt[C.lj[q]][C.li[q]];
+        A.u[C.o[q]] = X.u[q];
+      }
+      block_partials<2>(v, part_buf(A.part, k + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++k, G)) return;
+      double tt[2];
+      grid_totals<2>(part_buf(A.part, k), G, tt);
+      rr = tt[0];
+      if (sweep == 0) bb = tt[1];
+    }
+    const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    if (rel <= A.tol) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) *A.rel = rel;
+      break;
+    }
+    if (total >= A.max_iter) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *A.rel = rel;
+        atomicOr(A.bar.status, ST_NOCONV);
+      }
+      break;
+    }
+    // inner solve of A_R e = r stopped at ||r_j|| <= tol_abs.  FP32 reduces
+    // the residual by tol_in (what FP32 can deliver) but never further than
+    // the outer target; FP64 goes straight to the outer target.
+    const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
+                                            : 0.5 * A.tol * sqrt(bb);
+    double gam = 0.0, alpha = 0.0, beta = 0.0;
+    for (int j = 0;; j++) {
+      // pass j: (j >= 1) n = A m_{j-1} and the recurrences with alpha_{j-1},
+      // beta_{j-1}; (j == 0) w_0 = A u_0.  Then the partial sums of pass j
+      // and m_j = M^-1 w_j, published for the neighbours.  zt holds u_0
+      // (j == 0) or m_{j-1} of the tile on entry.
+      const R al = (R)alpha, bt = (R)beta;
+      const R* mprev = A.m[(j + 1) & 1];
+      R* mnext = A.m[j & 1];
+      double v[3] = {0.0, 0.0, 0.0};  // (r,u), (w,u), (r,r)
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        if (!(F.nf[q] & NB_SELF)) continue;
+        if (j == 0) {
+          X.w[q] = apply_at(F, C, q, A.u, zt, true, nx);
+        } else {
+          const R n = apply_at(F, C, q, mprev, zt, true, nx);
+          const R m = zt[C.lj[q]][C.li[q]];
+          const bool first = j == 1;
+          X.z[q] = first ? n : fma(bt, X.z[q], n);
+          X.q[q] = first ? m : fma(bt, X.q[q], m);
+          X.s[q] = first ? X.w[q] : fma(bt, X.s[q], X.w[q]);
+          X.p[q] = first ? X.u[q] : fma(bt, X.p[q], X.u[q]);
+          X.e[q] = fma(al, X.p[q], X.e[q]);
+          X.r[q] = fma(-al, X.s[q], X.r[q]);
+          X.u[q] = fma(-al, X.q[q], X.u[q]);
+          X.w[q] = fma(-al, X.z[q], X.w[q]);
+        }
+      }
+      R wc[2];
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        wc[q] = R(0);
+        if (!(F.nf[q] & NB_SELF)) continue;
+        wc[q] = X.w[q];
+        v[0] += (double)X.r[q] * (double)X.u[q];
+        v[1] += (double)X.w[q] * (double)X.u[q];
+        v[2] += (double)X.r[q] * (double)X.r[q];
+      }
+      __syncthreads();  // the tile's LDS values are read before the sweeps overwrite them
+      tile_precond(C, T, wc, zt);
+#pragma unroll
+      for (int q = 0; q < 2; q++)
+        if (F.nf[q] & NB_SELF) mnext[C.o[q]] = zt[C.lj[q]][C.li[q]];
+      block_partials<3>(v, part_buf(A.part, k + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++k, G)) return;
+      double tt[3];
+      grid_totals<3>(part_buf(A.part, k), G, tt);
+      const double gn = tt[0], dn = tt[1], rn = tt[2];
+      if (j > 0) {
+        total++;
+        if (sqrt(rn) <= tol_abs || total >= A.max_iter || !(gn == gn)) break;
+      }
+      if (j == 0) {
+        alpha = dn != 0.0 ? gn / dn : 0.0;
+        beta = 0.0;
+      } else {
+        const double bn = gam != 0.0 ? gn / gam : 0.0;
+        const double den = dn - bn * gn / alpha;
+        if (!(den != 0.0)) break;
+        beta = bn;
+        alpha = gn / den;
+      }
+      gam = gn;
+    }
+    // x += e (FP64)
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+      if (F.nf[q] & NB_SELF) A.x[C.o[q]] += (double)X.e[q];
+    if (!grid_sync(A.bar, ++k, G)) return;
+    sweep++;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
+}
+
+// Persistent preconditioned CG (M^-1: the tile-block symmetric red-black SOR
+// above): pipelined when every participating block owns exactly one active
+// tile, Chronopoulos-Gear with a neighbour-tile sync otherwise.  The inner
+// solve runs in precision R; the outer loop refines the FP64 solution with
+// FP64 residuals until ||b - A x|| <= tol ||b||.
+template <typename R>
+__global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
+  __shared__ R zt[TY2][TX2];
+  const int nlist = *A.n_list;
+  const int G = max(1, min((int)gridDim.x, nlist));
+  if ((int)blockIdx.x >= G) return;
+  const Share S = share_of(G, nlist);
+  if (nlist >= 1 && nlist <= (int)gridDim.x)
+    pcg_pipelined(A, S, G, zt);
+  else
+    pcg_cg(A, S, G, zt);
+}
+
 
 __global__ void k_bar_reset(unsigned long long* count, unsigned* tflag, int ntiles) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0ull;
@@ -1234,9 +1460,13 @@ void set_vectors(PcgArgs<R>& A, R* const* v) {
   A.r = v[0];
   A.u = v[1];
   A.w = v[2];
-  A.p = v[3];
-  A.s = v[4];
-  A.e = v[5];
+  A.z = v[3];
+  A.q = v[4];
+  A.s = v[5];
+  A.p = v[6];
+  A.e = v[7];
+  A.m[0] = v[8];
+  A.m[1] = v[9];
 }
 
 PcgArgs<float> pcg_args32(const swe_nh_config* c, Ctx2D* x) {
@@ -1312,7 +1542,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->dg32 = (float*)take(4 * N);
   x->ce32 = (float*)take(4 * N);
   x->cn32 = (float*)take(4 * N);
-  for (int k = 0; k < 6; k++) {
+  for (int k = 0; k < PCG_NVEC; k++) {
     if (c->precision == 1)
       x->v32[k] = (float*)take(4 * N);
     else

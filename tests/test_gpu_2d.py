@@ -204,3 +204,19 @@ def test_deterministic_2d(B):
     b = run2d(B, c, 5, **kw)
     for x, y in zip(a[2:], b[2:]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_many_tiles_per_solver_block(B, precision):
+    """global extension on 1536 x 512 cells (1536 tiles, more than the
+    solver's blocks): every block of the persistent solver walks several
+    tiles (the Chronopoulos-Gear form with a neighbour-tile sync)"""
+    c = S.random_case_2d(1536, 512, seed=41, dx=1.0, dy=1.0, h0=10.0)
+    tol = 1e-13 if precision == 0 else 1e-11
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=5000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 1, **kw)
+    assert st["status"] == 0, st
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_GLOBAL, tol=1e-14), cfl=0.4).step(1)
+    bar = 1e-10 if precision == 0 else 1e-6
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= bar
