@@ -51,8 +51,7 @@ __global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict
   __syncthreads();
   if (threadIdx.x == 0) {
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const int par = P.fused ? (*P.step & 1) : 0;
-    atomicMax(&P.smax[par * P.nch + tl.x], pos_bits(m));
+    atomicMax(&P.smax[tl.x], pos_bits(m));
     if (fl) atomicOr(P.status, fl);
   }
 }
@@ -72,8 +71,9 @@ __device__ __forceinline__ Flux rusanov1d(double g, double eL, double mL, double
   Flux f;
   const double hL = eL + dL, hR = eR + dR;
   f.dry = !(hL > 0.0) || !(hR > 0.0);
-  const double uL = mL / hL, uR = mR / hR;
-  const double wL = kL / hL, wR = kR / hR;
+  const double rL = 1.0 / hL, rR = 1.0 / hR;
+  const double uL = mL * rL, uR = mR * rR;
+  const double wL = kL * rL, wR = kR * rR;
   const double db = fmin(dL, dR);
   const double sL = fmax(0.0, eL + db), sR = fmax(0.0, eR + db);
   const double lam = fmax(fabs(uL) + sqrt(g * sL), fabs(uR) + sqrt(g * sR));
@@ -165,16 +165,9 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
   const double t0 = t_in[tl.x];
   double dt;
   if (dt_from_speed) {
-    // fused step: the speed of Q^n is in buffer (step & 1); the other buffer
-    // collects the speed of Q^{n+1} during this step and is cleared here
-    const int par = P.fused ? (*P.step & 1) : 0;
-    const unsigned long long sm = P.smax[par * P.nch + tl.x];
-    dt = (P.cfl > 0.0) ? P.cfl * P.dx / __longlong_as_double((long long)sm) : P.dt_fixed;
-    if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) {
-      P.dt[tl.x] = dt;
-      if (P.fused) P.smax[(par ^ 1) * P.nch + tl.x] = 0ull;
-    }
-    if (P.fused && blockIdx.x == 0 && threadIdx.x == 0) *P.n_act = 0;
+    dt = (P.cfl > 0.0) ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[tl.x])
+                       : P.dt_fixed;
+    if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.dt[tl.x] = dt;
   } else {
     dt = dt_in[tl.x];
   }
@@ -655,7 +648,7 @@ struct StepSmem {
       FaceNH fq[T + 1];  // faces start .. end
     } q;
     struct {
-      double a[RW], b[RW], c[RW], d[3][RW];
+      double a[RW], b[RW], c[RW], d[3][RW], r[RW];  // r = 1 / b
     } s;  // tile system
   } u;
   uint8_t raw[T + 2 + 2 * EMAXF];
@@ -707,7 +700,7 @@ __device__ __forceinline__ void step_cell(const SM& S, const double* d, double g
 struct WinQ {
   const double *h, *m, *k, *d;  // window arrays
   int lo, n;
-  double dx;
+  double dx, idx, i2dx;  // dx, 1 / dx, 1 / (2 dx)
   __device__ double H(int i) const { return h[reflect(i, n) - lo]; }
   __device__ double D(int i) const { return d[reflect(i, n) - lo]; }
   // momentum of cell i, odd under the wall reflection
@@ -726,24 +719,24 @@ __device__ double indicator_win(const WinQ& Q, int i, int crit) {
       return fabs((Q.H(i) - d) / d);
     }
     case SWE_NH_CRIT_ETA_X:
-      return fabs(((Q.H(i + 1) - Q.D(i + 1)) - (Q.H(i - 1) - Q.D(i - 1))) / (2.0 * Q.dx));
+      return fabs(((Q.H(i + 1) - Q.D(i + 1)) - (Q.H(i - 1) - Q.D(i - 1))) * Q.i2dx);
     case SWE_NH_CRIT_U:
       return fabs(Q.Mo(i) / Q.H(i));
     case SWE_NH_CRIT_U_X:
-      return fabs((Q.Mo(i + 1) / Q.H(i + 1) - Q.Mo(i - 1) / Q.H(i - 1)) / (2.0 * Q.dx));
+      return fabs((Q.Mo(i + 1) / Q.H(i + 1) - Q.Mo(i - 1) / Q.H(i - 1)) * Q.i2dx);
     case SWE_NH_CRIT_W:
       return fabs(Q.K(i) / Q.H(i));
     default:  // SWE_NH_CRIT_W_X
-      return fabs((Q.K(i + 1) / Q.H(i + 1) - Q.K(i - 1) / Q.H(i - 1)) / (2.0 * Q.dx));
+      return fabs((Q.K(i + 1) / Q.H(i + 1) - Q.K(i - 1) / Q.H(i - 1)) * Q.i2dx);
   }
 }
 
 // d_x, 4 + d_x^2 and phi (Eq. 5) at channel cell s from the window
 __device__ CellNH cell_win(const WinQ& Q, const K1D& P, const Chan& c, const Motion& M, int s) {
   const double dl = Q.D(s - 1), d0 = Q.D(s), dr = Q.D(s + 1);
-  const double D = (dr - dl) / (2.0 * Q.dx);
-  const double dxx = (dr - 2.0 * d0 + dl) / (Q.dx * Q.dx);
-  const double ex = ((Q.H(s + 1) - dr) - (Q.H(s - 1) - dl)) / (2.0 * Q.dx);
+  const double D = (dr - dl) * Q.i2dx;
+  const double dxx = (dr - 2.0 * d0 + dl) * (Q.idx * Q.idx);
+  const double ex = ((Q.H(s + 1) - dr) - (Q.H(s - 1) - dl)) * Q.i2dx;
   const double hs = Q.H(s);
   const double u = Q.Mo(s) / hs;
   const BedRate br = bed_rate(M, body_shape(c, (s + 0.5) * Q.dx - M.X, 0.0));
@@ -759,14 +752,14 @@ __device__ FaceNH face_win(const WinQ& Q, const K1D& P, double dt, int f, double
                            double phir) {
   const double hl = Q.H(f - 1), hr = Q.H(f);
   const double hf = 0.5 * (hl + hr);
-  const double Df = (Q.D(f) - Q.D(f - 1)) / Q.dx;
-  const double hx = (hr - hl) / Q.dx;
+  const double Df = (Q.D(f) - Q.D(f - 1)) * Q.idx;
+  const double hx = (hr - hl) * Q.idx;
   const double af = 4.0 + Df * Df;
   const double s11 = (2.0 * hx - 3.0 * Df) / (2.0 * hf);
   FaceNH q;
   q.K = 4.0 * dt * hf / (P.rho * af);
-  q.a = -1.0 / Q.dx + 0.5 * s11;
-  q.b = 1.0 / Q.dx + 0.5 * s11;
+  q.a = -Q.idx + 0.5 * s11;
+  q.b = Q.idx + 0.5 * s11;
   q.fd = dt / P.rho * (0.5 * (phil + phir)) * Df;
   q.qp = 0.5 * (Q.Mo(f - 1) + Q.Mo(f)) + q.fd;
   return q;
@@ -787,14 +780,14 @@ __device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
       double bi = Y.b[i], ai = 0.0, ci = 0.0;
       double di[3] = {Y.d[0][i], Y.d[1][i], Y.d[2][i]};
       if (im >= 0) {
-        const double k1 = Y.a[i] / Y.b[im];
+        const double k1 = Y.a[i] * Y.r[im];
         ai = -Y.a[im] * k1;
         bi -= Y.c[im] * k1;
 #pragma unroll
         for (int r = 0; r < 3; r++) di[r] -= Y.d[r][im] * k1;
       }
       if (ip < RW) {
-        const double k2 = Y.c[i] / Y.b[ip];
+        const double k2 = Y.c[i] * Y.r[ip];
         ci = -Y.c[ip] * k2;
         bi -= Y.a[ip] * k2;
 #pragma unroll
@@ -813,6 +806,7 @@ __device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
       Y.a[i] = na[j];
       Y.b[i] = nb[j];
       Y.c[i] = nc[j];
+      Y.r[i] = 1.0 / nb[j];
 #pragma unroll
       for (int r = 0; r < 3; r++) Y.d[r][i] = nd[j][r];
     }
@@ -832,7 +826,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
                                                const double* __restrict__ hw,
                                                double* __restrict__ hn, double* __restrict__ hun,
                                                double* __restrict__ hwn, uint8_t* __restrict__ mask,
-                                               double* __restrict__ p) {
+                                               double* __restrict__ p, int par) {
   using SM = StepSmem<T, NT>;
   constexpr int WMAX = SM::WMAX, RW = SM::RW;
   constexpr int Q = (WMAX - 4 + NT - 1) / NT;  // window cells per thread
@@ -841,15 +835,22 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
-  const int step = *P.step, par = step & 1;
+  const int step = P.step[par];
   const double dt =
       (P.cfl > 0.0)
           ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[par * P.nch + tl.x])
           : P.dt_fixed;
-  if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.dt[tl.x] = dt;
+  const double t0 = P.t[par * P.nch + tl.x], t1 = t0 + dt;
+  if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) {
+    P.dt[tl.x] = dt;
+    P.t[(par ^ 1) * P.nch + tl.x] = t1;  // the next step's start time
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.step[par ^ 1] = step + 1;
+    P.n_acc[par ^ 1] = 0;  // counts the next step
+  }
   const int ee = P.enlarge, HL = 6 + ee, W = T + 2 * HL;
   const int lo = start - HL;  // window cell w <-> channel cell lo + w
-  const double t0 = P.t[tl.x], t1 = t0 + dt;
   const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t1);
   const double idx = 1.0 / P.dx;
   if (threadIdx.x == 0) sflags = 0;
@@ -941,7 +942,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   __syncthreads();
 
   // ---- criterion, enlargement ----
-  const WinQ QW{S.e, S.m, S.k, S.d1, lo, n, P.dx};
+  const WinQ QW{S.e, S.m, S.k, S.d1, lo, n, P.dx, idx, 0.5 * idx};
   int mode;
   {
     const bool wcrit = (P.crit == SWE_NH_CRIT_W || P.crit == SWE_NH_CRIT_W_X);
@@ -1001,7 +1002,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   const int F = 2 * blockIdx.x, L = F + 1;
   if (threadIdx.x == 0) {
     P.tile_cnt[blockIdx.x] = m;
-    if (m) atomicAdd(P.n_acc, m);
+    if (m) atomicAdd(&P.n_acc[par], m);
   }
   if (m == 0) {
     if (threadIdx.x == 0) {
@@ -1032,10 +1033,10 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
     const FaceNH fl = S.u.q.fq[k - 1], fr = S.u.q.fq[k];
     const CellNH c0 = S.u.q.cq[k];
     const double hs = S.e[w], ms = S.m[w], ks = S.k[w];
-    const double s22 = 3.0 * dt / (P.rho * hs);
+    const double rh = 1.0 / hs, dtr = dt / P.rho;
+    const double s22 = 3.0 * dtr * rh;
     const BedRate br = bed_rate(M1, body_shape(c, (i + 0.5) * P.dx - M1.X, 0.0));
-    const double f2 = -2.0 * br.d_t - 2.0 * ks / hs - c0.D * ms / (2.0 * hs) -
-                      dt * c0.al * c0.phi / (2.0 * P.rho * hs);
+    const double f2 = -2.0 * br.d_t - (2.0 * ks + 0.5 * c0.D * ms + 0.5 * dtr * c0.al * c0.phi) * rh;
     ra[q] = (i > 0 && S.mk[k - 1]) ? fl.K * fl.a * fl.b : 0.0;
     rb[q] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
     rc[q] = (i + 1 < n && S.mk[k + 1]) ? fr.K * fr.a * fr.b : 0.0;
@@ -1103,18 +1104,19 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
     }
     Y.d[1][j] = first ? 1.0 : 0.0;
     Y.d[2][j] = last ? 1.0 : 0.0;
+    Y.r[j] = 1.0 / Y.b[j];
   }
   __syncthreads();
   pcr_tile<T, NT>(S, m);
   for (int j = threadIdx.x; j < m; j += NT) {
-    const double ib = 1.0 / Y.b[j];
+    const double ib = Y.r[j];
     P.zw[pb + j + ZW_Z * zs] = Y.d[0][j] * ib;
     P.zw[pb + j + ZW_U * zs] = Y.d[1][j] * ib;
     P.zw[pb + j + ZW_V * zs] = Y.d[2][j] * ib;
   }
   if (threadIdx.x == 0) {
-    const double z1 = Y.d[0][1] / Y.b[1], u1 = Y.d[1][1] / Y.b[1], v1 = Y.d[2][1] / Y.b[1];
-    const double zL = Y.d[0][m - 2] / Y.b[m - 2], vL = Y.d[2][m - 2] / Y.b[m - 2];
+    const double z1 = Y.d[0][1] * Y.r[1], u1 = Y.d[1][1] * Y.r[1], v1 = Y.d[2][1] * Y.r[1];
+    const double zL = Y.d[0][m - 2] * Y.r[m - 2], vL = Y.d[2][m - 2] * Y.r[m - 2];
     P.dg1[F] = b0 + c0 * u1;
     P.up1[F] = c0 * v1;
     P.rh1[F] = d0 - c0 * z1;
@@ -1124,61 +1126,72 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   }
 }
 
-namespace {
-// t += dt, step + 1, publish the marked-cell count, clear the speed buffer
-// this step read (it collects the speed of the step after next)
-__device__ void finish_step(const K1D& P, int par) {
-  for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) {
-    P.t[ch] += P.dt[ch];
-    P.smax[par * P.nch + ch] = 0ull;
-  }
-  if (threadIdx.x == 0) {
-    *P.step += 1;
-    *P.n_act = *P.n_acc;
-    *P.n_acc = 0;
-  }
-}
-}  // namespace
 
 // Projection of the marked cells (a6) from the level-1 solution -- solved
 // here, redundantly by every tile that needs it, when it has at most L1MAX
 // rows (L1LOCAL), else read from P.x1 -- and the speed of their new state.
-// fin = 1: the last block to finish ends the step (advances t and the step
-// counter, publishes the marked-cell count, clears the speed buffer this
-// step read); fin = 2: k_finish1d does that; fin = 0: stage timing.
+// par: parity of the step within the run (the time, step counter, marked
+// count and speed buffers alternate with it).
 template <int T, int NT, bool L1LOCAL>
 __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict__ mask,
                                                 double* hun, double* hwn, double* p,
-                                                int fin) {
+                                                int par) {
   constexpr int L1 = L1LOCAL ? L1MAX : 1, RPT = L1LOCAL ? L1MAX / NT : 1;
   __shared__ double xs[T + 2];
-  __shared__ double la[L1], lb[L1], lc[L1], ld[L1];
+  __shared__ double la[L1], lb[L1], lc[L1], ld[L1], lr[L1];
+  __shared__ double rdg[L1], rup[L1], rrh[L1];  // level-1 rows as stored (2 per tile)
+  __shared__ int rcnt[(L1 + 1) / 2];
   __shared__ int tpos[(L1 + 1) / 2], tlist[(L1 + 1) / 2];  // tile <-> compact level-1 tile
   __shared__ int wc[NT / 64];
-  __shared__ int last;
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
-  const int par = *P.step & 1;
   const double dt = P.dt[tl.x];
+  // the speed buffer this step read collects the speed of the step after next
+  if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.smax[par * P.nch + tl.x] = 0ull;
   const int m = P.tile_cnt[blockIdx.x];
   double smax = 0.0;
   int flags = 0;
   if (m > 0) {
+    // the tile's marked rows and their stored data first: the loads are in
+    // flight while the level-1 system is solved
+    int rank[T / NT];
+    bool on[T / NT];
+    const int64_t m0 = c.off + start - 1;  // mask[m0 + k]: tile-local cell k
+    tile_ranks<T, NT>([&](int k) { return k <= len && mask[m0 + k] != 0; }, rank, on);
+    const int64_t zs = (int64_t)P.ntiles * T;
+    const int64_t pb = (int64_t)blockIdx.x * T;
+    double zr[T / NT][ZW_N];
+#pragma unroll
+    for (int q = 0; q < T / NT; q++) {
+      if (!on[q]) continue;
+      const double* z = P.zw + pb + rank[q];
+#pragma unroll
+      for (int v = 0; v < ZW_N; v++) zr[q][v] = z[v * zs];
+    }
+    const bool nb_l = start > 0 && mask[m0], nb_r = end < n && mask[m0 + len + 1];
     // level-1 solution of row j (= 2 tile + 0 first / 1 last)
     auto x1 = [&](int j) {
       if (!L1LOCAL) return P.x1[j];
       const int r = 2 * tpos[j >> 1] + (j & 1);
-      return ld[r] / lb[r];
+      return ld[r] * lr[r];
     };
     if (L1LOCAL) {
       // Level-1 system restricted to the marked tiles (an unmarked tile's two
       // identity rows are decoupled from everything), in tile order; solved
-      // by parallel cyclic reduction.
+      // by parallel cyclic reduction (lr holds 1 / lb).
+      // all level-1 rows and tile counts in one round of loads
+      for (int g = threadIdx.x; g < 2 * P.ntiles; g += NT) {
+        rdg[g] = P.dg1[g];
+        rup[g] = P.up1[g];
+        rrh[g] = P.rh1[g];
+      }
+      for (int t = threadIdx.x; t < P.ntiles; t += NT) rcnt[t] = P.tile_cnt[t];
+      __syncthreads();
       int base = 0;
       for (int t0 = 0; t0 < P.ntiles; t0 += NT) {
         const int t = t0 + threadIdx.x;
-        const bool mt = t < P.ntiles && P.tile_cnt[t] > 0;
+        const bool mt = t < P.ntiles && rcnt[t] > 0;
         const unsigned long long bal = __ballot(mt);
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         if (lane == 0) wc[wv] = __popcll(bal);
@@ -1198,22 +1211,23 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
       // coupling of compact row j to row j + 1
       auto up_c = [&](int j) {
         const int t = tlist[j >> 1];
-        if ((j & 1) == 0) return P.up1[2 * t];
-        return (j + 1 < n1 && tlist[(j >> 1) + 1] == t + 1) ? P.up1[2 * t + 1] : 0.0;
+        if ((j & 1) == 0) return rup[2 * t];
+        return (j + 1 < n1 && tlist[(j >> 1) + 1] == t + 1) ? rup[2 * t + 1] : 0.0;
       };
       for (int j = threadIdx.x; j < L1; j += NT) {
         if (j < n1) {
           const int g = 2 * tlist[j >> 1] + (j & 1);
           la[j] = j > 0 ? up_c(j - 1) : 0.0;
-          lb[j] = P.dg1[g];
+          lb[j] = rdg[g];
           lc[j] = up_c(j);
-          ld[j] = P.rh1[g];
+          ld[j] = rrh[g];
         } else {
           la[j] = 0.0;
           lb[j] = 1.0;
           lc[j] = 0.0;
           ld[j] = 0.0;
         }
+        lr[j] = 1.0 / lb[j];
       }
       __syncthreads();
       for (int s = 1; s < n1; s <<= 1) {
@@ -1225,13 +1239,13 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
           const int im = i - s, ip = i + s;
           double ai = 0.0, bi = lb[i], ci = 0.0, di = ld[i];
           if (im >= 0) {
-            const double k1 = la[i] / lb[im];
+            const double k1 = la[i] * lr[im];
             ai = -la[im] * k1;
             bi -= lc[im] * k1;
             di -= ld[im] * k1;
           }
           if (ip < L1) {
-            const double k2 = lc[i] / lb[ip];
+            const double k2 = lc[i] * lr[ip];
             ci = -lc[ip] * k2;
             bi -= la[ip] * k2;
             di -= ld[ip] * k2;
@@ -1250,74 +1264,64 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
           lb[i] = nb[r];
           lc[i] = nc[r];
           ld[i] = nd[r];
+          lr[i] = 1.0 / nb[r];
         }
         __syncthreads();
       }
     }
-    int rank[T / NT];
-    bool on[T / NT];
-    const int64_t m0 = c.off + start - 1;  // mask[m0 + k]: tile-local cell k
-    tile_ranks<T, NT>([&](int k) { return k <= len && mask[m0 + k] != 0; }, rank, on);
-    const int64_t zs = (int64_t)P.ntiles * T;
-    const int64_t pb = (int64_t)blockIdx.x * T;
     const double xF = x1(2 * blockIdx.x), xL = x1(2 * blockIdx.x + 1);
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
       const int k = 1 + threadIdx.x + NT * q;
       if (k > len) continue;
-      double x = 0.0;
-      if (on[q]) {
-        const double* z = P.zw + pb + rank[q];
-        x = z[ZW_Z * zs] + z[ZW_U * zs] * xF + z[ZW_V * zs] * xL;
-      }
-      xs[k] = x;
+      xs[k] = on[q] ? zr[q][ZW_Z] + zr[q][ZW_U] * xF + zr[q][ZW_V] * xL : 0.0;
     }
     if (threadIdx.x == 0) {
-      xs[0] = (start > 0 && mask[m0]) ? x1(2 * blockIdx.x - 1) : 0.0;
-      xs[len + 1] = (end < n && mask[m0 + len + 1]) ? x1(2 * blockIdx.x + 2) : 0.0;
+      xs[0] = nb_l ? x1(2 * blockIdx.x - 1) : 0.0;
+      xs[len + 1] = nb_r ? x1(2 * blockIdx.x + 2) : 0.0;
     }
     __syncthreads();
+    const double rdt4 = P.rho / (4.0 * dt), dtr = dt / P.rho;
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
       if (!on[q]) continue;
       const int k = 1 + threadIdx.x + NT * q;
       const int64_t gi = c.off + start + k - 1;
-      const double* z = P.zw + pb + rank[q];
+      const double* z = zr[q];
       const double pc = xs[k], pl = xs[k - 1], pr = xs[k + 1];
-      const double dql = z[ZW_FL * zs] - z[ZW_KL * zs] * (z[ZW_AL * zs] * pl + z[ZW_BL * zs] * pc);
-      const double dqr = z[ZW_FR * zs] - z[ZW_KR * zs] * (z[ZW_AR * zs] * pc + z[ZW_BR * zs] * pr);
+      const double dql = z[ZW_FL] - z[ZW_KL] * (z[ZW_AL] * pl + z[ZW_BL] * pc);
+      const double dqr = z[ZW_FR] - z[ZW_KR] * (z[ZW_AR] * pc + z[ZW_BR] * pr);
       const double dm = 0.5 * (dql + dqr);
-      const double Pb = 1.5 * pc - P.rho * z[ZW_D * zs] * dm / (4.0 * dt) + z[ZW_P * zs];
-      const double hh = z[ZW_HT * zs];
-      const double mn = z[ZW_MT * zs] + dm, kn = z[ZW_KT * zs] + dt * Pb / P.rho;
+      const double Pb = 1.5 * pc - rdt4 * z[ZW_D] * dm + z[ZW_P];
+      const double mn = z[ZW_MT] + dm, kn = z[ZW_KT] + dtr * Pb;
       hun[gi] = mn;
       hwn[gi] = kn;
       p[gi] = pc;
-      final_state(P.g, hh, mn, kn, smax, flags);
+      final_state(P.g, z[ZW_HT], mn, kn, smax, flags);
     }
   }
   flush_speed<NT>(P, tl.x, par, smax, flags);
-  if (fin != 1) return;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int prev = __hip_atomic_fetch_add(P.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = prev == (int)gridDim.x - 1;
-  }
-  __syncthreads();
-  if (last) {
-    finish_step(P, par);
-    if (threadIdx.x == 0) *P.done = 0;
-  }
 }
 
-// end of the step for grids too large for the arrival counter
-__global__ void k_finish1d(K1D P) { finish_step(P, *P.step & 1); }
+// prologue of a run of fused steps: both speed buffers and the first marked
+// count cleared (buffer 0 then collects the speed of the caller's state)
+__global__ void k_run_begin(K1D P) {
+  for (int i = threadIdx.x; i < 2 * P.nch; i += blockDim.x) P.smax[i] = 0ull;
+  if (threadIdx.x == 0) P.n_acc[0] = 0;
+}
 
-// prologue of a run of steps: speed of the caller's state into buffer
-// (step & 1) after clearing it
-__global__ void k_smax_clear(K1D P) {
-  const int par = *P.step & 1;
-  for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) P.smax[par * P.nch + ch] = 0ull;
+// end of a run of fused steps: time, step counter and the speed of the new
+// state back in slot 0, the last step's marked count published
+__global__ void k_run_end(K1D P, int last_par) {
+  if (last_par)
+    for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) {
+      P.t[ch] = P.t[P.nch + ch];
+      P.smax[ch] = P.smax[P.nch + ch];
+    }
+  if (threadIdx.x == 0) {
+    if (last_par) P.step[0] = P.step[1];
+    *P.n_act = P.n_acc[last_par ^ 1];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1444,48 +1448,47 @@ void launch_scatter_packed(const int* act_cell, const int* n_act, int64_t max_ro
 
 template <int T, int NT>
 static void launch_step_t(const K1D& P, const double* h, const double* hu, const double* hw,
-                          double* hn, double* hun, double* hwn, uint8_t* mask, double* p,
+                          double* hn, double* hun, double* hwn, uint8_t* mask, double* p, int par,
                           hipStream_t s) {
   hipLaunchKernelGGL((k_step1d<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn, hun, hwn,
-                     mask, p);
+                     mask, p, par);
 }
 void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
-                   double* hun, double* hwn, uint8_t* mask, double* p, hipStream_t s) {
+                   double* hun, double* hwn, uint8_t* mask, double* p, int par, hipStream_t s) {
   if (P.tile == 128)
-    launch_step_t<128, 128>(P, h, hu, hw, hn, hun, hwn, mask, p, s);
+    launch_step_t<128, 128>(P, h, hu, hw, hn, hun, hwn, mask, p, par, s);
   else if (P.tile == 256)
-    launch_step_t<256, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, s);
+    launch_step_t<256, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, par, s);
   else
-    launch_step_t<512, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, s);
+    launch_step_t<512, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, par, s);
 }
-constexpr int FIN_INLINE_MAX = 2048;  // largest grid that ends the step with a counter
-
 template <int T, int NT>
 static void launch_apply_t(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
-                           int fin, hipStream_t s) {
+                           int par, hipStream_t s) {
   if (2 * P.ntiles <= L1MAX)
     hipLaunchKernelGGL((k_apply1d<T, NT, true>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun, hwn,
-                       p, fin);
+                       p, par);
   else
     hipLaunchKernelGGL((k_apply1d<T, NT, false>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun,
-                       hwn, p, fin);
+                       hwn, p, par);
 }
 void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
-                    int advance, hipStream_t s) {
-  const int fin = !advance ? 0 : (P.ntiles <= FIN_INLINE_MAX ? 1 : 2);
+                    int par, hipStream_t s) {
   if (P.tile == 128)
-    launch_apply_t<128, 128>(P, mask, hun, hwn, p, fin, s);
+    launch_apply_t<128, 128>(P, mask, hun, hwn, p, par, s);
   else if (P.tile == 256)
-    launch_apply_t<256, 256>(P, mask, hun, hwn, p, fin, s);
+    launch_apply_t<256, 256>(P, mask, hun, hwn, p, par, s);
   else
-    launch_apply_t<512, 256>(P, mask, hun, hwn, p, fin, s);
-  if (fin == 2) hipLaunchKernelGGL(k_finish1d, dim3(1), dim3(256), 0, s, P);
+    launch_apply_t<512, 256>(P, mask, hun, hwn, p, par, s);
+}
+void launch_run_end(const K1D& P, int last_par, hipStream_t s) {
+  hipLaunchKernelGGL(k_run_end, dim3(1), dim3(256), 0, s, P, last_par);
 }
 bool level1_local(const K1D& P) { return 2 * P.ntiles <= L1MAX; }
 int fused_max_enlarge() { return EMAXF; }
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_smax_clear, dim3(1), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_speed1d, dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw);
 }
 

@@ -185,13 +185,13 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   P.ch = cv.take<Chan>(nch);
   P.tiles = cv.take<int2>(ntiles);
   P.first_tile = cv.take<int>(nch);
-  P.t = cv.take<double>(nch);
+  P.t = cv.take<double>(2 * (size_t)nch);
   P.dt = cv.take<double>(nch);
   P.smax = cv.take<unsigned long long>(2 * (size_t)nch);
   x->stage_t = cv.take<double>(nch);
   x->stage_dt = cv.take<double>(nch);
   x->status = cv.take<int>(1);
-  x->step = cv.take<int>(1);
+  x->step = cv.take<int>(2);
   x->n_act = cv.take<int>(1);
   x->conv = cv.take<int>(1);
   x->iters = cv.take<int>(1);
@@ -200,8 +200,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   int* nbuf64 = cv.take<int>(TRI_MAX_LEVELS);
   int* nbuf32 = cv.take<int>(TRI_MAX_LEVELS);
   int* nbuf1 = cv.take<int>(TRI_MAX_LEVELS);
-  P.done = cv.take<int>(1);
-  P.n_acc = cv.take<int>(1);
+  P.n_acc = cv.take<int>(2);
   x->n1 = cv.take<int>(1);
   if (c->dim == 1) {
     P.tile_cnt = cv.take<int>(ntiles);
@@ -278,12 +277,12 @@ void solve1d(swe_nh_ctx* c, hipStream_t s, int with_residual) {
 // fused FP64 step from (h, hu, hw) into (hn, hun, hwn)
 void enqueue_fused1d(swe_nh_ctx* c, hipStream_t s, const double* h, const double* hu,
                      const double* hw, double* hn, double* hun, double* hwn, double* p,
-                     uint8_t* mask) {
+                     uint8_t* mask, int par) {
   K1D& P = c->k1;
   uint8_t* M = mask ? mask : c->mask_ws;
-  launch_step1d(P, h, hu, hw, hn, hun, hwn, M, p, s);
+  launch_step1d(P, h, hu, hw, hn, hun, hwn, M, p, par, s);
   if (!level1_local(P)) launch_tri_solve(c->T1, c->n1, nullptr, s);
-  launch_apply1d(P, M, hun, hwn, p, 1, s);
+  launch_apply1d(P, M, hun, hwn, p, par, s);
 }
 
 void enqueue_step1d(swe_nh_ctx* c, hipStream_t s, double* h, double* hu, double* hw, double* p,
@@ -445,14 +444,14 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   INIT_COPY(P.dt, zeros.data(), sizeof(double) * c->nch);
   INIT_COPY(P.smax, zu.data(), sizeof(unsigned long long) * c->nch);
   INIT_COPY(P.smax + c->nch, zu.data(), sizeof(unsigned long long) * c->nch);
-  INIT_COPY(P.done, zi, sizeof(int));
-  INIT_COPY(P.n_acc, zi, sizeof(int));
+  INIT_COPY(P.n_acc, zi, 2 * sizeof(int));
+  INIT_COPY(P.t + c->nch, zeros.data(), sizeof(double) * c->nch);
   if (P.fused) {
     INIT_COPY(c->n1, &n1, sizeof(int));
     INIT_COPY(c->T1.n, zi, sizeof(int) * TRI_MAX_LEVELS);
   }
   INIT_COPY(c->status, zi, sizeof(int));
-  INIT_COPY(c->step, zi, sizeof(int));
+  INIT_COPY(c->step, zi, 2 * sizeof(int));
   INIT_COPY(c->n_act, zi, sizeof(int));
   INIT_COPY(c->conv, zi, sizeof(int));
   INIT_COPY(c->iters, zi, sizeof(int));
@@ -515,19 +514,19 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
     if (fused) {
       // even steps: caller arrays -> workspace; odd steps: back
       rc = capture_graph(c, [&](hipStream_t s) {
-        enqueue_fused1d(c, s, h, hu, hw, c->ht, c->mt, c->kt, p, mask);
+        enqueue_fused1d(c, s, h, hu, hw, c->ht, c->mt, c->kt, p, mask, 0);
       }, &c->gexec);
       if (rc == SWE_NH_OK)
         rc = capture_graph(c, [&](hipStream_t s) {
-          enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask);
+          enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask, 1);
         }, &c->gexec2);
       // GSTEPS (even) steps per launch: the host's per-launch cost is paid
       // once for all of them; starts and ends in the caller's arrays
       if (rc == SWE_NH_OK)
         rc = capture_graph(c, [&](hipStream_t s) {
           for (int k = 0; k < GSTEPS; k += 2) {
-            enqueue_fused1d(c, s, h, hu, hw, c->ht, c->mt, c->kt, p, mask);
-            enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask);
+            enqueue_fused1d(c, s, h, hu, hw, c->ht, c->mt, c->kt, p, mask, 0);
+            enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask, 1);
           }
         }, &c->gexecN);
     } else {
@@ -558,10 +557,13 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
     for (; i + GSTEPS <= nsteps; i += GSTEPS) HIPCHK(c, hipGraphLaunch(c->gexecN, c->stream));
   for (; i < nsteps; i++)
     HIPCHK(c, hipGraphLaunch((fused && (i & 1)) ? c->gexec2 : c->gexec, c->stream));
-  if (fused && (nsteps & 1)) {  // the last step wrote the workspace copy
-    launch_copy(c->ht, h, c->ncells, c->stream);
-    launch_copy(c->mt, hu, c->ncells, c->stream);
-    launch_copy(c->kt, hw, c->ncells, c->stream);
+  if (fused && nsteps > 0) {
+    if (nsteps & 1) {  // the last step wrote the workspace copy
+      launch_copy(c->ht, h, c->ncells, c->stream);
+      launch_copy(c->mt, hu, c->ncells, c->stream);
+      launch_copy(c->kt, hw, c->ncells, c->stream);
+    }
+    launch_run_end(c->k1, nsteps & 1, c->stream);
     int rc = after_launch(c);
     if (rc) return rc;
   }
@@ -767,7 +769,7 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
         // the caller's state; nothing advances.
         double *s0 = c->T64.dg[0], *s1 = c->T64.up[0], *s2 = c->T64.rh[0], *s3 = c->T64.x[0];
         switch (stage) {
-          case 0: launch_step1d(P, h, hu, hw, s0, s1, s2, M, s3, s); break;
+          case 0: launch_step1d(P, h, hu, hw, s0, s1, s2, M, s3, 0, s); break;
           case 1: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
           case 2: launch_apply1d(P, M, s1, s2, s3, 0, s); break;
           default: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s);

@@ -22,11 +22,11 @@ struct K1D {
   double dx, g, rho, cfl, dt_fixed, k_nh;
   int crit, enlarge, first_global, ntiles;
   int tile;                // cells per 1D tile: 128, 256 or 512
-  double* t;               // [batch] time at the start of the step
+  double* t;               // [batch] time at the start of the step (fused: [2][batch] by parity)
   double* dt;              // [batch] step of the current step
   unsigned long long* smax;  // [batch] bit pattern of the max wave speed
   int* status;             // ST_* bits
-  int* step;               // steps taken
+  int* step;               // steps taken (fused: [2] by parity)
   int* tile_cnt;           // [ntiles]
   int* tile_off;           // [ntiles]
   int* n_act;              // marked cells
@@ -35,8 +35,7 @@ struct K1D {
   // tile-fused step (FP64): smax is then [2][batch], selected by step parity
   int fused;
   int nch;
-  int* done;               // blocks of the projection kernel finished this step
-  int* n_acc;              // marked cells counted during the step (published at its end)
+  int* n_acc;              // [2] marked cells counted during a step, by step parity
   double* zw;              // [ZW_N][ntiles * tile] per marked row, tile-padded
   double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
   const double* x1;        // level-1 solution
@@ -77,9 +76,10 @@ void launch_advance(const K1D& P, int nch, hipStream_t s);
 // state (h, hu, hw) into a second state buffer (hn, hun, hwn), and the
 // projection from the level-1 solution (plus next-step speed and advance)
 void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
-                   double* hun, double* hwn, uint8_t* mask, double* p, hipStream_t s);
+                   double* hun, double* hwn, uint8_t* mask, double* p, int par, hipStream_t s);
 void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
-                    int advance, hipStream_t s);
+                    int par, hipStream_t s);
+void launch_run_end(const K1D& P, int last_par, hipStream_t s);
 bool level1_local(const K1D& P);  // the projection kernel solves the level-1 system itself
 int fused_max_enlarge();
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
