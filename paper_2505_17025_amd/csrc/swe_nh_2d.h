@@ -16,7 +16,8 @@ constexpr int PCG_NVEC = 10;  // inner vectors of the 2D solver
 
 struct Ctx2D {
   int nx = 0, ny = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
-  int grid_pcg = 0;          // blocks of the persistent PCG kernel
+  int grid_pcg = 0;          // blocks of the persistent solver (Chronopoulos-Gear form)
+  int grid_pipe = 0;         // blocks of the persistent solver (pipelined form)
   // predictor output
   double *ht = nullptr, *mt = nullptr, *nt = nullptr, *kt = nullptr;
   uint8_t* mask_ws = nullptr;

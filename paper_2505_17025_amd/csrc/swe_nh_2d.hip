@@ -815,6 +815,7 @@ struct PcgArgs {
   const R *dgR, *ceR, *cnR;
   R *r, *u, *w, *z, *q, *s, *p, *e;
   R* m[2];          // M^-1 w, double-buffered by pass parity (pipelined form)
+  int pipe_blocks;  // grid of the pipelined form (decides which form runs)
   unsigned* tflag;  // per tile: last neighbour-sync stamp passed (Chronopoulos-Gear form)
   double* part;
   Bar bar;
@@ -876,7 +877,9 @@ __device__ __forceinline__ void for_cells(int nx, int ny, int tiles_x, const int
 // red, black, ..., red (GS_HALF of them, a palindrome, so the preconditioner
 // is symmetric), over-relaxation GS_OMEGA.  Thread t owns the tile cells 2t
 // and 2t + 1 (row-major), one of each colour.
-constexpr int GS_HALF = 7;
+constexpr int GS_HALF = 9;
+constexpr int PCG_K = 1;  // tiles per block of the pipelined solver (2 halves the barrier
+                          // participants but doubles the registers: slower here)
 constexpr double GS_OMEGA = 1.5;
 
 template <typename R>
@@ -1188,50 +1191,95 @@ __device__ void pcg_cg(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2])
 }
 
 
+// u = M^-1 r on the K tiles of a block at once (the sweeps of all K tiles
+// share the block's barriers); slot k of zt holds tile k
+template <typename R, int K>
+__device__ void tile_precond_k(const TileCells<R> (&C)[K], const TileOp<R> (&T)[K],
+                               const R (&rc)[K][2], R (*z)[TY2][TX2]) {
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int q = 0; q < 2; q++) z[k][C[k].lj[q]][C[k].li[q]] = R(0);
+  __syncthreads();
+  const R om = (R)GS_OMEGA;
+  for (int hs = 0; hs < GS_HALF; hs++) {
+    const int colour = hs & 1;  // 0: red ((i + j) even) first and last
+#pragma unroll
+    for (int k = 0; k < K; k++)
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        const int li = C[k].li[q], lj = C[k].lj[q];
+        const uint8_t f = C[k].nb[q];
+        if (((li + lj) & 1) != colour || !(f & NB_SELF)) continue;
+        R a = rc[k][q];
+        if (f & NB_E) a -= T[k].cE[q] * z[k][lj][li + 1];
+        if (f & NB_W) a -= T[k].cW[q] * z[k][lj][li - 1];
+        if (f & NB_N) a -= T[k].cN[q] * z[k][lj + 1][li];
+        if (f & NB_S) a -= T[k].cS[q] * z[k][lj - 1][li];
+        z[k][lj][li] = (R(1) - om) * z[k][lj][li] + om * a / T[k].dg[q];
+      }
+    __syncthreads();
+  }
+}
+
 // Preconditioned CG in the pipelined form of Ghysels and Vanroose (2014)
-// for blocks that own one tile each: per iteration one pass and one grid
-// barrier, which both completes the reduction of (r,u), (w,u), (r,r) and
-// publishes m = M^-1 w (tile-local) for the neighbours' n = A m of the next
-// pass (m double-buffered by pass parity).  The vectors stay in registers and
-// the tile's m stays in LDS for the whole solve.
-template <typename R>
-__device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2]) {
+// for blocks that own up to K tiles each: per iteration one pass and one
+// grid barrier, which both completes the reduction of (r,u), (w,u), (r,r)
+// and publishes m = M^-1 w (tile-local) for the neighbours' n = A m of the
+// next pass (m double-buffered by pass parity).  The vectors stay in
+// registers and the tiles' m stays in LDS for the whole solve.
+template <typename R, int K>
+__device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TY2][TX2]) {
   const int nx = A.nx;
-  const TileCells<R> C = tile_cells(A, A.tile_list[S.t0]);
-  const FullOp<R> F = full_op(A, C);
-  const TileOp<R> T = restrict_op(F, C);
-  Cells<R> X{};
-  unsigned k = 0;  // grid barriers passed
+  TileCells<R> C[K];
+  FullOp<R> F[K];
+  TileOp<R> T[K];
+  Cells<R> X[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const bool has = S.t0 + k < S.t1;
+    C[k] = tile_cells(A, has ? A.tile_list[S.t0 + k] : A.tile_list[S.t0]);
+    if (!has) C[k].nb[0] = C[k].nb[1] = 0;  // an empty slot: no cells of the system
+    F[k] = full_op(A, C[k]);
+    T[k] = restrict_op(F[k], C[k]);
+    X[k] = Cells<R>{};
+  }
+  unsigned bk = 0;  // grid barriers passed
   double bb = 0.0, rr = 0.0;
   int total = 0, sweep = 0;
   for (;;) {
     // FP64 residual of the current solution -> r_0 (precision R), u_0 = M^-1 r_0
     {
       double v[2] = {0.0, 0.0};
-      R rc[2];
+      R rc[K][2];
 #pragma unroll
-      for (int q = 0; q < 2; q++) {
-        rc[q] = R(0);
-        if (!(F.nf[q] & NB_SELF)) continue;
-        const int64_t o = C.o[q];
-        const double rv = A.b[o] - apply5<double, double>(A.dg, A.ce, A.cn, A.x, F.nf[q], o, nx);
-        rc[q] = (R)rv;
-        X.r[q] = rc[q];
-        X.e[q] = R(0);
-        v[0] += rv * rv;
-        if (sweep == 0) v[1] += A.b[o] * A.b[o];
-      }
-      tile_precond(C, T, rc, zt);
+      for (int k = 0; k < K; k++)
 #pragma unroll
-      for (int q = 0; q < 2; q++) {
-        if (!(F.nf[q] & NB_SELF)) continue;
-        X.u[q] = zt[C.lj[q]][C.li[q]];
-        A.u[C.o[q]] = X.u[q];
-      }
-      block_partials<2>(v, part_buf(A.part, k + 1), S.vb, G);
-      if (!grid_sync(A.bar, ++k, G)) return;
+        for (int q = 0; q < 2; q++) {
+          rc[k][q] = R(0);
+          if (!(F[k].nf[q] & NB_SELF)) continue;
+          const int64_t o = C[k].o[q];
+          const double rv =
+              A.b[o] - apply5<double, double>(A.dg, A.ce, A.cn, A.x, F[k].nf[q], o, nx);
+          rc[k][q] = (R)rv;
+          X[k].r[q] = rc[k][q];
+          X[k].e[q] = R(0);
+          v[0] += rv * rv;
+          if (sweep == 0) v[1] += A.b[o] * A.b[o];
+        }
+      tile_precond_k<R, K>(C, T, rc, zt);
+#pragma unroll
+      for (int k = 0; k < K; k++)
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+          if (!(F[k].nf[q] & NB_SELF)) continue;
+          X[k].u[q] = zt[k][C[k].lj[q]][C[k].li[q]];
+          A.u[C[k].o[q]] = X[k].u[q];
+        }
+      block_partials<2>(v, part_buf(A.part, bk + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++bk, G)) return;
       double tt[2];
-      grid_totals<2>(part_buf(A.part, k), G, tt);
+      grid_totals<2>(part_buf(A.part, bk), G, tt);
       rr = tt[0];
       if (sweep == 0) bb = tt[1];
     }
@@ -1257,49 +1305,50 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
       // pass j: (j >= 1) n = A m_{j-1} and the recurrences with alpha_{j-1},
       // beta_{j-1}; (j == 0) w_0 = A u_0.  Then the partial sums of pass j
       // and m_j = M^-1 w_j, published for the neighbours.  zt holds u_0
-      // (j == 0) or m_{j-1} of the tile on entry.
+      // (j == 0) or m_{j-1} of the tiles on entry.
       const R al = (R)alpha, bt = (R)beta;
       const R* mprev = A.m[(j + 1) & 1];
       R* mnext = A.m[j & 1];
       double v[3] = {0.0, 0.0, 0.0};  // (r,u), (w,u), (r,r)
+      R wc[K][2];
 #pragma unroll
-      for (int q = 0; q < 2; q++) {
-        if (!(F.nf[q] & NB_SELF)) continue;
-        if (j == 0) {
-          X.w[q] = apply_at(F, C, q, A.u, zt, true, nx);
-        } else {
-          const R n = apply_at(F, C, q, mprev, zt, true, nx);
-          const R m = zt[C.lj[q]][C.li[q]];
-          const bool first = j == 1;
-          X.z[q] = first ? n : fma(bt, X.z[q], n);
-          X.q[q] = first ? m : fma(bt, X.q[q], m);
-          X.s[q] = first ? X.w[q] : fma(bt, X.s[q], X.w[q]);
-          X.p[q] = first ? X.u[q] : fma(bt, X.p[q], X.u[q]);
-          X.e[q] = fma(al, X.p[q], X.e[q]);
-          X.r[q] = fma(-al, X.s[q], X.r[q]);
-          X.u[q] = fma(-al, X.q[q], X.u[q]);
-          X.w[q] = fma(-al, X.z[q], X.w[q]);
+      for (int k = 0; k < K; k++)
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+          wc[k][q] = R(0);
+          if (!(F[k].nf[q] & NB_SELF)) continue;
+          Cells<R>& Y = X[k];
+          if (j == 0) {
+            Y.w[q] = apply_at(F[k], C[k], q, A.u, zt[k], true, nx);
+          } else {
+            const R n = apply_at(F[k], C[k], q, mprev, zt[k], true, nx);
+            const R m = zt[k][C[k].lj[q]][C[k].li[q]];
+            const bool first = j == 1;
+            Y.z[q] = first ? n : fma(bt, Y.z[q], n);
+            Y.q[q] = first ? m : fma(bt, Y.q[q], m);
+            Y.s[q] = first ? Y.w[q] : fma(bt, Y.s[q], Y.w[q]);
+            Y.p[q] = first ? Y.u[q] : fma(bt, Y.p[q], Y.u[q]);
+            Y.e[q] = fma(al, Y.p[q], Y.e[q]);
+            Y.r[q] = fma(-al, Y.s[q], Y.r[q]);
+            Y.u[q] = fma(-al, Y.q[q], Y.u[q]);
+            Y.w[q] = fma(-al, Y.z[q], Y.w[q]);
+          }
+          wc[k][q] = Y.w[q];
+          v[0] += (double)Y.r[q] * (double)Y.u[q];
+          v[1] += (double)Y.w[q] * (double)Y.u[q];
+          v[2] += (double)Y.r[q] * (double)Y.r[q];
         }
-      }
-      R wc[2];
+      __syncthreads();  // the tiles' LDS values are read before the sweeps overwrite them
+      tile_precond_k<R, K>(C, T, wc, zt);
 #pragma unroll
-      for (int q = 0; q < 2; q++) {
-        wc[q] = R(0);
-        if (!(F.nf[q] & NB_SELF)) continue;
-        wc[q] = X.w[q];
-        v[0] += (double)X.r[q] * (double)X.u[q];
-        v[1] += (double)X.w[q] * (double)X.u[q];
-        v[2] += (double)X.r[q] * (double)X.r[q];
-      }
-      __syncthreads();  // the tile's LDS values are read before the sweeps overwrite them
-      tile_precond(C, T, wc, zt);
+      for (int k = 0; k < K; k++)
 #pragma unroll
-      for (int q = 0; q < 2; q++)
-        if (F.nf[q] & NB_SELF) mnext[C.o[q]] = zt[C.lj[q]][C.li[q]];
-      block_partials<3>(v, part_buf(A.part, k + 1), S.vb, G);
-      if (!grid_sync(A.bar, ++k, G)) return;
+        for (int q = 0; q < 2; q++)
+          if (F[k].nf[q] & NB_SELF) mnext[C[k].o[q]] = zt[k][C[k].lj[q]][C[k].li[q]];
+      block_partials<3>(v, part_buf(A.part, bk + 1), S.vb, G);
+      if (!grid_sync(A.bar, ++bk, G)) return;
       double tt[3];
-      grid_totals<3>(part_buf(A.part, k), G, tt);
+      grid_totals<3>(part_buf(A.part, bk), G, tt);
       const double gn = tt[0], dn = tt[1], rn = tt[2];
       if (j > 0) {
         total++;
@@ -1319,32 +1368,42 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
     }
     // x += e (FP64)
 #pragma unroll
-    for (int q = 0; q < 2; q++)
-      if (F.nf[q] & NB_SELF) A.x[C.o[q]] += (double)X.e[q];
-    if (!grid_sync(A.bar, ++k, G)) return;
+    for (int k = 0; k < K; k++)
+#pragma unroll
+      for (int q = 0; q < 2; q++)
+        if (F[k].nf[q] & NB_SELF) A.x[C[k].o[q]] += (double)X[k].e[q];
+    if (!grid_sync(A.bar, ++bk, G)) return;
     sweep++;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
 }
 
 // Persistent preconditioned CG (M^-1: the tile-block symmetric red-black SOR
-// above): pipelined when every participating block owns exactly one active
-// tile, Chronopoulos-Gear with a neighbour-tile sync otherwise.  The inner
-// solve runs in precision R; the outer loop refines the FP64 solution with
-// FP64 residuals until ||b - A x|| <= tol ||b||.
+// above), two kernels launched one after the other of which exactly one
+// works: pipelined when the active tiles fit PCG_K per block of its grid,
+// Chronopoulos-Gear with a neighbour-tile sync otherwise (separate kernels,
+// so that each gets its own register budget and grid).  The inner solve runs
+// in precision R; the outer loop refines the FP64 solution with FP64
+// residuals until ||b - A x|| <= tol ||b||.
 template <typename R>
-__global__ void __launch_bounds__(NT2) k_pcg2d(PcgArgs<R> A) {
-  __shared__ R zt[TY2][TX2];
+__global__ void __launch_bounds__(NT2) k_pcg2d_pipe(PcgArgs<R> A) {
+  __shared__ R zt[PCG_K][TY2][TX2];
   const int nlist = *A.n_list;
-  const int G = max(1, min((int)gridDim.x, nlist));
+  if (nlist < 1 || nlist > PCG_K * A.pipe_blocks) return;  // the other form's case
+  const int G = (nlist + PCG_K - 1) / PCG_K;
   if ((int)blockIdx.x >= G) return;
-  const Share S = share_of(G, nlist);
-  if (nlist >= 1 && nlist <= (int)gridDim.x)
-    pcg_pipelined(A, S, G, zt);
-  else
-    pcg_cg(A, S, G, zt);
+  pcg_pipelined<R, PCG_K>(A, share_of(G, nlist), G, zt);
 }
 
+template <typename R>
+__global__ void __launch_bounds__(NT2) k_pcg2d_cg(PcgArgs<R> A) {
+  __shared__ R zt[TY2][TX2];
+  const int nlist = *A.n_list;
+  if (nlist >= 1 && nlist <= PCG_K * A.pipe_blocks) return;  // the pipelined form's case
+  const int G = max(1, min((int)gridDim.x, nlist));
+  if ((int)blockIdx.x >= G) return;
+  pcg_cg(A, share_of(G, nlist), G, zt);
+}
 
 __global__ void k_bar_reset(unsigned long long* count, unsigned* tflag, int ntiles) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0ull;
@@ -1452,6 +1511,7 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.rel = x->rel;
   A.tol = c->tol;
   A.max_iter = c->max_iter;
+  A.pipe_blocks = x->grid_pipe;
   return A;
 }
 
@@ -1499,10 +1559,15 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
   hipLaunchKernelGGL(k_bar_reset, dim3((x->ntiles + 255) / 256), dim3(256), 0, s, x->bar, x->tflag,
                      x->ntiles);
-  if (c->precision == 1)
-    hipLaunchKernelGGL(k_pcg2d<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, pcg_args32(c, x));
-  else
-    hipLaunchKernelGGL(k_pcg2d<double>, dim3(x->grid_pcg), dim3(NT2), 0, s, pcg_args64(c, x));
+  if (c->precision == 1) {
+    const PcgArgs<float> A = pcg_args32(c, x);
+    hipLaunchKernelGGL(k_pcg2d_pipe<float>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
+    hipLaunchKernelGGL(k_pcg2d_cg<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, A);
+  } else {
+    const PcgArgs<double> A = pcg_args64(c, x);
+    hipLaunchKernelGGL(k_pcg2d_pipe<double>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
+    hipLaunchKernelGGL(k_pcg2d_cg<double>, dim3(x->grid_pcg), dim3(NT2), 0, s, A);
+  }
 }
 
 }  // namespace
@@ -1575,11 +1640,19 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return SWE_NH_EHIP;
   hipError_t e = c->precision == 1
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg2d<float>, NT2, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg2d<double>, NT2, 0);
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg2d_cg<float>, NT2, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg2d_cg<double>, NT2, 0);
   if (e != hipSuccess || per_cu < 1) return SWE_NH_EHIP;
   const int cap = cus * per_cu;
   if (x->grid_pcg > cap) x->grid_pcg = cap;
+  int per_cu_p = 0;
+  e = c->precision == 1
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_p, k_pcg2d_pipe<float>, NT2, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_p, k_pcg2d_pipe<double>, NT2, 0);
+  if (e != hipSuccess || per_cu_p < 1) return SWE_NH_EHIP;
+  // the pipelined grid: enough blocks for every active tile at PCG_K per block
+  // when possible, never more than fit at once
+  x->grid_pipe = std::min(cus * per_cu_p, std::min(PCG_GMAX, (x->ntiles + PCG_K - 1) / PCG_K));
   int zi[2] = {0, 0};
   if (hipMemcpy(x->n_tiles_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   if (hipMemcpy(x->n_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
