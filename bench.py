@@ -235,7 +235,8 @@ def main():
                              "bytes_per_launch": ncell * 56.0, "stage_us": res["stage_us"]},
                 "cpu_baseline": None,
                 "extra": {"fp64_cell_steps_per_s": r64["cell_steps_per_s"],
-                          "fp64_roofline": step_roofline(ncell, r64s, None),
+                          "fp64_roofline": step_roofline(ncell, r64s, "step1d_ensemble512_pmc.txt"
+                                                         if tile == 256 else None),
                           "global_cell_steps_per_s": g["cell_steps_per_s"],
                           "n_active_last": res["n_active_last"]}}
         print(json.dumps(line), flush=True)
@@ -377,8 +378,16 @@ def run_2d(B, torch, S, steps, warmup):
                        "cells": c.nx * c.ny},
             "roofline": {"kernel": "k_pred2d", "bound": "hbm", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": None, "avg_launch_us": pred_us,
-                         "bytes_per_launch": c.nx * c.ny * 72.0},
+                         "traffic": pmc_traffic("pred2d_shelf2048_pmc.txt",
+                                                "paper_2505_17025_amd/csrc/swe_nh_2d.hip"),
+                         "avg_launch_us": pred_us, "bytes_per_launch": c.nx * c.ny * 72.0,
+                         "note": "the step's time is mostly the persistent solver, bound by "
+                                 "grid-barrier latency (see solve_share); the predictor is the "
+                                 "HBM-bound kernel of the step",
+                         "solve_share": 1.0 - (res["stage_us"]["predictor"] +
+                                               res["stage_us"]["mask"] +
+                                               res["stage_us"]["projection"]) /
+                                        (1e3 * res["ms_per_step"])},
             "cpu_baseline": None, "extra": out}
 
 

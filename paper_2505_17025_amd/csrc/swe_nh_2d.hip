@@ -134,9 +134,10 @@ __device__ __forceinline__ Flux2 rusanov2d(double g, double eL, double mL, doubl
   Flux2 f;
   const double hL = eL + dL, hR = eR + dR;
   f.dry = !(hL > 0.0) || !(hR > 0.0);
-  const double uL = mL / hL, uR = mR / hR;
-  const double vL = aL / hL, vR = aR / hR;
-  const double wL = bL / hL, wR = bR / hR;
+  const double rL = 1.0 / hL, rR = 1.0 / hR;
+  const double uL = mL * rL, uR = mR * rR;
+  const double vL = aL * rL, vR = aR * rR;
+  const double wL = bL * rL, wR = bR * rR;
   const double db = fmin(dL, dR);
   const double sL = fmax(0.0, eL + db), sR = fmax(0.0, eR + db);
   const double lam = fmax(fabs(uL) + sqrt(g * sL), fabs(uR) + sqrt(g * sR));
