@@ -239,11 +239,16 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double
 /* Measurement: launch one stage kernel of the step nreps times back to back
  * on the context's stream, with the launch configuration swe_nh_step uses,
  * between two HIP events, and return the mean time per launch in
- * microseconds (synchronises).  stage: 0 predictor, 1 criterion/mask,
- * 2 elliptic solve (all solver launches of one solve), 3 projection.  The
- * state arrays must hold a valid state of the context (for instance after
- * swe_nh_step); stage 0 uses the time step of the last step and does not
- * modify them (its output goes to the workspace).  Stages 1-3 reuse the
+ * microseconds (synchronises).  The state arrays must hold a valid state of
+ * the context (for instance after swe_nh_step).
+ * 1D with precision 0 and enlarge <= 8 (the fused step): stage 0 the fused
+ * step kernel (predictor, criterion, assembly, tile reduction), 1 the
+ * separate level-1 solve, 2 the projection kernel, 3 the stand-alone
+ * predictor; outputs go to workspace scratch, the caller's arrays and the
+ * time are not modified.
+ * Otherwise: stage 0 predictor, 1 criterion/mask, 2 elliptic solve (all
+ * solver launches of one solve), 3 projection; stage 0 uses the time step of
+ * the last step and writes only the workspace, stages 1-3 reuse the
  * workspace of the last step and may overwrite hu, hw (and hv) and p on the
  * marked cells with the same values. */
 int swe_nh_time_stage(swe_nh_ctx* ctx, int32_t stage, int32_t nreps, double* h, double* hu,
