@@ -41,19 +41,23 @@ def parse():
     ap.add_argument("--workload", default="slide1d",
                     choices=["slide1d", "ensemble1d", "shelf2d", "learned2d", "copycal"])
     ap.add_argument("--tile1d", type=int, default=0,
-                    help="1D tile (128, 256 or 512); 0: pick with the autotuner")
+                    help="1D cells per tile (32..512); 0: pick with the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     return ap.parse_args()
 
 
-def pmc_traffic(kernel_file, src_file):
+def pmc_traffic(kernel_file, src_file, tile=None):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, or None
-    when the kernel source changed since they were taken"""
+    when the kernel source (or the 1D tile length) changed since they were taken"""
     path = os.path.join(ROOT, "profiles", kernel_file)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
+    if tile is not None:
+        t = re.search(r"tile1d:\s*(\d+)", txt)
+        if not t or int(t.group(1)) != int(tile):
+            return None
     m = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
     src = open(os.path.join(ROOT, src_file), "rb").read()
     if not m or m.group(1) != hashlib.sha256(src).hexdigest():
@@ -121,14 +125,14 @@ def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000):
 STEP1D_BYTES = 65.0  # per cell: read h, hu, hw, d_s; write h, hu, hw, p (FP64) and the mask byte
 
 
-def step_roofline(ncell, stage_us, pmc_file):
+def step_roofline(ncell, stage_us, pmc_file, tile):
     """roofline of the fused 1D step kernel (the dominant kernel of the FP64 1D path)"""
     us = stage_us["step_kernel"]
     per_launch = ncell * STEP1D_BYTES
     achieved = per_launch / (us * 1e-6) / 1e9
     return {"kernel": "k_step1d", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": pmc_traffic(pmc_file, "paper_2505_17025_amd/csrc/swe_nh_1d.hip")
+            "traffic": pmc_traffic(pmc_file, "paper_2505_17025_amd/csrc/swe_nh_1d.hip", tile)
             if pmc_file else None,
             "avg_launch_us": us, "bytes_per_launch": per_launch,
             "bytes_per_cell": STEP1D_BYTES, "stage_us": stage_us}
@@ -185,7 +189,7 @@ def main():
                      "paper_context": "paper: adaptive saves more than 50% of the global time "
                                       "(t_local/t_global 0.07-0.40 with |eta/d| + 1-cell "
                                       "enlargement), hardware not stated"}
-        roof = step_roofline(case.n, res["stage_us"], "step1d_slide32768_pmc.txt")
+        roof = step_roofline(case.n, res["stage_us"], "step1d_slide32768_pmc.txt", tile)
         cpu = None
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
@@ -235,8 +239,8 @@ def main():
                              "bytes_per_launch": ncell * 56.0, "stage_us": res["stage_us"]},
                 "cpu_baseline": None,
                 "extra": {"fp64_cell_steps_per_s": r64["cell_steps_per_s"],
-                          "fp64_roofline": step_roofline(ncell, r64s, "step1d_ensemble512_pmc.txt"
-                                                         if tile == 256 else None),
+                          "fp64_roofline": step_roofline(ncell, r64s, "step1d_ensemble512_pmc.txt",
+                                                         tile),
                           "global_cell_steps_per_s": g["cell_steps_per_s"],
                           "n_active_last": res["n_active_last"]}}
         print(json.dumps(line), flush=True)

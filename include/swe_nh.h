@@ -106,8 +106,12 @@ typedef struct {
   int32_t max_iter;         /* PCG iterations (2D) or refinement sweeps (precision 1) */
   int32_t warm;             /* 2D initial guess: 0 zero, 1 previous p (the p array on
                                entry), 2 the warm-start network */
-  int32_t tile1d;           /* 1D cells per block of the stencil kernels: 128, 256, 512,
-                               or 0 for the built-in choice */
+  int32_t tile1d;           /* 1D cells per block of the stencil kernels, 32..512, or 0
+                               for the built-in choice.  The kernels' LDS windows come
+                               in capacities of 128, 256 and 512 cells; the smallest
+                               that holds the tile is used.  The FP64 fused step's
+                               window adds 6 + enlarge cells on each side, so a tile of
+                               capacity - 2 (6 + enlarge) cells fills whole wavefronts */
   const double* depth_static;  /* device [cells]: static depth d_s */
   const swe_nh_body* bodies;   /* host [batch] (1D) or [1] (2D) */
 } swe_nh_config;

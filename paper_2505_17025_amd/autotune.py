@@ -1,12 +1,15 @@
 """Launch-shape autotuner.
 
-The 1D stencil, criterion and compaction kernels work on tiles of 128, 256 or
-512 cells; which one is fastest depends on the packed length and on how the
-tiles spread over the 256 compute units (short channels favour small tiles,
-long ensembles favour large ones).  `tune_1d` times whole steps for every
+The 1D stencil, criterion and compaction kernels work on tiles whose LDS
+windows hold 128, 256 or 512 cells; which tile is fastest depends on the packed
+length and on how the tiles spread over the 256 compute units (short channels
+favour small tiles, long ensembles large ones).  The FP64 fused step widens a
+tile by 6 + e cells on each side (e = enlargement), so for each capacity the
+tile of capacity - 2 (6 + e) cells, whose window fills whole wavefronts, is a
+candidate beside the full capacity.  `tune_1d` times whole steps for every
 candidate on a copy of the caller's state and returns the fastest; results are
-kept per (cells, channels, precision, criterion) in a JSON table so that a
-later run on the same device skips the sweep.
+kept per (cells, channels, precision, criterion, enlargement) in a JSON table
+so that a later run on the same device skips the sweep.
 
 All timing goes through the library's own step entry point; this module only
 picks the knob.
@@ -21,12 +24,25 @@ import torch
 
 from . import swe_nh as B
 
-TILES_1D = (128, 256, 512)
+CAPACITIES_1D = (128, 256, 512)
+FUSED_MAX_ENLARGE = 8  # largest enlargement the fused FP64 step handles
+
+
+def candidates_1d(kw):
+    """tile lengths worth timing for the context options `kw`"""
+    e = int(kw.get("enlarge", 1))
+    fused = int(kw.get("precision", 0)) == 0 and e <= FUSED_MAX_ENLARGE
+    out = []
+    for cap in CAPACITIES_1D:
+        if fused:
+            out.append(cap - 2 * (6 + e))
+        out.append(cap)
+    return tuple(out)
 
 
 def _key(dev_name, cells, batch, kw):
     return (f"{dev_name}|1d|cells={cells}|batch={batch}|prec={kw.get('precision', 0)}"
-            f"|crit={kw.get('crit', 0)}")
+            f"|crit={kw.get('crit', 0)}|e={kw.get('enlarge', 1)}")
 
 
 def _load(path):
@@ -63,10 +79,12 @@ def _time_steps(case, kw, state, t0, nsteps, warmup):
     return el / nsteps
 
 
-def tune_1d(case, kw, state, t0, nsteps=200, warmup=20, table_path=None, candidates=TILES_1D):
+def tune_1d(case, kw, state, t0, nsteps=200, warmup=20, table_path=None, candidates=None):
     """fastest tile1d for `case` with the context options `kw`; `state` is the
     (h, hu, hw) device tensors (copied, never written) and `t0` the start
     time(s).  Returns (tile, {tile: seconds per step})."""
+    if candidates is None:
+        candidates = candidates_1d(kw)
     cells = int(state[0].numel())
     batch = len(case.channels) if hasattr(case, "channels") else 1
     key = _key(torch.cuda.get_device_name(0), cells, batch, kw)

@@ -143,8 +143,8 @@ __device__ __forceinline__ void stage_cell(const PredSmem<T>& S, const double* d
 }
 }  // namespace
 
-// Both Heun stages for a tile of T cells.  Thread t owns the window cells
-// e = 2 + t + NT q of the stage-1 range [2, T + 6): their Q^n and stage-1
+// Both Heun stages for a tile of at most T cells.  Thread t owns the window
+// cells e = 2 + t + NT q of the stage-1 range [2, tile + 6): their Q^n and stage-1
 // operator stay in registers for the final combination on the tile cells.
 template <int T, int NT>
 __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__ h,
@@ -153,15 +153,15 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
                                                double* __restrict__ ht, double* __restrict__ mt,
                                                double* __restrict__ kt, const double* t_in,
                                                const double* dt_in, int dt_from_speed) {
-  constexpr int WIN = T + 2 * HALO;
-  constexpr int R1 = T + 4;                 // stage-1 cells: window [2, T + 6)
+  constexpr int R1 = T + 4;  // stage-1 cells at most: window [2, tile + 6)
   constexpr int Q = (R1 + NT - 1) / NT;
   __shared__ PredSmem<T> S;
   __shared__ int sflags;
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, base = start - HALO;  // window cell e <-> channel cell base+e
-  const int end = min(start + T, n);
+  const int end = min(start + P.tile, n);
+  const int WIN = P.tile + 2 * HALO;  // window of this tile length
   const double t0 = t_in[tl.x];
   double dt;
   if (dt_from_speed) {
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
 
   double Qn[Q][3], L1[Q][3];
   // stage 1: faces [2, WIN - 1), cells [2, WIN - 2)
-  const int lo1 = max(0, start - 2), hi1 = min(n, start + T + 2);
+  const int lo1 = max(0, start - 2), hi1 = min(n, start + P.tile + 2);
   stage_faces<T>(S, S.d0, P.g, 2, WIN - 1, lo1, hi1, base, &flags);
   __syncthreads();
 #pragma unroll
@@ -241,14 +241,14 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
   }
   __syncthreads();
 
-  // stage 2 on the tile cells: faces [HALO, HALO + T + 1)
-  stage_faces<T>(S, S.d1, P.g, HALO, HALO + T + 1, start, end, base, &flags);
+  // stage 2 on the tile cells: faces [HALO, HALO + tile + 1)
+  stage_faces<T>(S, S.d1, P.g, HALO, HALO + P.tile + 1, start, end, base, &flags);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < Q; q++) {
     const int e = 2 + threadIdx.x + NT * q;
     const int i = base + e;
-    if (e < HALO || e >= HALO + T || i >= end) continue;
+    if (e < HALO || e >= HALO + P.tile || i >= end) continue;
     double a, b, k2;
     stage_cell<T>(S, S.d1, P.g, idx, e, a, b, k2);
     const int64_t gi = c.off + i;
@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(256) k_correct1d(K1D P, const double* __restri
 namespace {
 constexpr int EMAXF = 8;          // largest enlargement of the fused step
 constexpr int HMAXF = EMAXF + 2;  // Q~ beyond the tile: criterion stencil + enlargement
-constexpr int L1MAX = 512;        // level-1 rows solved inside the projection kernel
+constexpr int L1MAX = 1024;       // level-1 rows solved inside the projection kernel
 
 // checks one cell of the final state and folds its wave speed into s
 __device__ __forceinline__ void final_state(double g, double hh, double mm, double kk, double& s,
@@ -834,7 +834,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   __shared__ int sflags;
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
-  const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
+  const int n = c.n, start = tl.y, end = min(start + P.tile, n), len = end - start;
   const int step = P.step[par];
   const double dt =
       (P.cfl > 0.0)
@@ -849,7 +849,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
     P.step[par ^ 1] = step + 1;
     P.n_acc[par ^ 1] = 0;  // counts the next step
   }
-  const int ee = P.enlarge, HL = 6 + ee, W = T + 2 * HL;
+  const int ee = P.enlarge, HL = 6 + ee, W = P.tile + 2 * HL;
   const int lo = start - HL;  // window cell w <-> channel cell lo + w
   const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t1);
   const double idx = 1.0 / P.dx;
@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   }
   __syncthreads();
   double Qn[Q][3], L1[Q][3];
-  step_faces(S, S.d0, P.g, 2, W - 1, max(0, start - 2), min(n, start + T + 2), lo, flags);
+  step_faces(S, S.d0, P.g, 2, W - 1, max(0, start - 2), min(n, start + P.tile + 2), lo, flags);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < Q; q++) {
@@ -1145,7 +1145,7 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   __shared__ int wc[NT / 64];
   const int2 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
-  const int n = c.n, start = tl.y, end = min(start + T, n), len = end - start;
+  const int n = c.n, start = tl.y, end = min(start + P.tile, n), len = end - start;
   const double dt = P.dt[tl.x];
   // the speed buffer this step read collects the speed of the step after next
   if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.smax[par * P.nch + tl.x] = 0ull;
@@ -1371,10 +1371,10 @@ void launch_speed1d(const K1D& P, const double* h, const double* hu, const doubl
 void launch_pred1d(const K1D& P, const double* h, const double* hu, const double* hw, double* ht,
                    double* mt, double* kt, const double* t_in, const double* dt_in,
                    int dt_from_speed, hipStream_t s) {
-  if (P.tile == 128)
+  if (P.cap == 128)
     hipLaunchKernelGGL((k_pred1d<128, 128>), dim3(P.ntiles), dim3(128), 0, s, P, h, hu, hw, ht, mt,
                        kt, t_in, dt_in, dt_from_speed);
-  else if (P.tile == 256)
+  else if (P.cap == 256)
     hipLaunchKernelGGL((k_pred1d<256, 256>), dim3(P.ntiles), dim3(256), 0, s, P, h, hu, hw, ht, mt,
                        kt, t_in, dt_in, dt_from_speed);
   else
@@ -1455,9 +1455,9 @@ static void launch_step_t(const K1D& P, const double* h, const double* hu, const
 }
 void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
                    double* hun, double* hwn, uint8_t* mask, double* p, int par, hipStream_t s) {
-  if (P.tile == 128)
+  if (P.cap == 128)
     launch_step_t<128, 128>(P, h, hu, hw, hn, hun, hwn, mask, p, par, s);
-  else if (P.tile == 256)
+  else if (P.cap == 256)
     launch_step_t<256, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, par, s);
   else
     launch_step_t<512, 256>(P, h, hu, hw, hn, hun, hwn, mask, p, par, s);
@@ -1474,9 +1474,9 @@ static void launch_apply_t(const K1D& P, const uint8_t* mask, double* hun, doubl
 }
 void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
                     int par, hipStream_t s) {
-  if (P.tile == 128)
+  if (P.cap == 128)
     launch_apply_t<128, 128>(P, mask, hun, hwn, p, par, s);
-  else if (P.tile == 256)
+  else if (P.cap == 256)
     launch_apply_t<256, 256>(P, mask, hun, hwn, p, par, s);
   else
     launch_apply_t<512, 256>(P, mask, hun, hwn, p, par, s);

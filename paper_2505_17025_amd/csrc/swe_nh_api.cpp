@@ -102,8 +102,8 @@ int check_config(const swe_nh_config* c, std::string* why) {
   if (!(c->cfl > 0.0) && !(c->dt_fixed > 0.0)) return bad("need cfl > 0 or dt_fixed > 0");
   if (c->crit < 0 || c->crit > SWE_NH_CRIT_NONE) return bad("unknown criterion");
   if (c->enlarge < 0 || c->enlarge > 64) return bad("enlarge must be in [0, 64]");
-  if (c->tile1d != 0 && c->tile1d != 128 && c->tile1d != 256 && c->tile1d != 512)
-    return bad("tile1d must be 0, 128, 256 or 512");
+  if (c->tile1d != 0 && (c->tile1d < 32 || c->tile1d > TILE_MAX))
+    return bad("tile1d must be 0 or in [32, 512]");
   if (c->precision != 0 && c->precision != 1) return bad("precision must be 0 or 1");
   if (!c->depth_static) return bad("depth_static is required");
   if (!c->bodies) return bad("bodies is required");
@@ -134,12 +134,25 @@ int64_t total_cells(const swe_nh_config* c) {
 
 int n_channels(const swe_nh_config* c) { return c->dim == 2 ? 1 : c->batch; }
 
-// 1D tile size: the configured one, else 128 cells when tiles of 512 would
-// leave most of the 256 compute units idle
+bool fused_step(const swe_nh_config* c) {
+  return c->dim == 1 && c->precision == 0 && c->enlarge <= fused_max_enlarge();
+}
+
+// cells per 1D tile: the configured number, else a window capacity of 128
+// cells, or of 512 when tiles of 128 would give more than 1024 tiles.  The
+// fused step's window adds 6 + e cells on each side, so there the tile is the
+// capacity less twice that: the window then fills whole wavefronts.
 int tile_of(const swe_nh_config* c) {
-  if (c->tile1d == 128 || c->tile1d == 256 || c->tile1d == 512) return c->tile1d;
+  if (c->tile1d > 0) return c->tile1d;
   const int64_t N = c->dim == 2 ? (int64_t)c->nx * c->ny : (c->offsets ? c->offsets[c->batch] : c->nx);
-  return N <= 256 * 512 ? 128 : 512;
+  const int cap = N <= 256 * 512 ? 128 : 512;
+  return fused_step(c) ? cap - 2 * (6 + c->enlarge) : cap;
+}
+
+// LDS capacity of the tile kernels that hold a tile of tile_of(c) cells
+int cap_of(const swe_nh_config* c) {
+  const int t = tile_of(c);
+  return t <= 128 ? 128 : t <= 256 ? 256 : 512;
 }
 
 void tile_table(const swe_nh_config* c, std::vector<int2>* tiles, std::vector<int>* first) {
@@ -213,9 +226,9 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
     x->mask_ws = cv.take<uint8_t>(N);
     plan_levels(&x->T64, N, cv, nbuf64);
     if (c->precision == 1) plan_levels(&x->T32, N, cv, nbuf32);
-    if (c->precision == 0 && c->enlarge <= fused_max_enlarge()) {  // fused step
+    if (fused_step(c)) {
       plan_levels(&x->T1, 2 * (int64_t)ntiles, cv, nbuf1);
-      P.zw = cv.take<double>((size_t)ZW_N * ntiles * tile_of(c));
+      P.zw = cv.take<double>((size_t)ZW_N * ntiles * cap_of(c));
       P.dg1 = x->T1.dg[0];
       P.up1 = x->T1.up[0];
       P.rh1 = x->T1.rh[0];
@@ -424,8 +437,9 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.first_global = cfg->first_global;
   P.ntiles = (int)c->tiles.size();
   P.tile = tile_of(cfg);
+  P.cap = cap_of(cfg);
   P.nch = c->nch;
-  P.fused = (cfg->dim == 1 && cfg->precision == 0 && cfg->enlarge <= fused_max_enlarge()) ? 1 : 0;
+  P.fused = fused_step(cfg) ? 1 : 0;
   const int n1 = 2 * P.ntiles;
   std::vector<double> zeros(c->nch, 0.0);
   std::vector<unsigned long long> zu(c->nch, 0ull);

@@ -21,7 +21,8 @@ struct K1D {
   const double* ds;        // static depth [cells]
   double dx, g, rho, cfl, dt_fixed, k_nh;
   int crit, enlarge, first_global, ntiles;
-  int tile;                // cells per 1D tile: 128, 256 or 512
+  int tile;                // cells per 1D tile, at most cap
+  int cap;                 // capacity of the tile kernels' LDS windows: 128, 256 or 512
   double* t;               // [batch] time at the start of the step (fused: [2][batch] by parity)
   double* dt;              // [batch] step of the current step
   unsigned long long* smax;  // [batch] bit pattern of the max wave speed
@@ -36,7 +37,7 @@ struct K1D {
   int fused;
   int nch;
   int* n_acc;              // [2] marked cells counted during a step, by step parity
-  double* zw;              // [ZW_N][ntiles * tile] per marked row, tile-padded
+  double* zw;              // [ZW_N][ntiles * cap] per marked row, tile-padded
   double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
   const double* x1;        // level-1 solution
 };

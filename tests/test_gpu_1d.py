@@ -292,12 +292,12 @@ def test_refinement_reports_noconvergence(B):
 
 # ------------------------------------------------- fused FP64 step paths ----
 
-@pytest.mark.parametrize("tile", [128, 256, 512])
+@pytest.mark.parametrize("tile", [128, 256, 512, 114, 242, 498, 200, 37])
 @pytest.mark.parametrize("nsteps", [15, 16])
 def test_fused_step_tiles(B, tile, nsteps):
-    """every tile size of the fused step on ragged channels (channel ends
-    inside and at tile ends, 4-cell channels); odd step counts end in the
-    workspace copy of the state"""
+    """tile lengths of the fused step at and below each window capacity on
+    ragged channels (channel ends inside and at tile ends, 4-cell channels);
+    odd step counts end in the workspace copy of the state"""
     ens = ens_small(LENGTHS + [tile, tile + 1, 2 * tile - 1], seed=8)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=1, cfl=0.45, tile1d=tile)
     ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, nsteps, **kw)
@@ -316,12 +316,12 @@ def test_fused_step_tiles(B, tile, nsteps):
     assert st["n_active"] == total > 0
 
 
-@pytest.mark.parametrize("n", [70000, 300000])
-def test_fused_step_large_grids(B, n):
-    """level-1 system beyond the projection kernel's own solve (> 256 tiles)
-    and the step end by a separate kernel (> 2048 tiles)"""
+@pytest.mark.parametrize("n,tile", [(70000, 128), (300000, 128), (40000, 114)])
+def test_fused_step_large_grids(B, n, tile):
+    """level-1 system beyond the projection kernel's own solve (more than 512
+    tiles), and close to that limit (351 tiles)"""
     case = S.random_case_1d(n, seed=31, dx=0.05)
-    kw = dict(crit=S.CRIT_ETA_D, k_nh=3e-3, enlarge=2, cfl=0.45, tile1d=128)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=3e-3, enlarge=2, cfl=0.45, tile1d=tile)
     ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 5, **kw)
     assert st["status"] == 0
     ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(5)
@@ -330,6 +330,23 @@ def test_fused_step_large_grids(B, n):
     assert np.array_equal(mask.cpu().numpy(), ref.mask)
     for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
         assert rel(g, r) <= 1e-10
+
+
+def test_unfused_kernels_below_capacity(B):
+    """the stage kernels of the FP32 path with tiles shorter than their LDS
+    window (200 cells in a 256-cell window) on ragged channels"""
+    ens = ens_small(LENGTHS + [200, 201, 399], seed=9)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=1, cfl=0.45, tile1d=200, precision=1,
+              tol=1e-12, max_iter=8)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 9, **kw)
+    assert st["status"] == 0
+    o = ens.offsets
+    for j, c in enumerate(ens.channels):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.45).step(9)
+        sl = slice(o[j], o[j + 1])
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), j
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= 1e-6, j
 
 
 def test_wide_enlargement_uses_the_unfused_step(B):

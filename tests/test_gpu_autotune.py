@@ -24,7 +24,9 @@ def test_tune_1d_picks_a_candidate_and_persists(tmp_path):
     table = tmp_path / "tune.json"
     tile, times = autotune.tune_1d(case, kw, state, case.t0, nsteps=20, warmup=4,
                                    table_path=str(table))
-    assert tile in autotune.TILES_1D and set(times) == set(autotune.TILES_1D)
+    cands = autotune.candidates_1d(kw)
+    assert cands == (114, 128, 242, 256, 498, 512)
+    assert tile in cands and set(times) == set(cands)
     assert all(v > 0 for v in times.values()) and times[tile] == min(times.values())
     for a, b in zip(state, before):
         assert torch.equal(a, b)
