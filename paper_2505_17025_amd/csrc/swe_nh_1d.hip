@@ -71,7 +71,7 @@ __device__ __forceinline__ Flux rusanov1d(double g, double eL, double mL, double
   Flux f;
   const double hL = eL + dL, hR = eR + dR;
   f.dry = !(hL > 0.0) || !(hR > 0.0);
-  const double rL = 1.0 / hL, rR = 1.0 / hR;
+  const double rL = rcp64(hL), rR = rcp64(hR);
   const double uL = mL * rL, uR = mR * rR;
   const double wL = kL * rL, wR = kR * rR;
   const double db = fmin(dL, dR);
@@ -143,6 +143,26 @@ __device__ __forceinline__ void stage_cell(const PredSmem<T>& S, const double* d
 }
 }  // namespace
 
+namespace {
+// The body's motion at t0 and t1, evaluated by the first and the second
+// wavefront of the block and shared through LDS: it is the same for every
+// cell of a tile, so a block needs one evaluation per time, not one per
+// wavefront.  Contains a block barrier; needs at least two wavefronts.
+__device__ __forceinline__ void block_motions(const Chan& c, double t0, double t1, Motion& M0,
+                                              Motion& M1) {
+  __shared__ Motion slot[2];
+  const int wv = threadIdx.x >> 6;
+  if (wv < 2) {
+    const Motion m = body_motion(c, wv == 0 ? t0 : t1);
+    if ((threadIdx.x & 63) == 0) slot[wv] = m;
+  }
+  __syncthreads();
+  M0 = slot[0];
+  M1 = slot[1];
+}
+
+}  // namespace
+
 // Both Heun stages for a tile of at most T cells.  Thread t owns the window
 // cells e = 2 + t + NT q of the stage-1 range [2, tile + 6): their Q^n and stage-1
 // operator stay in registers for the final combination on the tile cells.
@@ -172,7 +192,8 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
     dt = dt_in[tl.x];
   }
   const double t1 = t0 + dt;
-  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t1);
+  Motion M0, M1;
+  block_motions(c, t0, t1, M0, M1);
   const double idx = 1.0 / P.dx;
   if (threadIdx.x == 0) sflags = 0;
   int flags = 0;
@@ -584,7 +605,7 @@ __device__ __forceinline__ void final_state(double g, double hh, double mm, doub
   } else if (!(hh > 0.0)) {
     flags |= ST_DRY;
   } else {
-    s = fmax(s, fabs(mm / hh) + sqrt(g * hh));
+    s = fmax(s, fabs(mm * rcp64(hh)) + sqrt(g * hh));
   }
 }
 
@@ -641,8 +662,9 @@ struct StepSmem {
   double e[WMAX], m[WMAX], k[WMAX], d0[WMAX], d1[WMAX];
   union {
     struct {
-      double Fh[WMAX], FmL[WMAX], FmR[WMAX], Fk[WMAX], hL[WMAX], hR[WMAX];
-    } f;  // face fluxes of a predictor stage
+      double se[WMAX], sm[WMAX], sk[WMAX], sd[WMAX];  // cell slopes
+      double Fh[WMAX], AL[WMAX], AR[WMAX], Fk[WMAX];  // face fluxes
+    } f;  // a predictor stage
     struct {
       CellNH cq[T + 2];  // cells start-1 .. end
       FaceNH fq[T + 1];  // faces start .. end
@@ -655,31 +677,38 @@ struct StepSmem {
   uint8_t mk[T + 2];
 };
 
+// minmod slopes of eta, hu, hw and the depth on window cells [c0, c1) of a
+// predictor stage (each cell's slopes serve both of its faces)
+template <typename SM>
+__device__ __forceinline__ void step_slopes(SM& S, const double* d, int c0, int c1) {
+  for (int w = c0 + threadIdx.x; w < c1; w += blockDim.x) {
+    S.u.f.se[w] = minmod(S.e[w] - S.e[w - 1], S.e[w + 1] - S.e[w]);
+    S.u.f.sm[w] = minmod(S.m[w] - S.m[w - 1], S.m[w + 1] - S.m[w]);
+    S.u.f.sk[w] = minmod(S.k[w] - S.k[w - 1], S.k[w + 1] - S.k[w]);
+    S.u.f.sd[w] = minmod(d[w] - d[w - 1], d[w + 1] - d[w]);
+  }
+}
+
 // face fluxes of one predictor stage on faces [f0, f1) of the window (face f
-// between window cells f-1 and f); dry faces touching channel cells of
-// [lo_cell, hi_cell) raise the flag
+// between window cells f-1 and f) from the slopes of step_slopes; the
+// momentum fluxes carry the centred bed source of the cell on each side,
+// g h (d_x) / 2 with the reconstructed depth at this face, so that a cell's
+// momentum update is the difference of two face values.  Dry faces touching
+// channel cells of [lo_cell, hi_cell) raise the flag.
 template <typename SM>
 __device__ __forceinline__ void step_faces(SM& S, const double* d, double g, int f0, int f1,
                                            int lo_cell, int hi_cell, int base, int& flags) {
   for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
     const int l = f - 1, r = f;
-    const double se_l = minmod(S.e[l] - S.e[l - 1], S.e[l + 1] - S.e[l]);
-    const double sm_l = minmod(S.m[l] - S.m[l - 1], S.m[l + 1] - S.m[l]);
-    const double sk_l = minmod(S.k[l] - S.k[l - 1], S.k[l + 1] - S.k[l]);
-    const double sd_l = minmod(d[l] - d[l - 1], d[l + 1] - d[l]);
-    const double se_r = minmod(S.e[r] - S.e[r - 1], S.e[r + 1] - S.e[r]);
-    const double sm_r = minmod(S.m[r] - S.m[r - 1], S.m[r + 1] - S.m[r]);
-    const double sk_r = minmod(S.k[r] - S.k[r - 1], S.k[r + 1] - S.k[r]);
-    const double sd_r = minmod(d[r] - d[r - 1], d[r + 1] - d[r]);
-    const Flux F = rusanov1d(g, S.e[l] + 0.5 * se_l, S.m[l] + 0.5 * sm_l, S.k[l] + 0.5 * sk_l,
-                             d[l] + 0.5 * sd_l, S.e[r] - 0.5 * se_r, S.m[r] - 0.5 * sm_r,
-                             S.k[r] - 0.5 * sk_r, d[r] - 0.5 * sd_r);
+    const double sdl = S.u.f.sd[l], sdr = S.u.f.sd[r];
+    const Flux F = rusanov1d(g, S.e[l] + 0.5 * S.u.f.se[l], S.m[l] + 0.5 * S.u.f.sm[l],
+                             S.k[l] + 0.5 * S.u.f.sk[l], d[l] + 0.5 * sdl,
+                             S.e[r] - 0.5 * S.u.f.se[r], S.m[r] - 0.5 * S.u.f.sm[r],
+                             S.k[r] - 0.5 * S.u.f.sk[r], d[r] - 0.5 * sdr);
     S.u.f.Fh[f] = F.Fh;
-    S.u.f.FmL[f] = F.FmL;
-    S.u.f.FmR[f] = F.FmR;
+    S.u.f.AL[f] = F.FmL - 0.5 * g * F.hL * sdl;
+    S.u.f.AR[f] = F.FmR + 0.5 * g * F.hR * sdr;
     S.u.f.Fk[f] = F.Fk;
-    S.u.f.hL[f] = F.hL;
-    S.u.f.hR[f] = F.hR;
     const int il = base + l, ir = base + r;
     const bool used = (il >= lo_cell && il < hi_cell) || (ir >= lo_cell && ir < hi_cell);
     if (F.dry && used) flags |= ST_DRY;
@@ -687,12 +716,10 @@ __device__ __forceinline__ void step_faces(SM& S, const double* d, double g, int
 }
 
 template <typename SM>
-__device__ __forceinline__ void step_cell(const SM& S, const double* d, double g, double idx,
-                                          int e, double& Lh, double& Lm, double& Lk) {
-  const double sd = minmod(d[e] - d[e - 1], d[e + 1] - d[e]);
+__device__ __forceinline__ void step_cell(const SM& S, double idx, int e, double& Lh, double& Lm,
+                                          double& Lk) {
   Lh = -(S.u.f.Fh[e + 1] - S.u.f.Fh[e]) * idx;
-  Lm = -(S.u.f.FmL[e + 1] - S.u.f.FmR[e]) * idx +
-       g * 0.5 * (S.u.f.hL[e + 1] + S.u.f.hR[e]) * sd * idx;
+  Lm = -(S.u.f.AL[e + 1] - S.u.f.AR[e]) * idx;
   Lk = -(S.u.f.Fk[e + 1] - S.u.f.Fk[e]) * idx;
 }
 
@@ -821,7 +848,7 @@ __device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
 // the speed of the unmarked cells' new state, assembly of the marked rows
 // (Eqs. 10-17) and their reduction to the two level-1 rows.
 template <int T, int NT>
-__global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__ h,
+__global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restrict__ h,
                                                const double* __restrict__ hu,
                                                const double* __restrict__ hw,
                                                double* __restrict__ hn, double* __restrict__ hun,
@@ -851,27 +878,46 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   }
   const int ee = P.enlarge, HL = 6 + ee, W = P.tile + 2 * HL;
   const int lo = start - HL;  // window cell w <-> channel cell lo + w
-  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t1);
   const double idx = 1.0 / P.dx;
   if (threadIdx.x == 0) sflags = 0;
   int flags = 0;
 
   // ---- predictor ----
-  for (int w = threadIdx.x; w < W; w += NT) {
+  // Q^n and d_s of the window into registers; meanwhile the body's motion at
+  // t^n and t^{n+1}, one wavefront each (the same for every cell of the tile)
+  constexpr int QL = (SM::WMAX + NT - 1) / NT;
+  double vh[QL], vm[QL], vk[QL], vd[QL];
+#pragma unroll
+  for (int q = 0; q < QL; q++) {
+    const int w = threadIdx.x + NT * q;
+    if (w >= W) continue;
     const int i = lo + w;
     const int s = reflect(max(-n, min(i, 2 * n - 1)), n);
     const int64_t gi = c.off + s;
+    vh[q] = h[gi];
+    vm[q] = (s == i ? 1.0 : -1.0) * hu[gi];
+    vk[q] = hw[gi];
+    vd[q] = P.ds[gi];
+  }
+  Motion M0, M1;
+  block_motions(c, t0, t1, M0, M1);
+#pragma unroll
+  for (int q = 0; q < QL; q++) {
+    const int w = threadIdx.x + NT * q;
+    if (w >= W) continue;
+    const int s = reflect(max(-n, min(lo + w, 2 * n - 1)), n);
     const double x = (s + 0.5) * P.dx;
-    const double ds = P.ds[gi];
-    const double dA = ds - body_shape(c, x - M0.X, 0.0).B;
-    S.e[w] = h[gi] - dA;
-    S.m[w] = (s == i ? 1.0 : -1.0) * hu[gi];
-    S.k[w] = hw[gi];
+    const double dA = vd[q] - body_shape(c, x - M0.X, 0.0).B;
+    S.e[w] = vh[q] - dA;
+    S.m[w] = vm[q];
+    S.k[w] = vk[q];
     S.d0[w] = dA;
-    S.d1[w] = ds - body_shape(c, x - M1.X, 0.0).B;
+    S.d1[w] = vd[q] - body_shape(c, x - M1.X, 0.0).B;
   }
   __syncthreads();
   double Qn[Q][3], L1[Q][3];
+  step_slopes(S, S.d0, 1, W - 1);
+  __syncthreads();
   step_faces(S, S.d0, P.g, 2, W - 1, max(0, start - 2), min(n, start + P.tile + 2), lo, flags);
   __syncthreads();
 #pragma unroll
@@ -880,7 +926,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
     Qn[q][0] = Qn[q][1] = Qn[q][2] = 0.0;
     L1[q][0] = L1[q][1] = L1[q][2] = 0.0;
     if (e < W - 2) {
-      step_cell(S, S.d0, P.g, idx, e, L1[q][0], L1[q][1], L1[q][2]);
+      step_cell(S, idx, e, L1[q][0], L1[q][1], L1[q][2]);
       Qn[q][0] = S.e[e] + S.d0[e];
       Qn[q][1] = S.m[e];
       Qn[q][2] = S.k[e];
@@ -914,6 +960,8 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
   }
   __syncthreads();
   // stage 2 on window cells [4, W - 4): the tile and e + 2 cells beyond
+  step_slopes(S, S.d1, 3, W - 3);
+  __syncthreads();
   step_faces(S, S.d1, P.g, 4, W - 3, start, end, lo, flags);
   __syncthreads();
   double Qt[Q][3];
@@ -923,7 +971,7 @@ __global__ void __launch_bounds__(NT) k_step1d(K1D P, const double* __restrict__
     Qt[q][0] = Qt[q][1] = Qt[q][2] = 0.0;
     if (e < 4 || e >= W - 4) continue;
     double a, b, k2;
-    step_cell(S, S.d1, P.g, idx, e, a, b, k2);
+    step_cell(S, idx, e, a, b, k2);
     Qt[q][0] = Qn[q][0] + 0.5 * dt * (L1[q][0] + a);
     Qt[q][1] = Qn[q][1] + 0.5 * dt * (L1[q][1] + b);
     Qt[q][2] = Qn[q][2] + 0.5 * dt * (L1[q][2] + k2);

@@ -134,7 +134,7 @@ __device__ __forceinline__ Flux2 rusanov2d(double g, double eL, double mL, doubl
   Flux2 f;
   const double hL = eL + dL, hR = eR + dR;
   f.dry = !(hL > 0.0) || !(hR > 0.0);
-  const double rL = 1.0 / hL, rR = 1.0 / hR;
+  const double rL = rcp64(hL), rR = rcp64(hR);
   const double uL = mL * rL, uR = mR * rR;
   const double vL = aL * rL, vR = aR * rR;
   const double wL = bL * rL, wR = bR * rR;

@@ -125,6 +125,19 @@ __device__ __forceinline__ BedRate bed_rate(const Motion& m, const Shape& s) {
   return r;
 }
 
+// 1 / x for finite nonzero x whose reciprocal is a normal number: the
+// hardware reciprocal estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each of which squares the relative error.  Within an
+// ulp or so of the correctly rounded quotient; used where the state is divided
+// by a depth in the stencil sweeps.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ double minmod(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   return fabs(a) < fabs(b) ? a : b;
