@@ -1198,9 +1198,10 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   // the speed buffer this step read collects the speed of the step after next
   if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.smax[par * P.nch + tl.x] = 0ull;
   const int m = P.tile_cnt[blockIdx.x];
+  if (m == 0) return;  // no marked cell: the step kernel already took this tile's speed
   double smax = 0.0;
   int flags = 0;
-  if (m > 0) {
+  {
     // the tile's marked rows and their stored data first: the loads are in
     // flight while the level-1 system is solved
     int rank[T / NT];

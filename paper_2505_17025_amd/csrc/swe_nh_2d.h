@@ -23,6 +23,7 @@ struct Ctx2D {
   uint8_t* mask_ws = nullptr;
   // tiles
   int* tile_cnt = nullptr;   // marked cells per tile
+  double* tspeed = nullptr;  // per tile: max (|u| + c)/dx + (|v| + c)/dy of the new state
   int* tile_list = nullptr;  // active tiles
   int* n_tiles_act = nullptr;
   int* n_act = nullptr;      // marked cells
@@ -58,6 +59,9 @@ struct Ctx2D {
 
 void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x);
 int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s);
+// speed of the caller's state -> dt of the first step of a call
+void launch_speed2d_prologue(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,
+                             const double* hu, const double* hv, const double* hw);
 void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, double* hu,
                     double* hv, double* hw, double* p, uint8_t* mask);
 void launch_pred2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,

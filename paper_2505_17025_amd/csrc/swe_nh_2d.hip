@@ -43,6 +43,7 @@ struct G2 {
   double* t;
   double* dt;
   unsigned long long* smax;
+  double* tspeed;  // [ntiles] max speed term of each tile's new state
   int* status;
   int* step;
 };
@@ -67,6 +68,7 @@ G2 make_g2(const swe_nh_config* c, const Ctx2D* x) {
   g.t = x->t;
   g.dt = x->dt;
   g.smax = x->smax;
+  g.tspeed = x->tspeed;
   g.status = x->status;
   g.step = x->step;
   return g;
@@ -81,30 +83,32 @@ __device__ __forceinline__ double depth2(const G2& G, const Chan& c, const Motio
 // ---------------------------------------------------------------------------
 // wave speed
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT2) k_speed2d(G2 G, const double* __restrict__ h,
-                                                 const double* __restrict__ hu,
-                                                 const double* __restrict__ hv,
-                                                 const double* __restrict__ hw) {
-  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
-  double s = 0.0;
-  int flags = 0;
-  for (int c = threadIdx.x; c < TN; c += NT2) {
-    const int i = i0 + c % TX2, j = j0 + c / TX2;
-    if (i >= G.nx || j >= G.ny) continue;
-    const int64_t o = (int64_t)j * G.nx + i;
-    const double hh = h[o], m = hu[o], n = hv[o], k = hw[o];
-    if (!isfinite(hh) || !isfinite(m) || !isfinite(n) || !isfinite(k)) {
-      flags |= ST_NAN;
-    } else if (!(hh > 0.0)) {
-      flags |= ST_DRY;
-    } else {
-      const double a = sqrt(G.g * hh);
-      s = fmax(s, (fabs(m / hh) + a) / G.dx + (fabs(n / hh) + a) / G.dy);
-    }
+// Each tile keeps the largest (|u| + c)/dx + (|v| + c)/dy of its state in
+// tspeed[tile] (plain stores by the block that owns the tile: the step's mask
+// pass for the unmarked cells, the projection for the marked ones); one block
+// reduces the tiles at the end of the step.  Thousands of blocks taking the
+// maximum on one address would serialise on it.
+
+// one cell's speed term (s) and state checks (flags)
+__device__ __forceinline__ void cell_speed2d(const G2& G, double idx, double idy, double hh,
+                                             double m, double n, double k, double& s,
+                                             int& flags) {
+  if (!isfinite(hh) || !isfinite(m) || !isfinite(n) || !isfinite(k)) {
+    flags |= ST_NAN;
+  } else if (!(hh > 0.0)) {
+    flags |= ST_DRY;
+  } else {
+    const double a = sqrt(G.g * hh), r = rcp64(hh);
+    s = fmax(s, (fabs(m * r) + a) * idx + (fabs(n * r) + a) * idy);
   }
-  s = wave_max(s);
+}
+
+// block maximum of s into *slot (max with its value when combine), flags into
+// the status word
+__device__ void flush_tile_speed(const G2& G, double* slot, double s, int flags, bool combine) {
   __shared__ double red[NT2 / 64];
   __shared__ int fl;
+  s = wave_max(s);
   if (threadIdx.x == 0) fl = 0;
   __syncthreads();
   if (flags) atomicOr(&fl, flags);
@@ -113,8 +117,45 @@ __global__ void __launch_bounds__(NT2) k_speed2d(G2 G, const double* __restrict_
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int w = 1; w < NT2 / 64; w++) m = fmax(m, red[w]);
-    atomicMax(G.smax, pos_bits(m));
+    *slot = combine ? fmax(m, *slot) : m;
     if (fl) atomicOr(G.status, fl);
+  }
+}
+
+__global__ void __launch_bounds__(NT2) k_speed2d(G2 G, const double* __restrict__ h,
+                                                 const double* __restrict__ hu,
+                                                 const double* __restrict__ hv,
+                                                 const double* __restrict__ hw) {
+  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
+  const double idx = 1.0 / G.dx, idy = 1.0 / G.dy;
+  double s = 0.0;
+  int flags = 0;
+  for (int c = threadIdx.x; c < TN; c += NT2) {
+    const int i = i0 + c % TX2, j = j0 + c / TX2;
+    if (i >= G.nx || j >= G.ny) continue;
+    const int64_t o = (int64_t)j * G.nx + i;
+    cell_speed2d(G, idx, idy, h[o], hu[o], hv[o], hw[o], s, flags);
+  }
+  flush_tile_speed(G, &G.tspeed[blockIdx.x], s, flags, false);
+}
+
+// maximum over the tiles -> *smax; with advance, also the end of a step:
+// t += dt and the step counter
+__global__ void __launch_bounds__(1024) k_speed_reduce2d(G2 G, int ntiles, int advance) {
+  __shared__ double red[1024 / 64];
+  double m = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += 1024) m = fmax(m, G.tspeed[t]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < 1024 / 64; w++) r = fmax(r, red[w]);
+    *G.smax = pos_bits(r);
+    if (advance) {
+      G.t[0] += G.dt[0];
+      *G.step += 1;
+    }
   }
 }
 
@@ -460,6 +501,9 @@ __global__ void __launch_bounds__(NT2) k_mask2d(G2 G, const double* __restrict__
     __syncthreads();
   }
   int local = 0;
+  const double idx = 1.0 / G.dx, idy = 1.0 / G.dy;
+  double sp = 0.0;
+  int flags = 0;
   for (int cc = threadIdx.x; cc < TN; cc += NT2) {
     const int ti = cc % TX2, tj = cc / TX2;
     const int i = i0 + ti, j = j0 + tj;
@@ -477,13 +521,18 @@ __global__ void __launch_bounds__(NT2) k_mask2d(G2 G, const double* __restrict__
     mask[o] = v;
     local += v;
     if (write_state) {
-      h[o] = ht[o];
-      hu[o] = mt[o];
-      hv[o] = nt[o];
-      hw[o] = kt[o];
-      if (!v) p[o] = 0.0;
+      const double hh = ht[o], mm = mt[o], nn = nt[o], kk = kt[o];
+      h[o] = hh;
+      hu[o] = mm;
+      hv[o] = nn;
+      hw[o] = kk;
+      if (!v) {
+        p[o] = 0.0;
+        cell_speed2d(G, idx, idy, hh, mm, nn, kk, sp, flags);  // final: no projection follows
+      }
     }
   }
+  if (write_state) flush_tile_speed(G, &G.tspeed[blockIdx.x], sp, flags, false);
   local = wave_sum_i(local);
   if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = local;
   __syncthreads();
@@ -1423,7 +1472,8 @@ __global__ void __launch_bounds__(NT2) k_correct2d(G2 G, const double* __restric
                                                    const int* tile_list, const int* n_list,
                                                    const double* t_in, const double* dt_in,
                                                    const double* __restrict__ x, double* hu,
-                                                   double* hv, double* hw, double* p) {
+                                                   double* hv, double* hw, double* p,
+                                                   int fold_speed) {
   if ((int)blockIdx.x >= *n_list) return;
   __shared__ Ring R;
   const int tile = tile_list[blockIdx.x];
@@ -1434,6 +1484,9 @@ __global__ void __launch_bounds__(NT2) k_correct2d(G2 G, const double* __restric
   fill_ring(R, G, c, M, ht, mt, nt, i0, j0);
   __syncthreads();
   const int nx = G.nx;
+  const double idx = 1.0 / G.dx, idy = 1.0 / G.dy;
+  double sp = 0.0;
+  int flags = 0;
   for (int cc = threadIdx.x; cc < TN; cc += NT2) {
     const int ti = cc % TX2, tj = cc / TX2;
     const int i = i0 + ti, j = j0 + tj;
@@ -1458,20 +1511,17 @@ __global__ void __launch_bounds__(NT2) k_correct2d(G2 G, const double* __restric
     const double al = 4.0 + R.Dx[w] * R.Dx[w] + R.Dy[w] * R.Dy[w];
     const double Pb = 1.5 * pc - G.rho * (R.Dx[w] * dm + R.Dy[w] * dn) / (4.0 * dt) +
                       al * R.phi[w] / 4.0;
-    hu[o] = mt[o] + dm;
-    hv[o] = nt[o] + dn;
-    hw[o] = kt[o] + dt * Pb / G.rho;
+    const double mn = mt[o] + dm, nn = nt[o] + dn, kn = kt[o] + dt * Pb / G.rho;
+    hu[o] = mn;
+    hv[o] = nn;
+    hw[o] = kn;
     if (p) p[o] = pc;
+    if (fold_speed) cell_speed2d(G, idx, idy, ht[o], mn, nn, kn, sp, flags);
   }
+  // the tile's speed: its unmarked cells were taken by the mask pass
+  if (fold_speed) flush_tile_speed(G, &G.tspeed[tile], sp, flags, true);
 }
 
-__global__ void k_advance2d(double* t, double* dt, unsigned long long* smax, int* step) {
-  if (threadIdx.x == 0) {
-    t[0] += dt[0];
-    smax[0] = 0ull;
-    *step += 1;
-  }
-}
 
 
 Sys2 sys_of(Ctx2D* x) {
@@ -1596,6 +1646,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->kt = (double*)take(8 * N);
   x->mask_ws = (uint8_t*)take(N);
   x->tile_cnt = (int*)take(4 * x->ntiles);
+  x->tspeed = (double*)take(8 * (size_t)x->ntiles);
   x->tile_list = (int*)take(4 * x->ntiles);
   x->n_tiles_act = (int*)take(4);
   x->n_act = (int*)take(4);
@@ -1675,14 +1726,13 @@ static void enqueue_nh2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const 
   launch_solve2d(c, x, s);
   if (hu)
     hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
-                       x->tile_list, x->n_tiles_act, t_in, dt_in, x->x, hu, hv, hw, p);
+                       x->tile_list, x->n_tiles_act, t_in, dt_in, x->x, hu, hv, hw, p, 1);
 }
 
 void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, double* hu,
                     double* hv, double* hw, double* p, uint8_t* mask) {
   const G2 G = make_g2(c, x);
   uint8_t* M = mask ? mask : x->mask_ws;
-  hipLaunchKernelGGL(k_speed2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw);
   hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw, x->ht, x->mt,
                      x->nt, x->kt, (const double*)x->t, (const double*)x->dt, 1);
   // the mask pass clears p only off the new marked area: p keeps the previous
@@ -1709,7 +1759,16 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
     hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
                        x->n_tiles_act, x->n_act);
   }
-  hipLaunchKernelGGL(k_advance2d, dim3(1), dim3(64), 0, s, x->t, x->dt, x->smax, x->step);
+  // the new state's speed (tiles written by the mask pass and the projection)
+  // -> dt of the next step; time and step counter advance
+  hipLaunchKernelGGL(k_speed_reduce2d, dim3(1), dim3(1024), 0, s, G, x->ntiles, 1);
+}
+
+void launch_speed2d_prologue(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,
+                             const double* hu, const double* hv, const double* hw) {
+  const G2 G = make_g2(c, x);
+  hipLaunchKernelGGL(k_speed2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw);
+  hipLaunchKernelGGL(k_speed_reduce2d, dim3(1), dim3(1024), 0, s, G, x->ntiles, 0);
 }
 
 void launch_pred2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,
@@ -1756,7 +1815,8 @@ void correct2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht
   launch_copy(nt, n_out, N, s);
   launch_copy(kt, k_out, N, s);
   hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
-                     x->tile_list, x->n_tiles_act, t_in, dt_in, p, m_out, n_out, k_out, nullptr);
+                     x->tile_list, x->n_tiles_act, t_in, dt_in, p, m_out, n_out, k_out, nullptr,
+                     0);
 }
 
 void time_stage2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, int stage, double* h,
@@ -1778,7 +1838,7 @@ void time_stage2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, int stage, do
     default:
       hipLaunchKernelGGL(k_correct2d, dim3(x->ntiles), dim3(NT2), 0, s, G, x->ht, x->mt, x->nt,
                          x->kt, x->mask_ws, x->tile_list, x->n_tiles_act, (const double*)x->t,
-                         (const double*)x->dt, x->x, hu, hv, hw, p);
+                         (const double*)x->dt, x->x, hu, hv, hw, p, 0);
   }
 }
 

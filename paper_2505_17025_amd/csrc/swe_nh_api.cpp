@@ -566,6 +566,11 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
     int rc = after_launch(c);
     if (rc) return rc;
   }
+  if (c->cfg.dim == 2 && nsteps > 0) {
+    launch_speed2d_prologue(&c->cfg, &c->c2, c->stream, h, hu, hv, hw);
+    int rc = after_launch(c);
+    if (rc) return rc;
+  }
   int i = 0;
   if (fused)
     for (; i + GSTEPS <= nsteps; i += GSTEPS) HIPCHK(c, hipGraphLaunch(c->gexecN, c->stream));
