@@ -301,17 +301,16 @@ def run_learned(B, torch, S, steps, warmup, n=1024, dx=4.0):
         st = ctx.sync_stats()
         if st["status"] != 0:
             raise RuntimeError(f"{name}: warmup status {st}")
+        it0 = st["iters_total"]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        its = 0
-        for _ in range(steps):
-            ctx.step(h, hu, hv, hw, p)
-            st = ctx.sync_stats()
-            if st["status"] != 0:
-                raise RuntimeError(f"{name}: step status {st}")
-            its += st["iters"]
+        ctx.step(h, hu, hv, hw, p, nsteps=steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
+        st = ctx.sync_stats()
+        if st["status"] != 0:
+            raise RuntimeError(f"{name}: step status {st}")
+        its = st["iters_total"] - it0
         out[name] = {"cell_steps_per_s": n * n * steps / el, "ms_per_step": 1e3 * el / steps,
                      "pcg_iters_per_step": its / steps, "n_active_last": st["n_active"]}
         log(name, json.dumps(out[name]))
@@ -351,18 +350,16 @@ def run_2d(B, torch, S, steps, warmup):
         st = ctx.sync_stats()
         if st["status"] != 0:
             raise RuntimeError(f"{name}: warmup status {st}")
+        it0 = st["iters_total"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        its = 0
-        for _ in range(steps):
-            ctx.step(h, hu, hv, hw, p)
-            st = ctx.sync_stats()
-            if st["status"] != 0:
-                raise RuntimeError(f"{name}: step status {st}")
-            its += st["iters"]
+        ctx.step(h, hu, hv, hw, p, nsteps=steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         st = ctx.sync_stats()
+        if st["status"] != 0:
+            raise RuntimeError(f"{name}: step status {st}")
+        its = st["iters_total"] - it0
         stage = {n: ctx.time_stage(i, 20, h, hu, hv, hw, p)
                  for i, n in enumerate(["predictor", "mask", "solve", "projection"])}
         out[name] = {"cell_steps_per_s": c.nx * c.ny * steps / el, "ms_per_step": 1e3 * el / steps,

@@ -124,6 +124,7 @@ typedef struct {
   double dt;                /* time step of the last step (channel 0) */
   double t;                 /* time after the last step (channel 0) */
   int64_t steps;            /* steps taken since init */
+  int64_t iters_total;      /* PCG iterations summed over all solves since init (2D; 0 in 1D) */
 } swe_nh_stats;
 
 typedef struct swe_nh_ctx swe_nh_ctx;

@@ -13,6 +13,7 @@ namespace swenh {
 constexpr int TX2 = 32;  // tile width (cells along x) of the 2D kernels
 constexpr int TY2 = 16;  // tile height
 constexpr int PCG_NVEC = 10;  // inner vectors of the 2D solver
+constexpr int CMAX2 = 128;     // most active tiles for which the solver adds the coarse space
 
 struct Ctx2D {
   int nx = 0, ny = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
@@ -25,6 +26,11 @@ struct Ctx2D {
   int* tile_cnt = nullptr;   // marked cells per tile
   double* tspeed = nullptr;  // per tile: max (|u| + c)/dx + (|v| + c)/dy of the new state
   int* tile_list = nullptr;  // active tiles
+  int* tile_pos = nullptr;   // per tile: position in tile_list, -1 when inactive
+  // coarse space of the preconditioner (one constant per active tile)
+  double* crow = nullptr;    // [ntiles][5] coarse operator rows: self, E, W, N, S
+  double* cinv = nullptr;    // [CMAX2 * CMAX2] inverse of the coarse operator
+  int* cused = nullptr;      // [CMAX2 + 3] tiles, age and use of that inverse
   int* n_tiles_act = nullptr;
   int* n_act = nullptr;      // marked cells
   // operator (FP64 and FP32 copies), neighbour flags, right-hand side, solution
@@ -39,6 +45,7 @@ struct Ctx2D {
   double* part = nullptr;    // [2][4][PCG_GMAX] block partial sums
   unsigned long long* bar = nullptr;  // grid barrier arrival counter
   int* iters = nullptr;
+  long long* iters_sum = nullptr;
   double* rel = nullptr;
   // learned warm start (warm = 2)
   char* cnn_ws = nullptr;

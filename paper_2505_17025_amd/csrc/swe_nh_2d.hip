@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(NT2) k_count2d(G2 G, const uint8_t* __restrict
 // list of tiles holding marked cells, in tile order; total marked cells
 __global__ void __launch_bounds__(1024) k_tiles2d(const int* __restrict__ tile_cnt, int ntiles,
                                                   int* __restrict__ tile_list, int* n_list,
-                                                  int* n_cells) {
+                                                  int* n_cells, int* __restrict__ tile_pos) {
   __shared__ int part[1024];
   __shared__ long long cells[1024];
   const int per = (ntiles + 1023) / 1024;
@@ -588,8 +588,11 @@ __global__ void __launch_bounds__(1024) k_tiles2d(const int* __restrict__ tile_c
     __syncthreads();
   }
   int run = part[threadIdx.x] - s;
-  for (int i = b; i < e; i++)
-    if (tile_cnt[i] > 0) tile_list[run++] = i;
+  for (int i = b; i < e; i++) {
+    const bool on = tile_cnt[i] > 0;
+    tile_pos[i] = on ? run : -1;
+    if (on) tile_list[run++] = i;
+  }
   if (threadIdx.x == 1023) {
     *n_list = part[1023];
     *n_cells = (int)cells[1023];
@@ -866,10 +869,14 @@ struct PcgArgs {
   R *r, *u, *w, *z, *q, *s, *p, *e;
   R* m[2];          // M^-1 w, double-buffered by pass parity (pipelined form)
   int pipe_blocks;  // grid of the pipelined form (decides which form runs)
+  const int* tile_pos;  // per tile: position in tile_list (-1: inactive)
+  const double* cinv;   // (Z^T A Z)^-1 of the active tiles (coarse space), or null
+  const int* cused;     // [2]: 1 when cinv is to be used
   unsigned* tflag;  // per tile: last neighbour-sync stamp passed (Chronopoulos-Gear form)
   double* part;
   Bar bar;
   int* iters;
+  long long* iters_sum;  // iterations summed over all solves
   double* rel;
   double tol, tol_in;
   int max_iter;
@@ -1237,7 +1244,10 @@ __device__ void pcg_cg(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2])
     if (!grid_sync(A.bar, ++k, G)) return;
     sweep++;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *A.iters = total;
+    *A.iters_sum += total;
+  }
 }
 
 
@@ -1272,6 +1282,101 @@ __device__ void tile_precond_k(const TileCells<R> (&C)[K], const TileOp<R> (&T)[
   }
 }
 
+// Coarse correction of the block's tile and of its four face neighbours:
+// c = (Z^T A Z)^-1 sig restricted to those tiles, where sig holds the tile
+// sums of the vector being preconditioned (one per active tile, list order).
+template <typename R>
+struct Coarse {
+  R own, e, w, n, s;
+};
+
+// the rows of (Z^T A Z)^-1 of the block's tile and its face neighbours (zero
+// rows for missing or inactive neighbours) -> rows[5][CMAX2]; returns whether
+// the coarse space is used (the block's tile at list position t, nc tiles)
+template <typename R>
+__device__ bool coarse_rows(const PcgArgs<R>& A, int t, int nc, double (*rows)[CMAX2]) {
+  const bool on = A.cinv != nullptr && nc <= CMAX2 && A.cused[2] == 1;
+  if (!on) return false;
+  const int tile = A.tile_list[t], tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+  int pos[5];
+  pos[0] = t;
+  pos[1] = tx + 1 < A.tiles_x ? A.tile_pos[tile + 1] : -1;
+  pos[2] = tx > 0 ? A.tile_pos[tile - 1] : -1;
+  pos[3] = ty + 1 < A.tiles_y ? A.tile_pos[tile + A.tiles_x] : -1;
+  pos[4] = ty > 0 ? A.tile_pos[tile - A.tiles_x] : -1;
+  for (int e = threadIdx.x; e < 5 * CMAX2; e += NT2) {
+    const int r = e / CMAX2, j = e % CMAX2;
+    rows[r][j] = (pos[r] >= 0 && j < nc) ? A.cinv[(int64_t)pos[r] * nc + j] : 0.0;
+  }
+  __syncthreads();
+  return true;
+}
+
+// grid_totals plus the coarse correction from the last of the NV partial
+// rows (the tile sums: one per block = one per active tile, list order)
+template <int NV, typename R>
+__device__ void grid_totals_coarse(const double* part, int G, double (&tot)[NV], bool on,
+                                   const double (*rows)[CMAX2], Coarse<R>& cc) {
+  __shared__ double sh[NV + 5][NT2 / 64];
+  double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    double sum = 0.0;
+    for (int b = threadIdx.x; b < G; b += NT2) {
+      const double v =
+          __hip_atomic_load(&part[(int64_t)k * G + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sum += v;
+      if (k == NV - 1 && on) {
+#pragma unroll
+        for (int r = 0; r < 5; r++) c[r] += rows[r][b] * v;
+      }
+    }
+    sum = wave_sum(sum);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = sum;
+  }
+  if (on) {
+#pragma unroll
+    for (int r = 0; r < 5; r++) {
+      const double t = wave_sum(c[r]);
+      if ((threadIdx.x & 63) == 0) sh[NV + r][threadIdx.x >> 6] = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++) {
+    double t = 0.0;
+    if (k < NV || on)
+      for (int w = 0; w < NT2 / 64; w++) t += sh[k][w];
+    if (k < NV)
+      tot[k] = t;
+    else
+      c[k - NV] = t;
+  }
+  cc.own = (R)c[0];
+  cc.e = (R)c[1];
+  cc.w = (R)c[2];
+  cc.n = (R)c[3];
+  cc.s = (R)c[4];
+}
+
+// (A v) at the thread's cell q where v = (tile-local part) + (coarse
+// constant of the tile the cell lies in): the tile's local part from LDS, the
+// neighbours' from memory
+template <typename R>
+__device__ __forceinline__ R apply_coarse(const FullOp<R>& F, const TileCells<R>& C, int q,
+                                          const R* v, const R (*zt)[TX2], int nx,
+                                          const Coarse<R>& K) {
+  const int64_t o = C.o[q];
+  const int li = C.li[q], lj = C.lj[q];
+  const uint8_t f = F.nf[q];
+  R a = F.dg[q] * (zt[lj][li] + K.own);
+  if (f & NB_E) a += F.cE[q] * (li + 1 < TX2 ? zt[lj][li + 1] + K.own : v[o + 1] + K.e);
+  if (f & NB_W) a += F.cW[q] * (li > 0 ? zt[lj][li - 1] + K.own : v[o - 1] + K.w);
+  if (f & NB_N) a += F.cN[q] * (lj + 1 < TY2 ? zt[lj + 1][li] + K.own : v[o + nx] + K.n);
+  if (f & NB_S) a += F.cS[q] * (lj > 0 ? zt[lj - 1][li] + K.own : v[o - nx] + K.s);
+  return a;
+}
+
 // Preconditioned CG in the pipelined form of Ghysels and Vanroose (2014)
 // for blocks that own up to K tiles each: per iteration one pass and one
 // grid barrier, which both completes the reduction of (r,u), (w,u), (r,r)
@@ -1279,7 +1384,8 @@ __device__ void tile_precond_k(const TileCells<R> (&C)[K], const TileOp<R> (&T)[
 // next pass (m double-buffered by pass parity).  The vectors stay in
 // registers and the tiles' m stays in LDS for the whole solve.
 template <typename R, int K>
-__device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TY2][TX2]) {
+__device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TY2][TX2],
+                              double (*crows)[CMAX2]) {
   const int nx = A.nx;
   TileCells<R> C[K];
   FullOp<R> F[K];
@@ -1294,13 +1400,17 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
     T[k] = restrict_op(F[k], C[k]);
     X[k] = Cells<R>{};
   }
+  // the coarse space needs one tile per block (its tile sums are the blocks'
+  // partial sums)
+  const bool coarse = (K == 1) && coarse_rows(A, S.t0, G, crows);
+  Coarse<R> cu{}, cm{};  // coarse constants of u_0 and of the last m
   unsigned bk = 0;  // grid barriers passed
   double bb = 0.0, rr = 0.0;
   int total = 0, sweep = 0;
   for (;;) {
     // FP64 residual of the current solution -> r_0 (precision R), u_0 = M^-1 r_0
     {
-      double v[2] = {0.0, 0.0};
+      double v[3] = {0.0, 0.0, 0.0};  // (r,r), (b,b), tile sum of r
       R rc[K][2];
 #pragma unroll
       for (int k = 0; k < K; k++)
@@ -1316,6 +1426,7 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
           X[k].e[q] = R(0);
           v[0] += rv * rv;
           if (sweep == 0) v[1] += A.b[o] * A.b[o];
+          v[2] += (double)rc[k][q];
         }
       tile_precond_k<R, K>(C, T, rc, zt);
 #pragma unroll
@@ -1323,15 +1434,19 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
 #pragma unroll
         for (int q = 0; q < 2; q++) {
           if (!(F[k].nf[q] & NB_SELF)) continue;
-          X[k].u[q] = zt[k][C[k].lj[q]][C[k].li[q]];
-          A.u[C[k].o[q]] = X[k].u[q];
+          A.u[C[k].o[q]] = zt[k][C[k].lj[q]][C[k].li[q]];  // the tile-local part
         }
-      block_partials<2>(v, part_buf(A.part, bk + 1), S.vb, G);
+      block_partials<3>(v, part_buf(A.part, bk + 1), S.vb, G);
       if (!grid_sync(A.bar, ++bk, G)) return;
-      double tt[2];
-      grid_totals<2>(part_buf(A.part, bk), G, tt);
+      double tt[3];
+      grid_totals_coarse<3, R>(part_buf(A.part, bk), G, tt, coarse, crows, cu);
       rr = tt[0];
       if (sweep == 0) bb = tt[1];
+#pragma unroll
+      for (int k = 0; k < K; k++)
+#pragma unroll
+        for (int q = 0; q < 2; q++)
+          if (F[k].nf[q] & NB_SELF) X[k].u[q] = zt[k][C[k].lj[q]][C[k].li[q]] + cu.own;
     }
     const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     if (rel <= A.tol) {
@@ -1354,12 +1469,14 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
     for (int j = 0;; j++) {
       // pass j: (j >= 1) n = A m_{j-1} and the recurrences with alpha_{j-1},
       // beta_{j-1}; (j == 0) w_0 = A u_0.  Then the partial sums of pass j
-      // and m_j = M^-1 w_j, published for the neighbours.  zt holds u_0
-      // (j == 0) or m_{j-1} of the tiles on entry.
+      // and m_j = M^-1 w_j: its tile-local part published for the
+      // neighbours, its coarse part from the tile sums of w_j after the
+      // barrier.  zt holds the tile-local part of u_0 (j == 0) or of m_{j-1}
+      // on entry.
       const R al = (R)alpha, bt = (R)beta;
       const R* mprev = A.m[(j + 1) & 1];
       R* mnext = A.m[j & 1];
-      double v[3] = {0.0, 0.0, 0.0};  // (r,u), (w,u), (r,r)
+      double v[4] = {0.0, 0.0, 0.0, 0.0};  // (r,u), (w,u), (r,r), tile sum of w
       R wc[K][2];
 #pragma unroll
       for (int k = 0; k < K; k++)
@@ -1369,10 +1486,12 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
           if (!(F[k].nf[q] & NB_SELF)) continue;
           Cells<R>& Y = X[k];
           if (j == 0) {
-            Y.w[q] = apply_at(F[k], C[k], q, A.u, zt[k], true, nx);
+            Y.w[q] = coarse ? apply_coarse(F[k], C[k], q, A.u, zt[k], nx, cu)
+                            : apply_at(F[k], C[k], q, A.u, zt[k], true, nx);
           } else {
-            const R n = apply_at(F[k], C[k], q, mprev, zt[k], true, nx);
-            const R m = zt[k][C[k].lj[q]][C[k].li[q]];
+            const R n = coarse ? apply_coarse(F[k], C[k], q, mprev, zt[k], nx, cm)
+                               : apply_at(F[k], C[k], q, mprev, zt[k], true, nx);
+            const R m = zt[k][C[k].lj[q]][C[k].li[q]] + cm.own;
             const bool first = j == 1;
             Y.z[q] = first ? n : fma(bt, Y.z[q], n);
             Y.q[q] = first ? m : fma(bt, Y.q[q], m);
@@ -1387,6 +1506,7 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
           v[0] += (double)Y.r[q] * (double)Y.u[q];
           v[1] += (double)Y.w[q] * (double)Y.u[q];
           v[2] += (double)Y.r[q] * (double)Y.r[q];
+          v[3] += (double)Y.w[q];
         }
       __syncthreads();  // the tiles' LDS values are read before the sweeps overwrite them
       tile_precond_k<R, K>(C, T, wc, zt);
@@ -1395,10 +1515,10 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
 #pragma unroll
         for (int q = 0; q < 2; q++)
           if (F[k].nf[q] & NB_SELF) mnext[C[k].o[q]] = zt[k][C[k].lj[q]][C[k].li[q]];
-      block_partials<3>(v, part_buf(A.part, bk + 1), S.vb, G);
+      block_partials<4>(v, part_buf(A.part, bk + 1), S.vb, G);
       if (!grid_sync(A.bar, ++bk, G)) return;
-      double tt[3];
-      grid_totals<3>(part_buf(A.part, bk), G, tt);
+      double tt[4];
+      grid_totals_coarse<4, R>(part_buf(A.part, bk), G, tt, coarse, crows, cm);
       const double gn = tt[0], dn = tt[1], rn = tt[2];
       if (j > 0) {
         total++;
@@ -1425,7 +1545,10 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
     if (!grid_sync(A.bar, ++bk, G)) return;
     sweep++;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *A.iters = total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *A.iters = total;
+    *A.iters_sum += total;
+  }
 }
 
 // Persistent preconditioned CG (M^-1: the tile-block symmetric red-black SOR
@@ -1438,11 +1561,12 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
 template <typename R>
 __global__ void __launch_bounds__(NT2) k_pcg2d_pipe(PcgArgs<R> A) {
   __shared__ R zt[PCG_K][TY2][TX2];
+  __shared__ double crows[5][CMAX2];
   const int nlist = *A.n_list;
   if (nlist < 1 || nlist > PCG_K * A.pipe_blocks) return;  // the other form's case
   const int G = (nlist + PCG_K - 1) / PCG_K;
   if ((int)blockIdx.x >= G) return;
-  pcg_pipelined<R, PCG_K>(A, share_of(G, nlist), G, zt);
+  pcg_pipelined<R, PCG_K>(A, share_of(G, nlist), G, zt, crows);
 }
 
 template <typename R>
@@ -1453,6 +1577,177 @@ __global__ void __launch_bounds__(NT2) k_pcg2d_cg(PcgArgs<R> A) {
   const int G = max(1, min((int)gridDim.x, nlist));
   if ((int)blockIdx.x >= G) return;
   pcg_cg(A, share_of(G, nlist), G, zt);
+}
+
+// ---- coarse space of the preconditioner ----
+// Two-level additive Schwarz (Nicolaides' coarse space): with Z the matrix
+// whose column k is the indicator of active tile k's unknowns, the
+// preconditioner is M^-1 = (tile-block SSOR) + Z (Z^T A Z)^-1 Z^T.  Z^T A Z is
+// symmetric positive definite (A is, and Z has full column rank); it couples
+// each tile with its four face neighbours.  The pipelined solver applies the
+// coarse part with the tile sums of w, which travel with the partial sums of
+// its one grid barrier per iteration; when more tiles are active than CMAX2
+// the solver runs without it.
+
+// row of Z^T A Z of active tile blockIdx.x (list order): sum of A over the
+// tile's own block, and of the couplings to each face-neighbour tile
+__global__ void __launch_bounds__(NT2) k_coarse2d(int nx, int ny, int tiles_x,
+                                                  const int* tile_list, const int* n_list,
+                                                  const uint8_t* __restrict__ nbf,
+                                                  const double* __restrict__ dg,
+                                                  const double* __restrict__ ce,
+                                                  const double* __restrict__ cn,
+                                                  double* __restrict__ crow) {
+  if ((int)blockIdx.x >= *n_list) return;
+  const int tile = tile_list[blockIdx.x];
+  const int i0 = (tile % tiles_x) * TX2, j0 = (tile / tiles_x) * TY2;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // self, E, W, N, S
+  for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+    const int li = cc % TX2, lj = cc / TX2, i = i0 + li, j = j0 + lj;
+    if (i >= nx || j >= ny) continue;
+    const int64_t o = (int64_t)j * nx + i;
+    const uint8_t f = nbf[o];
+    if (!(f & NB_SELF)) continue;
+    v[0] += dg[o];
+    if (f & NB_E) v[li + 1 < TX2 ? 0 : 1] += ce[o];
+    if (f & NB_W) v[li > 0 ? 0 : 2] += ce[o - 1];
+    if (f & NB_N) v[lj + 1 < TY2 ? 0 : 3] += cn[o];
+    if (f & NB_S) v[lj > 0 ? 0 : 4] += cn[o - nx];
+  }
+  __shared__ double sh[5][NT2 / 64];
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    const double t = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    double t = 0.0;
+    for (int w = 0; w < NT2 / 64; w++) t += sh[threadIdx.x][w];
+    crow[5 * (int64_t)blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+// (Z^T A Z)^-1 of the nc <= CMAX2 active tiles: the dense matrix in LDS,
+// inverted in place by Gauss-Jordan elimination without pivoting (an SPD
+// matrix needs none), written to cinv[nc][nc].  One block.
+//
+// The inverse is kept while the active tiles stay the same, for up to
+// CINV_AGE solves: any SPD matrix in its place still gives an SPD
+// preconditioner, and the operator changes little from one step to the next.
+//
+// The coarse space pays off when the operator couples the tiles strongly,
+// i.e. when the pressure's decay length (the screening of the s22 term) spans
+// several tiles; when it is shorter than a tile the tile-local part already
+// holds the solution's structure and the additive coarse term only adds to
+// the spectrum.  Measure: rho = max over tiles of (sum of the couplings to
+// the neighbour tiles) / (diagonal) of Z^T A Z, which tends to 1 as the
+// screening vanishes; the coarse space is used when rho >= CRHO.
+//
+// used[0] = nc of the stored inverse (-1: none), used[1] = solves since it was
+// made, used[2] = 1 when the solver uses it, used[3 ..] = its tile list.
+constexpr int CINV_AGE = 16;
+constexpr double CRHO = 0.95;
+
+__global__ void __launch_bounds__(1024) k_coarse_inv2d(int tiles_x, int tiles_y,
+                                                       const int* tile_list, const int* n_list,
+                                                       const int* tile_pos,
+                                                       const double* __restrict__ crow,
+                                                       double* __restrict__ cinv, int* used) {
+  const int nc = *n_list;
+  if (nc < 1 || nc > CMAX2) {
+    if (threadIdx.x == 0) {
+      used[0] = -1;
+      used[2] = 0;
+    }
+    return;
+  }
+  __shared__ int keep;
+  if (threadIdx.x == 0) keep = (used[0] == nc && used[1] + 1 < CINV_AGE) ? 1 : 0;
+  __syncthreads();
+  if (keep) {
+    if ((int)threadIdx.x < nc && used[3 + threadIdx.x] != tile_list[threadIdx.x]) keep = 0;
+    __syncthreads();
+    if (keep) {
+      if (threadIdx.x == 0) used[1] += 1;
+      return;
+    }
+  }
+  __shared__ double M[CMAX2][CMAX2];
+  __shared__ double col[CMAX2];
+  __shared__ double rho_w[1024 / 64];
+  for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) M[e / nc][e % nc] = 0.0;
+  __syncthreads();
+  double rho = 0.0;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const int tile = tile_list[i], tx = tile % tiles_x, ty = tile / tiles_x;
+    const double* r = crow + 5 * (int64_t)i;
+    M[i][i] = r[0];
+    double off = 0.0;
+    if (tx + 1 < tiles_x && tile_pos[tile + 1] >= 0) {
+      M[i][tile_pos[tile + 1]] = r[1];
+      off += fabs(r[1]);
+    }
+    if (tx > 0 && tile_pos[tile - 1] >= 0) {
+      M[i][tile_pos[tile - 1]] = r[2];
+      off += fabs(r[2]);
+    }
+    if (ty + 1 < tiles_y && tile_pos[tile + tiles_x] >= 0) {
+      M[i][tile_pos[tile + tiles_x]] = r[3];
+      off += fabs(r[3]);
+    }
+    if (ty > 0 && tile_pos[tile - tiles_x] >= 0) {
+      M[i][tile_pos[tile - tiles_x]] = r[4];
+      off += fabs(r[4]);
+    }
+    rho = fmax(rho, off / r[0]);
+  }
+  rho = wave_max(rho);
+  if ((threadIdx.x & 63) == 0) rho_w[threadIdx.x >> 6] = rho;
+  __syncthreads();
+  rho = rho_w[0];
+  for (int w = 1; w < 1024 / 64; w++) rho = fmax(rho, rho_w[w]);
+  if (!(rho >= CRHO)) {  // the coarse space would not help: recorded, not inverted
+    if ((int)threadIdx.x < nc) used[3 + threadIdx.x] = tile_list[threadIdx.x];
+    if (threadIdx.x == 0) {
+      used[0] = nc;
+      used[1] = 0;
+      used[2] = 0;
+    }
+    return;
+  }
+  // thread (ty, tx) of a 32 x 32 layout updates rows ty + 32 a, columns tx + 32 b
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = 0; k < nc; k++) {
+    const double inv = 1.0 / M[k][k];
+    // column k kept, row k scaled (off the pivot)
+    if ((int)threadIdx.x < nc) {
+      const int e = threadIdx.x;
+      col[e] = M[e][k];
+      if (e != k) M[k][e] *= inv;
+    }
+    __syncthreads();
+    for (int i = ty; i < nc; i += 32) {
+      const double ci = col[i];
+      for (int j = tx; j < nc; j += 32) {
+        if (i == k) {
+          if (j == k) M[k][k] = inv;
+        } else if (j == k) {
+          M[i][k] = -ci * inv;
+        } else {
+          M[i][j] -= ci * M[k][j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nc * nc; e += blockDim.x) cinv[e] = M[e / nc][e % nc];
+  if ((int)threadIdx.x < nc) used[3 + threadIdx.x] = tile_list[threadIdx.x];
+  if (threadIdx.x == 0) {
+    used[0] = nc;
+    used[1] = 0;
+    used[2] = 1;
+  }
 }
 
 __global__ void k_bar_reset(unsigned long long* count, unsigned* tflag, int ntiles) {
@@ -1559,10 +1854,14 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.bar.count = x->bar;
   A.bar.status = x->status;
   A.iters = x->iters;
+  A.iters_sum = x->iters_sum;
   A.rel = x->rel;
   A.tol = c->tol;
   A.max_iter = c->max_iter;
   A.pipe_blocks = x->grid_pipe;
+  A.tile_pos = x->tile_pos;
+  A.cinv = x->cinv;
+  A.cused = x->cused;
   return A;
 }
 
@@ -1610,6 +1909,15 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
   hipLaunchKernelGGL(k_bar_reset, dim3((x->ntiles + 255) / 256), dim3(256), 0, s, x->bar, x->tflag,
                      x->ntiles);
+  // coarse operator of the active tiles (the inversion exits when there are
+  // more than CMAX2 of them, and then the solver does without)
+  hipLaunchKernelGGL(k_coarse2d, dim3(std::min(x->ntiles, CMAX2)), dim3(NT2), 0, s, x->nx, x->ny,
+                     x->tiles_x, (const int*)x->tile_list, (const int*)x->n_tiles_act,
+                     (const uint8_t*)x->nb, (const double*)x->dg, (const double*)x->ce,
+                     (const double*)x->cn, x->crow);
+  hipLaunchKernelGGL(k_coarse_inv2d, dim3(1), dim3(1024), 0, s, x->tiles_x, x->tiles_y,
+                     (const int*)x->tile_list, (const int*)x->n_tiles_act,
+                     (const int*)x->tile_pos, (const double*)x->crow, x->cinv, x->cused);
   if (c->precision == 1) {
     const PcgArgs<float> A = pcg_args32(c, x);
     hipLaunchKernelGGL(k_pcg2d_pipe<float>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
@@ -1648,6 +1956,10 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->tile_cnt = (int*)take(4 * x->ntiles);
   x->tspeed = (double*)take(8 * (size_t)x->ntiles);
   x->tile_list = (int*)take(4 * x->ntiles);
+  x->tile_pos = (int*)take(4 * x->ntiles);
+  x->crow = (double*)take(8 * 5 * (size_t)x->ntiles);
+  x->cinv = (double*)take(8 * (size_t)CMAX2 * CMAX2);
+  x->cused = (int*)take(4 * (size_t)(CMAX2 + 3));
   x->n_tiles_act = (int*)take(4);
   x->n_act = (int*)take(4);
   x->dg = (double*)take(8 * N);
@@ -1669,6 +1981,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->bar = (unsigned long long*)take(8);
   x->tflag = (unsigned*)take(4 * (size_t)x->ntiles);
   x->iters = (int*)take(4);
+  x->iters_sum = (long long*)take(8);
   x->rel = (double*)take(8);
   if (c->warm == 2) {
     x->cnn_bytes = cnn_layout(1, c->ny, c->nx).bytes;
@@ -1709,6 +2022,11 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   if (hipMemcpy(x->n_tiles_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   if (hipMemcpy(x->n_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   if (hipMemcpy(x->iters, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  const long long zl = 0;
+  if (hipMemcpy(x->iters_sum, &zl, 8, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  const int none[3] = {-1, 0, 0};  // no coarse inverse yet
+  if (hipMemcpy(x->cused, none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess)
+    return SWE_NH_EHIP;
   (void)s;
   return SWE_NH_OK;
 }
@@ -1719,7 +2037,7 @@ static void enqueue_nh2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const 
                          const double* p_prev, double* hu, double* hv, double* hw, double* p) {
   const G2 G = make_g2(c, x);
   hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
-                     x->n_tiles_act, x->n_act);
+                     x->n_tiles_act, x->n_act, x->tile_pos);
   hipLaunchKernelGGL(k_assemble2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
                      x->tile_list, x->n_tiles_act, t_in, dt_in, sys_of(x), p_prev,
                      (int)(p_prev != nullptr));
@@ -1757,7 +2075,7 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
     enqueue_nh2d(c, x, s, x->ht, x->mt, x->nt, x->kt, M, x->t, x->dt, guess, hu, hv, hw, p);
   } else {
     hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
-                       x->n_tiles_act, x->n_act);
+                       x->n_tiles_act, x->n_act, x->tile_pos);
   }
   // the new state's speed (tiles written by the mask pass and the projection)
   // -> dt of the next step; time and step counter advance
@@ -1786,7 +2104,7 @@ void launch_mask2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const 
                      dt_in, mode, mask, x->tile_cnt, nullptr, nullptr, nullptr, nullptr, nullptr,
                      0);
   hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
-                     x->n_tiles_act, x->n_act);
+                     x->n_tiles_act, x->n_act, x->tile_pos);
 }
 
 void solve_pressure2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
@@ -1810,7 +2128,7 @@ void correct2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht
   const int64_t N = (int64_t)x->nx * x->ny;
   hipLaunchKernelGGL(k_count2d, dim3(x->ntiles), dim3(NT2), 0, s, G, mask, x->tile_cnt);
   hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
-                     x->n_tiles_act, x->n_act);
+                     x->n_tiles_act, x->n_act, x->tile_pos);
   launch_copy(mt, m_out, N, s);
   launch_copy(nt, n_out, N, s);
   launch_copy(kt, k_out, N, s);

@@ -611,6 +611,10 @@ int swe_nh_sync_stats(swe_nh_ctx* c, swe_nh_stats* out) {
   out->dt = dt;
   out->t = t;
   out->steps = c->steps_taken;
+  long long itsum = 0;
+  if (c->cfg.dim == 2)
+    HIPCHK(c, hipMemcpy(&itsum, c->c2.iters_sum, sizeof(long long), hipMemcpyDeviceToHost));
+  out->iters_total = itsum;
   int z = 0;
   HIPCHK(c, hipMemcpy(c->status, &z, sizeof(int), hipMemcpyHostToDevice));
   return SWE_NH_OK;

@@ -42,7 +42,7 @@ class swe_nh_config(C.Structure):
 class swe_nh_stats(C.Structure):
     _fields_ = [("n_active", C.c_int64), ("iters", C.c_int32), ("status", C.c_int32),
                 ("rel_res", C.c_double), ("dt", C.c_double), ("t", C.c_double),
-                ("steps", C.c_int64)]
+                ("steps", C.c_int64), ("iters_total", C.c_int64)]
 
 
 class SweNhError(RuntimeError):

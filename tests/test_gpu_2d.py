@@ -220,3 +220,39 @@ def test_many_tiles_per_solver_block(B, precision):
     bar = 1e-10 if precision == 0 else 1e-6
     for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
         assert rel(g, r) <= bar
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 256), (288, 256), (100, 40)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solver_around_the_coarse_space_limit(B, nx, ny, precision):
+    """global extension with 128 active tiles (the most the solver's coarse
+    space takes), 144 (the pipelined solver without it) and a few ragged
+    tiles: same results as the oracle"""
+    c = S.random_case_2d(nx, ny, seed=43, dx=1.0, dy=1.0, h0=10.0)
+    tol = 1e-13 if precision == 0 else 1e-11
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=5000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 2, **kw)
+    assert st["status"] == 0, st
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_GLOBAL, tol=1e-14), cfl=0.4).step(2)
+    bar = 1e-10 if precision == 0 else 1e-6
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= bar
+
+
+def test_iteration_total_accumulates(B):
+    """stats.iters_total sums the PCG iterations of every solve since init
+    (what the benchmark divides by the steps of one multi-step call)"""
+    c = case(nx=80, ny=64, seed=5)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=4e-3, cfl=0.4, precision=1, tol=1e-10, max_iter=5000)
+    ctx = B.context_2d(c, **kw)
+    ctx.set_time(c.t0)
+    h, hu, hv, hw = dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw)
+    p = torch.zeros_like(h)
+    assert ctx.sync_stats()["iters_total"] == 0
+    per_step = []
+    for _ in range(4):
+        ctx.step(h, hu, hv, hw, p)
+        st = ctx.sync_stats()
+        assert st["status"] == 0, st
+        per_step.append(st["iters"])
+    assert st["iters_total"] == sum(per_step) and sum(per_step) > 0
