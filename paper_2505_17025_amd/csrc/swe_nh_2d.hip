@@ -77,7 +77,7 @@ G2 make_g2(const swe_nh_config* c, const Ctx2D* x) {
 __device__ __forceinline__ double depth2(const G2& G, const Chan& c, const Motion& M, int i,
                                          int j) {
   const double x = (i + 0.5) * G.dx, y = (j + 0.5) * G.dy;
-  return G.ds[(int64_t)j * G.nx + i] - body_shape(c, x - M.X, y - c.y0).B;
+  return G.ds[(int64_t)j * G.nx + i] - body_B(c, x - M.X, y - c.y0);
 }
 
 // ---------------------------------------------------------------------------
@@ -215,19 +215,16 @@ __device__ __forceinline__ Flux2 face2d(const P2& S, const double* d, double g, 
   const double sar = minmod(t1[wr] - t1[wr - s], t1[wr + s] - t1[wr]);
   const double skr = minmod(S.k[wr] - S.k[wr - s], S.k[wr + s] - S.k[wr]);
   const double sdr = minmod(d[wr] - d[wr - s], d[wr + s] - d[wr]);
-  return rusanov2d(g, S.e[wl] + 0.5 * sel, nm[wl] + 0.5 * sml, t1[wl] + 0.5 * sal,
-                   S.k[wl] + 0.5 * skl, d[wl] + 0.5 * sdl, S.e[wr] - 0.5 * ser, nm[wr] - 0.5 * smr,
-                   t1[wr] - 0.5 * sar, S.k[wr] - 0.5 * skr, d[wr] - 0.5 * sdr);
-}
-
-// centred bed source g (h-_{+} + h+_{-}) / 2 * slope(d) / dx of a cell along one direction
-__device__ __forceinline__ double bed_src(const P2& S, const double* d, double g, int w, int s,
-                                          double inv) {
-  const double se = minmod(S.e[w] - S.e[w - s], S.e[w + s] - S.e[w]);
-  const double sd = minmod(d[w] - d[w - s], d[w + s] - d[w]);
-  const double hp = (S.e[w] + 0.5 * se) + (d[w] + 0.5 * sd);
-  const double hm = (S.e[w] - 0.5 * se) + (d[w] - 0.5 * sd);
-  return g * 0.5 * (hp + hm) * sd * inv;
+  const double eL = S.e[wl] + 0.5 * sel, dL = d[wl] + 0.5 * sdl;
+  const double eR = S.e[wr] - 0.5 * ser, dR = d[wr] - 0.5 * sdr;
+  Flux2 F = rusanov2d(g, eL, nm[wl] + 0.5 * sml, t1[wl] + 0.5 * sal, S.k[wl] + 0.5 * skl, dL, eR,
+                      nm[wr] - 0.5 * smr, t1[wr] - 0.5 * sar, S.k[wr] - 0.5 * skr, dR);
+  // the centred bed source g h (d slope) / 2 of each side's cell with its
+  // reconstructed depth at this face: a cell's normal-momentum update is then
+  // the difference of its two faces' values
+  F.FmL -= 0.5 * g * (eL + dL) * sdl;
+  F.FmR += 0.5 * g * (eR + dR) * sdr;
+  return F;
 }
 
 // L of one stage on the region of RXs x RYs cells at window offset O; the
@@ -268,9 +265,8 @@ __device__ void stage2d(P2& S, const double* d, const G2& G, int i0, int j0, dou
     if (!inreg(wi, wj)) continue;
     const int ri = wi - O, rj = wj - O;
     const int fl = rj * (RXs + 1) + ri, fr = fl + 1;
-    const int w = W(wi, wj);
     L[q][0] = -(S.F0[fr] - S.F0[fl]) * idx;
-    L[q][1] = -(S.F1[fr] - S.F2[fl]) * idx + bed_src(S, d, G.g, w, 1, idx);
+    L[q][1] = -(S.F1[fr] - S.F2[fl]) * idx;
     L[q][2] = -(S.F3[fr] - S.F3[fl]) * idx;
     L[q][3] = -(S.F4[fr] - S.F4[fl]) * idx;
   }
@@ -298,9 +294,8 @@ __device__ void stage2d(P2& S, const double* d, const G2& G, int i0, int j0, dou
     if (!inreg(wi, wj)) continue;
     const int ri = wi - O, rj = wj - O;
     const int fs = rj * RXs + ri, fn = fs + RXs;
-    const int w = W(wi, wj);
     L[q][0] += -(S.F0[fn] - S.F0[fs]) * idy;
-    L[q][2] += -(S.F1[fn] - S.F2[fs]) * idy + bed_src(S, d, G.g, w, WX, idy);
+    L[q][2] += -(S.F1[fn] - S.F2[fs]) * idy;
     L[q][1] += -(S.F3[fn] - S.F3[fs]) * idy;
     L[q][3] += -(S.F4[fn] - S.F4[fs]) * idy;
   }
@@ -975,7 +970,8 @@ __device__ __forceinline__ TileCells<R> tile_cells(const PcgArgs<R>& A, int tile
 // tile dropped)
 template <typename R>
 struct TileOp {
-  R dg[2], cE[2], cW[2], cN[2], cS[2];
+  R wdg[2];  // GS_OMEGA / diagonal
+  R cE[2], cW[2], cN[2], cS[2];
 };
 
 template <typename R>
@@ -985,7 +981,7 @@ __device__ __forceinline__ TileOp<R> tile_op(const PcgArgs<R>& A, const TileCell
   for (int q = 0; q < 2; q++) {
     const int64_t o = C.o[q];
     const uint8_t f = C.nb[q];
-    T.dg[q] = (f & NB_SELF) ? A.dgR[o] : R(1);
+    T.wdg[q] = (R)GS_OMEGA / ((f & NB_SELF) ? A.dgR[o] : R(1));
     T.cE[q] = (f & NB_E) ? A.ceR[o] : R(0);
     T.cW[q] = (f & NB_W) ? A.ceR[o - 1] : R(0);
     T.cN[q] = (f & NB_N) ? A.cnR[o] : R(0);
@@ -1014,7 +1010,7 @@ __device__ void tile_precond(const TileCells<R>& C, const TileOp<R>& T, const R 
       if (C.nb[q] & NB_W) a -= T.cW[q] * z[lj][li - 1];
       if (C.nb[q] & NB_N) a -= T.cN[q] * z[lj + 1][li];
       if (C.nb[q] & NB_S) a -= T.cS[q] * z[lj - 1][li];
-      z[lj][li] = (R(1) - om) * z[lj][li] + om * a / T.dg[q];
+      z[lj][li] = (R(1) - om) * z[lj][li] + T.wdg[q] * a;
     }
     __syncthreads();
   }
@@ -1050,7 +1046,7 @@ __device__ __forceinline__ TileOp<R> restrict_op(const FullOp<R>& F, const TileC
   TileOp<R> T;
 #pragma unroll
   for (int q = 0; q < 2; q++) {
-    T.dg[q] = F.dg[q];
+    T.wdg[q] = (R)GS_OMEGA / F.dg[q];
     T.cE[q] = (C.nb[q] & NB_E) ? F.cE[q] : R(0);
     T.cW[q] = (C.nb[q] & NB_W) ? F.cW[q] : R(0);
     T.cN[q] = (C.nb[q] & NB_N) ? F.cN[q] : R(0);
@@ -1276,7 +1272,7 @@ __device__ void tile_precond_k(const TileCells<R> (&C)[K], const TileOp<R> (&T)[
         if (f & NB_W) a -= T[k].cW[q] * z[k][lj][li - 1];
         if (f & NB_N) a -= T[k].cN[q] * z[k][lj + 1][li];
         if (f & NB_S) a -= T[k].cS[q] * z[k][lj - 1][li];
-        z[k][lj][li] = (R(1) - om) * z[k][lj][li] + om * a / T[k].dg[q];
+        z[k][lj][li] = (R(1) - om) * z[k][lj][li] + T[k].wdg[q] * a;
       }
     __syncthreads();
   }

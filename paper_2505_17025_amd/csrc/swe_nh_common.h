@@ -111,6 +111,23 @@ __device__ __forceinline__ Shape body_shape(const Chan& c, double xi, double zet
   return s;
 }
 
+// B alone (the depth needs nothing else), with the arithmetic of body_shape.
+// Far from the Gaussian mound the exponential is not evaluated: beyond
+// (xi^2 + zeta^2) / len^2 > 80 it is below amp e^-80 ~ 2e-35 amp, which no
+// depth of a wet cell registers.
+__device__ __forceinline__ double body_B(const Chan& c, double xi, double zeta) {
+  if (c.kind == SWE_NH_BODY_QUARTIC) {
+    if (!(fabs(xi) < 0.5 * c.len)) return 0.0;
+    const double z = xi * (2.0 / c.len), z2 = z * z;
+    return c.amp * (1.0 - z2 * z2);
+  }
+  if (c.kind == SWE_NH_BODY_GAUSS) {
+    const double q = (xi * xi + zeta * zeta) * (1.0 / (c.len * c.len));
+    return q > 80.0 ? 0.0 : c.amp * exp(-q);
+  }
+  return 0.0;
+}
+
 // time derivatives of the moving bottom d = d_s - B(x - X(t), y - y0)
 struct BedRate {
   double d_t, d_tt, d_xt, d_yt;
