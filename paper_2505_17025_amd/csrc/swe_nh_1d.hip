@@ -25,7 +25,7 @@ namespace swenh {
 __global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict__ h,
                                                  const double* __restrict__ hu,
                                                  const double* __restrict__ hw) {
-  const int2 tl = P.tiles[blockIdx.x];
+  const int4 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int end = min(tl.y + P.tile, c.n);
   double s = 0.0;
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
   constexpr int Q = (R1 + NT - 1) / NT;
   __shared__ PredSmem<T> S;
   __shared__ int sflags;
-  const int2 tl = P.tiles[blockIdx.x];
+  const int4 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, base = start - HALO;  // window cell e <-> channel cell base+e
   const int end = min(start + P.tile, n);
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(256) k_mask1d(K1D P, const double* __restrict_
                                                 int write_state) {
   __shared__ uint8_t raw[TILE_MAX + 2 * MAXE];
   __shared__ int cnt[4];
-  const int2 tl = P.tiles[blockIdx.x];
+  const int4 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int n = c.n, start = tl.y, end = min(start + P.tile, n);
   const int e = P.enlarge;
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(256) k_mask1d(K1D P, const double* __restrict_
 // tile counts of a caller-supplied mask
 __global__ void __launch_bounds__(256) k_count1d(K1D P, const uint8_t* __restrict__ mask) {
   __shared__ int cnt[4];
-  const int2 tl = P.tiles[blockIdx.x];
+  const int4 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int end = min(tl.y + P.tile, c.n);
   int local = 0;
@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int*
 // packed list of marked cells in cell order
 __global__ void __launch_bounds__(256) k_compact1d(K1D P, const uint8_t* __restrict__ mask) {
   __shared__ int wsum[4];
-  const int2 tl = P.tiles[blockIdx.x];
+  const int4 tl = P.tiles[blockIdx.x];
   const Chan c = P.ch[tl.x];
   const int end = min(tl.y + P.tile, c.n);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -675,6 +675,7 @@ struct StepSmem {
   } u;
   uint8_t raw[T + 2 + 2 * EMAXF];
   uint8_t mk[T + 2];
+  short cell_of[RW];  // tile system row -> tile cell
 };
 
 // minmod slopes of eta, hu, hw and the depth on window cells [c0, c1) of a
@@ -765,12 +766,12 @@ __device__ CellNH cell_win(const WinQ& Q, const K1D& P, const Chan& c, const Mot
   const double dxx = (dr - 2.0 * d0 + dl) * (Q.idx * Q.idx);
   const double ex = ((Q.H(s + 1) - dr) - (Q.H(s - 1) - dl)) * Q.i2dx;
   const double hs = Q.H(s);
-  const double u = Q.Mo(s) / hs;
+  const double u = Q.Mo(s) * rcp64(hs);
   const BedRate br = bed_rate(M, body_shape(c, (s + 0.5) * Q.dx - M.X, 0.0));
   CellNH q;
   q.D = D;
   q.al = 4.0 + D * D;
-  q.phi = P.rho * hs / q.al * (P.g * D * ex - br.d_tt - 2.0 * u * br.d_xt - u * u * dxx);
+  q.phi = P.rho * hs * rcp64(q.al) * (P.g * D * ex - br.d_tt - 2.0 * u * br.d_xt - u * u * dxx);
   return q;
 }
 
@@ -782,9 +783,10 @@ __device__ FaceNH face_win(const WinQ& Q, const K1D& P, double dt, int f, double
   const double Df = (Q.D(f) - Q.D(f - 1)) * Q.idx;
   const double hx = (hr - hl) * Q.idx;
   const double af = 4.0 + Df * Df;
-  const double s11 = (2.0 * hx - 3.0 * Df) / (2.0 * hf);
+  const double rhf = rcp64(hf);
+  const double s11 = (hx - 1.5 * Df) * rhf;
   FaceNH q;
-  q.K = 4.0 * dt * hf / (P.rho * af);
+  q.K = 4.0 * dt * hf * rcp64(P.rho * af);
   q.a = -Q.idx + 0.5 * s11;
   q.b = Q.idx + 0.5 * s11;
   q.fd = dt / P.rho * (0.5 * (phil + phir)) * Df;
@@ -833,7 +835,7 @@ __device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
       Y.a[i] = na[j];
       Y.b[i] = nb[j];
       Y.c[i] = nc[j];
-      Y.r[i] = 1.0 / nb[j];
+      Y.r[i] = rcp64(nb[j]);
 #pragma unroll
       for (int r = 0; r < 3; r++) Y.d[r][i] = nd[j][r];
     }
@@ -859,16 +861,17 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   constexpr int Q = (WMAX - 4 + NT - 1) / NT;  // window cells per thread
   __shared__ SM S;
   __shared__ int sflags;
-  const int2 tl = P.tiles[blockIdx.x];
-  const Chan c = P.ch[tl.x];
-  const int n = c.n, start = tl.y, end = min(start + P.tile, n), len = end - start;
+  const int4 tl = P.tiles[blockIdx.x];
+  const Chan c = P.ch[tl.x];  // body parameters, needed after the first loads
+  const int n = tl.w, start = tl.y, end = min(start + P.tile, n), len = end - start;
+  const int64_t off = tl.z;
   const int step = P.step[par];
   const double dt =
       (P.cfl > 0.0)
           ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[par * P.nch + tl.x])
           : P.dt_fixed;
   const double t0 = P.t[par * P.nch + tl.x], t1 = t0 + dt;
-  if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) {
+  if (start == 0 && threadIdx.x == 0) {  // the channel's first tile
     P.dt[tl.x] = dt;
     P.t[(par ^ 1) * P.nch + tl.x] = t1;  // the next step's start time
   }
@@ -893,7 +896,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     if (w >= W) continue;
     const int i = lo + w;
     const int s = reflect(max(-n, min(i, 2 * n - 1)), n);
-    const int64_t gi = c.off + s;
+    const int64_t gi = off + s;
     vh[q] = h[gi];
     vm[q] = (s == i ? 1.0 : -1.0) * hu[gi];
     vk[q] = hw[gi];
@@ -1031,7 +1034,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     const int k = 1 + threadIdx.x + NT * q;
     if (k > len) continue;
     const int i = start + k - 1, w = i - lo;
-    const int64_t gi = c.off + i;
+    const int64_t gi = off + i;
     const bool on = S.mk[k] != 0;
     const double hh = S.e[w], mm = S.m[w], kk = S.k[w];
     mask[gi] = on;
@@ -1081,7 +1084,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     const FaceNH fl = S.u.q.fq[k - 1], fr = S.u.q.fq[k];
     const CellNH c0 = S.u.q.cq[k];
     const double hs = S.e[w], ms = S.m[w], ks = S.k[w];
-    const double rh = 1.0 / hs, dtr = dt / P.rho;
+    const double rh = rcp64(hs), dtr = dt / P.rho;
     const double s22 = 3.0 * dtr * rh;
     const BedRate br = bed_rate(M1, body_shape(c, (i + 0.5) * P.dx - M1.X, 0.0));
     const double f2 = -2.0 * br.d_t - (2.0 * ks + 0.5 * c0.D * ms + 0.5 * dtr * c0.al * c0.phi) * rh;
@@ -1089,7 +1092,8 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     rb[q] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
     rc[q] = (i + 1 < n && S.mk[k + 1]) ? fr.K * fr.a * fr.b : 0.0;
     rd[q] = f2 + fl.b * fl.qp + fr.a * fr.qp;
-    double* z = P.zw + pb + rank[q];
+    S.cell_of[rank[q]] = (short)(k - 1);
+    double* z = P.zw + pb + (k - 1);  // in cell order: the projection needs no ranks
     z[ZW_KL * zs] = fl.K;
     z[ZW_AL * zs] = fl.a;
     z[ZW_BL * zs] = fl.b;
@@ -1132,9 +1136,10 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       P.dg1[L] = asL ? Y.b[0] : 1.0;
       P.up1[L] = asL ? Y.c[0] : 0.0;
       P.rh1[L] = asL ? Y.d[0][0] : 0.0;
-      P.zw[pb + ZW_Z * zs] = 0.0;
-      P.zw[pb + ZW_U * zs] = asL ? 0.0 : 1.0;
-      P.zw[pb + ZW_V * zs] = asL ? 1.0 : 0.0;
+      const int64_t cz = pb + S.cell_of[0];
+      P.zw[cz + ZW_Z * zs] = 0.0;
+      P.zw[cz + ZW_U * zs] = asL ? 0.0 : 1.0;
+      P.zw[cz + ZW_V * zs] = asL ? 1.0 : 0.0;
     }
     return;
   }
@@ -1152,15 +1157,16 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     }
     Y.d[1][j] = first ? 1.0 : 0.0;
     Y.d[2][j] = last ? 1.0 : 0.0;
-    Y.r[j] = 1.0 / Y.b[j];
+    Y.r[j] = rcp64(Y.b[j]);
   }
   __syncthreads();
   pcr_tile<T, NT>(S, m);
   for (int j = threadIdx.x; j < m; j += NT) {
     const double ib = Y.r[j];
-    P.zw[pb + j + ZW_Z * zs] = Y.d[0][j] * ib;
-    P.zw[pb + j + ZW_U * zs] = Y.d[1][j] * ib;
-    P.zw[pb + j + ZW_V * zs] = Y.d[2][j] * ib;
+    const int64_t cz = pb + S.cell_of[j];
+    P.zw[cz + ZW_Z * zs] = Y.d[0][j] * ib;
+    P.zw[cz + ZW_U * zs] = Y.d[1][j] * ib;
+    P.zw[cz + ZW_V * zs] = Y.d[2][j] * ib;
   }
   if (threadIdx.x == 0) {
     const double z1 = Y.d[0][1] * Y.r[1], u1 = Y.d[1][1] * Y.r[1], v1 = Y.d[2][1] * Y.r[1];
@@ -1191,30 +1197,32 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   __shared__ int rcnt[(L1 + 1) / 2];
   __shared__ int tpos[(L1 + 1) / 2], tlist[(L1 + 1) / 2];  // tile <-> compact level-1 tile
   __shared__ int wc[NT / 64];
-  const int2 tl = P.tiles[blockIdx.x];
-  const Chan c = P.ch[tl.x];
-  const int n = c.n, start = tl.y, end = min(start + P.tile, n), len = end - start;
+  const int4 tl = P.tiles[blockIdx.x];
+  const int n = tl.w, start = tl.y, end = min(start + P.tile, n), len = end - start;
+  const int64_t off = tl.z;
   const double dt = P.dt[tl.x];
   // the speed buffer this step read collects the speed of the step after next
-  if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.smax[par * P.nch + tl.x] = 0ull;
+  if (start == 0 && threadIdx.x == 0) P.smax[par * P.nch + tl.x] = 0ull;
   const int m = P.tile_cnt[blockIdx.x];
   if (m == 0) return;  // no marked cell: the step kernel already took this tile's speed
   double smax = 0.0;
   int flags = 0;
   {
-    // the tile's marked rows and their stored data first: the loads are in
-    // flight while the level-1 system is solved
-    int rank[T / NT];
+    // the tile's marked cells and their stored data (cell order) first, in
+    // one round of loads (the data of unmarked cells is read and ignored):
+    // they are in flight while the level-1 system is solved
     bool on[T / NT];
-    const int64_t m0 = c.off + start - 1;  // mask[m0 + k]: tile-local cell k
-    tile_ranks<T, NT>([&](int k) { return k <= len && mask[m0 + k] != 0; }, rank, on);
+    const int64_t m0 = off + start - 1;  // mask[m0 + k]: tile-local cell k
     const int64_t zs = (int64_t)P.ntiles * T;
     const int64_t pb = (int64_t)blockIdx.x * T;
     double zr[T / NT][ZW_N];
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
-      if (!on[q]) continue;
-      const double* z = P.zw + pb + rank[q];
+      const int k = 1 + threadIdx.x + NT * q;
+      on[q] = false;
+      if (k > len) continue;
+      on[q] = mask[m0 + k] != 0;
+      const double* z = P.zw + pb + (k - 1);
 #pragma unroll
       for (int v = 0; v < ZW_N; v++) zr[q][v] = z[v * zs];
     }
@@ -1276,7 +1284,7 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
           lc[j] = 0.0;
           ld[j] = 0.0;
         }
-        lr[j] = 1.0 / lb[j];
+        lr[j] = rcp64(lb[j]);
       }
       __syncthreads();
       for (int s = 1; s < n1; s <<= 1) {
@@ -1313,7 +1321,7 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
           lb[i] = nb[r];
           lc[i] = nc[r];
           ld[i] = nd[r];
-          lr[i] = 1.0 / nb[r];
+          lr[i] = rcp64(nb[r]);
         }
         __syncthreads();
       }
@@ -1335,7 +1343,7 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
     for (int q = 0; q < T / NT; q++) {
       if (!on[q]) continue;
       const int k = 1 + threadIdx.x + NT * q;
-      const int64_t gi = c.off + start + k - 1;
+      const int64_t gi = off + start + k - 1;
       const double* z = zr[q];
       const double pc = xs[k], pl = xs[k - 1], pr = xs[k + 1];
       const double dql = z[ZW_FL] - z[ZW_KL] * (z[ZW_AL] * pl + z[ZW_BL] * pc);

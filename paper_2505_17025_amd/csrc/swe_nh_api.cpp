@@ -59,7 +59,7 @@ struct swe_nh_ctx {
   double* stage_dt = nullptr;
   // 1D
   K1D k1{};
-  std::vector<int2> tiles;
+  std::vector<int4> tiles;
   double *ht = nullptr, *mt = nullptr, *kt = nullptr;
   uint8_t* mask_ws = nullptr;
   TriLevels<double> T64{};
@@ -155,13 +155,16 @@ int cap_of(const swe_nh_config* c) {
   return t <= 128 ? 128 : t <= 256 ? 256 : 512;
 }
 
-void tile_table(const swe_nh_config* c, std::vector<int2>* tiles, std::vector<int>* first) {
+// per tile: (channel, first cell, packed offset of the channel, cells of the
+// channel), so that a block has every index it needs from one load
+void tile_table(const swe_nh_config* c, std::vector<int4>* tiles, std::vector<int>* first) {
   const int nch = n_channels(c);
   const int T = tile_of(c);
   for (int b = 0; b < nch; b++) {
     const int64_t n = c->offsets ? c->offsets[b + 1] - c->offsets[b] : c->nx;
     first->push_back((int)tiles->size());
-    for (int64_t s = 0; s < n; s += T) tiles->push_back(make_int2(b, (int)s));
+    const int off = c->offsets ? (int)c->offsets[b] : 0;
+    for (int64_t s = 0; s < n; s += T) tiles->push_back(make_int4(b, (int)s, off, (int)n));
   }
 }
 
@@ -188,7 +191,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   Carve cv{base};
   const int nch = n_channels(c);
   const int64_t N = total_cells(c);
-  std::vector<int2> tiles;
+  std::vector<int4> tiles;
   std::vector<int> first;
   tile_table(c, &tiles, &first);
   const int ntiles = (int)tiles.size();
@@ -196,7 +199,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   swe_nh_ctx* x = ctx ? ctx : &tmp;
   K1D& P = x->k1;
   P.ch = cv.take<Chan>(nch);
-  P.tiles = cv.take<int2>(ntiles);
+  P.tiles = cv.take<int4>(ntiles);
   P.first_tile = cv.take<int>(nch);
   P.t = cv.take<double>(2 * (size_t)nch);
   P.dt = cv.take<double>(nch);
@@ -451,7 +454,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
     rc = SWE_NH_EHIP;
   INIT_COPY(P.ch, ch.data(), sizeof(Chan) * c->nch);
   if (cfg->dim == 1) {
-    INIT_COPY(P.tiles, c->tiles.data(), sizeof(int2) * c->tiles.size());
+    INIT_COPY(P.tiles, c->tiles.data(), sizeof(int4) * c->tiles.size());
     INIT_COPY(P.first_tile, first.data(), sizeof(int) * first.size());
   }
   INIT_COPY(P.t, zeros.data(), sizeof(double) * c->nch);

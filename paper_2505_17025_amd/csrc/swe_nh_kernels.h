@@ -16,7 +16,7 @@ constexpr int TRI_MAX_LEVELS = 6;
 // parameter block of the 1D kernels (passed by value)
 struct K1D {
   const Chan* ch;          // [batch]
-  const int2* tiles;       // [ntiles] (channel, first cell)
+  const int4* tiles;       // [ntiles] (channel, first cell, channel offset, channel cells)
   const int* first_tile;   // [batch]
   const double* ds;        // static depth [cells]
   double dx, g, rho, cfl, dt_fixed, k_nh;
