@@ -1181,6 +1181,38 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
 }
 
 
+// Tridiagonal solve of n <= 64 rows held one per lane of the calling
+// wavefront (a: sub-, b: main, c: super-diagonal, d: right-hand side; lanes
+// at or beyond n hold identity rows): parallel cyclic reduction with
+// cross-lane shuffles, no block barrier.  Returns x of the lane's row.
+__device__ __forceinline__ double wave_pcr(double a, double b, double c, double d, int n) {
+  const int lane = threadIdx.x & 63;
+  for (int s = 1; s < n; s <<= 1) {
+    const double am = __shfl_up(a, s), bm = __shfl_up(b, s), cm = __shfl_up(c, s),
+                 dm = __shfl_up(d, s);
+    const double ap = __shfl_down(a, s), bp = __shfl_down(b, s), cp = __shfl_down(c, s),
+                 dp = __shfl_down(d, s);
+    double na = 0.0, nb = b, nc = 0.0, nd = d;
+    if (lane >= s) {
+      const double k1 = a * rcp64(bm);
+      na = -am * k1;
+      nb -= cm * k1;
+      nd -= dm * k1;
+    }
+    if (lane + s < 64) {
+      const double k2 = c * rcp64(bp);
+      nc = -cp * k2;
+      nb -= ap * k2;
+      nd -= dp * k2;
+    }
+    a = na;
+    b = nb;
+    c = nc;
+    d = nd;
+  }
+  return d * rcp64(b);
+}
+
 // Projection of the marked cells (a6) from the level-1 solution -- solved
 // here, redundantly by every tile that needs it, when it has at most L1MAX
 // rows (L1LOCAL), else read from P.x1 -- and the speed of their new state.
@@ -1271,59 +1303,77 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
         if ((j & 1) == 0) return rup[2 * t];
         return (j + 1 < n1 && tlist[(j >> 1) + 1] == t + 1) ? rup[2 * t + 1] : 0.0;
       };
-      for (int j = threadIdx.x; j < L1; j += NT) {
-        if (j < n1) {
-          const int g = 2 * tlist[j >> 1] + (j & 1);
-          la[j] = j > 0 ? up_c(j - 1) : 0.0;
-          lb[j] = rdg[g];
-          lc[j] = up_c(j);
-          ld[j] = rrh[g];
-        } else {
-          la[j] = 0.0;
-          lb[j] = 1.0;
-          lc[j] = 0.0;
-          ld[j] = 0.0;
-        }
-        lr[j] = rcp64(lb[j]);
-      }
-      __syncthreads();
-      for (int s = 1; s < n1; s <<= 1) {
-        double na[RPT], nb[RPT], nc[RPT], nd[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-          const int i = threadIdx.x + NT * r;
-          if (i >= n1) continue;
-          const int im = i - s, ip = i + s;
-          double ai = 0.0, bi = lb[i], ci = 0.0, di = ld[i];
-          if (im >= 0) {
-            const double k1 = la[i] * lr[im];
-            ai = -la[im] * k1;
-            bi -= lc[im] * k1;
-            di -= ld[im] * k1;
+      if (n1 <= 64) {
+        // one wavefront solves it in registers; the others wait
+        if (threadIdx.x < 64) {
+          const int j = threadIdx.x;
+          double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+          if (j < n1) {
+            const int g = 2 * tlist[j >> 1] + (j & 1);
+            a = j > 0 ? up_c(j - 1) : 0.0;
+            b = rdg[g];
+            c = up_c(j);
+            d = rrh[g];
           }
-          if (ip < L1) {
-            const double k2 = lc[i] * lr[ip];
-            ci = -lc[ip] * k2;
-            bi -= la[ip] * k2;
-            di -= ld[ip] * k2;
-          }
-          na[r] = ai;
-          nb[r] = bi;
-          nc[r] = ci;
-          nd[r] = di;
+          ld[j] = wave_pcr(a, b, c, d, n1);
+          lr[j] = 1.0;
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-          const int i = threadIdx.x + NT * r;
-          if (i >= n1) continue;
-          la[i] = na[r];
-          lb[i] = nb[r];
-          lc[i] = nc[r];
-          ld[i] = nd[r];
-          lr[i] = rcp64(nb[r]);
+      } else {
+        for (int j = threadIdx.x; j < L1; j += NT) {
+          if (j < n1) {
+            const int g = 2 * tlist[j >> 1] + (j & 1);
+            la[j] = j > 0 ? up_c(j - 1) : 0.0;
+            lb[j] = rdg[g];
+            lc[j] = up_c(j);
+            ld[j] = rrh[g];
+          } else {
+            la[j] = 0.0;
+            lb[j] = 1.0;
+            lc[j] = 0.0;
+            ld[j] = 0.0;
+          }
+          lr[j] = rcp64(lb[j]);
         }
         __syncthreads();
+        for (int s = 1; s < n1; s <<= 1) {
+          double na[RPT], nb[RPT], nc[RPT], nd[RPT];
+#pragma unroll
+          for (int r = 0; r < RPT; r++) {
+            const int i = threadIdx.x + NT * r;
+            if (i >= n1) continue;
+            const int im = i - s, ip = i + s;
+            double ai = 0.0, bi = lb[i], ci = 0.0, di = ld[i];
+            if (im >= 0) {
+              const double k1 = la[i] * lr[im];
+              ai = -la[im] * k1;
+              bi -= lc[im] * k1;
+              di -= ld[im] * k1;
+            }
+            if (ip < L1) {
+              const double k2 = lc[i] * lr[ip];
+              ci = -lc[ip] * k2;
+              bi -= la[ip] * k2;
+              di -= ld[ip] * k2;
+            }
+            na[r] = ai;
+            nb[r] = bi;
+            nc[r] = ci;
+            nd[r] = di;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < RPT; r++) {
+            const int i = threadIdx.x + NT * r;
+            if (i >= n1) continue;
+            la[i] = na[r];
+            lb[i] = nb[r];
+            lc[i] = nc[r];
+            ld[i] = nd[r];
+            lr[i] = rcp64(nb[r]);
+          }
+          __syncthreads();
+        }
       }
     }
     const double xF = x1(2 * blockIdx.x), xL = x1(2 * blockIdx.x + 1);
