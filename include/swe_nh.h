@@ -234,10 +234,14 @@ int swe_nh_features(swe_nh_ctx* ctx, const double* ht, const double* mt, const d
                     const uint8_t* mask, const double* t1_host, const double* scales_host,
                     uint16_t* out);
 
-/* Use the network (device parameters, kept by reference) as the initial
- * guess of the 2D pressure solve of swe_nh_step when the context was
- * created with warm = 2: inputs scaled as in swe_nh_features, guess =
- * p_scale * network output on the marked cells (Pa). */
+/* Use the network (device parameters, kept by reference: the biases are read
+ * at each step, the weights are packed for the matrix cores by this call,
+ * so call it again after changing them) as the initial guess of the 2D
+ * pressure solve of swe_nh_step when the context was created with warm = 2:
+ * inputs scaled as in swe_nh_features, guess = p_scale * network output on
+ * the marked cells (Pa).  The network sees a window of at most 256 x 256
+ * cells placed over the active tiles each step; marked cells outside it
+ * start from 0. */
 int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double* scales_host,
                               double p_scale);
 

@@ -52,6 +52,8 @@ struct Ctx2D {
   size_t cnn_bytes = 0;
   uint16_t* feat = nullptr;
   double* guess = nullptr;
+  int crop_w = 0, crop_h = 0;  // window of the grid the network sees (cells, multiples of 16)
+  int* crop_org = nullptr;     // its origin (i0, j0), placed over the active tiles each step
   const float* net = nullptr;
   double fscale[4] = {1.0, 1.0, 1.0, 1.0};  // input scales of eta, hu, hv, -d_t
   double p_scale = 1.0;
@@ -66,6 +68,8 @@ struct Ctx2D {
 
 void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x);
 int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s);
+// the warm-start network's weights packed for the convolution kernels
+void pack_net2d(Ctx2D* x, hipStream_t s);
 // speed of the caller's state -> dt of the first step of a call
 void launch_speed2d_prologue(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,
                              const double* hu, const double* hv, const double* hw);

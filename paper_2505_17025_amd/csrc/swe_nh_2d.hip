@@ -1980,10 +1980,15 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->iters_sum = (long long*)take(8);
   x->rel = (double*)take(8);
   if (c->warm == 2) {
-    x->cnn_bytes = cnn_layout(1, c->ny, c->nx).bytes;
+    // the network runs on a window of at most 256 x 256 cells over the active
+    // tiles: the pressure's support plus the network's receptive field
+    x->crop_w = std::min(c->nx, 256);
+    x->crop_h = std::min(c->ny, 256);
+    x->cnn_bytes = cnn_layout(1, x->crop_h, x->crop_w).bytes;
     x->cnn_ws = take(x->cnn_bytes);
-    x->feat = (uint16_t*)take(2 * 16 * N);
+    x->feat = (uint16_t*)take(2 * 16 * (size_t)x->crop_w * x->crop_h);
     x->guess = (double*)take(8 * N);
+    x->crop_org = (int*)take(8);
   }
 }
 
@@ -2027,13 +2032,84 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   return SWE_NH_OK;
 }
 
+// origin of the network's w x h window: centred on the bounding box of the
+// active tiles, inside the grid (one block)
+__global__ void __launch_bounds__(256) k_crop2d(const int* tile_list, const int* n_list,
+                                                int tiles_x, int nx, int ny, int w, int h,
+                                                int* org) {
+  __shared__ int lo[2][256 / 64], hi[2][256 / 64];
+  const int nl = *n_list;
+  int bx0 = 1 << 30, by0 = 1 << 30, bx1 = -1, by1 = -1;
+  for (int t = threadIdx.x; t < nl; t += 256) {
+    const int tile = tile_list[t], tx = tile % tiles_x, ty = tile / tiles_x;
+    bx0 = min(bx0, tx);
+    bx1 = max(bx1, tx);
+    by0 = min(by0, ty);
+    by1 = max(by1, ty);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    bx0 = min(bx0, __shfl_xor(bx0, o));
+    by0 = min(by0, __shfl_xor(by0, o));
+    bx1 = max(bx1, __shfl_xor(bx1, o));
+    by1 = max(by1, __shfl_xor(by1, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    lo[0][threadIdx.x >> 6] = bx0;
+    lo[1][threadIdx.x >> 6] = by0;
+    hi[0][threadIdx.x >> 6] = bx1;
+    hi[1][threadIdx.x >> 6] = by1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 256 / 64; k++) {
+      bx0 = min(bx0, lo[0][k]);
+      by0 = min(by0, lo[1][k]);
+      bx1 = max(bx1, hi[0][k]);
+      by1 = max(by1, hi[1][k]);
+    }
+    int i0 = 0, j0 = 0;
+    if (nl > 0) {
+      const int cx = ((bx0 + bx1 + 1) * TX2) / 2, cy = ((by0 + by1 + 1) * TY2) / 2;
+      i0 = min(max(cx - w / 2, 0), nx - w);
+      j0 = min(max(cy - h / 2, 0), ny - h);
+    }
+    org[0] = i0;
+    org[1] = j0;
+  }
+}
+
+// the guess on the marked cells of the active tiles: scale * network output
+// inside the window, 0 outside it
+__global__ void __launch_bounds__(NT2) k_guess2d(const float* __restrict__ out,
+                                                 const int* org, int w, int h,
+                                                 const uint8_t* __restrict__ mask,
+                                                 const int* tile_list, const int* n_list,
+                                                 int tiles_x, int nx, int ny, double scale,
+                                                 double* __restrict__ guess) {
+  if ((int)blockIdx.x >= *n_list) return;
+  const int tile = tile_list[blockIdx.x];
+  const int i0 = (tile % tiles_x) * TX2, j0 = (tile / tiles_x) * TY2;
+  const int ox = org[0], oy = org[1];
+  for (int cc = threadIdx.x; cc < TN; cc += NT2) {
+    const int i = i0 + cc % TX2, j = j0 + cc / TX2;
+    if (i >= nx || j >= ny) continue;
+    const int64_t g = (int64_t)j * nx + i;
+    if (!mask[g]) continue;
+    const int li = i - ox, lj = j - oy;
+    guess[g] = (li >= 0 && li < w && lj >= 0 && lj < h)
+                   ? scale * (double)out[(int64_t)lj * w + li] : 0.0;
+  }
+}
+
 static void enqueue_nh2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* ht,
                          const double* mt, const double* nt, const double* kt,
                          const uint8_t* mask, const double* t_in, const double* dt_in,
-                         const double* p_prev, double* hu, double* hv, double* hw, double* p) {
+                         const double* p_prev, double* hu, double* hv, double* hw, double* p,
+                         bool tiles_ready = false) {
   const G2 G = make_g2(c, x);
-  hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
-                     x->n_tiles_act, x->n_act, x->tile_pos);
+  if (!tiles_ready)
+    hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
+                       x->n_tiles_act, x->n_act, x->tile_pos);
   hipLaunchKernelGGL(k_assemble2d, dim3(x->ntiles), dim3(NT2), 0, s, G, ht, mt, nt, kt, mask,
                      x->tile_list, x->n_tiles_act, t_in, dt_in, sys_of(x), p_prev,
                      (int)(p_prev != nullptr));
@@ -2056,19 +2132,29 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
                      hw, p, 1);
   if (c->crit != SWE_NH_CRIT_NONE) {
     const double* guess = c->warm == 1 ? p : nullptr;
+    bool tiles_ready = false;
     if (c->warm == 2 && x->net) {
-      const int64_t N = (int64_t)x->nx * x->ny;
-      const CnnLayout L = cnn_layout(1, x->ny, x->nx);
+      // the network on its window over the active tiles; the guess is read
+      // only on their marked cells
+      hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles,
+                         x->tile_list, x->n_tiles_act, x->n_act, x->tile_pos);
+      tiles_ready = true;
+      const int w = x->crop_w, hh = x->crop_h;
+      hipLaunchKernelGGL(k_crop2d, dim3(1), dim3(256), 0, s, (const int*)x->tile_list,
+                         (const int*)x->n_tiles_act, x->tiles_x, x->nx, x->ny, w, hh, x->crop_org);
+      const CnnLayout L = cnn_layout(1, hh, w);
       cnn_features(x->ch, c->depth_static, x->nx, x->ny, c->dx, c->dy, x->fscale, x->t, x->dt,
-                   x->ht, x->mt, x->nt, M, x->feat, s);
-      cnn_pack_weights(x->net, x->cnn_ws, L, false, s);
-      cnn_forward(x->net, x->feat, 1, x->ny, x->nx, x->cnn_ws, L,
-                  reinterpret_cast<float*>(x->cnn_ws + L.out), s);
-      cnn_scale_guess(reinterpret_cast<const float*>(x->cnn_ws + L.out), M, N, x->p_scale,
-                      x->guess, s);
+                   x->ht, x->mt, x->nt, M, x->feat, s, x->crop_org, w, hh);
+      float* out = reinterpret_cast<float*>(x->cnn_ws + L.out);
+      cnn_forward(x->net, x->feat, 1, hh, w, x->cnn_ws, L, out, s);
+      hipLaunchKernelGGL(k_guess2d, dim3(x->ntiles), dim3(NT2), 0, s, (const float*)out,
+                         (const int*)x->crop_org, w, hh, (const uint8_t*)M,
+                         (const int*)x->tile_list, (const int*)x->n_tiles_act, x->tiles_x, x->nx,
+                         x->ny, x->p_scale, x->guess);
       guess = x->guess;
     }
-    enqueue_nh2d(c, x, s, x->ht, x->mt, x->nt, x->kt, M, x->t, x->dt, guess, hu, hv, hw, p);
+    enqueue_nh2d(c, x, s, x->ht, x->mt, x->nt, x->kt, M, x->t, x->dt, guess, hu, hv, hw, p,
+                 tiles_ready);
   } else {
     hipLaunchKernelGGL(k_tiles2d, dim3(1), dim3(1024), 0, s, x->tile_cnt, x->ntiles, x->tile_list,
                        x->n_tiles_act, x->n_act, x->tile_pos);
@@ -2076,6 +2162,11 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
   // the new state's speed (tiles written by the mask pass and the projection)
   // -> dt of the next step; time and step counter advance
   hipLaunchKernelGGL(k_speed_reduce2d, dim3(1), dim3(1024), 0, s, G, x->ntiles, 1);
+}
+
+void pack_net2d(Ctx2D* x, hipStream_t s) {
+  if (x->net && x->cnn_ws)
+    cnn_pack_weights(x->net, x->cnn_ws, cnn_layout(1, x->crop_h, x->crop_w), false, s);
 }
 
 void launch_speed2d_prologue(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,

@@ -766,6 +766,9 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* c, const float* params, const double* 
   c->c2.net = params;
   for (int k = 0; k < 4; k++) c->c2.fscale[k] = scales_host[k];
   c->c2.p_scale = p_scale;
+  pack_net2d(&c->c2, c->stream);
+  int rc = after_launch(c);
+  if (rc) return rc;
   for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})  // the step must pick up the network
     if (*g) {
       hipGraphExecDestroy(*g);

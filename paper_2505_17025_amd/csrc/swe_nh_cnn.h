@@ -30,11 +30,11 @@ void cnn_forward(const float* params, const uint16_t* x, int n, int h, int w, ch
                  const CnnLayout& L, float* out, hipStream_t s);
 void cnn_backward(const float* params, const uint16_t* x, const float* dout, int n, int h, int w,
                   char* ws, const CnnLayout& L, float* grad, hipStream_t s);
+// network input of the grid (org null) or of its w x h window at org = (i0, j0)
+// (device), in the window's NHWC layout
 void cnn_features(const Chan* ch, const double* ds, int nx, int ny, double dx, double dy,
                   const double* scale, const double* t, const double* dt, const double* ht,
-                  const double* mt,
-                  const double* nt, const uint8_t* mask, uint16_t* out, hipStream_t s);
-void cnn_scale_guess(const float* o, const uint8_t* mask, int64_t n, double scale, double* guess,
-                     hipStream_t s);
+                  const double* mt, const double* nt, const uint8_t* mask, uint16_t* out,
+                  hipStream_t s, const int* org = nullptr, int w = 0, int h = 0);
 
 }  // namespace swenh

@@ -346,39 +346,35 @@ struct FScale {
   double s[4];
 };
 
+// over the window of w x h cells at org = (i0, j0) of the grid (org null: the
+// whole grid, w = nx, h = ny); out is the window's image
 __global__ void k_features(const Chan* ch, const double* __restrict__ ds, int nx, int ny,
                            double dx, double dy, FScale F, const double* t, const double* dt_,
                            const double* __restrict__ ht, const double* __restrict__ mt,
                            const double* __restrict__ nt, const uint8_t* __restrict__ mask,
-                           uint16_t* __restrict__ out) {
+                           uint16_t* __restrict__ out, const int* org, int w, int h) {
   const Chan c = ch[0];
   const Motion M = body_motion(c, t[0] + dt_[0]);
-  const int64_t n = (int64_t)nx * ny;
+  const int i0 = org ? org[0] : 0, j0 = org ? org[1] : 0;
+  const int64_t n = (int64_t)w * h;
   for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(o % nx), j = (int)(o / nx);
+    const int i = i0 + (int)(o % w), j = j0 + (int)(o / w);
+    const int64_t g = (int64_t)j * nx + i;
     const double x = (i + 0.5) * dx, y = (j + 0.5) * dy;
     const Shape S = body_shape(c, x - M.X, y - c.y0);
-    const double d = ds[o] - S.B;
+    const double d = ds[g] - S.B;
     const double dt = bed_rate(M, S).d_t;
     uint32_t v[5];
-    v[0] = f2bf((float)((ht[o] - d) / F.s[0]));
-    v[1] = f2bf((float)(mt[o] / F.s[1]));
-    v[2] = f2bf((float)(nt[o] / F.s[2]));
+    v[0] = f2bf((float)((ht[g] - d) / F.s[0]));
+    v[1] = f2bf((float)(mt[g] / F.s[1]));
+    v[2] = f2bf((float)(nt[g] / F.s[2]));
     v[3] = f2bf((float)(-dt / F.s[3]));
-    v[4] = f2bf(mask[o] ? 1.0f : 0.0f);
+    v[4] = f2bf(mask[g] ? 1.0f : 0.0f);
     uint4* dst = reinterpret_cast<uint4*>(out + o * 16);
     dst[0] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4], 0u);
     dst[1] = make_uint4(0u, 0u, 0u, 0u);
   }
-}
-
-// guess = (rho g h0) * net output on the marked cells (FP64)
-__global__ void k_scale_guess(const float* __restrict__ o, const uint8_t* __restrict__ mask,
-                              int64_t n, double scale, double* __restrict__ guess) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    guess[e] = mask[e] ? scale * (double)o[e] : 0.0;
 }
 
 int blocks_of(int64_t n) {
@@ -538,17 +534,17 @@ void cnn_adam(float* p, float* m, float* v, const float* g, int64_t n, int step,
 void cnn_features(const Chan* ch, const double* ds, int nx, int ny, double dx, double dy,
                   const double* scale, const double* t, const double* dt, const double* ht,
                   const double* mt, const double* nt, const uint8_t* mask, uint16_t* out,
-                  hipStream_t s) {
+                  hipStream_t s, const int* org, int w, int h) {
   FScale F;
   for (int k = 0; k < 4; k++) F.s[k] = scale[k];
-  hipLaunchKernelGGL(k_features, dim3(blocks_of((int64_t)nx * ny)), dim3(NTC), 0, s, ch, ds, nx,
-                     ny, dx, dy, F, t, dt, ht, mt, nt, mask, out);
+  if (!org) {
+    w = nx;
+    h = ny;
+  }
+  hipLaunchKernelGGL(k_features, dim3(blocks_of((int64_t)w * h)), dim3(NTC), 0, s, ch, ds, nx,
+                     ny, dx, dy, F, t, dt, ht, mt, nt, mask, out, org, w, h);
 }
 
-void cnn_scale_guess(const float* o, const uint8_t* mask, int64_t n, double scale, double* guess,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_guess, dim3(blocks_of(n)), dim3(NTC), 0, s, o, mask, n, scale, guess);
-}
 
 }  // namespace swenh
 
