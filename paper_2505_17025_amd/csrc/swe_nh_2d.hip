@@ -1988,7 +1988,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
     x->cnn_ws = take(x->cnn_bytes);
     x->feat = (uint16_t*)take(2 * 16 * (size_t)x->crop_w * x->crop_h);
     x->guess = (double*)take(8 * N);
-    x->crop_org = (int*)take(8);
+    x->crop_org = (int*)take(6 * sizeof(int));
   }
 }
 
@@ -2023,6 +2023,9 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   if (hipMemcpy(x->n_tiles_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   if (hipMemcpy(x->n_act, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   if (hipMemcpy(x->iters, zi, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  // the network's buffers start at zero: tiles of the window it skips keep
+  // finite values
+  if (x->cnn_ws && hipMemset(x->cnn_ws, 0, x->cnn_bytes) != hipSuccess) return SWE_NH_EHIP;
   const long long zl = 0;
   if (hipMemcpy(x->iters_sum, &zl, 8, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   const int none[3] = {-1, 0, 0};  // no coarse inverse yet
@@ -2032,8 +2035,11 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   return SWE_NH_OK;
 }
 
-// origin of the network's w x h window: centred on the bounding box of the
-// active tiles, inside the grid (one block)
+// origin of the network's w x h window, centred on the bounding box of the
+// active tiles and inside the grid, and the part of the window the network
+// computes: that box, widened by 16 cells (more than the 6-cell receptive
+// field of the six 3 x 3 layers, so the values on the active tiles are those
+// of the whole window).  org = (i0, j0, x0, y0, x1, y1).  One block.
 __global__ void __launch_bounds__(256) k_crop2d(const int* tile_list, const int* n_list,
                                                 int tiles_x, int nx, int ny, int w, int h,
                                                 int* org) {
@@ -2075,6 +2081,14 @@ __global__ void __launch_bounds__(256) k_crop2d(const int* tile_list, const int*
     }
     org[0] = i0;
     org[1] = j0;
+    if (nl > 0) {
+      org[2] = max(bx0 * TX2 - 16 - i0, 0);
+      org[3] = max(by0 * TY2 - 16 - j0, 0);
+      org[4] = min((bx1 + 1) * TX2 + 16 - i0, w);
+      org[5] = min((by1 + 1) * TY2 + 16 - j0, h);
+    } else {
+      org[2] = org[3] = org[4] = org[5] = 0;
+    }
   }
 }
 
@@ -2146,7 +2160,7 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
       cnn_features(x->ch, c->depth_static, x->nx, x->ny, c->dx, c->dy, x->fscale, x->t, x->dt,
                    x->ht, x->mt, x->nt, M, x->feat, s, x->crop_org, w, hh);
       float* out = reinterpret_cast<float*>(x->cnn_ws + L.out);
-      cnn_forward(x->net, x->feat, 1, hh, w, x->cnn_ws, L, out, s);
+      cnn_forward(x->net, x->feat, 1, hh, w, x->cnn_ws, L, out, s, x->crop_org + 2);
       hipLaunchKernelGGL(k_guess2d, dim3(x->ntiles), dim3(NT2), 0, s, (const float*)out,
                          (const int*)x->crop_org, w, hh, (const uint8_t*)M,
                          (const int*)x->tile_list, (const int*)x->n_tiles_act, x->tiles_x, x->nx,

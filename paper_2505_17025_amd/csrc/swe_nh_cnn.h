@@ -26,8 +26,10 @@ int64_t cnn_param_count();
 CnnLayout cnn_layout(int n, int h, int w);
 void cnn_pack_weights(const float* params, char* ws, const CnnLayout& L, bool with_transposed,
                       hipStream_t s);
+// box (device, nullable): [x0, y0, x1, y1) of the image, the pixel tiles to
+// compute (tiles outside it keep their old values)
 void cnn_forward(const float* params, const uint16_t* x, int n, int h, int w, char* ws,
-                 const CnnLayout& L, float* out, hipStream_t s);
+                 const CnnLayout& L, float* out, hipStream_t s, const int* box = nullptr);
 void cnn_backward(const float* params, const uint16_t* x, const float* dout, int n, int h, int w,
                   char* ws, const CnnLayout& L, float* grad, hipStream_t s);
 // network input of the grid (org null) or of its w x h window at org = (i0, j0)

@@ -85,12 +85,15 @@ __global__ void __launch_bounds__(NTC) k_conv(const uint16_t* __restrict__ in,
                                               const float* __restrict__ bias, int H, int W,
                                               uint16_t* __restrict__ out_bf,
                                               float* __restrict__ out_f,
-                                              const uint16_t* __restrict__ gate) {
+                                              const uint16_t* __restrict__ gate,
+                                              const int* box) {
   constexpr int RS = CI + CPAD;  // LDS row stride (halves) of a pixel / of a weight row
   __shared__ __attribute__((aligned(16))) uint16_t patch[PW * PW * RS];
   __shared__ __attribute__((aligned(16))) uint16_t wts[CO * 9 * RS];
   const int tiles_x = W / CT;
   const int tx0 = (blockIdx.x % tiles_x) * CT, ty0 = (blockIdx.x / tiles_x) * CT;
+  // only the pixel tiles that meet box = [x0, x1) x [y0, y1) (null: all)
+  if (box && (tx0 + CT <= box[0] || tx0 >= box[2] || ty0 + CT <= box[1] || ty0 >= box[3])) return;
   const int img = blockIdx.y;
   const int64_t ibase = (int64_t)img * H * W;
   // stage the input patch (zero outside the image) and the packed weights
@@ -449,7 +452,7 @@ void cnn_pack_weights(const float* params, char* ws, const CnnLayout& L, bool wi
 }
 
 void cnn_forward(const float* params, const uint16_t* x, int n, int h, int w, char* ws,
-                 const CnnLayout& L, float* out, hipStream_t s) {
+                 const CnnLayout& L, float* out, hipStream_t s, const int* box) {
   const dim3 grid((w / CT) * (h / CT), n);
   const uint16_t* in = x;
   for (int l = 0; l < NL; l++) {
@@ -458,16 +461,16 @@ void cnn_forward(const float* params, const uint16_t* x, int n, int h, int w, ch
     if (l == 0) {
       uint16_t* o = reinterpret_cast<uint16_t*>(ws + L.act[0]);
       hipLaunchKernelGGL((k_conv<16, 32, EPI_RELU>), grid, dim3(NTC), 0, s, in, wp, b, h, w, o,
-                         (float*)nullptr, (const uint16_t*)nullptr);
+                         (float*)nullptr, (const uint16_t*)nullptr, box);
       in = o;
     } else if (l < NL - 1) {
       uint16_t* o = reinterpret_cast<uint16_t*>(ws + L.act[l]);
       hipLaunchKernelGGL((k_conv<32, 32, EPI_RELU>), grid, dim3(NTC), 0, s, in, wp, b, h, w, o,
-                         (float*)nullptr, (const uint16_t*)nullptr);
+                         (float*)nullptr, (const uint16_t*)nullptr, box);
       in = o;
     } else {
       hipLaunchKernelGGL((k_conv<32, 16, EPI_LAST>), grid, dim3(NTC), 0, s, in, wp, b, h, w,
-                         (uint16_t*)nullptr, out, (const uint16_t*)nullptr);
+                         (uint16_t*)nullptr, out, (const uint16_t*)nullptr, box);
     }
   }
 }
@@ -504,10 +507,12 @@ void cnn_backward(const float* params, const uint16_t* x, const float* dout, int
       const uint16_t* gate = reinterpret_cast<const uint16_t*>(ws + L.act[l - 1]);
       if (l == NL - 1)
         hipLaunchKernelGGL((k_conv<16, 32, EPI_GATE>), grid, dim3(NTC), 0, s, dy, wt,
-                           (const float*)nullptr, h, w, dx, (float*)nullptr, gate);
+                           (const float*)nullptr, h, w, dx, (float*)nullptr, gate,
+                           (const int*)nullptr);
       else
         hipLaunchKernelGGL((k_conv<32, 32, EPI_GATE>), grid, dim3(NTC), 0, s, dy, wt,
-                           (const float*)nullptr, h, w, dx, (float*)nullptr, gate);
+                           (const float*)nullptr, h, w, dx, (float*)nullptr, gate,
+                           (const int*)nullptr);
       dy = dx;
     }
   }
