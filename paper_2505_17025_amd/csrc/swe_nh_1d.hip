@@ -658,6 +658,10 @@ template <int T, int NT>
 struct StepSmem {
   static constexpr int WMAX = T + 2 * (4 + HMAXF);  // predictor window
   static constexpr int RW = T > NT ? T : NT;        // rows of the in-LDS tile system
+  // two buffers let each reduction level end with one barrier instead of two;
+  // they fit beside the other members only for the 128-cell window (larger
+  // windows would lose blocks per CU)
+  static constexpr int NB = T <= 128 ? 2 : 1;
   // eta (then h~ after the predictor), hu, hw; depth at t^n and t^{n+1}
   double e[WMAX], m[WMAX], k[WMAX], d0[WMAX], d1[WMAX];
   union {
@@ -671,7 +675,7 @@ struct StepSmem {
     } q;
     struct {
       double a[RW], b[RW], c[RW], d[3][RW], r[RW];  // r = 1 / b
-    } s;  // tile system
+    } s[NB];  // tile system (the reduction alternates between NB buffers)
   } u;
   uint8_t raw[T + 2 + 2 * EMAXF];
   uint8_t mk[T + 2];
@@ -795,12 +799,14 @@ __device__ FaceNH face_win(const WinQ& Q, const K1D& P, double dt, int f, double
 }
 
 // parallel cyclic reduction of the first m rows of the tile system (rows
-// m..RW are identity), three right-hand sides
+// m..RW are identity), three right-hand sides, starting in buffer 0; returns
+// the buffer that holds the result
 template <int T, int NT>
-__device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
-  constexpr int RW = StepSmem<T, NT>::RW, RPT = RW / NT;
-  auto& Y = S.u.s;
+__device__ int pcr_tile(StepSmem<T, NT>& S, int m) {
+  constexpr int RW = StepSmem<T, NT>::RW, RPT = RW / NT, NB = StepSmem<T, NT>::NB;
+  int cur = 0;
   for (int s = 1; s < m; s <<= 1) {
+    const auto& Y = S.u.s[cur];
     double na[RPT], nb[RPT], nc[RPT], nd[RPT][3];
 #pragma unroll
     for (int j = 0; j < RPT; j++) {
@@ -828,19 +834,25 @@ __device__ void pcr_tile(StepSmem<T, NT>& S, int m) {
 #pragma unroll
       for (int r = 0; r < 3; r++) nd[j][r] = di[r];
     }
-    __syncthreads();
+    // one buffer: everyone has read before anyone writes; two: the level
+    // writes the other buffer, whose last readers finished a barrier ago
+    if (NB == 1) __syncthreads();
+    const int nxt = (NB == 2) ? cur ^ 1 : cur;
+    auto& Z = S.u.s[nxt];
 #pragma unroll
     for (int j = 0; j < RPT; j++) {
       const int i = RPT * threadIdx.x + j;
-      Y.a[i] = na[j];
-      Y.b[i] = nb[j];
-      Y.c[i] = nc[j];
-      Y.r[i] = rcp64(nb[j]);
+      Z.a[i] = na[j];
+      Z.b[i] = nb[j];
+      Z.c[i] = nc[j];
+      Z.r[i] = rcp64(nb[j]);
 #pragma unroll
-      for (int r = 0; r < 3; r++) Y.d[r][i] = nd[j][r];
+      for (int r = 0; r < 3; r++) Z.d[r][i] = nd[j][r];
     }
     __syncthreads();
+    cur = nxt;
   }
+  return cur;
 }
 }  // namespace
 
@@ -1109,7 +1121,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     z[ZW_KT * zs] = ks;
   }
   __syncthreads();  // cq, fq dead: the tile system takes their place
-  auto& Y = S.u.s;
+  auto& Y = S.u.s[0];
   for (int j = threadIdx.x; j < RW; j += NT) {
     Y.a[j] = 0.0;
     Y.b[j] = 1.0;
@@ -1160,17 +1172,17 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     Y.r[j] = rcp64(Y.b[j]);
   }
   __syncthreads();
-  pcr_tile<T, NT>(S, m);
+  const auto& X = S.u.s[pcr_tile<T, NT>(S, m)];
   for (int j = threadIdx.x; j < m; j += NT) {
-    const double ib = Y.r[j];
+    const double ib = X.r[j];
     const int64_t cz = pb + S.cell_of[j];
-    P.zw[cz + ZW_Z * zs] = Y.d[0][j] * ib;
-    P.zw[cz + ZW_U * zs] = Y.d[1][j] * ib;
-    P.zw[cz + ZW_V * zs] = Y.d[2][j] * ib;
+    P.zw[cz + ZW_Z * zs] = X.d[0][j] * ib;
+    P.zw[cz + ZW_U * zs] = X.d[1][j] * ib;
+    P.zw[cz + ZW_V * zs] = X.d[2][j] * ib;
   }
   if (threadIdx.x == 0) {
-    const double z1 = Y.d[0][1] * Y.r[1], u1 = Y.d[1][1] * Y.r[1], v1 = Y.d[2][1] * Y.r[1];
-    const double zL = Y.d[0][m - 2] * Y.r[m - 2], vL = Y.d[2][m - 2] * Y.r[m - 2];
+    const double z1 = X.d[0][1] * X.r[1], u1 = X.d[1][1] * X.r[1], v1 = X.d[2][1] * X.r[1];
+    const double zL = X.d[0][m - 2] * X.r[m - 2], vL = X.d[2][m - 2] * X.r[m - 2];
     P.dg1[F] = b0 + c0 * u1;
     P.up1[F] = c0 * v1;
     P.rh1[F] = d0 - c0 * z1;
