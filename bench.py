@@ -189,7 +189,7 @@ def main():
                      "paper_context": "paper: adaptive saves more than 50% of the global time "
                                       "(t_local/t_global 0.07-0.40 with |eta/d| + 1-cell "
                                       "enlargement), hardware not stated"}
-        roof = step_roofline(case.n, res["stage_us"], "step1d_slide32768_pmc.txt", tile)
+        roof = step_roofline(case.n, res["stage_us"], f"step1d_slide32768_tile{tile}_pmc.txt", tile)
         cpu = None
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
@@ -239,7 +239,8 @@ def main():
                              "bytes_per_launch": ncell * 56.0, "stage_us": res["stage_us"]},
                 "cpu_baseline": None,
                 "extra": {"fp64_cell_steps_per_s": r64["cell_steps_per_s"],
-                          "fp64_roofline": step_roofline(ncell, r64s, "step1d_ensemble512_pmc.txt",
+                          "fp64_roofline": step_roofline(ncell, r64s,
+                                                         f"step1d_ensemble512_tile{tile}_pmc.txt",
                                                          tile),
                           "global_cell_steps_per_s": g["cell_steps_per_s"],
                           "n_active_last": res["n_active_last"]}}

@@ -248,7 +248,10 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double
 /* Measurement: launch one stage kernel of the step nreps times back to back
  * on the context's stream, with the launch configuration swe_nh_step uses,
  * between two HIP events, and return the mean time per launch in
- * microseconds (synchronises).  The state arrays must hold a valid state of
+ * microseconds (synchronises).  The launches are captured into a graph of
+ * up to 50 of them, replayed once untimed and then timed, so the host's
+ * per-launch cost is not counted; nreps is rounded up to a multiple of the
+ * graph's length.  The state arrays must hold a valid state of
  * the context (for instance after swe_nh_step).
  * 1D with precision 0 and enlarge <= 8 (the fused step): stage 0 the fused
  * step kernel (predictor, criterion, assembly, tile reduction), 1 the

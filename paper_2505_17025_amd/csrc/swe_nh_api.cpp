@@ -34,6 +34,7 @@ struct Carve {
 }  // namespace
 
 constexpr int GSTEPS = 8;  // steps per graph launch on the fused 1D path (even)
+constexpr int TIME_BATCH = 50;  // stage launches per graph in swe_nh_time_stage
 
 struct swe_nh_ctx {
   swe_nh_config cfg{};
@@ -782,48 +783,65 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
   if (!c || !h || !hu || !hw || !p || !avg_us_host || nreps < 1 || stage < 0 || stage > 3)
     return fail(c, SWE_NH_EINVAL, "bad arguments");
   if ((c->cfg.dim == 1) != (hv == nullptr)) return fail(c, SWE_NH_EINVAL, "hv must be NULL iff dim == 1");
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
-  hipStream_t s = c->stream;
-  HIPCHK(c, hipEventRecord(e0, s));
-  for (int r = 0; r < nreps; r++) {
-    if (c->cfg.dim == 1) {
-      K1D& P = c->k1;
-      uint8_t* M = c->mask_ws;
-      if (P.fused) {
-        // stage 0: the fused step kernel, 1: level-1 solve, 2: projection,
-        // 3: the stand-alone predictor.  Outputs go to workspace scratch
-        // (level-0 arrays of the packed solver, unused by this path), never
-        // the caller's state; nothing advances.
-        double *s0 = c->T64.dg[0], *s1 = c->T64.up[0], *s2 = c->T64.rh[0], *s3 = c->T64.x[0];
-        switch (stage) {
-          case 0: launch_step1d(P, h, hu, hw, s0, s1, s2, M, s3, 0, s); break;
-          case 1: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
-          case 2: launch_apply1d(P, M, s1, s2, s3, 0, s); break;
-          default: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s);
-        }
-        continue;
-      }
-      switch (stage) {
-        case 0: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s); break;
-        case 1: launch_mask1d(P, c->ht, c->mt, c->kt, P.t, P.dt, 0, M, nullptr, nullptr, nullptr,
-                              nullptr, 0, s); break;
-        case 2: solve1d(c, s, 0); break;
-        default: launch_correct1d(P, c->ncells, c->ht, c->mt, c->kt, M, P.t, P.dt, c->T64.x[0],
-                                  hu, hw, p, s);
-      }
-    } else {
+  // one launch of the stage, enqueued on s
+  auto one = [&](hipStream_t s) {
+    if (c->cfg.dim == 2) {
       time_stage2d(&c->cfg, &c->c2, s, stage, h, hu, hv, hw, p);
+      return;
     }
-  }
-  HIPCHK(c, hipEventRecord(e1, s));
-  HIPCHK(c, hipEventSynchronize(e1));
+    K1D& P = c->k1;
+    uint8_t* M = c->mask_ws;
+    if (P.fused) {
+      // stage 0: the fused step kernel, 1: level-1 solve, 2: projection,
+      // 3: the stand-alone predictor.  Outputs go to workspace scratch
+      // (level-0 arrays of the packed solver, unused by this path), never
+      // the caller's state; nothing advances.
+      double *s0 = c->T64.dg[0], *s1 = c->T64.up[0], *s2 = c->T64.rh[0], *s3 = c->T64.x[0];
+      switch (stage) {
+        case 0: launch_step1d(P, h, hu, hw, s0, s1, s2, M, s3, 0, s); break;
+        case 1: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
+        case 2: launch_apply1d(P, M, s1, s2, s3, 0, s); break;
+        default: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s);
+      }
+      return;
+    }
+    switch (stage) {
+      case 0: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s); break;
+      case 1: launch_mask1d(P, c->ht, c->mt, c->kt, P.t, P.dt, 0, M, nullptr, nullptr, nullptr,
+                            nullptr, 0, s); break;
+      case 2: solve1d(c, s, 0); break;
+      default: launch_correct1d(P, c->ncells, c->ht, c->mt, c->kt, M, P.t, P.dt, c->T64.x[0],
+                                hu, hw, p, s);
+    }
+  };
+  // The launches are replayed from a graph of up to TIME_BATCH of them, so
+  // that the host's per-launch cost does not enter the time of short
+  // kernels; nreps is rounded up to a whole number of graph launches and
+  // the mean is taken over the launches actually run.  One untimed replay
+  // comes first.
+  const int batch = nreps < TIME_BATCH ? nreps : TIME_BATCH;
+  const int nlaunch = (nreps + batch - 1) / batch;
+  hipGraphExec_t gx = nullptr;
+  int rc = capture_graph(c, [&](hipStream_t s) {
+    for (int r = 0; r < batch; r++) one(s);
+  }, &gx);
+  if (rc != SWE_NH_OK) return rc;
+  hipStream_t s = c->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipGraphLaunch(gx, s);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; r < nlaunch && e == hipSuccess; r++) e = hipGraphLaunch(gx, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
-  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  *avg_us_host = 1000.0 * ms / nreps;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipGraphExecDestroy(gx);
+  if (e != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("time_stage: ") + hipGetErrorString(e));
+  *avg_us_host = 1000.0 * ms / (double(nlaunch) * batch);
   return after_launch(c);
 }
 

@@ -266,6 +266,39 @@ def test_deterministic_and_graph_replay(B):
     assert torch.equal(h, a[2]) and torch.equal(hu, a[3]) and torch.equal(hw, a[4])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stage_timing_leaves_the_run_unchanged(B, precision):
+    """swe_nh_time_stage replays each stage from a graph (nreps 3 and 70,
+    the latter rounded up to two graphs of 50).  On the fused path the
+    stages write only workspace scratch, so the state and a continued run
+    are bit-identical to a run that was never timed; the unfused stages
+    reuse the step's workspace and may rewrite the state, so there only the
+    times are checked"""
+    case = S.random_case_1d(9000, seed=4)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, cfl=0.4, precision=precision)
+    ref = run_gpu(B, case, 20, **kw)
+    ctx = B.context_1d(case, **kw)
+    ctx.set_time(case.t0)
+    h, hu, hw = dt(case.h), dt(case.hu), dt(case.hw)
+    p = torch.zeros_like(h)
+    ctx.step(h, hu, None, hw, p, nsteps=10)
+    ctx.sync_stats()
+    snap = [x.clone() for x in (h, hu, hw, p)]
+    for stage in range(4):
+        for nreps in (3, 70):
+            us = ctx.time_stage(stage, nreps, h, hu, None, hw, p)
+            assert 0.0 < us < 1e5
+    if precision:
+        return
+    for x, y in zip((h, hu, hw, p), snap):
+        assert torch.equal(x, y)
+    ctx.step(h, hu, None, hw, p, nsteps=10)
+    st = ctx.sync_stats()
+    assert st["status"] == 0
+    for x, y in zip((h, hu, hw, p), ref[2:6]):
+        assert torch.equal(x, y)
+
+
 def test_empty_area_and_status_codes(B):
     case = S.random_case_1d(700, seed=1)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=1e6, cfl=0.4)
@@ -360,3 +393,32 @@ def test_wide_enlargement_uses_the_unfused_step(B):
     assert np.array_equal(mask.cpu().numpy(), ref.mask)
     for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
         assert rel(g, r) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_ensemble_sampled_channels(B, precision):
+    """the 512-channel ensemble at its full size (18.3M cells) in the
+    benchmark's launch configuration (tiles of 242 cells, the FP64 fused step
+    or the FP32 solve with FP64 refinement); channels are independent, so the
+    oracle checks the shortest, the longest and a middle channel exactly"""
+    ens = S.ensemble_case(n_channels=512, n_min=4096, n_max=65536, seed=17026)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=precision, tol=1e-12,
+              max_iter=6, tile1d=242)
+    nsteps = 60  # every sampled channel has a marked area by then
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, nsteps, **kw)
+    assert st["status"] == 0, st
+    lens = [c.n for c in ens.channels]
+    picks = {int(np.argmin(lens)), int(np.argmax(lens)), 255}
+    o = ens.offsets
+    tg = ctx.get_time()
+    tol = 1e-10 if precision == 0 else 1e-6
+    for j in picks:
+        c = ens.channels[j]
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.5).step(nsteps)
+        sl = slice(int(o[j]), int(o[j + 1]))
+        assert abs(tg[j] - ref.time) <= 1e-13 * ref.time
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), j
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= tol, j
+        assert ref.last_active > 0
+        assert rel(p[sl], ref.p) <= tol, j
