@@ -1,6 +1,7 @@
 """Benchmark of the adaptive non-hydrostatic SWE hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload slide1d|ensemble1d|shelf2d]
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+                [--workload slide1d|long1d|ensemble1d|shelf2d|learned2d|copycal]
 
 A step is one full pass of the hot path (predictor, criterion and
 enlargement, compaction, elliptic assembly and solve, projection) over the
@@ -39,7 +40,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="slide1d",
-                    choices=["slide1d", "ensemble1d", "shelf2d", "learned2d", "copycal"])
+                    choices=["slide1d", "long1d", "ensemble1d", "shelf2d", "learned2d",
+                             "copycal"])
     ap.add_argument("--tile1d", type=int, default=0,
                     help="1D cells per tile (32..512); 0: pick with the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -168,8 +170,10 @@ def main():
         warmup = args.warmup if args.warmup is not None else 200
         case = S.slide_case(n=32768, dx=0.005)
         kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=0)
-        tile, tune_us = (args.tile1d, None) if args.tile1d else tune_tile(B, torch, case, kw, 400,
-                                                                           100)
+        # each candidate tile runs the whole span of the timed run (the marked
+        # region, and with it the best tile, changes along the run)
+        tile, tune_us = (args.tile1d, None) if args.tile1d else tune_tile(B, torch, case, kw,
+                                                                           steps, warmup)
         kw["tile1d"] = tile
         log(f"slide1d: {case.n} cells, {warmup} warmup + {steps} timed steps")
         res = run_1d(B, torch, case, kw, steps, warmup)
@@ -205,6 +209,37 @@ def main():
                            "cells": case.n, "criterion": "eta_d", "k_nh": 1e-3, "enlarge": 1,
                            "tile1d": tile, "autotune_us_per_step": tune_us},
                 "roofline": roof, "cpu_baseline": cpu, "extra": extra}
+        print(json.dumps(line), flush=True)
+    elif args.workload == "long1d":
+        # the same slide at the head of one channel of 2^26 cells (336 km):
+        # the 1D step kernels at a size where HBM, not latency, can bind
+        steps = args.steps or 200
+        warmup = args.warmup if args.warmup is not None else 20
+        n = 1 << 26
+        case = S.slide_case(n=n, dx=0.005)
+        kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=0)
+        tile, tune_us = (args.tile1d, None) if args.tile1d else tune_tile(B, torch, case, kw, 40,
+                                                                           10)
+        kw["tile1d"] = tile
+        log(f"long1d: {n} cells, {warmup} warmup + {steps} timed steps")
+        res = run_1d(B, torch, case, kw, steps, warmup, reps_stage=50)
+        log("adaptive fp64:", json.dumps(res))
+        extra = {}
+        if not args.no_extra:
+            g = run_1d(B, torch, case, dict(kw, crit=S.CRIT_GLOBAL), steps, warmup, reps_stage=0)
+            extra = {"global_fp64_cell_steps_per_s": g["cell_steps_per_s"],
+                     "adaptive_over_global": res["cell_steps_per_s"] / g["cell_steps_per_s"],
+                     "n_active_last": res["n_active_last"]}
+        roof = step_roofline(n, res["stage_us"], f"step1d_long67108864_tile{tile}_pmc.txt", tile)
+        line = {"metric": METRIC, "value": res["cell_steps_per_s"], "unit": "cell-steps/s",
+                "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": res["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                "data": "synthetic",
+                "config": {"workload": "1D slide (as the 32768-cell workload) at the head of one "
+                                       "channel of 2^26 cells, dx=0.005 m, adaptive |eta/d|>1e-3 "
+                                       "+ 1-cell enlargement, FP64 direct solve, CFL 0.5",
+                           "cells": n, "tile1d": tile, "autotune_us_per_step": tune_us},
+                "roofline": roof, "cpu_baseline": None, "extra": extra}
         print(json.dumps(line), flush=True)
     elif args.workload == "ensemble1d":
         steps = args.steps or 200

@@ -8,8 +8,11 @@ tile by 6 + e cells on each side (e = enlargement), so for each capacity the
 tile of capacity - 2 (6 + e) cells, whose window fills whole wavefronts, is a
 candidate beside the full capacity.  `tune_1d` times whole steps for every
 candidate on a copy of the caller's state and returns the fastest; results are
-kept per (cells, channels, precision, criterion, enlargement) in a JSON table
-so that a later run on the same device skips the sweep.
+kept per (cells, channels, precision, criterion, enlargement, steps timed) in a
+JSON table so that a later run on the same device skips the sweep.  The span of
+steps matters: the marked region grows during a run, and a tile that is best
+while few tiles are marked can lose later (its level-1 system outgrows one
+wavefront sooner), so the span should cover the run being tuned for.
 
 All timing goes through the library's own step entry point; this module only
 picks the knob.
@@ -40,9 +43,9 @@ def candidates_1d(kw):
     return tuple(out)
 
 
-def _key(dev_name, cells, batch, kw):
+def _key(dev_name, cells, batch, kw, warmup, nsteps):
     return (f"{dev_name}|1d|cells={cells}|batch={batch}|prec={kw.get('precision', 0)}"
-            f"|crit={kw.get('crit', 0)}|e={kw.get('enlarge', 1)}")
+            f"|crit={kw.get('crit', 0)}|e={kw.get('enlarge', 1)}|steps={warmup}+{nsteps}")
 
 
 def _load(path):
@@ -87,7 +90,7 @@ def tune_1d(case, kw, state, t0, nsteps=200, warmup=20, table_path=None, candida
         candidates = candidates_1d(kw)
     cells = int(state[0].numel())
     batch = len(case.channels) if hasattr(case, "channels") else 1
-    key = _key(torch.cuda.get_device_name(0), cells, batch, kw)
+    key = _key(torch.cuda.get_device_name(0), cells, batch, kw, warmup, nsteps)
     table = _load(table_path)
     if key in table:
         e = table[key]

@@ -1,12 +1,13 @@
 // swe_nh_1d.hip -- 1D kernels of the non-hydrostatic SWE step (gfx950).
 //
 // Layout: all channels packed back to back in one FP64 array per field; a
-// launch tile is 128, 256 or 512 consecutive cells of one channel (tile table built on
+// launch tile is 32..512 consecutive cells of one channel (tile table built on
 // the host).  Kernels never read across a channel end: the two ghost cells
 // on each side are reflections of the channel's own cells.
 //
 //   k_speed1d   max |u| + sqrt(g h) per channel (atomic max on the bit
-//               pattern, exact) and state checks -> dt (Sec. 3.1 CFL rule)
+//               pattern into the channel's speed slots, exact) and state
+//               checks -> dt (Sec. 3.1 CFL rule)
 //   k_pred1d    both Heun stages (Eqs. 8-9) of the hydrostatic FV operator
 //               fused in LDS with a 4-cell halo
 //   k_mask1d    criterion (Sec. 5.1) + enlargement (Sec. 5.2), tile counts
@@ -18,6 +19,16 @@
 #include "swe_nh_kernels.h"
 
 namespace swenh {
+
+// maximum wave speed of channel ch in speed buffer q: the maximum of its
+// slots, returned to every lane of the calling wavefront
+__device__ __forceinline__ double read_speed(const K1D& P, int q, int ch) {
+  const unsigned long long* s = P.smax + speed_at(q * P.nch + ch, 0, P.nslot);
+  const int k = (threadIdx.x & 63) & (P.nslot - 1);
+  double v = __longlong_as_double((long long)s[(size_t)k * SPEED_PAD]);
+  for (int o = P.nslot >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // ---------------------------------------------------------------------------
 // wave speed and state check
@@ -51,7 +62,7 @@ __global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict
   __syncthreads();
   if (threadIdx.x == 0) {
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    atomicMax(&P.smax[tl.x], pos_bits(m));
+    atomicMax(&P.smax[speed_at(tl.x, blockIdx.x & (P.nslot - 1), P.nslot)], pos_bits(m));
     if (fl) atomicOr(P.status, fl);
   }
 }
@@ -185,8 +196,7 @@ __global__ void __launch_bounds__(NT) k_pred1d(K1D P, const double* __restrict__
   const double t0 = t_in[tl.x];
   double dt;
   if (dt_from_speed) {
-    dt = (P.cfl > 0.0) ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[tl.x])
-                       : P.dt_fixed;
+    dt = (P.cfl > 0.0) ? P.cfl * P.dx / read_speed(P, 0, tl.x) : P.dt_fixed;
     if (blockIdx.x == P.first_tile[tl.x] && threadIdx.x == 0) P.dt[tl.x] = dt;
   } else {
     dt = dt_in[tl.x];
@@ -623,7 +633,8 @@ __device__ void flush_speed(const K1D& P, int chan, int par, double s, int flags
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int w = 1; w < NT / 64; w++) m = fmax(m, red[w]);
-    atomicMax(&P.smax[(par ^ 1) * P.nch + chan], pos_bits(m));
+    atomicMax(&P.smax[speed_at((par ^ 1) * P.nch + chan, blockIdx.x & (P.nslot - 1), P.nslot)],
+              pos_bits(m));
     if (fl) atomicOr(P.status, fl);
   }
 }
@@ -878,10 +889,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   const int n = tl.w, start = tl.y, end = min(start + P.tile, n), len = end - start;
   const int64_t off = tl.z;
   const int step = P.step[par];
-  const double dt =
-      (P.cfl > 0.0)
-          ? P.cfl * P.dx / __longlong_as_double((long long)P.smax[par * P.nch + tl.x])
-          : P.dt_fixed;
+  const double dt = (P.cfl > 0.0) ? P.cfl * P.dx / read_speed(P, par, tl.x) : P.dt_fixed;
   const double t0 = P.t[par * P.nch + tl.x], t1 = t0 + dt;
   if (start == 0 && threadIdx.x == 0) {  // the channel's first tile
     P.dt[tl.x] = dt;
@@ -1246,7 +1254,8 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   const int64_t off = tl.z;
   const double dt = P.dt[tl.x];
   // the speed buffer this step read collects the speed of the step after next
-  if (start == 0 && threadIdx.x == 0) P.smax[par * P.nch + tl.x] = 0ull;
+  if (start == 0 && threadIdx.x < P.nslot)
+    P.smax[speed_at(par * P.nch + tl.x, threadIdx.x, P.nslot)] = 0ull;
   const int m = P.tile_cnt[blockIdx.x];
   if (m == 0) return;  // no marked cell: the step kernel already took this tile's speed
   double smax = 0.0;
@@ -1425,18 +1434,20 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
 // prologue of a run of fused steps: both speed buffers and the first marked
 // count cleared (buffer 0 then collects the speed of the caller's state)
 __global__ void k_run_begin(K1D P) {
-  for (int i = threadIdx.x; i < 2 * P.nch; i += blockDim.x) P.smax[i] = 0ull;
+  for (int i = threadIdx.x; i < 2 * P.nch * P.nslot; i += blockDim.x)
+    P.smax[(size_t)i * SPEED_PAD] = 0ull;
   if (threadIdx.x == 0) P.n_acc[0] = 0;
 }
 
 // end of a run of fused steps: time, step counter and the speed of the new
 // state back in slot 0, the last step's marked count published
 __global__ void k_run_end(K1D P, int last_par) {
-  if (last_par)
-    for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) {
-      P.t[ch] = P.t[P.nch + ch];
-      P.smax[ch] = P.smax[P.nch + ch];
-    }
+  if (last_par) {
+    for (int ch = threadIdx.x; ch < P.nch; ch += blockDim.x) P.t[ch] = P.t[P.nch + ch];
+    const int ns = P.nch * P.nslot;
+    for (int i = threadIdx.x; i < ns; i += blockDim.x)
+      P.smax[(size_t)i * SPEED_PAD] = P.smax[(size_t)(ns + i) * SPEED_PAD];
+  }
   if (threadIdx.x == 0) {
     if (last_par) P.step[0] = P.step[1];
     *P.n_act = P.n_acc[last_par ^ 1];
@@ -1470,10 +1481,8 @@ __global__ void k_scatter_packed(const int* __restrict__ act_cell, const int* n_
 
 // end of a step: t += dt, speed reset, step counter
 __global__ void k_advance(K1D P, int nch) {
-  for (int c = threadIdx.x; c < nch; c += blockDim.x) {
-    P.t[c] += P.dt[c];
-    P.smax[c] = 0ull;
-  }
+  for (int c = threadIdx.x; c < nch; c += blockDim.x) P.t[c] += P.dt[c];
+  for (int i = threadIdx.x; i < nch * P.nslot; i += blockDim.x) P.smax[(size_t)i * SPEED_PAD] = 0ull;
   if (threadIdx.x == 0) *P.step += 1;
 }
 

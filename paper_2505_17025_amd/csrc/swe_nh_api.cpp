@@ -3,6 +3,7 @@
 // sequencing and hipGraph capture of the time step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -156,6 +157,19 @@ int cap_of(const swe_nh_config* c) {
   return t <= 128 ? 128 : t <= 256 ? 256 : 512;
 }
 
+// wave-speed slots per channel: a power of two, about one slot per 32 tiles
+// of the longest channel (1 in 2D, where the tiles publish their own maxima)
+int speed_slots(const swe_nh_config* c) {
+  if (c->dim != 1) return 1;
+  int64_t nmax = 0;
+  for (int b = 0; b < n_channels(c); b++)
+    nmax = std::max<int64_t>(nmax, c->offsets ? c->offsets[b + 1] - c->offsets[b] : c->nx);
+  const int64_t tiles = (nmax + tile_of(c) - 1) / tile_of(c);
+  int s = 1;
+  while (s < SPEED_SLOTS_MAX && (int64_t)s * 32 < tiles) s *= 2;
+  return s;
+}
+
 // per tile: (channel, first cell, packed offset of the channel, cells of the
 // channel), so that a block has every index it needs from one load
 void tile_table(const swe_nh_config* c, std::vector<int4>* tiles, std::vector<int>* first) {
@@ -204,7 +218,7 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
   P.first_tile = cv.take<int>(nch);
   P.t = cv.take<double>(2 * (size_t)nch);
   P.dt = cv.take<double>(nch);
-  P.smax = cv.take<unsigned long long>(2 * (size_t)nch);
+  P.smax = cv.take<unsigned long long>(speed_at(2 * nch, 0, speed_slots(c)));
   x->stage_t = cv.take<double>(nch);
   x->stage_dt = cv.take<double>(nch);
   x->status = cv.take<int>(1);
@@ -443,10 +457,11 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.tile = tile_of(cfg);
   P.cap = cap_of(cfg);
   P.nch = c->nch;
+  P.nslot = speed_slots(cfg);
   P.fused = fused_step(cfg) ? 1 : 0;
   const int n1 = 2 * P.ntiles;
   std::vector<double> zeros(c->nch, 0.0);
-  std::vector<unsigned long long> zu(c->nch, 0ull);
+  std::vector<unsigned long long> zu(speed_at(2 * c->nch, 0, P.nslot), 0ull);
   int zi[TRI_MAX_LEVELS * 2] = {0};
   int rc = SWE_NH_OK;
 #define INIT_COPY(dst, src, bytes)                                                  \
@@ -460,8 +475,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   }
   INIT_COPY(P.t, zeros.data(), sizeof(double) * c->nch);
   INIT_COPY(P.dt, zeros.data(), sizeof(double) * c->nch);
-  INIT_COPY(P.smax, zu.data(), sizeof(unsigned long long) * c->nch);
-  INIT_COPY(P.smax + c->nch, zu.data(), sizeof(unsigned long long) * c->nch);
+  INIT_COPY(P.smax, zu.data(), sizeof(unsigned long long) * zu.size());
   INIT_COPY(P.n_acc, zi, 2 * sizeof(int));
   INIT_COPY(P.t + c->nch, zeros.data(), sizeof(double) * c->nch);
   if (P.fused) {

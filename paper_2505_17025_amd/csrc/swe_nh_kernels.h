@@ -12,6 +12,17 @@ namespace swenh {
 constexpr int TILE_MAX = 512;   // largest 1D tile (cells per block of the stencil kernels)
 constexpr int TRI_ROWS = 1024;  // rows per block in the tridiagonal solver
 constexpr int TRI_MAX_LEVELS = 6;
+// The maximum wave speed of a channel is gathered in nslot partial maxima
+// (nslot a power of two <= SPEED_SLOTS_MAX): block b folds its maximum into
+// slot b % nslot, each slot on its own 128-byte line, so that the blocks of
+// a long channel do not all queue on one address; readers take the maximum
+// of the slots.  Slot k of channel ch, buffer q lies at
+// smax[speed_at(q * batch + ch, k, nslot)].
+constexpr int SPEED_SLOTS_MAX = 32;
+constexpr int SPEED_PAD = 16;  // unsigned long long per slot
+__host__ __device__ constexpr size_t speed_at(int qch, int k, int nslot) {
+  return ((size_t)qch * nslot + k) * SPEED_PAD;
+}
 
 // parameter block of the 1D kernels (passed by value)
 struct K1D {
@@ -25,7 +36,8 @@ struct K1D {
   int cap;                 // capacity of the tile kernels' LDS windows: 128, 256 or 512
   double* t;               // [batch] time at the start of the step (fused: [2][batch] by parity)
   double* dt;              // [batch] step of the current step
-  unsigned long long* smax;  // [batch] bit pattern of the max wave speed
+  unsigned long long* smax;  // [batch] slotted bit patterns of the max wave speed (speed_at)
+  int nslot;               // speed slots in use per channel (power of two, <= SPEED_SLOTS_MAX)
   int* status;             // ST_* bits
   int* step;               // steps taken (fused: [2] by parity)
   int* tile_cnt;           // [ntiles]

@@ -227,6 +227,34 @@ def test_slide_full_size_steps(B, precision):
         assert rel(g, r) <= tol
 
 
+@pytest.mark.parametrize("tile", [0, 114, 242])
+def test_long_channel_prefix_parity(B, tile):
+    """the slide at the head of one channel of 2^26 cells (the long-channel
+    benchmark; tile 0 = the fused default).  In 40 steps the disturbance
+    stays within the first metres, so the oracle run on the first 65536 cells
+    with a wall at its end is the exact prefix of the long run, and every
+    cell beyond it stays at rest bit for bit"""
+    n, n0 = 1 << 26, 65536
+    case = S.slide_case(n=n, dx=0.005)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, tile1d=tile)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 40, **kw)
+    assert st["status"] == 0
+    ds_tail = dt(case.ds[n0:])
+    del case
+    assert torch.equal(h[n0:], ds_tail)
+    for a in (hu, hw, p):
+        assert int(torch.count_nonzero(a[n0:])) == 0
+    assert int(torch.count_nonzero(mask[n0:])) == 0
+    head = S.slide_case(n=n0, dx=0.005)
+    ref = O.Sim1D(head, phys_of(kw), cfl=0.5).step(40)
+    assert st["n_active"] == ref.last_active > 0
+    assert np.array_equal(mask[:n0].cpu().numpy(), ref.mask)
+    d_end, *_ = O.forcing_1d(head.ds, head.dx, head.body, ref.time)
+    for g, r in ((h[:n0] - dt(d_end), ref.h - d_end), (hu[:n0], ref.hu), (hw[:n0], ref.hw),
+                 (p[:n0], ref.p)):
+        assert rel(g, r) <= 1e-10
+
+
 def test_batched_ensemble_parity(B):
     ens = S.ensemble_case(n_channels=6, n_min=600, n_max=5000, seed=3, dx=0.005)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5)
