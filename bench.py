@@ -180,12 +180,17 @@ def main():
         log("adaptive fp64:", json.dumps(res))
         extra = {}
         if not args.no_extra:
-            g = run_1d(B, torch, case, dict(kw, crit=S.CRIT_GLOBAL), steps, warmup, reps_stage=0)
+            # the global extension with its own best tile (every tile is
+            # marked, so its level-1 system has 2 rows per tile)
+            kg = dict(kw, crit=S.CRIT_GLOBAL)
+            kg["tile1d"], tune_g = tune_tile(B, torch, case, kg, steps, warmup)
+            g = run_1d(B, torch, case, kg, steps, warmup, reps_stage=0)
             log("global fp64:", json.dumps(g))
             r32 = run_1d(B, torch, case, dict(kw, precision=1, tol=1e-12, max_iter=6), steps,
                          warmup, reps_stage=0)
             log("adaptive fp32+refine:", json.dumps(r32))
             extra = {"global_fp64_cell_steps_per_s": g["cell_steps_per_s"],
+                     "global_tile1d": kg["tile1d"],
                      "adaptive_over_global": res["cell_steps_per_s"] / g["cell_steps_per_s"],
                      "adaptive_fp32_refine_cell_steps_per_s": r32["cell_steps_per_s"],
                      "fp32_refine_sweeps_last": r32["iters_last"],

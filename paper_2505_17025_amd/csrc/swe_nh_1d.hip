@@ -1340,6 +1340,49 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
           lr[j] = 1.0;
         }
         __syncthreads();
+      } else if (n1 <= 128) {
+        // two rows per lane (2l, 2l + 1): one cyclic-reduction level
+        // eliminates the odd rows, one wavefront solves the even rows as
+        // above, and each odd row follows from its two even neighbours
+        if (threadIdx.x < 64) {
+          const int l = threadIdx.x, j0 = 2 * l, j1 = j0 + 1;
+          double a0 = 0.0, b0 = 1.0, c0 = 0.0, d0 = 0.0;
+          double a1 = 0.0, b1 = 1.0, c1 = 0.0, d1 = 0.0;
+          if (j0 < n1) {
+            const int g = 2 * tlist[j0 >> 1];
+            a0 = j0 > 0 ? up_c(j0 - 1) : 0.0;
+            b0 = rdg[g];
+            c0 = up_c(j0);
+            d0 = rrh[g];
+          }
+          if (j1 < n1) {
+            const int g = 2 * tlist[j1 >> 1] + 1;
+            a1 = up_c(j0);
+            b1 = rdg[g];
+            c1 = up_c(j1);
+            d1 = rrh[g];
+          }
+          const double am = __shfl_up(a1, 1), bm = __shfl_up(b1, 1), cm = __shfl_up(c1, 1),
+                       dm = __shfl_up(d1, 1);  // row 2l - 1
+          double na = 0.0, nb = b0, nd = d0;
+          if (l > 0) {
+            const double k1 = a0 * rcp64(bm);
+            na = -am * k1;
+            nb -= cm * k1;
+            nd -= dm * k1;
+          }
+          const double r1 = rcp64(b1), k2 = c0 * r1;
+          const double nc = -c1 * k2;
+          nb -= a1 * k2;
+          nd -= d1 * k2;
+          const double xe = wave_pcr(na, nb, nc, nd, (n1 + 1) >> 1);
+          const double xn = __shfl_down(xe, 1);  // x of row 2l + 2
+          ld[j0] = xe;
+          ld[j1] = (d1 - a1 * xe - (l < 63 ? c1 * xn : 0.0)) * r1;
+          lr[j0] = 1.0;
+          lr[j1] = 1.0;
+        }
+        __syncthreads();
       } else {
         for (int j = threadIdx.x; j < L1; j += NT) {
           if (j < n1) {

@@ -377,6 +377,38 @@ def test_fused_step_tiles(B, tile, nsteps):
     assert st["n_active"] == total > 0
 
 
+@pytest.mark.parametrize("ntiles", [20, 32, 33, 50, 64, 65, 100])
+def test_level1_solve_regimes(B, ntiles):
+    """every tile marked (global mode), tiles of 114 cells, the last one
+    ragged: the projection kernel's level-1 system has 2 rows per tile and is
+    solved by one wavefront up to 64 rows, with two rows per lane up to 128,
+    and by block PCR beyond"""
+    case = S.random_case_1d(114 * ntiles - 5, seed=40 + ntiles, dx=0.05)
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.45, tile1d=114)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 6, **kw)
+    assert st["status"] == 0 and st["n_active"] == case.n
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(6)
+    for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+
+
+def test_level1_two_rows_per_lane_across_channels(B):
+    """the two-rows-per-lane level-1 solve (100 rows) on three channels in
+    global mode: no coupling between one channel's last tile and the next
+    channel's first"""
+    ens = ens_small([114 * 10 - 3, 114 * 15, 114 * 24 + 7], seed=12)
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.45, tile1d=114)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 6, **kw)
+    assert st["status"] == 0
+    o = ens.offsets
+    for j, c in enumerate(ens.channels):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.45).step(6)
+        sl = slice(o[j], o[j + 1])
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw),
+                     (p[sl], ref.p)):
+            assert rel(g, r) <= 1e-10, j
+
+
 @pytest.mark.parametrize("n,tile", [(70000, 128), (300000, 128), (40000, 114)])
 def test_fused_step_large_grids(B, n, tile):
     """level-1 system beyond the projection kernel's own solve (more than 512
