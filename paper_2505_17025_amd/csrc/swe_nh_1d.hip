@@ -172,6 +172,30 @@ __device__ __forceinline__ void block_motions(const Chan& c, double t0, double t
   M1 = slot[1];
 }
 
+// the fused step's time step (from the channel's speed slots) and the body's
+// motion at t^n (wavefront 0) and t^{n+1} (wavefront 1, which also reduces
+// the speed slots), shared through LDS; needs at least two wavefronts
+__device__ __forceinline__ void block_step_motions(const K1D& P, int par, int ch, const Chan& c,
+                                                   double t0, double& dt, Motion& M0,
+                                                   Motion& M1) {
+  __shared__ Motion slot[2];
+  __shared__ double sdt;
+  const int wv = threadIdx.x >> 6;
+  if (wv < 2) {
+    double d = 0.0;
+    if (wv == 1) d = (P.cfl > 0.0) ? P.cfl * P.dx / read_speed(P, par, ch) : P.dt_fixed;
+    const Motion m = body_motion(c, wv == 0 ? t0 : t0 + d);
+    if ((threadIdx.x & 63) == 0) {
+      slot[wv] = m;
+      if (wv == 1) sdt = d;
+    }
+  }
+  __syncthreads();
+  dt = sdt;
+  M0 = slot[0];
+  M1 = slot[1];
+}
+
 }  // namespace
 
 // Both Heun stages for a tile of at most T cells.  Thread t owns the window
@@ -879,6 +903,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
                                                double* __restrict__ hn, double* __restrict__ hun,
                                                double* __restrict__ hwn, uint8_t* __restrict__ mask,
                                                double* __restrict__ p, int par) {
+  static_assert(NT >= 128, "the step kernel needs two wavefronts for its time step and motions");
   using SM = StepSmem<T, NT>;
   constexpr int WMAX = SM::WMAX, RW = SM::RW;
   constexpr int Q = (WMAX - 4 + NT - 1) / NT;  // window cells per thread
@@ -889,12 +914,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   const int n = tl.w, start = tl.y, end = min(start + P.tile, n), len = end - start;
   const int64_t off = tl.z;
   const int step = P.step[par];
-  const double dt = (P.cfl > 0.0) ? P.cfl * P.dx / read_speed(P, par, tl.x) : P.dt_fixed;
-  const double t0 = P.t[par * P.nch + tl.x], t1 = t0 + dt;
-  if (start == 0 && threadIdx.x == 0) {  // the channel's first tile
-    P.dt[tl.x] = dt;
-    P.t[(par ^ 1) * P.nch + tl.x] = t1;  // the next step's start time
-  }
+  const double t0 = P.t[par * P.nch + tl.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     P.step[par ^ 1] = step + 1;
     P.n_acc[par ^ 1] = 0;  // counts the next step
@@ -923,7 +943,13 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     vd[q] = P.ds[gi];
   }
   Motion M0, M1;
-  block_motions(c, t0, t1, M0, M1);
+  double dt;
+  block_step_motions(P, par, tl.x, c, t0, dt, M0, M1);
+  const double t1 = t0 + dt;
+  if (start == 0 && threadIdx.x == 0) {  // the channel's first tile
+    P.dt[tl.x] = dt;
+    P.t[(par ^ 1) * P.nch + tl.x] = t1;  // the next step's start time
+  }
 #pragma unroll
   for (int q = 0; q < QL; q++) {
     const int w = threadIdx.x + NT * q;
