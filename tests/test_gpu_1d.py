@@ -255,6 +255,59 @@ def test_long_channel_prefix_parity(B, tile):
         assert rel(g, r) <= 1e-10
 
 
+@pytest.mark.parametrize("fr", [0, 1, 2])
+def test_whittaker_slide_fixed_dt_parity(B, fr):
+    """the sliding-block flume with the piecewise motion law of Eq. 21 and
+    Table 2 (Fr = 0.125, 0.25, 0.375; Sec. 4.3), fixed dt = 0.005 s, |eta/d|
+    with one-cell enlargement: 560 steps cover the law's acceleration,
+    constant-velocity and stopping phases"""
+    case = S.whittaker_case(fr_index=fr)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.0, dt_fixed=0.005)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 560, **kw)
+    assert st["status"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.0, dt_fixed=0.005).step(560)
+    assert ref.time > case.body.q[4]  # past the stop of the law
+    assert abs(st["t"] - ref.time) <= 1e-12 * ref.time
+    assert st["n_active"] == ref.last_active > 0
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    d_end, *_ = O.forcing_1d(case.ds, case.dx, case.body, ref.time)
+    for g, r in ((h - dt(d_end), ref.h - d_end), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+
+
+def test_body_kinds_and_laws_in_one_ensemble(B):
+    """one packed run, fixed dt, of channels whose bodies cover every shape
+    and motion law: none, a resting quartic, a Gaussian at constant velocity,
+    the sinusoidal ramp and the piecewise law"""
+    bodies = [S.Body(),
+              S.Body(kind=S.BODY_QUARTIC, law=S.LAW_FIXED, amp=0.04, length=1.5, x0=60.0),
+              S.Body(kind=S.BODY_GAUSS, law=S.LAW_CONST_VEL, amp=0.05, length=0.8, x0=30.0,
+                     dir=-1.0, q=(0.9, 0, 0, 0, 0)),
+              S.Body(kind=S.BODY_QUARTIC, law=S.LAW_SIN_RAMP, amp=0.06, length=1.2, x0=40.0,
+                     dir=0.95, q=(1.5, 0.8, 0, 0, 0)),
+              S.Body(kind=S.BODY_QUARTIC, law=S.LAW_PIECEWISE, amp=0.05, length=1.0, x0=50.0,
+                     q=(1.5, 0.491, 0.327, 2.327, 2.654))]
+    chans = [S.random_case_1d(n, seed=70 + j, dx=0.05, body=b)
+             for j, (n, b) in enumerate(zip([1800, 2500, 1300, 3100, 2000], bodies))]
+    ens = S.Ensemble(chans)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=1, cfl=0.0, dt_fixed=4e-3)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 60, **kw)
+    assert st["status"] == 0
+    o = ens.offsets
+    total = 0
+    for j, c in enumerate(chans):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.0, dt_fixed=4e-3).step(60)
+        sl = slice(o[j], o[j + 1])
+        d_end, *_ = O.forcing_1d(c.ds, c.dx, c.body, ref.time)
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), j
+        for g, r in ((h[sl] - dt(d_end), ref.h - d_end), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= 1e-10, j
+        if ref.last_active:
+            assert rel(p[sl], ref.p) <= 1e-10, j
+        total += ref.last_active
+    assert st["n_active"] == total > 0
+
+
 def test_batched_ensemble_parity(B):
     ens = S.ensemble_case(n_channels=6, n_min=600, n_max=5000, seed=3, dx=0.005)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5)
