@@ -803,45 +803,89 @@ __device__ bool grid_sync(const Bar& B, unsigned k, int G) {
   return ok != 0;
 }
 
+// LDS rows for the solver's reductions: up to 9 rows of NT2 doubles, shared
+// by the block partials and the grid totals (they are separated by barriers)
+__device__ __forceinline__ double (*red_rows())[NT2] {
+  __shared__ double rows[9][NT2];
+  return rows;
+}
+
+// fixed-order sum of the first nrow rows of NT2 values in `rows`: 16 lanes
+// per row each add 16 consecutive values, then a butterfly over the 16
+// lanes; the sums land in out[row] (all threads synchronised on return)
+__device__ __forceinline__ void sum_rows(const double (*rows)[NT2], int nrow, double* out) {
+  if (threadIdx.x < nrow * 16) {
+    const int k = threadIdx.x >> 4, s = threadIdx.x & 15;
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) a += rows[k][16 * s + i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) a += __shfl_xor(a, o, 16);
+    if (s == 0) out[k] = a;
+  }
+  __syncthreads();
+}
+
 // block partial sums (fixed order) of NV values -> part[v][vb]
 template <int NV>
 __device__ void block_partials(double (&v)[NV], double* part, int vb, int G) {
-  __shared__ double sh[NV][NT2 / 64];
+  static_assert(NV <= 4, "one wavefront sums the rows");
+  double (*rows)[NT2] = red_rows();
 #pragma unroll
-  for (int k = 0; k < NV; k++) {
-    const double s = wave_sum(v[k]);
-    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
-  }
+  for (int k = 0; k < NV; k++) rows[k][threadIdx.x] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < NV * 16) {
+    const int k = threadIdx.x >> 4, s = threadIdx.x & 15;
+    double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
-      double s = 0.0;
-      for (int w = 0; w < NT2 / 64; w++) s += sh[k][w];
-      part[(int64_t)k * G + vb] = s;
-    }
+    for (int i = 0; i < 16; i++) a += rows[k][16 * s + i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) a += __shfl_xor(a, o, 16);
+    if (s == 0) part[(int64_t)k * G + vb] = a;
   }
 }
 
-// the same fixed-order totals of the G partial sums in every block
+// The same fixed-order totals of the G partial sums in every block; with
+// `on`, also the coarse correction: rows `crow` (5 rows of the coarse
+// inverse, one entry per block = per active tile) times the last partial
+// row (the tile sums).  Thread t adds the partials b = t, t + NT2, ...
+template <int NV>
+__device__ void grid_totals_rows(const double* part, int G, double (&tot)[NV], bool on,
+                                 const double (*crow)[CMAX2], double (&c)[5]) {
+  static_assert(NV + 5 <= 9, "reduction rows");
+  __shared__ double out[NV + 5];
+  double (*rows)[NT2] = red_rows();
+  double a[NV + 5];
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++) a[k] = 0.0;
+  for (int b = threadIdx.x; b < G; b += NT2) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      const double v =
+          __hip_atomic_load(&part[(int64_t)k * G + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a[k] += v;
+      if (k == NV - 1 && on) {
+#pragma unroll
+        for (int r = 0; r < 5; r++) a[NV + r] += crow[r][b] * v;
+      }
+    }
+  }
+  const int nrow = on ? NV + 5 : NV;
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++)
+    if (k < nrow) rows[k][threadIdx.x] = a[k];
+  __syncthreads();
+  sum_rows(rows, nrow, out);
+#pragma unroll
+  for (int k = 0; k < NV; k++) tot[k] = out[k];
+#pragma unroll
+  for (int r = 0; r < 5; r++) c[r] = on ? out[NV + r] : 0.0;
+}
+
 template <int NV>
 __device__ void grid_totals(const double* part, int G, double (&tot)[NV]) {
-  __shared__ double sh[NV][NT2 / 64];
-#pragma unroll
-  for (int k = 0; k < NV; k++) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < G; b += NT2)
-      s += __hip_atomic_load(&part[(int64_t)k * G + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; k++) {
-    double s = 0.0;
-    for (int w = 0; w < NT2 / 64; w++) s += sh[k][w];
-    tot[k] = s;
-  }
+  double c[5];
+  grid_totals_rows<NV>(part, G, tot, false, nullptr, c);
 }
 
 // partial sums of the phase that ends with barrier k: two buffers, so that a
@@ -992,28 +1036,17 @@ __device__ __forceinline__ TileOp<R> tile_op(const PcgArgs<R>& A, const TileCell
 
 // u = M^-1 r on one tile; rc[q]: r of the thread's cells (0 off the system);
 // z: LDS [TY2][TX2]; result in z (all threads synchronised on return)
+template <typename R, int K>
+__device__ void tile_precond_k(const TileCells<R> (&C)[K], const TileOp<R> (&T)[K],
+                               const R (&rc)[K][2], R (*z)[TY2][TX2]);
+
 template <typename R>
 __device__ void tile_precond(const TileCells<R>& C, const TileOp<R>& T, const R (&rc)[2],
                              R (*z)[TX2]) {
-#pragma unroll
-  for (int q = 0; q < 2; q++) z[C.lj[q]][C.li[q]] = R(0);
-  __syncthreads();
-  const R om = (R)GS_OMEGA;
-  for (int hs = 0; hs < GS_HALF; hs++) {
-    const int colour = hs & 1;  // 0: red ((i + j) even) first and last
-#pragma unroll
-    for (int q = 0; q < 2; q++) {
-      const int li = C.li[q], lj = C.lj[q];
-      if (((li + lj) & 1) != colour || !(C.nb[q] & NB_SELF)) continue;
-      R a = rc[q];
-      if (C.nb[q] & NB_E) a -= T.cE[q] * z[lj][li + 1];
-      if (C.nb[q] & NB_W) a -= T.cW[q] * z[lj][li - 1];
-      if (C.nb[q] & NB_N) a -= T.cN[q] * z[lj + 1][li];
-      if (C.nb[q] & NB_S) a -= T.cS[q] * z[lj - 1][li];
-      z[lj][li] = (R(1) - om) * z[lj][li] + T.wdg[q] * a;
-    }
-    __syncthreads();
-  }
+  const TileCells<R> Ck[1] = {C};
+  const TileOp<R> Tk[1] = {T};
+  const R rk[1][2] = {{rc[0], rc[1]}};
+  tile_precond_k<R, 1>(Ck, Tk, rk, reinterpret_cast<R(*)[TY2][TX2]>(z));
 }
 
 // The full operator at the thread's cells (couplings across tile edges kept)
@@ -1249,31 +1282,64 @@ __device__ void pcg_cg(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2])
 
 // u = M^-1 r on the K tiles of a block at once (the sweeps of all K tiles
 // share the block's barriers); slot k of zt holds tile k
+// one cell of a thread in the red-black sweeps
+template <typename R>
+struct SorCell {
+  int li, lj;
+  uint8_t f;
+  R r, wdg, cE, cW, cN, cS;
+};
+
+template <typename R>
+__device__ __forceinline__ SorCell<R> sor_cell(const TileCells<R>& C, const TileOp<R>& T,
+                                               const R (&rc)[2], int q) {
+  SorCell<R> X;
+  X.li = q ? C.li[1] : C.li[0];
+  X.lj = C.lj[0];
+  X.f = q ? C.nb[1] : C.nb[0];
+  X.r = q ? rc[1] : rc[0];
+  X.wdg = q ? T.wdg[1] : T.wdg[0];
+  X.cE = q ? T.cE[1] : T.cE[0];
+  X.cW = q ? T.cW[1] : T.cW[0];
+  X.cN = q ? T.cN[1] : T.cN[0];
+  X.cS = q ? T.cS[1] : T.cS[0];
+  return X;
+}
+
+template <typename R>
+__device__ __forceinline__ void sor_relax(const SorCell<R>& X, R (*z)[TX2], R om) {
+  if (!(X.f & NB_SELF)) return;
+  R a = X.r;
+  if (X.f & NB_E) a -= X.cE * z[X.lj][X.li + 1];
+  if (X.f & NB_W) a -= X.cW * z[X.lj][X.li - 1];
+  if (X.f & NB_N) a -= X.cN * z[X.lj + 1][X.li];
+  if (X.f & NB_S) a -= X.cS * z[X.lj - 1][X.li];
+  z[X.lj][X.li] = (R(1) - om) * z[X.lj][X.li] + X.wdg * a;
+}
+
+// The thread's two cells 2t, 2t + 1 are neighbours in one row, so one is red
+// and one black: each half-sweep relaxes exactly one cell per thread.  The
+// first (red) half-sweep starts from z = 0, where a red cell's neighbours
+// are all zero: it takes wdg r, and the black cells are cleared with it.
 template <typename R, int K>
 __device__ void tile_precond_k(const TileCells<R> (&C)[K], const TileOp<R> (&T)[K],
                                const R (&rc)[K][2], R (*z)[TY2][TX2]) {
+  SorCell<R> X[K][2];  // [tile][colour]
 #pragma unroll
-  for (int k = 0; k < K; k++)
-#pragma unroll
-    for (int q = 0; q < 2; q++) z[k][C[k].lj[q]][C[k].li[q]] = R(0);
+  for (int k = 0; k < K; k++) {
+    const int q0 = (C[k].li[0] + C[k].lj[0]) & 1;  // colour of cell 0
+    X[k][0] = sor_cell(C[k], T[k], rc[k], q0);      // red: (i + j) even
+    X[k][1] = sor_cell(C[k], T[k], rc[k], q0 ^ 1);
+    const SorCell<R>& Rd = X[k][0];
+    z[k][Rd.lj][Rd.li] = (Rd.f & NB_SELF) ? Rd.wdg * Rd.r : R(0);
+    z[k][X[k][1].lj][X[k][1].li] = R(0);
+  }
   __syncthreads();
   const R om = (R)GS_OMEGA;
-  for (int hs = 0; hs < GS_HALF; hs++) {
-    const int colour = hs & 1;  // 0: red ((i + j) even) first and last
 #pragma unroll
-    for (int k = 0; k < K; k++)
+  for (int hs = 1; hs < GS_HALF; hs++) {
 #pragma unroll
-      for (int q = 0; q < 2; q++) {
-        const int li = C[k].li[q], lj = C[k].lj[q];
-        const uint8_t f = C[k].nb[q];
-        if (((li + lj) & 1) != colour || !(f & NB_SELF)) continue;
-        R a = rc[k][q];
-        if (f & NB_E) a -= T[k].cE[q] * z[k][lj][li + 1];
-        if (f & NB_W) a -= T[k].cW[q] * z[k][lj][li - 1];
-        if (f & NB_N) a -= T[k].cN[q] * z[k][lj + 1][li];
-        if (f & NB_S) a -= T[k].cS[q] * z[k][lj - 1][li];
-        z[k][lj][li] = (R(1) - om) * z[k][lj][li] + T[k].wdg[q] * a;
-      }
+    for (int k = 0; k < K; k++) sor_relax(X[k][hs & 1], z[k], om);
     __syncthreads();
   }
 }
@@ -1313,41 +1379,8 @@ __device__ bool coarse_rows(const PcgArgs<R>& A, int t, int nc, double (*rows)[C
 template <int NV, typename R>
 __device__ void grid_totals_coarse(const double* part, int G, double (&tot)[NV], bool on,
                                    const double (*rows)[CMAX2], Coarse<R>& cc) {
-  __shared__ double sh[NV + 5][NT2 / 64];
-  double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < NV; k++) {
-    double sum = 0.0;
-    for (int b = threadIdx.x; b < G; b += NT2) {
-      const double v =
-          __hip_atomic_load(&part[(int64_t)k * G + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      sum += v;
-      if (k == NV - 1 && on) {
-#pragma unroll
-        for (int r = 0; r < 5; r++) c[r] += rows[r][b] * v;
-      }
-    }
-    sum = wave_sum(sum);
-    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = sum;
-  }
-  if (on) {
-#pragma unroll
-    for (int r = 0; r < 5; r++) {
-      const double t = wave_sum(c[r]);
-      if ((threadIdx.x & 63) == 0) sh[NV + r][threadIdx.x >> 6] = t;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV + 5; k++) {
-    double t = 0.0;
-    if (k < NV || on)
-      for (int w = 0; w < NT2 / 64; w++) t += sh[k][w];
-    if (k < NV)
-      tot[k] = t;
-    else
-      c[k - NV] = t;
-  }
+  double c[5];
+  grid_totals_rows<NV>(part, G, tot, on, rows, c);
   cc.own = (R)c[0];
   cc.e = (R)c[1];
   cc.w = (R)c[2];
