@@ -43,6 +43,12 @@ struct Ctx2D {
   double* v64[PCG_NVEC] = {};
   unsigned* tflag = nullptr;  // per tile: neighbour-sync stamp
   double* part = nullptr;    // [2][4][PCG_GMAX] block partial sums
+  // tagged words of the pipelined solver: M^-1 w by tag parity (1 word per
+  // value in FP32, 2 in FP64) and the block partials [2][4][PCG_GMAX][2]
+  unsigned long long* mtag[2] = {nullptr, nullptr};
+  unsigned long long* pt = nullptr;
+  size_t tag_bytes = 0;
+  unsigned* tag_base = nullptr;  // first tag of the next solve
   unsigned long long* bar = nullptr;  // grid barrier arrival counter
   int* iters = nullptr;
   long long* iters_sum = nullptr;

@@ -803,6 +803,62 @@ __device__ bool grid_sync(const Bar& B, unsigned k, int G) {
   return ok != 0;
 }
 
+// Tagged words: the pipelined solver publishes each value of a pass with the
+// pass's tag in the upper half of a 64-bit word (agent-scope relaxed atomic
+// stores; an FP64 value takes two words, each with the tag), and a reader
+// polls until every word it needs carries the tag it expects.  The values
+// validate themselves, so a pass needs neither the arrival counter nor the
+// cache write-back and invalidation of the barrier's fences.  Tags grow over
+// the context's life (never reused while a word could still hold them).
+__device__ __forceinline__ void put_tagged(unsigned long long* w, float v, unsigned tag) {
+  __hip_atomic_store(w, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put_tagged(unsigned long long* w, double v, unsigned tag) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  __hip_atomic_store(w, ((unsigned long long)tag << 32) | (b & 0xffffffffull), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 1, ((unsigned long long)tag << 32) | (b >> 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long load_word(const unsigned long long* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// one poll: true (and the value) when the words carry the tag
+__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, float& v) {
+  const unsigned long long a = load_word(w);
+  if ((unsigned)(a >> 32) != tag) return false;
+  v = __uint_as_float((unsigned)a);
+  return true;
+}
+__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, double& v) {
+  const unsigned long long a = load_word(w), b = load_word(w + 1);
+  if ((unsigned)(a >> 32) != tag || (unsigned)(b >> 32) != tag) return false;
+  v = __longlong_as_double((long long)((b << 32) | (a & 0xffffffffull)));
+  return true;
+}
+// bounded poll as in wait_count; false when the wait timed out or the solve aborted
+template <typename V>
+__device__ bool get_tagged(const unsigned long long* w, unsigned tag, V& v, const Bar& B) {
+  const unsigned long long t0 = wall_clock64();
+  unsigned polls = 0;
+  while (!try_tagged(w, tag, v)) {
+    if ((++polls & 255u) == 0u) {
+      if (aborted(B)) return false;
+      if (wall_clock64() - t0 > WAIT_TICKS) {
+        atomicOr(B.status, ST_ABORT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+template <typename R>
+constexpr int tag_words() {
+  return sizeof(R) / 4;  // 64-bit words per tagged value
+}
+
 // LDS rows for the solver's reductions: up to 9 rows of NT2 doubles, shared
 // by the block partials and the grid totals (they are separated by barriers)
 __device__ __forceinline__ double (*red_rows())[NT2] {
@@ -888,6 +944,67 @@ __device__ void grid_totals(const double* part, int G, double (&tot)[NV]) {
   grid_totals_rows<NV>(part, G, tot, false, nullptr, c);
 }
 
+// block_partials with tagged words: pt[(k G + vb) 2 + {0, 1}]
+template <int NV>
+__device__ void block_partials_tagged(double (&v)[NV], unsigned long long* pt, int vb, int G,
+                                      unsigned tag) {
+  static_assert(NV <= 4, "one wavefront sums the rows");
+  double (*rows)[NT2] = red_rows();
+#pragma unroll
+  for (int k = 0; k < NV; k++) rows[k][threadIdx.x] = v[k];
+  __syncthreads();
+  if (threadIdx.x < NV * 16) {
+    const int k = threadIdx.x >> 4, s = threadIdx.x & 15;
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) a += rows[k][16 * s + i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) a += __shfl_xor(a, o, 16);
+    if (s == 0) put_tagged(pt + ((int64_t)k * G + vb) * 2, a, tag);
+  }
+}
+
+// grid_totals_rows over tagged partials: every block polls the G partials of
+// the pass (this is the pass's only grid-wide wait).  Returns false in every
+// thread when the solve aborted (*abort_flag, an LDS word, is then set).
+template <int NV>
+__device__ bool grid_totals_tagged(const unsigned long long* pt, int G, unsigned tag,
+                                   double (&tot)[NV], bool on, const double (*crow)[CMAX2],
+                                   double (&c)[5], const Bar& B, int* abort_flag) {
+  static_assert(NV + 5 <= 9, "reduction rows");
+  __shared__ double out[NV + 5];
+  double (*rows)[NT2] = red_rows();
+  double a[NV + 5];
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++) a[k] = 0.0;
+  bool ok = true;
+  for (int b = threadIdx.x; b < G && ok; b += NT2) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      double v = 0.0;
+      if (ok) ok = get_tagged(pt + ((int64_t)k * G + b) * 2, tag, v, B);
+      a[k] += v;
+      if (k == NV - 1 && on) {
+#pragma unroll
+        for (int r = 0; r < 5; r++) a[NV + r] += crow[r][b] * v;
+      }
+    }
+  }
+  if (!ok) *abort_flag = 1;
+  const int nrow = on ? NV + 5 : NV;
+  __syncthreads();  // the block partials' reads of the rows are done
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++)
+    if (k < nrow) rows[k][threadIdx.x] = a[k];
+  __syncthreads();
+  sum_rows(rows, nrow, out);
+#pragma unroll
+  for (int k = 0; k < NV; k++) tot[k] = out[k];
+#pragma unroll
+  for (int r = 0; r < 5; r++) c[r] = on ? out[NV + r] : 0.0;
+  return *abort_flag == 0;
+}
+
 // partial sums of the phase that ends with barrier k: two buffers, so that a
 // block already writing the next phase's partials cannot overwrite values
 // another block is still reading
@@ -906,7 +1023,10 @@ struct PcgArgs {
   double* x;
   const R *dgR, *ceR, *cnR;
   R *r, *u, *w, *z, *q, *s, *p, *e;
-  R* m[2];          // M^-1 w, double-buffered by pass parity (pipelined form)
+  R* m[2];          // M^-1 w, double-buffered by pass parity (unused by the tagged form)
+  unsigned long long* mt[2];  // tagged M^-1 w on the tiles' edge cells, by tag parity
+  unsigned long long* pt;     // tagged block partials [2][4][PCG_GMAX][2], by tag parity
+  unsigned* tag_base;         // first tag of the next solve
   int pipe_blocks;  // grid of the pipelined form (decides which form runs)
   const int* tile_pos;  // per tile: position in tile_list (-1: inactive)
   const double* cinv;   // (Z^T A Z)^-1 of the active tiles (coarse space), or null
@@ -1406,6 +1526,83 @@ __device__ __forceinline__ R apply_coarse(const FullOp<R>& F, const TileCells<R>
   return a;
 }
 
+// whether the thread's cell q couples to a cell outside its tile in
+// direction d (0 E, 1 W, 2 N, 3 S), and that cell's offset from it
+template <typename R>
+__device__ __forceinline__ bool off_tile(const FullOp<R>& F, const TileCells<R>& C, int q, int d) {
+  const uint8_t f = F.nf[q];
+  const int li = C.li[q], lj = C.lj[q];
+  switch (d) {
+    case 0: return (f & NB_E) && li + 1 == TX2;
+    case 1: return (f & NB_W) && li == 0;
+    case 2: return (f & NB_N) && lj + 1 == TY2;
+    default: return (f & NB_S) && lj == 0;
+  }
+}
+__device__ __forceinline__ int64_t dir_offset(int d, int nx) {
+  return d == 0 ? 1 : d == 1 ? -1 : d == 2 ? (int64_t)nx : -(int64_t)nx;
+}
+
+// the values of the tagged vector mt outside the tile that the thread's cells
+// couple to, polled until they carry `tag`: hv[q][d]
+template <typename R, int K>
+__device__ bool halo_tagged(const FullOp<R> (&F)[K], const TileCells<R> (&C)[K],
+                            const unsigned long long* mt, unsigned tag, int nx, R (&hv)[K][2][4],
+                            const Bar& B) {
+  constexpr int W = tag_words<R>();
+  unsigned need = 0;
+#pragma unroll
+  for (int k = 0; k < K; k++)
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+      for (int d = 0; d < 4; d++) {
+        hv[k][q][d] = R(0);
+        if (off_tile(F[k], C[k], q, d)) need |= 1u << (8 * k + 4 * q + d);
+      }
+  if (!need) return true;
+  const unsigned long long t0 = wall_clock64();
+  unsigned polls = 0;
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < K; k++)
+#pragma unroll
+      for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+          const unsigned bit = 1u << (8 * k + 4 * q + d);
+          if (!(need & bit)) continue;
+          const int64_t o = C[k].o[q] + dir_offset(d, nx);
+          if (try_tagged(mt + o * W, tag, hv[k][q][d])) need &= ~bit;
+        }
+    if (!need) return true;
+    if ((++polls & 255u) == 0u) {
+      if (aborted(B)) return false;
+      if (wall_clock64() - t0 > WAIT_TICKS) {
+        atomicOr(B.status, ST_ABORT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// (A v) at the thread's cell q with v's tile-local part from LDS, its values
+// outside the tile from hv (E, W, N, S), plus the coarse constants
+template <typename R>
+__device__ __forceinline__ R apply_halo(const FullOp<R>& F, const TileCells<R>& C, int q,
+                                        const R (&hv)[4], const R (*zt)[TX2],
+                                        const Coarse<R>& K) {
+  const int li = C.li[q], lj = C.lj[q];
+  const uint8_t f = F.nf[q];
+  R a = F.dg[q] * (zt[lj][li] + K.own);
+  if (f & NB_E) a += F.cE[q] * (li + 1 < TX2 ? zt[lj][li + 1] + K.own : hv[0] + K.e);
+  if (f & NB_W) a += F.cW[q] * (li > 0 ? zt[lj][li - 1] + K.own : hv[1] + K.w);
+  if (f & NB_N) a += F.cN[q] * (lj + 1 < TY2 ? zt[lj + 1][li] + K.own : hv[2] + K.n);
+  if (f & NB_S) a += F.cS[q] * (lj > 0 ? zt[lj - 1][li] + K.own : hv[3] + K.s);
+  return a;
+}
+
 // Preconditioned CG in the pipelined form of Ghysels and Vanroose (2014)
 // for blocks that own up to K tiles each: per iteration one pass and one
 // grid barrier, which both completes the reduction of (r,u), (w,u), (r,r)
@@ -1413,9 +1610,13 @@ __device__ __forceinline__ R apply_coarse(const FullOp<R>& F, const TileCells<R>
 // next pass (m double-buffered by pass parity).  The vectors stay in
 // registers and the tiles' m stays in LDS for the whole solve.
 template <typename R, int K>
-__device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TY2][TX2],
-                              double (*crows)[CMAX2]) {
+__device__ unsigned pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TY2][TX2],
+                                  double (*crows)[CMAX2], unsigned base) {
   const int nx = A.nx;
+  __shared__ int s_abort;  // set by any thread whose poll of a pass timed out or saw an abort
+  if (threadIdx.x == 0) s_abort = 0;
+  __syncthreads();
+  unsigned tp = 0;  // tags used: the pass with tag base + tp is the latest
   TileCells<R> C[K];
   FullOp<R> F[K];
   TileOp<R> T[K];
@@ -1466,7 +1667,7 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
           A.u[C[k].o[q]] = zt[k][C[k].lj[q]][C[k].li[q]];  // the tile-local part
         }
       block_partials<3>(v, part_buf(A.part, bk + 1), S.vb, G);
-      if (!grid_sync(A.bar, ++bk, G)) return;
+      if (!grid_sync(A.bar, ++bk, G)) return tp;
       double tt[3];
       grid_totals_coarse<3, R>(part_buf(A.part, bk), G, tt, coarse, crows, cu);
       rr = tt[0];
@@ -1503,8 +1704,10 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
       // barrier.  zt holds the tile-local part of u_0 (j == 0) or of m_{j-1}
       // on entry.
       const R al = (R)alpha, bt = (R)beta;
-      const R* mprev = A.m[(j + 1) & 1];
-      R* mnext = A.m[j & 1];
+      const unsigned tag = base + (++tp);
+      R hv[K][2][4];  // m_{j-1} outside the tiles (tag - 1)
+      if (j > 0 && !halo_tagged<R, K>(F, C, A.mt[(tag - 1) & 1], tag - 1, nx, hv, A.bar))
+        s_abort = 1;
       double v[4] = {0.0, 0.0, 0.0, 0.0};  // (r,u), (w,u), (r,r), tile sum of w
       R wc[K][2];
 #pragma unroll
@@ -1518,8 +1721,7 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
             Y.w[q] = coarse ? apply_coarse(F[k], C[k], q, A.u, zt[k], nx, cu)
                             : apply_at(F[k], C[k], q, A.u, zt[k], true, nx);
           } else {
-            const R n = coarse ? apply_coarse(F[k], C[k], q, mprev, zt[k], nx, cm)
-                               : apply_at(F[k], C[k], q, mprev, zt[k], true, nx);
+            const R n = apply_halo(F[k], C[k], q, hv[k][q], zt[k], cm);
             const R m = zt[k][C[k].lj[q]][C[k].li[q]] + cm.own;
             const bool first = j == 1;
             Y.z[q] = first ? n : fma(bt, Y.z[q], n);
@@ -1538,16 +1740,28 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
           v[3] += (double)Y.w[q];
         }
       __syncthreads();  // the tiles' LDS values are read before the sweeps overwrite them
+      if (s_abort) return tp;
       tile_precond_k<R, K>(C, T, wc, zt);
+      // m_j on the tiles' edge cells, for the neighbours' next pass
+      unsigned long long* mw = A.mt[tag & 1];
 #pragma unroll
       for (int k = 0; k < K; k++)
 #pragma unroll
-        for (int q = 0; q < 2; q++)
-          if (F[k].nf[q] & NB_SELF) mnext[C[k].o[q]] = zt[k][C[k].lj[q]][C[k].li[q]];
-      block_partials<4>(v, part_buf(A.part, bk + 1), S.vb, G);
-      if (!grid_sync(A.bar, ++bk, G)) return;
-      double tt[4];
-      grid_totals_coarse<4, R>(part_buf(A.part, bk), G, tt, coarse, crows, cm);
+        for (int q = 0; q < 2; q++) {
+          const int li = C[k].li[q], lj = C[k].lj[q];
+          const bool edge = li == 0 || li == TX2 - 1 || lj == 0 || lj == TY2 - 1;
+          if (edge && (F[k].nf[q] & NB_SELF))
+            put_tagged(mw + C[k].o[q] * tag_words<R>(), zt[k][lj][li], tag);
+        }
+      unsigned long long* pw = A.pt + (size_t)(tag & 1u) * (8 * PCG_GMAX);
+      block_partials_tagged<4>(v, pw, S.vb, G, tag);
+      double tt[4], c5[5];
+      if (!grid_totals_tagged<4>(pw, G, tag, tt, coarse, crows, c5, A.bar, &s_abort)) return tp;
+      cm.own = (R)c5[0];
+      cm.e = (R)c5[1];
+      cm.w = (R)c5[2];
+      cm.n = (R)c5[3];
+      cm.s = (R)c5[4];
       const double gn = tt[0], dn = tt[1], rn = tt[2];
       if (j > 0) {
         total++;
@@ -1571,13 +1785,14 @@ __device__ void pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R (*zt
 #pragma unroll
       for (int q = 0; q < 2; q++)
         if (F[k].nf[q] & NB_SELF) A.x[C[k].o[q]] += (double)X[k].e[q];
-    if (!grid_sync(A.bar, ++bk, G)) return;
+    if (!grid_sync(A.bar, ++bk, G)) return tp;
     sweep++;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *A.iters = total;
     *A.iters_sum += total;
   }
+  return tp;
 }
 
 // Persistent preconditioned CG (M^-1: the tile-block symmetric red-black SOR
@@ -1595,7 +1810,11 @@ __global__ void __launch_bounds__(NT2) k_pcg2d_pipe(PcgArgs<R> A) {
   if (nlist < 1 || nlist > PCG_K * A.pipe_blocks) return;  // the other form's case
   const int G = (nlist + PCG_K - 1) / PCG_K;
   if ((int)blockIdx.x >= G) return;
-  pcg_pipelined<R, PCG_K>(A, share_of(G, nlist), G, zt, crows);
+  // every block reads the tag base before block 0 can pass its first pass
+  const unsigned base = *A.tag_base;
+  const unsigned used = pcg_pipelined<R, PCG_K>(A, share_of(G, nlist), G, zt, crows, base);
+  // no block is more than one pass ahead of block 0, even after an abort
+  if (blockIdx.x == 0 && threadIdx.x == 0) *A.tag_base = base + used + 2;
 }
 
 template <typename R>
@@ -1891,6 +2110,10 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.tile_pos = x->tile_pos;
   A.cinv = x->cinv;
   A.cused = x->cused;
+  A.mt[0] = x->mtag[0];
+  A.mt[1] = x->mtag[1];
+  A.pt = x->pt;
+  A.tag_base = x->tag_base;
   return A;
 }
 
@@ -2007,6 +2230,12 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
       x->v64[k] = (double*)take(8 * N);
   }
   x->part = (double*)take(8 * 2 * 4 * (size_t)PCG_GMAX);
+  const size_t tw = c->precision == 1 ? 1 : 2;  // 64-bit words per tagged value
+  x->tag_bytes = 8 * (2 * tw * N + 2 * 4 * 2 * (size_t)PCG_GMAX) + 256;
+  x->mtag[0] = (unsigned long long*)take(x->tag_bytes);
+  x->mtag[1] = x->mtag[0] + tw * N;
+  x->pt = x->mtag[1] + tw * N;
+  x->tag_base = (unsigned*)take(4);
   x->bar = (unsigned long long*)take(8);
   x->tflag = (unsigned*)take(4 * (size_t)x->ntiles);
   x->iters = (int*)take(4);
@@ -2061,6 +2290,10 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   if (x->cnn_ws && hipMemset(x->cnn_ws, 0, x->cnn_bytes) != hipSuccess) return SWE_NH_EHIP;
   const long long zl = 0;
   if (hipMemcpy(x->iters_sum, &zl, 8, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
+  // tagged words start with tag 0, which no pass uses (tags start at 2)
+  if (hipMemset(x->mtag[0], 0, x->tag_bytes) != hipSuccess) return SWE_NH_EHIP;
+  const unsigned one = 1;
+  if (hipMemcpy(x->tag_base, &one, 4, hipMemcpyHostToDevice) != hipSuccess) return SWE_NH_EHIP;
   const int none[3] = {-1, 0, 0};  // no coarse inverse yet
   if (hipMemcpy(x->cused, none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess)
     return SWE_NH_EHIP;
