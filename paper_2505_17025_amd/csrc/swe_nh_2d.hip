@@ -837,23 +837,6 @@ __device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned
   v = __longlong_as_double((long long)((b << 32) | (a & 0xffffffffull)));
   return true;
 }
-// bounded poll as in wait_count; false when the wait timed out or the solve aborted
-template <typename V>
-__device__ bool get_tagged(const unsigned long long* w, unsigned tag, V& v, const Bar& B) {
-  const unsigned long long t0 = wall_clock64();
-  unsigned polls = 0;
-  while (!try_tagged(w, tag, v)) {
-    if ((++polls & 255u) == 0u) {
-      if (aborted(B)) return false;
-      if (wall_clock64() - t0 > WAIT_TICKS) {
-        atomicOr(B.status, ST_ABORT);
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  return true;
-}
 template <typename R>
 constexpr int tag_words() {
   return sizeof(R) / 4;  // 64-bit words per tagged value
@@ -962,47 +945,6 @@ __device__ void block_partials_tagged(double (&v)[NV], unsigned long long* pt, i
     for (int o = 8; o > 0; o >>= 1) a += __shfl_xor(a, o, 16);
     if (s == 0) put_tagged(pt + ((int64_t)k * G + vb) * 2, a, tag);
   }
-}
-
-// grid_totals_rows over tagged partials: every block polls the G partials of
-// the pass (this is the pass's only grid-wide wait).  Returns false in every
-// thread when the solve aborted (*abort_flag, an LDS word, is then set).
-template <int NV>
-__device__ bool grid_totals_tagged(const unsigned long long* pt, int G, unsigned tag,
-                                   double (&tot)[NV], bool on, const double (*crow)[CMAX2],
-                                   double (&c)[5], const Bar& B, int* abort_flag) {
-  static_assert(NV + 5 <= 9, "reduction rows");
-  __shared__ double out[NV + 5];
-  double (*rows)[NT2] = red_rows();
-  double a[NV + 5];
-#pragma unroll
-  for (int k = 0; k < NV + 5; k++) a[k] = 0.0;
-  bool ok = true;
-  for (int b = threadIdx.x; b < G && ok; b += NT2) {
-#pragma unroll
-    for (int k = 0; k < NV; k++) {
-      double v = 0.0;
-      if (ok) ok = get_tagged(pt + ((int64_t)k * G + b) * 2, tag, v, B);
-      a[k] += v;
-      if (k == NV - 1 && on) {
-#pragma unroll
-        for (int r = 0; r < 5; r++) a[NV + r] += crow[r][b] * v;
-      }
-    }
-  }
-  if (!ok) *abort_flag = 1;
-  const int nrow = on ? NV + 5 : NV;
-  __syncthreads();  // the block partials' reads of the rows are done
-#pragma unroll
-  for (int k = 0; k < NV + 5; k++)
-    if (k < nrow) rows[k][threadIdx.x] = a[k];
-  __syncthreads();
-  sum_rows(rows, nrow, out);
-#pragma unroll
-  for (int k = 0; k < NV; k++) tot[k] = out[k];
-#pragma unroll
-  for (int r = 0; r < 5; r++) c[r] = on ? out[NV + r] : 0.0;
-  return *abort_flag == 0;
 }
 
 // partial sums of the phase that ends with barrier k: two buffers, so that a
@@ -1543,14 +1485,23 @@ __device__ __forceinline__ int64_t dir_offset(int d, int nx) {
   return d == 0 ? 1 : d == 1 ? -1 : d == 2 ? (int64_t)nx : -(int64_t)nx;
 }
 
-// the values of the tagged vector mt outside the tile that the thread's cells
-// couple to, polled until they carry `tag`: hv[q][d]
-template <typename R, int K>
-__device__ bool halo_tagged(const FullOp<R> (&F)[K], const TileCells<R> (&C)[K],
-                            const unsigned long long* mt, unsigned tag, int nx, R (&hv)[K][2][4],
-                            const Bar& B) {
+// The end of a pass: one polling loop gathers both the pass's block partials
+// (all G of them, thread t taking b = t, t + NT2, ...) and the values of the
+// vector just published (mt) outside the thread's tiles, for the next pass's
+// product, so that the two waits overlap; then the fixed-order totals as in
+// grid_totals_rows.  Returns false in every thread when the solve aborted.
+template <int NV, typename R, int K>
+__device__ bool pass_end_tagged(const unsigned long long* pt, int G, unsigned tag,
+                                double (&tot)[NV], bool on, const double (*crow)[CMAX2],
+                                double (&c)[5], const FullOp<R> (&F)[K],
+                                const TileCells<R> (&C)[K], const unsigned long long* mt, int nx,
+                                R (&hv)[K][2][4], const Bar& B, int* abort_flag) {
+  static_assert(NV + 5 <= 9, "reduction rows");
+  constexpr int NBT = PCG_GMAX / NT2;  // partials per thread
+  static_assert(NBT * NV <= 32 && 8 * K <= 32, "poll masks");
   constexpr int W = tag_words<R>();
-  unsigned need = 0;
+  __shared__ double out[NV + 5];
+  unsigned nh = 0, np = 0;
 #pragma unroll
   for (int k = 0; k < K; k++)
 #pragma unroll
@@ -1558,12 +1509,20 @@ __device__ bool halo_tagged(const FullOp<R> (&F)[K], const TileCells<R> (&C)[K],
 #pragma unroll
       for (int d = 0; d < 4; d++) {
         hv[k][q][d] = R(0);
-        if (off_tile(F[k], C[k], q, d)) need |= 1u << (8 * k + 4 * q + d);
+        if (off_tile(F[k], C[k], q, d)) nh |= 1u << (8 * k + 4 * q + d);
       }
-  if (!need) return true;
+  double pv[NBT][NV];
+#pragma unroll
+  for (int i = 0; i < NBT; i++)
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      pv[i][k] = 0.0;
+      if ((int)threadIdx.x + NT2 * i < G) np |= 1u << (NV * i + k);
+    }
+  bool ok = true;
   const unsigned long long t0 = wall_clock64();
   unsigned polls = 0;
-  for (;;) {
+  while (nh | np) {
 #pragma unroll
     for (int k = 0; k < K; k++)
 #pragma unroll
@@ -1571,20 +1530,56 @@ __device__ bool halo_tagged(const FullOp<R> (&F)[K], const TileCells<R> (&C)[K],
 #pragma unroll
         for (int d = 0; d < 4; d++) {
           const unsigned bit = 1u << (8 * k + 4 * q + d);
-          if (!(need & bit)) continue;
-          const int64_t o = C[k].o[q] + dir_offset(d, nx);
-          if (try_tagged(mt + o * W, tag, hv[k][q][d])) need &= ~bit;
+          if ((nh & bit) &&
+              try_tagged(mt + (C[k].o[q] + dir_offset(d, nx)) * W, tag, hv[k][q][d]))
+            nh &= ~bit;
         }
-    if (!need) return true;
+#pragma unroll
+    for (int i = 0; i < NBT; i++)
+#pragma unroll
+      for (int k = 0; k < NV; k++) {
+        const unsigned bit = 1u << (NV * i + k);
+        const int b = threadIdx.x + NT2 * i;
+        if ((np & bit) && try_tagged(pt + ((int64_t)k * G + b) * 2, tag, pv[i][k])) np &= ~bit;
+      }
+    if (!(nh | np)) break;
     if ((++polls & 255u) == 0u) {
-      if (aborted(B)) return false;
-      if (wall_clock64() - t0 > WAIT_TICKS) {
-        atomicOr(B.status, ST_ABORT);
-        return false;
+      if (aborted(B) || wall_clock64() - t0 > WAIT_TICKS) {
+        if (!aborted(B)) atomicOr(B.status, ST_ABORT);
+        ok = false;
+        break;
       }
     }
     __builtin_amdgcn_s_sleep(1);
   }
+  if (!ok) *abort_flag = 1;
+  double a[NV + 5];
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++) a[k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NBT; i++) {
+    const int b = threadIdx.x + NT2 * i;
+    if (b >= G) continue;
+#pragma unroll
+    for (int k = 0; k < NV; k++) a[k] += pv[i][k];
+    if (on) {
+#pragma unroll
+      for (int r = 0; r < 5; r++) a[NV + r] += crow[r][b] * pv[i][NV - 1];
+    }
+  }
+  double (*rows)[NT2] = red_rows();
+  const int nrow = on ? NV + 5 : NV;
+  __syncthreads();  // the block partials' reads of the rows are done
+#pragma unroll
+  for (int k = 0; k < NV + 5; k++)
+    if (k < nrow) rows[k][threadIdx.x] = a[k];
+  __syncthreads();
+  sum_rows(rows, nrow, out);
+#pragma unroll
+  for (int k = 0; k < NV; k++) tot[k] = out[k];
+#pragma unroll
+  for (int r = 0; r < 5; r++) c[r] = on ? out[NV + r] : 0.0;
+  return *abort_flag == 0;
 }
 
 // (A v) at the thread's cell q with v's tile-local part from LDS, its values
@@ -1696,6 +1691,7 @@ __device__ unsigned pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R 
     const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
                                             : 0.5 * A.tol * sqrt(bb);
     double gam = 0.0, alpha = 0.0, beta = 0.0;
+    R hv[K][2][4];  // m of the last pass outside the tiles (gathered at its end)
     for (int j = 0;; j++) {
       // pass j: (j >= 1) n = A m_{j-1} and the recurrences with alpha_{j-1},
       // beta_{j-1}; (j == 0) w_0 = A u_0.  Then the partial sums of pass j
@@ -1705,9 +1701,6 @@ __device__ unsigned pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R 
       // on entry.
       const R al = (R)alpha, bt = (R)beta;
       const unsigned tag = base + (++tp);
-      R hv[K][2][4];  // m_{j-1} outside the tiles (tag - 1)
-      if (j > 0 && !halo_tagged<R, K>(F, C, A.mt[(tag - 1) & 1], tag - 1, nx, hv, A.bar))
-        s_abort = 1;
       double v[4] = {0.0, 0.0, 0.0, 0.0};  // (r,u), (w,u), (r,r), tile sum of w
       R wc[K][2];
 #pragma unroll
@@ -1756,7 +1749,9 @@ __device__ unsigned pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R 
       unsigned long long* pw = A.pt + (size_t)(tag & 1u) * (8 * PCG_GMAX);
       block_partials_tagged<4>(v, pw, S.vb, G, tag);
       double tt[4], c5[5];
-      if (!grid_totals_tagged<4>(pw, G, tag, tt, coarse, crows, c5, A.bar, &s_abort)) return tp;
+      if (!pass_end_tagged<4, R, K>(pw, G, tag, tt, coarse, crows, c5, F, C, mw, nx, hv, A.bar,
+                                    &s_abort))
+        return tp;
       cm.own = (R)c5[0];
       cm.e = (R)c5[1];
       cm.w = (R)c5[2];
