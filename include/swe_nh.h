@@ -254,10 +254,12 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double
  * graph's length.  The state arrays must hold a valid state of
  * the context (for instance after swe_nh_step).
  * 1D with precision 0 and enlarge <= 8 (the fused step): stage 0 the fused
- * step kernel (predictor, criterion, assembly, tile reduction), 1 the
- * separate level-1 solve, 2 the projection kernel, 3 the stand-alone
- * predictor; outputs go to workspace scratch, the caller's arrays and the
- * time are not modified.
+ * step kernel (predictor, criterion, assembly, tile reduction; in the
+ * one-kernel step of grids of at most 512 tiles also the level-1 solve and
+ * the projection), 1 the separate level-1 solve, 2 the projection kernel
+ * (both report 0 in the one-kernel step, which has neither), 3 the
+ * stand-alone predictor; outputs go to workspace scratch, the caller's
+ * arrays and the time are not modified.
  * Otherwise: stage 0 predictor, 1 criterion/mask, 2 elliptic solve (all
  * solver launches of one solve), 3 projection; stage 0 uses the time step of
  * the last step and writes only the workspace, stages 1-3 reuse the

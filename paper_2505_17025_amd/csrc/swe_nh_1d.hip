@@ -889,14 +889,272 @@ __device__ int pcr_tile(StepSmem<T, NT>& S, int m) {
   }
   return cur;
 }
+// Tridiagonal solve of n <= 64 rows held one per lane of the calling
+// wavefront (a: sub-, b: main, c: super-diagonal, d: right-hand side; lanes
+// at or beyond n hold identity rows): parallel cyclic reduction with
+// cross-lane shuffles, no block barrier.  Returns x of the lane's row.
+__device__ __forceinline__ double wave_pcr(double a, double b, double c, double d, int n) {
+  const int lane = threadIdx.x & 63;
+  for (int s = 1; s < n; s <<= 1) {
+    const double am = __shfl_up(a, s), bm = __shfl_up(b, s), cm = __shfl_up(c, s),
+                 dm = __shfl_up(d, s);
+    const double ap = __shfl_down(a, s), bp = __shfl_down(b, s), cp = __shfl_down(c, s),
+                 dp = __shfl_down(d, s);
+    double na = 0.0, nb = b, nc = 0.0, nd = d;
+    if (lane >= s) {
+      const double k1 = a * rcp64(bm);
+      na = -am * k1;
+      nb -= cm * k1;
+      nd -= dm * k1;
+    }
+    if (lane + s < 64) {
+      const double k2 = c * rcp64(bp);
+      nc = -cp * k2;
+      nb -= ap * k2;
+      nd -= dp * k2;
+    }
+    a = na;
+    b = nb;
+    c = nc;
+    d = nd;
+  }
+  return d * rcp64(b);
+}
+
+// polls the 6 level-1 row values of tile t (12 words) in one loop, so their
+// loads overlap; false when the wait timed out or the step aborted
+__device__ bool poll_rows6(const unsigned long long* rw, int t, unsigned tag, double (&v)[6],
+                           int* status) {
+  unsigned need = 0x3fu;
+  const unsigned long long t0 = wall_clock64();
+  unsigned polls = 0;
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+      if ((need & (1u << k)) && try_tagged(rw + ((size_t)t * 6 + k) * 2, tag, v[k]))
+        need &= ~(1u << k);
+    if (!need) return true;
+    if ((++polls & 255u) == 0u) {
+      if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_ABORT)
+        return false;
+      if (wall_clock64() - t0 > POLL_TICKS) {
+        atomicOr(status, ST_ABORT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// One-kernel step, level-1 part.  Every tile publishes its marked count (and,
+// when marked, its F and L rows: dg, up, rh) as tagged words.  Block 0 and
+// every marked block then poll all counts and list the marked tiles in tile
+// order (onepass_counts).  Up to 64 marked tiles, each marked block solves
+// the level-1 system itself (onepass_solve_local: the rows coupled like the
+// packed system, F-L within a tile and L to the next tile's F when the two
+// tiles are neighbours; two rows per lane of one wavefront, one
+// cyclic-reduction level, then wave_pcr), which saves a round of
+// publishing; beyond, block 0 runs a Thomas sweep and publishes the solution
+// (onepass_solve_publish).  Once block 0 has every count, every block has
+// read the speed buffer of the step: block 0 clears it and records the tag.
+
+// the marked tiles in tile order -> tl (LDS); returns their number, or -1
+// when a poll timed out or the step aborted (all threads of the block call)
+__device__ int onepass_counts(const K1D& P, unsigned tag, int* tl) {
+  __shared__ int s_nm;
+  const unsigned long long* cw = P.tw;
+  __syncthreads();  // the block's own tile data in LDS is consumed
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    // all the lane's counts (tiles lane + 64 i) polled in one loop
+    constexpr int NI = ONEPASS_TILES / 64;
+    unsigned cnt[NI];
+    unsigned need = 0;
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+      cnt[i] = 0;
+      if (lane + 64 * i < P.ntiles) need |= 1u << i;
+    }
+    bool ok = true;
+    const unsigned long long c0 = wall_clock64();
+    unsigned polls = 0;
+    while (need) {
+#pragma unroll
+      for (int i = 0; i < NI; i++)
+        if ((need & (1u << i)) && try_tagged(cw + lane + 64 * i, tag, cnt[i])) need &= ~(1u << i);
+      if (!need) break;
+      if ((++polls & 255u) == 0u) {
+        if ((__hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_ABORT) ||
+            wall_clock64() - c0 > POLL_TICKS) {
+          atomicOr(P.status, ST_ABORT);
+          ok = false;
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    int base = 0;
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+      const int t = lane + 64 * i;
+      const bool mt = t < P.ntiles && cnt[i] > 0;
+      const unsigned long long bal = __ballot(mt);
+      if (mt) tl[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+      base += __popcll(bal);
+    }
+    const unsigned long long bad = __ballot(!ok);
+    if (lane == 0) s_nm = bad ? -1 : base;
+  }
+  __syncthreads();
+  return s_nm;
+}
+
+// nm <= 64 marked tiles: the level-1 system solved by wavefront 0 of the
+// calling block; xv = x of this tile's F and L rows, of the previous tile's L
+// row (when nb_l) and of the next tile's F row (when nb_r).  False when a
+// poll failed.  All threads of the block call.
+__device__ bool onepass_solve_local(const K1D& P, unsigned tag, const int* tl, int nm, bool nb_l,
+                                    bool nb_r, double* xv) {
+  __shared__ int s_ok;
+  const unsigned long long* rw = P.tw + P.ntiles;
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // F: dg, up, rh; L: dg, up, rh
+    bool ok = true;
+    const int t = l < nm ? tl[l] : -2;
+    if (l < nm) ok = poll_rows6(rw, t, tag, v, P.status);
+    const double upLprev = __shfl_up(v[4], 1);
+    double a0 = 0.0, b0 = 1.0, c0 = 0.0, d0 = 0.0, a1 = 0.0, b1 = 1.0, c1 = 0.0, d1 = 0.0;
+    if (l < nm) {
+      a0 = (l > 0 && tl[l - 1] == t - 1) ? upLprev : 0.0;
+      b0 = v[0];
+      c0 = v[1];
+      d0 = v[2];
+      a1 = v[1];
+      b1 = v[3];
+      c1 = (l + 1 < nm && tl[l + 1] == t + 1) ? v[4] : 0.0;
+      d1 = v[5];
+    }
+    // rows 2l (F) and 2l + 1 (L): the odd rows eliminated from the even ones
+    const double am = __shfl_up(a1, 1), bm = __shfl_up(b1, 1), cm = __shfl_up(c1, 1),
+                 dm = __shfl_up(d1, 1);  // row 2l - 1
+    double na = 0.0, nb = b0, nd = d0;
+    if (l > 0) {
+      const double k1 = a0 * rcp64(bm);
+      na = -am * k1;
+      nb -= cm * k1;
+      nd -= dm * k1;
+    }
+    const double r1 = rcp64(b1), k2 = c0 * r1;
+    const double nc = -c1 * k2;
+    nb -= a1 * k2;
+    nd -= d1 * k2;
+    const double xe = wave_pcr(na, nb, nc, nd, nm);
+    const double xn = __shfl_down(xe, 1);  // x of row 2l + 2
+    const double xo = (d1 - a1 * xe - (l < 63 ? c1 * xn : 0.0)) * r1;
+    // this tile's compact position r: its neighbours, when marked, are r -+ 1
+    const unsigned long long me = __ballot(l < nm && t == (int)blockIdx.x);
+    const int r = me ? __ffsll((long long)me) - 1 : 0;
+    const double xF = __shfl(xe, r), xL = __shfl(xo, r);
+    const double xP = __shfl(xo, r > 0 ? r - 1 : 0), xN = __shfl(xe, r + 1 < 64 ? r + 1 : r);
+    const unsigned long long bad = __ballot(!ok);
+    if (l == 0) {
+      xv[0] = xF;
+      xv[1] = xL;
+      xv[2] = nb_l ? xP : 0.0;
+      xv[3] = nb_r ? xN : 0.0;
+      s_ok = bad ? 0 : 1;
+    }
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// nm > 64 marked tiles: block 0 solves by a Thomas sweep (one thread) over
+// rows staged in LDS (st: 64 tiles x 6 values), recurrences in P.l1s, and
+// publishes x per marked tile (F, L) as tagged words.  All threads of block 0
+// call; false when a poll failed.
+__device__ bool onepass_solve_publish(const K1D& P, unsigned tag, const int* tl, int nm,
+                                      double (*st)[6]) {
+  __shared__ int s_ok;
+  const unsigned long long* rw = P.tw + P.ntiles;
+  unsigned long long* xw = P.tw + 13 * (size_t)P.ntiles;
+  double* cps = P.l1s;
+  double* dps = P.l1s + 2 * (size_t)P.ntiles;
+  double cp = 0.0, dp = 0.0, upLprev = 0.0;
+  int tprev = -2;
+  if (threadIdx.x == 0) s_ok = 1;
+  for (int r0 = 0; r0 < nm; r0 += 64) {
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int r = r0 + threadIdx.x;
+      bool ok = true;
+      if (r < nm) {
+        double v[6];
+        ok = poll_rows6(rw, tl[r], tag, v, P.status);
+#pragma unroll
+        for (int k = 0; k < 6; k++) st[threadIdx.x][k] = v[k];
+      }
+      const unsigned long long bad = __ballot(!ok);
+      if (threadIdx.x == 0 && bad) s_ok = 0;
+    }
+    __syncthreads();
+    if (!s_ok) return false;
+    if (threadIdx.x == 0) {
+      const int r1 = min(nm, r0 + 64);
+      for (int r = r0; r < r1; r++) {
+        const int t = tl[r];
+        const double* v = st[r - r0];
+        // row F of tile t
+        double a = tprev == t - 1 ? upLprev : 0.0;
+        double den = v[0] - a * cp;
+        cp = v[1] / den;
+        dp = (v[2] - a * dp) / den;
+        cps[2 * r] = cp;
+        dps[2 * r] = dp;
+        // row L
+        a = v[1];
+        den = v[3] - a * cp;
+        const double c = (r + 1 < nm && tl[r + 1] == t + 1) ? v[4] : 0.0;
+        cp = c / den;
+        dp = (v[5] - a * dp) / den;
+        cps[2 * r + 1] = cp;
+        dps[2 * r + 1] = dp;
+        tprev = t;
+        upLprev = v[4];
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    double x = 0.0;
+    for (int j = 2 * nm - 1; j >= 0; j--) {
+      x = dps[j] - cps[j] * x;
+      put_tagged(xw + (size_t)tl[j >> 1] * 4 + 2 * (j & 1), x, tag);
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// block 0, once it has every count: every block has read the speed buffer
+// `par`, which is cleared for the step after next, and the tag is recorded
+__device__ void onepass_block0(const K1D& P, int par, unsigned tag) {
+  if (!P.keep_speed)
+    for (int i = threadIdx.x; i < P.nch * P.nslot; i += blockDim.x)
+      P.smax[((size_t)par * P.nch * P.nslot + i) * SPEED_PAD] = 0ull;
+  if (threadIdx.x == 0) *P.tag1 = tag;
+}
+
 }  // namespace
 
 // Whole step of a tile up to the level-1 rows: dt from the speed of Q^n, both
 // Heun stages (Eqs. 8-9), criterion and enlargement (Secs. 5.1-5.2), the new
 // state's defaults (h = h~, hu = hu~, hw = hw~, p = 0 off the marked area),
 // the speed of the unmarked cells' new state, assembly of the marked rows
-// (Eqs. 10-17) and their reduction to the two level-1 rows.
-template <int T, int NT>
+// (Eqs. 10-17) and their reduction to the two level-1 rows.  ONE: the
+// one-kernel step, which goes on to the level-1 solve (block 0) and the
+// projection of the marked cells (Eqs. 10-11), as the projection kernel does.
+template <int T, int NT, bool ONE>
 __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restrict__ h,
                                                const double* __restrict__ hu,
                                                const double* __restrict__ hw,
@@ -1101,14 +1359,31 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     P.tile_cnt[blockIdx.x] = m;
     if (m) atomicAdd(&P.n_acc[par], m);
   }
+  // one-kernel step: the tag of this step's words; block 0's solver scratch
+  // lives in the LDS union once the block's own tile is done
+  const unsigned tag = ONE ? *P.tag1 + 1u : 0u;
+  int* l1tl = reinterpret_cast<int*>(&S.u);
+  double(*l1st)[6] = reinterpret_cast<double(*)[6]>(reinterpret_cast<char*>(&S.u) +
+                                                     sizeof(int) * ONEPASS_TILES);
   if (m == 0) {
-    if (threadIdx.x == 0) {
-      P.dg1[F] = 1.0;
-      P.up1[F] = 0.0;
-      P.rh1[F] = 0.0;
-      P.dg1[L] = 1.0;
-      P.up1[L] = 0.0;
-      P.rh1[L] = 0.0;
+    if constexpr (ONE) {
+      if (threadIdx.x == 0) put_tagged(P.tw + blockIdx.x, 0u, tag);
+      if (blockIdx.x == 0) {
+        const int nm = onepass_counts(P, tag, l1tl);
+        if (nm >= 0) {
+          onepass_block0(P, par, tag);
+          if (nm > 64) onepass_solve_publish(P, tag, l1tl, nm, l1st);
+        }
+      }
+    } else {
+      if (threadIdx.x == 0) {
+        P.dg1[F] = 1.0;
+        P.up1[F] = 0.0;
+        P.rh1[F] = 0.0;
+        P.dg1[L] = 1.0;
+        P.up1[L] = 0.0;
+        P.rh1[L] = 0.0;
+      }
     }
     return;
   }
@@ -1122,6 +1397,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   const int64_t zs = (int64_t)P.ntiles * T;  // stride of the zw planes
   const int64_t pb = (int64_t)blockIdx.x * T;
   double ra[T / NT], rb[T / NT], rc[T / NT], rd[T / NT];
+  double zr[T / NT][ZW_N];  // ONE: the projection data of the thread's cells, kept in registers
 #pragma unroll
   for (int q = 0; q < T / NT; q++) {
     if (!on[q]) continue;
@@ -1139,20 +1415,36 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     rc[q] = (i + 1 < n && S.mk[k + 1]) ? fr.K * fr.a * fr.b : 0.0;
     rd[q] = f2 + fl.b * fl.qp + fr.a * fr.qp;
     S.cell_of[rank[q]] = (short)(k - 1);
-    double* z = P.zw + pb + (k - 1);  // in cell order: the projection needs no ranks
-    z[ZW_KL * zs] = fl.K;
-    z[ZW_AL * zs] = fl.a;
-    z[ZW_BL * zs] = fl.b;
-    z[ZW_FL * zs] = fl.fd;
-    z[ZW_KR * zs] = fr.K;
-    z[ZW_AR * zs] = fr.a;
-    z[ZW_BR * zs] = fr.b;
-    z[ZW_FR * zs] = fr.fd;
-    z[ZW_D * zs] = c0.D;
-    z[ZW_P * zs] = c0.al * c0.phi / 4.0;
-    z[ZW_HT * zs] = hs;
-    z[ZW_MT * zs] = ms;
-    z[ZW_KT * zs] = ks;
+    if constexpr (ONE) {
+      zr[q][ZW_KL] = fl.K;
+      zr[q][ZW_AL] = fl.a;
+      zr[q][ZW_BL] = fl.b;
+      zr[q][ZW_FL] = fl.fd;
+      zr[q][ZW_KR] = fr.K;
+      zr[q][ZW_AR] = fr.a;
+      zr[q][ZW_BR] = fr.b;
+      zr[q][ZW_FR] = fr.fd;
+      zr[q][ZW_D] = c0.D;
+      zr[q][ZW_P] = c0.al * c0.phi / 4.0;
+      zr[q][ZW_HT] = hs;
+      zr[q][ZW_MT] = ms;
+      zr[q][ZW_KT] = ks;
+    } else {
+      double* z = P.zw + pb + (k - 1);  // in cell order: the projection needs no ranks
+      z[ZW_KL * zs] = fl.K;
+      z[ZW_AL * zs] = fl.a;
+      z[ZW_BL * zs] = fl.b;
+      z[ZW_FL * zs] = fl.fd;
+      z[ZW_KR * zs] = fr.K;
+      z[ZW_AR * zs] = fr.a;
+      z[ZW_BR * zs] = fr.b;
+      z[ZW_FR * zs] = fr.fd;
+      z[ZW_D * zs] = c0.D;
+      z[ZW_P * zs] = c0.al * c0.phi / 4.0;
+      z[ZW_HT * zs] = hs;
+      z[ZW_MT * zs] = ms;
+      z[ZW_KT * zs] = ks;
+    }
   }
   __syncthreads();  // cq, fq dead: the tile system takes their place
   auto& Y = S.u.s[0];
@@ -1173,91 +1465,162 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     Y.d[0][j] = rd[q];
   }
   __syncthreads();
+  double l1v[6];  // thread 0: the tile's level-1 rows (F: dg, up, rh; L: dg, up, rh)
   if (m == 1) {
+    const bool asL = Y.c[0] != 0.0;  // couples to the next tile's first row
     if (threadIdx.x == 0) {
-      const bool asL = Y.c[0] != 0.0;  // couples to the next tile's first row
-      P.dg1[F] = asL ? 1.0 : Y.b[0];
-      P.up1[F] = 0.0;
-      P.rh1[F] = asL ? 0.0 : Y.d[0][0];
-      P.dg1[L] = asL ? Y.b[0] : 1.0;
-      P.up1[L] = asL ? Y.c[0] : 0.0;
-      P.rh1[L] = asL ? Y.d[0][0] : 0.0;
+      l1v[0] = asL ? 1.0 : Y.b[0];
+      l1v[1] = 0.0;
+      l1v[2] = asL ? 0.0 : Y.d[0][0];
+      l1v[3] = asL ? Y.b[0] : 1.0;
+      l1v[4] = asL ? Y.c[0] : 0.0;
+      l1v[5] = asL ? Y.d[0][0] : 0.0;
+    }
+    if constexpr (ONE) {
+#pragma unroll
+      for (int q = 0; q < T / NT; q++) {
+        zr[q][ZW_Z] = 0.0;
+        zr[q][ZW_U] = asL ? 0.0 : 1.0;
+        zr[q][ZW_V] = asL ? 1.0 : 0.0;
+      }
+    } else if (threadIdx.x == 0) {
       const int64_t cz = pb + S.cell_of[0];
       P.zw[cz + ZW_Z * zs] = 0.0;
       P.zw[cz + ZW_U * zs] = asL ? 0.0 : 1.0;
       P.zw[cz + ZW_V * zs] = asL ? 1.0 : 0.0;
     }
-    return;
-  }
-  // keep the end rows, then pin them: x_first and x_last become parameters
-  const double b0 = Y.b[0], c0 = Y.c[0], d0 = Y.d[0][0];
-  const double aL = Y.a[m - 1], bL = Y.b[m - 1], cL = Y.c[m - 1], dL = Y.d[0][m - 1];
-  __syncthreads();
-  for (int j = threadIdx.x; j < RW; j += NT) {
-    const bool first = j == 0, last = j == m - 1;
-    if (first || last) {
-      Y.a[j] = 0.0;
-      Y.c[j] = 0.0;
-      Y.b[j] = 1.0;
-      Y.d[0][j] = 0.0;
+  } else {
+    // keep the end rows, then pin them: x_first and x_last become parameters
+    const double b0 = Y.b[0], c0 = Y.c[0], d0 = Y.d[0][0];
+    const double aL = Y.a[m - 1], bL = Y.b[m - 1], cL = Y.c[m - 1], dL = Y.d[0][m - 1];
+    __syncthreads();
+    for (int j = threadIdx.x; j < RW; j += NT) {
+      const bool first = j == 0, last = j == m - 1;
+      if (first || last) {
+        Y.a[j] = 0.0;
+        Y.c[j] = 0.0;
+        Y.b[j] = 1.0;
+        Y.d[0][j] = 0.0;
+      }
+      Y.d[1][j] = first ? 1.0 : 0.0;
+      Y.d[2][j] = last ? 1.0 : 0.0;
+      Y.r[j] = rcp64(Y.b[j]);
     }
-    Y.d[1][j] = first ? 1.0 : 0.0;
-    Y.d[2][j] = last ? 1.0 : 0.0;
-    Y.r[j] = rcp64(Y.b[j]);
+    __syncthreads();
+    const auto& X = S.u.s[pcr_tile<T, NT>(S, m)];
+    if constexpr (ONE) {
+#pragma unroll
+      for (int q = 0; q < T / NT; q++) {
+        if (!on[q]) continue;
+        const int j = rank[q];
+        const double ib = X.r[j];
+        zr[q][ZW_Z] = X.d[0][j] * ib;
+        zr[q][ZW_U] = X.d[1][j] * ib;
+        zr[q][ZW_V] = X.d[2][j] * ib;
+      }
+    } else {
+      for (int j = threadIdx.x; j < m; j += NT) {
+        const double ib = X.r[j];
+        const int64_t cz = pb + S.cell_of[j];
+        P.zw[cz + ZW_Z * zs] = X.d[0][j] * ib;
+        P.zw[cz + ZW_U * zs] = X.d[1][j] * ib;
+        P.zw[cz + ZW_V * zs] = X.d[2][j] * ib;
+      }
+    }
+    if (threadIdx.x == 0) {
+      const double z1 = X.d[0][1] * X.r[1], u1 = X.d[1][1] * X.r[1], v1 = X.d[2][1] * X.r[1];
+      const double zL = X.d[0][m - 2] * X.r[m - 2], vL = X.d[2][m - 2] * X.r[m - 2];
+      l1v[0] = b0 + c0 * u1;
+      l1v[1] = c0 * v1;
+      l1v[2] = d0 - c0 * z1;
+      l1v[3] = bL + aL * vL;
+      l1v[4] = cL;
+      l1v[5] = dL - aL * zL;
+    }
   }
-  __syncthreads();
-  const auto& X = S.u.s[pcr_tile<T, NT>(S, m)];
-  for (int j = threadIdx.x; j < m; j += NT) {
-    const double ib = X.r[j];
-    const int64_t cz = pb + S.cell_of[j];
-    P.zw[cz + ZW_Z * zs] = X.d[0][j] * ib;
-    P.zw[cz + ZW_U * zs] = X.d[1][j] * ib;
-    P.zw[cz + ZW_V * zs] = X.d[2][j] * ib;
-  }
-  if (threadIdx.x == 0) {
-    const double z1 = X.d[0][1] * X.r[1], u1 = X.d[1][1] * X.r[1], v1 = X.d[2][1] * X.r[1];
-    const double zL = X.d[0][m - 2] * X.r[m - 2], vL = X.d[2][m - 2] * X.r[m - 2];
-    P.dg1[F] = b0 + c0 * u1;
-    P.up1[F] = c0 * v1;
-    P.rh1[F] = d0 - c0 * z1;
-    P.dg1[L] = bL + aL * vL;
-    P.up1[L] = cL;
-    P.rh1[L] = dL - aL * zL;
+  if constexpr (!ONE) {
+    if (threadIdx.x == 0) {
+      P.dg1[F] = l1v[0];
+      P.up1[F] = l1v[1];
+      P.rh1[F] = l1v[2];
+      P.dg1[L] = l1v[3];
+      P.up1[L] = l1v[4];
+      P.rh1[L] = l1v[5];
+    }
+  } else {
+    // ---- one-kernel step: publish the rows and count, block 0 solves the
+    // level-1 system, then the projection of the marked cells ----
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; k++)
+        put_tagged(P.tw + P.ntiles + ((size_t)blockIdx.x * 6 + k) * 2, l1v[k], tag);
+      put_tagged(P.tw + blockIdx.x, (unsigned)m, tag);
+    }
+    const int nm = onepass_counts(P, tag, l1tl);
+    if (nm < 0) return;
+    if (blockIdx.x == 0) onepass_block0(P, par, tag);
+    const bool nb_l = start > 0 && S.mk[0] != 0, nb_r = end < n && S.mk[len + 1] != 0;
+    __shared__ double xv[4];  // x of the tile's F and L rows, of the previous L, of the next F
+    __shared__ int xok;
+    if (nm <= 64) {
+      if (!onepass_solve_local(P, tag, l1tl, nm, nb_l, nb_r, xv)) return;
+    } else {
+      bool ok = true;
+      if (blockIdx.x == 0) ok = onepass_solve_publish(P, tag, l1tl, nm, l1st);
+      if (threadIdx.x < 64) {
+        const unsigned long long* xw = P.tw + 13 * (size_t)P.ntiles;
+        const int j = threadIdx.x;
+        double v = 0.0;
+        bool good = ok;
+        if (j < 4 && ok && (j < 2 || (j == 2 && nb_l) || (j == 3 && nb_r))) {
+          const int64_t tt = j == 2 ? (int64_t)blockIdx.x - 1 : j == 3 ? (int64_t)blockIdx.x + 1
+                                                                        : (int64_t)blockIdx.x;
+          good = poll_tagged(xw + tt * 4 + (j == 1 || j == 2 ? 2 : 0), tag, v, P.status);
+        }
+        if (j < 4) xv[j] = v;
+        const unsigned long long bad = __ballot(!good);
+        if (j == 0) xok = bad ? 0 : 1;
+      }
+      __syncthreads();
+      if (!xok) return;
+    }
+    double* xs = reinterpret_cast<double*>(&S.u);  // p on tile cells 0 .. len + 1
+#pragma unroll
+    for (int q = 0; q < T / NT; q++) {
+      const int k = 1 + threadIdx.x + NT * q;
+      if (k > len) continue;
+      xs[k] = on[q] ? zr[q][ZW_Z] + zr[q][ZW_U] * xv[0] + zr[q][ZW_V] * xv[1] : 0.0;
+    }
+    if (threadIdx.x == 0) {
+      xs[0] = nb_l ? xv[2] : 0.0;
+      xs[len + 1] = nb_r ? xv[3] : 0.0;
+    }
+    __syncthreads();
+    const double rdt4 = P.rho / (4.0 * dt), dtr = dt / P.rho;
+    double sp = 0.0;
+    int fl3 = 0;
+#pragma unroll
+    for (int q = 0; q < T / NT; q++) {
+      if (!on[q]) continue;
+      const int k = 1 + threadIdx.x + NT * q;
+      const int64_t gi = off + start + k - 1;
+      const double* z = zr[q];
+      const double pc = xs[k], pl = xs[k - 1], pr = xs[k + 1];
+      const double dql = z[ZW_FL] - z[ZW_KL] * (z[ZW_AL] * pl + z[ZW_BL] * pc);
+      const double dqr = z[ZW_FR] - z[ZW_KR] * (z[ZW_AR] * pc + z[ZW_BR] * pr);
+      const double dm = 0.5 * (dql + dqr);
+      const double Pb = 1.5 * pc - rdt4 * z[ZW_D] * dm + z[ZW_P];
+      const double mn = z[ZW_MT] + dm, kn = z[ZW_KT] + dtr * Pb;
+      hun[gi] = mn;
+      hwn[gi] = kn;
+      p[gi] = pc;
+      final_state(P.g, z[ZW_HT], mn, kn, sp, fl3);
+    }
+    flush_speed<NT>(P, tl.x, par, sp, fl3);
   }
 }
 
 
-// Tridiagonal solve of n <= 64 rows held one per lane of the calling
-// wavefront (a: sub-, b: main, c: super-diagonal, d: right-hand side; lanes
-// at or beyond n hold identity rows): parallel cyclic reduction with
-// cross-lane shuffles, no block barrier.  Returns x of the lane's row.
-__device__ __forceinline__ double wave_pcr(double a, double b, double c, double d, int n) {
-  const int lane = threadIdx.x & 63;
-  for (int s = 1; s < n; s <<= 1) {
-    const double am = __shfl_up(a, s), bm = __shfl_up(b, s), cm = __shfl_up(c, s),
-                 dm = __shfl_up(d, s);
-    const double ap = __shfl_down(a, s), bp = __shfl_down(b, s), cp = __shfl_down(c, s),
-                 dp = __shfl_down(d, s);
-    double na = 0.0, nb = b, nc = 0.0, nd = d;
-    if (lane >= s) {
-      const double k1 = a * rcp64(bm);
-      na = -am * k1;
-      nb -= cm * k1;
-      nd -= dm * k1;
-    }
-    if (lane + s < 64) {
-      const double k2 = c * rcp64(bp);
-      nc = -cp * k2;
-      nb -= ap * k2;
-      nd -= dp * k2;
-    }
-    a = na;
-    b = nb;
-    c = nc;
-    d = nd;
-  }
-  return d * rcp64(b);
-}
 
 // Projection of the marked cells (a6) from the level-1 solution -- solved
 // here, redundantly by every tile that needs it, when it has at most L1MAX
@@ -1647,8 +2010,29 @@ template <int T, int NT>
 static void launch_step_t(const K1D& P, const double* h, const double* hu, const double* hw,
                           double* hn, double* hun, double* hwn, uint8_t* mask, double* p, int par,
                           hipStream_t s) {
-  hipLaunchKernelGGL((k_step1d<T, NT>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn, hun, hwn,
-                     mask, p, par);
+  if (P.onepass)
+    hipLaunchKernelGGL((k_step1d<T, NT, true>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn,
+                       hun, hwn, mask, p, par);
+  else
+    hipLaunchKernelGGL((k_step1d<T, NT, false>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn,
+                       hun, hwn, mask, p, par);
+}
+// blocks of the one-kernel step kernel that fit on the device at once
+template <int T, int NT>
+static int onepass_resident_t() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step1d<T, NT, true>, NT, 0) !=
+      hipSuccess)
+    return 0;
+  return cus * per_cu;
+}
+int onepass_resident(const K1D& P) {
+  if (P.cap == 128) return onepass_resident_t<128, 128>();
+  if (P.cap == 256) return onepass_resident_t<256, 256>();
+  return onepass_resident_t<512, 256>();
 }
 void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
                    double* hun, double* hwn, uint8_t* mask, double* p, int par, hipStream_t s) {

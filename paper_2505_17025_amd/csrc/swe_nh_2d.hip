@@ -803,40 +803,12 @@ __device__ bool grid_sync(const Bar& B, unsigned k, int G) {
   return ok != 0;
 }
 
-// Tagged words: the pipelined solver publishes each value of a pass with the
-// pass's tag in the upper half of a 64-bit word (agent-scope relaxed atomic
-// stores; an FP64 value takes two words, each with the tag), and a reader
-// polls until every word it needs carries the tag it expects.  The values
-// validate themselves, so a pass needs neither the arrival counter nor the
-// cache write-back and invalidation of the barrier's fences.  Tags grow over
-// the context's life (never reused while a word could still hold them).
-__device__ __forceinline__ void put_tagged(unsigned long long* w, float v, unsigned tag) {
-  __hip_atomic_store(w, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void put_tagged(unsigned long long* w, double v, unsigned tag) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  __hip_atomic_store(w, ((unsigned long long)tag << 32) | (b & 0xffffffffull), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(w + 1, ((unsigned long long)tag << 32) | (b >> 32), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long load_word(const unsigned long long* w) {
-  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// one poll: true (and the value) when the words carry the tag
-__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, float& v) {
-  const unsigned long long a = load_word(w);
-  if ((unsigned)(a >> 32) != tag) return false;
-  v = __uint_as_float((unsigned)a);
-  return true;
-}
-__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, double& v) {
-  const unsigned long long a = load_word(w), b = load_word(w + 1);
-  if ((unsigned)(a >> 32) != tag || (unsigned)(b >> 32) != tag) return false;
-  v = __longlong_as_double((long long)((b << 32) | (a & 0xffffffffull)));
-  return true;
-}
+// The pipelined solver publishes each value of a pass with the pass's tag
+// (tagged words, put_tagged / try_tagged): a reader polls until every word
+// it needs carries the tag it expects.  The values validate themselves, so a
+// pass needs neither the arrival counter nor the cache write-back and
+// invalidation of the barrier's fences.  Tags grow over the context's life
+// (never reused while a word could still hold them).
 template <typename R>
 constexpr int tag_words() {
   return sizeof(R) / 4;  // 64-bit words per tagged value

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -251,6 +252,10 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
       P.up1 = x->T1.up[0];
       P.rh1 = x->T1.rh[0];
       P.x1 = x->T1.x[0];
+      // tagged words of the one-kernel step: counts, rows, solution
+      P.tw = cv.take<unsigned long long>(17 * (size_t)ntiles);
+      P.tag1 = cv.take<unsigned>(1);
+      P.l1s = cv.take<double>(4 * (size_t)ntiles);
     }
     x->nparts = resid_blocks(N);
     x->part = cv.take<double>(x->nparts);
@@ -312,6 +317,7 @@ void enqueue_fused1d(swe_nh_ctx* c, hipStream_t s, const double* h, const double
   K1D& P = c->k1;
   uint8_t* M = mask ? mask : c->mask_ws;
   launch_step1d(P, h, hu, hw, hn, hun, hwn, M, p, par, s);
+  if (P.onepass) return;  // the step kernel also solved and projected
   if (!level1_local(P)) launch_tri_solve(c->T1, c->n1, nullptr, s);
   launch_apply1d(P, M, hun, hwn, p, par, s);
 }
@@ -459,6 +465,8 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.nch = c->nch;
   P.nslot = speed_slots(cfg);
   P.fused = fused_step(cfg) ? 1 : 0;
+  P.onepass = 0;
+  P.keep_speed = 0;
   const int n1 = 2 * P.ntiles;
   std::vector<double> zeros(c->nch, 0.0);
   std::vector<unsigned long long> zu(speed_at(2 * c->nch, 0, P.nslot), 0ull);
@@ -481,6 +489,19 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   if (P.fused) {
     INIT_COPY(c->n1, &n1, sizeof(int));
     INIT_COPY(c->T1.n, zi, sizeof(int) * TRI_MAX_LEVELS);
+    // tag 0 is never used: the words start invalid
+    if (rc == SWE_NH_OK && hipMemset(P.tw, 0, 17 * sizeof(unsigned long long) * P.ntiles) != hipSuccess)
+      rc = SWE_NH_EHIP;
+    INIT_COPY(P.tag1, zi, sizeof(unsigned));
+    // the one-kernel step when its blocks all fit on the device at once (block
+    // 0 waits for every tile's count; the marked tiles wait for block 0)
+    const char* env = std::getenv("SWE_NH_ONEPASS");
+    const bool allow = !(env && env[0] == '0');
+    P.onepass = 0;
+    if (rc == SWE_NH_OK && allow && P.ntiles <= ONEPASS_TILES) {
+      const int fit = onepass_resident(P);
+      P.onepass = (fit >= P.ntiles) ? 1 : 0;
+    }
   }
   INIT_COPY(c->status, zi, sizeof(int));
   INIT_COPY(c->step, zi, 2 * sizeof(int));
@@ -797,6 +818,10 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
   if (!c || !h || !hu || !hw || !p || !avg_us_host || nreps < 1 || stage < 0 || stage > 3)
     return fail(c, SWE_NH_EINVAL, "bad arguments");
   if ((c->cfg.dim == 1) != (hv == nullptr)) return fail(c, SWE_NH_EINVAL, "hv must be NULL iff dim == 1");
+  if (c->cfg.dim == 1 && c->k1.fused && c->k1.onepass && (stage == 1 || stage == 2)) {
+    *avg_us_host = 0.0;  // the one-kernel step has no separate level-1 solve or projection
+    return SWE_NH_OK;
+  }
   // one launch of the stage, enqueued on s
   auto one = [&](hipStream_t s) {
     if (c->cfg.dim == 2) {
@@ -811,8 +836,10 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
       // (level-0 arrays of the packed solver, unused by this path), never
       // the caller's state; nothing advances.
       double *s0 = c->T64.dg[0], *s1 = c->T64.up[0], *s2 = c->T64.rh[0], *s3 = c->T64.x[0];
+      K1D Pt = P;
+      Pt.keep_speed = 1;  // replays of the step kernel must all read the same dt
       switch (stage) {
-        case 0: launch_step1d(P, h, hu, hw, s0, s1, s2, M, s3, 0, s); break;
+        case 0: launch_step1d(Pt, h, hu, hw, s0, s1, s2, M, s3, 0, s); break;
         case 1: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
         case 2: launch_apply1d(P, M, s1, s2, s3, 0, s); break;
         default: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s);

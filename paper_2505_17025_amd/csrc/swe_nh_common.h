@@ -184,4 +184,68 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
+// Tagged words: a value published with a tag in the upper half of a 64-bit
+// word (agent-scope relaxed atomic stores; an FP64 value takes two words,
+// each with the tag).  A reader polls with agent-scope relaxed atomic loads
+// until each word carries the tag it expects: single-copy atomicity makes a
+// word's value and tag consistent, so no ordering between words (no fence)
+// is needed.
+__device__ __forceinline__ void put_tagged(unsigned long long* w, float v, unsigned tag) {
+  __hip_atomic_store(w, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put_tagged(unsigned long long* w, unsigned v, unsigned tag) {
+  __hip_atomic_store(w, ((unsigned long long)tag << 32) | v, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put_tagged(unsigned long long* w, double v, unsigned tag) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  __hip_atomic_store(w, ((unsigned long long)tag << 32) | (b & 0xffffffffull), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 1, ((unsigned long long)tag << 32) | (b >> 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long load_word(const unsigned long long* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// one poll: true (and the value) when the words carry the tag
+__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, float& v) {
+  const unsigned long long a = load_word(w);
+  if ((unsigned)(a >> 32) != tag) return false;
+  v = __uint_as_float((unsigned)a);
+  return true;
+}
+__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, unsigned& v) {
+  const unsigned long long a = load_word(w);
+  if ((unsigned)(a >> 32) != tag) return false;
+  v = (unsigned)a;
+  return true;
+}
+__device__ __forceinline__ bool try_tagged(const unsigned long long* w, unsigned tag, double& v) {
+  const unsigned long long a = load_word(w), b = load_word(w + 1);
+  if ((unsigned)(a >> 32) != tag || (unsigned)(b >> 32) != tag) return false;
+  v = __longlong_as_double((long long)((b << 32) | (a & 0xffffffffull)));
+  return true;
+}
+// bounded polls: a wait longer than POLL_TICKS (wall_clock64 ticks at 100 MHz)
+// or another wait's abort (ST_ABORT in *status) ends it with false
+constexpr unsigned long long POLL_TICKS = 50000000ull;
+template <typename V>
+__device__ bool poll_tagged(const unsigned long long* w, unsigned tag, V& v, int* status) {
+  const unsigned long long t0 = wall_clock64();
+  unsigned polls = 0;
+  while (!try_tagged(w, tag, v)) {
+    if ((++polls & 255u) == 0u) {
+      if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_ABORT)
+        return false;
+      if (wall_clock64() - t0 > POLL_TICKS) {
+        atomicOr(status, ST_ABORT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
 }  // namespace swenh

@@ -10,6 +10,7 @@
 namespace swenh {
 
 constexpr int TILE_MAX = 512;   // largest 1D tile (cells per block of the stencil kernels)
+constexpr int ONEPASS_TILES = 512;  // most tiles of the one-kernel fused step
 constexpr int TRI_ROWS = 1024;  // rows per block in the tridiagonal solver
 constexpr int TRI_MAX_LEVELS = 6;
 // The maximum wave speed of a channel is gathered in nslot partial maxima
@@ -52,6 +53,17 @@ struct K1D {
   double* zw;              // [ZW_N][ntiles * cap] per marked row, tile-padded
   double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
   const double* x1;        // level-1 solution
+  // one-kernel step (onepass, at most ONEPASS_TILES tiles): the tiles publish
+  // their marked counts and level-1 rows as tagged words, block 0 solves the
+  // level-1 system and publishes its solution, and the marked tiles project
+  // in the same kernel.  tw: [ntiles] counts, [ntiles][12] rows (F and L:
+  // dg, up, rh), [ntiles][4] solution (F, L); tag1: tag of the last step;
+  // l1s: [2][2 ntiles] scratch of block 0's sequential solve
+  int onepass;
+  int keep_speed;  // stage timing: block 0 leaves the speed buffer the step read in place
+  unsigned long long* tw;
+  unsigned* tag1;
+  double* l1s;
 };
 
 // per marked row of the tile-fused step: solution basis of the tile's
@@ -94,6 +106,7 @@ void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn,
                     int par, hipStream_t s);
 void launch_run_end(const K1D& P, int last_par, hipStream_t s);
 bool level1_local(const K1D& P);  // the projection kernel solves the level-1 system itself
+int onepass_resident(const K1D& P);  // blocks of the one-kernel step that fit at once (0: error)
 int fused_max_enlarge();
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
                            hipStream_t s);

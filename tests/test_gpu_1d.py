@@ -209,7 +209,7 @@ def test_solitary_wave_full_run_parity(B):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_slide_full_size_steps(B, precision):
+def test_slide_full_size_steps(B, precision, step_mode):
     """moving-bottom slide at its full size (N = 32768), adaptive |eta/d|, in the
     launch configuration the benchmark times"""
     case = S.slide_case(n=32768, dx=0.005)
@@ -225,6 +225,11 @@ def test_slide_full_size_steps(B, precision):
     d_end, *_ = O.forcing_1d(case.ds, case.dx, case.body, ref.time)
     for g, r in ((h - dt(d_end), ref.h - d_end), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
         assert rel(g, r) <= tol
+    if precision == 0:
+        # the benchmark's form: one kernel per step at this size (no separate
+        # level-1 solve to time), unless forced to two kernels
+        us = ctx.time_stage(1, 3, h, hu, None, hw, p)
+        assert (us == 0.0) == (step_mode == "one-kernel")
 
 
 @pytest.mark.parametrize("tile", [0, 114, 242])
@@ -329,7 +334,7 @@ def test_batched_ensemble_parity(B):
     assert st["n_active"] == total
 
 
-def test_deterministic_and_graph_replay(B):
+def test_deterministic_and_graph_replay(B, step_mode):
     case = S.random_case_1d(5000, seed=2)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, cfl=0.4)
     a = run_gpu(B, case, 30, **kw)
@@ -348,7 +353,7 @@ def test_deterministic_and_graph_replay(B):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_stage_timing_leaves_the_run_unchanged(B, precision):
+def test_stage_timing_leaves_the_run_unchanged(B, precision, step_mode):
     """swe_nh_time_stage replays each stage from a graph (nreps 3 and 70,
     the latter rounded up to two graphs of 50).  On the fused path the
     stages write only workspace scratch, so the state and a continued run
@@ -368,7 +373,8 @@ def test_stage_timing_leaves_the_run_unchanged(B, precision):
     for stage in range(4):
         for nreps in (3, 70):
             us = ctx.time_stage(stage, nreps, h, hu, None, hw, p)
-            assert 0.0 < us < 1e5
+            # the one-kernel step has no separate level-1 solve or projection (0)
+            assert (0.0 <= us if stage in (1, 2) else 0.0 < us) and us < 1e5
     if precision:
         return
     for x, y in zip((h, hu, hw, p), snap):
@@ -406,9 +412,22 @@ def test_refinement_reports_noconvergence(B):
 
 # ------------------------------------------------- fused FP64 step paths ----
 
+@pytest.fixture(params=["one-kernel", "two-kernel"])
+def step_mode(request, monkeypatch):
+    """the fused step's two forms: one kernel (block 0 solves the level-1
+    system, the marked tiles project in the same launch) where every tile
+    fits on the device, and the step kernel + projection kernel otherwise
+    (forced with SWE_NH_ONEPASS=0, read when a context is created)"""
+    if request.param == "two-kernel":
+        monkeypatch.setenv("SWE_NH_ONEPASS", "0")
+    else:
+        monkeypatch.delenv("SWE_NH_ONEPASS", raising=False)
+    return request.param
+
+
 @pytest.mark.parametrize("tile", [128, 256, 512, 114, 242, 498, 200, 37])
 @pytest.mark.parametrize("nsteps", [15, 16])
-def test_fused_step_tiles(B, tile, nsteps):
+def test_fused_step_tiles(B, tile, nsteps, step_mode):
     """tile lengths of the fused step at and below each window capacity on
     ragged channels (channel ends inside and at tile ends, 4-cell channels);
     odd step counts end in the workspace copy of the state"""
@@ -431,11 +450,12 @@ def test_fused_step_tiles(B, tile, nsteps):
 
 
 @pytest.mark.parametrize("ntiles", [20, 32, 33, 50, 64, 65, 100])
-def test_level1_solve_regimes(B, ntiles):
+def test_level1_solve_regimes(B, ntiles, step_mode):
     """every tile marked (global mode), tiles of 114 cells, the last one
-    ragged: the projection kernel's level-1 system has 2 rows per tile and is
-    solved by one wavefront up to 64 rows, with two rows per lane up to 128,
-    and by block PCR beyond"""
+    ragged: the level-1 system has 2 rows per tile.  Two-kernel form: solved
+    by one wavefront up to 64 rows, with two rows per lane up to 128, by
+    block PCR beyond.  One-kernel form: two rows per lane up to 64 marked
+    tiles, a Thomas sweep beyond"""
     case = S.random_case_1d(114 * ntiles - 5, seed=40 + ntiles, dx=0.05)
     kw = dict(crit=S.CRIT_GLOBAL, cfl=0.45, tile1d=114)
     ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 6, **kw)
@@ -445,7 +465,7 @@ def test_level1_solve_regimes(B, ntiles):
         assert rel(g, r) <= 1e-10
 
 
-def test_level1_two_rows_per_lane_across_channels(B):
+def test_level1_two_rows_per_lane_across_channels(B, step_mode):
     """the two-rows-per-lane level-1 solve (100 rows) on three channels in
     global mode: no coupling between one channel's last tile and the next
     channel's first"""
