@@ -1107,17 +1107,17 @@ __device__ bool onepass_solve_publish(const K1D& P, unsigned tag, const int* tl,
         const double* v = st[r - r0];
         // row F of tile t
         double a = tprev == t - 1 ? upLprev : 0.0;
-        double den = v[0] - a * cp;
-        cp = v[1] / den;
-        dp = (v[2] - a * dp) / den;
+        double rd = rcp64(v[0] - a * cp);
+        cp = v[1] * rd;
+        dp = (v[2] - a * dp) * rd;
         cps[2 * r] = cp;
         dps[2 * r] = dp;
         // row L
         a = v[1];
-        den = v[3] - a * cp;
+        rd = rcp64(v[3] - a * cp);
         const double c = (r + 1 < nm && tl[r + 1] == t + 1) ? v[4] : 0.0;
-        cp = c / den;
-        dp = (v[5] - a * dp) / den;
+        cp = c * rd;
+        dp = (v[5] - a * dp) * rd;
         cps[2 * r + 1] = cp;
         dps[2 * r + 1] = dp;
         tprev = t;

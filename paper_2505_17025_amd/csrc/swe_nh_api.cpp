@@ -498,7 +498,10 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
     const char* env = std::getenv("SWE_NH_ONEPASS");
     const bool allow = !(env && env[0] == '0');
     P.onepass = 0;
-    if (rc == SWE_NH_OK && allow && P.ntiles <= ONEPASS_TILES) {
+    // (the global extension marks every tile: beyond 64 tiles its level-1
+    // system would take the one-kernel form's slow path every step)
+    const bool global_many = cfg->crit == SWE_NH_CRIT_GLOBAL && P.ntiles > 64;
+    if (rc == SWE_NH_OK && allow && !global_many && P.ntiles <= ONEPASS_TILES) {
       const int fit = onepass_resident(P);
       P.onepass = (fit >= P.ntiles) ? 1 : 0;
     }

@@ -465,6 +465,22 @@ def test_level1_solve_regimes(B, ntiles, step_mode):
         assert rel(g, r) <= 1e-10
 
 
+@pytest.mark.parametrize("ntiles", [70, 300])
+def test_many_marked_tiles(B, ntiles, step_mode):
+    """more than 64 marked tiles under an adaptive criterion (tiles of 37
+    cells, a low threshold marks nearly every tile): the one-kernel form's
+    Thomas sweep in block 0"""
+    case = S.random_case_1d(37 * ntiles - 11, seed=90 + ntiles, dx=0.05)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-4, enlarge=1, cfl=0.45, tile1d=37)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 6, **kw)
+    assert st["status"] == 0
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(6)
+    assert st["n_active"] == ref.last_active > 64 * 37
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+
+
 def test_level1_two_rows_per_lane_across_channels(B, step_mode):
     """the two-rows-per-lane level-1 solve (100 rows) on three channels in
     global mode: no coupling between one channel's last tile and the next
