@@ -208,6 +208,23 @@ def time_run_oracle(O, case, ph, dt_fixed, nsteps, reps=3):
     return best, sim
 
 
+def cpu_baseline_ensemble(ens, kw, nch=8, nsteps=100):
+    """the oracle on the first nch channels of the ensemble, channel after
+    channel (FP64 direct solve: the oracle has no FP32 mode)"""
+    import oracle as O
+    ph = O.phys_struct(crit=kw["crit"], k_nh=kw["k_nh"], enlarge=kw["enlarge"])
+    cells, el = 0, 0.0
+    for c in ens.channels[:nch]:
+        sim = O.Sim1D(c, ph, cfl=kw["cfl"])
+        t0 = time.perf_counter()
+        sim.step(nsteps)
+        el += time.perf_counter() - t0
+        cells += c.n
+    return {"value": cells * nsteps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nsteps} steps of the first {nch} channels ({cells} cells), "
+                      f"single-threaded plain-C FP64 oracle, {el:.1f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -394,7 +411,7 @@ def main():
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                              "traffic": None, "avg_launch_us": pred_us,
                              "bytes_per_launch": ncell * 56.0, "stage_us": res["stage_us"]},
-                "cpu_baseline": None,
+                "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_ensemble(ens, kw),
                 "extra": {"fp64_cell_steps_per_s": r64["cell_steps_per_s"],
                           "fp64_roofline": step_roofline(ncell, r64s,
                                                          f"step1d_ensemble512_tile{tile}_pmc.txt",
