@@ -1362,12 +1362,14 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   // one-kernel step: the tag of this step's words; block 0's solver scratch
   // lives in the LDS union once the block's own tile is done
   const unsigned tag = ONE ? *P.tag1 + 1u : 0u;
+  // the count goes out as soon as it is known, so that it is visible long
+  // before the marked tiles finish their elliptic rows and poll the counts
+  if (ONE && threadIdx.x == 0) put_tagged(P.tw + blockIdx.x, (unsigned)m, tag);
   int* l1tl = reinterpret_cast<int*>(&S.u);
   double(*l1st)[6] = reinterpret_cast<double(*)[6]>(reinterpret_cast<char*>(&S.u) +
                                                      sizeof(int) * ONEPASS_TILES);
   if (m == 0) {
     if constexpr (ONE) {
-      if (threadIdx.x == 0) put_tagged(P.tw + blockIdx.x, 0u, tag);
       if (blockIdx.x == 0) {
         const int nm = onepass_counts(P, tag, l1tl);
         if (nm >= 0) {
@@ -1554,7 +1556,6 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
 #pragma unroll
       for (int k = 0; k < 6; k++)
         put_tagged(P.tw + P.ntiles + ((size_t)blockIdx.x * 6 + k) * 2, l1v[k], tag);
-      put_tagged(P.tw + blockIdx.x, (unsigned)m, tag);
     }
     const int nm = onepass_counts(P, tag, l1tl);
     if (nm < 0) return;
