@@ -958,22 +958,39 @@ __device__ bool poll_rows6(const unsigned long long* rw, int t, unsigned tag, do
 // (onepass_solve_publish).  Once block 0 has every count, every block has
 // read the speed buffer of the step: block 0 clears it and records the tag.
 
+constexpr int ONEPASS_NI = ONEPASS_TILES / 64;  // count words per lane of wavefront 0
+
+// loads of the count words, issued early (wavefront 0, lane l: tiles l + 64 i)
+// and checked only in onepass_counts: the round trip overlaps the caller's
+// own work in between
+__device__ __forceinline__ void onepass_prefetch(const K1D& P,
+                                                 unsigned long long (&pre)[ONEPASS_NI]) {
+#pragma unroll
+  for (int i = 0; i < ONEPASS_NI; i++) {
+    const int t = (int)threadIdx.x + 64 * i;
+    pre[i] = (threadIdx.x < 64 && t < P.ntiles) ? load_word(P.tw + t) : 0ull;
+  }
+}
+
 // the marked tiles in tile order -> tl (LDS); returns their number, or -1
-// when a poll timed out or the step aborted (all threads of the block call)
-__device__ int onepass_counts(const K1D& P, unsigned tag, int* tl) {
+// when a poll timed out or the step aborted (all threads of the block call;
+// pre: the words of onepass_prefetch, or 0 to poll them all)
+__device__ int onepass_counts(const K1D& P, unsigned tag, int* tl,
+                              const unsigned long long (&pre)[ONEPASS_NI]) {
   __shared__ int s_nm;
   const unsigned long long* cw = P.tw;
   __syncthreads();  // the block's own tile data in LDS is consumed
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    // all the lane's counts (tiles lane + 64 i) polled in one loop
-    constexpr int NI = ONEPASS_TILES / 64;
+    // all the lane's counts (tiles lane + 64 i): those already in the
+    // prefetched words, the rest polled in one loop
+    constexpr int NI = ONEPASS_NI;
     unsigned cnt[NI];
     unsigned need = 0;
 #pragma unroll
     for (int i = 0; i < NI; i++) {
-      cnt[i] = 0;
-      if (lane + 64 * i < P.ntiles) need |= 1u << i;
+      cnt[i] = (unsigned)pre[i];
+      if (lane + 64 * i < P.ntiles && (unsigned)(pre[i] >> 32) != tag) need |= 1u << i;
     }
     bool ok = true;
     const unsigned long long c0 = wall_clock64();
@@ -1365,13 +1382,17 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   // the count goes out as soon as it is known, so that it is visible long
   // before the marked tiles finish their elliptic rows and poll the counts
   if (ONE && threadIdx.x == 0) put_tagged(P.tw + blockIdx.x, (unsigned)m, tag);
+  unsigned long long pre[ONEPASS_NI];  // ONE: the count words, loaded before the tile reduction
   int* l1tl = reinterpret_cast<int*>(&S.u);
   double(*l1st)[6] = reinterpret_cast<double(*)[6]>(reinterpret_cast<char*>(&S.u) +
                                                      sizeof(int) * ONEPASS_TILES);
   if (m == 0) {
     if constexpr (ONE) {
       if (blockIdx.x == 0) {
-        const int nm = onepass_counts(P, tag, l1tl);
+        unsigned long long pre[ONEPASS_NI];
+#pragma unroll
+        for (int i = 0; i < ONEPASS_NI; i++) pre[i] = 0ull;
+        const int nm = onepass_counts(P, tag, l1tl, pre);
         if (nm >= 0) {
           onepass_block0(P, par, tag);
           if (nm > 64) onepass_solve_publish(P, tag, l1tl, nm, l1st);
@@ -1448,6 +1469,10 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       z[ZW_KT * zs] = ks;
     }
   }
+  // a marked tile needs every count once its rows are out: load them now,
+  // when the other tiles have long published theirs; the loads return during
+  // the tile reduction
+  if constexpr (ONE) onepass_prefetch(P, pre);
   __syncthreads();  // cq, fq dead: the tile system takes their place
   auto& Y = S.u.s[0];
   for (int j = threadIdx.x; j < RW; j += NT) {
@@ -1557,7 +1582,7 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       for (int k = 0; k < 6; k++)
         put_tagged(P.tw + P.ntiles + ((size_t)blockIdx.x * 6 + k) * 2, l1v[k], tag);
     }
-    const int nm = onepass_counts(P, tag, l1tl);
+    const int nm = onepass_counts(P, tag, l1tl, pre);
     if (nm < 0) return;
     if (blockIdx.x == 0) onepass_block0(P, par, tag);
     const bool nb_l = start > 0 && S.mk[0] != 0, nb_r = end < n && S.mk[len + 1] != 0;
