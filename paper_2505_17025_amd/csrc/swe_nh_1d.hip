@@ -1367,10 +1367,12 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       final_state(P.g, hh, mm, kk, smax, fl2);
     }
   }
-  flush_speed<NT>(P, tl.x, par, smax, fl2);
   int rank[T / NT];
   bool on[T / NT];
   const int m = tile_ranks<T, NT>([&](int k) { return k <= len && S.mk[k] != 0; }, rank, on);
+  // the one-kernel step's marked tiles fold these speeds into their
+  // projection's flush (one flush, after the critical path's polls)
+  if (!ONE || m == 0) flush_speed<NT>(P, tl.x, par, smax, fl2);
   const int F = 2 * blockIdx.x, L = F + 1;
   if (threadIdx.x == 0) {
     P.tile_cnt[blockIdx.x] = m;
@@ -1623,8 +1625,8 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     }
     __syncthreads();
     const double rdt4 = P.rho / (4.0 * dt), dtr = dt / P.rho;
-    double sp = 0.0;
-    int fl3 = 0;
+    double sp = smax;  // the unmarked cells' speed and flags from above
+    int fl3 = fl2;
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
       if (!on[q]) continue;
