@@ -135,7 +135,15 @@ size_t swe_nh_workspace_bytes(const swe_nh_config* cfg);
 /* Validate cfg, carve the caller's device workspace (>= workspace_bytes,
  * 256-byte aligned), upload channel tables and set t = 0.  stream is a
  * hipStream_t (NULL = the default stream).  The workspace must outlive the
- * context.  Returns SWE_NH_EINVAL / SWE_NH_ENOMEM / SWE_NH_EHIP on failure. */
+ * context.  Returns SWE_NH_EINVAL / SWE_NH_ENOMEM / SWE_NH_EHIP on failure.
+ *
+ * The 1D FP64 fused step of a grid of at most 512 tiles whose blocks all fit
+ * on the device at once runs as one kernel whose blocks exchange tagged
+ * words (the 2D solver's iterations do the same); such kernels assume that
+ * no other long-running kernel holds the device's compute units while they
+ * run.  Every wait is bounded: a step that cannot complete ends with
+ * SWE_NH_EHIP after about 0.5 s.  With SWE_NH_ONEPASS=0 in the environment
+ * when a context is created, the 1D step uses its two-kernel form. */
 int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t workspace_bytes, void* stream,
                 swe_nh_ctx** out);
 
