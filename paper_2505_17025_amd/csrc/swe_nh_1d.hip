@@ -1169,7 +1169,7 @@ __device__ void onepass_block0(const K1D& P, int par, unsigned tag) {
 // state's defaults (h = h~, hu = hu~, hw = hw~, p = 0 off the marked area),
 // the speed of the unmarked cells' new state, assembly of the marked rows
 // (Eqs. 10-17) and their reduction to the two level-1 rows.  ONE: the
-// one-kernel step, which goes on to the level-1 solve (block 0) and the
+// one-kernel step, which goes on to the level-1 solve and the
 // projection of the marked cells (Eqs. 10-11), as the projection kernel does.
 template <int T, int NT, bool ONE>
 __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restrict__ h,
@@ -1378,8 +1378,9 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
     P.tile_cnt[blockIdx.x] = m;
     if (m) atomicAdd(&P.n_acc[par], m);
   }
-  // one-kernel step: the tag of this step's words; block 0's solver scratch
-  // lives in the LDS union once the block's own tile is done
+  // one-kernel step: the tag of this step's words; the level-1 scratch (the
+  // marked tiles' list, staged rows) lives in the LDS union once the block's
+  // own tile is done
   const unsigned tag = ONE ? *P.tag1 + 1u : 0u;
   // the count goes out as soon as it is known, so that it is visible long
   // before the marked tiles finish their elliptic rows and poll the counts
@@ -1577,8 +1578,9 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       P.rh1[L] = l1v[5];
     }
   } else {
-    // ---- one-kernel step: publish the rows and count, block 0 solves the
-    // level-1 system, then the projection of the marked cells ----
+    // ---- one-kernel step: publish the rows, gather every marked tile's
+    // rows and solve the level-1 system here (up to 64 marked tiles; beyond,
+    // block 0 solves and publishes), then project the marked cells ----
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int k = 0; k < 6; k++)

@@ -54,9 +54,10 @@ struct K1D {
   double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
   const double* x1;        // level-1 solution
   // one-kernel step (onepass, at most ONEPASS_TILES tiles): the tiles publish
-  // their marked counts and level-1 rows as tagged words, block 0 solves the
-  // level-1 system and publishes its solution, and the marked tiles project
-  // in the same kernel.  tw: [ntiles] counts, [ntiles][12] rows (F and L:
+  // their marked counts and level-1 rows as tagged words, each marked tile
+  // solves the level-1 system itself (beyond 64 marked tiles block 0 solves
+  // it and publishes the solution), and the marked tiles project in the same
+  // kernel.  tw: [ntiles] counts, [ntiles][12] rows (F and L:
   // dg, up, rh), [ntiles][4] solution (F, L); tag1: tag of the last step;
   // l1s: [2][2 ntiles] scratch of block 0's sequential solve
   int onepass;
