@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(256) k_speed1d(K1D P, const double* __restrict
     } else if (!(hh > 0.0)) {
       flags |= ST_DRY;
     } else {
-      s = fmax(s, fabs(mm / hh) + sqrt(P.g * hh));
+      s = fmax(s, fabs(mm / hh) + sqrt64(P.g * hh));
     }
   }
   s = wave_max(s);
@@ -87,7 +87,7 @@ __device__ __forceinline__ Flux rusanov1d(double g, double eL, double mL, double
   const double wL = kL * rL, wR = kR * rR;
   const double db = fmin(dL, dR);
   const double sL = fmax(0.0, eL + db), sR = fmax(0.0, eR + db);
-  const double lam = fmax(fabs(uL) + sqrt(g * sL), fabs(uR) + sqrt(g * sR));
+  const double lam = fmax(fabs(uL) + sqrt64(g * sL), fabs(uR) + sqrt64(g * sR));
   const double qL = sL * uL, qR = sR * uR;
   const double pL = 0.5 * g * sL * sL, pR = 0.5 * g * sR * sR;
   f.Fh = 0.5 * (qL + qR) - 0.5 * lam * (sR - sL);
@@ -639,7 +639,7 @@ __device__ __forceinline__ void final_state(double g, double hh, double mm, doub
   } else if (!(hh > 0.0)) {
     flags |= ST_DRY;
   } else {
-    s = fmax(s, fabs(mm * rcp64(hh)) + sqrt(g * hh));
+    s = fmax(s, fabs(mm * rcp64(hh)) + sqrt64(g * hh));
   }
 }
 

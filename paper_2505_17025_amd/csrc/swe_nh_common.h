@@ -155,6 +155,23 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// sqrt(x) for x = 0 or x >= 2^-960 (a wave speed squared, g times a depth):
+// the hardware estimate y of 1/sqrt(x), one coupled Newton step on s = x y
+// ~ sqrt(x) and t = y / 2 ~ 1 / (2 sqrt(x)) (with e = 1/2 - s t both become
+// s (1 + e) and t (1 + e), squaring the relative error), then one correction
+// s + t (x - s^2).  No scaling of tiny or huge arguments and no special cases
+// beyond 0, which is what the library square root spends most of its
+// instructions on; within an ulp of the correctly rounded root.
+__device__ __forceinline__ double sqrt64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, t = 0.5 * y;
+  const double e = fma(-s, t, 0.5);
+  s = fma(s, e, s);
+  t = fma(t, e, t);
+  s = fma(fma(-s, s, x), t, s);
+  return x > 0.0 ? s : 0.0;
+}
+
 __device__ __forceinline__ double minmod(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   return fabs(a) < fabs(b) ? a : b;
