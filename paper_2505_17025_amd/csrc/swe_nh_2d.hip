@@ -98,7 +98,7 @@ __device__ __forceinline__ void cell_speed2d(const G2& G, double idx, double idy
   } else if (!(hh > 0.0)) {
     flags |= ST_DRY;
   } else {
-    const double a = sqrt(G.g * hh), r = rcp64(hh);
+    const double a = sqrt64(G.g * hh), r = rcp64(hh);
     s = fmax(s, (fabs(m * r) + a) * idx + (fabs(n * r) + a) * idy);
   }
 }
@@ -181,7 +181,7 @@ __device__ __forceinline__ Flux2 rusanov2d(double g, double eL, double mL, doubl
   const double wL = bL * rL, wR = bR * rR;
   const double db = fmin(dL, dR);
   const double sL = fmax(0.0, eL + db), sR = fmax(0.0, eR + db);
-  const double lam = fmax(fabs(uL) + sqrt(g * sL), fabs(uR) + sqrt(g * sR));
+  const double lam = fmax(fabs(uL) + sqrt64(g * sL), fabs(uR) + sqrt64(g * sR));
   const double qL = sL * uL, qR = sR * uR;
   f.Fh = 0.5 * (qL + qR) - 0.5 * lam * (sR - sL);
   const double Fm = 0.5 * (qL * uL + 0.5 * g * sL * sL + qR * uR + 0.5 * g * sR * sR) -
