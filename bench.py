@@ -228,8 +228,8 @@ def cpu_baseline_ensemble(ens, kw, nch=8, nsteps=100):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2505_17025_amd import binding
