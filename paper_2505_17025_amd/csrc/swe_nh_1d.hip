@@ -1472,9 +1472,9 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       z[ZW_KT * zs] = ks;
     }
   }
-  // a marked tile needs every count once its rows are out: load them now,
-  // when the other tiles have long published theirs; the loads return during
-  // the tile reduction
+  // a marked tile needs every count once its rows are out: load them now, so
+  // that the loads return during the tile reduction; the counts of the
+  // slowest tiles are not out yet and are polled again after it
   if constexpr (ONE) onepass_prefetch(P, pre);
   __syncthreads();  // cq, fq dead: the tile system takes their place
   auto& Y = S.u.s[0];
