@@ -439,28 +439,49 @@ __global__ void __launch_bounds__(256) k_count1d(K1D P, const uint8_t* __restric
   if (threadIdx.x == 0) P.tile_cnt[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
 }
 
-// exclusive scan of cnt[0..n) into off, total into *total (one block of 1024)
+// exclusive scan of cnt[0..n) into off, total into *total: one block of 1024
+// threads walks the array in chunks of 4096 (each thread scans 4 consecutive
+// counts, the wavefronts scan the thread sums with shuffles, 16 wavefront
+// sums are scanned by the first wavefront) and a running carry joins them
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int* __restrict__ off,
                                                int n, int* total) {
-  __shared__ int part[1024];
-  const int per = (n + blockDim.x - 1) / blockDim.x;
-  const int b = threadIdx.x * per, e = min(b + per, n);
-  int s = 0;
-  for (int i = b; i < e; i++) s += cnt[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+  __shared__ int wsum[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += 4096) {
+    const int i0 = base + 4 * (int)threadIdx.x;
+    int v[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = i0 + j < n ? cnt[i0 + j] : 0;
+    const int ts = v[0] + v[1] + v[2] + v[3];
+    int x = ts;  // inclusive scan of the thread sums within the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    part[threadIdx.x] += v;
+    if (wv == 0) {
+      int w = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const int y = __shfl_up(w, o, 64);
+        if (lane >= o) w += y;
+      }
+      if (lane < 16) wsum[lane] = w;
+    }
     __syncthreads();
+    int run = carry + (wv > 0 ? wsum[wv - 1] : 0) + x - ts;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (i0 + j < n) off[i0 + j] = run;
+      run += v[j];
+    }
+    carry += wsum[15];
+    __syncthreads();  // wsum is rewritten by the next chunk
   }
-  int run = part[threadIdx.x] - s;
-  for (int i = b; i < e; i++) {
-    off[i] = run;
-    run += cnt[i];
-  }
-  if (threadIdx.x == blockDim.x - 1) *total = part[threadIdx.x];
+  if (threadIdx.x == 0) *total = carry;
 }
 
 // packed list of marked cells in cell order
@@ -561,23 +582,24 @@ __global__ void __launch_bounds__(256) k_assemble1d(K1D P, const double* __restr
                                                     const double* t_in, const double* dt_in,
                                                     double* __restrict__ dg, double* __restrict__ up,
                                                     double* __restrict__ rh) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= *P.n_act) return;
-  const int gi = P.act_cell[k], ci = P.act_chan[k];
-  const Chan c = P.ch[ci];
-  const int i = (int)(gi - c.off), n = c.n;
-  Local L{&P, &c, ht, mt, kt, body_motion(c, t_in[ci] + dt_in[ci]), dt_in[ci], P.dx};
-  const CellNH cm = L.cell(reflect(i - 1, n)), c0 = L.cell(i), cp = L.cell(reflect(i + 1, n));
-  const FaceNH fl = L.face(i, cm.phi, c0.phi), fr = L.face(i + 1, c0.phi, cp.phi);
-  const double hs = ht[gi];
-  const double s22 = 3.0 * L.dt / (P.rho * hs);
-  const double xx = (i + 0.5) * P.dx;
-  const BedRate br = bed_rate(L.M, body_shape(c, xx - L.M.X, 0.0));
-  const double f2 = -2.0 * br.d_t - 2.0 * kt[gi] / hs - c0.D * mt[gi] / (2.0 * hs) -
-                    L.dt * c0.al * c0.phi / (2.0 * P.rho * hs);
-  dg[k] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
-  up[k] = (i + 1 < n && mask[gi + 1]) ? fr.K * fr.a * fr.b : 0.0;
-  rh[k] = f2 + fl.b * fl.qp + fr.a * fr.qp;
+  const int na = *P.n_act;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x) {
+    const int gi = P.act_cell[k], ci = P.act_chan[k];
+    const Chan c = P.ch[ci];
+    const int i = (int)(gi - c.off), n = c.n;
+    Local L{&P, &c, ht, mt, kt, body_motion(c, t_in[ci] + dt_in[ci]), dt_in[ci], P.dx};
+    const CellNH cm = L.cell(reflect(i - 1, n)), c0 = L.cell(i), cp = L.cell(reflect(i + 1, n));
+    const FaceNH fl = L.face(i, cm.phi, c0.phi), fr = L.face(i + 1, c0.phi, cp.phi);
+    const double hs = ht[gi];
+    const double s22 = 3.0 * L.dt / (P.rho * hs);
+    const double xx = (i + 0.5) * P.dx;
+    const BedRate br = bed_rate(L.M, body_shape(c, xx - L.M.X, 0.0));
+    const double f2 = -2.0 * br.d_t - 2.0 * kt[gi] / hs - c0.D * mt[gi] / (2.0 * hs) -
+                      L.dt * c0.al * c0.phi / (2.0 * P.rho * hs);
+    dg[k] = s22 + fl.K * fl.b * fl.b + fr.K * fr.a * fr.a;
+    up[k] = (i + 1 < n && mask[gi + 1]) ? fr.K * fr.a * fr.b : 0.0;
+    rh[k] = f2 + fl.b * fl.qp + fr.a * fr.qp;
+  }
 }
 
 // projection on the packed rows: x = packed pressure
@@ -588,24 +610,25 @@ __global__ void __launch_bounds__(256) k_correct1d(K1D P, const double* __restri
                                                    const double* t_in, const double* dt_in,
                                                    const double* __restrict__ x, double* hu,
                                                    double* hw, double* p) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= *P.n_act) return;
-  const int gi = P.act_cell[k], ci = P.act_chan[k];
-  const Chan c = P.ch[ci];
-  const int i = (int)(gi - c.off), n = c.n;
-  Local L{&P, &c, ht, mt, kt, body_motion(c, t_in[ci] + dt_in[ci]), dt_in[ci], P.dx};
-  const CellNH cm = L.cell(reflect(i - 1, n)), c0 = L.cell(i), cp = L.cell(reflect(i + 1, n));
-  const FaceNH fl = L.face(i, cm.phi, c0.phi), fr = L.face(i + 1, c0.phi, cp.phi);
-  const double pc = x[k];
-  const double pl = (i > 0 && mask[gi - 1]) ? x[k - 1] : 0.0;
-  const double pr = (i + 1 < n && mask[gi + 1]) ? x[k + 1] : 0.0;
-  const double dql = fl.fd - fl.K * (fl.a * pl + fl.b * pc);
-  const double dqr = fr.fd - fr.K * (fr.a * pc + fr.b * pr);
-  const double dm = 0.5 * (dql + dqr);
-  const double Pb = 1.5 * pc - P.rho * c0.D * dm / (4.0 * L.dt) + c0.al * c0.phi / 4.0;
-  hu[gi] = mt[gi] + dm;
-  hw[gi] = kt[gi] + L.dt * Pb / P.rho;
-  if (p) p[gi] = pc;
+  const int na = *P.n_act;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x) {
+    const int gi = P.act_cell[k], ci = P.act_chan[k];
+    const Chan c = P.ch[ci];
+    const int i = (int)(gi - c.off), n = c.n;
+    Local L{&P, &c, ht, mt, kt, body_motion(c, t_in[ci] + dt_in[ci]), dt_in[ci], P.dx};
+    const CellNH cm = L.cell(reflect(i - 1, n)), c0 = L.cell(i), cp = L.cell(reflect(i + 1, n));
+    const FaceNH fl = L.face(i, cm.phi, c0.phi), fr = L.face(i + 1, c0.phi, cp.phi);
+    const double pc = x[k];
+    const double pl = (i > 0 && mask[gi - 1]) ? x[k - 1] : 0.0;
+    const double pr = (i + 1 < n && mask[gi + 1]) ? x[k + 1] : 0.0;
+    const double dql = fl.fd - fl.K * (fl.a * pl + fl.b * pc);
+    const double dqr = fr.fd - fr.K * (fr.a * pc + fr.b * pr);
+    const double dm = 0.5 * (dql + dqr);
+    const double Pb = 1.5 * pc - P.rho * c0.D * dm / (4.0 * L.dt) + c0.al * c0.phi / 4.0;
+    hu[gi] = mt[gi] + dm;
+    hw[gi] = kt[gi] + L.dt * Pb / P.rho;
+    if (p) p[gi] = pc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1932,13 +1955,15 @@ __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b,
 // p (packed rows) -> full array
 __global__ void k_gather_packed(const int* __restrict__ act_cell, const int* n_act,
                                 const double* __restrict__ full, double* __restrict__ packed) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < *n_act) packed[k] = full[act_cell[k]];
+  const int na = *n_act;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x)
+    packed[k] = full[act_cell[k]];
 }
 __global__ void k_scatter_packed(const int* __restrict__ act_cell, const int* n_act,
                                  const double* __restrict__ packed, double* __restrict__ full) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < *n_act) full[act_cell[k]] = packed[k];
+  const int na = *n_act;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < na; k += gridDim.x * blockDim.x)
+    full[act_cell[k]] = packed[k];
 }
 
 // end of a step: t += dt, speed reset, step counter
@@ -1953,6 +1978,13 @@ __global__ void k_advance(K1D P, int nch) {
 // launchers
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+// grid of the kernels that walk the marked rows with a grid-stride loop: the
+// row count lives on the device, and a grid sized by the host bound (every
+// cell) spent most of its time in blocks that only load the count and exit
+static inline int rows_grid(int64_t max_rows) {
+  const int b = blocks_for(max_rows, 256);
+  return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+}
 
 void launch_speed1d(const K1D& P, const double* h, const double* hu, const double* hw,
                     hipStream_t s) {
@@ -1989,14 +2021,14 @@ void launch_compact1d(const K1D& P, const uint8_t* mask, hipStream_t s) {
 void launch_assemble1d(const K1D& P, int64_t max_rows, const double* ht, const double* mt,
                        const double* kt, const uint8_t* mask, const double* t_in,
                        const double* dt_in, double* dg, double* up, double* rh, hipStream_t s) {
-  hipLaunchKernelGGL(k_assemble1d, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s, P, ht, mt,
+  hipLaunchKernelGGL(k_assemble1d, dim3(rows_grid(max_rows)), dim3(256), 0, s, P, ht, mt,
                      kt, mask, t_in, dt_in, dg, up, rh);
 }
 void launch_correct1d(const K1D& P, int64_t max_rows, const double* ht, const double* mt,
                       const double* kt, const uint8_t* mask, const double* t_in,
                       const double* dt_in, const double* x, double* hu, double* hw, double* p,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_correct1d, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s, P, ht, mt,
+  hipLaunchKernelGGL(k_correct1d, dim3(rows_grid(max_rows)), dim3(256), 0, s, P, ht, mt,
                      kt, mask, t_in, dt_in, x, hu, hw, p);
 }
 void launch_advance(const K1D& P, int nch, hipStream_t s) {
@@ -2027,12 +2059,12 @@ void launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
 }
 void launch_gather_packed(const int* act_cell, const int* n_act, int64_t max_rows,
                           const double* full, double* packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_packed, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s, act_cell,
+  hipLaunchKernelGGL(k_gather_packed, dim3(rows_grid(max_rows)), dim3(256), 0, s, act_cell,
                      n_act, full, packed);
 }
 void launch_scatter_packed(const int* act_cell, const int* n_act, int64_t max_rows,
                            const double* packed, double* full, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_packed, dim3(blocks_for(max_rows, 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_scatter_packed, dim3(rows_grid(max_rows)), dim3(256), 0, s,
                      act_cell, n_act, packed, full);
 }
 
