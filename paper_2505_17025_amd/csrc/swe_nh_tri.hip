@@ -133,48 +133,50 @@ __global__ void __launch_bounds__(TPB) k_tri_reduce(const R* __restrict__ dg,
   const int n = *n_in;
   const int nchunks = (n + TRI_ROWS - 1) / TRI_ROWS;
   if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = 2 * nchunks;
-  if ((int)blockIdx.x >= nchunks) return;
   __shared__ TriSmem<R, 3> S;
   const int t = threadIdx.x;
-  const int row0 = blockIdx.x * TRI_ROWS;
-  const Rows4<R> q = load4(dg, up, rh, n, row0 + 4 * t);
-  reduce4(q, S, t);
-  __syncthreads();
-  // keep the block's end rows, then pin them: x_0 and x_last are parameters
-  const R b0 = S.b[0], c0 = S.c[0], d0 = S.d[0][0];
-  const R aL = S.a[RROWS - 1], bL = S.b[RROWS - 1], dL = S.d[0][RROWS - 1];
-  __syncthreads();
-  for (int j = 0; j < 2; j++) {
-    const int i = 2 * t + j;
-    const bool first = (i == 0), last = (i == RROWS - 1);
-    if (first || last) {
-      S.a[i] = R(0);
-      S.c[i] = R(0);
-      S.b[i] = R(1);
-      S.d[0][i] = R(0);
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {  // the block's chunks
+    const int row0 = cb * TRI_ROWS;
+    const Rows4<R> q = load4(dg, up, rh, n, row0 + 4 * t);
+    reduce4(q, S, t);
+    __syncthreads();
+    // keep the block's end rows, then pin them: x_0 and x_last are parameters
+    const R b0 = S.b[0], c0 = S.c[0], d0 = S.d[0][0];
+    const R aL = S.a[RROWS - 1], bL = S.b[RROWS - 1], dL = S.d[0][RROWS - 1];
+    __syncthreads();
+    for (int j = 0; j < 2; j++) {
+      const int i = 2 * t + j;
+      const bool first = (i == 0), last = (i == RROWS - 1);
+      if (first || last) {
+        S.a[i] = R(0);
+        S.c[i] = R(0);
+        S.b[i] = R(1);
+        S.d[0][i] = R(0);
+      }
+      S.d[1][i] = first ? R(1) : R(0);
+      S.d[2][i] = last ? R(1) : R(0);
     }
-    S.d[1][i] = first ? R(1) : R(0);
-    S.d[2][i] = last ? R(1) : R(0);
-  }
-  __syncthreads();
-  pcr<R, 3>(S);
-  if (t == 0) {
-    const R z1 = S.d[0][1] / S.b[1], u1 = S.d[1][1] / S.b[1], v1 = S.d[2][1] / S.b[1];
-    const R zL = S.d[0][RROWS - 2] / S.b[RROWS - 2];
-    const R vL = S.d[2][RROWS - 2] / S.b[RROWS - 2];
-    const int o = 2 * blockIdx.x;
-    dg2[o] = b0 + c0 * u1;
-    up2[o] = c0 * v1;
-    rh2[o] = d0 - c0 * z1;
-    dg2[o + 1] = bL + aL * vL;
-    rh2[o + 1] = dL - aL * zL;
-    const int lastrow = row0 + TRI_ROWS - 1;
-    up2[o + 1] = (lastrow + 1 < n) ? up[lastrow] : R(0);
+    __syncthreads();
+    pcr<R, 3>(S);
+    if (t == 0) {
+      const R z1 = S.d[0][1] / S.b[1], u1 = S.d[1][1] / S.b[1], v1 = S.d[2][1] / S.b[1];
+      const R zL = S.d[0][RROWS - 2] / S.b[RROWS - 2];
+      const R vL = S.d[2][RROWS - 2] / S.b[RROWS - 2];
+      const int o = 2 * cb;
+      dg2[o] = b0 + c0 * u1;
+      up2[o] = c0 * v1;
+      rh2[o] = d0 - c0 * z1;
+      dg2[o + 1] = bL + aL * vL;
+      rh2[o + 1] = dL - aL * zL;
+      const int lastrow = row0 + TRI_ROWS - 1;
+      up2[o + 1] = (lastrow + 1 < n) ? up[lastrow] : R(0);
+    }
+    __syncthreads();  // S is rewritten by the next chunk
   }
 }
 
-// xnext == nullptr: the whole system fits one block (top level); otherwise
-// block c has end values xnext[2c], xnext[2c + 1]
+// xnext == nullptr: the whole system fits one chunk (top level); otherwise
+// chunk c has end values xnext[2c], xnext[2c + 1]
 template <typename R>
 __global__ void __launch_bounds__(TPB) k_tri_solve(const R* __restrict__ dg,
                                                    const R* __restrict__ up,
@@ -184,41 +186,52 @@ __global__ void __launch_bounds__(TPB) k_tri_solve(const R* __restrict__ dg,
   if (conv && *conv) return;
   const int n = *n_in;
   const int nchunks = (n + TRI_ROWS - 1) / TRI_ROWS;
-  if ((int)blockIdx.x >= nchunks) return;
   __shared__ TriSmem<R, 1> S;
   const int t = threadIdx.x;
-  const int row0 = blockIdx.x * TRI_ROWS;
-  const Rows4<R> q = load4(dg, up, rh, n, row0 + 4 * t);
-  reduce4(q, S, t);
-  __syncthreads();
-  if (xnext) {
-    if (t == 0) {
-      S.a[0] = R(0);
-      S.c[0] = R(0);
-      S.b[0] = R(1);
-      S.d[0][0] = xnext[2 * blockIdx.x];
-      S.a[RROWS - 1] = R(0);
-      S.c[RROWS - 1] = R(0);
-      S.b[RROWS - 1] = R(1);
-      S.d[0][RROWS - 1] = xnext[2 * blockIdx.x + 1];
-    }
+  for (int cb = blockIdx.x; cb < nchunks; cb += gridDim.x) {  // the block's chunks
+    const int row0 = cb * TRI_ROWS;
+    const Rows4<R> q = load4(dg, up, rh, n, row0 + 4 * t);
+    reduce4(q, S, t);
     __syncthreads();
+    if (xnext) {
+      if (t == 0) {
+        S.a[0] = R(0);
+        S.c[0] = R(0);
+        S.b[0] = R(1);
+        S.d[0][0] = xnext[2 * cb];
+        S.a[RROWS - 1] = R(0);
+        S.c[RROWS - 1] = R(0);
+        S.b[RROWS - 1] = R(1);
+        S.d[0][RROWS - 1] = xnext[2 * cb + 1];
+      }
+      __syncthreads();
+    }
+    pcr<R, 1>(S);
+    const R xf = S.d[0][2 * t] / S.b[2 * t];
+    const R xl = S.d[0][2 * t + 1] / S.b[2 * t + 1];
+    const R det = q.d[1] * q.d[2] - q.u[1] * q.u[1];
+    const R r1 = q.b[1] - q.u[0] * xf, r2 = q.b[2] - q.u[2] * xl;
+    const R x1 = (q.d[2] * r1 - q.u[1] * r2) / det;
+    const R x2 = (q.d[1] * r2 - q.u[1] * r1) / det;
+    const int r = row0 + 4 * t;
+    if (r < n) x[r] = xf;
+    if (r + 1 < n) x[r + 1] = x1;
+    if (r + 2 < n) x[r + 2] = x2;
+    if (r + 3 < n) x[r + 3] = xl;
+    __syncthreads();  // S is rewritten by the next chunk
   }
-  pcr<R, 1>(S);
-  const R xf = S.d[0][2 * t] / S.b[2 * t];
-  const R xl = S.d[0][2 * t + 1] / S.b[2 * t + 1];
-  const R det = q.d[1] * q.d[2] - q.u[1] * q.u[1];
-  const R r1 = q.b[1] - q.u[0] * xf, r2 = q.b[2] - q.u[2] * xl;
-  const R x1 = (q.d[2] * r1 - q.u[1] * r2) / det;
-  const R x2 = (q.d[1] * r2 - q.u[1] * r1) / det;
-  const int r = row0 + 4 * t;
-  if (r < n) x[r] = xf;
-  if (r + 1 < n) x[r + 1] = x1;
-  if (r + 2 < n) x[r + 2] = x2;
-  if (r + 3 < n) x[r + 3] = xl;
 }
 
 }  // namespace
+
+// blocks of a level: the row count lives on the device and the host only
+// knows its bound, so a block walks several chunks rather than the grid
+// holding one block per possible chunk (most of which would only load the
+// count and exit)
+static int tri_grid(int64_t nmax) {
+  const int64_t b = (nmax + TRI_ROWS - 1) / TRI_ROWS;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
 
 template <typename R>
 void launch_tri_solve(const TriLevels<R>& T, const int* n0, const int* conv, hipStream_t s) {
@@ -227,7 +240,7 @@ void launch_tri_solve(const TriLevels<R>& T, const int* n0, const int* conv, hip
   nl[0] = n0;
   for (int l = 1; l < T.nlev; l++) nl[l] = T.n + l;
   for (int l = 0; l + 1 < T.nlev; l++) {
-    const int blocks = (int)((T.nmax[l] + TRI_ROWS - 1) / TRI_ROWS);
+    const int blocks = tri_grid(T.nmax[l]);
     hipLaunchKernelGGL(k_tri_reduce<R>, dim3(blocks), dim3(TPB), 0, s, T.dg[l], T.up[l], T.rh[l],
                        nl[l], T.dg[l + 1], T.up[l + 1], T.rh[l + 1], T.n + l + 1, conv);
   }
@@ -235,7 +248,7 @@ void launch_tri_solve(const TriLevels<R>& T, const int* n0, const int* conv, hip
   hipLaunchKernelGGL(k_tri_solve<R>, dim3(1), dim3(TPB), 0, s, T.dg[top], T.up[top], T.rh[top],
                      nl[top], (const R*)nullptr, T.x[top], conv);
   for (int l = T.nlev - 2; l >= 0; l--) {
-    const int blocks = (int)((T.nmax[l] + TRI_ROWS - 1) / TRI_ROWS);
+    const int blocks = tri_grid(T.nmax[l]);
     hipLaunchKernelGGL(k_tri_solve<R>, dim3(blocks), dim3(TPB), 0, s, T.dg[l], T.up[l], T.rh[l],
                        nl[l], (const R*)T.x[l + 1], T.x[l], conv);
   }
@@ -298,14 +311,16 @@ __global__ void k_resid_final(const double* part, const double* part_b, int npar
                               double tol, double* norms, double* rel, int* iters, int* conv,
                               int is_first) {
   if (conv && *conv && !is_first) return;
-  if (threadIdx.x != 0) return;
-  double rr = 0.0;
-  for (int i = 0; i < nparts; i++) rr += part[i];
-  if (part_b) {
-    double bb = 0.0;
-    for (int i = 0; i < nparts; i++) bb += part_b[i];
-    norms[1] = bb;
+  // one wavefront: strided partial sums, then a shuffle reduction
+  double rr = 0.0, bsum = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) {
+    rr += part[i];
+    if (part_b) bsum += part_b[i];
   }
+  rr = wave_sum(rr);
+  bsum = wave_sum(bsum);
+  if (threadIdx.x != 0) return;
+  if (part_b) norms[1] = bsum;
   norms[0] = rr;
   const double bb = norms[1];
   const double r = bb > 0.0 ? sqrt(rr / bb) : 0.0;
