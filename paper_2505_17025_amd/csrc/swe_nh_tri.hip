@@ -4,15 +4,16 @@
 //
 // Block-recursive Schur complement, no pivoting (every Schur complement of
 // the SPD matrix is SPD):
-//   * a block owns TRI_ROWS = 1024 consecutive rows, 4 per thread;
+//   * a chunk is TRI_ROWS = 1024 consecutive rows, 4 per thread of the block
+//     that walks it (a level's grid is capped, so a block may walk several);
 //   * each thread eliminates its two interior rows (closed 2x2 inverse),
 //     leaving a 512-row tridiagonal system of the threads' end rows in LDS;
 //   * reduce: that system, with its first and last rows pinned, is solved by
 //     parallel cyclic reduction for three right-hand sides, which yields the
-//     block's Schur complement on its first and last rows -> 2 rows per block
+//     chunk's Schur complement on its first and last rows -> 2 rows per chunk
 //     of the next level;
 //   * the last level (<= 1024 rows) is solved by one block;
-//   * back-substitution re-runs each block with its end rows known.
+//   * back-substitution re-runs each chunk with its end rows known.
 #include "swe_nh_common.h"
 #include "swe_nh_kernels.h"
 
