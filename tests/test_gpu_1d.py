@@ -544,6 +544,23 @@ def test_wide_enlargement_uses_the_unfused_step(B):
         assert rel(g, r) <= 1e-10
 
 
+def test_unfused_path_beyond_one_pass_of_its_grids(B):
+    """the FP32 solve with FP64 refinement with every cell of 1.2M marked:
+    more marked rows than the row kernels' capped grid covers in one pass
+    (2048 blocks of 256), more 1024-row chunks than a tridiagonal level's
+    blocks (1024), and tile counts spanning two chunks of the scan"""
+    n = 1_200_000
+    case = S.random_case_1d(n, seed=41, dx=0.05)
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.45, precision=1, tol=1e-12, max_iter=8, tile1d=242)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 2, **kw)
+    assert st["status"] == 0, st
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(2)
+    assert st["n_active"] == ref.last_active == n
+    assert np.array_equal(mask.cpu().numpy(), ref.mask)
+    for g, r in ((h - dt(case.ds), ref.h - case.ds), (hu, ref.hu), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-6
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_ensemble_sampled_channels(B, precision):
     """the 512-channel ensemble at its full size (18.3M cells) in the
