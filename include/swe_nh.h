@@ -18,8 +18,9 @@
  *
  * Memory: every array argument is a DEVICE pointer to contiguous FP64 (or
  * uint8 for masks) memory owned by the caller, structure-of-arrays, x
- * fastest; 2D arrays are [ny][nx].  The library owns no device memory: all
- * scratch lives in a caller-provided workspace of swe_nh_workspace_bytes().
+ * fastest; 2D arrays are [ny][nx].  The library allocates no device memory:
+ * all scratch lives in a caller-provided workspace of swe_nh_workspace_bytes(),
+ * except for the fixed static scratch of swe_nh_cnn_forward_noalloc.
  * Host pointers are marked "host".
  *
  * Streams and asynchrony: every call is enqueued on the stream given to
@@ -218,6 +219,26 @@ size_t swe_nh_cnn_workspace_bytes(int32_t n, int32_t h, int32_t w);
  * activations in ws for a following swe_nh_cnn_backward. */
 int swe_nh_cnn_forward(const float* params, const uint16_t* x, int32_t n, int32_t h, int32_t w,
                        float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Allocation-free variant of swe_nh_cnn_forward for callers that cannot
+ * allocate device memory: code under stream or graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same network, kernels and output
+ * as swe_nh_cnn_forward, but the packed weights and the activations live in
+ * the library's own static device scratch of SWE_NH_CNN_NOALLOC_SCRATCH_BYTES
+ * (one copy per device, held from the library's load until the process ends)
+ * instead of a caller workspace; the call allocates nothing.  params, x, out
+ * as in swe_nh_cnn_forward (caller-owned device buffers).
+ * Limits: n * h * w <= SWE_NH_CNN_NOALLOC_MAX_PIXELS (else SWE_NH_ENOMEM), h
+ * and w multiples of 16 (else SWE_NH_EINVAL); stream must belong to the
+ * current device (else SWE_NH_EINVAL; NULL = its default stream).  Inference
+ * only: nothing is kept for swe_nh_cnn_backward.  Every call on a device
+ * uses that device's one scratch, which keeps the last call's contents: calls
+ * that overlap in time on one device (several streams or threads) race, and
+ * the caller must serialise them. */
+#define SWE_NH_CNN_NOALLOC_MAX_PIXELS 131072
+#define SWE_NH_CNN_NOALLOC_SCRATCH_BYTES (17u << 20)
+int swe_nh_cnn_forward_noalloc(const float* params, const uint16_t* x, int32_t n, int32_t h,
+                               int32_t w, float* out, void* stream);
 
 /* grad (parameter-shaped, FP32) = d(sum(out * dout)) / d(params) for the
  * batch of the last swe_nh_cnn_forward on the same workspace. */

@@ -24,6 +24,7 @@ struct CnnLayout {
 
 int64_t cnn_param_count();
 CnnLayout cnn_layout(int n, int h, int w);
+CnnLayout cnn_layout_infer(int n, int h, int w);
 void cnn_pack_weights(const float* params, char* ws, const CnnLayout& L, bool with_transposed,
                       hipStream_t s);
 // box (device, nullable): [x0, y0, x1, y1) of the image, the pixel tiles to

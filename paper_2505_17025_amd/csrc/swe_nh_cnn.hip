@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "swe_nh.h"
 #include "swe_nh_cnn.h"
 #include "swe_nh_common.h"
@@ -551,6 +553,45 @@ void cnn_features(const Chan* ch, const double* ds, int nx, int ny, double dx, d
 }
 
 
+// Inference-only layout: the packed forward weights and two activation
+// buffers that the layers use in turn (layer l reads one, writes the other).
+CnnLayout cnn_layout_infer(int n, int h, int w) {
+  CnnLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    const size_t o = off;
+    off += bytes ? bytes : 1;
+    return o;
+  };
+  const int64_t npix = (int64_t)n * h * w;
+  for (int l = 0; l < NL; l++) L.wpk[l] = take(2 * packed_elems(l, 0));
+  const size_t a = take(2 * npix * 32), b = take(2 * npix * 32);
+  for (int l = 0; l < NL - 1; l++) L.act[l] = (l & 1) ? b : a;
+  L.bytes = off;
+  return L;
+}
+
+// Scratch of the allocation-free inference entry point.  Each device holds
+// its own copy from module load until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device.
+static __device__ __align__(256) unsigned char scratch[SWE_NH_CNN_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];  // per device ordinal, set on the first call on that device
+
+// device address of `scratch` on device dev (which must be current), or null
+static void* scratch_on(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace swenh
 
 // ---------------------------------------------------------------------------
@@ -583,6 +624,28 @@ int swe_nh_cnn_forward(const float* params, const uint16_t* x, int32_t n, int32_
   hipStream_t s = (hipStream_t)stream;
   cnn_pack_weights(params, (char*)ws, L, true, s);
   cnn_forward(params, x, n, h, w, (char*)ws, L, out, s);
+  return hipGetLastError() == hipSuccess ? SWE_NH_OK : SWE_NH_EHIP;
+}
+
+int swe_nh_cnn_forward_noalloc(const float* params, const uint16_t* x, int32_t n, int32_t h,
+                               int32_t w, float* out, void* stream) {
+  if (!params || !x || !out) return SWE_NH_EINVAL;
+  if (n < 1 || h < 16 || w < 16 || h % 16 || w % 16) return SWE_NH_EINVAL;
+  if ((int64_t)n * h * w > SWE_NH_CNN_NOALLOC_MAX_PIXELS) return SWE_NH_ENOMEM;
+  const CnnLayout L = cnn_layout_infer(n, h, w);
+  if (L.bytes > SWE_NH_CNN_NOALLOC_SCRATCH_BYTES) return SWE_NH_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SWE_NH_EHIP;
+  if (s) {  // the scratch address is per device: the stream must be the current device's
+    int sdev = -1;
+    if (hipStreamGetDevice(s, &sdev) != hipSuccess) return SWE_NH_EHIP;
+    if (sdev != dev) return SWE_NH_EINVAL;
+  }
+  char* ws = static_cast<char*>(scratch_on(dev));
+  if (!ws) return SWE_NH_EHIP;
+  cnn_pack_weights(params, ws, L, false, s);
+  cnn_forward(params, x, n, h, w, ws, L, out, s);
   return hipGetLastError() == hipSuccess ? SWE_NH_OK : SWE_NH_EHIP;
 }
 

@@ -80,13 +80,15 @@ def _load():
     lib.swe_nh_cnn_workspace_bytes.restype = C.c_size_t
     lib.swe_nh_cnn_workspace_bytes.argtypes = [i32, i32, i32]
     lib.swe_nh_cnn_forward.argtypes = [vp, vp, i32, i32, i32, vp, vp, C.c_size_t, vp]
+    lib.swe_nh_cnn_forward_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     lib.swe_nh_cnn_backward.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, C.c_size_t, vp]
     lib.swe_nh_cnn_mse.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, C.c_size_t, vp]
     lib.swe_nh_cnn_adam.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float,
                                     C.c_float, vp]
     lib.swe_nh_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
     lib.swe_nh_set_warm_start_net.argtypes = [vp, vp, C.POINTER(dbl), dbl]
-    for name in ("swe_nh_cnn_forward", "swe_nh_cnn_backward", "swe_nh_cnn_mse", "swe_nh_cnn_adam",
+    for name in ("swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
+                 "swe_nh_cnn_mse", "swe_nh_cnn_adam",
                  "swe_nh_features", "swe_nh_set_warm_start_net", "swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
                  "swe_nh_sync_stats", "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure",
                  "swe_nh_correct"):
@@ -99,8 +101,9 @@ EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_l
             "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step", "swe_nh_sync_stats",
             "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct",
             "swe_nh_time_stage", "swe_nh_cnn_param_count", "swe_nh_cnn_workspace_bytes",
-            "swe_nh_cnn_forward", "swe_nh_cnn_backward", "swe_nh_cnn_mse", "swe_nh_cnn_adam",
-            "swe_nh_features", "swe_nh_set_warm_start_net"]
+            "swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
+            "swe_nh_cnn_mse", "swe_nh_cnn_adam", "swe_nh_features", "swe_nh_set_warm_start_net"]
+NOALLOC_MAX_PIXELS = 131072
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -262,6 +265,13 @@ def context_1d(case_or_ensemble, **kw) -> Context:
 def context_2d(case, **kw) -> Context:
     return Context(dim=2, nx=case.nx, ny=case.ny, dx=case.dx, dy=case.dy,
                    depth_static=torch.from_numpy(np.asarray(case.ds)), bodies=[case.body], **kw)
+
+
+def cnn_forward_noalloc(params, x, n, h, w, out):
+    """swe_nh_cnn_forward_noalloc on the current stream; returns the status code"""
+    stream = torch.cuda.current_stream(out.device).cuda_stream
+    return int(LIB.swe_nh_cnn_forward_noalloc(_ptr(params), _ptr(x), int(n), int(h), int(w),
+                                              _ptr(out), C.c_void_p(stream)))
 
 
 class Net:
