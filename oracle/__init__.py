@@ -10,7 +10,9 @@ Parity status: every function here is pinned by the CPU test suite
 paper's printed values, except the 2D extension, which the paper does not
 contain: its pins are reductions (y-invariant data equals the 1D oracle,
 x<->y transpose symmetry, lake at rest, mass, dense solve, the 2D linear
-dispersion relation).
+dispersion relation).  oracle/rkdg1d.py is the paper's own discretisation
+(RKDG-P1 predictor, LDG-P1 elliptic solve) in NumPy, pinned by
+tests/test_oracle_rkdg.py.
 """
 from __future__ import annotations
 
