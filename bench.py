@@ -1,17 +1,20 @@
 """Benchmark of the adaptive non-hydrostatic SWE hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W]
-                [--workload slide1d|long1d|ensemble1d|shelf2d|learned2d|paper1d|copycal]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--preroll R]
+                [--workload ensemble1d|slide1d|long1d|shelf2d|learned2d|paper1d|copycal]
 
 A step is one full pass of the hot path (predictor, criterion and
 enlargement, compaction, elliptic assembly and solve, projection) over the
-whole grid.  The headline workload is the 1D moving-bottom slide (quartic
-block of length 0.4 m and height 0.05 m sliding down a 15 degree slope into
-h0 = 0.4 m, sinusoidal-ramp displacement, N = 32768 cells, dx = 5 mm,
-adaptive |eta/d| > 1e-3 with one-cell enlargement, FP64, CFL 0.5); the same
-run with the global extension and with the FP32 inner solve + FP64
-refinement are reported beside it.  value = cell-steps/s (all cells, marked
-or not) with the state resident in HBM.  Prints ONE JSON line on stdout.
+whole grid.  The headline workload (the default) is the largest one-GPU
+configuration: an ensemble of 512 independent 1D moving-bottom channels
+(lengths uniform in 4096..65536 cells, 18.3M cells in all; slide length,
+height and slope angle from seeded uniform ranges; adaptive |eta/d| > 1e-3
+with one-cell enlargement; FP32 inner solve with FP64 refinement, CFL 0.5),
+timed after an untimed pre-roll of R steps (default 2500, the middle of the
+configuration's 5000 steps) so that the timed steps see a representative
+marked area.  The FP64 solve and the global extension from the same state
+are reported beside it.  value = cell-steps/s (all cells, marked or not)
+with the state resident in HBM.  Prints ONE JSON line on stdout.
 """
 import argparse
 import hashlib
@@ -40,7 +43,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="slide1d",
+    ap.add_argument("--preroll", type=int, default=None,
+                    help="ensemble1d: untimed steps before the warm-up (default 2500)")
+    ap.add_argument("--workload", default="ensemble1d",
                     choices=["slide1d", "long1d", "ensemble1d", "shelf2d", "learned2d",
                              "paper1d", "copycal"])
     ap.add_argument("--tile1d", type=int, default=0,
@@ -69,12 +74,15 @@ def pmc_traffic(kernel_file, src_file, tile=None):
     return float(t.group(1)) if t else None
 
 
-def tune_tile(B, torch, case, kw, nsteps, warmup):
-    """tile1d picked by the launch-shape autotuner on this workload"""
+def tune_tile(B, torch, case, kw, nsteps, warmup, start=None):
+    """tile1d picked by the launch-shape autotuner on this workload (from the
+    state start = (h, hu, hw, times) when given)"""
     from paper_2505_17025_amd import autotune
     dev = torch.device("cuda:0")
     f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    if hasattr(case, "channels"):
+    if start is not None:
+        state, t0 = tuple(start[:3]), list(start[3])
+    elif hasattr(case, "channels"):
         state = (f(case.packed("h")), f(case.packed("hu")), f(case.packed("hw")))
         t0 = [c.t0 for c in case.channels]
     else:
@@ -85,10 +93,16 @@ def tune_tile(B, torch, case, kw, nsteps, warmup):
     return tile, {str(k): v * 1e6 for k, v in times.items()}
 
 
-def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000):
+def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000, start=None):
+    """steps timed after warmup untimed ones; start: (h, hu, hw, times) to
+    begin from (device tensors, copied) instead of the case's initial state"""
     dev = torch.device("cuda:0")
     f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    if hasattr(case, "channels"):
+    if start is not None:
+        ctx = B.context_1d(case, **kw)
+        ctx.set_time(list(start[3]))
+        h, hu, hw = (a.clone() for a in start[:3])
+    elif hasattr(case, "channels"):
         ctx = B.context_1d(case, **kw)
         ctx.set_time([c.t0 for c in case.channels])
         h, hu, hw = f(case.packed("h")), f(case.packed("hu")), f(case.packed("hw"))
@@ -114,7 +128,7 @@ def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000):
            "n_active_last": int(st["n_active"]), "t_end": st["t"], "iters_last": st["iters"],
            "cells": ncell}
     if reps_stage:
-        if kw.get("precision", 0) == 0:  # fused step: its kernels one by one
+        if kw.get("enlarge", 1) <= 8:  # fused step: its kernels one by one
             names = ["step_kernel", "level1_solve", "projection", "predictor_alone"]
             reps = [reps_stage] * 4
         else:
@@ -123,6 +137,42 @@ def run_1d(B, torch, case, kw, steps, warmup, reps_stage=2000):
         out["stage_us"] = {nm: ctx.time_stage(i, r, h, hu, None, hw, p)
                            for i, (nm, r) in enumerate(zip(names, reps))}
     return out
+
+
+def preroll_1d(B, torch, case, kw, nsteps):
+    """the state after nsteps untimed steps from the case's initial state:
+    (h, hu, hw, times), device tensors and a host array of channel times"""
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = B.context_1d(case, **kw)
+    ctx.set_time([c.t0 for c in case.channels])
+    h, hu, hw = f(case.packed("h")), f(case.packed("hu")), f(case.packed("hw"))
+    p = torch.zeros_like(h)
+    ctx.step(h, hu, None, hw, p, nsteps=nsteps)
+    st = ctx.sync_stats()
+    if st["status"] != 0:
+        raise RuntimeError(f"pre-roll status {st}")
+    log(f"pre-roll: {nsteps} steps, t = {st['t']:.4f} s, {st['n_active']} marked cells")
+    return h, hu, hw, ctx.get_time()
+
+
+# algorithmic bytes of a 1D step: predictor (read h, hu, hw; write h, hu, hw)
+# and the mask byte per cell, and per marked cell the elliptic work (read Q~
+# and d_s, write hu, hw, p)
+ALG_BYTES_CELL, ALG_BYTES_ACTIVE = 49.0, 56.0
+
+
+def ensemble_roofline(ncell, n_active, stage_us, pmc_file, tile):
+    """roofline of the fused 1D step kernel on algorithmic bytes"""
+    us = stage_us["step_kernel"]
+    per_launch = ncell * ALG_BYTES_CELL + n_active * ALG_BYTES_ACTIVE
+    achieved = per_launch / (us * 1e-6) / 1e9
+    return {"kernel": "k_step1d", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pmc_traffic(pmc_file, "paper_2505_17025_amd/csrc/swe_nh_1d.hip", tile),
+            "avg_launch_us": us, "bytes_per_launch": per_launch,
+            "bytes_per_cell": ALG_BYTES_CELL, "bytes_per_active_cell": ALG_BYTES_ACTIVE,
+            "n_active": n_active, "stage_us": stage_us}
 
 
 STEP1D_BYTES = 65.0  # per cell: read h, hu, hw, d_s; write h, hu, hw, p (FP64) and the mask byte
@@ -208,21 +258,31 @@ def time_run_oracle(O, case, ph, dt_fixed, nsteps, reps=3):
     return best, sim
 
 
-def cpu_baseline_ensemble(ens, kw, nch=8, nsteps=100):
+def cpu_baseline_ensemble(ens, kw, nch=8, nsteps=100, start=None):
     """the oracle on the first nch channels of the ensemble, channel after
-    channel (FP64 direct solve: the oracle has no FP32 mode)"""
+    channel (FP64 direct solve: the oracle has no FP32 mode); start: the
+    (h, hu, hw, times) the GPU run starts from"""
     import oracle as O
+    import swe_inputs as S
     ph = O.phys_struct(crit=kw["crit"], k_nh=kw["k_nh"], enlarge=kw["enlarge"])
     cells, el = 0, 0.0
-    for c in ens.channels[:nch]:
+    o = ens.offsets
+    if start is not None:
+        hs, hus, hws = (a.cpu().numpy() for a in start[:3])
+    for j, c in enumerate(ens.channels[:nch]):
+        if start is not None:
+            sl = slice(int(o[j]), int(o[j + 1]))
+            c = S.Case1D(n=c.n, dx=c.dx, ds=c.ds, h=hs[sl].copy(), hu=hus[sl].copy(),
+                         hw=hws[sl].copy(), body=c.body, t0=float(start[3][j]))
         sim = O.Sim1D(c, ph, cfl=kw["cfl"])
         t0 = time.perf_counter()
         sim.step(nsteps)
         el += time.perf_counter() - t0
         cells += c.n
     return {"value": cells * nsteps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nsteps} steps of the first {nch} channels ({cells} cells), "
-                      f"single-threaded plain-C FP64 oracle, {el:.1f} s"}
+            "sample": f"{nsteps} steps of the first {nch} channels ({cells} cells)"
+                      + (" from the GPU run's start state" if start is not None else "")
+                      + f", single-threaded plain-C FP64 oracle, {el:.1f} s"}
 
 
 def main():
@@ -381,43 +441,54 @@ def main():
                                   "run wall times on unstated hardware with its DG/LDG solver"}}
         print(json.dumps(line), flush=True)
     elif args.workload == "ensemble1d":
-        steps = args.steps or 200
-        warmup = args.warmup if args.warmup is not None else 20
+        steps = args.steps or 20
+        warmup = args.warmup if args.warmup is not None else 5
+        preroll = args.preroll if args.preroll is not None else 2500
         ens = S.ensemble_case(n_channels=512, n_min=4096, n_max=65536, seed=17026)
         kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1, tol=1e-12,
                   max_iter=6)
-        log(f"ensemble1d: 512 channels, {int(ens.offsets[-1])} cells")
+        ncell = int(ens.offsets[-1])
+        log(f"ensemble1d: 512 channels, {ncell} cells, pre-roll {preroll} steps")
+        start = preroll_1d(B, torch, ens, dict(kw, precision=0, tile1d=242), preroll)
         tile, tune_us = (args.tile1d, None) if args.tile1d else tune_tile(
-            B, torch, ens, dict(kw, precision=0), 30, 5)
+            B, torch, ens, kw, 20, 5, start=start)
         kw["tile1d"] = tile
-        res = run_1d(B, torch, ens, kw, steps, warmup, reps_stage=50)
+        res = run_1d(B, torch, ens, kw, steps, warmup, reps_stage=50, start=start)
         log("adaptive fp32+refine:", json.dumps(res))
-        r64 = run_1d(B, torch, ens, dict(kw, precision=0), steps, warmup, reps_stage=50)
-        g = run_1d(B, torch, ens, dict(kw, crit=S.CRIT_GLOBAL), steps, warmup, reps_stage=0)
-        ncell = res["cells"]
-        pred_us = res["stage_us"]["predictor"]
-        achieved = ncell * 56.0 / (pred_us * 1e-6) / 1e9
-        r64s = r64.get("stage_us")
+        roof = ensemble_roofline(ncell, res["n_active_last"], res["stage_us"],
+                                 f"step1d_f32r_ensemble512_tile{tile}_pmc.txt", tile)
+        extra = {"preroll_steps": preroll, "t_start": float(np.min(start[3])),
+                 "n_active_last": res["n_active_last"], "refine_sweeps_last": res["iters_last"]}
+        if not args.no_extra:
+            r64 = run_1d(B, torch, ens, dict(kw, precision=0), steps, warmup, reps_stage=50,
+                         start=start)
+            log("adaptive fp64:", json.dumps(r64))
+            g = run_1d(B, torch, ens, dict(kw, crit=S.CRIT_GLOBAL), steps, warmup, reps_stage=0,
+                       start=start)
+            log("global fp32+refine:", json.dumps(g))
+            extra.update({
+                "fp64_cell_steps_per_s": r64["cell_steps_per_s"],
+                "fp64_ms_per_step": r64["ms_per_step"],
+                "fp64_roofline": ensemble_roofline(ncell, r64["n_active_last"], r64["stage_us"],
+                                                   f"step1d_ensemble512_tile{tile}_pmc.txt",
+                                                   tile),
+                "global_cell_steps_per_s": g["cell_steps_per_s"],
+                "adaptive_over_global": res["cell_steps_per_s"] / g["cell_steps_per_s"]})
+        cpu = None
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            cpu = cpu_baseline_ensemble(ens, kw, start=start)
         line = {"metric": METRIC, "value": res["cell_steps_per_s"], "unit": "cell-steps/s",
                 "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": res["ms_per_step"],
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
                 "data": "synthetic",
-                "config": {"workload": "512 independent 1D slide channels, lengths U{4096..65536}, "
-                                       "slide length/height/slope from seeded uniform ranges, "
-                                       "adaptive |eta/d|, FP32 solve + FP64 refinement, one "
-                                       "hipGraph per step", "cells": ncell, "tile1d": tile,
-                           "autotune_us_per_step": tune_us},
-                "roofline": {"kernel": "k_pred1d", "bound": "hbm", "achieved": achieved,
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                             "traffic": None, "avg_launch_us": pred_us,
-                             "bytes_per_launch": ncell * 56.0, "stage_us": res["stage_us"]},
-                "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_ensemble(ens, kw),
-                "extra": {"fp64_cell_steps_per_s": r64["cell_steps_per_s"],
-                          "fp64_roofline": step_roofline(ncell, r64s,
-                                                         f"step1d_ensemble512_tile{tile}_pmc.txt",
-                                                         tile),
-                          "global_cell_steps_per_s": g["cell_steps_per_s"],
-                          "n_active_last": res["n_active_last"]}}
+                "config": {"workload": "512 independent 1D slide channels, lengths U{4096..65536} "
+                                       "(18.3M cells), slide length/height/slope from seeded "
+                                       "uniform ranges, adaptive |eta/d|>1e-3 + 1-cell "
+                                       "enlargement, FP32 inner solve + FP64 refinement (tol "
+                                       f"1e-12), CFL 0.5, timed after a {preroll}-step pre-roll",
+                           "cells": ncell, "tile1d": tile, "autotune_us_per_step": tune_us},
+                "roofline": roof, "cpu_baseline": cpu, "extra": extra}
         print(json.dumps(line), flush=True)
     elif args.workload == "copycal":
         # plain device copy of known size: the HBM counters of a profiled run

@@ -102,15 +102,21 @@ typedef struct {
   double k_nh;              /* threshold, paper value 1e-3 */
   int32_t enlarge;          /* cells added on each side of the marked area (paper: 1) */
   int32_t first_global;     /* |w| and |w_x|: global model on the first step (Sec. 5.1.2) */
-  int32_t precision;        /* 0: FP64 solve; 1: FP32 inner solve + FP64 residual refinement */
-  double tol;               /* ||b - A p||_2 <= tol ||b||_2 (2D PCG, and 1D refinement) */
+  int32_t precision;        /* 0: FP64 solve; 1: FP32 inner solve + FP64 residual refinement
+                               (1D fused step, enlarge <= 8: each tile's interior system
+                               is reduced in FP32 and refined with FP64 residuals, the
+                               tiles' coupling system is solved in FP64) */
+  double tol;               /* 2D PCG and the 1D unfused refinement (enlarge > 8):
+                               ||b - A p||_2 <= tol ||b||_2.  1D fused refinement: each
+                               tile's componentwise backward error
+                               max_j |r_j| / (|A| |x| + |b|)_j <= tol */
   int32_t max_iter;         /* PCG iterations (2D) or refinement sweeps (precision 1) */
   int32_t warm;             /* 2D initial guess: 0 zero, 1 previous p (the p array on
                                entry), 2 the warm-start network */
   int32_t tile1d;           /* 1D cells per block of the stencil kernels, 32..512, or 0
                                for the built-in choice.  The kernels' LDS windows come
                                in capacities of 128, 256 and 512 cells; the smallest
-                               that holds the tile is used.  The FP64 fused step's
+                               that holds the tile is used.  The fused step's
                                window adds 6 + enlarge cells on each side, so a tile of
                                capacity - 2 (6 + enlarge) cells fills whole wavefronts */
   const double* depth_static;  /* device [cells]: static depth d_s */
@@ -119,9 +125,11 @@ typedef struct {
 
 typedef struct {
   int64_t n_active;         /* cells in the non-hydrostatic area of the last step */
-  int32_t iters;            /* PCG iterations (2D) / refinement sweeps of the last step */
+  int32_t iters;            /* PCG iterations (2D) / refinement sweeps of the last step
+                               (1D fused: the most sweeps any tile took) */
   int32_t status;           /* swe_nh_status of the last step(s) (first failure wins) */
-  double rel_res;           /* ||b - A p|| / ||b|| of the last solve (when computed) */
+  double rel_res;           /* ||b - A p|| / ||b|| of the last solve (when computed; 1D
+                               fused refinement: the largest tile backward error) */
   double dt;                /* time step of the last step (channel 0) */
   double t;                 /* time after the last step (channel 0) */
   int64_t steps;            /* steps taken since init */
@@ -138,7 +146,7 @@ size_t swe_nh_workspace_bytes(const swe_nh_config* cfg);
  * hipStream_t (NULL = the default stream).  The workspace must outlive the
  * context.  Returns SWE_NH_EINVAL / SWE_NH_ENOMEM / SWE_NH_EHIP on failure.
  *
- * The 1D FP64 fused step of a grid of at most 512 tiles whose blocks all fit
+ * The 1D fused step of a grid of at most 512 tiles whose blocks all fit
  * on the device at once runs as one kernel whose blocks exchange tagged
  * words (the 2D solver's iterations do the same); such kernels assume that
  * no other long-running kernel holds the device's compute units while they
@@ -282,7 +290,7 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double
  * per-launch cost is not counted; nreps is rounded up to a multiple of the
  * graph's length.  The state arrays must hold a valid state of
  * the context (for instance after swe_nh_step).
- * 1D with precision 0 and enlarge <= 8 (the fused step): stage 0 the fused
+ * 1D with enlarge <= 8 (the fused step, either precision): stage 0 the fused
  * step kernel (predictor, criterion, assembly, tile reduction; in the
  * one-kernel step of grids of at most 512 tiles also the level-1 solve and
  * the projection), 1 the separate level-1 solve, 2 the projection kernel

@@ -3,8 +3,8 @@
 The 1D stencil, criterion and compaction kernels work on tiles whose LDS
 windows hold 128, 256 or 512 cells; which tile is fastest depends on the packed
 length and on how the tiles spread over the 256 compute units (short channels
-favour small tiles, long ensembles large ones).  The FP64 fused step widens a
-tile by 6 + e cells on each side (e = enlargement), so for each capacity the
+favour small tiles, long ensembles large ones).  The fused step (either
+precision) widens a tile by 6 + e cells on each side (e = enlargement), so for each capacity the
 tile of capacity - 2 (6 + e) cells, whose window fills whole wavefronts, is a
 candidate beside the full capacity.  `tune_1d` times whole steps for every
 candidate on a copy of the caller's state and returns the fastest; results are
@@ -28,13 +28,13 @@ import torch
 from . import swe_nh as B
 
 CAPACITIES_1D = (128, 256, 512)
-FUSED_MAX_ENLARGE = 8  # largest enlargement the fused FP64 step handles
+FUSED_MAX_ENLARGE = 8  # largest enlargement the fused step handles
 
 
 def candidates_1d(kw):
     """tile lengths worth timing for the context options `kw`"""
     e = int(kw.get("enlarge", 1))
-    fused = int(kw.get("precision", 0)) == 0 and e <= FUSED_MAX_ENLARGE
+    fused = e <= FUSED_MAX_ENLARGE
     out = []
     for cap in CAPACITIES_1D:
         if fused:

@@ -734,6 +734,14 @@ struct StepSmem {
     struct {
       double a[RW], b[RW], c[RW], d[3][RW], r[RW];  // r = 1 / b
     } s[NB];  // tile system (the reduction alternates between NB buffers)
+    struct {
+      float a[RW], b[RW], c[RW], r[RW];  // FP32 tile system, r = 1 / b
+      float d[2][3][RW];                 // right-hand sides, alternating by level
+      double x[3][RW];                   // FP64 solution, by row
+      double ends[8];                    // FP64 first and last rows before pinning
+      double red[1][NT / 64];            // block maxima
+      double red6[6][NT / 64];
+    } g;  // FP32 reduction with FP64 refinement
   } u;
   uint8_t raw[T + 2 + 2 * EMAXF];
   uint8_t mk[T + 2];
@@ -912,6 +920,263 @@ __device__ int pcr_tile(StepSmem<T, NT>& S, int m) {
   }
   return cur;
 }
+// ---- FP32 tile reduction with FP64 refinement ----
+// The pinned tile system M X = D (three right-hand sides: the tile's rows and
+// unit vectors at its first and last row) is reduced in FP32 by the parallel
+// cyclic reduction of pcr_tile, which keeps each level's two elimination
+// factors of every row in registers, so that a later right-hand side needs
+// only two products per level and column.  Classical iterative refinement
+// follows: R = D - M X from the FP64 rows, E = M^-1 R with the FP32 factors,
+// X += E in FP64, until the normwise backward error of every column,
+// max_j |R_j| / max_j (|M| |X| + |D|)_j over the unpinned rows (the pinned
+// rows' residuals are zero), is at most tol (the measure of
+// Rigal and Gaches 1967; a backward-stable solve reaches the unit roundoff,
+// whatever the condition number).  The tile's own column is refined scaled
+// by the power of two that brings its largest right-hand side to [1, 2)
+// (exact, and undone at the end), and every residual goes to FP32 scaled the
+// same way: far from the slide the right-hand sides can lie below FP32's
+// range, and even in FP64's subnormal range, where no residual could be
+// computed to a relative accuracy.  In the reduction thread t
+// owns rows RPT t .. RPT t + RPT - 1; in the residual, the rows of its marked
+// cells (rank[q]).  On return u.g.x holds the FP64 basis columns z, u, v by
+// row and u.g.ends the FP64 first row (b, c, d) and last row (a, b, c, d)
+// before pinning; returns the sweeps taken, or -1 - sweeps when tol was not
+// reached in max_sweeps.
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int RW>
+constexpr int levels_of() {
+  int l = 0;
+  while ((1 << l) < RW) l++;
+  return l;
+}
+
+// exponent e with 2^e <= v < 2^(e+1) (0 for v == 0)
+__device__ __forceinline__ int exp2_of(double v) { return v > 0.0 ? ilogb(v) : 0; }
+
+// block maxima of the thread's values v[0..N) (all threads get them; one barrier)
+template <int NT, int N>
+__device__ __forceinline__ void block_max(double (&v)[N], double (*red)[NT / 64]) {
+#pragma unroll
+  for (int k = 0; k < N; k++) v[k] = wave_max(v[k]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < N; k++) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; k++) {
+    v[k] = red[k][0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; w++) v[k] = fmax(v[k], red[k][w]);
+  }
+}
+
+template <int T, int NT>
+__device__ int refine_tile32(StepSmem<T, NT>& S, int m, const double (&ra)[T / NT],
+                             const double (&rb)[T / NT], const double (&rc)[T / NT],
+                             const double (&rd)[T / NT], const int (&rank)[T / NT],
+                             const bool (&on)[T / NT], double tol, int max_sweeps,
+                             double& berr_out) {
+  constexpr int RW = StepSmem<T, NT>::RW, RPT = RW / NT, LV = levels_of<RW>(), QN = T / NT;
+  auto& G = S.u.g;
+  // identity rows, and the largest right-hand side of the tile's own rows
+  double dmax[1] = {0.0};
+#pragma unroll
+  for (int q = 0; q < QN; q++)
+    if (on[q] && rank[q] != 0 && rank[q] != m - 1) dmax[0] = fmax(dmax[0], fabs(rd[q]));
+  for (int j = threadIdx.x; j < RW; j += NT) {
+    G.a[j] = 0.0f;
+    G.b[j] = 1.0f;
+    G.c[j] = 0.0f;
+    G.r[j] = 1.0f;
+    G.d[0][0][j] = 0.0f;
+    G.d[0][1][j] = j == 0 ? 1.0f : 0.0f;
+    G.d[0][2][j] = j == m - 1 ? 1.0f : 0.0f;
+  }
+  block_max<NT, 1>(dmax, G.red);  // its barrier also orders the identity rows
+  const int e0 = exp2_of(dmax[0]);
+#pragma unroll
+  for (int q = 0; q < QN; q++) {
+    if (!on[q]) continue;
+    const int j = rank[q];
+    if (j == 0) {
+      G.ends[0] = rb[q];
+      G.ends[1] = rc[q];
+      G.ends[2] = rd[q];
+    } else if (j == m - 1) {
+      G.ends[3] = ra[q];
+      G.ends[4] = rb[q];
+      G.ends[5] = rc[q];
+      G.ends[6] = rd[q];
+    } else {
+      const float bj = (float)rb[q];
+      G.a[j] = (float)ra[q];
+      G.b[j] = bj;
+      G.c[j] = (float)rc[q];
+      G.r[j] = rcp32(bj);
+      G.d[0][0][j] = (float)ldexp(rd[q], -e0);  // exact while the scaled value is normal
+    }
+  }
+  __syncthreads();
+  // FP32 reduction of the matrix and the three columns, factors kept
+  float k1[RPT][LV], k2[RPT][LV];
+  int cur = 0;
+#pragma unroll
+  for (int lv = 0; lv < LV; lv++) {
+    const int s = 1 << lv;
+#pragma unroll
+    for (int jj = 0; jj < RPT; jj++) k1[jj][lv] = k2[jj][lv] = 0.0f;
+    if (s >= m) continue;  // m is the same for the whole block
+    float na[RPT], nb[RPT], nc[RPT], nd[RPT][3];
+#pragma unroll
+    for (int jj = 0; jj < RPT; jj++) {
+      const int i = RPT * threadIdx.x + jj, im = i - s, ip = i + s;
+      float bi = G.b[i], ai = 0.0f, ci = 0.0f;
+      float di[3] = {G.d[cur][0][i], G.d[cur][1][i], G.d[cur][2][i]};
+      if (im >= 0) {
+        const float f = G.a[i] * G.r[im];
+        k1[jj][lv] = f;
+        ai = -G.a[im] * f;
+        bi -= G.c[im] * f;
+#pragma unroll
+        for (int r = 0; r < 3; r++) di[r] -= G.d[cur][r][im] * f;
+      }
+      if (ip < RW) {
+        const float f = G.c[i] * G.r[ip];
+        k2[jj][lv] = f;
+        ci = -G.c[ip] * f;
+        bi -= G.a[ip] * f;
+#pragma unroll
+        for (int r = 0; r < 3; r++) di[r] -= G.d[cur][r][ip] * f;
+      }
+      na[jj] = ai;
+      nb[jj] = bi;
+      nc[jj] = ci;
+#pragma unroll
+      for (int r = 0; r < 3; r++) nd[jj][r] = di[r];
+    }
+    __syncthreads();  // the matrix is reduced in place: all reads before any write
+#pragma unroll
+    for (int jj = 0; jj < RPT; jj++) {
+      const int i = RPT * threadIdx.x + jj;
+      G.a[i] = na[jj];
+      G.b[i] = nb[jj];
+      G.c[i] = nc[jj];
+      G.r[i] = rcp32(nb[jj]);
+#pragma unroll
+      for (int r = 0; r < 3; r++) G.d[cur ^ 1][r][i] = nd[jj][r];
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  float rbf[RPT];
+  double X[RPT][3];
+#pragma unroll
+  for (int jj = 0; jj < RPT; jj++) {
+    const int i = RPT * threadIdx.x + jj;
+    rbf[jj] = G.r[i];
+#pragma unroll
+    for (int r = 0; r < 3; r++) X[jj][r] = (double)(G.d[cur][r][i] * rbf[jj]);  // column 0 scaled
+  }
+  int sweeps = 0;
+  double berr = 0.0;
+  for (;;) {
+#pragma unroll
+    for (int jj = 0; jj < RPT; jj++)
+#pragma unroll
+      for (int r = 0; r < 3; r++) G.x[r][RPT * threadIdx.x + jj] = X[jj][r];
+    __syncthreads();
+    // FP64 residual of the thread's marked rows (per column the largest |R_j|
+    // and (|M| |X| + |D|)_j), computed again after the reduction, when it
+    // goes to FP32 scaled, rather than kept in registers across it
+    auto resid = [&](int q, int r, double& den) {
+      const int j = rank[q];
+      const double dj = j == 0 ? (r == 1 ? 1.0 : 0.0)
+                               : j == m - 1 ? (r == 2 ? 1.0 : 0.0)
+                                            : (r == 0 ? ldexp(rd[q], -e0) : 0.0);
+      if (j == 0 || j == m - 1) {
+        den = 0.0;  // the pinned rows' scale is arbitrary (and their residual zero)
+        return dj - G.x[r][j];
+      }
+      const double t0 = ra[q] * G.x[r][j - 1], t1 = rb[q] * G.x[r][j], t2 = rc[q] * G.x[r][j + 1];
+      den = fabs(t0) + fabs(t1) + fabs(t2) + fabs(dj);
+      return dj - t0 - t1 - t2;
+    };
+    double mx[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) mx[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < QN; q++) {
+      if (!on[q]) continue;
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        double den;
+        const double rv = resid(q, r, den);
+        mx[r] = fmax(mx[r], fabs(rv));
+        mx[3 + r] = fmax(mx[3 + r], den);
+      }
+    }
+    block_max<NT, 6>(mx, G.red6);
+    berr = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+      if (mx[r] > 0.0) berr = fmax(berr, mx[r] / mx[3 + r]);
+    if (berr <= tol || sweeps >= max_sweeps) break;
+    // the residuals, scaled per column, as FP32 right-hand sides
+    int er[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) er[r] = exp2_of(mx[r]);
+#pragma unroll
+    for (int q = 0; q < QN; q++) {
+      if (!on[q]) continue;
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        double den;
+        G.d[cur][r][rank[q]] = (float)ldexp(resid(q, r, den), -er[r]);
+      }
+    }
+    __syncthreads();
+    // E = M^-1 R with the kept factors (the pinned rows' residuals are zero)
+#pragma unroll
+    for (int lv = 0; lv < LV; lv++) {
+      const int s = 1 << lv;
+      if (s >= m) continue;
+      float nd[RPT][3];
+#pragma unroll
+      for (int jj = 0; jj < RPT; jj++) {
+        const int i = RPT * threadIdx.x + jj, im = i - s, ip = i + s;
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+          float v = G.d[cur][r][i];
+          if (im >= 0) v -= G.d[cur][r][im] * k1[jj][lv];
+          if (ip < RW) v -= G.d[cur][r][ip] * k2[jj][lv];
+          nd[jj][r] = v;
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < RPT; jj++)
+#pragma unroll
+        for (int r = 0; r < 3; r++) G.d[cur ^ 1][r][RPT * threadIdx.x + jj] = nd[jj][r];
+      __syncthreads();
+      cur ^= 1;
+    }
+#pragma unroll
+    for (int jj = 0; jj < RPT; jj++)
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+        X[jj][r] += ldexp((double)(G.d[cur][r][RPT * threadIdx.x + jj] * rbf[jj]), er[r]);
+    sweeps++;
+  }
+  // the tile's own column back to its scale (the caller reads u.g.x after a
+  // barrier of its own)
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < RPT; jj++) G.x[0][RPT * threadIdx.x + jj] = ldexp(X[jj][0], e0);
+  __syncthreads();
+  berr_out = berr;
+  return berr <= tol ? sweeps : -1 - sweeps;
+}
+
 // Tridiagonal solve of n <= 64 rows held one per lane of the calling
 // wavefront (a: sub-, b: main, c: super-diagonal, d: right-hand side; lanes
 // at or beyond n hold identity rows): parallel cyclic reduction with
@@ -1194,7 +1459,7 @@ __device__ void onepass_block0(const K1D& P, int par, unsigned tag) {
 // (Eqs. 10-17) and their reduction to the two level-1 rows.  ONE: the
 // one-kernel step, which goes on to the level-1 solve and the
 // projection of the marked cells (Eqs. 10-11), as the projection kernel does.
-template <int T, int NT, bool ONE>
+template <int T, int NT, bool ONE, bool F32R>
 __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restrict__ h,
                                                const double* __restrict__ hu,
                                                const double* __restrict__ hw,
@@ -1216,6 +1481,10 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     P.step[par ^ 1] = step + 1;
     P.n_acc[par ^ 1] = 0;  // counts the next step
+    if constexpr (F32R) {
+      P.sweeps[par ^ 1] = 0;
+      P.berr[par ^ 1] = 0ull;
+    }
   }
   const int ee = P.enlarge, HL = 6 + ee, W = P.tile + 2 * HL;
   const int lo = start - HL;  // window cell w <-> channel cell lo + w
@@ -1541,6 +1810,41 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
       P.zw[cz + ZW_Z * zs] = 0.0;
       P.zw[cz + ZW_U * zs] = asL ? 0.0 : 1.0;
       P.zw[cz + ZW_V * zs] = asL ? 1.0 : 0.0;
+    }
+  } else if constexpr (F32R) {
+    double berr;
+    const int sw = refine_tile32<T, NT>(S, m, ra, rb, rc, rd, rank, on, P.tol, P.max_sweeps, berr);
+    if (threadIdx.x == 0) {
+      atomicMax(&P.sweeps[par], sw < 0 ? -1 - sw : sw);
+      atomicMax(&P.berr[par], pos_bits(berr));
+      if (sw < 0) atomicOr(P.status, ST_NOCONV);
+    }
+    const auto& GX = S.u.g.x;
+    if constexpr (ONE) {
+#pragma unroll
+      for (int q = 0; q < T / NT; q++) {
+        if (!on[q]) continue;
+        const int j = rank[q];
+        zr[q][ZW_Z] = GX[0][j];
+        zr[q][ZW_U] = GX[1][j];
+        zr[q][ZW_V] = GX[2][j];
+      }
+    } else {
+      for (int j = threadIdx.x; j < m; j += NT) {
+        const int64_t cz = pb + S.cell_of[j];
+        P.zw[cz + ZW_Z * zs] = GX[0][j];
+        P.zw[cz + ZW_U * zs] = GX[1][j];
+        P.zw[cz + ZW_V * zs] = GX[2][j];
+      }
+    }
+    if (threadIdx.x == 0) {
+      const double* E = S.u.g.ends;
+      l1v[0] = E[0] + E[1] * GX[1][1];
+      l1v[1] = E[1] * GX[2][1];
+      l1v[2] = E[2] - E[1] * GX[0][1];
+      l1v[3] = E[4] + E[3] * GX[2][m - 2];
+      l1v[4] = E[5];
+      l1v[5] = E[6] - E[3] * GX[0][m - 2];
     }
   } else {
     // keep the end rows, then pin them: x_first and x_last become parameters
@@ -1921,7 +2225,13 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
 __global__ void k_run_begin(K1D P) {
   for (int i = threadIdx.x; i < 2 * P.nch * P.nslot; i += blockDim.x)
     P.smax[(size_t)i * SPEED_PAD] = 0ull;
-  if (threadIdx.x == 0) P.n_acc[0] = 0;
+  if (threadIdx.x == 0) {
+    P.n_acc[0] = 0;
+    if (P.refine) {
+      P.sweeps[0] = 0;
+      P.berr[0] = 0ull;
+    }
+  }
 }
 
 // end of a run of fused steps: time, step counter and the speed of the new
@@ -1936,6 +2246,10 @@ __global__ void k_run_end(K1D P, int last_par) {
   if (threadIdx.x == 0) {
     if (last_par) P.step[0] = P.step[1];
     *P.n_act = P.n_acc[last_par ^ 1];
+    if (P.refine) {  // the last step's refinement: most sweeps, largest backward error
+      *P.iters_out = P.sweeps[last_par ^ 1];
+      *P.rel_out = __longlong_as_double((long long)P.berr[last_par ^ 1]);
+    }
   }
 }
 
@@ -2072,29 +2386,43 @@ template <int T, int NT>
 static void launch_step_t(const K1D& P, const double* h, const double* hu, const double* hw,
                           double* hn, double* hun, double* hwn, uint8_t* mask, double* p, int par,
                           hipStream_t s) {
-  if (P.onepass)
-    hipLaunchKernelGGL((k_step1d<T, NT, true>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn,
-                       hun, hwn, mask, p, par);
-  else
-    hipLaunchKernelGGL((k_step1d<T, NT, false>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu, hw, hn,
-                       hun, hwn, mask, p, par);
+  if (P.onepass) {
+    if (P.refine)
+      hipLaunchKernelGGL((k_step1d<T, NT, true, true>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu,
+                         hw, hn, hun, hwn, mask, p, par);
+    else
+      hipLaunchKernelGGL((k_step1d<T, NT, true, false>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu,
+                         hw, hn, hun, hwn, mask, p, par);
+  } else {
+    if (P.refine)
+      hipLaunchKernelGGL((k_step1d<T, NT, false, true>), dim3(P.ntiles), dim3(NT), 0, s, P, h,
+                         hu, hw, hn, hun, hwn, mask, p, par);
+    else
+      hipLaunchKernelGGL((k_step1d<T, NT, false, false>), dim3(P.ntiles), dim3(NT), 0, s, P, h,
+                         hu, hw, hn, hun, hwn, mask, p, par);
+  }
 }
 // blocks of the one-kernel step kernel that fit on the device at once
-template <int T, int NT>
+template <int T, int NT, bool F32R>
 static int onepass_resident_t() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step1d<T, NT, true>, NT, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step1d<T, NT, true, F32R>, NT, 0) !=
       hipSuccess)
     return 0;
   return cus * per_cu;
 }
 int onepass_resident(const K1D& P) {
-  if (P.cap == 128) return onepass_resident_t<128, 128>();
-  if (P.cap == 256) return onepass_resident_t<256, 256>();
-  return onepass_resident_t<512, 256>();
+  if (P.refine) {
+    if (P.cap == 128) return onepass_resident_t<128, 128, true>();
+    if (P.cap == 256) return onepass_resident_t<256, 256, true>();
+    return onepass_resident_t<512, 256, true>();
+  }
+  if (P.cap == 128) return onepass_resident_t<128, 128, false>();
+  if (P.cap == 256) return onepass_resident_t<256, 256, false>();
+  return onepass_resident_t<512, 256, false>();
 }
 void launch_step1d(const K1D& P, const double* h, const double* hu, const double* hw, double* hn,
                    double* hun, double* hwn, uint8_t* mask, double* p, int par, hipStream_t s) {

@@ -138,7 +138,7 @@ int64_t total_cells(const swe_nh_config* c) {
 int n_channels(const swe_nh_config* c) { return c->dim == 2 ? 1 : c->batch; }
 
 bool fused_step(const swe_nh_config* c) {
-  return c->dim == 1 && c->precision == 0 && c->enlarge <= fused_max_enlarge();
+  return c->dim == 1 && c->enlarge <= fused_max_enlarge();
 }
 
 // cells per 1D tile: the configured number, else a window capacity of 128
@@ -256,6 +256,8 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
       P.tw = cv.take<unsigned long long>(17 * (size_t)ntiles);
       P.tag1 = cv.take<unsigned>(1);
       P.l1s = cv.take<double>(4 * (size_t)ntiles);
+      P.sweeps = cv.take<int>(2);
+      P.berr = cv.take<unsigned long long>(2);
     }
     x->nparts = resid_blocks(N);
     x->part = cv.take<double>(x->nparts);
@@ -467,6 +469,11 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.fused = fused_step(cfg) ? 1 : 0;
   P.onepass = 0;
   P.keep_speed = 0;
+  P.refine = (P.fused && cfg->precision == 1) ? 1 : 0;
+  P.max_sweeps = cfg->max_iter;
+  P.tol = cfg->tol;
+  P.iters_out = c->iters;
+  P.rel_out = c->rel;
   const int n1 = 2 * P.ntiles;
   std::vector<double> zeros(c->nch, 0.0);
   std::vector<unsigned long long> zu(speed_at(2 * c->nch, 0, P.nslot), 0ull);
@@ -493,6 +500,8 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
     if (rc == SWE_NH_OK && hipMemset(P.tw, 0, 17 * sizeof(unsigned long long) * P.ntiles) != hipSuccess)
       rc = SWE_NH_EHIP;
     INIT_COPY(P.tag1, zi, sizeof(unsigned));
+    INIT_COPY(P.sweeps, zi, 2 * sizeof(int));
+    INIT_COPY(P.berr, zi, 2 * sizeof(unsigned long long));
     // the one-kernel step when its blocks all fit on the device at once (block
     // 0 waits for every tile's count; the marked tiles wait for block 0)
     const char* env = std::getenv("SWE_NH_ONEPASS");

@@ -62,6 +62,19 @@ struct K1D {
   // l1s: [2][2 ntiles] scratch of block 0's sequential solve
   int onepass;
   int keep_speed;  // stage timing: block 0 leaves the speed buffer the step read in place
+  // FP32 inner solve with FP64 refinement in the tile-fused step (refine = 1):
+  // each tile's interior system is reduced in FP32 and refined with FP64
+  // residuals until its componentwise backward error is at most tol, in at
+  // most max_sweeps sweeps; sweeps / berr: [2] by step parity, the largest
+  // sweep count and backward error (bit pattern) of the step's tiles;
+  // iters_out / rel_out receive the last step's at the end of a run
+  int refine;
+  int max_sweeps;
+  double tol;
+  int* sweeps;
+  unsigned long long* berr;
+  int* iters_out;
+  double* rel_out;
   unsigned long long* tw;
   unsigned* tag1;
   double* l1s;

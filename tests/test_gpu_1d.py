@@ -357,9 +357,8 @@ def test_stage_timing_leaves_the_run_unchanged(B, precision, step_mode):
     """swe_nh_time_stage replays each stage from a graph (nreps 3 and 70,
     the latter rounded up to two graphs of 50).  On the fused path the
     stages write only workspace scratch, so the state and a continued run
-    are bit-identical to a run that was never timed; the unfused stages
-    reuse the step's workspace and may rewrite the state, so there only the
-    times are checked"""
+    are bit-identical to a run that was never timed (both precisions run the
+    fused step)"""
     case = S.random_case_1d(9000, seed=4)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, cfl=0.4, precision=precision)
     ref = run_gpu(B, case, 20, **kw)
@@ -375,8 +374,6 @@ def test_stage_timing_leaves_the_run_unchanged(B, precision, step_mode):
             us = ctx.time_stage(stage, nreps, h, hu, None, hw, p)
             # the one-kernel step has no separate level-1 solve or projection (0)
             assert (0.0 <= us if stage in (1, 2) else 0.0 < us) and us < 1e5
-    if precision:
-        return
     for x, y in zip((h, hu, hw, p), snap):
         assert torch.equal(x, y)
     ctx.step(h, hu, None, hw, p, nsteps=10)
@@ -403,10 +400,14 @@ def test_empty_area_and_status_codes(B):
     assert st["status"] == B.ENAN
 
 
-def test_refinement_reports_noconvergence(B):
+@pytest.mark.parametrize("enlarge", [1, 9])
+def test_refinement_reports_noconvergence(B, enlarge):
+    """an unreachable tolerance: the fused step's tile refinement (enlarge 1)
+    and the unfused packed solve's refinement (enlarge 9, beyond the fused
+    window) both stop after max_iter sweeps and report ENOCONV"""
     case = S.slide_case(n=4096, dx=0.005)
     _, st, *_ = run_gpu(B, case, 3, crit=S.CRIT_GLOBAL, cfl=0.5, precision=1, tol=1e-30,
-                        max_iter=2)
+                        max_iter=2, enlarge=enlarge)
     assert st["status"] == B.ENOCONV and st["iters"] == 2
 
 
@@ -465,13 +466,16 @@ def test_level1_solve_regimes(B, ntiles, step_mode):
         assert rel(g, r) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("ntiles", [70, 300])
-def test_many_marked_tiles(B, ntiles, step_mode):
+def test_many_marked_tiles(B, ntiles, precision, step_mode):
     """more than 64 marked tiles under an adaptive criterion (tiles of 37
     cells, a low threshold marks nearly every tile): the one-kernel form's
-    Thomas sweep in block 0"""
+    Thomas sweep in block 0; with the FP32 tile reduction the refinement
+    reaches the FP64 bar too"""
     case = S.random_case_1d(37 * ntiles - 11, seed=90 + ntiles, dx=0.05)
-    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-4, enlarge=1, cfl=0.45, tile1d=37)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-4, enlarge=1, cfl=0.45, tile1d=37, precision=precision,
+              tol=1e-12, max_iter=8)
     ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 6, **kw)
     assert st["status"] == 0
     ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(6)
@@ -498,6 +502,53 @@ def test_level1_two_rows_per_lane_across_channels(B, step_mode):
             assert rel(g, r) <= 1e-10, j
 
 
+@pytest.mark.parametrize("tile", [128, 256, 512, 114, 242, 37])
+def test_fused_fp32_refinement_tiles(B, tile, step_mode):
+    """the fused step with each tile's interior system reduced in FP32 and
+    refined with FP64 residuals (tol 1e-12 on the componentwise backward
+    error) on ragged channels: every field within 1e-8 of the FP64 oracle,
+    far inside the 1e-6 bar of the FP32 path, and at least one sweep taken
+    (FP32 alone does not reach the tolerance)"""
+    ens = ens_small(LENGTHS + [tile, tile + 1, 2 * tile - 1], seed=18)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=1, cfl=0.45, tile1d=tile, precision=1,
+              tol=1e-12, max_iter=8)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 15, **kw)
+    assert st["status"] == 0, st
+    assert 1 <= st["iters"] <= 8 and 0.0 < st["rel_res"] <= 1e-12, st
+    o = ens.offsets
+    total = 0
+    for j, c in enumerate(ens.channels):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.45).step(15)
+        sl = slice(o[j], o[j + 1])
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), j
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= 1e-8, j
+        if ref.last_active:
+            assert rel(p[sl], ref.p) <= 1e-8, j
+        total += ref.last_active
+    assert st["n_active"] == total > 0
+
+
+def test_fused_fp32_refinement_stops_at_tol(B):
+    """a loose tolerance is met by the FP32 reduction alone (no sweep), a
+    tight one needs sweeps and then meets the FP32 path's bar, which the
+    FP32 reduction alone does not"""
+    case = S.slide_case(n=32768, dx=0.005)
+    res = {}
+    for tol in (1e-2, 1e-13):
+        kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=1, tol=tol,
+                  max_iter=8)
+        ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 200, **kw)
+        assert st["status"] == 0, st
+        res[tol] = (st, hu.cpu().numpy(), p.cpu().numpy())
+    assert res[1e-2][0]["iters"] == 0 and res[1e-2][0]["rel_res"] <= 1e-2
+    assert res[1e-13][0]["iters"] >= 2 and res[1e-13][0]["rel_res"] <= 1e-13
+    ref = O.Sim1D(case, phys_of(kw), cfl=0.5).step(200)
+    e_loose = rel(res[1e-2][2], ref.p)
+    e_tight = max(rel(res[1e-13][1], ref.hu), rel(res[1e-13][2], ref.p))
+    assert e_tight <= 1e-8 < 1e-6 < e_loose <= 1e-3, (e_tight, e_loose)
+
+
 @pytest.mark.parametrize("n,tile", [(70000, 128), (300000, 128), (40000, 114)])
 def test_fused_step_large_grids(B, n, tile):
     """level-1 system beyond the projection kernel's own solve (more than 512
@@ -515,10 +566,11 @@ def test_fused_step_large_grids(B, n, tile):
 
 
 def test_unfused_kernels_below_capacity(B):
-    """the stage kernels of the FP32 path with tiles shorter than their LDS
-    window (200 cells in a 256-cell window) on ragged channels"""
+    """the stage kernels of the unfused FP32 path (an enlargement beyond the
+    fused step's window keeps it) with tiles shorter than their LDS window
+    (200 cells in a 256-cell window) on ragged channels"""
     ens = ens_small(LENGTHS + [200, 201, 399], seed=9)
-    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=1, cfl=0.45, tile1d=200, precision=1,
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, enlarge=9, cfl=0.45, tile1d=200, precision=1,
               tol=1e-12, max_iter=8)
     ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 9, **kw)
     assert st["status"] == 0
@@ -545,13 +597,15 @@ def test_wide_enlargement_uses_the_unfused_step(B):
 
 
 def test_unfused_path_beyond_one_pass_of_its_grids(B):
-    """the FP32 solve with FP64 refinement with every cell of 1.2M marked:
-    more marked rows than the row kernels' capped grid covers in one pass
-    (2048 blocks of 256), more 1024-row chunks than a tridiagonal level's
-    blocks (1024), and tile counts spanning two chunks of the scan"""
+    """the unfused FP32 solve with FP64 refinement (enlargement beyond the
+    fused window) with every cell of 1.2M marked: more marked rows than the
+    row kernels' capped grid covers in one pass (2048 blocks of 256), more
+    1024-row chunks than a tridiagonal level's blocks (1024), and tile counts
+    spanning two chunks of the scan"""
     n = 1_200_000
     case = S.random_case_1d(n, seed=41, dx=0.05)
-    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.45, precision=1, tol=1e-12, max_iter=8, tile1d=242)
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.45, precision=1, tol=1e-12, max_iter=8, tile1d=242,
+              enlarge=9)
     ctx, st, h, hu, hw, p, mask = run_gpu(B, case, 2, **kw)
     assert st["status"] == 0, st
     ref = O.Sim1D(case, phys_of(kw), cfl=0.45).step(2)
