@@ -751,6 +751,12 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
 // ---------------------------------------------------------------------------
 // persistent PCG with FP64 refinement
 // ---------------------------------------------------------------------------
+// An inner solve also ends when its recursively updated residual has not
+// fallen by 10% for STALL_ITERS iterations: rounding in the recurrences
+// (pipelined CG in FP32 above all) can hold it above the inner target for
+// good, and the FP64 residual of the next refinement sweep then restarts it.
+constexpr int STALL_ITERS = 50;
+
 // The inner solve is pipelined CG with a tile-block preconditioner
 // (symmetric red-black SOR on each tile's own block of A); see k_pcg2d.
 //
@@ -1237,6 +1243,8 @@ __device__ void pcg_cg(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2])
     const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
                                             : 0.5 * A.tol * sqrt(bb);
     double gam = 0.0, alpha = 0.0, beta = 0.0;
+    double rbest = 0.0;  // stall guard, as in the pipelined solver
+    int ibest = 0;
     for (int it = 0;; it++) {
       const R al = (R)alpha, bt = (R)beta;
       double v[3] = {0.0, 0.0, 0.0};  // (r,u), (r,r), (w,u)
@@ -1285,9 +1293,14 @@ __device__ void pcg_cg(const PcgArgs<R>& A, const Share& S, int G, R (*zt)[TX2])
       double tt[3];
       grid_totals<3>(part_buf(A.part, k), G, tt);
       const double gn = tt[0], rn = tt[1], dn = tt[2];
+      if (it == 0 || rn < 0.81 * rbest) {
+        rbest = rn;
+        ibest = it;
+      }
       if (it > 0) {
         total++;
         if (sqrt(rn) <= tol_abs || total >= A.max_iter || !(gn == gn)) break;
+        if (it - ibest >= STALL_ITERS) break;
       }
       if (it == 0) {
         alpha = dn != 0.0 ? gn / dn : 0.0;
@@ -1663,6 +1676,8 @@ __device__ unsigned pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R 
     const double tol_abs = (sizeof(R) == 4) ? fmax(A.tol_in * sqrt(rr), 0.5 * A.tol * sqrt(bb))
                                             : 0.5 * A.tol * sqrt(bb);
     double gam = 0.0, alpha = 0.0, beta = 0.0;
+    double rbest = 0.0;  // stall guard: the smallest ||r_j||^2 that cut the last best by 10%
+    int jbest = 0;
     R hv[K][2][4];  // m of the last pass outside the tiles (gathered at its end)
     for (int j = 0;; j++) {
       // pass j: (j >= 1) n = A m_{j-1} and the recurrences with alpha_{j-1},
@@ -1730,9 +1745,17 @@ __device__ unsigned pcg_pipelined(const PcgArgs<R>& A, const Share& S, int G, R 
       cm.n = (R)c5[3];
       cm.s = (R)c5[4];
       const double gn = tt[0], dn = tt[1], rn = tt[2];
+      if (j == 0 || rn < 0.81 * rbest) {
+        rbest = rn;
+        jbest = j;
+      }
       if (j > 0) {
         total++;
         if (sqrt(rn) <= tol_abs || total >= A.max_iter || !(gn == gn)) break;
+        // the recursively updated residual has stalled (rounding in the
+        // recurrences, worst in FP32): end this inner solve, and the FP64
+        // residual of the next sweep restarts it
+        if (j - jbest >= STALL_ITERS) break;
       }
       if (j == 0) {
         alpha = dn != 0.0 ? gn / dn : 0.0;
