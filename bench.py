@@ -46,8 +46,8 @@ def parse():
     ap.add_argument("--preroll", type=int, default=None,
                     help="ensemble1d: untimed steps before the warm-up (default 2500)")
     ap.add_argument("--workload", default="ensemble1d",
-                    choices=["slide1d", "long1d", "ensemble1d", "shelf2d", "learned2d",
-                             "paper1d", "copycal"])
+                    choices=["ensemble1d", "slide1d", "long1d", "enlarge1d", "shelf2d",
+                             "learned2d", "paper1d", "copycal"])
     ap.add_argument("--tile1d", type=int, default=0,
                     help="1D cells per tile (32..512); 0: pick with the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -246,6 +246,28 @@ def time_run_gpu(B, torch, case, kw, nsteps, reps):
     return float(np.median(times)), h, st
 
 
+def final_state_1d(B, torch, case, kw, nsteps):
+    """the state after nsteps from the case's initial state, and the time per step"""
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = B.context_1d(case, **kw)
+    ctx.set_time(case.t0)
+    h, hu, hw = f(case.h), f(case.hu), f(case.hw)
+    p = torch.zeros_like(h)
+    ctx.step(h, hu, None, hw, p, nsteps=1)  # captures the graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(h, hu, None, hw, p, nsteps=nsteps - 1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = ctx.sync_stats()
+    if st["status"] != 0:
+        raise RuntimeError(f"status {st}")
+    return {"h": h.cpu().numpy(), "hu": hu.cpu().numpy(), "hw": hw.cpu().numpy(),
+            "p": p.cpu().numpy(), "t": st["t"], "n_active": int(st["n_active"]),
+            "ms_per_step": 1e3 * el / max(nsteps - 1, 1)}
+
+
 def time_run_oracle(O, case, ph, dt_fixed, nsteps, reps=3):
     """best of reps whole runs (the first call of the process also loads the library)"""
     best = None
@@ -379,6 +401,43 @@ def main():
                            "cells": n, "tile1d": tile, "autotune_us_per_step": tune_us},
                 "roofline": roof, "cpu_baseline": None, "extra": extra}
         print(json.dumps(line), flush=True)
+    elif args.workload == "enlarge1d":
+        # the enlargement study of Sec. 5.2 at the headline channel's
+        # resolution: the paper enlarges the marked area by one element, while
+        # the non-hydrostatic pressure decays over h / sqrt(3) (the screened
+        # operator's length), about 46 cells of the 32768-cell slide
+        nsteps = args.steps or 4000
+        rows = []
+        setups = [("1D slide, 32768 cells, dx = 5 mm, h0 = 0.4 m", S.slide_case(n=32768, dx=0.005),
+                   0.4, dict(cfl=0.5)),
+                  ("flume of Sec. 4.3, Fr = 0.25, dx = 0.075 m, h0 = 0.175 m",
+                   S.whittaker_case(fr_index=1), 0.175, dict(cfl=0.0, dt_fixed=0.005))]
+        for name, case, h0, tk in setups:
+            e_decay = int(math.ceil(h0 / (math.sqrt(3.0) * case.dx)))
+            res = {}
+            for key, kw in (("global", dict(crit=S.CRIT_GLOBAL, enlarge=1)),
+                            ("e1", dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1)),
+                            (f"e{e_decay}", dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=e_decay))):
+                res[key] = final_state_1d(B, torch, case, dict(kw, **tk), nsteps)
+                log(name, key, res[key]["ms_per_step"], "ms/step")
+            g = res["global"]
+            row = {"setup": name, "steps": nsteps, "t_end": g["t"], "decay_cells": e_decay}
+            for key in res:
+                if key == "global":
+                    continue
+                r = res[key]
+                dh = r["h"] - g["h"]  # = eta - eta_global (same bottom at the same time)
+                row[key] = {"eta_diff_vs_global_m": {"max": float(np.abs(dh).max()),
+                                                     "rms": float(np.sqrt(np.mean(dh ** 2)))},
+                            "rel_l2_vs_global": {f: float(np.linalg.norm(r[f] - g[f]) /
+                                                          max(np.linalg.norm(g[f]), 1e-300))
+                                                 for f in ("hu", "hw", "p")},
+                            "marked_fraction": r["n_active"] / case.n,
+                            "t_local_over_t_global": r["ms_per_step"] / g["ms_per_step"]}
+            row["ms_per_step"] = {k: v["ms_per_step"] for k, v in res.items()}
+            rows.append(row)
+            log(json.dumps(row))
+        print(json.dumps({"workload": "enlarge1d", "setups": rows}), flush=True)
     elif args.workload == "paper1d":
         import oracle as O
         reps = args.steps or 5

@@ -30,7 +30,11 @@ constexpr int H2 = 4;
 constexpr int WX = TX2 + 2 * H2, WY = TY2 + 2 * H2, WN = WX * WY;
 constexpr int R1X = TX2 + 4, R1Y = TY2 + 4, R1N = R1X * R1Y;
 constexpr int NFACE = ((R1X + 1) * R1Y > R1X * (R1Y + 1)) ? (R1X + 1) * R1Y : R1X * (R1Y + 1);
-constexpr int QMAX = (R1N + NT2 - 1) / NT2;
+constexpr int NTP = 512;  // threads of the predictor kernel
+constexpr int QMAX = (R1N + NTP - 1) / NTP;
+// slope cells of one direction of a stage: the region widened by one cell
+// across the faces' direction
+constexpr int NSLOPE = ((R1X + 2) * R1Y > R1X * (R1Y + 2)) ? (R1X + 2) * R1Y : R1X * (R1Y + 2);
 constexpr int TN = TX2 * TY2;
 constexpr int MAXE2 = 64;
 
@@ -195,41 +199,21 @@ __device__ __forceinline__ Flux2 rusanov2d(double g, double eL, double mL, doubl
 
 struct P2 {
   double e[WN], m[WN], n[WN], k[WN], d0[WN], d1[WN];
-  double F0[NFACE], F1[NFACE], F2[NFACE], F3[NFACE], F4[NFACE];
+  // minmod slopes of one direction (eta, normal and tangential momentum, hw,
+  // depth) on the slope cells, then, in the same space, the face fluxes
+  union {
+    double sl[5][NSLOPE];
+    double F[5][NFACE];
+  } u;
 };
 
 __device__ __forceinline__ int W(int i, int j) { return j * WX + i; }
 
-// face of the window between cells wl and wr (step s: 1 along x, WX along y)
-__device__ __forceinline__ Flux2 face2d(const P2& S, const double* d, double g, int wl, int wr,
-                                        int s, bool xdir) {
-  const double* nm = xdir ? S.m : S.n;  // normal momentum
-  const double* t1 = xdir ? S.n : S.m;  // tangential momentum
-  const double sel = minmod(S.e[wl] - S.e[wl - s], S.e[wl + s] - S.e[wl]);
-  const double sml = minmod(nm[wl] - nm[wl - s], nm[wl + s] - nm[wl]);
-  const double sal = minmod(t1[wl] - t1[wl - s], t1[wl + s] - t1[wl]);
-  const double skl = minmod(S.k[wl] - S.k[wl - s], S.k[wl + s] - S.k[wl]);
-  const double sdl = minmod(d[wl] - d[wl - s], d[wl + s] - d[wl]);
-  const double ser = minmod(S.e[wr] - S.e[wr - s], S.e[wr + s] - S.e[wr]);
-  const double smr = minmod(nm[wr] - nm[wr - s], nm[wr + s] - nm[wr]);
-  const double sar = minmod(t1[wr] - t1[wr - s], t1[wr + s] - t1[wr]);
-  const double skr = minmod(S.k[wr] - S.k[wr - s], S.k[wr + s] - S.k[wr]);
-  const double sdr = minmod(d[wr] - d[wr - s], d[wr + s] - d[wr]);
-  const double eL = S.e[wl] + 0.5 * sel, dL = d[wl] + 0.5 * sdl;
-  const double eR = S.e[wr] - 0.5 * ser, dR = d[wr] - 0.5 * sdr;
-  Flux2 F = rusanov2d(g, eL, nm[wl] + 0.5 * sml, t1[wl] + 0.5 * sal, S.k[wl] + 0.5 * skl, dL, eR,
-                      nm[wr] - 0.5 * smr, t1[wr] - 0.5 * sar, S.k[wr] - 0.5 * skr, dR);
-  // the centred bed source g h (d slope) / 2 of each side's cell with its
-  // reconstructed depth at this face: a cell's normal-momentum update is then
-  // the difference of its two faces' values
-  F.FmL -= 0.5 * g * (eL + dL) * sdl;
-  F.FmR += 0.5 * g * (eR + dR) * sdr;
-  return F;
-}
-
 // L of one stage on the region of RXs x RYs cells at window offset O; the
-// thread's cells are region cells r = threadIdx.x + NT2 q (stage 1 layout);
-// only cells with `want` set are evaluated.
+// thread's cells are region cells r = threadIdx.x + NTP q (stage 1 layout);
+// only cells with `want` set are evaluated.  Per direction: the minmod
+// slopes of every cell once, the face fluxes from the cells' reconstructed
+// values, then each cell's update from its two faces.
 template <int RXs, int RYs, int O>
 __device__ void stage2d(P2& S, const double* d, const G2& G, int i0, int j0, double (&L)[QMAX][4],
                         int* flags) {
@@ -242,67 +226,103 @@ __device__ void stage2d(P2& S, const double* d, const G2& G, int i0, int j0, dou
   auto inreg = [&](int wi, int wj) {
     return wi >= O && wi < O + RXs && wj >= O && wj < O + RYs;
   };
-  // x-faces
-  for (int f = threadIdx.x; f < (RXs + 1) * RYs; f += NT2) {
-    const int fi = f % (RXs + 1), rj = f / (RXs + 1);
-    const int wl = W(O + fi - 1, O + rj), wr = wl + 1;
-    const Flux2 F = face2d(S, d, G.g, wl, wr, 1, true);
-    S.F0[f] = F.Fh;
-    S.F1[f] = F.FmL;
-    S.F2[f] = F.FmR;
-    S.F3[f] = F.Ft1;
-    S.F4[f] = F.Ft2;
-    const bool used = (inreg(O + fi - 1, O + rj) && dom(O + fi - 1, O + rj)) ||
-                      (inreg(O + fi, O + rj) && dom(O + fi, O + rj));
-    if (F.dry && used) *flags |= ST_DRY;
-  }
-  __syncthreads();
+  constexpr int FPT = ((RXs + 1) * RYs > RXs * (RYs + 1) ? (RXs + 1) * RYs : RXs * (RYs + 1));
+  constexpr int FQ = (FPT + NTP - 1) / NTP;  // faces per thread
 #pragma unroll
-  for (int q = 0; q < QMAX; q++) {
-    const int r = threadIdx.x + NT2 * q;
-    if (r >= R1N) break;
-    const int wi = 2 + r % R1X, wj = 2 + r / R1X;  // stage-1 layout
-    if (!inreg(wi, wj)) continue;
-    const int ri = wi - O, rj = wj - O;
-    const int fl = rj * (RXs + 1) + ri, fr = fl + 1;
-    L[q][0] = -(S.F0[fr] - S.F0[fl]) * idx;
-    L[q][1] = -(S.F1[fr] - S.F2[fl]) * idx;
-    L[q][2] = -(S.F3[fr] - S.F3[fl]) * idx;
-    L[q][3] = -(S.F4[fr] - S.F4[fl]) * idx;
-  }
-  __syncthreads();
-  // y-faces: normal momentum hv, tangential hu
-  for (int f = threadIdx.x; f < RXs * (RYs + 1); f += NT2) {
-    const int ri = f % RXs, fj = f / RXs;
-    const int wl = W(O + ri, O + fj - 1), wr = wl + WX;
-    const Flux2 F = face2d(S, d, G.g, wl, wr, WX, false);
-    S.F0[f] = F.Fh;
-    S.F1[f] = F.FmL;
-    S.F2[f] = F.FmR;
-    S.F3[f] = F.Ft1;
-    S.F4[f] = F.Ft2;
-    const bool used = (inreg(O + ri, O + fj - 1) && dom(O + ri, O + fj - 1)) ||
-                      (inreg(O + ri, O + fj) && dom(O + ri, O + fj));
-    if (F.dry && used) *flags |= ST_DRY;
-  }
-  __syncthreads();
+  for (int dir = 0; dir < 2; dir++) {
+    const bool xd = dir == 0;
+    const int s = xd ? 1 : WX;
+    const double* nm = xd ? S.m : S.n;  // normal momentum
+    const double* t1 = xd ? S.n : S.m;  // tangential momentum
+    // slope cells: xd: (RXs + 2) x RYs from (O - 1, O); else RXs x (RYs + 2) from (O, O - 1)
+    const int SX = xd ? RXs + 2 : RXs, SY = xd ? RYs : RYs + 2;
+    const int sw0 = xd ? W(O - 1, O) : W(O, O - 1);
+    for (int c = threadIdx.x; c < SX * SY; c += NTP) {
+      const int w = sw0 + (c / SX) * WX + c % SX;
+      S.u.sl[0][c] = minmod(S.e[w] - S.e[w - s], S.e[w + s] - S.e[w]);
+      S.u.sl[1][c] = minmod(nm[w] - nm[w - s], nm[w + s] - nm[w]);
+      S.u.sl[2][c] = minmod(t1[w] - t1[w - s], t1[w + s] - t1[w]);
+      S.u.sl[3][c] = minmod(S.k[w] - S.k[w - s], S.k[w + s] - S.k[w]);
+      S.u.sl[4][c] = minmod(d[w] - d[w - s], d[w + s] - d[w]);
+    }
+    __syncthreads();
+    // faces: xd: (RXs + 1) x RYs, face fi between region cells fi - 1 and fi
+    const int NF = xd ? (RXs + 1) * RYs : RXs * (RYs + 1);
+    double fv[FQ][5];
 #pragma unroll
-  for (int q = 0; q < QMAX; q++) {
-    const int r = threadIdx.x + NT2 * q;
-    if (r >= R1N) break;
-    const int wi = 2 + r % R1X, wj = 2 + r / R1X;
-    if (!inreg(wi, wj)) continue;
-    const int ri = wi - O, rj = wj - O;
-    const int fs = rj * RXs + ri, fn = fs + RXs;
-    L[q][0] += -(S.F0[fn] - S.F0[fs]) * idy;
-    L[q][2] += -(S.F1[fn] - S.F2[fs]) * idy;
-    L[q][1] += -(S.F3[fn] - S.F3[fs]) * idy;
-    L[q][3] += -(S.F4[fn] - S.F4[fs]) * idy;
+    for (int q = 0; q < FQ; q++) {
+      const int f = threadIdx.x + NTP * q;
+      if (f >= NF) continue;
+      int wl, cl;  // window cell and slope cell left of (below) the face
+      if (xd) {
+        const int fi = f % (RXs + 1), rj = f / (RXs + 1);
+        wl = W(O + fi - 1, O + rj);
+        cl = rj * SX + fi;
+      } else {
+        const int ri = f % RXs, fj = f / RXs;
+        wl = W(O + ri, O + fj - 1);
+        cl = fj * SX + ri;
+      }
+      const int wr = wl + s, cr = cl + (xd ? 1 : SX);
+      const double eL = S.e[wl] + 0.5 * S.u.sl[0][cl], dL = d[wl] + 0.5 * S.u.sl[4][cl];
+      const double eR = S.e[wr] - 0.5 * S.u.sl[0][cr], dR = d[wr] - 0.5 * S.u.sl[4][cr];
+      Flux2 F = rusanov2d(G.g, eL, nm[wl] + 0.5 * S.u.sl[1][cl], t1[wl] + 0.5 * S.u.sl[2][cl],
+                          S.k[wl] + 0.5 * S.u.sl[3][cl], dL, eR, nm[wr] - 0.5 * S.u.sl[1][cr],
+                          t1[wr] - 0.5 * S.u.sl[2][cr], S.k[wr] - 0.5 * S.u.sl[3][cr], dR);
+      // the centred bed source g h (d slope) / 2 of each side's cell with its
+      // reconstructed depth at this face: a cell's normal-momentum update is
+      // then the difference of its two faces' values
+      fv[q][0] = F.Fh;
+      fv[q][1] = F.FmL - 0.5 * G.g * (eL + dL) * S.u.sl[4][cl];
+      fv[q][2] = F.FmR + 0.5 * G.g * (eR + dR) * S.u.sl[4][cr];
+      fv[q][3] = F.Ft1;
+      fv[q][4] = F.Ft2;
+      if (F.dry) {
+        const int li = (wl % WX), lj = (wl / WX), ri2 = (wr % WX), rj2 = (wr / WX);
+        const bool used = (inreg(li, lj) && dom(li, lj)) || (inreg(ri2, rj2) && dom(ri2, rj2));
+        if (used) *flags |= ST_DRY;
+      }
+    }
+    __syncthreads();  // the slopes are read: the fluxes take their space
+#pragma unroll
+    for (int q = 0; q < FQ; q++) {
+      const int f = threadIdx.x + NTP * q;
+      if (f >= NF) continue;
+#pragma unroll
+      for (int v = 0; v < 5; v++) S.u.F[v][f] = fv[q][v];
+    }
+    __syncthreads();
+    const double id = xd ? idx : idy;
+#pragma unroll
+    for (int q = 0; q < QMAX; q++) {
+      const int r = threadIdx.x + NTP * q;
+      if (r >= R1N) break;
+      const int wi = 2 + r % R1X, wj = 2 + r / R1X;  // stage-1 layout
+      if (!inreg(wi, wj)) continue;
+      const int ri = wi - O, rj = wj - O;
+      const int fl = xd ? rj * (RXs + 1) + ri : rj * RXs + ri;
+      const int fr = fl + (xd ? 1 : RXs);
+      const double a0 = -(S.u.F[0][fr] - S.u.F[0][fl]) * id;
+      const double an = -(S.u.F[1][fr] - S.u.F[2][fl]) * id;  // normal momentum
+      const double at = -(S.u.F[3][fr] - S.u.F[3][fl]) * id;  // tangential
+      const double ak = -(S.u.F[4][fr] - S.u.F[4][fl]) * id;
+      if (xd) {
+        L[q][0] = a0;
+        L[q][1] = an;
+        L[q][2] = at;
+        L[q][3] = ak;
+      } else {
+        L[q][0] += a0;
+        L[q][2] += an;
+        L[q][1] += at;
+        L[q][3] += ak;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT2) k_pred2d(G2 G, const double* __restrict__ h,
+__global__ void __launch_bounds__(NTP) k_pred2d(G2 G, const double* __restrict__ h,
                                                 const double* __restrict__ hu,
                                                 const double* __restrict__ hv,
                                                 const double* __restrict__ hw,
@@ -326,7 +346,7 @@ __global__ void __launch_bounds__(NT2) k_pred2d(G2 G, const double* __restrict__
   const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t0 + dt);
   if (threadIdx.x == 0) sflags = 0;
   int flags = 0;
-  for (int w = threadIdx.x; w < WN; w += NT2) {
+  for (int w = threadIdx.x; w < WN; w += NTP) {
     const int ii = wi0 + w % WX, jj = wj0 + w / WX;
     const int si = reflect(min(max(ii, -H2), G.nx + H2 - 1), G.nx);
     const int sj = reflect(min(max(jj, -H2), G.ny + H2 - 1), G.ny);
@@ -349,7 +369,7 @@ __global__ void __launch_bounds__(NT2) k_pred2d(G2 G, const double* __restrict__
   // Q* = Q^n + dt L(Q^n) on the stage-1 region, then ghosts reflected from Q*
 #pragma unroll
   for (int q = 0; q < QMAX; q++) {
-    const int r = threadIdx.x + NT2 * q;
+    const int r = threadIdx.x + NTP * q;
     if (r >= R1N) break;
     const int wi = 2 + r % R1X, wj = 2 + r / R1X, w = W(wi, wj);
     const int i = wi0 + wi, j = wj0 + wj;
@@ -364,7 +384,7 @@ __global__ void __launch_bounds__(NT2) k_pred2d(G2 G, const double* __restrict__
     S.k[w] = Qn[q][3] + dt * L1[q][3];
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < R1N; r += NT2) {
+  for (int r = threadIdx.x; r < R1N; r += NTP) {
     const int wi = 2 + r % R1X, wj = 2 + r / R1X, w = W(wi, wj);
     const int i = wi0 + wi, j = wj0 + wj;
     if (i >= 0 && i < G.nx && j >= 0 && j < G.ny) continue;
@@ -388,7 +408,7 @@ __global__ void __launch_bounds__(NT2) k_pred2d(G2 G, const double* __restrict__
   stage2d<TX2, TY2, H2>(S, S.d1, G, i0, j0, L2, &flags);
 #pragma unroll
   for (int q = 0; q < QMAX; q++) {
-    const int r = threadIdx.x + NT2 * q;
+    const int r = threadIdx.x + NTP * q;
     if (r >= R1N) break;
     const int wi = 2 + r % R1X, wj = 2 + r / R1X;
     if (wi < H2 || wi >= H2 + TX2 || wj < H2 || wj >= H2 + TY2) continue;
@@ -2393,7 +2413,7 @@ void enqueue_step2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, double* h, 
                     double* hv, double* hw, double* p, uint8_t* mask) {
   const G2 G = make_g2(c, x);
   uint8_t* M = mask ? mask : x->mask_ws;
-  hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw, x->ht, x->mt,
+  hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NTP), 0, s, G, h, hu, hv, hw, x->ht, x->mt,
                      x->nt, x->kt, (const double*)x->t, (const double*)x->dt, 1);
   // the mask pass clears p only off the new marked area: p keeps the previous
   // pressure where it is needed as the initial guess
@@ -2449,7 +2469,7 @@ void launch_speed2d_prologue(const swe_nh_config* c, Ctx2D* x, hipStream_t s, co
 void launch_pred2d_stage(const swe_nh_config* c, Ctx2D* x, hipStream_t s, const double* h,
                          const double* hu, const double* hv, const double* hw, const double* t_in,
                          const double* dt_in, double* ht, double* mt, double* nt, double* kt) {
-  hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, make_g2(c, x), h, hu, hv, hw, ht,
+  hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NTP), 0, s, make_g2(c, x), h, hu, hv, hw, ht,
                      mt, nt, kt, t_in, dt_in, 0);
 }
 
@@ -2499,7 +2519,7 @@ void time_stage2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, int stage, do
   const G2 G = make_g2(c, x);
   switch (stage) {
     case 0:
-      hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NT2), 0, s, G, h, hu, hv, hw, x->ht,
+      hipLaunchKernelGGL(k_pred2d, dim3(x->ntiles), dim3(NTP), 0, s, G, h, hu, hv, hw, x->ht,
                          x->mt, x->nt, x->kt, (const double*)x->t, (const double*)x->dt, 0);
       break;
     case 1:
