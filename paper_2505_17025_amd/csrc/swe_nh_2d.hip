@@ -2169,6 +2169,10 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
 }
 
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
+  if (x->mg_levels > 0) {
+    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), s);
+    return;
+  }
   hipLaunchKernelGGL(k_bar_reset, dim3((x->ntiles + 255) / 256), dim3(256), 0, s, x->bar, x->tflag,
                      x->ntiles);
   // coarse operator of the active tiles (the inversion exits when there are
@@ -2251,6 +2255,48 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->iters = (int*)take(4);
   x->iters_sum = (long long*)take(8);
   x->rel = (double*)take(8);
+  x->mg_levels = 0;
+  if (c->crit == SWE_NH_CRIT_GLOBAL) {
+    // every cell is marked: CG with a multigrid preconditioner when the grid
+    // coarsens to at most 1024 cells by 2 x 2 aggregation
+    x->mg_levels = mg_plan_levels(c->nx, c->ny, x->mg_nx, x->mg_ny);
+    const int L = x->mg_levels;
+    for (int l = 0; l <= L && L > 0; l++) {
+      const int64_t n = (int64_t)x->mg_nx[l] * x->mg_ny[l];
+      if (l == 0) {
+        x->mg_c[0] = x->dg32;
+        x->mg_e[0] = x->ce32;
+        x->mg_n[0] = x->cn32;
+      } else {
+        x->mg_c[l] = (float*)take(4 * n);
+        x->mg_e[l] = (float*)take(4 * n);
+        x->mg_n[l] = (float*)take(4 * n);
+        x->mg_b[l] = (float*)take(4 * n);
+        x->mg_z[l] = (float*)take(4 * n);
+      }
+      if (l < L) x->mg_x[l] = (float*)take(4 * n);
+    }
+    if (L > 0) {
+      MgArgs& A = x->mg_args;
+      A.nx = c->nx;
+      A.ny = c->ny;
+      A.dg = x->dg;
+      A.ce = x->ce;
+      A.cn = x->cn;
+      A.b = x->b;
+      A.x = x->x;
+      A.r = (double*)take(8 * N);
+      A.z = (double*)take(8 * N);
+      A.q = (double*)take(8 * N);
+      A.p[0] = (double*)take(8 * N);
+      A.p[1] = (double*)take(8 * N);
+      A.part = (double*)take(8 * 2 * 2048);
+      A.st = (MgState*)take(sizeof(MgState));
+      A.iters = x->iters;
+      A.iters_sum = x->iters_sum;
+      A.rel = x->rel;
+    }
+  }
   if (c->warm == 2) {
     // the network runs on a window of at most 256 x 256 cells over the active
     // tiles: the pressure's support plus the network's receptive field
@@ -2272,6 +2318,7 @@ int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s) {
   x->status = k1.status;
   x->step = k1.step;
   x->ch = k1.ch;
+  x->mg_args.status = k1.status;
   // the persistent solver needs all its blocks resident at once
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SWE_NH_EHIP;

@@ -208,10 +208,11 @@ def test_deterministic_2d(B):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_many_tiles_per_solver_block(B, precision):
-    """global extension on 1536 x 512 cells (1536 tiles, more than the
+    """global extension on 1536 x 510 cells (1536 tiles, more than the
     solver's blocks): every block of the persistent solver walks several
-    tiles (the Chronopoulos-Gear form with a neighbour-tile sync)"""
-    c = S.random_case_2d(1536, 512, seed=41, dx=1.0, dy=1.0, h0=10.0)
+    tiles (the Chronopoulos-Gear form with a neighbour-tile sync).  The odd
+    extent after one halving keeps the grid off the multigrid solver."""
+    c = S.random_case_2d(1536, 510, seed=41, dx=1.0, dy=1.0, h0=10.0)
     tol = 1e-13 if precision == 0 else 1e-11
     kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=5000, warm=1)
     ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 1, **kw)
@@ -222,12 +223,13 @@ def test_many_tiles_per_solver_block(B, precision):
         assert rel(g, r) <= bar
 
 
-@pytest.mark.parametrize("nx,ny", [(256, 256), (288, 256), (100, 40)])
+@pytest.mark.parametrize("nx,ny", [(256, 254), (288, 254), (100, 41)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solver_around_the_coarse_space_limit(B, nx, ny, precision):
     """global extension with 128 active tiles (the most the solver's coarse
     space takes), 144 (the pipelined solver without it) and a few ragged
-    tiles: same results as the oracle"""
+    tiles: same results as the oracle (grids that do not halve evenly to
+    1024 cells, so the tile solver runs, not the multigrid one)"""
     c = S.random_case_2d(nx, ny, seed=43, dx=1.0, dy=1.0, h0=10.0)
     tol = 1e-13 if precision == 0 else 1e-11
     kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=5000, warm=1)
@@ -256,3 +258,57 @@ def test_iteration_total_accumulates(B):
         assert st["status"] == 0, st
         per_step.append(st["iters"])
     assert st["iters_total"] == sum(per_step) and sum(per_step) > 0
+
+
+@pytest.mark.parametrize("nx,ny", [(100, 40), (256, 192), (320, 288), (512, 512)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_global_multigrid_steps(B, nx, ny, precision):
+    """global extension on grids that halve evenly down to at most 1024
+    cells (1 to 4 coarsenings, ragged tiles at 100 x 40): the CG with the
+    multigrid preconditioner gives the oracle's steps, in a few dozen
+    iterations"""
+    c = S.random_case_2d(nx, ny, seed=47, dx=1.0, dy=1.0, h0=10.0)
+    tol = 1e-13 if precision == 0 else 1e-11
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=5000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 2, **kw)
+    assert st["status"] == 0, st
+    assert 0 < st["iters"] <= 64 and st["rel_res"] <= tol, st
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_GLOBAL, tol=1e-14), cfl=0.4).step(2)
+    bar = 1e-10 if precision == 0 else 1e-6
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= bar
+
+
+def test_global_multigrid_solve_stage(B):
+    """the multigrid solve through the pressure stage on a full mask: the
+    oracle's CG pressure to 1e-10, zero guess and a warm guess"""
+    c = case(nx=192, ny=128, seed=9)
+    m = np.ones((c.ny, c.nx), np.uint8)
+    t0, dt = 0.2, 0.01
+    ph = O.phys_struct()
+    cell, xf, yf = O.nh_coeffs_2d(c.ds, c.dx, c.dy, c.body, ph, t0 + dt, dt, c.h, c.hu, c.hv, c.hw)
+    rhs = O.nh_rhs_2d(cell, xf, yf, m)
+    pref, _, _ = O.cg_2d(cell, xf, yf, m, rhs, tol=1e-14)
+    args = (dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw))
+    its = []
+    for warm, p0 in ((0, 3.0), (1, None)):
+        ctx = B.context_2d(c, crit=S.CRIT_GLOBAL, precision=1, tol=1e-13, max_iter=5000, warm=warm)
+        p = (torch.full((c.ny, c.nx), p0, dtype=torch.float64, device=DEV) if p0 is not None
+             else dt_(pref * (1.0 + 1e-6)))
+        it, rr = ctx.solve_pressure(*args, torch.tensor(m, device=DEV), t0, dt, p)
+        assert ctx.sync_stats()["status"] == 0
+        assert rr <= 1e-13 and 0 < it <= 64
+        assert rel(p, pref) <= 1e-10
+        its.append(it)
+    assert its[1] < its[0], its
+
+
+def test_global_multigrid_no_convergence_status(B):
+    """an iteration cap below what the tolerance needs: the step reports
+    no convergence (status code), the pressure is the last iterate"""
+    c = S.random_case_2d(256, 192, seed=47, dx=1.0, dy=1.0, h0=10.0)
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=0, tol=1e-14, max_iter=2, warm=0)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 1, **kw)
+    assert st["status"] == B.ENOCONV
+    assert st["iters"] == 2 and st["rel_res"] > 1e-14
+    assert torch.isfinite(p).all()
