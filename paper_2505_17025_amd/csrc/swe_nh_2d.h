@@ -16,7 +16,8 @@ constexpr int PCG_NVEC = 10;  // inner vectors of the 2D solver
 constexpr int CMAX2 = 128;     // most active tiles for which the solver adds the coarse space
 
 constexpr int MG_MAXL = 12;    // most levels of the multigrid preconditioner (global extension)
-constexpr int MG_BUDGET = 64;  // most iterations of the multigrid-preconditioned CG
+constexpr int MG_BUDGET = 32;  // iterations of the multigrid-preconditioned CG in a step
+constexpr int MG_COARSE_MAX = 4096;  // most cells of the multigrid's coarsest level (one block)
 
 // scalars of the multigrid-preconditioned CG (device)
 struct MgState {
@@ -30,8 +31,10 @@ struct MgArgs {
   int nx = 0, ny = 0;
   const double *dg = nullptr, *ce = nullptr, *cn = nullptr, *b = nullptr;
   double* x = nullptr;
-  double *r = nullptr, *z = nullptr, *q = nullptr, *p[2] = {nullptr, nullptr};
-  double* part = nullptr;  // block partial sums [2][2048]
+  double *r = nullptr, *q = nullptr, *p[2] = {nullptr, nullptr};
+  float* z = nullptr;      // the preconditioned residual (output of the FP32 V-cycle)
+  double* part = nullptr;  // block partial sums [2][npart]
+  int npart = 0;
   MgState* st = nullptr;
   double tol = 0.0;
   int* iters = nullptr;
@@ -80,12 +83,12 @@ struct Ctx2D {
   double* rel = nullptr;
   // multigrid-preconditioned CG of the global extension (mg_levels > 0):
   // level l has mg_nx[l] x mg_ny[l] cells; operator C, E, N (level 0: the
-  // FP32 copy dg32, ce32, cn32), smoothed values x (l < mg_levels),
-  // right-hand side b and output z (l >= 1), all FP32
+  // FP32 copy dg32, ce32, cn32), right-hand side b and output z (l >= 1),
+  // all FP32
   int mg_levels = 0;
   int mg_nx[MG_MAXL] = {}, mg_ny[MG_MAXL] = {};
   float *mg_c[MG_MAXL] = {}, *mg_e[MG_MAXL] = {}, *mg_n[MG_MAXL] = {};
-  float *mg_x[MG_MAXL] = {}, *mg_b[MG_MAXL] = {}, *mg_z[MG_MAXL] = {};
+  float *mg_b[MG_MAXL] = {}, *mg_z[MG_MAXL] = {};
   MgArgs mg_args;
   // learned warm start (warm = 2)
   char* cnn_ws = nullptr;
@@ -107,12 +110,19 @@ struct Ctx2D {
 };
 
 // levels of the multigrid for an nx x ny grid (2 x 2 aggregation while both
-// extents are even and the level has more than 1024 cells); the number of
-// coarsenings, 0 when the grid does not reach 1024 cells that way
+// extents are even and the level has more than MG_COARSE_MAX cells); the
+// number of coarsenings, 0 when the grid does not reach MG_COARSE_MAX cells
+// that way
 int mg_plan_levels(int nx, int ny, int* lnx, int* lny);
+// block partial sums one reduction of that solver needs at most
+int mg_partials(int nx, int ny);
 // the global extension's solve of A x = b (x holds the initial guess): CG in
-// FP64 preconditioned by one FP32 V-cycle, at most budget iterations
-void launch_mg_solve2d(Ctx2D* x, double tol, int budget, hipStream_t s);
+// FP64 preconditioned by one FP32 V-cycle, at most budget iterations.  With
+// last, a solve that misses the tolerance sets the no-convergence status;
+// otherwise another solver continues (launch_mg_account2d after it adds the
+// multigrid iterations to the statistics)
+void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t s);
+void launch_mg_account2d(Ctx2D* x, hipStream_t s);
 
 void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x);
 int init2d(const swe_nh_config* c, Ctx2D* x, const K1D& k1, hipStream_t s);

@@ -979,6 +979,7 @@ struct PcgArgs {
   double* rel;
   double tol, tol_in;
   int max_iter;
+  const int* skip;  // the solve returns at once when *skip == 1 (null: never)
 };
 
 template <typename T, typename V>
@@ -1816,6 +1817,7 @@ template <typename R>
 __global__ void __launch_bounds__(NT2) k_pcg2d_pipe(PcgArgs<R> A) {
   __shared__ R zt[PCG_K][TY2][TX2];
   __shared__ double crows[5][CMAX2];
+  if (A.skip && *A.skip == 1) return;
   const int nlist = *A.n_list;
   if (nlist < 1 || nlist > PCG_K * A.pipe_blocks) return;  // the other form's case
   const int G = (nlist + PCG_K - 1) / PCG_K;
@@ -1830,6 +1832,7 @@ __global__ void __launch_bounds__(NT2) k_pcg2d_pipe(PcgArgs<R> A) {
 template <typename R>
 __global__ void __launch_bounds__(NT2) k_pcg2d_cg(PcgArgs<R> A) {
   __shared__ R zt[TY2][TX2];
+  if (A.skip && *A.skip == 1) return;
   const int nlist = *A.n_list;
   if (nlist >= 1 && nlist <= PCG_K * A.pipe_blocks) return;  // the pipelined form's case
   const int G = max(1, min((int)gridDim.x, nlist));
@@ -2124,6 +2127,7 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.mt[1] = x->mtag[1];
   A.pt = x->pt;
   A.tag_base = x->tag_base;
+  A.skip = nullptr;
   return A;
 }
 
@@ -2168,31 +2172,53 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
     p[i] = mask[i] ? x[i] : 0.0;
 }
 
-void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
-  if (x->mg_levels > 0) {
-    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), s);
-    return;
-  }
+// the tile solver on the system in x (its initial guess in x->x); with
+// skip, it returns at once when *skip == 1, and runs at most max_iter
+// iterations
+void launch_tile_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, bool coarse,
+                         const int* skip, int max_iter) {
   hipLaunchKernelGGL(k_bar_reset, dim3((x->ntiles + 255) / 256), dim3(256), 0, s, x->bar, x->tflag,
                      x->ntiles);
-  // coarse operator of the active tiles (the inversion exits when there are
-  // more than CMAX2 of them, and then the solver does without)
-  hipLaunchKernelGGL(k_coarse2d, dim3(std::min(x->ntiles, CMAX2)), dim3(NT2), 0, s, x->nx, x->ny,
-                     x->tiles_x, (const int*)x->tile_list, (const int*)x->n_tiles_act,
-                     (const uint8_t*)x->nb, (const double*)x->dg, (const double*)x->ce,
-                     (const double*)x->cn, x->crow);
-  hipLaunchKernelGGL(k_coarse_inv2d, dim3(1), dim3(1024), 0, s, x->tiles_x, x->tiles_y,
-                     (const int*)x->tile_list, (const int*)x->n_tiles_act,
-                     (const int*)x->tile_pos, (const double*)x->crow, x->cinv, x->cused);
+  if (coarse) {
+    // coarse operator of the active tiles (the inversion exits when there are
+    // more than CMAX2 of them, and then the solver does without)
+    hipLaunchKernelGGL(k_coarse2d, dim3(std::min(x->ntiles, CMAX2)), dim3(NT2), 0, s, x->nx,
+                       x->ny, x->tiles_x, (const int*)x->tile_list, (const int*)x->n_tiles_act,
+                       (const uint8_t*)x->nb, (const double*)x->dg, (const double*)x->ce,
+                       (const double*)x->cn, x->crow);
+    hipLaunchKernelGGL(k_coarse_inv2d, dim3(1), dim3(1024), 0, s, x->tiles_x, x->tiles_y,
+                       (const int*)x->tile_list, (const int*)x->n_tiles_act,
+                       (const int*)x->tile_pos, (const double*)x->crow, x->cinv, x->cused);
+  }
   if (c->precision == 1) {
-    const PcgArgs<float> A = pcg_args32(c, x);
+    PcgArgs<float> A = pcg_args32(c, x);
+    A.skip = skip;
+    A.max_iter = max_iter;
     hipLaunchKernelGGL(k_pcg2d_pipe<float>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
     hipLaunchKernelGGL(k_pcg2d_cg<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, A);
   } else {
-    const PcgArgs<double> A = pcg_args64(c, x);
+    PcgArgs<double> A = pcg_args64(c, x);
+    A.skip = skip;
+    A.max_iter = max_iter;
     hipLaunchKernelGGL(k_pcg2d_pipe<double>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
     hipLaunchKernelGGL(k_pcg2d_cg<double>, dim3(x->grid_pcg), dim3(NT2), 0, s, A);
   }
+}
+
+void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
+  if (x->mg_levels > 0) {
+    // the multigrid CG for up to MG_BUDGET iterations (a captured step cannot
+    // size a launch sequence by the iteration count); if it has not met the
+    // tolerance by then, the tile solver continues from its iterate
+    const bool more = c->max_iter > MG_BUDGET;
+    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), !more, s);
+    if (more) {
+      launch_tile_solve2d(c, x, s, false, &x->mg_args.st->done, c->max_iter - MG_BUDGET);
+      launch_mg_account2d(x, s);
+    }
+    return;
+  }
+  launch_tile_solve2d(c, x, s, true, nullptr, c->max_iter);
 }
 
 }  // namespace
@@ -2258,25 +2284,21 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->mg_levels = 0;
   if (c->crit == SWE_NH_CRIT_GLOBAL) {
     // every cell is marked: CG with a multigrid preconditioner when the grid
-    // coarsens to at most 1024 cells by 2 x 2 aggregation
+    // coarsens to at most MG_COARSE_MAX cells by 2 x 2 aggregation
     x->mg_levels = mg_plan_levels(c->nx, c->ny, x->mg_nx, x->mg_ny);
     const int L = x->mg_levels;
-    for (int l = 0; l <= L && L > 0; l++) {
+    for (int l = 1; l <= L; l++) {
       const int64_t n = (int64_t)x->mg_nx[l] * x->mg_ny[l];
-      if (l == 0) {
-        x->mg_c[0] = x->dg32;
-        x->mg_e[0] = x->ce32;
-        x->mg_n[0] = x->cn32;
-      } else {
-        x->mg_c[l] = (float*)take(4 * n);
-        x->mg_e[l] = (float*)take(4 * n);
-        x->mg_n[l] = (float*)take(4 * n);
-        x->mg_b[l] = (float*)take(4 * n);
-        x->mg_z[l] = (float*)take(4 * n);
-      }
-      if (l < L) x->mg_x[l] = (float*)take(4 * n);
+      x->mg_c[l] = (float*)take(4 * n);
+      x->mg_e[l] = (float*)take(4 * n);
+      x->mg_n[l] = (float*)take(4 * n);
+      x->mg_b[l] = (float*)take(4 * n);
+      x->mg_z[l] = (float*)take(4 * n);
     }
     if (L > 0) {
+      x->mg_c[0] = x->dg32;
+      x->mg_e[0] = x->ce32;
+      x->mg_n[0] = x->cn32;
       MgArgs& A = x->mg_args;
       A.nx = c->nx;
       A.ny = c->ny;
@@ -2286,11 +2308,12 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
       A.b = x->b;
       A.x = x->x;
       A.r = (double*)take(8 * N);
-      A.z = (double*)take(8 * N);
+      A.z = (float*)take(4 * N);
       A.q = (double*)take(8 * N);
       A.p[0] = (double*)take(8 * N);
       A.p[1] = (double*)take(8 * N);
-      A.part = (double*)take(8 * 2 * 2048);
+      A.npart = mg_partials(c->nx, c->ny);
+      A.part = (double*)take(8 * 2 * (size_t)A.npart);
       A.st = (MgState*)take(sizeof(MgState));
       A.iters = x->iters;
       A.iters_sum = x->iters_sum;

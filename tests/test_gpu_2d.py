@@ -260,17 +260,18 @@ def test_iteration_total_accumulates(B):
     assert st["iters_total"] == sum(per_step) and sum(per_step) > 0
 
 
-@pytest.mark.parametrize("nx,ny", [(100, 40), (256, 192), (320, 288), (512, 512)])
+@pytest.mark.parametrize("nx,ny", [(200, 80), (256, 192), (320, 288), (512, 512)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_global_multigrid_steps(B, nx, ny, precision):
-    """global extension on grids that halve evenly down to at most 1024
-    cells (1 to 4 coarsenings, ragged tiles at 100 x 40): the CG with the
-    multigrid preconditioner gives the oracle's steps, in a few dozen
-    iterations"""
+    """global extension on grids that halve evenly down to at most 4096
+    cells (1 to 3 coarsenings; tiles of the smoothing kernels ragged at
+    200 x 80 and 320 x 288): the CG with the multigrid preconditioner gives
+    the oracle's steps, in a few dozen iterations"""
     c = S.random_case_2d(nx, ny, seed=47, dx=1.0, dy=1.0, h0=10.0)
     tol = 1e-13 if precision == 0 else 1e-11
     kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=5000, warm=1)
     ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 2, **kw)
+    print("multigrid CG iterations of the last step", st["iters"])
     assert st["status"] == 0, st
     assert 0 < st["iters"] <= 64 and st["rel_res"] <= tol, st
     ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_GLOBAL, tol=1e-14), cfl=0.4).step(2)
@@ -301,6 +302,26 @@ def test_global_multigrid_solve_stage(B):
         assert rel(p, pref) <= 1e-10
         its.append(it)
     assert its[1] < its[0], its
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_global_multigrid_continued_by_the_tile_solver(B, precision):
+    """a grid whose coarsest level (100 x 40 cells) is far from the pressure's
+    decay length, so the multigrid CG needs more than its per-step budget of
+    32 iterations: the tile solver continues from its iterate, the step meets
+    the tolerance, counts the iterations of both and matches the oracle"""
+    c = S.random_case_2d(200, 80, seed=47, dx=1.0, dy=1.0, h0=10.0)
+    tol = 1e-13 if precision == 0 else 1e-11
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=20000,
+              warm=0)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 1, **kw)
+    print("iterations", st["iters"], "rel_res", st["rel_res"])
+    assert st["status"] == 0, st
+    assert st["iters"] > 32 and st["rel_res"] <= tol, st
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_GLOBAL, tol=1e-14), cfl=0.4).step(1)
+    bar = 1e-10 if precision == 0 else 1e-6
+    for g, r in ((hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= bar
 
 
 def test_global_multigrid_no_convergence_status(B):
