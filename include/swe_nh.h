@@ -305,6 +305,37 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double
 int swe_nh_time_stage(swe_nh_ctx* ctx, int32_t stage, int32_t nreps, double* h, double* hu,
                       double* hv, double* hw, double* p, double* avg_us_host);
 
+/* ---- The paper's own 1D discretisation (global model, one channel) ----
+ * Sec. 3.1 Eqs. 6-9: RKDG with nodal P1 elements (consistent mass, element
+ * integrals of the flux and of the bed source g h d_x by three-point Gauss
+ * quadrature, Rusanov flux at the faces, mirror states at the walls, Heun
+ * with the bottom at t^{n+1} in stage 2); Sec. 3.2 Eqs. 14-17: LDG-P1 for
+ * the elliptic system with the alternating flux p* = p+, (hu)* = (hu)-,
+ * p* = 0 at both walls and at the left wall (hu)* = (hu)+ - p+ / (s12 dx);
+ * Eqs. 10-11: hu = q and hw from the bottom pressure, node by node.  The
+ * bottom is d = d_static - B(x - X(t)) (flat static depth, the body of
+ * swe_nh_body with y ignored).  No slope limiter and no wetting and drying. */
+#define SWE_NH_DG_MAX_ELEMS 1024
+
+typedef struct {
+  int32_t n;           /* elements, 1 .. SWE_NH_DG_MAX_ELEMS; element i spans [i dx, (i+1) dx] */
+  double dx, dt;       /* element width (m) and fixed time step (s) */
+  double g, rho;
+  double d_static;     /* flat static depth (m), > 0 */
+  swe_nh_body body;    /* moving bottom (kind SWE_NH_BODY_NONE: flat bottom) */
+} swe_nh_dg1d_config;
+
+/* Advance nsteps steps of dt from time t0 in one launch on stream (one
+ * workgroup holds the channel).  h, hu, hw: device [n][2] node values,
+ * element-major (node j of element i at 2 i + j), Q^n on entry and Q^{n+1}
+ * on return; p: device [n][2], receives the NH pressure of the last step;
+ * status: a device int32 the call uses as scratch.  Synchronises the stream.
+ * Returns SWE_NH_EINVAL (bad sizes or null pointers), SWE_NH_EDRY (a node
+ * depth <= 0 entered a predictor stage), SWE_NH_ENAN (non-finite result) or
+ * SWE_NH_EHIP. */
+int swe_nh_dg1d_run(const swe_nh_dg1d_config* cfg, double t0, int32_t nsteps, double* h,
+                    double* hu, double* hw, double* p, int32_t* status, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

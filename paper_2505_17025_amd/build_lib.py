@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libswe_nh.so")
 SOURCES = ["swe_nh_1d.hip", "swe_nh_tri.hip", "swe_nh_2d.hip", "swe_nh_mg2d.hip", "swe_nh_cnn.hip",
-           "swe_nh_api.cpp"]
+           "swe_nh_dg1d.hip", "swe_nh_api.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

@@ -39,6 +39,11 @@ class swe_nh_config(C.Structure):
                 ("bodies", C.POINTER(swe_nh_body))]
 
 
+class swe_nh_dg1d_config(C.Structure):
+    _fields_ = [("n", C.c_int32), ("dx", C.c_double), ("dt", C.c_double), ("g", C.c_double),
+                ("rho", C.c_double), ("d_static", C.c_double), ("body", swe_nh_body)]
+
+
 class swe_nh_stats(C.Structure):
     _fields_ = [("n_active", C.c_int64), ("iters", C.c_int32), ("status", C.c_int32),
                 ("rel_res", C.c_double), ("dt", C.c_double), ("t", C.c_double),
@@ -87,11 +92,13 @@ def _load():
                                     C.c_float, vp]
     lib.swe_nh_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
     lib.swe_nh_set_warm_start_net.argtypes = [vp, vp, C.POINTER(dbl), dbl]
+    lib.swe_nh_dg1d_run.argtypes = [C.POINTER(swe_nh_dg1d_config), dbl, i32, vp, vp, vp, vp, vp,
+                                    vp]
     for name in ("swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
                  "swe_nh_cnn_mse", "swe_nh_cnn_adam",
                  "swe_nh_features", "swe_nh_set_warm_start_net", "swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
                  "swe_nh_sync_stats", "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure",
-                 "swe_nh_correct"):
+                 "swe_nh_correct", "swe_nh_dg1d_run"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -102,8 +109,10 @@ EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_l
             "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct",
             "swe_nh_time_stage", "swe_nh_cnn_param_count", "swe_nh_cnn_workspace_bytes",
             "swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
-            "swe_nh_cnn_mse", "swe_nh_cnn_adam", "swe_nh_features", "swe_nh_set_warm_start_net"]
+            "swe_nh_cnn_mse", "swe_nh_cnn_adam", "swe_nh_features", "swe_nh_set_warm_start_net",
+            "swe_nh_dg1d_run"]
 NOALLOC_MAX_PIXELS = 131072
+DG_MAX_ELEMS = 1024
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -272,6 +281,17 @@ def cnn_forward_noalloc(params, x, n, h, w, out):
     stream = torch.cuda.current_stream(out.device).cuda_stream
     return int(LIB.swe_nh_cnn_forward_noalloc(_ptr(params), _ptr(x), int(n), int(h), int(w),
                                               _ptr(out), C.c_void_p(stream)))
+
+
+def dg1d_run(n, dx, dt, d_static, body, t0, nsteps, h, hu, hw, p, status, g=9.81, rho=1000.0):
+    """swe_nh_dg1d_run on the current stream: h, hu, hw, p device [n, 2]
+    (FP64), status a device int32 scratch word; returns the status code"""
+    cfg = swe_nh_dg1d_config()
+    cfg.n, cfg.dx, cfg.dt, cfg.g, cfg.rho, cfg.d_static = int(n), dx, dt, g, rho, d_static
+    cfg.body = body_struct(body)
+    stream = torch.cuda.current_stream(h.device).cuda_stream
+    return int(LIB.swe_nh_dg1d_run(C.byref(cfg), float(t0), int(nsteps), _ptr(h), _ptr(hu),
+                                   _ptr(hw), _ptr(p), _ptr(status), C.c_void_p(stream)))
 
 
 class Net:

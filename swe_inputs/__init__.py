@@ -132,19 +132,20 @@ def slide_case(n=32768, dx=0.005, h0=0.4, theta_deg=15.0, length=0.4, height=0.0
     return Case1D(n=n, dx=dx, ds=ds, h=h, hu=np.zeros(n), hw=np.zeros(n), body=body)
 
 
-def _body_profile_1d(n, dx, body: Body, t: float):
+def _body_profile_1d(n, dx, body: Body, t: float, x=None):
     """B(x - X(0)) for the quartic body at rest at its start position (used
     only to lay down the still-water initial state; the solvers evaluate the
-    moving bottom themselves)."""
-    x = (np.arange(n) + 0.5) * dx
+    moving bottom themselves); x: the points (default: cell centres)"""
+    if x is None:
+        x = (np.arange(n) + 0.5) * dx
     assert t == 0.0
-    xi = x - body.x0
+    xi = np.asarray(x, dtype=np.float64) - body.x0
     if body.kind == BODY_QUARTIC:
         z = 2.0 * xi / body.length
         return np.where(np.abs(xi) < 0.5 * body.length, body.amp * (1.0 - z ** 4), 0.0)
     if body.kind == BODY_GAUSS:
         return body.amp * np.exp(-(xi * xi) / body.length ** 2)
-    return np.zeros(n)
+    return np.zeros(np.shape(xi))
 
 
 def whittaker_case(fr_index=1, n=None, dx=0.075, h0=0.175, length_domain=30.0) -> Case1D:
@@ -160,6 +161,31 @@ def whittaker_case(fr_index=1, n=None, dx=0.075, h0=0.175, length_domain=30.0) -
     ds = np.full(n, h0)
     h = ds - _body_profile_1d(n, dx, body, 0.0)
     return Case1D(n=n, dx=dx, ds=ds, h=h, hu=np.zeros(n), hw=np.zeros(n), body=body)
+
+
+# ----------------------------------------------------------------------------
+# node values [3, n, 2] (h, hu, hw at the two ends of each P1 element
+# [i dx, (i + 1) dx]) for the paper's own discretisation
+# ----------------------------------------------------------------------------
+
+def dg_nodes(n, dx):
+    x0 = np.arange(n) * dx
+    return np.stack([x0, x0 + dx], axis=1)
+
+
+def dg_solitary_state(n, dx, a, d, x0, g: float = G):
+    """the Serre solitary wave at t = 0 at the element nodes"""
+    eta, u, hw = solitary_exact(dg_nodes(n, dx), 0.0, a, d, x0, g)
+    h = d + eta
+    return np.stack([h, h * u, hw])
+
+
+def dg_still_water_state(n, dx, h0, body: Body):
+    """still water over the body at rest at its start position, flat static
+    depth h0"""
+    x = dg_nodes(n, dx)
+    h = h0 - _body_profile_1d(n, dx, body, 0.0, x=x)
+    return np.stack([h, np.zeros_like(h), np.zeros_like(h)])
 
 
 @dataclasses.dataclass
