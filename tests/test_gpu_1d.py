@@ -620,7 +620,10 @@ def test_full_size_ensemble_sampled_channels(B, precision):
     """the 512-channel ensemble at its full size (18.3M cells) in the
     benchmark's launch configuration (tiles of 242 cells, the FP64 fused step
     or the FP32 solve with FP64 refinement); channels are independent, so the
-    oracle checks the shortest, the longest and a middle channel exactly"""
+    oracle checks 16 of them exactly (the shortest, the longest and 14 drawn
+    with a fixed seed), and every channel conserves its mass (the predictor's
+    fluxes are conservative between reflective walls and the correction
+    leaves h alone)"""
     ens = S.ensemble_case(n_channels=512, n_min=4096, n_max=65536, seed=17026)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, precision=precision, tol=1e-12,
               max_iter=6, tile1d=242)
@@ -628,10 +631,17 @@ def test_full_size_ensemble_sampled_channels(B, precision):
     ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, nsteps, **kw)
     assert st["status"] == 0, st
     lens = [c.n for c in ens.channels]
-    picks = {int(np.argmin(lens)), int(np.argmax(lens)), 255}
+    picks = [int(np.argmin(lens)), int(np.argmax(lens)), 255]
+    rest = [j for j in range(512) if j not in picks]
+    picks += [int(j) for j in np.random.default_rng(512).choice(rest, 13, replace=False)]
     o = ens.offsets
+    hs = h.cpu().numpy()
+    for j, c in enumerate(ens.channels):
+        m0 = c.h.sum()
+        assert abs(hs[int(o[j]):int(o[j + 1])].sum() - m0) <= 1e-12 * m0, j
     tg = ctx.get_time()
     tol = 1e-10 if precision == 0 else 1e-6
+    marked = 0
     for j in picks:
         c = ens.channels[j]
         ref = O.Sim1D(c, phys_of(kw), cfl=0.5).step(nsteps)
@@ -640,5 +650,7 @@ def test_full_size_ensemble_sampled_channels(B, precision):
         assert np.array_equal(mask[sl].cpu().numpy(), ref.mask), j
         for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
             assert rel(g, r) <= tol, j
-        assert ref.last_active > 0
-        assert rel(p[sl], ref.p) <= tol, j
+        marked += ref.last_active
+        if ref.last_active > 0:
+            assert rel(p[sl], ref.p) <= tol, j
+    assert marked > 0

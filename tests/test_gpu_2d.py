@@ -193,6 +193,13 @@ def test_full_size_shelf_properties(B):
     rhs = O.nh_rhs_2d(cell, xf, yf, mref)
     r = rhs - O.nh_apply_2d(cell, xf, yf, mref, pg.cpu().numpy())
     assert np.linalg.norm(r[mref == 1]) <= 1.01e-10 * np.linalg.norm(rhs[mref == 1])
+    # the projection of the full-size state with that pressure, cell by cell
+    outs = [torch.empty_like(h) for _ in range(3)]
+    ctx.correct(*[dt_(a) for a in ref], mg, pg, t, dtv, *outs)
+    assert ctx.sync_stats()["status"] == 0
+    mc, nc, kc = O.nh_correct_2d(cell, xf, yf, dtv, 1000.0, mt, nt, kt, mref, pg.cpu().numpy())
+    assert rel(outs[0], mc) <= 1e-12 and rel(outs[1], nc) <= 1e-12
+    assert rel(outs[2] - dt_(kt), kc - kt) <= 1e-11
     assert abs(hs.sum() - c.h.sum()) <= 1e-12 * c.h.sum()
     assert abs(mass0 - c.h.sum()) <= 1e-12 * c.h.sum()
 
@@ -333,3 +340,22 @@ def test_global_multigrid_no_convergence_status(B):
     assert st["status"] == B.ENOCONV
     assert st["iters"] == 2 and st["rel_res"] > 1e-14
     assert torch.isfinite(p).all()
+
+
+def test_status_codes_2d(B):
+    """a non-finite value in the state gives ENAN, a cell whose depth is not
+    positive gives EDRY (both in a whole step); the state stays finite where
+    it was"""
+    c = case(nx=96, ny=64, seed=13)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=4e-3, cfl=0.0, dt_fixed=0.005, precision=0, tol=1e-12,
+              max_iter=2000)
+    for mutate, want in ((lambda h: h.__setitem__((10, 20), np.nan), B.ENAN),
+                         (lambda h: h.__setitem__((30, 40), -0.5), B.EDRY)):
+        hh = c.h.copy()
+        mutate(hh)
+        ctx = B.context_2d(c, **kw)
+        ctx.set_time(c.t0)
+        h, hu, hv, hw = dt_(hh), dt_(c.hu), dt_(c.hv), dt_(c.hw)
+        p = torch.zeros_like(h)
+        ctx.step(h, hu, hv, hw, p, nsteps=1)
+        assert ctx.sync_stats()["status"] == want
