@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--preroll", type=int, default=None,
-                    help="ensemble1d: untimed steps before the warm-up (default 2500)")
+                    help="ensemble1d: untimed steps before the warm-up (default 2500); "
+                         "shelf2d: untimed adaptive steps from t = 0 (default 0)")
     ap.add_argument("--workload", default="ensemble1d",
                     choices=["ensemble1d", "slide1d", "long1d", "enlarge1d", "shelf2d",
                              "learned2d", "paper1d", "dg1d", "copycal"])
@@ -574,7 +575,7 @@ def main():
     elif args.workload == "shelf2d":
         steps = args.steps or 50
         warmup = args.warmup if args.warmup is not None else 40
-        res = run_2d(B, torch, S, steps, warmup)
+        res = run_2d(B, torch, S, steps, warmup, args.preroll or 0)
         print(json.dumps(res), flush=True)
 
 
@@ -711,20 +712,52 @@ def run_dg1d(B, torch, S, reps):
                               "cyclic reduction)"}}
 
 
-def run_2d(B, torch, S, steps, warmup):
+def preroll_2d(B, torch, S, c, nsteps, chunk=250):
+    """the shelf's adaptive FP32 run from t = 0 for nsteps untimed steps
+    (progress logged per chunk); returns (h, hu, hv, hw, p, t, trajectory)"""
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    ctx = B.context_2d(c, crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.5, tol=1e-10, max_iter=5000,
+                       warm=1, precision=1)
+    ctx.set_time(0.0)
+    h, hu, hv, hw = f(c.h), f(c.hu), f(c.hv), f(c.hw)
+    p = torch.zeros_like(h)
+    traj, done = [], 0
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        t0 = time.perf_counter()
+        ctx.step(h, hu, hv, hw, p, nsteps=k)
+        st = ctx.sync_stats()
+        el = time.perf_counter() - t0
+        if st["status"] != 0:
+            raise RuntimeError(f"shelf pre-roll: status {st}")
+        done += k
+        row = {"step": done, "t": float(ctx.get_time()[0]), "n_active": st["n_active"],
+               "ms_per_step": 1e3 * el / k}
+        traj.append(row)
+        log("pre-roll", json.dumps(row))
+    return h, hu, hv, hw, p, float(ctx.get_time()[0]), traj
+
+
+def run_2d(B, torch, S, steps, warmup, preroll=0):
     c = S.shelf_case_2d()
     dev = torch.device("cuda:0")
     f = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    start = preroll_2d(B, torch, S, c, preroll) if preroll > 0 else None
     out = {}
     for name, kw in (("adaptive_fp32", dict(crit=S.CRIT_ETA_D, precision=1)),
                      ("adaptive_fp64", dict(crit=S.CRIT_ETA_D, precision=0)),
                      ("global_fp32", dict(crit=S.CRIT_GLOBAL, precision=1))):
         ctx = B.context_2d(c, k_nh=1e-3, enlarge=1, cfl=0.5, tol=1e-10, max_iter=5000, warm=1,
                            **kw)
-        ctx.set_time(0.0)
         log(f"{name}: {warmup} warmup + {steps} timed steps")
-        h, hu, hv, hw = f(c.h), f(c.hu), f(c.hv), f(c.hw)
-        p = torch.zeros_like(h)
+        if start is None:
+            ctx.set_time(0.0)
+            h, hu, hv, hw = f(c.h), f(c.hu), f(c.hv), f(c.hw)
+            p = torch.zeros_like(h)
+        else:
+            ctx.set_time(start[5])
+            h, hu, hv, hw, p = (a.clone() for a in start[:5])
         ctx.step(h, hu, hv, hw, p, nsteps=warmup)
         st = ctx.sync_stats()
         if st["status"] != 0:
@@ -755,7 +788,8 @@ def run_2d(B, torch, S, steps, warmup):
             "config": {"workload": "2D 2048x2048 shelf, dx=1 m, 50 m depth + Gaussian-correlated "
                                    "perturbation (sigma 2 m, 40 m), Gaussian mound 3 m / 60 m at "
                                    "8 m/s, adaptive |eta/d|, FP32 PCG + FP64 refinement, tol 1e-10",
-                       "cells": c.nx * c.ny},
+                       "cells": c.nx * c.ny, "preroll_steps": preroll,
+                       "preroll": start[6] if start is not None else None},
             "roofline": {"kernel": "k_pred2d", "bound": "hbm", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "traffic": pmc_traffic("pred2d_shelf2048_pmc.txt",

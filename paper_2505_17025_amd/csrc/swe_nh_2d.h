@@ -18,11 +18,21 @@ constexpr int CMAX2 = 128;     // most active tiles for which the solver adds th
 constexpr int MG_MAXL = 12;    // most levels of the multigrid preconditioner (global extension)
 constexpr int MG_BUDGET = 32;  // iterations of the multigrid-preconditioned CG in a step
 constexpr int MG_COARSE_MAX = 4096;  // most cells of the multigrid's coarsest level (one block)
+// active tiles above which an adaptive step's system goes to the multigrid CG
+// on the active tiles' bounding box: up to CMAX2 tiles the tile solver has
+// its coarse space and its pipelined iterations (7-9 us each) cost less than
+// the multigrid's launches (about 90 us per iteration however small the box);
+// beyond, its iteration count grows with the marked area (on the 2048^2
+// shelf: 3-12 ms per step against 2.5-3.1 ms with the multigrid)
+constexpr int MG_MIN_TILES = CMAX2;
 
 // scalars of the multigrid-preconditioned CG (device)
 struct MgState {
-  int done;  // 0 running, 1 converged, 2 stopped on a non-finite residual
-  int it;    // iterations taken
+  int done;    // 0 running, 1 converged, 2 stopped on a non-finite residual
+  int it;      // iterations taken
+  int use;     // 1: this step's system is solved by the multigrid CG
+  int ok;      // 1: the multigrid CG met the tolerance (its true residual)
+  int box[4];  // x0, y0, x1, y1: the cells it works on (multiples of 2^levels)
   double rho, beta, alpha, rr, bb;
 };
 
@@ -116,6 +126,10 @@ struct Ctx2D {
 int mg_plan_levels(int nx, int ny, int* lnx, int* lny);
 // block partial sums one reduction of that solver needs at most
 int mg_partials(int nx, int ny);
+// this step's box and choice: the whole grid (global), or the bounding box of
+// the active tiles when there are more than MG_MIN_TILES of them; the cells
+// of inactive tiles inside the box get identity rows
+void launch_mg_box2d(Ctx2D* x, bool global, hipStream_t s);
 // the global extension's solve of A x = b (x holds the initial guess): CG in
 // FP64 preconditioned by one FP32 V-cycle, at most budget iterations.  With
 // last, a solve that misses the tolerance sets the no-convergence status;

@@ -980,6 +980,7 @@ struct PcgArgs {
   double tol, tol_in;
   int max_iter;
   const int* skip;  // the solve returns at once when *skip == 1 (null: never)
+  const int* used;  // iterations another solver already spent on this system (null: none)
 };
 
 template <typename T, typename V>
@@ -1822,9 +1823,11 @@ __global__ void __launch_bounds__(NT2) k_pcg2d_pipe(PcgArgs<R> A) {
   if (nlist < 1 || nlist > PCG_K * A.pipe_blocks) return;  // the other form's case
   const int G = (nlist + PCG_K - 1) / PCG_K;
   if ((int)blockIdx.x >= G) return;
+  PcgArgs<R> B = A;
+  if (B.used) B.max_iter -= *B.used;
   // every block reads the tag base before block 0 can pass its first pass
   const unsigned base = *A.tag_base;
-  const unsigned used = pcg_pipelined<R, PCG_K>(A, share_of(G, nlist), G, zt, crows, base);
+  const unsigned used = pcg_pipelined<R, PCG_K>(B, share_of(G, nlist), G, zt, crows, base);
   // no block is more than one pass ahead of block 0, even after an abort
   if (blockIdx.x == 0 && threadIdx.x == 0) *A.tag_base = base + used + 2;
 }
@@ -1837,7 +1840,9 @@ __global__ void __launch_bounds__(NT2) k_pcg2d_cg(PcgArgs<R> A) {
   if (nlist >= 1 && nlist <= PCG_K * A.pipe_blocks) return;  // the pipelined form's case
   const int G = max(1, min((int)gridDim.x, nlist));
   if ((int)blockIdx.x >= G) return;
-  pcg_cg(A, share_of(G, nlist), G, zt);
+  PcgArgs<R> B = A;
+  if (B.used) B.max_iter -= *B.used;
+  pcg_cg(B, share_of(G, nlist), G, zt);
 }
 
 // ---- coarse space of the preconditioner ----
@@ -2128,6 +2133,7 @@ PcgArgs<R> pcg_common(const swe_nh_config* c, Ctx2D* x) {
   A.pt = x->pt;
   A.tag_base = x->tag_base;
   A.skip = nullptr;
+  A.used = nullptr;
   return A;
 }
 
@@ -2173,10 +2179,10 @@ __global__ void k_copy_masked2d(const double* __restrict__ x, const uint8_t* __r
 }
 
 // the tile solver on the system in x (its initial guess in x->x); with
-// skip, it returns at once when *skip == 1, and runs at most max_iter
-// iterations
+// skip, it returns at once when *skip == 1; it runs at most max_iter
+// iterations less *used (when given)
 void launch_tile_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, bool coarse,
-                         const int* skip, int max_iter) {
+                         const int* skip, const int* used) {
   hipLaunchKernelGGL(k_bar_reset, dim3((x->ntiles + 255) / 256), dim3(256), 0, s, x->bar, x->tflag,
                      x->ntiles);
   if (coarse) {
@@ -2193,13 +2199,13 @@ void launch_tile_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, bool c
   if (c->precision == 1) {
     PcgArgs<float> A = pcg_args32(c, x);
     A.skip = skip;
-    A.max_iter = max_iter;
+    A.used = used;
     hipLaunchKernelGGL(k_pcg2d_pipe<float>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
     hipLaunchKernelGGL(k_pcg2d_cg<float>, dim3(x->grid_pcg), dim3(NT2), 0, s, A);
   } else {
     PcgArgs<double> A = pcg_args64(c, x);
     A.skip = skip;
-    A.max_iter = max_iter;
+    A.used = used;
     hipLaunchKernelGGL(k_pcg2d_pipe<double>, dim3(x->grid_pipe), dim3(NT2), 0, s, A);
     hipLaunchKernelGGL(k_pcg2d_cg<double>, dim3(x->grid_pcg), dim3(NT2), 0, s, A);
   }
@@ -2207,18 +2213,20 @@ void launch_tile_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, bool c
 
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
   if (x->mg_levels > 0) {
-    // the multigrid CG for up to MG_BUDGET iterations (a captured step cannot
-    // size a launch sequence by the iteration count); if it has not met the
-    // tolerance by then, the tile solver continues from its iterate
-    const bool more = c->max_iter > MG_BUDGET;
-    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), !more, s);
-    if (more) {
-      launch_tile_solve2d(c, x, s, false, &x->mg_args.st->done, c->max_iter - MG_BUDGET);
-      launch_mg_account2d(x, s);
-    }
+    // the multigrid CG on its box (the whole grid in the global extension,
+    // the active tiles' bounding box when they are many) for up to MG_BUDGET
+    // iterations (a captured step cannot size a launch sequence by the
+    // iteration count); the tile solver takes the step when the multigrid
+    // is not chosen, and continues from its iterate when it has not met the
+    // tolerance by then
+    const bool global = c->crit == SWE_NH_CRIT_GLOBAL;
+    launch_mg_box2d(x, global, s);
+    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), false, s);
+    launch_tile_solve2d(c, x, s, !global, &x->mg_args.st->ok, &x->mg_args.st->it);
+    launch_mg_account2d(x, s);
     return;
   }
-  launch_tile_solve2d(c, x, s, true, nullptr, c->max_iter);
+  launch_tile_solve2d(c, x, s, true, nullptr, nullptr);
 }
 
 }  // namespace
@@ -2282,9 +2290,10 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->iters_sum = (long long*)take(8);
   x->rel = (double*)take(8);
   x->mg_levels = 0;
-  if (c->crit == SWE_NH_CRIT_GLOBAL) {
-    // every cell is marked: CG with a multigrid preconditioner when the grid
-    // coarsens to at most MG_COARSE_MAX cells by 2 x 2 aggregation
+  if (c->crit != SWE_NH_CRIT_NONE) {
+    // CG with a multigrid preconditioner for the global extension and for
+    // large active areas, when the grid coarsens to at most MG_COARSE_MAX
+    // cells by 2 x 2 aggregation
     x->mg_levels = mg_plan_levels(c->nx, c->ny, x->mg_nx, x->mg_ny);
     const int L = x->mg_levels;
     for (int l = 1; l <= L; l++) {

@@ -10,14 +10,12 @@
 // coarser grids.
 //
 // Levels: cells aggregated 2 x 2 while both extents stay even and the grid
-// holds more than MG_COARSE_MAX cells.  Coarse operators by Galerkin
-// projection with piecewise-constant transfers (R = sum over the four
-// children, P = R^T): again 5-point, computed once per solve.  One V-cycle:
-// on each level one red-black Gauss-Seidel sweep from zero, restriction of
-// the residual, correction from the coarser level scaled by MG_OMEGA
-// (piecewise-constant prolongation under-corrects smooth error by about half;
-// over-correction restores the convergence rate), then one black-red sweep,
-// so that the V-cycle is a symmetric operator; on the coarsest level (at most
+// holds more than MG_COARSE_MAX cells, with the coarse operators of
+// k_mg_coarsen (5-point, computed once per solve).  One V-cycle: on each
+// level one red-black Gauss-Seidel sweep from zero, restriction of the
+// residual (R = sum over the four children), the coarser level's correction
+// added piecewise constant (P = R^T), then one black-red sweep, so that the
+// V-cycle is a symmetric operator; on the coarsest level (at most
 // MG_COARSE_MAX cells, one block, in LDS) MG_COARSE_SWEEPS symmetric sweeps
 // from zero.  The V-cycle runs in FP32; the Krylov vectors, the operator of
 // the iteration and every dot product are FP64, so the solution is an FP64
@@ -47,15 +45,26 @@ namespace {
 
 constexpr int NTM = 256;             // threads per block of the level kernels
 constexpr int MG_GRID_MAX = 2048;    // most blocks of a level kernel (grid-stride)
-constexpr float MG_OMEGA = 1.8f;     // coarse-correction scale
-constexpr int MG_COARSE_SWEEPS = 1;  // symmetric sweeps on the coarsest level
+constexpr int MG_COARSE_SWEEPS = 4;  // symmetric sweeps on the coarsest level
 
 struct Lvl {
-  int nx, ny;
+  int nx, ny, l;  // cells, level
   const float *C, *E, *N;
 };
 
-__device__ __forceinline__ bool done_of(const MgState* s) { return s->done != 0; }
+// the cells of level l the solve works on: the level-0 box (multiples of
+// 2^levels) halved l times
+struct Box {
+  int x0, y0, x1, y1;
+  __device__ bool in(int i, int j) const { return i >= x0 && j >= y0 && i < x1 && j < y1; }
+};
+__device__ __forceinline__ Box box_of(const MgState* st, int l) {
+  return Box{st->box[0] >> l, st->box[1] >> l, st->box[2] >> l, st->box[3] >> l};
+}
+
+// the kernels of an iteration return at once when the multigrid CG is not
+// this step's solver or has converged
+__device__ __forceinline__ bool idle(const MgState* s) { return !s->use || s->done != 0; }
 
 // block sum of v (every thread of the block calls) -> part[blockIdx.x]
 template <int NT = NTM>
@@ -80,25 +89,49 @@ int blocks_for(int64_t n) {
 // ---------------------------------------------------------------------------
 // level operators
 // ---------------------------------------------------------------------------
-// Galerkin coarse operator R A P of the aggregates of 2 x 2 cells: the
-// children's diagonals plus twice the couplings inside the aggregate; the
-// couplings across its east and north edges.
+// Coarse operator of the aggregates of 2 x 2 cells.  The Galerkin product
+// R A P with piecewise-constant P keeps the mass-like part of A (its
+// diagonal excess over the couplings, M = C + sum of the row's couplings,
+// which are negative) exactly, but weighs the Laplacian-like rest about
+// twice too strongly for smooth error, so the coarse correction would come
+// out about half as large as it should.  The coarse operator is therefore
+// (R A P + diag(R M+ P)) / 2, M+ = max(M, 0): couplings half the Galerkin
+// ones, diagonal half the Galerkin diagonal plus half the children's mass.
+// It is symmetric positive definite (half an SPD matrix plus a non-negative
+// diagonal), so the V-cycle is an SPD preconditioner without any scaling of
+// its coarse correction.
 __global__ void __launch_bounds__(NTM) k_mg_coarsen(int nxf, const float* __restrict__ Cf,
                                                      const float* __restrict__ Ef,
                                                      const float* __restrict__ Nf, int nxc,
-                                                     int nyc, float* __restrict__ Cc,
+                                                     int lc, float* __restrict__ Cc,
                                                      float* __restrict__ Ec,
-                                                     float* __restrict__ Nc) {
-  const int64_t n = (int64_t)nxc * nyc;
+                                                     float* __restrict__ Nc, const MgState* st) {
+  if (!st->use) return;
+  const Box Bc = box_of(st, lc);
+  const int bw = Bc.x1 - Bc.x0;
+  const int64_t n = (int64_t)bw * (Bc.y1 - Bc.y0);
   for (int64_t o = blockIdx.x * (int64_t)NTM + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * NTM) {
-    const int I = (int)(o % nxc), J = (int)(o / nxc);
+    const int I = Bc.x0 + (int)(o % bw), J = Bc.y0 + (int)(o / bw);
+    const int64_t c = (int64_t)J * nxc + I;
     const int64_t f00 = (int64_t)(2 * J) * nxf + 2 * I, f01 = f00 + 1, f10 = f00 + nxf,
                   f11 = f10 + 1;
-    Cc[o] = Cf[f00] + Cf[f01] + Cf[f10] + Cf[f11] + 2.0f * (Ef[f00] + Ef[f10]) +
-            2.0f * (Nf[f00] + Nf[f01]);
-    Ec[o] = I + 1 < nxc ? Ef[f01] + Ef[f11] : 0.0f;
-    Nc[o] = J + 1 < nyc ? Nf[f10] + Nf[f11] : 0.0f;
+    const bool w = I > Bc.x0, e = I + 1 < Bc.x1, s = J > Bc.y0, nn = J + 1 < Bc.y1;
+    // the children's couplings: inside the aggregate, and across its edges
+    const float ei0 = Ef[f00], ei1 = Ef[f10], ni0 = Nf[f00], ni1 = Nf[f01];
+    const float ee0 = e ? Ef[f01] : 0.0f, ee1 = e ? Ef[f11] : 0.0f;
+    const float ew0 = w ? Ef[f00 - 1] : 0.0f, ew1 = w ? Ef[f10 - 1] : 0.0f;
+    const float nn0 = nn ? Nf[f10] : 0.0f, nn1 = nn ? Nf[f11] : 0.0f;
+    const float ns0 = s ? Nf[f00 - nxf] : 0.0f, ns1 = s ? Nf[f01 - nxf] : 0.0f;
+    const float c00 = Cf[f00], c01 = Cf[f01], c10 = Cf[f10], c11 = Cf[f11];
+    const float gal = c00 + c01 + c10 + c11 + 2.0f * (ei0 + ei1) + 2.0f * (ni0 + ni1);
+    const float mass = fmaxf(c00 + ew0 + ei0 + ns0 + ni0, 0.0f) +
+                       fmaxf(c01 + ei0 + ee0 + ns1 + ni1, 0.0f) +
+                       fmaxf(c10 + ew1 + ei1 + ni0 + nn0, 0.0f) +
+                       fmaxf(c11 + ei1 + ee1 + ni1 + nn1, 0.0f);
+    Cc[c] = 0.5f * (gal + mass);
+    Ec[c] = 0.5f * (ee0 + ee1);
+    Nc[c] = 0.5f * (nn0 + nn1);
   }
 }
 
@@ -106,9 +139,9 @@ __global__ void __launch_bounds__(NTM) k_mg_coarsen(int nxf, const float* __rest
 // smoothing sweeps on LDS tiles
 // ---------------------------------------------------------------------------
 // A block takes MTX x MTY cells of a level plus a ring of two cells (the
-// right-hand side and the operator, FP32, in LDS; cells off the grid have
+// right-hand side and the operator, FP32, in LDS; cells outside the box have
 // C = 1 and no couplings, so their values stay 0) and one thread per 2 x 2
-// aggregate of the tile.  The pre-smoothing sweep from zero is never stored:
+// aggregate of the tile; blocks whose tile misses the box return at once.  The pre-smoothing sweep from zero is never stored:
 // its red values are b / C and its black values follow from those, so the
 // kernel of the way up recomputes them.
 constexpr int MTX = 64, MTY = 32;                // cells of a tile (even)
@@ -122,12 +155,12 @@ struct MgTile {
 __device__ __forceinline__ int tiles_x_of(int nx) { return (nx + MTX - 1) / MTX; }
 
 // The tile's right-hand side and operator into LDS, and the red cells'
-// starting values: b / C from zero, plus omega times the coarse correction e
-// of their aggregate on the way up (UP).  Every load of a thread is issued
+// starting values: b / C from zero, plus the coarse correction e of their
+// aggregate on the way up (UP).  Every load of a thread is issued
 // before its first store.
 template <bool UP, typename B>
-__device__ void load_tile(MgTile& T, const Lvl& L, const B* __restrict__ b, int i0, int j0,
-                          int nxc, const float* __restrict__ e) {
+__device__ void load_tile(MgTile& T, const Lvl& L, const Box& Bx, const B* __restrict__ b, int i0,
+                          int j0, int nxc, const float* __restrict__ e) {
   constexpr int KN = (RN + MNT - 1) / MNT;
   float bb[KN], cc[KN], ee[KN], nn[KN], cor[KN];
 #pragma unroll
@@ -139,7 +172,7 @@ __device__ void load_tile(MgTile& T, const Lvl& L, const B* __restrict__ b, int 
     ee[k] = 0.0f;
     nn[k] = 0.0f;
     cor[k] = 0.0f;
-    if (w < RN && i >= 0 && j >= 0 && i < L.nx && j < L.ny) {
+    if (w < RN && Bx.in(i, j)) {
       const int64_t o = (int64_t)j * L.nx + i;
       bb[k] = (float)b[o];
       cc[k] = L.C[o];
@@ -156,7 +189,7 @@ __device__ void load_tile(MgTile& T, const Lvl& L, const B* __restrict__ b, int 
     T.C[w] = cc[k];
     T.E[w] = ee[k];
     T.N[w] = nn[k];
-    if ((((w % RX) + (w / RX)) & 1) == 0) T.v[w] = bb[k] / cc[k] + (UP ? MG_OMEGA * cor[k] : 0.0f);
+    if ((((w % RX) + (w / RX)) & 1) == 0) T.v[w] = bb[k] / cc[k] + (UP ? cor[k] : 0.0f);
   }
 }
 
@@ -186,18 +219,20 @@ __device__ __forceinline__ int agg_w00() {
 // aggregates restricted to the coarse right-hand side bc (the residual is
 // zero on the black cells, just updated)
 template <typename B>
-__global__ void __launch_bounds__(MNT) k_mg_down(Lvl L, const B* __restrict__ b, int nxc, int nyc,
+__global__ void __launch_bounds__(MNT) k_mg_down(Lvl L, const B* __restrict__ b, int nxc,
                                                   float* __restrict__ bc, const MgState* st) {
-  if (done_of(st)) return;
-  __shared__ MgTile T;
+  if (idle(st)) return;
+  const Box Bx = box_of(st, L.l), Bc = box_of(st, L.l + 1);
   const int tx = tiles_x_of(L.nx);
   const int i0 = (blockIdx.x % tx) * MTX, j0 = (blockIdx.x / tx) * MTY;
-  load_tile<false>(T, L, b, i0, j0, 0, nullptr);
+  if (i0 >= Bx.x1 || j0 >= Bx.y1 || i0 + MTX <= Bx.x0 || j0 + MTY <= Bx.y0) return;
+  __shared__ MgTile T;
+  load_tile<false>(T, L, Bx, b, i0, j0, 0, nullptr);
   __syncthreads();
   black_sweep(T);
   __syncthreads();
   const int I = i0 / 2 + threadIdx.x % (MTX / 2), J = j0 / 2 + threadIdx.x / (MTX / 2);
-  if (I < nxc && J < nyc) {
+  if (Bc.in(I, J)) {
     const int w00 = agg_w00(), w11 = w00 + RX + 1;
     const float r00 = T.b[w00] - T.C[w00] * T.v[w00] - off_sum(T, w00);
     const float r11 = T.b[w11] - T.C[w11] * T.v[w11] - off_sum(T, w11);
@@ -205,26 +240,31 @@ __global__ void __launch_bounds__(MNT) k_mg_down(Lvl L, const B* __restrict__ b,
   }
 }
 
-// the way up: the pre-smoothed red values plus omega times the coarse
-// correction e of their aggregate, post-smoothing (black, then red), the
+// the way up: the pre-smoothed red values plus the coarse correction e of
+// their aggregate, post-smoothing (black, then red), the
 // result to z; on the finest level (part != null) also the block's partial
 // sum of r . z with the FP64 residual r = b
 template <typename B>
 __global__ void __launch_bounds__(MNT) k_mg_up(Lvl L, const B* __restrict__ b, int nxc,
                                                 const float* __restrict__ e, float* __restrict__ z,
                                                 double* __restrict__ part, const MgState* st) {
-  if (done_of(st)) return;
-  __shared__ MgTile T;
+  if (idle(st)) return;
+  const Box Bx = box_of(st, L.l);
   const int tx = tiles_x_of(L.nx);
   const int i0 = (blockIdx.x % tx) * MTX, j0 = (blockIdx.x / tx) * MTY;
-  load_tile<true>(T, L, b, i0, j0, nxc, e);
+  if (i0 >= Bx.x1 || j0 >= Bx.y1 || i0 + MTX <= Bx.x0 || j0 + MTY <= Bx.y0) {
+    if (part && threadIdx.x == 0) part[blockIdx.x] = 0.0;  // a tile with no work adds nothing
+    return;
+  }
+  __shared__ MgTile T;
+  load_tile<true>(T, L, Bx, b, i0, j0, nxc, e);
   __syncthreads();
   black_sweep(T);
   __syncthreads();
   const int ax = threadIdx.x % (MTX / 2), ay = threadIdx.x / (MTX / 2);
   const int i = i0 + 2 * ax, j = j0 + 2 * ay;
   double acc = 0.0;
-  if (i < L.nx && j < L.ny) {
+  if (Bx.in(i, j)) {
     const int w00 = agg_w00(), w11 = w00 + RX + 1;
     const float z00 = (T.b[w00] - off_sum(T, w00)) / T.C[w00];
     const float z11 = (T.b[w11] - off_sum(T, w11)) / T.C[w11];
@@ -250,29 +290,33 @@ constexpr int KC = MG_COARSE_MAX / NTC;
 static_assert(MG_COARSE_MAX % NTC == 0, "the coarsest level's cells split evenly over its threads");
 __global__ void __launch_bounds__(NTC) k_mg_coarsest(Lvl L, const float* __restrict__ b,
                                                       float* __restrict__ x, const MgState* st) {
-  if (done_of(st)) return;
+  if (idle(st)) return;
   __shared__ float sx[MG_COARSE_MAX];
   const int n = L.nx * L.ny;
+  const Box Bx = box_of(st, L.l);
   float rb[KC], ic[KC], cw[KC], ce[KC], cs[KC], cn[KC];
   int nw[KC], ne[KC], ns[KC], nn[KC], col[KC];
 #pragma unroll
   for (int k = 0; k < KC; k++) {
     const int o = threadIdx.x + k * NTC;
-    const bool in = o < n;
-    const int i = in ? o % L.nx : 0, j = in ? o / L.nx : 0;
-    const bool w = in && i > 0, e = in && i + 1 < L.nx, s = in && j > 0, nr = in && j + 1 < L.ny;
+    const int i = o < n ? o % L.nx : 0, j = o < n ? o / L.nx : 0;
+    const bool in = o < n && Bx.in(i, j);
+    const bool w = in && i > Bx.x0, e = in && i + 1 < Bx.x1, s = in && j > Bx.y0,
+               nr = in && j + 1 < Bx.y1;
     rb[k] = in ? b[o] : 0.0f;
     ic[k] = in ? 1.0f / L.C[o] : 0.0f;
     cw[k] = w ? L.E[o - 1] : 0.0f;
     ce[k] = e ? L.E[o] : 0.0f;
     cs[k] = s ? L.N[o - L.nx] : 0.0f;
     cn[k] = nr ? L.N[o] : 0.0f;
-    nw[k] = w ? o - 1 : 0;
-    ne[k] = e ? o + 1 : 0;
-    ns[k] = s ? o - L.nx : 0;
-    nn[k] = nr ? o + L.nx : 0;
+    // a missing neighbour points at the cell itself (with a zero coupling):
+    // every value read is one the block has written
+    nw[k] = w ? o - 1 : o;
+    ne[k] = e ? o + 1 : o;
+    ns[k] = s ? o - L.nx : o;
+    nn[k] = nr ? o + L.nx : o;
     col[k] = in ? (i + j) & 1 : 2;
-    if (in) sx[o] = 0.0f;
+    sx[o] = 0.0f;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 2 * MG_COARSE_SWEEPS; sweep++) {
@@ -293,31 +337,128 @@ __global__ void __launch_bounds__(NTC) k_mg_coarsest(Lvl L, const float* __restr
 }
 
 // ---------------------------------------------------------------------------
+// this step's box and choice
+// ---------------------------------------------------------------------------
+// The multigrid CG solves the system on a box of whole aggregates of the
+// coarsest level: the whole grid in the global extension, else the bounding
+// box of the active tiles when there are more than min_tiles of them (below
+// that, the tile solver's iterations cost less than the levels' launches).
+// One block.
+__global__ void __launch_bounds__(1024) k_mg_box(MgState* st, const int* __restrict__ tile_list,
+                                                 const int* n_list, int tiles_x, int tx2, int ty2,
+                                                 int nx, int ny, int align, int global,
+                                                 int min_tiles) {
+  __shared__ int red[4][1024 / 64];
+  const int nl = *n_list;
+  int v[4] = {1 << 30, 1 << 30, -1, -1};  // tile x0, y0, x1, y1
+  if (!global)
+    for (int t = threadIdx.x; t < nl; t += 1024) {
+      const int tile = tile_list[t], tx = tile % tiles_x, ty = tile / tiles_x;
+      v[0] = min(v[0], tx);
+      v[1] = min(v[1], ty);
+      v[2] = max(v[2], tx);
+      v[3] = max(v[3], ty);
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    v[0] = min(v[0], __shfl_xor(v[0], o));
+    v[1] = min(v[1], __shfl_xor(v[1], o));
+    v[2] = max(v[2], __shfl_xor(v[2], o));
+    v[3] = max(v[3], __shfl_xor(v[3], o));
+  }
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < 1024 / 64; w++) {
+    v[0] = min(v[0], red[0][w]);
+    v[1] = min(v[1], red[1][w]);
+    v[2] = max(v[2], red[2][w]);
+    v[3] = max(v[3], red[3][w]);
+  }
+  int b[4] = {0, 0, nx, ny};
+  int use = 1;
+  if (!global) {
+    use = nl > min_tiles ? 1 : 0;
+    if (use) {
+      b[0] = (v[0] * tx2) / align * align;
+      b[1] = (v[1] * ty2) / align * align;
+      b[2] = min(((v[2] + 1) * tx2 + align - 1) / align * align, nx);
+      b[3] = min(((v[3] + 1) * ty2 + align - 1) / align * align, ny);
+    }
+  }
+  for (int k = 0; k < 4; k++) st->box[k] = b[k];
+  st->use = use;
+  st->ok = 0;
+  st->done = 0;
+  st->it = 0;
+}
+
+// identity rows (and a zero right-hand side and guess) on the cells of the
+// box whose tiles hold no marked cell: the assembly visits only the active
+// tiles.  One block per tile.
+__global__ void __launch_bounds__(256) k_mg_identity(const MgState* st,
+                                                     const int* __restrict__ tile_pos,
+                                                     int tiles_x, int tx2, int ty2, int nx,
+                                                     double* dg, double* ce, double* cn, double* b,
+                                                     double* x, float* dg32, float* ce32,
+                                                     float* cn32, uint8_t* nb) {
+  if (!st->use || tile_pos[blockIdx.x] >= 0) return;
+  const Box Bx = box_of(st, 0);
+  const int i0 = (blockIdx.x % tiles_x) * tx2, j0 = (blockIdx.x / tiles_x) * ty2;
+  for (int c = threadIdx.x; c < tx2 * ty2; c += 256) {
+    const int i = i0 + c % tx2, j = j0 + c / tx2;
+    if (!Bx.in(i, j)) continue;
+    const int64_t o = (int64_t)j * nx + i;
+    dg[o] = 1.0;
+    ce[o] = 0.0;
+    cn[o] = 0.0;
+    b[o] = 0.0;
+    x[o] = 0.0;
+    dg32[o] = 1.0f;
+    ce32[o] = 0.0f;
+    cn32[o] = 0.0f;
+    nb[o] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // conjugate gradients (FP64)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double apply5_64(const double* dg, const double* ce, const double* cn,
-                                            const double* v, int64_t o, int i, int j, int nx,
-                                            int ny) {
-  double a = dg[o] * v[o];
-  if (i > 0) a += ce[o - 1] * v[o - 1];
-  if (i + 1 < nx) a += ce[o] * v[o + 1];
-  if (j > 0) a += cn[o - nx] * v[o - nx];
-  if (j + 1 < ny) a += cn[o] * v[o + nx];
+// A x at cell (i, j) of the box (couplings across the box's edge are zero:
+// the cells beyond it hold no marked cell)
+__device__ __forceinline__ double apply5_64(const MgArgs& A, const Box& Bx, const double* v,
+                                            int64_t o, int i, int j) {
+  double a = A.dg[o] * v[o];
+  if (i > Bx.x0) a += A.ce[o - 1] * v[o - 1];
+  if (i + 1 < Bx.x1) a += A.ce[o] * v[o + 1];
+  if (j > Bx.y0) a += A.cn[o - A.nx] * v[o - A.nx];
+  if (j + 1 < Bx.y1) a += A.cn[o] * v[o + A.nx];
   return a;
+}
+
+// grid-stride loop over the cells of the box: f(o, i, j) with o = j nx + i
+template <typename F>
+__device__ __forceinline__ void for_box(const MgArgs& A, const Box& Bx, F f) {
+  const int bw = Bx.x1 - Bx.x0;
+  const int64_t n = (int64_t)bw * (Bx.y1 - Bx.y0);
+  for (int64_t k = blockIdx.x * (int64_t)NTM + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * NTM) {
+    const int i = Bx.x0 + (int)(k % bw), j = Bx.y0 + (int)(k / bw);
+    f((int64_t)j * A.nx + i, i, j);
+  }
 }
 
 // r = b - A x, partial sums of r.r and b.b
 __global__ void __launch_bounds__(NTM) k_cg_init(MgArgs A) {
-  const int64_t n = (int64_t)A.nx * A.ny;
+  if (!A.st->use) return;
+  const Box Bx = box_of(A.st, 0);
   double rr = 0.0, bb = 0.0;
-  for (int64_t o = blockIdx.x * (int64_t)NTM + threadIdx.x; o < n;
-       o += (int64_t)gridDim.x * NTM) {
-    const int i = (int)(o % A.nx), j = (int)(o / A.nx);
-    const double r = A.b[o] - apply5_64(A.dg, A.ce, A.cn, A.x, o, i, j, A.nx, A.ny);
+  for_box(A, Bx, [&](int64_t o, int i, int j) {
+    const double r = A.b[o] - apply5_64(A, Bx, A.x, o, i, j);
     A.r[o] = r;
     rr += r * r;
     bb += A.b[o] * A.b[o];
-  }
+  });
   block_partial(rr, A.part);
   block_partial(bb, A.part + A.npart);
 }
@@ -326,47 +467,44 @@ __global__ void __launch_bounds__(NTM) k_cg_init(MgArgs A) {
 // q = A p, partial sums of p.q
 __global__ void __launch_bounds__(NTM) k_cg_pq(MgArgs A) {
   const MgState* st = A.st;
-  if (done_of(st)) return;
+  if (idle(st)) return;
+  const Box Bx = box_of(st, 0);
   const int par = st->it & 1;
   const double* po = A.p[par ^ 1];
   double* pn = A.p[par];
   const double beta = st->beta;
-  const int64_t n = (int64_t)A.nx * A.ny;
   // the first direction is z itself (p_old is not read: it may hold anything)
   const bool first = st->it == 0;
   auto pv = [&](int64_t o) { return first ? (double)A.z[o] : (double)A.z[o] + beta * po[o]; };
   double pq = 0.0;
-  for (int64_t o = blockIdx.x * (int64_t)NTM + threadIdx.x; o < n;
-       o += (int64_t)gridDim.x * NTM) {
-    const int i = (int)(o % A.nx), j = (int)(o / A.nx);
+  for_box(A, Bx, [&](int64_t o, int i, int j) {
     const double pc = pv(o);
     double q = A.dg[o] * pc;
-    if (i > 0) q += A.ce[o - 1] * pv(o - 1);
-    if (i + 1 < A.nx) q += A.ce[o] * pv(o + 1);
-    if (j > 0) q += A.cn[o - A.nx] * pv(o - A.nx);
-    if (j + 1 < A.ny) q += A.cn[o] * pv(o + A.nx);
+    if (i > Bx.x0) q += A.ce[o - 1] * pv(o - 1);
+    if (i + 1 < Bx.x1) q += A.ce[o] * pv(o + 1);
+    if (j > Bx.y0) q += A.cn[o - A.nx] * pv(o - A.nx);
+    if (j + 1 < Bx.y1) q += A.cn[o] * pv(o + A.nx);
     pn[o] = pc;
     A.q[o] = q;
     pq += pc * q;
-  }
+  });
   block_partial(pq, A.part);
 }
 
 // x += alpha p, r -= alpha q, partial sums of r.r
 __global__ void __launch_bounds__(NTM) k_cg_update(MgArgs A) {
   const MgState* st = A.st;
-  if (done_of(st)) return;
+  if (idle(st)) return;
+  const Box Bx = box_of(st, 0);
   const double* p = A.p[st->it & 1];
   const double alpha = st->alpha;
-  const int64_t n = (int64_t)A.nx * A.ny;
   double rr = 0.0;
-  for (int64_t o = blockIdx.x * (int64_t)NTM + threadIdx.x; o < n;
-       o += (int64_t)gridDim.x * NTM) {
+  for_box(A, Bx, [&](int64_t o, int, int) {
     A.x[o] += alpha * p[o];
     const double r = A.r[o] - alpha * A.q[o];
     A.r[o] = r;
     rr += r * r;
-  }
+  });
   block_partial(rr, A.part);
 }
 
@@ -389,7 +527,7 @@ __device__ double sum_partials(const double* part, int nb) {
 // convergence test, the iteration count)
 __global__ void __launch_bounds__(1024) k_cg_scalars(MgArgs A, int what, int nb) {
   MgState* st = A.st;
-  if (what != 0 && st->done) return;
+  if (!st->use || (what != 0 && st->done)) return;
   const double s = sum_partials(A.part, nb);
   if (what == 0) {
     const double bb = sum_partials(A.part + A.npart, nb);
@@ -417,27 +555,27 @@ __global__ void __launch_bounds__(1024) k_cg_scalars(MgArgs A, int what, int nb)
 
 // partial sums of the true residual ||b - A x||^2 of the final iterate
 __global__ void __launch_bounds__(NTM) k_cg_true(MgArgs A) {
-  const int64_t n = (int64_t)A.nx * A.ny;
+  if (!A.st->use) return;
+  const Box Bx = box_of(A.st, 0);
   double rr = 0.0;
-  for (int64_t o = blockIdx.x * (int64_t)NTM + threadIdx.x; o < n;
-       o += (int64_t)gridDim.x * NTM) {
-    const int i = (int)(o % A.nx), j = (int)(o / A.nx);
-    const double r = A.b[o] - apply5_64(A.dg, A.ce, A.cn, A.x, o, i, j, A.nx, A.ny);
+  for_box(A, Bx, [&](int64_t o, int i, int j) {
+    const double r = A.b[o] - apply5_64(A, Bx, A.x, o, i, j);
     rr += r * r;
-  }
+  });
   block_partial(rr, A.part);
 }
 
 // statistics of the solve: iterations, relative true residual; a solve
 // whose true residual misses the tolerance (the recursive one met it) counts
 // as not converged: the continuing solver then takes over, or (last) the
-// no-convergence status is set
+// no-convergence status is set.  Nothing when the tile solver has the step.
 __global__ void __launch_bounds__(1024) k_cg_finish(MgArgs A, int nb, int last) {
   MgState* st = A.st;
+  if (!st->use) return;
   const double rr = sum_partials(A.part, nb);
   if (threadIdx.x != 0) return;
   const bool ok = st->done == 1 && (st->bb == 0.0 || rr <= A.tol * A.tol * st->bb);
-  if (!ok && st->done == 1) st->done = 0;
+  st->ok = ok ? 1 : 0;
   *A.iters = st->it;
   *A.iters_sum += st->it;
   *A.rel = st->bb > 0.0 ? sqrt(rr / st->bb) : 0.0;
@@ -447,7 +585,7 @@ __global__ void __launch_bounds__(1024) k_cg_finish(MgArgs A, int nb, int last) 
 // after a continuing solver (which wrote its own iteration count): the step's
 // count is the sum of both
 __global__ void k_cg_account(MgArgs A) {
-  if (A.st->done != 1) *A.iters += A.st->it;
+  if (A.st->use && !A.st->ok) *A.iters += A.st->it;
 }
 
 }  // namespace
@@ -481,7 +619,7 @@ void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t 
   MgArgs A = x->mg_args;
   A.tol = tol;
   auto lvl = [&](int l) {
-    return Lvl{x->mg_nx[l], x->mg_ny[l], x->mg_c[l], x->mg_e[l], x->mg_n[l]};
+    return Lvl{x->mg_nx[l], x->mg_ny[l], l, x->mg_c[l], x->mg_e[l], x->mg_n[l]};
   };
   auto tiles = [&](int l) { return tiles_of(x->mg_nx[l], x->mg_ny[l]); };
   // the coarse operators of this solve (level 0 is the FP32 copy of the
@@ -490,8 +628,8 @@ void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t 
     const int64_t nc = (int64_t)x->mg_nx[l + 1] * x->mg_ny[l + 1];
     hipLaunchKernelGGL(k_mg_coarsen, dim3(blocks_for(nc)), dim3(NTM), 0, s, x->mg_nx[l],
                        (const float*)x->mg_c[l], (const float*)x->mg_e[l],
-                       (const float*)x->mg_n[l], x->mg_nx[l + 1], x->mg_ny[l + 1], x->mg_c[l + 1],
-                       x->mg_e[l + 1], x->mg_n[l + 1]);
+                       (const float*)x->mg_n[l], x->mg_nx[l + 1], l + 1, x->mg_c[l + 1],
+                       x->mg_e[l + 1], x->mg_n[l + 1], (const MgState*)A.st);
   }
   const int g0 = blocks_for(n0);
   hipLaunchKernelGGL(k_cg_init, dim3(g0), dim3(NTM), 0, s, A);
@@ -500,11 +638,10 @@ void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t 
   for (int it = 0; it < budget; it++) {
     // z = V-cycle(r)
     hipLaunchKernelGGL(k_mg_down<double>, dim3(tiles(0)), dim3(MNT), 0, s, lvl(0),
-                       (const double*)A.r, x->mg_nx[1], x->mg_ny[1], x->mg_b[1], st);
+                       (const double*)A.r, x->mg_nx[1], x->mg_b[1], st);
     for (int l = 1; l < L; l++)
       hipLaunchKernelGGL(k_mg_down<float>, dim3(tiles(l)), dim3(MNT), 0, s, lvl(l),
-                         (const float*)x->mg_b[l], x->mg_nx[l + 1], x->mg_ny[l + 1],
-                         x->mg_b[l + 1], st);
+                         (const float*)x->mg_b[l], x->mg_nx[l + 1], x->mg_b[l + 1], st);
     hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(NTC), 0, s, lvl(L),
                        (const float*)x->mg_b[L], x->mg_z[L], st);
     for (int l = L - 1; l >= 1; l--)
@@ -522,6 +659,15 @@ void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t 
   }
   hipLaunchKernelGGL(k_cg_true, dim3(g0), dim3(NTM), 0, s, A);
   hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(1024), 0, s, A, g0, (int)last);
+}
+
+void launch_mg_box2d(Ctx2D* x, bool global, hipStream_t s) {
+  hipLaunchKernelGGL(k_mg_box, dim3(1), dim3(1024), 0, s, x->mg_args.st,
+                     (const int*)x->tile_list, (const int*)x->n_tiles_act, x->tiles_x, TX2, TY2,
+                     x->nx, x->ny, 1 << x->mg_levels, global ? 1 : 0, MG_MIN_TILES);
+  hipLaunchKernelGGL(k_mg_identity, dim3(x->ntiles), dim3(256), 0, s,
+                     (const MgState*)x->mg_args.st, (const int*)x->tile_pos, x->tiles_x, TX2, TY2,
+                     x->nx, x->dg, x->ce, x->cn, x->b, x->x, x->dg32, x->ce32, x->cn32, x->nb);
 }
 
 void launch_mg_account2d(Ctx2D* x, hipStream_t s) {

@@ -307,6 +307,28 @@ def random_case_2d(nx, ny, seed, dx=0.5, dy=0.5, h0=2.0, amp=0.05, mom=0.05, ver
     return Case2D(nx=nx, ny=ny, dx=dx, dy=dy, ds=ds, h=h, hu=hu, hv=hv, hw=hw, body=body, t0=0.05)
 
 
+def hump_case_2d(nx, ny, seed, dx=1.0, h0=10.0, amp=0.01, radius=100.0, cx=None, cy=None,
+                 body=None) -> Case2D:
+    """a Gaussian hump of water, eta = amp h0 exp(-r^2 / radius^2), at rest
+    over a seeded, gently perturbed bottom (2% of h0, correlation 4 dx): the
+    non-hydrostatic area is a disc whose bounding box leaves much of the
+    grid outside"""
+    rng = np.random.default_rng(seed)
+    ds = h0 + 0.02 * h0 * gaussian_field_2d(nx, ny, dx, dx, 1.0, 4 * dx, int(rng.integers(1 << 30)))
+    cx = 0.4 * nx * dx if cx is None else cx
+    cy = 0.55 * ny * dx if cy is None else cy
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(x, y)
+    eta = amp * h0 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / radius ** 2)
+    h = ds + eta
+    z = np.zeros_like(h)
+    if body is None:
+        body = Body()
+    return Case2D(nx=nx, ny=ny, dx=dx, dy=dx, ds=ds, h=h, hu=z, hv=z.copy(), hw=z.copy(),
+                  body=body, t0=0.0)
+
+
 def warm_start_case_2d(seed, n=1024, dx=2.0, h0=50.0) -> Case2D:
     """2D slide scenario for the learned warm start: the shelf of the 2D
     benchmark (50 m, Gaussian-correlated perturbation with std 2 m and

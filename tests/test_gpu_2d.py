@@ -313,11 +313,12 @@ def test_global_multigrid_solve_stage(B):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_global_multigrid_continued_by_the_tile_solver(B, precision):
-    """a grid whose coarsest level (100 x 40 cells) is far from the pressure's
-    decay length, so the multigrid CG needs more than its per-step budget of
-    32 iterations: the tile solver continues from its iterate, the step meets
+    """cells four times wider than high (the point smoother leaves the
+    anisotropic error's smooth-along-x part, ~65 multigrid iterations from a
+    zero guess), so the multigrid CG uses its per-step budget of 32
+    iterations: the tile solver continues from its iterate, the step meets
     the tolerance, counts the iterations of both and matches the oracle"""
-    c = S.random_case_2d(200, 80, seed=47, dx=1.0, dy=1.0, h0=10.0)
+    c = S.random_case_2d(200, 80, seed=47, dx=1.0, dy=0.25, h0=10.0)
     tol = 1e-13 if precision == 0 else 1e-11
     kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=precision, tol=tol, max_iter=20000,
               warm=0)
@@ -359,3 +360,31 @@ def test_status_codes_2d(B):
         p = torch.zeros_like(h)
         ctx.step(h, hu, hv, hw, p, nsteps=1)
         assert ctx.sync_stats()["status"] == want
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adaptive_multigrid_on_the_active_box(B, precision):
+    """an adaptive step whose marked area (a disc of ~113k cells, 251 active
+    tiles: more than the 128 up to which the tile solver keeps its coarse
+    space) sends the solve to the multigrid CG on the active tiles'
+    bounding box, with identity rows on the box's unmarked tiles: the
+    oracle's masks and fields, in multigrid's few dozen iterations"""
+    c = S.hump_case_2d(640, 512, seed=5, amp=0.01, radius=125.0)
+    tol = 1e-13 if precision == 0 else 1e-11
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.4, precision=precision, tol=tol,
+              max_iter=20000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 3, **kw)
+    print("active", st["n_active"], "iterations", st["iters"], "rel_res", st["rel_res"])
+    assert st["status"] == 0, st
+    assert st["n_active"] > 128 * 512 and st["iters"] <= 32, st
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, tol=1e-14),
+                  cfl=0.4).step(3)
+    assert np.array_equal(m.cpu().numpy(), ref.mask)
+    bar = 1e-10 if precision == 0 else 1e-6
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= bar
+    # a second context gives the same bits (the box leaves cells of the
+    # coarsest level outside it, whose LDS values the sweeps must not read)
+    again = run2d(B, c, 3, **kw)
+    for x, y in zip((h, hu, hv, hw, p), again[2:7]):
+        assert torch.equal(x, y)
