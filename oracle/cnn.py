@@ -7,9 +7,14 @@ weights are [Cout][3][3][Cin] followed by its Cout biases, all layers packed
 in one flat FP32 parameter vector.  The optimiser is Adam (Kingma & Ba 2015,
 "Adam: A Method for Stochastic Optimization", Algorithm 1).
 
+The mask proposal trains the same network as a per-cell classifier with the
+weighted binary cross-entropy of its logits (bce_logits).
+
 Pinned by tests/test_oracle_cnn.py: the convolution against its definition
 written as nested loops, the backward pass against finite differences of a
-scalar loss, Adam against the published update written out step by step.
+scalar loss, Adam against the published update written out step by step, the
+cross-entropy against its definition -t log s(o) - (1 - t) log(1 - s(o)),
+its gradient against finite differences.
 """
 import numpy as np
 
@@ -110,3 +115,19 @@ def init_params(seed):
         W = rng.standard_normal((co, 3, 3, ci)) * np.sqrt(2.0 / (9 * ci))
         out.append((W, np.zeros(co)))
     return pack(out).astype(np.float32)
+
+
+def bce_logits(out, target, weight):
+    """weighted mean binary cross-entropy of logits o against targets t in
+    [0, 1]: loss = sum w l / sum w with l = -t log s(o) - (1 - t) log(1 - s(o)),
+    s the logistic function, written in the overflow-free form
+    l = max(o, 0) - o t + log(1 + exp(-|o|)); gradient w (s(o) - t) / sum w"""
+    o = np.asarray(out, dtype=np.float64)
+    t = np.asarray(target, dtype=np.float64)
+    w = np.asarray(weight, dtype=np.float64)
+    sw = w.sum()
+    if sw <= 0.0:
+        return 0.0, np.zeros_like(o)
+    l = np.maximum(o, 0.0) - o * t + np.log1p(np.exp(-np.abs(o)))
+    s = 1.0 / (1.0 + np.exp(-o))
+    return float((w * l).sum() / sw), w * (s - t) / sw

@@ -76,3 +76,35 @@ def test_adam_matches_published_update():
             vh = ref_v[i] / (1 - 0.999 ** t)
             ref_p[i] -= 1e-2 * mh / (np.sqrt(vh) + 1e-8)
     assert np.allclose(p, ref_p, rtol=1e-14, atol=1e-14)
+
+
+def test_bce_logits_definition_and_gradient():
+    """the cross-entropy against its definition from the logistic function
+    (moderate logits, where the direct form is accurate), its value at o = 0
+    (log 2 whatever the target), its large-logit limits, and its gradient
+    against central differences"""
+    rng = np.random.default_rng(7)
+    o = rng.normal(0.0, 3.0, (2, 5, 6))
+    t = (rng.random(o.shape) < 0.3).astype(np.float64)
+    t[0, 0, :3] = 0.25  # soft targets too
+    w = rng.random(o.shape)
+    loss, g = C.bce_logits(o, t, w)
+    s = 1.0 / (1.0 + np.exp(-o))
+    direct = -(t * np.log(s) + (1.0 - t) * np.log(1.0 - s))
+    assert abs(loss - (w * direct).sum() / w.sum()) <= 1e-12 * abs(loss)
+    z = np.zeros((1, 2, 2))
+    for tv in (0.0, 0.5, 1.0):
+        l0, _ = C.bce_logits(z, np.full(z.shape, tv), np.ones(z.shape))
+        assert abs(l0 - np.log(2.0)) <= 1e-15
+    big = np.array([[[40.0, -40.0]]])
+    lb, gb = C.bce_logits(big, np.array([[[1.0, 0.0]]]), np.ones(big.shape))
+    assert 0.0 < lb <= 1e-17 and np.abs(gb).max() <= 1e-17
+    lw, _ = C.bce_logits(big, np.array([[[0.0, 1.0]]]), np.ones(big.shape))
+    assert abs(lw - 40.0) <= 1e-12
+    for idx in [(0, 1, 2), (1, 4, 5), (0, 0, 1)]:
+        e = 1e-6
+        op, om = o.copy(), o.copy()
+        op[idx] += e
+        om[idx] -= e
+        fd = (C.bce_logits(op, t, w)[0] - C.bce_logits(om, t, w)[0]) / (2 * e)
+        assert abs(fd - g[idx]) <= 1e-7 * max(abs(g[idx]), 1e-3)
