@@ -260,6 +260,15 @@ int swe_nh_cnn_mse(const float* out, const float* target, const float* weight, i
                    int32_t h, int32_t w, float* dout, float* loss, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* The mask proposal's loss: weighted binary cross-entropy of the logits out
+ * against targets in [0, 1], *loss = sum wt l / sum wt with
+ * l = max(o, 0) - o t + log(1 + exp(-|o|)) (device scalar, accumulated in
+ * FP64), dout = wt (1 / (1 + exp(-o)) - t) / sum wt.  Same buffers and
+ * workspace as swe_nh_cnn_mse. */
+int swe_nh_cnn_bce(const float* out, const float* target, const float* weight, int32_t n,
+                   int32_t h, int32_t w, float* dout, float* loss, void* ws, size_t ws_bytes,
+                   void* stream);
+
 /* One Adam step (Kingma & Ba 2015) on FP32 parameters; step counts from 1. */
 int swe_nh_cnn_adam(float* params, float* m, float* v, const float* grad, int64_t count,
                     int32_t step, float lr, float beta1, float beta2, float eps, void* stream);

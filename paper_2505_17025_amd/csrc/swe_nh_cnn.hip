@@ -330,6 +330,51 @@ __global__ void k_mse_grad(const float* __restrict__ o, const float* __restrict_
     dout[e] = sc * w[e] * (o[e] - t[e]);
 }
 
+// weighted binary cross-entropy of logits (the mask proposal): loss =
+// sum w l / sum w, l = max(o, 0) - o t + log(1 + exp(-|o|)) (the logistic
+// cross-entropy without overflow), dout = w (s(o) - t) / sum w with s the
+// logistic function; the partial sums in FP64 like the MSE's
+__global__ void k_bce_part(const float* __restrict__ o, const float* __restrict__ t,
+                           const float* __restrict__ w, int64_t n, double* part) {
+  double se = 0.0, sw = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)o[e];
+    const double l = fmax(x, 0.0) - x * (double)t[e] + log1p(exp(-fabs(x)));
+    se += (double)w[e] * l;
+    sw += (double)w[e];
+  }
+  __shared__ double sh[2][NTC / 64];
+  se = wave_sum(se);
+  sw = wave_sum(sw);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = se;
+    sh[1][threadIdx.x >> 6] = sw;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < NTC / 64; k++) {
+      a += sh[0][k];
+      b += sh[1][k];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ void k_bce_grad(const float* __restrict__ o, const float* __restrict__ t,
+                           const float* __restrict__ w, int64_t n, const double* wsum,
+                           float* __restrict__ dout) {
+  const double s = *wsum;
+  const float sc = s > 0.0 ? (float)(1.0 / s) : 0.0f;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float sg = 1.0f / (1.0f + expf(-o[e]));
+    dout[e] = sc * w[e] * (sg - t[e]);
+  }
+}
+
 // Adam (Kingma & Ba 2015, Algorithm 1) on FP32 master weights
 __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
@@ -531,6 +576,17 @@ void cnn_mse(const float* o, const float* t, const float* wgt, int64_t n, char* 
                      (const double*)wsum, dout);
 }
 
+void cnn_bce(const float* o, const float* t, const float* wgt, int64_t n, char* ws,
+             const CnnLayout& L, float* dout, float* loss, hipStream_t s) {
+  double* part = reinterpret_cast<double*>(ws + L.mse_part);
+  double* wsum = reinterpret_cast<double*>(ws + L.mse_w);
+  const int nb = blocks_of(n) < 1024 ? blocks_of(n) : 1024;
+  hipLaunchKernelGGL(k_bce_part, dim3(nb), dim3(NTC), 0, s, o, t, wgt, n, part);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, loss, wsum);
+  hipLaunchKernelGGL(k_bce_grad, dim3(blocks_of(n)), dim3(NTC), 0, s, o, t, wgt, n,
+                     (const double*)wsum, dout);
+}
+
 void cnn_adam(float* p, float* m, float* v, const float* g, int64_t n, int step, float lr,
               float b1, float b2, float eps, hipStream_t s) {
   const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
@@ -668,6 +724,17 @@ int swe_nh_cnn_mse(const float* out, const float* target, const float* weight, i
   if (rc) return rc;
   const CnnLayout L = cnn_layout(n, h, w);
   cnn_mse(out, target, weight, (int64_t)n * h * w, (char*)ws, L, dout, loss, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SWE_NH_OK : SWE_NH_EHIP;
+}
+
+int swe_nh_cnn_bce(const float* out, const float* target, const float* weight, int32_t n,
+                   int32_t h, int32_t w, float* dout, float* loss, void* ws, size_t ws_bytes,
+                   void* stream) {
+  if (!out || !target || !weight || !dout || !loss || !ws) return SWE_NH_EINVAL;
+  const int rc = cnn_args_ok(n, h, w, ws_bytes);
+  if (rc) return rc;
+  const CnnLayout L = cnn_layout(n, h, w);
+  cnn_bce(out, target, weight, (int64_t)n * h * w, (char*)ws, L, dout, loss, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SWE_NH_OK : SWE_NH_EHIP;
 }
 

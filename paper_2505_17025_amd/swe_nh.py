@@ -88,6 +88,7 @@ def _load():
     lib.swe_nh_cnn_forward_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     lib.swe_nh_cnn_backward.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, C.c_size_t, vp]
     lib.swe_nh_cnn_mse.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, C.c_size_t, vp]
+    lib.swe_nh_cnn_bce.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, C.c_size_t, vp]
     lib.swe_nh_cnn_adam.argtypes = [vp, vp, vp, vp, i64, i32, C.c_float, C.c_float, C.c_float,
                                     C.c_float, vp]
     lib.swe_nh_features.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
@@ -95,7 +96,7 @@ def _load():
     lib.swe_nh_dg1d_run.argtypes = [C.POINTER(swe_nh_dg1d_config), dbl, i32, vp, vp, vp, vp, vp,
                                     vp]
     for name in ("swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
-                 "swe_nh_cnn_mse", "swe_nh_cnn_adam",
+                 "swe_nh_cnn_mse", "swe_nh_cnn_bce", "swe_nh_cnn_adam",
                  "swe_nh_features", "swe_nh_set_warm_start_net", "swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
                  "swe_nh_sync_stats", "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure",
                  "swe_nh_correct", "swe_nh_dg1d_run"):
@@ -109,7 +110,8 @@ EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_l
             "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct",
             "swe_nh_time_stage", "swe_nh_cnn_param_count", "swe_nh_cnn_workspace_bytes",
             "swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
-            "swe_nh_cnn_mse", "swe_nh_cnn_adam", "swe_nh_features", "swe_nh_set_warm_start_net",
+            "swe_nh_cnn_mse", "swe_nh_cnn_bce", "swe_nh_cnn_adam", "swe_nh_features",
+            "swe_nh_set_warm_start_net",
             "swe_nh_dg1d_run"]
 NOALLOC_MAX_PIXELS = 131072
 DG_MAX_ELEMS = 1024
@@ -331,6 +333,12 @@ class Net:
                                     _ptr(dout), _ptr(loss), C.c_void_p(self.wsp),
                                     C.c_size_t(self.nbytes), C.c_void_p(self.stream)),
                  "swe_nh_cnn_mse")
+
+    def bce(self, out, target, weight, dout, loss):
+        self._ok(LIB.swe_nh_cnn_bce(_ptr(out), _ptr(target), _ptr(weight), self.n, self.h, self.w,
+                                    _ptr(dout), _ptr(loss), C.c_void_p(self.wsp),
+                                    C.c_size_t(self.nbytes), C.c_void_p(self.stream)),
+                 "swe_nh_cnn_bce")
 
     def adam(self, params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self._ok(LIB.swe_nh_cnn_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad),
