@@ -119,6 +119,10 @@ typedef struct {
                                that holds the tile is used.  The fused step's
                                window adds 6 + enlarge cells on each side, so a tile of
                                capacity - 2 (6 + enlarge) cells fills whole wavefronts */
+  int32_t step1d_form;      /* 1D fused step: 0 one kernel when the blocks of every tile
+                               fit on the device at once (and the two-kernel form
+                               otherwise), 1 always the two-kernel form (step kernel,
+                               level-1 solve, projection kernel) */
   const double* depth_static;  /* device [cells]: static depth d_s */
   const swe_nh_body* bodies;   /* host [batch] (1D) or [1] (2D) */
 } swe_nh_config;
@@ -151,8 +155,8 @@ size_t swe_nh_workspace_bytes(const swe_nh_config* cfg);
  * words (the 2D solver's iterations do the same); such kernels assume that
  * no other long-running kernel holds the device's compute units while they
  * run.  Every wait is bounded: a step that cannot complete ends with
- * SWE_NH_EHIP after about 0.5 s.  With SWE_NH_ONEPASS=0 in the environment
- * when a context is created, the 1D step uses its two-kernel form. */
+ * SWE_NH_EHIP after about 0.5 s.  cfg->step1d_form = 1 selects the two-kernel
+ * form, which has no such waits. */
 int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t workspace_bytes, void* stream,
                 swe_nh_ctx** out);
 

@@ -107,6 +107,7 @@ int check_config(const swe_nh_config* c, std::string* why) {
   if (c->enlarge < 0 || c->enlarge > 64) return bad("enlarge must be in [0, 64]");
   if (c->tile1d != 0 && (c->tile1d < 32 || c->tile1d > TILE_MAX))
     return bad("tile1d must be 0 or in [32, 512]");
+  if (c->step1d_form != 0 && c->step1d_form != 1) return bad("step1d_form must be 0 or 1");
   if (c->precision != 0 && c->precision != 1) return bad("precision must be 0 or 1");
   if (!c->depth_static) return bad("depth_static is required");
   if (!c->bodies) return bad("bodies is required");
@@ -504,8 +505,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
     INIT_COPY(P.berr, zi, 2 * sizeof(unsigned long long));
     // the one-kernel step when its blocks all fit on the device at once (block
     // 0 waits for every tile's count; the marked tiles wait for block 0)
-    const char* env = std::getenv("SWE_NH_ONEPASS");
-    const bool allow = !(env && env[0] == '0');
+    const bool allow = cfg->step1d_form == 0;
     P.onepass = 0;
     // (the global extension marks every tile: beyond 64 tiles its level-1
     // system would take the one-kernel form's slow path every step)

@@ -414,15 +414,14 @@ def test_refinement_reports_noconvergence(B, enlarge):
 # ------------------------------------------------- fused FP64 step paths ----
 
 @pytest.fixture(params=["one-kernel", "two-kernel"])
-def step_mode(request, monkeypatch):
+def step_mode(request, monkeypatch, B):
     """the fused step's two forms: one kernel (block 0 solves the level-1
     system, the marked tiles project in the same launch) where every tile
     fits on the device, and the step kernel + projection kernel otherwise
-    (forced with SWE_NH_ONEPASS=0, read when a context is created)"""
+    (forced by the configuration's step1d_form = 1)"""
     if request.param == "two-kernel":
-        monkeypatch.setenv("SWE_NH_ONEPASS", "0")
-    else:
-        monkeypatch.delenv("SWE_NH_ONEPASS", raising=False)
+        make = B.context_1d
+        monkeypatch.setattr(B, "context_1d", lambda *a, **k: make(*a, **{**k, "step1d_form": 1}))
     return request.param
 
 
