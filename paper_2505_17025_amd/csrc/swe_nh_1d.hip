@@ -724,7 +724,6 @@ struct StepSmem {
   double e[WMAX], m[WMAX], k[WMAX], d0[WMAX], d1[WMAX];
   union {
     struct {
-      double se[WMAX], sm[WMAX], sk[WMAX], sd[WMAX];  // cell slopes
       double Fh[WMAX], AL[WMAX], AR[WMAX], Fk[WMAX];  // face fluxes
     } f;  // a predictor stage
     struct {
@@ -748,20 +747,11 @@ struct StepSmem {
   short cell_of[RW];  // tile system row -> tile cell
 };
 
-// minmod slopes of eta, hu, hw and the depth on window cells [c0, c1) of a
-// predictor stage (each cell's slopes serve both of its faces)
-template <typename SM>
-__device__ __forceinline__ void step_slopes(SM& S, const double* d, int c0, int c1) {
-  for (int w = c0 + threadIdx.x; w < c1; w += blockDim.x) {
-    S.u.f.se[w] = minmod(S.e[w] - S.e[w - 1], S.e[w + 1] - S.e[w]);
-    S.u.f.sm[w] = minmod(S.m[w] - S.m[w - 1], S.m[w + 1] - S.m[w]);
-    S.u.f.sk[w] = minmod(S.k[w] - S.k[w - 1], S.k[w + 1] - S.k[w]);
-    S.u.f.sd[w] = minmod(d[w] - d[w - 1], d[w + 1] - d[w]);
-  }
-}
-
 // face fluxes of one predictor stage on faces [f0, f1) of the window (face f
-// between window cells f-1 and f) from the slopes of step_slopes; the
+// between window cells f-1 and f) from the minmod slopes of eta, hu, hw and
+// the depth in the two cells beside the face (each face takes them from the
+// four cells f-2 .. f+1 itself: recomputing a slope per face is cheaper than
+// a pass that stores them and the barrier after it); the
 // momentum fluxes carry the centred bed source of the cell on each side,
 // g h (d_x) / 2 with the reconstructed depth at this face, so that a cell's
 // momentum update is the difference of two face values.  Dry faces touching
@@ -771,11 +761,17 @@ __device__ __forceinline__ void step_faces(SM& S, const double* d, double g, int
                                            int lo_cell, int hi_cell, int base, int& flags) {
   for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
     const int l = f - 1, r = f;
-    const double sdl = S.u.f.sd[l], sdr = S.u.f.sd[r];
-    const Flux F = rusanov1d(g, S.e[l] + 0.5 * S.u.f.se[l], S.m[l] + 0.5 * S.u.f.sm[l],
-                             S.k[l] + 0.5 * S.u.f.sk[l], d[l] + 0.5 * sdl,
-                             S.e[r] - 0.5 * S.u.f.se[r], S.m[r] - 0.5 * S.u.f.sm[r],
-                             S.k[r] - 0.5 * S.u.f.sk[r], d[r] - 0.5 * sdr);
+    const double e0 = S.e[l - 1], e1 = S.e[l], e2 = S.e[r], e3 = S.e[r + 1];
+    const double m0 = S.m[l - 1], m1 = S.m[l], m2 = S.m[r], m3 = S.m[r + 1];
+    const double k0 = S.k[l - 1], k1 = S.k[l], k2 = S.k[r], k3 = S.k[r + 1];
+    const double d0 = d[l - 1], d1 = d[l], d2 = d[r], d3 = d[r + 1];
+    const double sdl = minmod(d1 - d0, d2 - d1), sdr = minmod(d2 - d1, d3 - d2);
+    const Flux F = rusanov1d(g, e1 + 0.5 * minmod(e1 - e0, e2 - e1),
+                             m1 + 0.5 * minmod(m1 - m0, m2 - m1),
+                             k1 + 0.5 * minmod(k1 - k0, k2 - k1), d1 + 0.5 * sdl,
+                             e2 - 0.5 * minmod(e2 - e1, e3 - e2),
+                             m2 - 0.5 * minmod(m2 - m1, m3 - m2),
+                             k2 - 0.5 * minmod(k2 - k1, k3 - k2), d2 - 0.5 * sdr);
     S.u.f.Fh[f] = F.Fh;
     S.u.f.AL[f] = F.FmL - 0.5 * g * F.hL * sdl;
     S.u.f.AR[f] = F.FmR + 0.5 * g * F.hR * sdr;
@@ -1511,12 +1507,19 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   }
   Motion M0, M1;
   double dt;
-  block_step_motions(P, par, tl.x, c, t0, dt, M0, M1);
-  const double t1 = t0 + dt;
-  if (start == 0 && threadIdx.x == 0) {  // the channel's first tile
-    P.dt[tl.x] = dt;
-    P.t[(par ^ 1) * P.nch + tl.x] = t1;  // the next step's start time
+  if constexpr (ONE) {
+    block_step_motions(P, par, tl.x, c, t0, dt, M0, M1);
+    if (start == 0 && threadIdx.x == 0) {  // the channel's first tile
+      P.dt[tl.x] = dt;
+      P.t[(par ^ 1) * P.nch + tl.x] = t0 + dt;  // the next step's start time
+    }
+  } else {  // from the channel's step table
+    const double* ct = P.ctab + (size_t)tl.x * CTAB_N;
+    dt = ct[CT_DT];
+    M0 = Motion{ct[CT_X0], ct[CT_V0], ct[CT_A0]};
+    M1 = Motion{ct[CT_X1], ct[CT_V1], ct[CT_A1]};
   }
+  const double t1 = t0 + dt;
 #pragma unroll
   for (int q = 0; q < QL; q++) {
     const int w = threadIdx.x + NT * q;
@@ -1532,8 +1535,6 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   }
   __syncthreads();
   double Qn[Q][3], L1[Q][3];
-  step_slopes(S, S.d0, 1, W - 1);
-  __syncthreads();
   step_faces(S, S.d0, P.g, 2, W - 1, max(0, start - 2), min(n, start + P.tile + 2), lo, flags);
   __syncthreads();
 #pragma unroll
@@ -1576,8 +1577,6 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   }
   __syncthreads();
   // stage 2 on window cells [4, W - 4): the tile and e + 2 cells beyond
-  step_slopes(S, S.d1, 3, W - 3);
-  __syncthreads();
   step_faces(S, S.d1, P.g, 4, W - 3, start, end, lo, flags);
   __syncthreads();
   double Qt[Q][3];
@@ -2220,6 +2219,36 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   flush_speed<NT>(P, tl.x, par, smax, flags);
 }
 
+// the two-kernel step's table: per channel, dt from the speed slots of
+// buffer `par` (their maximum, as read_speed takes it) and the body's motion
+// at both ends of the step; the step's dt and the next step's start time go
+// to P.dt and P.t[par ^ 1] here, so the step kernel's blocks only read them
+__global__ void k_chan_step(K1D P, int par) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= P.nch) return;
+  double dt = P.dt_fixed;
+  if (P.cfl > 0.0) {
+    const unsigned long long* s = P.smax + speed_at(par * P.nch + ch, 0, P.nslot);
+    double v = 0.0;
+    for (int k = 0; k < P.nslot; k++)
+      v = fmax(v, __longlong_as_double((long long)s[(size_t)k * SPEED_PAD]));
+    dt = P.cfl * P.dx / v;
+  }
+  const Chan c = P.ch[ch];
+  const double t0 = P.t[par * P.nch + ch];
+  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t0 + dt);
+  double* ct = P.ctab + (size_t)ch * CTAB_N;
+  ct[CT_DT] = dt;
+  ct[CT_X0] = M0.X;
+  ct[CT_V0] = M0.V;
+  ct[CT_A0] = M0.A;
+  ct[CT_X1] = M1.X;
+  ct[CT_V1] = M1.V;
+  ct[CT_A1] = M1.A;
+  P.dt[ch] = dt;
+  P.t[(par ^ 1) * P.nch + ch] = t0 + dt;
+}
+
 // prologue of a run of fused steps: both speed buffers and the first marked
 // count cleared (buffer 0 then collects the speed of the caller's state)
 __global__ void k_run_begin(K1D P) {
@@ -2394,6 +2423,7 @@ static void launch_step_t(const K1D& P, const double* h, const double* hu, const
       hipLaunchKernelGGL((k_step1d<T, NT, true, false>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu,
                          hw, hn, hun, hwn, mask, p, par);
   } else {
+    hipLaunchKernelGGL(k_chan_step, dim3((P.nch + 63) / 64), dim3(64), 0, s, P, par);
     if (P.refine)
       hipLaunchKernelGGL((k_step1d<T, NT, false, true>), dim3(P.ntiles), dim3(NT), 0, s, P, h,
                          hu, hw, hn, hun, hwn, mask, p, par);

@@ -77,6 +77,9 @@ struct K1D {
   double* rel_out;
   unsigned long long* tw;
   unsigned* tag1;
+  // two-kernel step: per channel, the step's dt and the body's motion at t^n
+  // and t^{n+1} ([batch][CTAB_N]), written by k_chan_step before the step kernel
+  double* ctab;
   double* l1s;
 };
 
@@ -90,6 +93,9 @@ enum {
   ZW_HT, ZW_MT, ZW_KT,               // h~, hu~, hw~
   ZW_N
 };
+
+// per-channel step table of the two-kernel step (doubles per channel)
+enum { CT_DT, CT_X0, CT_V0, CT_A0, CT_X1, CT_V1, CT_A1, CTAB_N = 8 };
 
 // ---- 1D stencil / mask / projection ----
 void launch_speed1d(const K1D& P, const double* h, const double* hu, const double* hw,
