@@ -56,9 +56,25 @@ def parse():
     return ap.parse_args()
 
 
-def pmc_traffic(kernel_file, src_file, tile=None):
+CSRC = "paper_2505_17025_amd/csrc/"
+# the sources a kernel's counters depend on: its file and the headers it includes
+SRC_1D = [CSRC + "swe_nh_1d.hip", CSRC + "swe_nh_common.h", CSRC + "swe_nh_kernels.h",
+          "include/swe_nh.h"]
+SRC_2D = [CSRC + "swe_nh_2d.hip", CSRC + "swe_nh_2d.h", CSRC + "swe_nh_cnn.h",
+          CSRC + "swe_nh_common.h", CSRC + "swe_nh_kernels.h", "include/swe_nh.h"]
+
+
+def sources_sha256(files):
+    """one digest over the named sources, in order"""
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel_file, src_files, tile=None):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, or None
-    when the kernel source (or the 1D tile length) changed since they were taken"""
+    when the kernel's sources (or the 1D tile length) changed since they were taken"""
     path = os.path.join(ROOT, "profiles", kernel_file)
     if not os.path.exists(path):
         return None
@@ -67,9 +83,8 @@ def pmc_traffic(kernel_file, src_file, tile=None):
         t = re.search(r"tile1d:\s*(\d+)", txt)
         if not t or int(t.group(1)) != int(tile):
             return None
-    m = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
-    src = open(os.path.join(ROOT, src_file), "rb").read()
-    if not m or m.group(1) != hashlib.sha256(src).hexdigest():
+    m = re.search(r"sources_sha256:\s*([0-9a-f]+)", txt)
+    if not m or m.group(1) != sources_sha256(src_files):
         return None
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     return float(t.group(1)) if t else None
@@ -149,11 +164,16 @@ def preroll_1d(B, torch, case, kw, nsteps):
     ctx.set_time([c.t0 for c in case.channels])
     h, hu, hw = f(case.packed("h")), f(case.packed("hu")), f(case.packed("hw"))
     p = torch.zeros_like(h)
-    ctx.step(h, hu, None, hw, p, nsteps=nsteps)
-    st = ctx.sync_stats()
-    if st["status"] != 0:
-        raise RuntimeError(f"pre-roll status {st}")
-    log(f"pre-roll: {nsteps} steps, t = {st['t']:.4f} s, {st['n_active']} marked cells")
+    done = 0
+    while done < nsteps:  # in chunks, each logged (a profiler can slow the steps many times)
+        k = min(500, nsteps - done)
+        ctx.step(h, hu, None, hw, p, nsteps=k)
+        done += k
+        st = ctx.sync_stats()
+        if st["status"] != 0:
+            raise RuntimeError(f"pre-roll status {st}")
+        log(f"pre-roll: {done} of {nsteps} steps, t = {st['t']:.4f} s, "
+            f"{st['n_active']} marked cells")
     return h, hu, hw, ctx.get_time()
 
 
@@ -170,7 +190,7 @@ def ensemble_roofline(ncell, n_active, stage_us, pmc_file, tile):
     achieved = per_launch / (us * 1e-6) / 1e9
     return {"kernel": "k_step1d", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": pmc_traffic(pmc_file, "paper_2505_17025_amd/csrc/swe_nh_1d.hip", tile),
+            "traffic": pmc_traffic(pmc_file, SRC_1D, tile),
             "avg_launch_us": us, "bytes_per_launch": per_launch,
             "bytes_per_cell": ALG_BYTES_CELL, "bytes_per_active_cell": ALG_BYTES_ACTIVE,
             "n_active": n_active, "stage_us": stage_us}
@@ -186,7 +206,7 @@ def step_roofline(ncell, stage_us, pmc_file, tile):
     achieved = per_launch / (us * 1e-6) / 1e9
     return {"kernel": "k_step1d", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": pmc_traffic(pmc_file, "paper_2505_17025_amd/csrc/swe_nh_1d.hip", tile)
+            "traffic": pmc_traffic(pmc_file, SRC_1D, tile)
             if pmc_file else None,
             "avg_launch_us": us, "bytes_per_launch": per_launch,
             "bytes_per_cell": STEP1D_BYTES, "stage_us": stage_us}
@@ -792,8 +812,7 @@ def run_2d(B, torch, S, steps, warmup, preroll=0):
                        "preroll": start[6] if start is not None else None},
             "roofline": {"kernel": "k_pred2d", "bound": "hbm", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": pmc_traffic("pred2d_shelf2048_pmc.txt",
-                                                "paper_2505_17025_amd/csrc/swe_nh_2d.hip"),
+                         "traffic": pmc_traffic("pred2d_shelf2048_pmc.txt", SRC_2D),
                          "avg_launch_us": pred_us, "bytes_per_launch": c.nx * c.ny * 72.0,
                          "note": "the step's time is mostly the persistent solver, bound by "
                                  "grid-barrier latency (see solve_share); the predictor is the "

@@ -2219,34 +2219,28 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   flush_speed<NT>(P, tl.x, par, smax, flags);
 }
 
-// the two-kernel step's table: per channel, dt from the speed slots of
-// buffer `par` (their maximum, as read_speed takes it) and the body's motion
-// at both ends of the step; the step's dt and the next step's start time go
-// to P.dt and P.t[par ^ 1] here, so the step kernel's blocks only read them
-__global__ void k_chan_step(K1D P, int par) {
-  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+// the two-kernel step's table: per channel (one wavefront each), dt from the
+// speed slots of buffer `par` (their maximum, read by one lane each as
+// read_speed does) and the body's motion at both ends of the step (lanes 0
+// and 1); the step's dt and the next step's start time go to P.dt and
+// P.t[par ^ 1] here, so the step kernel's blocks only read them
+__global__ void __launch_bounds__(256) k_chan_step(K1D P, int par) {
+  const int ch = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (ch >= P.nch) return;
-  double dt = P.dt_fixed;
-  if (P.cfl > 0.0) {
-    const unsigned long long* s = P.smax + speed_at(par * P.nch + ch, 0, P.nslot);
-    double v = 0.0;
-    for (int k = 0; k < P.nslot; k++)
-      v = fmax(v, __longlong_as_double((long long)s[(size_t)k * SPEED_PAD]));
-    dt = P.cfl * P.dx / v;
-  }
-  const Chan c = P.ch[ch];
+  const double dt = (P.cfl > 0.0) ? P.cfl * P.dx / read_speed(P, par, ch) : P.dt_fixed;
   const double t0 = P.t[par * P.nch + ch];
-  const Motion M0 = body_motion(c, t0), M1 = body_motion(c, t0 + dt);
-  double* ct = P.ctab + (size_t)ch * CTAB_N;
-  ct[CT_DT] = dt;
-  ct[CT_X0] = M0.X;
-  ct[CT_V0] = M0.V;
-  ct[CT_A0] = M0.A;
-  ct[CT_X1] = M1.X;
-  ct[CT_V1] = M1.V;
-  ct[CT_A1] = M1.A;
-  P.dt[ch] = dt;
-  P.t[(par ^ 1) * P.nch + ch] = t0 + dt;
+  if (lane < 2) {
+    const Motion M = body_motion(P.ch[ch], lane == 0 ? t0 : t0 + dt);
+    double* ct = P.ctab + (size_t)ch * CTAB_N + (lane == 0 ? CT_X0 : CT_X1);
+    ct[0] = M.X;
+    ct[1] = M.V;
+    ct[2] = M.A;
+    if (lane == 0) {
+      P.ctab[(size_t)ch * CTAB_N + CT_DT] = dt;
+      P.dt[ch] = dt;
+      P.t[(par ^ 1) * P.nch + ch] = t0 + dt;
+    }
+  }
 }
 
 // prologue of a run of fused steps: both speed buffers and the first marked
@@ -2423,7 +2417,7 @@ static void launch_step_t(const K1D& P, const double* h, const double* hu, const
       hipLaunchKernelGGL((k_step1d<T, NT, true, false>), dim3(P.ntiles), dim3(NT), 0, s, P, h, hu,
                          hw, hn, hun, hwn, mask, p, par);
   } else {
-    hipLaunchKernelGGL(k_chan_step, dim3((P.nch + 63) / 64), dim3(64), 0, s, P, par);
+    hipLaunchKernelGGL(k_chan_step, dim3((P.nch + 3) / 4), dim3(256), 0, s, P, par);
     if (P.refine)
       hipLaunchKernelGGL((k_step1d<T, NT, false, true>), dim3(P.ntiles), dim3(NT), 0, s, P, h,
                          hu, hw, hn, hun, hwn, mask, p, par);

@@ -172,9 +172,12 @@ __device__ __forceinline__ double sqrt64(double x) {
   return x > 0.0 ? s : 0.0;
 }
 
+// minmod(a, b): the argument of smaller magnitude when both have one sign,
+// else zero, as max(min(a, b), 0) + min(max(a, b), 0) (one of the two terms
+// is always zero, so the sum is exact): five instructions, no compare and
+// select chains
 __device__ __forceinline__ double minmod(double a, double b) {
-  if (a * b <= 0.0) return 0.0;
-  return fabs(a) < fabs(b) ? a : b;
+  return fmax(fmin(a, b), 0.0) + fmin(fmax(a, b), 0.0);
 }
 
 // reflect a channel-local cell index into [0, n)
