@@ -37,7 +37,7 @@ class OrcBody(C.Structure):
 class OrcPhys(C.Structure):
     _fields_ = [("g", C.c_double), ("rho", C.c_double), ("k_nh", C.c_double),
                 ("crit", C.c_int32), ("enlarge", C.c_int32), ("first_global", C.c_int32),
-                ("tol", C.c_double), ("max_iter", C.c_int32)]
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("tensor", C.c_int32)]
 
 
 def lib():
@@ -69,8 +69,9 @@ def body_struct(body) -> OrcBody:
 
 
 def phys_struct(g=9.81, rho=1000.0, k_nh=1e-3, crit=6, enlarge=1, first_global=1, tol=1e-13,
-                max_iter=100000) -> OrcPhys:
-    return OrcPhys(g, rho, k_nh, int(crit), int(enlarge), int(first_global), tol, int(max_iter))
+                max_iter=100000, tensor=0) -> OrcPhys:
+    return OrcPhys(g, rho, k_nh, int(crit), int(enlarge), int(first_global), tol, int(max_iter),
+                   int(tensor))
 
 
 class OracleError(RuntimeError):
@@ -311,13 +312,27 @@ def nh_coeffs_2d(ds, dx, dy, body, phys, t1, dt, ht, mt, nt, kt):
     return cell, xf, yf
 
 
-def nh_apply_2d(cell, xf, yf, mask, p):
+def nh_pairs_2d(ds, dx, dy, body, t1, xf, yf):
+    """the exact-tensor operator's off-diagonal entry per owner cell [ny, nx]"""
+    ds = _f64(ds)
+    ny, nx = ds.shape
+    kxy = np.empty((ny, nx))
+    b = body_struct(body)
+    _check(lib().orc_nh_pairs_2d(C.c_int32(nx), C.c_int32(ny), C.c_double(dx), C.c_double(dy),
+                                 _p(ds), C.byref(b), C.c_double(t1), _p(_f64(xf)), _p(_f64(yf)),
+                                 _p(kxy)), "nh_pairs_2d")
+    return kxy
+
+
+def nh_apply_2d(cell, xf, yf, mask, p, kxy=None):
+    """A p; kxy (from nh_pairs_2d) selects the exact-tensor operator"""
     ny, nx = mask.shape
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     p = _f64(p)
     out = np.empty((ny, nx))
-    lib().orc_nh_apply_2d(C.c_int32(nx), C.c_int32(ny), _p(cell), _p(xf), _p(yf), _p(mask), _p(p),
-                          _p(out))
+    kxy = None if kxy is None else _f64(kxy)
+    lib().orc_nh_apply7_2d(C.c_int32(nx), C.c_int32(ny), _p(cell), _p(xf), _p(yf), _p(kxy),
+                           _p(mask), _p(p), _p(out))
     return out
 
 
@@ -329,26 +344,28 @@ def nh_rhs_2d(cell, xf, yf, mask):
     return out
 
 
-def cg_2d(cell, xf, yf, mask, rhs, tol=1e-13, max_iter=100000, x0=None):
+def cg_2d(cell, xf, yf, mask, rhs, tol=1e-13, max_iter=100000, x0=None, kxy=None):
     ny, nx = mask.shape
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     rhs = _f64(rhs)
     x = np.zeros((ny, nx)) if x0 is None else _f64(x0).copy()
     it, rr = C.c_int32(), C.c_double()
-    _check(lib().orc_cg_2d(C.c_int32(nx), C.c_int32(ny), _p(cell), _p(xf), _p(yf), _p(mask),
-                           _p(rhs), C.c_double(tol), C.c_int32(max_iter), _p(x), C.byref(it),
-                           C.byref(rr)), "cg_2d")
+    kxy = None if kxy is None else _f64(kxy)
+    _check(lib().orc_cg7_2d(C.c_int32(nx), C.c_int32(ny), _p(cell), _p(xf), _p(yf), _p(kxy),
+                            _p(mask), _p(rhs), C.c_double(tol), C.c_int32(max_iter), _p(x),
+                            C.byref(it), C.byref(rr)), "cg_2d")
     return x, it.value, rr.value
 
 
-def nh_correct_2d(cell, xf, yf, dt, rho, mt, nt, kt, mask, p):
+def nh_correct_2d(cell, xf, yf, dt, rho, mt, nt, kt, mask, p, kxy=None):
     mt, nt, kt, p = map(_f64, (mt, nt, kt, p))
     ny, nx = mt.shape
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     mo, no, ko = np.empty((ny, nx)), np.empty((ny, nx)), np.empty((ny, nx))
-    lib().orc_nh_correct_2d(C.c_int32(nx), C.c_int32(ny), _p(cell), _p(xf), _p(yf),
-                            C.c_double(dt), C.c_double(rho), _p(mt), _p(nt), _p(kt), _p(mask),
-                            _p(p), _p(mo), _p(no), _p(ko))
+    kxy = None if kxy is None else _f64(kxy)
+    lib().orc_nh_correct7_2d(C.c_int32(nx), C.c_int32(ny), _p(cell), _p(xf), _p(yf), _p(kxy),
+                             C.c_double(dt), C.c_double(rho), _p(mt), _p(nt), _p(kt), _p(mask),
+                             _p(p), _p(mo), _p(no), _p(ko))
     return mo, no, ko
 
 

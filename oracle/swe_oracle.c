@@ -796,7 +796,8 @@ int orc_mask_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds, 
  * x-face (j, f), f = 0..nx between cells (j, f-1) and (j, f); y-face (f, i)
  * between (f-1, i) and (f, i).  Face rows: 0 K, 1 a, 2 b, 3 q_pred, 4 (dt/rho) phi_f d_n,f
  * K on an x-face is the xx entry of S12^{-1} = (dt h / rho)(I - grad d grad d^T / alpha);
- * the off-diagonal d_x d_y / alpha coupling of the tensor is dropped. */
+ * the off-diagonal d_x d_y / alpha coupling of the tensor is dropped here and
+ * added pair by pair by orc_nh_pairs_2d for the exact-tensor operator. */
 int orc_nh_coeffs_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds,
                      const orc_body* b, const orc_phys* ph, double t1, double dt, const double* ht,
                      const double* mt, const double* nt, const double* kt, double* cell,
@@ -888,10 +889,68 @@ int orc_nh_coeffs_2d(int32_t nx, int32_t ny, double dx, double dy, const double*
   return ORC_OK;
 }
 
-/* (A p)_c = s22_c p_c + sum over the four faces of K_f G_{f,c} (G p)_f on NH
- * cells (p read as 0 off the mask); identity on the other cells */
-int orc_nh_apply_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
-                    const double* yface, const uint8_t* mask, const double* p, double* Ap) {
+/* The exact-tensor operator (a reading of the 2D extension, which the paper
+ * leaves to future work): the flux correction at the faces is the tensor
+ * S12^{-1} = (dt h / rho)(I - grad d grad d^T / alpha) applied to the face
+ * gradients (G p)_f.  Its diagonal is the face coefficient K of
+ * orc_nh_coeffs_2d.  Its off-diagonal couples an x-face with a y-face, so the
+ * faces are paired: cell o owns the x-face east of it and the y-face north of
+ * it, and the pair's 2 x 2 block is [[K_e, k], [k, K_n]] with
+ *   k = -sqrt(K_e K_n) S_x S_y / sqrt((4 + S_x^2)(4 + S_y^2)),
+ * S_x, S_y the normal bottom slopes of the two faces.  Where the face values
+ * agree (a planar bottom under uniform h) the block is the tensor exactly:
+ * K_e = c (4 + S_y^2) / alpha, K_n = c (4 + S_x^2) / alpha, k = -c S_x S_y / alpha
+ * with c = dt h / rho.  |k| < sqrt(K_e K_n) always, so every block and the
+ * operator stay symmetric positive definite.  Wall faces have a zero normal
+ * slope (mirrored depth), so pairs with a wall face have k = 0. */
+int orc_nh_pairs_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds,
+                    const orc_body* b, double t1, const double* xface, const double* yface,
+                    double* kxy) {
+  int64_t N = (int64_t)nx * ny;
+  double *d = dalloc(N), *w1 = dalloc(N), *w2 = dalloc(N), *w3 = dalloc(N), *w4 = dalloc(N);
+  orc_forcing_2d(nx, ny, dx, dy, ds, b, t1, d, w1, w2, w3, w4);
+  for (int32_t j = 0; j < ny; j++) {
+    for (int32_t i = 0; i < nx; i++) {
+      int64_t c = IDX(j, i);
+      double Sx = (d[IDX(j, mirror(i + 1, nx))] - d[c]) / dx;
+      double Sy = (d[IDX(mirror(j + 1, ny), i)] - d[c]) / dy;
+      double Ke = xface[(int64_t)j * (nx + 1) + i + 1];
+      double Kn = yface[(int64_t)(j + 1) * nx + i];
+      kxy[c] = -sqrt(Ke * Kn) * Sx * Sy / sqrt((4.0 + Sx * Sx) * (4.0 + Sy * Sy));
+    }
+  }
+  free(d); free(w1); free(w2); free(w3); free(w4);
+  return ORC_OK;
+}
+
+/* p at (j, i), read as 0 off the grid and off the mask */
+static double p_at(int32_t nx, int32_t ny, const uint8_t* mask, const double* p, int32_t j,
+                   int32_t i) {
+  if (i < 0 || i >= nx || j < 0 || j >= ny || !mask[IDX(j, i)]) return 0.0;
+  return p[IDX(j, i)];
+}
+
+/* (G p) on the x-face east of cell (j, i) and on the y-face north of it */
+static double grad_east(int32_t nx, int32_t ny, const double* xface, const uint8_t* mask,
+                        const double* p, int32_t j, int32_t i) {
+  int64_t NX = (int64_t)ny * (nx + 1), f = (int64_t)j * (nx + 1) + i + 1;
+  return xface[NX + f] * p_at(nx, ny, mask, p, j, i) +
+         xface[2 * NX + f] * p_at(nx, ny, mask, p, j, i + 1);
+}
+static double grad_north(int32_t nx, int32_t ny, const double* yface, const uint8_t* mask,
+                         const double* p, int32_t j, int32_t i) {
+  int64_t NY = (int64_t)(ny + 1) * nx, f = (int64_t)(j + 1) * nx + i;
+  return yface[NY + f] * p_at(nx, ny, mask, p, j, i) +
+         yface[2 * NY + f] * p_at(nx, ny, mask, p, j + 1, i);
+}
+
+/* (A p)_c = s22_c p_c + sum over the four faces of G_{f,c} (flux correction)_f
+ * on NH cells (p read as 0 off the mask); identity on the other cells.  The
+ * flux correction at a face is K_f (G p)_f, plus with the tensor k of the
+ * face's pair times (G p) on the pair's other face. */
+int orc_nh_apply7_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+                     const double* yface, const double* kxy, const uint8_t* mask,
+                     const double* p, double* Ap) {
   int64_t N = (int64_t)nx * ny, NX = (int64_t)ny * (nx + 1), NY = (int64_t)(ny + 1) * nx;
   const double* s22 = cell + 4 * N;
   for (int32_t j = 0; j < ny; j++) {
@@ -899,22 +958,35 @@ int orc_nh_apply_2d(int32_t nx, int32_t ny, const double* cell, const double* xf
       int64_t c = IDX(j, i);
       if (!mask[c]) { Ap[c] = p[c]; continue; }
       double pc = p[c];
-      double pw = (i > 0 && mask[c - 1]) ? p[c - 1] : 0.0;
-      double pe = (i + 1 < nx && mask[c + 1]) ? p[c + 1] : 0.0;
-      double ps = (j > 0 && mask[c - nx]) ? p[c - nx] : 0.0;
-      double pn = (j + 1 < ny && mask[c + nx]) ? p[c + nx] : 0.0;
+      double pw = p_at(nx, ny, mask, p, j, i - 1), pe = p_at(nx, ny, mask, p, j, i + 1);
+      double ps = p_at(nx, ny, mask, p, j - 1, i), pn = p_at(nx, ny, mask, p, j + 1, i);
       int64_t fw = (int64_t)j * (nx + 1) + i, fe = fw + 1;
       int64_t fs = (int64_t)j * nx + i, fn = fs + nx;
-      double v = s22[c] * pc;
+      /* flux corrections of the four faces, diagonal part */
+      double qw = xface[fw] * (xface[NX + fw] * pw + xface[2 * NX + fw] * pc);
+      double qe = xface[fe] * (xface[NX + fe] * pc + xface[2 * NX + fe] * pe);
+      double qs = yface[fs] * (yface[NY + fs] * ps + yface[2 * NY + fs] * pc);
+      double qn = yface[fn] * (yface[NY + fn] * pc + yface[2 * NY + fn] * pn);
+      if (kxy) {
+        /* east and north faces: the pair of this cell; west face: the pair of
+         * the cell to the west (its x-face); south face: the pair of the cell
+         * to the south (its y-face) */
+        qe += kxy[c] * grad_north(nx, ny, yface, mask, p, j, i);
+        qn += kxy[c] * grad_east(nx, ny, xface, mask, p, j, i);
+        if (i > 0) qw += kxy[c - 1] * grad_north(nx, ny, yface, mask, p, j, i - 1);
+        if (j > 0) qs += kxy[c - nx] * grad_east(nx, ny, xface, mask, p, j - 1, i);
+      }
       /* west face: c is its right cell (coefficient b); east face: left cell (a) */
-      v += xface[fw] * xface[2 * NX + fw] * (xface[NX + fw] * pw + xface[2 * NX + fw] * pc);
-      v += xface[fe] * xface[NX + fe] * (xface[NX + fe] * pc + xface[2 * NX + fe] * pe);
-      v += yface[fs] * yface[2 * NY + fs] * (yface[NY + fs] * ps + yface[2 * NY + fs] * pc);
-      v += yface[fn] * yface[NY + fn] * (yface[NY + fn] * pc + yface[2 * NY + fn] * pn);
-      Ap[c] = v;
+      Ap[c] = s22[c] * pc + xface[2 * NX + fw] * qw + xface[NX + fe] * qe +
+              yface[2 * NY + fs] * qs + yface[NY + fn] * qn;
     }
   }
   return ORC_OK;
+}
+
+int orc_nh_apply_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+                    const double* yface, const uint8_t* mask, const double* p, double* Ap) {
+  return orc_nh_apply7_2d(nx, ny, cell, xface, yface, NULL, mask, p, Ap);
 }
 
 int orc_nh_rhs_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
@@ -944,14 +1016,14 @@ static double dot_masked(int64_t N, const uint8_t* mask, const double* a, const 
 
 /* plain conjugate gradients on the NH cells, starting from x (warm start);
  * stops when ||rhs - A x|| <= tol ||rhs|| */
-int orc_cg_2d(int32_t nx, int32_t ny, const double* cell, const double* xface, const double* yface,
-              const uint8_t* mask, const double* rhs, double tol, int32_t max_iter, double* x,
-              int32_t* iters, double* rel_res) {
+int orc_cg7_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+               const double* yface, const double* kxy, const uint8_t* mask, const double* rhs,
+               double tol, int32_t max_iter, double* x, int32_t* iters, double* rel_res) {
   int64_t N = (int64_t)nx * ny;
   double *r = dalloc(N), *pp = dalloc(N), *q = dalloc(N);
   for (int64_t c = 0; c < N; c++)
     if (!mask[c]) x[c] = 0.0;
-  orc_nh_apply_2d(nx, ny, cell, xface, yface, mask, x, q);
+  orc_nh_apply7_2d(nx, ny, cell, xface, yface, kxy, mask, x, q);
   for (int64_t c = 0; c < N; c++) {
     r[c] = mask[c] ? rhs[c] - q[c] : 0.0;
     pp[c] = r[c];
@@ -966,7 +1038,7 @@ int orc_cg_2d(int32_t nx, int32_t ny, const double* cell, const double* xface, c
   }
   while (bn > 0.0 && sqrt(rr) > tol * bn) {
     if (it >= max_iter) { st = ORC_ENOCONV; break; }
-    orc_nh_apply_2d(nx, ny, cell, xface, yface, mask, pp, q);
+    orc_nh_apply7_2d(nx, ny, cell, xface, yface, kxy, mask, pp, q);
     double pq = dot_masked(N, mask, pp, q);
     double alpha = rr / pq;
     for (int64_t c = 0; c < N; c++) {
@@ -981,7 +1053,7 @@ int orc_cg_2d(int32_t nx, int32_t ny, const double* cell, const double* xface, c
     it++;
   }
   /* true residual of the returned iterate */
-  orc_nh_apply_2d(nx, ny, cell, xface, yface, mask, x, q);
+  orc_nh_apply7_2d(nx, ny, cell, xface, yface, kxy, mask, x, q);
   double tr = 0.0;
   for (int64_t c = 0; c < N; c++)
     if (mask[c]) tr += (rhs[c] - q[c]) * (rhs[c] - q[c]);
@@ -991,10 +1063,17 @@ int orc_cg_2d(int32_t nx, int32_t ny, const double* cell, const double* xface, c
   return st;
 }
 
-int orc_nh_correct_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
-                      const double* yface, double dt, double rho, const double* mt,
-                      const double* nt, const double* kt, const uint8_t* mask, const double* p,
-                      double* m_out, double* n_out, double* k_out) {
+int orc_cg_2d(int32_t nx, int32_t ny, const double* cell, const double* xface, const double* yface,
+              const uint8_t* mask, const double* rhs, double tol, int32_t max_iter, double* x,
+              int32_t* iters, double* rel_res) {
+  return orc_cg7_2d(nx, ny, cell, xface, yface, NULL, mask, rhs, tol, max_iter, x, iters, rel_res);
+}
+
+int orc_nh_correct7_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+                       const double* yface, const double* kxy, double dt, double rho,
+                       const double* mt, const double* nt, const double* kt,
+                       const uint8_t* mask, const double* p, double* m_out, double* n_out,
+                       double* k_out) {
   int64_t N = (int64_t)nx * ny, NX = (int64_t)ny * (nx + 1), NY = (int64_t)(ny + 1) * nx;
   const double *Dx = cell, *Dy = cell + N, *al = cell + 2 * N, *phi = cell + 3 * N;
 #define PV(jj, ii) (((ii) >= 0 && (ii) < nx && (jj) >= 0 && (jj) < ny && mask[IDX(jj, ii)]) ? p[IDX(jj, ii)] : 0.0)
@@ -1013,6 +1092,12 @@ int orc_nh_correct_2d(int32_t nx, int32_t ny, const double* cell, const double* 
       double dqe = xface[4 * NX + fe] - xface[fe] * (xface[NX + fe] * PV(j, i) + xface[2 * NX + fe] * PV(j, i + 1));
       double dqs = yface[4 * NY + fs] - yface[fs] * (yface[NY + fs] * PV(j - 1, i) + yface[2 * NY + fs] * PV(j, i));
       double dqn = yface[4 * NY + fn] - yface[fn] * (yface[NY + fn] * PV(j, i) + yface[2 * NY + fn] * PV(j + 1, i));
+      if (kxy) { /* the tensor's off-diagonal part, pair by pair as in orc_nh_apply7_2d */
+        dqe -= kxy[c] * grad_north(nx, ny, yface, mask, p, j, i);
+        dqn -= kxy[c] * grad_east(nx, ny, xface, mask, p, j, i);
+        if (i > 0) dqw -= kxy[c - 1] * grad_north(nx, ny, yface, mask, p, j, i - 1);
+        if (j > 0) dqs -= kxy[c - nx] * grad_east(nx, ny, xface, mask, p, j - 1, i);
+      }
       double dm = 0.5 * (dqw + dqe), dn = 0.5 * (dqs + dqn);
       double Pb = 1.5 * p[c] - rho * (Dx[c] * dm + Dy[c] * dn) / (4.0 * dt) + al[c] * phi[c] / 4.0;
       m_out[c] = mt[c] + dm;
@@ -1022,6 +1107,14 @@ int orc_nh_correct_2d(int32_t nx, int32_t ny, const double* cell, const double* 
   }
 #undef PV
   return ORC_OK;
+}
+
+int orc_nh_correct_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+                      const double* yface, double dt, double rho, const double* mt,
+                      const double* nt, const double* kt, const uint8_t* mask, const double* p,
+                      double* m_out, double* n_out, double* k_out) {
+  return orc_nh_correct7_2d(nx, ny, cell, xface, yface, NULL, dt, rho, mt, nt, kt, mask, p, m_out,
+                            n_out, k_out);
 }
 
 int orc_step_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds, const orc_body* b,
@@ -1043,6 +1136,7 @@ int orc_step_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds, 
   if (!(dt > 0.0)) return ORC_EINVAL;
   double *ht = dalloc(N), *mt = dalloc(N), *nt = dalloc(N), *kt = dalloc(N), *rh = dalloc(N);
   double *cell = dalloc(7 * N), *xf = dalloc(5 * NX), *yf = dalloc(5 * NY);
+  double* kxy = ph->tensor ? dalloc(N) : NULL;
   int32_t na = 0, it = 0;
   double rr = 0.0;
   int st = orc_predict_2d(nx, ny, dx, dy, ds, b, ph, *t, dt, h, m, n_, k, ht, mt, nt, kt);
@@ -1052,10 +1146,11 @@ int orc_step_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds, 
   if (na > 0) {
     st = orc_nh_coeffs_2d(nx, ny, dx, dy, ds, b, ph, *t + dt, dt, ht, mt, nt, kt, cell, xf, yf);
     if (st != ORC_OK) goto done;
+    if (kxy) orc_nh_pairs_2d(nx, ny, dx, dy, ds, b, *t + dt, xf, yf, kxy);
     orc_nh_rhs_2d(nx, ny, cell, xf, yf, mask, rh);
-    st = orc_cg_2d(nx, ny, cell, xf, yf, mask, rh, ph->tol, ph->max_iter, p, &it, &rr);
+    st = orc_cg7_2d(nx, ny, cell, xf, yf, kxy, mask, rh, ph->tol, ph->max_iter, p, &it, &rr);
     if (st != ORC_OK) goto done;
-    orc_nh_correct_2d(nx, ny, cell, xf, yf, dt, ph->rho, mt, nt, kt, mask, p, m, n_, k);
+    orc_nh_correct7_2d(nx, ny, cell, xf, yf, kxy, dt, ph->rho, mt, nt, kt, mask, p, m, n_, k);
   } else {
     for (int64_t c = 0; c < N; c++) { p[c] = 0.0; m[c] = mt[c]; n_[c] = nt[c]; k[c] = kt[c]; }
   }
@@ -1066,6 +1161,6 @@ done:
   if (n_active) *n_active = na;
   if (iters) *iters = it;
   if (rel_res) *rel_res = rr;
-  free(ht); free(mt); free(nt); free(kt); free(rh); free(cell); free(xf); free(yf);
+  free(ht); free(mt); free(nt); free(kt); free(rh); free(cell); free(xf); free(yf); free(kxy);
   return st;
 }

@@ -61,6 +61,7 @@ typedef struct {
   int32_t first_global; /* |w|, |w_x| criteria: global on the first step (Sec. 5.1.2) */
   double tol;           /* 2D CG: stop when ||b - A p|| <= tol ||b|| */
   int32_t max_iter;
+  int32_t tensor;       /* 2D: 1 = the exact-tensor (7-point) operator, 0 = its diagonal */
 } orc_phys;
 
 /* ---- forcing ---- */
@@ -131,6 +132,23 @@ int orc_nh_correct_2d(int32_t nx, int32_t ny, const double* cell, const double* 
                       const double* yface, double dt, double rho, const double* mt,
                       const double* nt, const double* kt, const uint8_t* mask, const double* p,
                       double* m_out, double* n_out, double* k_out);
+/* the exact-tensor operator: per owner cell (j, i) the off-diagonal entry of
+ * the face tensor that pairs the x-face east of the cell with the y-face north
+ * of it; kxy == NULL in the routines below means the diagonal (5-point) form */
+int orc_nh_pairs_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds,
+                    const orc_body* b, double t1, const double* xface, const double* yface,
+                    double* kxy /* [ny*nx] */);
+int orc_nh_apply7_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+                     const double* yface, const double* kxy, const uint8_t* mask,
+                     const double* p, double* Ap);
+int orc_cg7_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+               const double* yface, const double* kxy, const uint8_t* mask, const double* rhs,
+               double tol, int32_t max_iter, double* x, int32_t* iters, double* rel_res);
+int orc_nh_correct7_2d(int32_t nx, int32_t ny, const double* cell, const double* xface,
+                       const double* yface, const double* kxy, double dt, double rho,
+                       const double* mt, const double* nt, const double* kt,
+                       const uint8_t* mask, const double* p, double* m_out, double* n_out,
+                       double* k_out);
 int orc_step_2d(int32_t nx, int32_t ny, double dx, double dy, const double* ds, const orc_body* b,
                 const orc_phys* ph, double cfl, double dt_fixed, int32_t step_index, double* t,
                 double* h, double* m, double* n_, double* k, double* p, uint8_t* mask,
