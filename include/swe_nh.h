@@ -123,6 +123,17 @@ typedef struct {
                                fit on the device at once (and the two-kernel form
                                otherwise), 1 always the two-kernel form (step kernel,
                                level-1 solve, projection kernel) */
+  int32_t tensor2d;         /* 2D elliptic operator: 0 the diagonal of the face tensor
+                               S12^{-1} (5-point stencil), 1 the exact tensor: its
+                               off-diagonal d_x d_y / alpha coupling on pairs of faces
+                               (the x-face east of a cell with the y-face north of it),
+                               a 7-point stencil that adds the neighbours (i-1, j+1) and
+                               (i+1, j-1) (Sec. 3.2 Eqs. 12-17 in the 2D vector form).
+                               1 is solved by CG with the multigrid preconditioner on the
+                               active cells' bounding box at every active-tile count, so
+                               the grid must coarsen by 2 x 2 aggregation to at most 4096
+                               cells (nx, ny multiples of 2^L with nx ny / 4^L <= 4096,
+                               L >= 1), else init fails with SWE_NH_EINVAL; 1D: 0 */
   const double* depth_static;  /* device [cells]: static depth d_s */
   const swe_nh_body* bodies;   /* host [batch] (1D) or [1] (2D) */
 } swe_nh_config;

@@ -17,6 +17,8 @@ constexpr int CMAX2 = 128;     // most active tiles for which the solver adds th
 
 constexpr int MG_MAXL = 12;    // most levels of the multigrid preconditioner (global extension)
 constexpr int MG_BUDGET = 32;  // iterations of the multigrid-preconditioned CG in a step
+// the same for the exact-tensor operator, which no other solver continues
+constexpr int MG_BUDGET_TENSOR = 64;
 constexpr int MG_COARSE_MAX = 4096;  // most cells of the multigrid's coarsest level (one block)
 // active tiles above which an adaptive step's system goes to the multigrid CG
 // on the active tiles' bounding box: up to CMAX2 tiles the tile solver has
@@ -40,6 +42,9 @@ struct MgState {
 struct MgArgs {
   int nx = 0, ny = 0;
   const double *dg = nullptr, *ce = nullptr, *cn = nullptr, *b = nullptr;
+  // the exact-tensor operator: coupling of each cell with (i+1, j-1) (nullptr:
+  // the 5-point operator)
+  const double* cd = nullptr;
   double* x = nullptr;
   double *r = nullptr, *q = nullptr, *p[2] = {nullptr, nullptr};
   float* z = nullptr;      // the preconditioned residual (output of the FP32 V-cycle)
@@ -75,6 +80,11 @@ struct Ctx2D {
   double *dg = nullptr, *ce = nullptr, *cn = nullptr, *b = nullptr, *x = nullptr;
   float *dg32 = nullptr, *ce32 = nullptr, *cn32 = nullptr;
   uint8_t* nb = nullptr;
+  // the exact-tensor operator (tensor2d): each cell's coupling with (i+1, j-1);
+  // the FP32 copy (the multigrid's level 0) drops these couplings and adds
+  // their magnitudes to its diagonal, which keeps it above the operator
+  double* cd = nullptr;
+  int tensor = 0;
   // inner Krylov vectors, FP32 (precision 1) or FP64 (precision 0):
   // r, u, w, z, q, s, p, e, m[2] of the pipelined CG
   float* v32[PCG_NVEC] = {};
@@ -127,9 +137,9 @@ int mg_plan_levels(int nx, int ny, int* lnx, int* lny);
 // block partial sums one reduction of that solver needs at most
 int mg_partials(int nx, int ny);
 // this step's box and choice: the whole grid (global), or the bounding box of
-// the active tiles when there are more than MG_MIN_TILES of them; the cells
-// of inactive tiles inside the box get identity rows
-void launch_mg_box2d(Ctx2D* x, bool global, hipStream_t s);
+// the active tiles when there are more than min_tiles of them; the cells of
+// inactive tiles inside the box get identity rows
+void launch_mg_box2d(Ctx2D* x, bool global, int min_tiles, hipStream_t s);
 // the global extension's solve of A x = b (x holds the initial guess): CG in
 // FP64 preconditioned by one FP32 V-cycle, at most budget iterations.  With
 // last, a solve that misses the tolerance sets the no-convergence status;

@@ -9,7 +9,8 @@
 //                  LDS (4-cell halo); face fluxes computed once per direction
 //   k_mask2d       criterion + (2e+1)^2 box enlargement, tile counts
 //   k_tiles2d      list of tiles holding marked cells
-//   k_assemble2d   5-point operator of the elliptic system (FP64 + FP32 copy)
+//   k_assemble2d   5-point (or exact-tensor 7-point) operator of the elliptic
+//                  system (FP64 + FP32 copy)
 //   k_pcg2d<R>     persistent CG preconditioned by tile-block symmetric
 //                  red-black SOR (pipelined form when each block owns one
 //                  tile, Chronopoulos-Gear otherwise), in precision R with
@@ -42,6 +43,7 @@ struct G2 {
   int nx, ny, tiles_x;
   double dx, dy, g, rho, cfl, dt_fixed, k_nh;
   int crit, enlarge, first_global;
+  int tensor;  // the exact-tensor (7-point) elliptic operator
   const double* ds;
   const Chan* ch;
   double* t;
@@ -67,6 +69,7 @@ G2 make_g2(const swe_nh_config* c, const Ctx2D* x) {
   g.crit = c->crit;
   g.enlarge = c->enlarge;
   g.first_global = c->first_global;
+  g.tensor = c->tensor2d;
   g.ds = c->depth_static;
   g.ch = x->ch;
   g.t = x->t;
@@ -625,7 +628,7 @@ struct Ring {
 };
 
 struct Face2 {
-  double K, a, b, qp, fd;
+  double K, a, b, qp, fd, Dn;  // Dn: the bottom's normal slope at the face
 };
 
 // fills the ring (tile +- 1) with the quantities the faces need
@@ -684,7 +687,20 @@ __device__ __forceinline__ Face2 face_coef(const Ring& R, const G2& G, double dt
   f.b = 1.0 / del + 0.5 * s11;
   f.fd = dt / G.rho * (0.5 * (R.phi[l] + R.phi[r])) * Dn;
   f.qp = qf + f.fd;
+  f.Dn = Dn;
   return f;
+}
+
+// The exact-tensor operator pairs the x-face east of a cell (fx) with the
+// y-face north of it (fy): the face tensor's off-diagonal entry of the pair,
+// -d_x d_y / alpha times dt h / rho, taken as the geometric mean of the two
+// faces' diagonal entries times the tensor's correlation of their normal
+// slopes, -S_x S_y / sqrt((4 + S_x^2)(4 + S_y^2)).  That is the tensor itself
+// where the faces' values agree, and |k| < sqrt(K_x K_y) always, so the
+// operator stays symmetric positive definite.  A wall face has S = 0.
+__device__ __forceinline__ double pair_k(const Face2& fx, const Face2& fy) {
+  return -sqrt(fx.K * fy.K) * fx.Dn * fy.Dn /
+         sqrt((4.0 + fx.Dn * fx.Dn) * (4.0 + fy.Dn * fy.Dn));
 }
 
 enum : uint8_t { NB_W = 1, NB_E = 2, NB_S = 4, NB_N = 8, NB_SELF = 16 };
@@ -704,6 +720,7 @@ struct Sys2 {
   double *dg, *ce, *cn, *b, *x;
   float *dg32, *ce32, *cn32;
   uint8_t* nb;
+  double* cd;  // the exact-tensor operator's coupling with (i+1, j-1), or nullptr
 };
 
 __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restrict__ ht,
@@ -739,6 +756,7 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
       Y.dg32[o] = 1.0f;
       Y.ce32[o] = 0.0f;
       Y.cn32[o] = 0.0f;
+      if (Y.cd) Y.cd[o] = 0.0;
       continue;
     }
     const int w = (tj + 1) * RGX + (ti + 1);
@@ -753,15 +771,34 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
     const double f2 = -2.0 * br.d_t - 2.0 * kt[o] / hs -
                       (R.Dx[w] * mt[o] + R.Dy[w] * nt[o]) / (2.0 * hs) -
                       dt * al * R.phi[w] / (2.0 * G.rho * hs);
-    const double dg = s22 + fw.K * fw.b * fw.b + fe.K * fe.a * fe.a + fs.K * fs.b * fs.b +
-                      fn.K * fn.a * fn.a;
-    const double ce = (nb & NB_E) ? fe.K * fe.a * fe.b : 0.0;
-    const double cn = (nb & NB_N) ? fn.K * fn.a * fn.b : 0.0;
+    double dg = s22 + fw.K * fw.b * fw.b + fe.K * fe.a * fe.a + fs.K * fs.b * fs.b +
+                fn.K * fn.a * fn.a;
+    double ce = (nb & NB_E) ? fe.K * fe.a * fe.b : 0.0;
+    double cn = (nb & NB_N) ? fn.K * fn.a * fn.b : 0.0;
+    double lump = 0.0;
+    if (G.tensor) {
+      // this cell's pair (its east and north faces) adds to its diagonal and
+      // to its couplings with E and N; the pair of the cell below couples
+      // this cell with (i+1, j-1), the pair of the cell to the west couples it
+      // with (i-1, j+1) (stored at that cell; here only for the FP32 copy)
+      const double k0 = pair_k(fe, fn);
+      dg += 2.0 * k0 * fe.a * fn.a;
+      if (nb & NB_E) ce += k0 * fn.a * fe.b;
+      if (nb & NB_N) cn += k0 * fe.a * fn.b;
+      const Face2 feS = face_coef(R, G, dt, w - RGX, w - RGX + 1, true);
+      const Face2 fnW = face_coef(R, G, dt, w - 1, w - 1 + RGX, false);
+      const bool se = i + 1 < G.nx && j > 0 && mask[o - G.nx + 1];
+      const bool nw = i > 0 && j + 1 < G.ny && mask[o + G.nx - 1];
+      const double cse = se ? pair_k(feS, fs) * feS.b * fs.b : 0.0;
+      const double cnw = nw ? pair_k(fw, fnW) * fw.b * fnW.b : 0.0;
+      Y.cd[o] = cse;
+      lump = fabs(cse) + fabs(cnw);
+    }
     Y.dg[o] = dg;
     Y.ce[o] = ce;
     Y.cn[o] = cn;
     Y.b[o] = f2 + fw.b * fw.qp + fe.a * fe.qp + fs.b * fs.qp + fn.a * fn.qp;
-    Y.dg32[o] = (float)dg;
+    Y.dg32[o] = (float)(dg + lump);
     Y.ce32[o] = (float)ce;
     Y.cn32[o] = (float)cn;
     Y.x[o] = warm ? p_prev[o] : 0.0;
@@ -2064,10 +2101,26 @@ __global__ void __launch_bounds__(NT2) k_correct2d(G2 G, const double* __restric
     const Face2 fs = face_coef(R, G, dt, w - RGX, w, false);
     const Face2 fn = face_coef(R, G, dt, w, w + RGX, false);
     const double pc = x[o];
-    const double dqw = fw.fd - fw.K * (fw.a * pv(i - 1, j) + fw.b * pc);
-    const double dqe = fe.fd - fe.K * (fe.a * pc + fe.b * pv(i + 1, j));
-    const double dqs = fs.fd - fs.K * (fs.a * pv(i, j - 1) + fs.b * pc);
-    const double dqn = fn.fd - fn.K * (fn.a * pc + fn.b * pv(i, j + 1));
+    double dqw = fw.fd - fw.K * (fw.a * pv(i - 1, j) + fw.b * pc);
+    double dqe = fe.fd - fe.K * (fe.a * pc + fe.b * pv(i + 1, j));
+    double dqs = fs.fd - fs.K * (fs.a * pv(i, j - 1) + fs.b * pc);
+    double dqn = fn.fd - fn.K * (fn.a * pc + fn.b * pv(i, j + 1));
+    if (G.tensor) {
+      // the off-diagonal flux of each face's pair: east and north faces pair
+      // with each other, the west face with the north face of the cell to the
+      // west, the south face with the east face of the cell below
+      const double k0 = pair_k(fe, fn);
+      dqe -= k0 * (fn.a * pc + fn.b * pv(i, j + 1));
+      dqn -= k0 * (fe.a * pc + fe.b * pv(i + 1, j));
+      if (i > 0) {
+        const Face2 fnW = face_coef(R, G, dt, w - 1, w - 1 + RGX, false);
+        dqw -= pair_k(fw, fnW) * (fnW.a * pv(i - 1, j) + fnW.b * pv(i - 1, j + 1));
+      }
+      if (j > 0) {
+        const Face2 feS = face_coef(R, G, dt, w - RGX, w - RGX + 1, true);
+        dqs -= pair_k(feS, fs) * (feS.a * pv(i, j - 1) + feS.b * pv(i + 1, j - 1));
+      }
+    }
     const double dm = 0.5 * (dqw + dqe), dn = 0.5 * (dqs + dqn);
     const double al = 4.0 + R.Dx[w] * R.Dx[w] + R.Dy[w] * R.Dy[w];
     const double Pb = 1.5 * pc - G.rho * (R.Dx[w] * dm + R.Dy[w] * dn) / (4.0 * dt) +
@@ -2096,6 +2149,7 @@ Sys2 sys_of(Ctx2D* x) {
   Y.ce32 = x->ce32;
   Y.cn32 = x->cn32;
   Y.nb = x->nb;
+  Y.cd = x->cd;
   return Y;
 }
 
@@ -2220,7 +2274,15 @@ void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
     // is not chosen, and continues from its iterate when it has not met the
     // tolerance by then
     const bool global = c->crit == SWE_NH_CRIT_GLOBAL;
-    launch_mg_box2d(x, global, s);
+    if (x->tensor) {
+      // the exact-tensor operator: the multigrid CG at every active-tile
+      // count (the tile solver's blocks exchange no corner values), with no
+      // solver to continue it
+      launch_mg_box2d(x, global, 0, s);
+      launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET_TENSOR), true, s);
+      return;
+    }
+    launch_mg_box2d(x, global, MG_MIN_TILES, s);
     launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), false, s);
     launch_tile_solve2d(c, x, s, !global, &x->mg_args.st->ok, &x->mg_args.st->it);
     launch_mg_account2d(x, s);
@@ -2271,6 +2333,8 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
   x->dg32 = (float*)take(4 * N);
   x->ce32 = (float*)take(4 * N);
   x->cn32 = (float*)take(4 * N);
+  x->tensor = c->tensor2d;
+  x->cd = c->tensor2d ? (double*)take(8 * N) : nullptr;
   for (int k = 0; k < PCG_NVEC; k++) {
     if (c->precision == 1)
       x->v32[k] = (float*)take(4 * N);
@@ -2314,6 +2378,7 @@ void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x) {
       A.dg = x->dg;
       A.ce = x->ce;
       A.cn = x->cn;
+      A.cd = x->cd;
       A.b = x->b;
       A.x = x->x;
       A.r = (double*)take(8 * N);

@@ -108,6 +108,8 @@ int check_config(const swe_nh_config* c, std::string* why) {
   if (c->tile1d != 0 && (c->tile1d < 32 || c->tile1d > TILE_MAX))
     return bad("tile1d must be 0 or in [32, 512]");
   if (c->step1d_form != 0 && c->step1d_form != 1) return bad("step1d_form must be 0 or 1");
+  if (c->tensor2d != 0 && c->tensor2d != 1) return bad("tensor2d must be 0 or 1");
+  if (c->tensor2d && c->dim != 2) return bad("tensor2d is a 2D operator");
   if (c->precision != 0 && c->precision != 1) return bad("precision must be 0 or 1");
   if (!c->depth_static) return bad("depth_static is required");
   if (!c->bodies) return bad("bodies is required");
@@ -127,6 +129,11 @@ int check_config(const swe_nh_config* c, std::string* why) {
     if ((int64_t)c->nx * c->ny >= (int64_t(1) << 31)) return bad("grid too large");
     if (c->max_iter < 1) return bad("max_iter must be >= 1");
     if (!(c->tol > 0.0)) return bad("tol must be > 0");
+    if (c->tensor2d) {
+      int lnx[MG_MAXL + 1], lny[MG_MAXL + 1];
+      if (mg_plan_levels(c->nx, c->ny, lnx, lny) == 0)
+        return bad("tensor2d needs a grid that coarsens by 2 x 2 aggregation to <= 4096 cells");
+    }
   }
   return SWE_NH_OK;
 }

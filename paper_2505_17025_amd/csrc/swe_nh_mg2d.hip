@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(256) k_mg_identity(const MgState* st,
                                                      int tiles_x, int tx2, int ty2, int nx,
                                                      double* dg, double* ce, double* cn, double* b,
                                                      double* x, float* dg32, float* ce32,
-                                                     float* cn32, uint8_t* nb) {
+                                                     float* cn32, uint8_t* nb, double* cd) {
   if (!st->use || tile_pos[blockIdx.x] >= 0) return;
   const Box Bx = box_of(st, 0);
   const int i0 = (blockIdx.x % tiles_x) * tx2, j0 = (blockIdx.x / tiles_x) * ty2;
@@ -418,21 +418,34 @@ __global__ void __launch_bounds__(256) k_mg_identity(const MgState* st,
     ce32[o] = 0.0f;
     cn32[o] = 0.0f;
     nb[o] = 0;
+    if (cd) cd[o] = 0.0;
   }
 }
 
 // ---------------------------------------------------------------------------
 // conjugate gradients (FP64)
 // ---------------------------------------------------------------------------
+// the exact-tensor operator's two more couplings of cell (i, j) with v: to
+// (i+1, j-1), stored at the cell, and to (i-1, j+1), stored at that cell
+template <typename V>
+__device__ __forceinline__ double apply_diag(const MgArgs& A, const Box& Bx, V v, int64_t o,
+                                             int i, int j) {
+  double a = 0.0;
+  if (i + 1 < Bx.x1 && j > Bx.y0) a += A.cd[o] * v(o - A.nx + 1);
+  if (i > Bx.x0 && j + 1 < Bx.y1) a += A.cd[o + A.nx - 1] * v(o + A.nx - 1);
+  return a;
+}
+
 // A x at cell (i, j) of the box (couplings across the box's edge are zero:
 // the cells beyond it hold no marked cell)
-__device__ __forceinline__ double apply5_64(const MgArgs& A, const Box& Bx, const double* v,
-                                            int64_t o, int i, int j) {
+__device__ __forceinline__ double apply_64(const MgArgs& A, const Box& Bx, const double* v,
+                                           int64_t o, int i, int j) {
   double a = A.dg[o] * v[o];
   if (i > Bx.x0) a += A.ce[o - 1] * v[o - 1];
   if (i + 1 < Bx.x1) a += A.ce[o] * v[o + 1];
   if (j > Bx.y0) a += A.cn[o - A.nx] * v[o - A.nx];
   if (j + 1 < Bx.y1) a += A.cn[o] * v[o + A.nx];
+  if (A.cd) a += apply_diag(A, Bx, [&](int64_t u) { return v[u]; }, o, i, j);
   return a;
 }
 
@@ -454,7 +467,7 @@ __global__ void __launch_bounds__(NTM) k_cg_init(MgArgs A) {
   const Box Bx = box_of(A.st, 0);
   double rr = 0.0, bb = 0.0;
   for_box(A, Bx, [&](int64_t o, int i, int j) {
-    const double r = A.b[o] - apply5_64(A, Bx, A.x, o, i, j);
+    const double r = A.b[o] - apply_64(A, Bx, A.x, o, i, j);
     A.r[o] = r;
     rr += r * r;
     bb += A.b[o] * A.b[o];
@@ -484,6 +497,7 @@ __global__ void __launch_bounds__(NTM) k_cg_pq(MgArgs A) {
     if (i + 1 < Bx.x1) q += A.ce[o] * pv(o + 1);
     if (j > Bx.y0) q += A.cn[o - A.nx] * pv(o - A.nx);
     if (j + 1 < Bx.y1) q += A.cn[o] * pv(o + A.nx);
+    if (A.cd) q += apply_diag(A, Bx, pv, o, i, j);
     pn[o] = pc;
     A.q[o] = q;
     pq += pc * q;
@@ -559,7 +573,7 @@ __global__ void __launch_bounds__(NTM) k_cg_true(MgArgs A) {
   const Box Bx = box_of(A.st, 0);
   double rr = 0.0;
   for_box(A, Bx, [&](int64_t o, int i, int j) {
-    const double r = A.b[o] - apply5_64(A, Bx, A.x, o, i, j);
+    const double r = A.b[o] - apply_64(A, Bx, A.x, o, i, j);
     rr += r * r;
   });
   block_partial(rr, A.part);
@@ -571,7 +585,13 @@ __global__ void __launch_bounds__(NTM) k_cg_true(MgArgs A) {
 // no-convergence status is set.  Nothing when the tile solver has the step.
 __global__ void __launch_bounds__(1024) k_cg_finish(MgArgs A, int nb, int last) {
   MgState* st = A.st;
-  if (!st->use) return;
+  if (!st->use) {  // nothing marked (the tile solver, if any, has the step)
+    if (last && threadIdx.x == 0) {
+      *A.iters = 0;
+      *A.rel = 0.0;
+    }
+    return;
+  }
   const double rr = sum_partials(A.part, nb);
   if (threadIdx.x != 0) return;
   const bool ok = st->done == 1 && (st->bb == 0.0 || rr <= A.tol * A.tol * st->bb);
@@ -661,13 +681,14 @@ void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t 
   hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(1024), 0, s, A, g0, (int)last);
 }
 
-void launch_mg_box2d(Ctx2D* x, bool global, hipStream_t s) {
+void launch_mg_box2d(Ctx2D* x, bool global, int min_tiles, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_box, dim3(1), dim3(1024), 0, s, x->mg_args.st,
                      (const int*)x->tile_list, (const int*)x->n_tiles_act, x->tiles_x, TX2, TY2,
-                     x->nx, x->ny, 1 << x->mg_levels, global ? 1 : 0, MG_MIN_TILES);
+                     x->nx, x->ny, 1 << x->mg_levels, global ? 1 : 0, min_tiles);
   hipLaunchKernelGGL(k_mg_identity, dim3(x->ntiles), dim3(256), 0, s,
                      (const MgState*)x->mg_args.st, (const int*)x->tile_pos, x->tiles_x, TX2, TY2,
-                     x->nx, x->dg, x->ce, x->cn, x->b, x->x, x->dg32, x->ce32, x->cn32, x->nb);
+                     x->nx, x->dg, x->ce, x->cn, x->b, x->x, x->dg32, x->ce32, x->cn32, x->nb,
+                     x->cd);
 }
 
 void launch_mg_account2d(Ctx2D* x, hipStream_t s) {

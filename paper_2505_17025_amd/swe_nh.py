@@ -35,7 +35,7 @@ class swe_nh_config(C.Structure):
                 ("dt_fixed", C.c_double), ("crit", C.c_int32), ("k_nh", C.c_double),
                 ("enlarge", C.c_int32), ("first_global", C.c_int32), ("precision", C.c_int32),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("warm", C.c_int32),
-                ("tile1d", C.c_int32), ("step1d_form", C.c_int32),
+                ("tile1d", C.c_int32), ("step1d_form", C.c_int32), ("tensor2d", C.c_int32),
                 ("depth_static", C.c_void_p),
                 ("bodies", C.POINTER(swe_nh_body))]
 
@@ -146,7 +146,7 @@ class Context:
     def __init__(self, *, dim, nx, ny=1, dx, dy=0.0, depth_static: torch.Tensor,
                  bodies: Sequence, offsets: Optional[Sequence[int]] = None, g=9.81, rho=1000.0,
                  cfl=0.5, dt_fixed=0.0, crit=6, k_nh=1e-3, enlarge=1, first_global=1,
-                 precision=0, tol=1e-12, max_iter=8, warm=1, tile1d=0, step1d_form=0,
+                 precision=0, tol=1e-12, max_iter=8, warm=1, tile1d=0, step1d_form=0, tensor2d=0,
                  device="cuda"):
         self.device = torch.device(device)
         self.depth = depth_static.to(self.device, torch.float64).contiguous()
@@ -166,6 +166,7 @@ class Context:
         cfg.precision, cfg.tol, cfg.max_iter, cfg.warm = precision, tol, max_iter, warm
         cfg.tile1d = tile1d
         cfg.step1d_form = step1d_form
+        cfg.tensor2d = tensor2d
         cfg.depth_static = C.c_void_p(self.depth.data_ptr())
         cfg.bodies = self._bodies
         self.cfg = cfg

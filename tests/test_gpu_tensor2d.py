@@ -1,0 +1,172 @@
+"""GPU parity of the exact-tensor 2D operator (tensor2d = 1: the face
+tensor's off-diagonal on pairs of faces, a 7-point stencil) against the
+oracle's (oracle/swe_oracle.c, orc_nh_pairs_2d and the *7_2d routines),
+through the C ABI.
+
+The cases carry a planar tilt of the bottom in both directions (slopes
+0.05 and -0.04 on top of the random relief), so the pair coupling changes
+the pressure by far more than the bars: each test also checks that the
+diagonal (5-point) oracle misses the GPU result."""
+import numpy as np
+import pytest
+
+import oracle as O
+import swe_inputs as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_17025_amd import swe_nh
+    return swe_nh
+
+
+def dt_(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(g, r):
+    g = g.detach().cpu().numpy() if hasattr(g, "detach") else np.asarray(g)
+    return np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300)
+
+
+def tilted(c, sx=0.05, sy=-0.04):
+    """the case with a planar tilt added to the bottom and the water column"""
+    x = (np.arange(c.nx) + 0.5) * c.dx
+    y = (np.arange(c.ny) + 0.5) * c.dy
+    X, Y = np.meshgrid(x, y)
+    t = sx * X + sy * Y
+    t -= t.min()
+    c.ds = c.ds + t
+    c.h = c.h + t
+    return c
+
+
+def blob_mask(c, seed):
+    rng = np.random.default_rng(seed)
+    m = (rng.random((c.ny, c.nx)) < 0.2).astype(np.uint8)
+    m[5:40, 10:90] = 1
+    m[0:4, 0:6] = 1                       # a patch at the corner walls
+    m[c.ny - 6:, c.nx - 9:] = 1           # and at the opposite corner
+    m[20, :] = 1                          # a row spanning every tile column
+    m[:, 70] = 1                          # a column spanning every tile row
+    return m
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_tensor_pressure_and_projection_stage_parity(B, full):
+    c = tilted(S.random_case_2d(128, 96, seed=21, dx=0.5, dy=0.4, h0=2.0))
+    m = np.ones((c.ny, c.nx), np.uint8) if full else blob_mask(c, 2)
+    t0, dt = 0.2, 0.01
+    ph = O.phys_struct()
+    cell, xf, yf = O.nh_coeffs_2d(c.ds, c.dx, c.dy, c.body, ph, t0 + dt, dt, c.h, c.hu, c.hv, c.hw)
+    kxy = O.nh_pairs_2d(c.ds, c.dx, c.dy, c.body, t0 + dt, xf, yf)
+    rhs = O.nh_rhs_2d(cell, xf, yf, m)
+    pref, _, _ = O.cg_2d(cell, xf, yf, m, rhs, tol=1e-14, kxy=kxy)
+    p5, _, _ = O.cg_2d(cell, xf, yf, m, rhs, tol=1e-14)
+    ctx = B.context_2d(c, crit=S.CRIT_ETA_D, precision=0, tol=1e-13, max_iter=5000, warm=0,
+                       tensor2d=1)
+    p = torch.full((c.ny, c.nx), 3.0, dtype=torch.float64, device=DEV)
+    args = (dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw))
+    it, rr = ctx.solve_pressure(*args, torch.tensor(m, device=DEV), t0, dt, p)
+    st = ctx.sync_stats()
+    print("iterations", it, "rel_res", rr, "5-point vs 7-point", rel(p5, pref))
+    assert st["status"] == 0, st
+    assert rr <= 1e-13 and 0 < it <= 64
+    assert rel(p, pref) <= 1e-10
+    assert rel(p5, pref) > 1e-6  # the pair coupling is in effect
+    assert np.all(p.cpu().numpy()[m == 0] == 0.0)
+    mref, nref, kref = O.nh_correct_2d(cell, xf, yf, dt, 1000.0, c.hu, c.hv, c.hw, m, pref,
+                                       kxy=kxy)
+    outs = [torch.empty_like(args[0]) for _ in range(3)]
+    ctx.correct(*args, torch.tensor(m, device=DEV), dt_(pref), t0, dt, *outs)
+    assert ctx.sync_stats()["status"] == 0
+    assert rel(outs[0], mref) <= 1e-12
+    assert rel(outs[1], nref) <= 1e-12
+    assert rel(outs[2] - args[3], kref - c.hw) <= 1e-11
+    m5, n5, _ = O.nh_correct_2d(cell, xf, yf, dt, 1000.0, c.hu, c.hv, c.hw, m, pref)
+    assert rel(m5 - c.hu, mref - c.hu) > 1e-6
+
+
+def run2d(B, c, nsteps, **kw):
+    ctx = B.context_2d(c, **kw)
+    ctx.set_time(c.t0)
+    h, hu, hv, hw = dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw)
+    p = torch.zeros_like(h)
+    m = torch.zeros((c.ny, c.nx), dtype=torch.uint8, device=DEV)
+    ctx.step(h, hu, hv, hw, p, m, nsteps=nsteps)
+    return ctx, ctx.sync_stats(), h, hu, hv, hw, p, m
+
+
+@pytest.mark.parametrize("crit", [S.CRIT_GLOBAL, S.CRIT_ETA_D])
+@pytest.mark.parametrize("nx,ny", [(128, 96), (200, 80)])
+def test_tensor_steps_parity(B, crit, nx, ny):
+    """whole steps (the adaptive ones on the multigrid CG over the active
+    tiles' bounding box at any active-tile count; 200 x 80: ragged smoothing
+    tiles)"""
+    c = tilted(S.random_case_2d(nx, ny, seed=11, dx=0.5, dy=0.4, h0=2.0))
+    kw = dict(crit=crit, k_nh=0.04, enlarge=1, cfl=0.4, precision=0, tol=1e-13, max_iter=5000,
+              warm=1, tensor2d=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 6, **kw)
+    print("n_active", st["n_active"], "iterations", st["iters"], "rel_res", st["rel_res"])
+    assert st["status"] == 0, st
+    assert 0 < st["iters"] <= 64
+    ph = O.phys_struct(crit=crit, k_nh=0.04, enlarge=1, tol=1e-14, tensor=1)
+    ref = O.Sim2D(c, ph, cfl=0.4).step(6)
+    assert np.array_equal(m.cpu().numpy(), ref.mask)
+    assert st["n_active"] == ref.last_active
+    if crit == S.CRIT_ETA_D:
+        assert 0.1 * nx * ny < ref.last_active < 0.9 * nx * ny
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+    ref5 = O.Sim2D(c, O.phys_struct(crit=crit, k_nh=0.04, enlarge=1, tol=1e-14), cfl=0.4).step(6)
+    assert rel(p, ref5.p) > 1e-6
+
+
+def test_tensor_adaptive_box_with_few_tiles(B):
+    """a small hump on a larger grid: a handful of active tiles, whose
+    bounding box leaves most of the grid out, still on the multigrid CG
+    (the tile solver has no tensor operator); two contexts give the same bits"""
+    c = tilted(S.hump_case_2d(256, 192, seed=5, amp=0.01, radius=12.0), sx=0.03, sy=0.02)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, cfl=0.4, precision=0, tol=1e-13,
+              max_iter=5000, warm=1, tensor2d=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 3, **kw)
+    print("active", st["n_active"], "iterations", st["iters"], "rel_res", st["rel_res"])
+    assert st["status"] == 0, st
+    assert 0 < st["n_active"] < 8 * 512
+    ref = O.Sim2D(c, O.phys_struct(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1, tol=1e-14, tensor=1),
+                  cfl=0.4).step(3)
+    assert np.array_equal(m.cpu().numpy(), ref.mask)
+    for g, r in ((h - dt_(c.ds), ref.h - c.ds), (hu, ref.hu), (hv, ref.hv), (hw, ref.hw), (p, ref.p)):
+        assert rel(g, r) <= 1e-10
+    again = run2d(B, c, 3, **kw)
+    for x, y in zip((h, hu, hv, hw, p), again[2:7]):
+        assert torch.equal(x, y)
+
+
+def test_tensor_no_convergence_status(B):
+    c = tilted(S.random_case_2d(128, 96, seed=3, dx=0.5, dy=0.4, h0=2.0))
+    kw = dict(crit=S.CRIT_GLOBAL, cfl=0.4, precision=0, tol=1e-14, max_iter=2, warm=0,
+              tensor2d=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 1, **kw)
+    assert st["status"] == B.ENOCONV
+    assert st["iters"] == 2 and st["rel_res"] > 1e-14
+    assert torch.isfinite(p).all()
+
+
+def test_tensor_config_checks(B):
+    """grids that do not coarsen to the multigrid's coarsest level, and 1D,
+    are rejected at init"""
+    c = S.random_case_2d(70, 37, seed=3)
+    with pytest.raises(B.SweNhError) as e:
+        B.context_2d(c, crit=S.CRIT_GLOBAL, tensor2d=1)
+    assert e.value.code == B.EINVAL
+    c1 = S.random_case_1d(64, seed=1)
+    with pytest.raises(B.SweNhError) as e:
+        B.context_1d(c1, tensor2d=1)
+    assert e.value.code == B.EINVAL
