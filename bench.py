@@ -767,7 +767,10 @@ def run_2d(B, torch, S, steps, warmup, preroll=0):
     out = {}
     for name, kw in (("adaptive_fp32", dict(crit=S.CRIT_ETA_D, precision=1)),
                      ("adaptive_fp64", dict(crit=S.CRIT_ETA_D, precision=0)),
-                     ("global_fp32", dict(crit=S.CRIT_GLOBAL, precision=1))):
+                     ("global_fp32", dict(crit=S.CRIT_GLOBAL, precision=1)),
+                     # the exact-tensor (7-point) operator, solved by the multigrid CG
+                     ("adaptive_tensor", dict(crit=S.CRIT_ETA_D, precision=0, tensor2d=1)),
+                     ("global_tensor", dict(crit=S.CRIT_GLOBAL, precision=0, tensor2d=1))):
         ctx = B.context_2d(c, k_nh=1e-3, enlarge=1, cfl=0.5, tol=1e-10, max_iter=5000, warm=1,
                            **kw)
         log(f"{name}: {warmup} warmup + {steps} timed steps")

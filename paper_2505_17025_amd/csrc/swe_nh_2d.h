@@ -17,8 +17,14 @@ constexpr int CMAX2 = 128;     // most active tiles for which the solver adds th
 
 constexpr int MG_MAXL = 12;    // most levels of the multigrid preconditioner (global extension)
 constexpr int MG_BUDGET = 32;  // iterations of the multigrid-preconditioned CG in a step
-// the same for the exact-tensor operator, which no other solver continues
-constexpr int MG_BUDGET_TENSOR = 64;
+// the same for the exact-tensor operator, which no other solver continues: a
+// first solve of MG_TENSOR_FIRST iterations, then a restart from the true
+// residual of its iterate (for a recursive residual that drifted from the
+// true one, or more iterations) up to MG_BUDGET_TENSOR in all.  Every
+// iteration's launches are paid whether or not it is needed (about 2 us
+// each), which is why the restart's share is small
+constexpr int MG_TENSOR_FIRST = 40;
+constexpr int MG_BUDGET_TENSOR = 48;
 constexpr int MG_COARSE_MAX = 4096;  // most cells of the multigrid's coarsest level (one block)
 // active tiles above which an adaptive step's system goes to the multigrid CG
 // on the active tiles' bounding box: up to CMAX2 tiles the tile solver has
@@ -51,7 +57,9 @@ struct MgArgs {
   double* part = nullptr;  // block partial sums [2][npart]
   int npart = 0;
   MgState* st = nullptr;
-  double tol = 0.0;
+  double tol = 0.0;      // on the true residual of the final iterate
+  double tol_rec = 0.0;  // on the recursively updated residual (the stopping test)
+  int restart = 0;       // a second solve from the true residual of the first one's iterate
   int* iters = nullptr;
   long long* iters_sum = nullptr;
   double* rel = nullptr;
@@ -80,9 +88,9 @@ struct Ctx2D {
   double *dg = nullptr, *ce = nullptr, *cn = nullptr, *b = nullptr, *x = nullptr;
   float *dg32 = nullptr, *ce32 = nullptr, *cn32 = nullptr;
   uint8_t* nb = nullptr;
-  // the exact-tensor operator (tensor2d): each cell's coupling with (i+1, j-1);
-  // the FP32 copy (the multigrid's level 0) drops these couplings and adds
-  // their magnitudes to its diagonal, which keeps it above the operator
+  // the exact-tensor operator (tensor2d): each cell's coupling with (i+1, j-1)
+  // (dg, ce, cn then hold the 7-point operator's entries; the FP32 copy, the
+  // multigrid's level 0, stays the 5-point operator, which preconditions it)
   double* cd = nullptr;
   int tensor = 0;
   // inner Krylov vectors, FP32 (precision 1) or FP64 (precision 0):
@@ -145,7 +153,10 @@ void launch_mg_box2d(Ctx2D* x, bool global, int min_tiles, hipStream_t s);
 // last, a solve that misses the tolerance sets the no-convergence status;
 // otherwise another solver continues (launch_mg_account2d after it adds the
 // multigrid iterations to the statistics)
-void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t s);
+// With restart, it continues a previous solve that missed the tolerance from
+// the true residual of its iterate (and does nothing after one that met it);
+// the coarse operators are that solve's, the iteration counts add up.
+void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, bool restart, hipStream_t s);
 void launch_mg_account2d(Ctx2D* x, hipStream_t s);
 
 void plan2d(const swe_nh_config* c, char* base, size_t* off, Ctx2D* x);

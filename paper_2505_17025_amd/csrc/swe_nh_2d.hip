@@ -771,36 +771,33 @@ __global__ void __launch_bounds__(NT2) k_assemble2d(G2 G, const double* __restri
     const double f2 = -2.0 * br.d_t - 2.0 * kt[o] / hs -
                       (R.Dx[w] * mt[o] + R.Dy[w] * nt[o]) / (2.0 * hs) -
                       dt * al * R.phi[w] / (2.0 * G.rho * hs);
-    double dg = s22 + fw.K * fw.b * fw.b + fe.K * fe.a * fe.a + fs.K * fs.b * fs.b +
-                fn.K * fn.a * fn.a;
-    double ce = (nb & NB_E) ? fe.K * fe.a * fe.b : 0.0;
-    double cn = (nb & NB_N) ? fn.K * fn.a * fn.b : 0.0;
-    double lump = 0.0;
+    const double dg = s22 + fw.K * fw.b * fw.b + fe.K * fe.a * fe.a + fs.K * fs.b * fs.b +
+                      fn.K * fn.a * fn.a;
+    const double ce = (nb & NB_E) ? fe.K * fe.a * fe.b : 0.0;
+    const double cn = (nb & NB_N) ? fn.K * fn.a * fn.b : 0.0;
+    // the FP32 copy (the multigrid's level 0) is the 5-point operator in both
+    // forms: with the exact tensor it preconditions the 7-point operator
+    Y.dg32[o] = (float)dg;
+    Y.ce32[o] = (float)ce;
+    Y.cn32[o] = (float)cn;
     if (G.tensor) {
       // this cell's pair (its east and north faces) adds to its diagonal and
       // to its couplings with E and N; the pair of the cell below couples
-      // this cell with (i+1, j-1), the pair of the cell to the west couples it
-      // with (i-1, j+1) (stored at that cell; here only for the FP32 copy)
+      // this cell with (i+1, j-1), stored here (the coupling with (i-1, j+1)
+      // is stored at that cell)
       const double k0 = pair_k(fe, fn);
-      dg += 2.0 * k0 * fe.a * fn.a;
-      if (nb & NB_E) ce += k0 * fn.a * fe.b;
-      if (nb & NB_N) cn += k0 * fe.a * fn.b;
       const Face2 feS = face_coef(R, G, dt, w - RGX, w - RGX + 1, true);
-      const Face2 fnW = face_coef(R, G, dt, w - 1, w - 1 + RGX, false);
       const bool se = i + 1 < G.nx && j > 0 && mask[o - G.nx + 1];
-      const bool nw = i > 0 && j + 1 < G.ny && mask[o + G.nx - 1];
-      const double cse = se ? pair_k(feS, fs) * feS.b * fs.b : 0.0;
-      const double cnw = nw ? pair_k(fw, fnW) * fw.b * fnW.b : 0.0;
-      Y.cd[o] = cse;
-      lump = fabs(cse) + fabs(cnw);
+      Y.dg[o] = dg + 2.0 * k0 * fe.a * fn.a;
+      Y.ce[o] = (nb & NB_E) ? ce + k0 * fn.a * fe.b : 0.0;
+      Y.cn[o] = (nb & NB_N) ? cn + k0 * fe.a * fn.b : 0.0;
+      Y.cd[o] = se ? pair_k(feS, fs) * feS.b * fs.b : 0.0;
+    } else {
+      Y.dg[o] = dg;
+      Y.ce[o] = ce;
+      Y.cn[o] = cn;
     }
-    Y.dg[o] = dg;
-    Y.ce[o] = ce;
-    Y.cn[o] = cn;
     Y.b[o] = f2 + fw.b * fw.qp + fe.a * fe.qp + fs.b * fs.qp + fn.a * fn.qp;
-    Y.dg32[o] = (float)(dg + lump);
-    Y.ce32[o] = (float)ce;
-    Y.cn32[o] = (float)cn;
     Y.x[o] = warm ? p_prev[o] : 0.0;
   }
 }
@@ -2276,14 +2273,18 @@ void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
     const bool global = c->crit == SWE_NH_CRIT_GLOBAL;
     if (x->tensor) {
       // the exact-tensor operator: the multigrid CG at every active-tile
-      // count (the tile solver's blocks exchange no corner values), with no
-      // solver to continue it
+      // count (the tile solver's blocks exchange no corner values); a solve
+      // that misses the tolerance within MG_TENSOR_FIRST iterations, or whose
+      // recursive residual drifted from the true one, is restarted from the
+      // true residual of its iterate for the rest of MG_BUDGET_TENSOR
       launch_mg_box2d(x, global, 0, s);
-      launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET_TENSOR), true, s);
+      const int b1 = std::min(c->max_iter, MG_TENSOR_FIRST);
+      launch_mg_solve2d(x, c->tol, b1, false, false, s);
+      launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET_TENSOR) - b1, true, true, s);
       return;
     }
     launch_mg_box2d(x, global, MG_MIN_TILES, s);
-    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), false, s);
+    launch_mg_solve2d(x, c->tol, std::min(c->max_iter, MG_BUDGET), false, false, s);
     launch_tile_solve2d(c, x, s, !global, &x->mg_args.st->ok, &x->mg_args.st->it);
     launch_mg_account2d(x, s);
     return;

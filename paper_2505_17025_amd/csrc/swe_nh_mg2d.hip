@@ -462,8 +462,11 @@ __device__ __forceinline__ void for_box(const MgArgs& A, const Box& Bx, F f) {
 }
 
 // r = b - A x, partial sums of r.r and b.b
+// a restarted solve does nothing after a first solve that met the tolerance
+__device__ __forceinline__ bool restart_done(const MgArgs& A) { return A.restart && A.st->ok; }
+
 __global__ void __launch_bounds__(NTM) k_cg_init(MgArgs A) {
-  if (!A.st->use) return;
+  if (!A.st->use || restart_done(A)) return;
   const Box Bx = box_of(A.st, 0);
   double rr = 0.0, bb = 0.0;
   for_box(A, Bx, [&](int64_t o, int i, int j) {
@@ -541,7 +544,7 @@ __device__ double sum_partials(const double* part, int nb) {
 // convergence test, the iteration count)
 __global__ void __launch_bounds__(1024) k_cg_scalars(MgArgs A, int what, int nb) {
   MgState* st = A.st;
-  if (!st->use || (what != 0 && st->done)) return;
+  if (!st->use || (what != 0 && st->done) || restart_done(A)) return;
   const double s = sum_partials(A.part, nb);
   if (what == 0) {
     const double bb = sum_partials(A.part + A.npart, nb);
@@ -549,7 +552,7 @@ __global__ void __launch_bounds__(1024) k_cg_scalars(MgArgs A, int what, int nb)
       st->bb = bb;
       st->rr = s;
       st->it = 0;
-      st->done = (bb == 0.0 || s <= A.tol * A.tol * bb) ? 1 : 0;
+      st->done = (bb == 0.0 || s <= A.tol_rec * A.tol_rec * bb) ? 1 : 0;
     }
     return;
   }
@@ -563,13 +566,13 @@ __global__ void __launch_bounds__(1024) k_cg_scalars(MgArgs A, int what, int nb)
     st->rr = s;
     st->it += 1;
     if (!(s == s)) st->done = 2;  // not a number: stop, reported as no convergence
-    else if (s <= A.tol * A.tol * st->bb) st->done = 1;
+    else if (s <= A.tol_rec * A.tol_rec * st->bb) st->done = 1;
   }
 }
 
 // partial sums of the true residual ||b - A x||^2 of the final iterate
 __global__ void __launch_bounds__(NTM) k_cg_true(MgArgs A) {
-  if (!A.st->use) return;
+  if (!A.st->use || restart_done(A)) return;
   const Box Bx = box_of(A.st, 0);
   double rr = 0.0;
   for_box(A, Bx, [&](int64_t o, int i, int j) {
@@ -592,11 +595,12 @@ __global__ void __launch_bounds__(1024) k_cg_finish(MgArgs A, int nb, int last) 
     }
     return;
   }
+  if (restart_done(A)) return;
   const double rr = sum_partials(A.part, nb);
   if (threadIdx.x != 0) return;
   const bool ok = st->done == 1 && (st->bb == 0.0 || rr <= A.tol * A.tol * st->bb);
   st->ok = ok ? 1 : 0;
-  *A.iters = st->it;
+  *A.iters = A.restart ? *A.iters + st->it : st->it;
   *A.iters_sum += st->it;
   *A.rel = st->bb > 0.0 ? sqrt(rr / st->bb) : 0.0;
   if (last && !ok) atomicOr(A.status, ST_NOCONV);
@@ -633,18 +637,25 @@ static int tiles_of(int nx, int ny) {
 
 int mg_partials(int nx, int ny) { return std::max(MG_GRID_MAX, tiles_of(nx, ny)); }
 
-void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, hipStream_t s) {
+void launch_mg_solve2d(Ctx2D* x, double tol, int budget, bool last, bool restart,
+                       hipStream_t s) {
   const int L = x->mg_levels;
   const int64_t n0 = (int64_t)x->nx * x->ny;
   MgArgs A = x->mg_args;
   A.tol = tol;
+  // the recursive residual stops the iteration; the true residual of the
+  // final iterate must then meet tol.  With no solver to continue (last), the
+  // recursion aims at half the tolerance, so that its drift from the true
+  // residual cannot fail a converged solve
+  A.tol_rec = last ? 0.5 * tol : tol;
+  A.restart = restart ? 1 : 0;
   auto lvl = [&](int l) {
     return Lvl{x->mg_nx[l], x->mg_ny[l], l, x->mg_c[l], x->mg_e[l], x->mg_n[l]};
   };
   auto tiles = [&](int l) { return tiles_of(x->mg_nx[l], x->mg_ny[l]); };
   // the coarse operators of this solve (level 0 is the FP32 copy of the
   // operator written by the assembly)
-  for (int l = 0; l < L; l++) {
+  for (int l = 0; l < L && !restart; l++) {
     const int64_t nc = (int64_t)x->mg_nx[l + 1] * x->mg_ny[l + 1];
     hipLaunchKernelGGL(k_mg_coarsen, dim3(blocks_for(nc)), dim3(NTM), 0, s, x->mg_nx[l],
                        (const float*)x->mg_c[l], (const float*)x->mg_e[l],
