@@ -93,6 +93,11 @@ struct Ctx2D {
   // multigrid's level 0, stays the 5-point operator, which preconditions it)
   double* cd = nullptr;
   int tensor = 0;
+  // an adaptive 5-point step captured without the multigrid's launches (the
+  // tile solver takes every step): chosen by the host while few tiles are
+  // active, where the multigrid would not be used and its idle launches cost
+  // more than the solve
+  int mg_off = 0;
   // inner Krylov vectors, FP32 (precision 1) or FP64 (precision 0):
   // r, u, w, z, q, s, p, e, m[2] of the pipelined CG
   float* v32[PCG_NVEC] = {};

@@ -2263,7 +2263,8 @@ void launch_tile_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s, bool c
 }
 
 void launch_solve2d(const swe_nh_config* c, Ctx2D* x, hipStream_t s) {
-  if (x->mg_levels > 0) {
+  const bool mg_off = x->mg_off && !x->tensor && c->crit != SWE_NH_CRIT_GLOBAL;
+  if (x->mg_levels > 0 && !mg_off) {
     // the multigrid CG on its box (the whole grid in the global extension,
     // the active tiles' bounding box when they are many) for up to MG_BUDGET
     // iterations (a captured step cannot size a launch sequence by the

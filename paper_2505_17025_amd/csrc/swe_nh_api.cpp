@@ -75,6 +75,14 @@ struct swe_nh_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraphExec_t gexec2 = nullptr;
   hipGraphExec_t gexecN = nullptr;  // fused 1D path: GSTEPS steps in one graph
+  // adaptive 2D (5-point): the step without the multigrid's launches, chosen
+  // from the active-tile count of an earlier call (read back through pinned
+  // memory once an event says the copy is done; never waited for)
+  hipGraphExec_t gexecT = nullptr;
+  int* tiles_host = nullptr;
+  hipEvent_t tiles_ev = nullptr;
+  bool tiles_pending = false;
+  bool mg_graph = false;
   const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t steps_taken = 0;
 };
@@ -382,6 +390,14 @@ int after_launch(swe_nh_ctx* c) {
   return SWE_NH_OK;
 }
 
+// adaptive 2D steps with the 5-point operator choose per call between a step
+// graph with the multigrid's launches and one without (the tile solver then
+// takes every step, as it can at any active-tile count)
+bool mg_choice(const swe_nh_ctx* c) {
+  return c->cfg.dim == 2 && c->c2.mg_levels > 0 && !c->c2.tensor &&
+         c->cfg.crit != SWE_NH_CRIT_GLOBAL && c->cfg.crit != SWE_NH_CRIT_NONE;
+}
+
 // captures the work enqueued by f on the private stream into an executable graph
 template <typename F>
 int capture_graph(swe_nh_ctx* c, F f, hipGraphExec_t* out) {
@@ -439,6 +455,14 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   if (e != hipSuccess) {
     delete c;
     return SWE_NH_EHIP;
+  }
+  if (mg_choice(c)) {
+    e = hipHostMalloc((void**)&c->tiles_host, sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tiles_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      swe_nh_destroy(c);
+      return SWE_NH_EHIP;
+    }
   }
   // channel table
   std::vector<Chan> ch(c->nch);
@@ -547,6 +571,9 @@ void swe_nh_destroy(swe_nh_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->gexec2) hipGraphExecDestroy(c->gexec2);
   if (c->gexecN) hipGraphExecDestroy(c->gexecN);
+  if (c->gexecT) hipGraphExecDestroy(c->gexecT);
+  if (c->tiles_ev) hipEventDestroy(c->tiles_ev);
+  if (c->tiles_host) hipHostFree(c->tiles_host);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
@@ -575,14 +602,32 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
   if ((c->cfg.dim == 1) != (hv == nullptr)) return fail(c, SWE_NH_EINVAL, "hv must be NULL iff dim == 1");
   const bool fused = c->cfg.dim == 1 && c->k1.fused;
   const void* key[6] = {h, hu, hv, hw, p, mask};
-  bool same = c->gexec != nullptr;
+  bool same = c->gexec != nullptr || c->gexecT != nullptr;
   for (int i = 0; i < 6 && same; i++) same = (key[i] == c->gkey[i]);
+  const bool choice = mg_choice(c);
+  if (choice && c->tiles_pending) {
+    // the active tiles at the end of an earlier call, if its copy is done:
+    // the multigrid graph above MG_MIN_TILES of them, back to the tile
+    // solver's below half of that
+    const hipError_t q = hipEventQuery(c->tiles_ev);
+    if (q == hipSuccess) {
+      c->tiles_pending = false;
+      const int nt = *c->tiles_host;
+      if (nt > MG_MIN_TILES) c->mg_graph = true;
+      else if (nt <= MG_MIN_TILES / 2) c->mg_graph = false;
+    } else {
+      (void)hipGetLastError();  // not ready is not an error of this call
+    }
+  }
+  hipGraphExec_t* g2d = (choice && !c->mg_graph) ? &c->gexecT : &c->gexec;
   if (!same) {
-    for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})
+    for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN, &c->gexecT})
       if (*g) {
         hipGraphExecDestroy(*g);
         *g = nullptr;
       }
+  }
+  if (!same || (c->cfg.dim == 2 && *g2d == nullptr)) {
     int rc;
     if (fused) {
       // even steps: caller arrays -> workspace; odd steps: back
@@ -602,16 +647,18 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
             enqueue_fused1d(c, s, c->ht, c->mt, c->kt, h, hu, hw, p, mask, 1);
           }
         }, &c->gexecN);
+    } else if (c->cfg.dim == 1) {
+      rc = capture_graph(c, [&](hipStream_t s) { enqueue_step1d(c, s, h, hu, hw, p, mask); },
+                         &c->gexec);
     } else {
+      c->c2.mg_off = g2d == &c->gexecT ? 1 : 0;
       rc = capture_graph(c, [&](hipStream_t s) {
-        if (c->cfg.dim == 1)
-          enqueue_step1d(c, s, h, hu, hw, p, mask);
-        else
-          enqueue_step2d(&c->cfg, &c->c2, s, h, hu, hv, hw, p, mask);
-      }, &c->gexec);
+        enqueue_step2d(&c->cfg, &c->c2, s, h, hu, hv, hw, p, mask);
+      }, g2d);
+      c->c2.mg_off = 0;
     }
     if (rc != SWE_NH_OK) {
-      for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})
+      for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN, &c->gexecT})
         if (*g) {
           hipGraphExecDestroy(*g);
           *g = nullptr;
@@ -633,8 +680,15 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
   int i = 0;
   if (fused)
     for (; i + GSTEPS <= nsteps; i += GSTEPS) HIPCHK(c, hipGraphLaunch(c->gexecN, c->stream));
+  hipGraphExec_t one = c->cfg.dim == 2 ? *g2d : c->gexec;
   for (; i < nsteps; i++)
-    HIPCHK(c, hipGraphLaunch((fused && (i & 1)) ? c->gexec2 : c->gexec, c->stream));
+    HIPCHK(c, hipGraphLaunch((fused && (i & 1)) ? c->gexec2 : one, c->stream));
+  if (choice && nsteps > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->tiles_host, c->c2.n_tiles_act, sizeof(int),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(c->tiles_ev, c->stream));
+    c->tiles_pending = true;
+  }
   if (fused && nsteps > 0) {
     if (nsteps & 1) {  // the last step wrote the workspace copy
       launch_copy(c->ht, h, c->ncells, c->stream);
@@ -825,7 +879,7 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* c, const float* params, const double* 
   pack_net2d(&c->c2, c->stream);
   int rc = after_launch(c);
   if (rc) return rc;
-  for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN})  // the step must pick up the network
+  for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN, &c->gexecT})  // the step must pick up the network
     if (*g) {
       hipGraphExecDestroy(*g);
       *g = nullptr;

@@ -4,10 +4,11 @@
 // 32 -> 32 -> 1, ReLU between layers.  Activations are BF16 in NHWC layout,
 // weights are kept in FP32 (master copy, [Cout][3][3][Cin] per layer followed
 // by the biases) and packed to BF16 per launch; every product accumulates in
-// FP32 on v_mfma_f32_16x16x16_bf16.
+// FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16 where a layer has 32
+// input channels, v_mfma_f32_16x16x16_bf16 for the first layer's 16).
 //
 // A convolution is an implicit GEMM: M = 16 pixels of an image row, N = 16
-// output channels, K = 16 input channels of one tap.  A block owns a 16 x 16
+// output channels, K = the input channels of one tap (32, or 16).  A block owns a 16 x 16
 // pixel tile (4 waves x 4 rows), with the input patch (tile + 1-pixel halo)
 // and the packed weights in LDS.  The input-gradient pass is the same kernel
 // on the output gradient with the weights transposed and the taps flipped,
@@ -27,6 +28,7 @@ namespace swenh {
 namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int CT = 16;       // tile edge (pixels)
@@ -121,22 +123,50 @@ __global__ void __launch_bounds__(NTC) k_conv(const uint16_t* __restrict__ in,
   for (int r = 0; r < 4; r++)
 #pragma unroll
     for (int nb = 0; nb < NB; nb++) acc[r][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (CI % 32 == 0) {
+    // K = 32 input channels per product (gfx950's 16x16x32 BF16 form: lane
+    // holds 8 consecutive k of row / column lane % 16, k0 = 8 (lane / 16))
+    const int kq8 = (lane >> 4) * 8;
 #pragma unroll 1
-  for (int t = 0; t < 9; t++) {
-    const int ky = t / 3, kx = t % 3;
+    for (int t = 0; t < 9; t++) {
+      const int ky = t / 3, kx = t % 3;
 #pragma unroll
-    for (int c0 = 0; c0 < CI; c0 += 16) {
-      s4 b[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; nb++)
-        b[nb] = *reinterpret_cast<const s4*>(wts + ((nb * 16 + xr) * 9 + t) * RS + c0 + kq);
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int y = wv * 4 + r;
-        const s4 a = *reinterpret_cast<const s4*>(patch + ((y + ky) * PW + xr + kx) * RS + c0 + kq);
+      for (int c0 = 0; c0 < CI; c0 += 32) {
+        bf8 b[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; nb++)
-          acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[r][nb], 0, 0, 0);
+          b[nb] = *reinterpret_cast<const bf8*>(wts + ((nb * 16 + xr) * 9 + t) * RS + c0 + kq8);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int y = wv * 4 + r;
+          const bf8 a =
+              *reinterpret_cast<const bf8*>(patch + ((y + ky) * PW + xr + kx) * RS + c0 + kq8);
+#pragma unroll
+          for (int nb = 0; nb < NB; nb++)
+            acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[r][nb], 0, 0, 0);
+        }
+      }
+    }
+  } else {
+    // K = 16 (the first layer's 16 input channels)
+#pragma unroll 1
+    for (int t = 0; t < 9; t++) {
+      const int ky = t / 3, kx = t % 3;
+#pragma unroll
+      for (int c0 = 0; c0 < CI; c0 += 16) {
+        s4 b[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+          b[nb] = *reinterpret_cast<const s4*>(wts + ((nb * 16 + xr) * 9 + t) * RS + c0 + kq);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int y = wv * 4 + r;
+          const s4 a =
+              *reinterpret_cast<const s4*>(patch + ((y + ky) * PW + xr + kx) * RS + c0 + kq);
+#pragma unroll
+          for (int nb = 0; nb < NB; nb++)
+            acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[r][nb], 0, 0, 0);
+        }
       }
     }
   }
@@ -254,23 +284,36 @@ __global__ void __launch_bounds__(NTC) k_conv_bwdw(const uint16_t* __restrict__ 
   if (threadIdx.x < CO) part_b[(int64_t)blockIdx.x * CO + threadIdx.x] = bsum;
 }
 
-// grad[layer] = sum over blocks of the partials (fixed order)
-__global__ void k_reduce_w(const float* __restrict__ part, const float* __restrict__ part_b,
-                           int nblk, int cin, int co_real, int co_pad, float* __restrict__ gw,
-                           float* __restrict__ gb) {
-  const int nw = co_real * 9 * cin;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nw + co_real;
-       e += gridDim.x * blockDim.x) {
-    float s = 0.0f;
-    if (e < nw) {
-      for (int b = 0; b < nblk; b++) s += part[(int64_t)b * co_pad * 9 * cin + e];
-      gw[e] = s;
-    } else {
-      const int co = e - nw;
-      for (int b = 0; b < nblk; b++) s += part_b[(int64_t)b * co_pad + co];
-      gb[co] = s;
-    }
+// grad[layer] = sum over blocks of the partials, in a fixed order: 64
+// gradient entries per block, each of its 8 wavefronts sums a contiguous
+// eighth of the partials, wavefront 0 adds the eight sums in order (one
+// thread per entry walking every partial left most CUs idle)
+constexpr int RW_WAVES = 8;
+__global__ void __launch_bounds__(64 * RW_WAVES) k_reduce_w(const float* __restrict__ part,
+                                                            const float* __restrict__ part_b,
+                                                            int nblk, int cin, int co_real,
+                                                            int co_pad, float* __restrict__ gw,
+                                                            float* __restrict__ gb) {
+  __shared__ float red[RW_WAVES][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = co_real * 9 * cin, e = blockIdx.x * 64 + lane;
+  const int per = (nblk + RW_WAVES - 1) / RW_WAVES;
+  const int b0 = min(nblk, wv * per), b1 = min(nblk, b0 + per);
+  float s = 0.0f;
+  if (e < nw) {
+    for (int b = b0; b < b1; b++) s += part[(int64_t)b * co_pad * 9 * cin + e];
+  } else if (e < nw + co_real) {
+    for (int b = b0; b < b1; b++) s += part_b[(int64_t)b * co_pad + (e - nw)];
   }
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0 || e >= nw + co_real) return;
+  float t = red[0][lane];
+  for (int k = 1; k < RW_WAVES; k++) t += red[k][lane];
+  if (e < nw)
+    gw[e] = t;
+  else
+    gb[e - nw] = t;
 }
 
 // FP32 output gradient of the last layer -> BF16 NHWC with 16 channels
@@ -309,12 +352,30 @@ __global__ void k_mse_part(const float* __restrict__ o, const float* __restrict_
   }
 }
 
-__global__ void k_mse_final(const double* part, int nb, float* loss, double* wsum) {
-  if (threadIdx.x != 0) return;
+// the loss from the block partials: one block, a fixed order (each thread a
+// strided subset, then the wavefronts' sums in order)
+constexpr int MF_NT = 1024;
+__global__ void __launch_bounds__(MF_NT) k_mse_final(const double* part, int nb, float* loss,
+                                                     double* wsum) {
+  __shared__ double sh[2][MF_NT / 64];
   double a = 0.0, b = 0.0;
-  for (int k = 0; k < nb; k++) {
+  for (int k = threadIdx.x; k < nb; k += MF_NT) {
     a += part[2 * k];
     b += part[2 * k + 1];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = a;
+    sh[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  a = 0.0;
+  b = 0.0;
+  for (int k = 0; k < MF_NT / 64; k++) {
+    a += sh[0][k];
+    b += sh[1][k];
   }
   *wsum = b;
   *loss = b > 0.0 ? (float)(a / b) : 0.0f;
@@ -546,7 +607,7 @@ void cnn_backward(const float* params, const uint16_t* x, const float* dout, int
       hipLaunchKernelGGL((k_conv_bwdw<16, 32>), dim3(L.nblk_w), dim3(NTC), 0, s, xin, dy, n, h, w,
                          part, part_b);
     const int nw = COUTL[l] * 9 * CINL[l] + COUTL[l];
-    hipLaunchKernelGGL(k_reduce_w, dim3((nw + NTC - 1) / NTC), dim3(NTC), 0, s, part, part_b,
+    hipLaunchKernelGGL(k_reduce_w, dim3((nw + 63) / 64), dim3(64 * RW_WAVES), 0, s, part, part_b,
                        L.nblk_w, CINL[l], COUTL[l], cpad16(COUTL[l]), gw, gb);
     if (l > 0) {
       uint16_t* dx = bufs[l & 1];
@@ -571,7 +632,7 @@ void cnn_mse(const float* o, const float* t, const float* wgt, int64_t n, char* 
   double* wsum = reinterpret_cast<double*>(ws + L.mse_w);
   const int nb = blocks_of(n) < 1024 ? blocks_of(n) : 1024;
   hipLaunchKernelGGL(k_mse_part, dim3(nb), dim3(NTC), 0, s, o, t, wgt, n, part);
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, loss, wsum);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(MF_NT), 0, s, (const double*)part, nb, loss, wsum);
   hipLaunchKernelGGL(k_mse_grad, dim3(blocks_of(n)), dim3(NTC), 0, s, o, t, wgt, n,
                      (const double*)wsum, dout);
 }
@@ -582,7 +643,7 @@ void cnn_bce(const float* o, const float* t, const float* wgt, int64_t n, char* 
   double* wsum = reinterpret_cast<double*>(ws + L.mse_w);
   const int nb = blocks_of(n) < 1024 ? blocks_of(n) : 1024;
   hipLaunchKernelGGL(k_bce_part, dim3(nb), dim3(NTC), 0, s, o, t, wgt, n, part);
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, s, (const double*)part, nb, loss, wsum);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(MF_NT), 0, s, (const double*)part, nb, loss, wsum);
   hipLaunchKernelGGL(k_bce_grad, dim3(blocks_of(n)), dim3(NTC), 0, s, o, t, wgt, n,
                      (const double*)wsum, dout);
 }
