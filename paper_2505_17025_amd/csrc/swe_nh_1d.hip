@@ -1978,22 +1978,192 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
 
 
 
+// LDS of the level-1 solve of one channel (rows of its marked tiles)
+template <int NT>
+struct L1Smem {
+  double la[L1MAX], lb[L1MAX], lc[L1MAX], ld[L1MAX], lr[L1MAX];
+  double rdg[L1MAX], rup[L1MAX], rrh[L1MAX];  // level-1 rows as stored (2 per tile)
+  int rcnt[L1MAX / 2];
+  int tpos[L1MAX / 2], tlist[L1MAX / 2];  // tile <-> compact level-1 tile
+  int wc[NT / 64];
+};
+
+// The level-1 system of the tiles [t_lo, t_lo + ntc) (one channel, at most
+// L1MAX / 2 tiles: the channels' systems are decoupled) restricted to its
+// marked tiles (an unmarked tile's two identity rows are decoupled from
+// everything), in tile order, solved in LDS by the whole block: after it,
+// row k of local tile t (marked) has x = ld[r] lr[r], r = 2 tpos[t] + k.
+// Parallel cyclic reduction (lr holds 1 / lb); up to 64 rows on one
+// wavefront, up to 128 with one elimination level before that.
+template <int NT>
+__device__ void level1_solve_lds(const K1D& P, int t_lo, int ntc, L1Smem<NT>& S) {
+  // the channel's level-1 rows and tile counts in one round of loads
+  for (int g = threadIdx.x; g < 2 * ntc; g += NT) {
+    S.rdg[g] = P.dg1[2 * t_lo + g];
+    S.rup[g] = P.up1[2 * t_lo + g];
+    S.rrh[g] = P.rh1[2 * t_lo + g];
+  }
+  for (int t = threadIdx.x; t < ntc; t += NT) S.rcnt[t] = P.tile_cnt[t_lo + t];
+  __syncthreads();
+  int base = 0;
+  for (int t0 = 0; t0 < ntc; t0 += NT) {
+    const int t = t0 + threadIdx.x;
+    const bool mt = t < ntc && S.rcnt[t] > 0;
+    const unsigned long long bal = __ballot(mt);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) S.wc[wv] = __popcll(bal);
+    __syncthreads();
+    int wb = 0, tot = 0;
+    for (int w = 0; w < NT / 64; w++) {
+      if (w < wv) wb += S.wc[w];
+      tot += S.wc[w];
+    }
+    const int r = base + wb + __popcll(bal & ((1ull << lane) - 1ull));
+    if (t < ntc) S.tpos[t] = mt ? r : -1;
+    if (mt) S.tlist[r] = t;
+    base += tot;
+    __syncthreads();
+  }
+  const int n1 = 2 * base;
+  // coupling of compact row j to row j + 1
+  auto up_c = [&](int j) {
+    const int t = S.tlist[j >> 1];
+    if ((j & 1) == 0) return S.rup[2 * t];
+    return (j + 1 < n1 && S.tlist[(j >> 1) + 1] == t + 1) ? S.rup[2 * t + 1] : 0.0;
+  };
+  if (n1 <= 64) {
+    // one wavefront solves it in registers; the others wait
+    if (threadIdx.x < 64) {
+      const int j = threadIdx.x;
+      double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+      if (j < n1) {
+        const int g = 2 * S.tlist[j >> 1] + (j & 1);
+        a = j > 0 ? up_c(j - 1) : 0.0;
+        b = S.rdg[g];
+        c = up_c(j);
+        d = S.rrh[g];
+      }
+      S.ld[j] = wave_pcr(a, b, c, d, n1);
+      S.lr[j] = 1.0;
+    }
+    __syncthreads();
+  } else if (n1 <= 128) {
+    // two rows per lane (2l, 2l + 1): one cyclic-reduction level
+    // eliminates the odd rows, one wavefront solves the even rows as
+    // above, and each odd row follows from its two even neighbours
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x, j0 = 2 * l, j1 = j0 + 1;
+      double a0 = 0.0, b0 = 1.0, c0 = 0.0, d0 = 0.0;
+      double a1 = 0.0, b1 = 1.0, c1 = 0.0, d1 = 0.0;
+      if (j0 < n1) {
+        const int g = 2 * S.tlist[j0 >> 1];
+        a0 = j0 > 0 ? up_c(j0 - 1) : 0.0;
+        b0 = S.rdg[g];
+        c0 = up_c(j0);
+        d0 = S.rrh[g];
+      }
+      if (j1 < n1) {
+        const int g = 2 * S.tlist[j1 >> 1] + 1;
+        a1 = up_c(j0);
+        b1 = S.rdg[g];
+        c1 = up_c(j1);
+        d1 = S.rrh[g];
+      }
+      const double am = __shfl_up(a1, 1), bm = __shfl_up(b1, 1), cm = __shfl_up(c1, 1),
+                   dm = __shfl_up(d1, 1);  // row 2l - 1
+      double na = 0.0, nb = b0, nd = d0;
+      if (l > 0) {
+        const double k1 = a0 * rcp64(bm);
+        na = -am * k1;
+        nb -= cm * k1;
+        nd -= dm * k1;
+      }
+      const double r1 = rcp64(b1), k2 = c0 * r1;
+      const double nc = -c1 * k2;
+      nb -= a1 * k2;
+      nd -= d1 * k2;
+      const double xe = wave_pcr(na, nb, nc, nd, (n1 + 1) >> 1);
+      const double xn = __shfl_down(xe, 1);  // x of row 2l + 2
+      S.ld[j0] = xe;
+      S.ld[j1] = (d1 - a1 * xe - (l < 63 ? c1 * xn : 0.0)) * r1;
+      S.lr[j0] = 1.0;
+      S.lr[j1] = 1.0;
+    }
+    __syncthreads();
+  } else {
+    for (int j = threadIdx.x; j < L1MAX; j += NT) {
+      if (j < n1) {
+        const int g = 2 * S.tlist[j >> 1] + (j & 1);
+        S.la[j] = j > 0 ? up_c(j - 1) : 0.0;
+        S.lb[j] = S.rdg[g];
+        S.lc[j] = up_c(j);
+        S.ld[j] = S.rrh[g];
+      } else {
+        S.la[j] = 0.0;
+        S.lb[j] = 1.0;
+        S.lc[j] = 0.0;
+        S.ld[j] = 0.0;
+      }
+      S.lr[j] = rcp64(S.lb[j]);
+    }
+    __syncthreads();
+    for (int s = 1; s < n1; s <<= 1) {
+      double na[(L1MAX / NT)], nb[(L1MAX / NT)], nc[(L1MAX / NT)], nd[(L1MAX / NT)];
+#pragma unroll
+      for (int r = 0; r < (L1MAX / NT); r++) {
+        const int i = threadIdx.x + NT * r;
+        if (i >= n1) continue;
+        const int im = i - s, ip = i + s;
+        double ai = 0.0, bi = S.lb[i], ci = 0.0, di = S.ld[i];
+        if (im >= 0) {
+          const double k1 = S.la[i] * S.lr[im];
+          ai = -S.la[im] * k1;
+          bi -= S.lc[im] * k1;
+          di -= S.ld[im] * k1;
+        }
+        if (ip < L1MAX) {
+          const double k2 = S.lc[i] * S.lr[ip];
+          ci = -S.lc[ip] * k2;
+          bi -= S.la[ip] * k2;
+          di -= S.ld[ip] * k2;
+        }
+        na[r] = ai;
+        nb[r] = bi;
+        nc[r] = ci;
+        nd[r] = di;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < (L1MAX / NT); r++) {
+        const int i = threadIdx.x + NT * r;
+        if (i >= n1) continue;
+        S.la[i] = na[r];
+        S.lb[i] = nb[r];
+        S.lc[i] = nc[r];
+        S.ld[i] = nd[r];
+        S.lr[i] = rcp64(nb[r]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Projection of the marked cells (a6) from the level-1 solution -- solved
-// here, redundantly by every tile that needs it, when it has at most L1MAX
-// rows (L1LOCAL), else read from P.x1 -- and the speed of their new state.
+// here, redundantly by every tile that needs it, when the whole level-1
+// system has at most L1MAX rows (L1LOCAL; each tile solves its channel's
+// part: the channels' systems are decoupled), else read from P.x1 -- and the
+// speed of their new state.
 // par: parity of the step within the run (the time, step counter, marked
 // count and speed buffers alternate with it).
 template <int T, int NT, bool L1LOCAL>
 __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict__ mask,
                                                 double* hun, double* hwn, double* p,
                                                 int par) {
-  constexpr int L1 = L1LOCAL ? L1MAX : 1, RPT = L1LOCAL ? L1MAX / NT : 1;
   __shared__ double xs[T + 2];
-  __shared__ double la[L1], lb[L1], lc[L1], ld[L1], lr[L1];
-  __shared__ double rdg[L1], rup[L1], rrh[L1];  // level-1 rows as stored (2 per tile)
-  __shared__ int rcnt[(L1 + 1) / 2];
-  __shared__ int tpos[(L1 + 1) / 2], tlist[(L1 + 1) / 2];  // tile <-> compact level-1 tile
-  __shared__ int wc[NT / 64];
+  // the level-1 solve's LDS only where this kernel solves it
+  __shared__ typename std::conditional<L1LOCAL, L1Smem<NT>, char>::type l1s;
+  L1Smem<NT>* L1S = nullptr;
+  if constexpr (L1LOCAL) L1S = &l1s;
   const int4 tl = P.tiles[blockIdx.x];
   const int n = tl.w, start = tl.y, end = min(start + P.tile, n), len = end - start;
   const int64_t off = tl.z;
@@ -2025,166 +2195,17 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
       for (int v = 0; v < ZW_N; v++) zr[q][v] = z[v * zs];
     }
     const bool nb_l = start > 0 && mask[m0], nb_r = end < n && mask[m0 + len + 1];
+    // the channel's tiles [t_lo, t_lo + ntc): local tile t <-> tile t_lo + t
+    const int t_lo = L1LOCAL ? P.first_tile[tl.x] : 0;
+    const int ntc = L1LOCAL ? (tl.x + 1 < P.nch ? P.first_tile[tl.x + 1] : P.ntiles) - t_lo : 0;
     // level-1 solution of row j (= 2 tile + 0 first / 1 last)
     auto x1 = [&](int j) {
       if (!L1LOCAL) return P.x1[j];
-      const int r = 2 * tpos[j >> 1] + (j & 1);
-      return ld[r] * lr[r];
+      const int jl = j - 2 * t_lo;
+      const int r = 2 * L1S->tpos[jl >> 1] + (jl & 1);
+      return L1S->ld[r] * L1S->lr[r];
     };
-    if (L1LOCAL) {
-      // Level-1 system restricted to the marked tiles (an unmarked tile's two
-      // identity rows are decoupled from everything), in tile order; solved
-      // by parallel cyclic reduction (lr holds 1 / lb).
-      // all level-1 rows and tile counts in one round of loads
-      for (int g = threadIdx.x; g < 2 * P.ntiles; g += NT) {
-        rdg[g] = P.dg1[g];
-        rup[g] = P.up1[g];
-        rrh[g] = P.rh1[g];
-      }
-      for (int t = threadIdx.x; t < P.ntiles; t += NT) rcnt[t] = P.tile_cnt[t];
-      __syncthreads();
-      int base = 0;
-      for (int t0 = 0; t0 < P.ntiles; t0 += NT) {
-        const int t = t0 + threadIdx.x;
-        const bool mt = t < P.ntiles && rcnt[t] > 0;
-        const unsigned long long bal = __ballot(mt);
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        if (lane == 0) wc[wv] = __popcll(bal);
-        __syncthreads();
-        int wb = 0, tot = 0;
-        for (int w = 0; w < NT / 64; w++) {
-          if (w < wv) wb += wc[w];
-          tot += wc[w];
-        }
-        const int r = base + wb + __popcll(bal & ((1ull << lane) - 1ull));
-        if (t < P.ntiles) tpos[t] = mt ? r : -1;
-        if (mt) tlist[r] = t;
-        base += tot;
-        __syncthreads();
-      }
-      const int n1 = 2 * base;
-      // coupling of compact row j to row j + 1
-      auto up_c = [&](int j) {
-        const int t = tlist[j >> 1];
-        if ((j & 1) == 0) return rup[2 * t];
-        return (j + 1 < n1 && tlist[(j >> 1) + 1] == t + 1) ? rup[2 * t + 1] : 0.0;
-      };
-      if (n1 <= 64) {
-        // one wavefront solves it in registers; the others wait
-        if (threadIdx.x < 64) {
-          const int j = threadIdx.x;
-          double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
-          if (j < n1) {
-            const int g = 2 * tlist[j >> 1] + (j & 1);
-            a = j > 0 ? up_c(j - 1) : 0.0;
-            b = rdg[g];
-            c = up_c(j);
-            d = rrh[g];
-          }
-          ld[j] = wave_pcr(a, b, c, d, n1);
-          lr[j] = 1.0;
-        }
-        __syncthreads();
-      } else if (n1 <= 128) {
-        // two rows per lane (2l, 2l + 1): one cyclic-reduction level
-        // eliminates the odd rows, one wavefront solves the even rows as
-        // above, and each odd row follows from its two even neighbours
-        if (threadIdx.x < 64) {
-          const int l = threadIdx.x, j0 = 2 * l, j1 = j0 + 1;
-          double a0 = 0.0, b0 = 1.0, c0 = 0.0, d0 = 0.0;
-          double a1 = 0.0, b1 = 1.0, c1 = 0.0, d1 = 0.0;
-          if (j0 < n1) {
-            const int g = 2 * tlist[j0 >> 1];
-            a0 = j0 > 0 ? up_c(j0 - 1) : 0.0;
-            b0 = rdg[g];
-            c0 = up_c(j0);
-            d0 = rrh[g];
-          }
-          if (j1 < n1) {
-            const int g = 2 * tlist[j1 >> 1] + 1;
-            a1 = up_c(j0);
-            b1 = rdg[g];
-            c1 = up_c(j1);
-            d1 = rrh[g];
-          }
-          const double am = __shfl_up(a1, 1), bm = __shfl_up(b1, 1), cm = __shfl_up(c1, 1),
-                       dm = __shfl_up(d1, 1);  // row 2l - 1
-          double na = 0.0, nb = b0, nd = d0;
-          if (l > 0) {
-            const double k1 = a0 * rcp64(bm);
-            na = -am * k1;
-            nb -= cm * k1;
-            nd -= dm * k1;
-          }
-          const double r1 = rcp64(b1), k2 = c0 * r1;
-          const double nc = -c1 * k2;
-          nb -= a1 * k2;
-          nd -= d1 * k2;
-          const double xe = wave_pcr(na, nb, nc, nd, (n1 + 1) >> 1);
-          const double xn = __shfl_down(xe, 1);  // x of row 2l + 2
-          ld[j0] = xe;
-          ld[j1] = (d1 - a1 * xe - (l < 63 ? c1 * xn : 0.0)) * r1;
-          lr[j0] = 1.0;
-          lr[j1] = 1.0;
-        }
-        __syncthreads();
-      } else {
-        for (int j = threadIdx.x; j < L1; j += NT) {
-          if (j < n1) {
-            const int g = 2 * tlist[j >> 1] + (j & 1);
-            la[j] = j > 0 ? up_c(j - 1) : 0.0;
-            lb[j] = rdg[g];
-            lc[j] = up_c(j);
-            ld[j] = rrh[g];
-          } else {
-            la[j] = 0.0;
-            lb[j] = 1.0;
-            lc[j] = 0.0;
-            ld[j] = 0.0;
-          }
-          lr[j] = rcp64(lb[j]);
-        }
-        __syncthreads();
-        for (int s = 1; s < n1; s <<= 1) {
-          double na[RPT], nb[RPT], nc[RPT], nd[RPT];
-#pragma unroll
-          for (int r = 0; r < RPT; r++) {
-            const int i = threadIdx.x + NT * r;
-            if (i >= n1) continue;
-            const int im = i - s, ip = i + s;
-            double ai = 0.0, bi = lb[i], ci = 0.0, di = ld[i];
-            if (im >= 0) {
-              const double k1 = la[i] * lr[im];
-              ai = -la[im] * k1;
-              bi -= lc[im] * k1;
-              di -= ld[im] * k1;
-            }
-            if (ip < L1) {
-              const double k2 = lc[i] * lr[ip];
-              ci = -lc[ip] * k2;
-              bi -= la[ip] * k2;
-              di -= ld[ip] * k2;
-            }
-            na[r] = ai;
-            nb[r] = bi;
-            nc[r] = ci;
-            nd[r] = di;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int r = 0; r < RPT; r++) {
-            const int i = threadIdx.x + NT * r;
-            if (i >= n1) continue;
-            la[i] = na[r];
-            lb[i] = nb[r];
-            lc[i] = nc[r];
-            ld[i] = nd[r];
-            lr[i] = rcp64(nb[r]);
-          }
-          __syncthreads();
-        }
-      }
-    }
+    if (L1LOCAL) level1_solve_lds<NT>(P, t_lo, ntc, *L1S);
     const double xF = x1(2 * blockIdx.x), xL = x1(2 * blockIdx.x + 1);
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
@@ -2217,6 +2238,23 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
     }
   }
   flush_speed<NT>(P, tl.x, par, smax, flags);
+}
+
+// The level-1 systems of the channels when the whole system is too large
+// for the projection kernel but each channel's part fits (at most L1MAX
+// rows), one block per channel: the marked tiles' solution into P.x1 (an
+// unmarked tile's rows are identity rows with a zero right-hand side: 0)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_level1_chan(K1D P) {
+  __shared__ L1Smem<NT> S;
+  const int ch = blockIdx.x;
+  const int t_lo = P.first_tile[ch];
+  const int ntc = (ch + 1 < P.nch ? P.first_tile[ch + 1] : P.ntiles) - t_lo;
+  level1_solve_lds<NT>(P, t_lo, ntc, S);
+  for (int g = threadIdx.x; g < 2 * ntc; g += NT) {
+    const int r = S.tpos[g >> 1], k = 2 * r + (g & 1);
+    P.x1[2 * t_lo + g] = r >= 0 ? S.ld[k] * S.lr[k] : 0.0;
+  }
 }
 
 // the two-kernel step's table: per channel (one wavefront each), dt from the
@@ -2460,7 +2498,7 @@ void launch_step1d(const K1D& P, const double* h, const double* hu, const double
 template <int T, int NT>
 static void launch_apply_t(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
                            int par, hipStream_t s) {
-  if (2 * P.ntiles <= L1MAX)
+  if (level1_local(P))
     hipLaunchKernelGGL((k_apply1d<T, NT, true>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun, hwn,
                        p, par);
   else
@@ -2480,6 +2518,10 @@ void launch_run_end(const K1D& P, int last_par, hipStream_t s) {
   hipLaunchKernelGGL(k_run_end, dim3(1), dim3(256), 0, s, P, last_par);
 }
 bool level1_local(const K1D& P) { return 2 * P.ntiles <= L1MAX; }
+bool level1_per_channel(const K1D& P) { return 2 * P.max_ch_tiles <= L1MAX; }
+void launch_level1_chan(const K1D& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_level1_chan<256>, dim3(P.nch), dim3(256), 0, s, P);
+}
 int fused_max_enlarge() { return EMAXF; }
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
                            hipStream_t s) {

@@ -337,7 +337,12 @@ void enqueue_fused1d(swe_nh_ctx* c, hipStream_t s, const double* h, const double
   uint8_t* M = mask ? mask : c->mask_ws;
   launch_step1d(P, h, hu, hw, hn, hun, hwn, M, p, par, s);
   if (P.onepass) return;  // the step kernel also solved and projected
-  if (!level1_local(P)) launch_tri_solve(c->T1, c->n1, nullptr, s);
+  if (!level1_local(P)) {
+    if (level1_per_channel(P))
+      launch_level1_chan(P, s);
+    else
+      launch_tri_solve(c->T1, c->n1, nullptr, s);
+  }
   launch_apply1d(P, M, hun, hwn, p, par, s);
 }
 
@@ -498,6 +503,11 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   P.tile = tile_of(cfg);
   P.cap = cap_of(cfg);
   P.nch = c->nch;
+  P.max_ch_tiles = 0;
+  for (int b = 0; b < (int)first.size(); b++) {
+    const int end = b + 1 < (int)first.size() ? first[b + 1] : P.ntiles;
+    P.max_ch_tiles = std::max(P.max_ch_tiles, end - first[b]);
+  }
   P.nslot = speed_slots(cfg);
   P.fused = fused_step(cfg) ? 1 : 0;
   P.onepass = 0;
@@ -896,6 +906,10 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
     *avg_us_host = 0.0;  // the one-kernel step has no separate level-1 solve or projection
     return SWE_NH_OK;
   }
+  if (c->cfg.dim == 1 && c->k1.fused && stage == 1 && level1_local(c->k1)) {
+    *avg_us_host = 0.0;  // the projection kernel solves the level-1 system itself
+    return SWE_NH_OK;
+  }
   // one launch of the stage, enqueued on s
   auto one = [&](hipStream_t s) {
     if (c->cfg.dim == 2) {
@@ -914,7 +928,12 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
       Pt.keep_speed = 1;  // replays of the step kernel must all read the same dt
       switch (stage) {
         case 0: launch_step1d(Pt, h, hu, hw, s0, s1, s2, M, s3, 0, s); break;
-        case 1: launch_tri_solve(c->T1, c->n1, nullptr, s); break;
+        case 1:
+          if (level1_per_channel(P))
+            launch_level1_chan(P, s);
+          else
+            launch_tri_solve(c->T1, c->n1, nullptr, s);
+          break;
         case 2: launch_apply1d(P, M, s1, s2, s3, 0, s); break;
         default: launch_pred1d(P, h, hu, hw, c->ht, c->mt, c->kt, P.t, P.dt, 0, s);
       }

@@ -49,10 +49,11 @@ struct K1D {
   // tile-fused step (FP64): smax is then [2][batch], selected by step parity
   int fused;
   int nch;
+  int max_ch_tiles;  // most tiles of one channel
   int* n_acc;              // [2] marked cells counted during a step, by step parity
   double* zw;              // [ZW_N][ntiles * cap] per marked row, tile-padded
   double *dg1, *up1, *rh1; // level-1 rows: first and last marked row of each tile
-  const double* x1;        // level-1 solution
+  double* x1;              // level-1 solution
   // one-kernel step (onepass, at most ONEPASS_TILES tiles): the tiles publish
   // their marked counts and level-1 rows as tagged words, each marked tile
   // solves the level-1 system itself (beyond 64 marked tiles block 0 solves
@@ -126,6 +127,9 @@ void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn,
                     int par, hipStream_t s);
 void launch_run_end(const K1D& P, int last_par, hipStream_t s);
 bool level1_local(const K1D& P);  // the projection kernel solves the level-1 system itself
+// else one block per channel solves it when every channel's part is small enough
+bool level1_per_channel(const K1D& P);
+void launch_level1_chan(const K1D& P, hipStream_t s);
 int onepass_resident(const K1D& P);  // blocks of the one-kernel step that fit at once (0: error)
 int fused_max_enlarge();
 void launch_speed_prologue(const K1D& P, const double* h, const double* hu, const double* hw,
