@@ -1667,7 +1667,10 @@ __global__ void __launch_bounds__(NT, 5) k_step1d(K1D P, const double* __restric
   const int F = 2 * blockIdx.x, L = F + 1;
   if (threadIdx.x == 0) {
     P.tile_cnt[blockIdx.x] = m;
-    if (m) atomicAdd(&P.n_acc[par], m);
+    if (m) {
+      atomicAdd(&P.n_acc[par], m);
+      if (!ONE) P.mlist[atomicAdd(P.mcount, 1)] = blockIdx.x;  // for the projection
+    }
   }
   // one-kernel step: the tag of this step's words; the level-1 scratch (the
   // marked tiles' list, staged rows) lives in the LDS union once the block's
@@ -2148,30 +2151,16 @@ __device__ void level1_solve_lds(const K1D& P, int t_lo, int ntc, L1Smem<NT>& S)
   }
 }
 
-// Projection of the marked cells (a6) from the level-1 solution -- solved
-// here, redundantly by every tile that needs it, when the whole level-1
-// system has at most L1MAX rows (L1LOCAL; each tile solves its channel's
-// part: the channels' systems are decoupled), else read from P.x1 -- and the
-// speed of their new state.
-// par: parity of the step within the run (the time, step counter, marked
-// count and speed buffers alternate with it).
+// the projection of tile b (nothing for a tile without marked cells)
 template <int T, int NT, bool L1LOCAL>
-__global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict__ mask,
-                                                double* hun, double* hwn, double* p,
-                                                int par) {
-  __shared__ double xs[T + 2];
-  // the level-1 solve's LDS only where this kernel solves it
-  __shared__ typename std::conditional<L1LOCAL, L1Smem<NT>, char>::type l1s;
-  L1Smem<NT>* L1S = nullptr;
-  if constexpr (L1LOCAL) L1S = &l1s;
-  const int4 tl = P.tiles[blockIdx.x];
+__device__ __forceinline__ void apply_tile(const K1D& P, int b, const uint8_t* __restrict__ mask,
+                                           double* hun, double* hwn, double* p, int par,
+                                           double* xs, L1Smem<NT>* L1S) {
+  const int4 tl = P.tiles[b];
   const int n = tl.w, start = tl.y, end = min(start + P.tile, n), len = end - start;
   const int64_t off = tl.z;
   const double dt = P.dt[tl.x];
-  // the speed buffer this step read collects the speed of the step after next
-  if (start == 0 && threadIdx.x < P.nslot)
-    P.smax[speed_at(par * P.nch + tl.x, threadIdx.x, P.nslot)] = 0ull;
-  const int m = P.tile_cnt[blockIdx.x];
+  const int m = P.tile_cnt[b];
   if (m == 0) return;  // no marked cell: the step kernel already took this tile's speed
   double smax = 0.0;
   int flags = 0;
@@ -2182,7 +2171,7 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
     bool on[T / NT];
     const int64_t m0 = off + start - 1;  // mask[m0 + k]: tile-local cell k
     const int64_t zs = (int64_t)P.ntiles * T;
-    const int64_t pb = (int64_t)blockIdx.x * T;
+    const int64_t pb = (int64_t)b * T;
     double zr[T / NT][ZW_N];
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
@@ -2206,7 +2195,7 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
       return L1S->ld[r] * L1S->lr[r];
     };
     if (L1LOCAL) level1_solve_lds<NT>(P, t_lo, ntc, *L1S);
-    const double xF = x1(2 * blockIdx.x), xL = x1(2 * blockIdx.x + 1);
+    const double xF = x1(2 * b), xL = x1(2 * b + 1);
 #pragma unroll
     for (int q = 0; q < T / NT; q++) {
       const int k = 1 + threadIdx.x + NT * q;
@@ -2214,8 +2203,8 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
       xs[k] = on[q] ? zr[q][ZW_Z] + zr[q][ZW_U] * xF + zr[q][ZW_V] * xL : 0.0;
     }
     if (threadIdx.x == 0) {
-      xs[0] = nb_l ? x1(2 * blockIdx.x - 1) : 0.0;
-      xs[len + 1] = nb_r ? x1(2 * blockIdx.x + 2) : 0.0;
+      xs[0] = nb_l ? x1(2 * b - 1) : 0.0;
+      xs[len + 1] = nb_r ? x1(2 * b + 2) : 0.0;
     }
     __syncthreads();
     const double rdt4 = P.rho / (4.0 * dt), dtr = dt / P.rho;
@@ -2240,6 +2229,35 @@ __global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict
   flush_speed<NT>(P, tl.x, par, smax, flags);
 }
 
+// Projection of the marked cells (a6) from the level-1 solution -- solved
+// here, redundantly by every tile that needs it, when the whole level-1
+// system has at most L1MAX rows (L1LOCAL: one block per tile, each solving
+// its channel's part; the channels' systems are decoupled), else read from
+// P.x1 (a grid of at most APPLY_GRID blocks walks the list of marked tiles
+// the step kernel appended: on the ensemble most tiles have no marked cell,
+// and a block per tile spent some 30 us launching blocks that exit at once)
+// -- and the speed of their new state.  par: parity of the step within the
+// run (the time, step counter, marked count and speed buffers alternate with
+// it).
+constexpr int APPLY_GRID = 2048;
+template <int T, int NT, bool L1LOCAL>
+__global__ void __launch_bounds__(NT) k_apply1d(K1D P, const uint8_t* __restrict__ mask,
+                                                double* hun, double* hwn, double* p,
+                                                int par) {
+  __shared__ double xs[T + 2];
+  // the level-1 solve's LDS only where this kernel solves it
+  __shared__ typename std::conditional<L1LOCAL, L1Smem<NT>, char>::type l1s;
+  if constexpr (L1LOCAL) {
+    apply_tile<T, NT, true>(P, blockIdx.x, mask, hun, hwn, p, par, xs, &l1s);
+  } else {
+    const int nm = *P.mcount;
+    for (int k = blockIdx.x; k < nm; k += gridDim.x) {
+      __syncthreads();  // the previous tile's last reads of xs
+      apply_tile<T, NT, false>(P, P.mlist[k], mask, hun, hwn, p, par, xs, nullptr);
+    }
+  }
+}
+
 // The level-1 systems of the channels when the whole system is too large
 // for the projection kernel but each channel's part fits (at most L1MAX
 // rows), one block per channel: the marked tiles' solution into P.x1 (an
@@ -2259,13 +2277,18 @@ __global__ void __launch_bounds__(NT) k_level1_chan(K1D P) {
 
 // the two-kernel step's table: per channel (one wavefront each), dt from the
 // speed slots of buffer `par` (their maximum, read by one lane each as
-// read_speed does) and the body's motion at both ends of the step (lanes 0
-// and 1); the step's dt and the next step's start time go to P.dt and
-// P.t[par ^ 1] here, so the step kernel's blocks only read them
+// read_speed does, then cleared) and the body's motion at both ends of the
+// step (lanes 0 and 1); the step's dt and the next step's start time go to
+// P.dt and P.t[par ^ 1] here, so the step kernel's blocks only read them
 __global__ void __launch_bounds__(256) k_chan_step(K1D P, int par) {
   const int ch = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *P.mcount = 0;  // the step's marked-tile list
   if (ch >= P.nch) return;
   const double dt = (P.cfl > 0.0) ? P.cfl * P.dx / read_speed(P, par, ch) : P.dt_fixed;
+  // the slots just read collect the speed of the step after next (stage
+  // timing replays the step and keeps them)
+  if (!P.keep_speed && lane < P.nslot)
+    P.smax[speed_at(par * P.nch + ch, lane, P.nslot)] = 0ull;
   const double t0 = P.t[par * P.nch + ch];
   if (lane < 2) {
     const Motion M = body_motion(P.ch[ch], lane == 0 ? t0 : t0 + dt);
@@ -2502,8 +2525,8 @@ static void launch_apply_t(const K1D& P, const uint8_t* mask, double* hun, doubl
     hipLaunchKernelGGL((k_apply1d<T, NT, true>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun, hwn,
                        p, par);
   else
-    hipLaunchKernelGGL((k_apply1d<T, NT, false>), dim3(P.ntiles), dim3(NT), 0, s, P, mask, hun,
-                       hwn, p, par);
+    hipLaunchKernelGGL((k_apply1d<T, NT, false>), dim3(std::min(P.ntiles, APPLY_GRID)), dim3(NT),
+                       0, s, P, mask, hun, hwn, p, par);
 }
 void launch_apply1d(const K1D& P, const uint8_t* mask, double* hun, double* hwn, double* p,
                     int par, hipStream_t s) {

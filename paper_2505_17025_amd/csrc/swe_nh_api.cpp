@@ -272,6 +272,8 @@ size_t plan(const swe_nh_config* c, char* base, swe_nh_ctx* ctx) {
       P.tw = cv.take<unsigned long long>(17 * (size_t)ntiles);
       P.tag1 = cv.take<unsigned>(1);
       P.ctab = cv.take<double>(CTAB_N * (size_t)nch);
+      P.mlist = cv.take<int>(ntiles);
+      P.mcount = cv.take<int>(1);
       P.l1s = cv.take<double>(4 * (size_t)ntiles);
       P.sweeps = cv.take<int>(2);
       P.berr = cv.take<unsigned long long>(2);

@@ -81,6 +81,10 @@ struct K1D {
   // two-kernel step: per channel, the step's dt and the body's motion at t^n
   // and t^{n+1} ([batch][CTAB_N]), written by k_chan_step before the step kernel
   double* ctab;
+  // two-kernel step: the marked tiles of the step (appended by the step
+  // kernel in any order; mcount reset by k_chan_step), walked by the projection
+  int* mlist;
+  int* mcount;
   double* l1s;
 };
 
