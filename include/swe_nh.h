@@ -191,6 +191,18 @@ int swe_nh_step(swe_nh_ctx* ctx, double* h, double* hu, double* hv, double* hw, 
 /* Synchronise the stream and read the statistics of the last step. */
 int swe_nh_sync_stats(swe_nh_ctx* ctx, swe_nh_stats* out);
 
+/* One full step (Secs. 3.1, 3.2, 5.1, 5.2: predictor, criterion and
+ * enlargement, elliptic solve, projection) with the model time in device
+ * memory: t_dev (device FP64, [batch] in 1D, [1] in 2D) holds t^n on entry and
+ * t^{n+1} on return; the context's own time is set from it first, so calls
+ * may interleave with swe_nh_step.  h, hu, hv, hw and p as for swe_nh_step
+ * (no mask output).  stats (host memory, may be NULL): when given, the call
+ * synchronises the stream and fills it as swe_nh_sync_stats does; when NULL
+ * the call returns without waiting.  Errors: SWE_NH_EINVAL for null
+ * arguments, the status codes of the step through stats. */
+int swe_nh_step_t(swe_nh_ctx* ctx, double* h, double* hu, double* hv, double* hw, double* p,
+                  double* t_dev, swe_nh_stats* stats);
+
 /* Stage entry points (same kernels as swe_nh_step), for callers that drive
  * the stages themselves and for parity tests. */
 

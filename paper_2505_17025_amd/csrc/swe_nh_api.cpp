@@ -715,6 +715,17 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
   return SWE_NH_OK;
 }
 
+int swe_nh_step_t(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, double* p,
+                  double* t_dev, swe_nh_stats* stats) {
+  if (!c || !t_dev) return fail(c, SWE_NH_EINVAL, "bad arguments");
+  const size_t tb = sizeof(double) * c->nch;
+  HIPCHK(c, hipMemcpyAsync(c->k1.t, t_dev, tb, hipMemcpyDeviceToDevice, c->stream));
+  int rc = swe_nh_step(c, h, hu, hv, hw, p, nullptr, 1);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(t_dev, c->k1.t, tb, hipMemcpyDeviceToDevice, c->stream));
+  return stats ? swe_nh_sync_stats(c, stats) : SWE_NH_OK;
+}
+
 int swe_nh_sync_stats(swe_nh_ctx* c, swe_nh_stats* out) {
   if (!c || !out) return SWE_NH_EINVAL;
   int st = 0, na = 0, it = 0;

@@ -73,6 +73,7 @@ def _load():
     lib.swe_nh_get_time.argtypes = [vp, C.POINTER(dbl)]
     lib.swe_nh_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
     lib.swe_nh_sync_stats.argtypes = [vp, C.POINTER(swe_nh_stats)]
+    lib.swe_nh_step_t.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(swe_nh_stats)]
     lib.swe_nh_predict.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp, vp, vp,
                                    vp]
     lib.swe_nh_mask.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dbl), i32, vp, C.POINTER(i64)]
@@ -107,7 +108,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_last_error",
-            "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step", "swe_nh_sync_stats",
+            "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step", "swe_nh_step_t",
+            "swe_nh_sync_stats",
             "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure", "swe_nh_correct",
             "swe_nh_time_stage", "swe_nh_cnn_param_count", "swe_nh_cnn_workspace_bytes",
             "swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
@@ -212,6 +214,15 @@ class Context:
     def step(self, h, hu, hv, hw, p, mask=None, nsteps=1):
         self._check(LIB.swe_nh_step(self.ctx, _ptr(h), _ptr(hu), _ptr(hv), _ptr(hw), _ptr(p),
                                     _ptr(mask), int(nsteps)), "swe_nh_step")
+
+    def step_t(self, h, hu, hv, hw, p, t_dev, stats=True):
+        """swe_nh_step_t: one step with the time in the device tensor t_dev;
+        returns the statistics (synchronising) or None"""
+        st = swe_nh_stats() if stats else None
+        self._check(LIB.swe_nh_step_t(self.ctx, _ptr(h), _ptr(hu), _ptr(hv), _ptr(hw), _ptr(p),
+                                      _ptr(t_dev), C.byref(st) if st is not None else None),
+                    "swe_nh_step_t")
+        return {k: getattr(st, k) for k, _ in swe_nh_stats._fields_} if st is not None else None
 
     def sync_stats(self):
         st = swe_nh_stats()

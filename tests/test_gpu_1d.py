@@ -337,6 +337,28 @@ def test_batched_ensemble_parity(B):
     assert st["n_active"] == total
 
 
+def test_step_with_device_time(B, step_mode):
+    """swe_nh_step_t (the time in device memory, statistics on request) gives
+    the bits of swe_nh_step on an ensemble, and the time after the steps"""
+    ens = ens_small([300, 2047, 4000])
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, cfl=0.4)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 6, **kw)
+    ctx2 = B.context_1d(ens, **kw)
+    pk = ens.packed
+    h2, hu2, hw2 = dt(pk("h")), dt(pk("hu")), dt(pk("hw"))
+    p2 = torch.zeros_like(h2)
+    t_dev = torch.tensor([c.t0 for c in ens.channels], dtype=torch.float64, device=DEV)
+    for k in range(6):
+        st2 = ctx2.step_t(h2, hu2, None, hw2, p2, t_dev, stats=(k % 2 == 0))
+        assert st2 is None or st2["status"] == 0
+    st2 = ctx2.sync_stats()
+    assert st2["status"] == 0 and st2["n_active"] == st["n_active"]
+    for x, y in ((h, h2), (hu, hu2), (hw, hw2), (p, p2)):
+        assert torch.equal(x, y)
+    assert np.array_equal(t_dev.cpu().numpy(), np.asarray(ctx.get_time()))
+    assert np.all(t_dev.cpu().numpy() > np.array([c.t0 for c in ens.channels]))
+
+
 def test_deterministic_and_graph_replay(B, step_mode):
     case = S.random_case_1d(5000, seed=2)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=2e-3, cfl=0.4)

@@ -204,6 +204,24 @@ def test_full_size_shelf_properties(B):
     assert abs(mass0 - c.h.sum()) <= 1e-12 * c.h.sum()
 
 
+def test_step_with_device_time_2d(B):
+    """swe_nh_step_t in 2D: the bits of swe_nh_step and the time after it"""
+    c = case(nx=66, ny=50, seed=11)
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=4e-3, enlarge=1, cfl=0.4, precision=0, tol=1e-12,
+              max_iter=5000, warm=1)
+    ctx, st, h, hu, hv, hw, p, m = run2d(B, c, 3, **kw)
+    ctx2 = B.context_2d(c, **kw)
+    h2, hu2, hv2, hw2 = dt_(c.h), dt_(c.hu), dt_(c.hv), dt_(c.hw)
+    p2 = torch.zeros_like(h2)
+    t_dev = torch.tensor([c.t0], dtype=torch.float64, device=DEV)
+    for _ in range(3):
+        st2 = ctx2.step_t(h2, hu2, hv2, hw2, p2, t_dev)
+        assert st2["status"] == 0
+    for x, y in ((h, h2), (hu, hu2), (hv, hv2), (hw, hw2), (p, p2)):
+        assert torch.equal(x, y)
+    assert float(t_dev.item()) == float(ctx.get_time()[0]) > c.t0
+
+
 def test_deterministic_2d(B):
     c = case(nx=80, ny=64, seed=2)
     kw = dict(crit=S.CRIT_ETA_D, k_nh=4e-3, cfl=0.4, precision=1, tol=1e-10, max_iter=5000)
