@@ -337,6 +337,34 @@ def test_batched_ensemble_parity(B):
     assert st["n_active"] == total
 
 
+@pytest.mark.parametrize("crit", [S.CRIT_GLOBAL, S.CRIT_ETA_D])
+@pytest.mark.parametrize("longest", [512, 513])
+def test_level1_per_channel_limit(B, crit, longest):
+    """an ensemble whose grid has more than 512 tiles (tiles of 37 cells) with
+    its longest channel at 512 tiles (the level-1 system solved one block per
+    channel, up to 1024 rows when every tile is marked) or 513 (the packed
+    tridiagonal solver): the oracle's channels"""
+    lengths = [37 * longest, 37 * 40 + 5, 37 * 300 - 11, 600]
+    chans = [S.random_case_1d(n, seed=70 + j, amp=0.01, mom=0.02, vert=0.01)
+             for j, n in enumerate(lengths)]
+    ens = S.Ensemble(chans)
+    kw = dict(crit=crit, k_nh=2e-3, enlarge=1, cfl=0.45, tile1d=37, step1d_form=1)
+    ctx, st, h, hu, hw, p, mask = run_gpu(B, ens, 12, **kw)
+    assert st["status"] == 0
+    o = ens.offsets
+    total = 0
+    for j, c in enumerate(chans):
+        ref = O.Sim1D(c, phys_of(kw), cfl=0.45).step(12)
+        sl = slice(o[j], o[j + 1])
+        assert np.array_equal(mask[sl].cpu().numpy(), ref.mask)
+        for g, r in ((h[sl] - dt(c.ds), ref.h - c.ds), (hu[sl], ref.hu), (hw[sl], ref.hw)):
+            assert rel(g, r) <= 1e-10
+        if ref.last_active:
+            assert rel(p[sl], ref.p) <= 1e-10
+        total += ref.last_active
+    assert st["n_active"] == total > 0
+
+
 def test_step_with_device_time(B, step_mode):
     """swe_nh_step_t (the time in device memory, statistics on request) gives
     the bits of swe_nh_step on an ensemble, and the time after the steps"""
