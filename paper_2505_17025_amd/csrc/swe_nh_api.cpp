@@ -414,12 +414,12 @@ int capture_graph(swe_nh_ctx* c, F f, hipGraphExec_t* out) {
   hipError_t e1 = hipGetLastError();
   hipError_t e2 = hipStreamEndCapture(c->cap, &g);
   if (e1 != hipSuccess || e2 != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return fail(c, SWE_NH_EHIP,
                 std::string("capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   }
   hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e3 != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("instantiate: ") + hipGetErrorString(e3));
   return SWE_NH_OK;
 }
@@ -570,8 +570,7 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
   if (rc == SWE_NH_OK && cfg->dim == 2) rc = init2d(&c->cfg, &c->c2, c->k1, c->stream);
   if (rc != SWE_NH_OK) {
     (void)hipGetLastError();  // do not leave a failed call behind for the caller's next check
-    hipStreamDestroy(c->cap);
-    delete c;
+    swe_nh_destroy(c);
     return rc;
   }
   *out = c;
@@ -580,13 +579,11 @@ int swe_nh_init(const swe_nh_config* cfg, void* workspace, size_t bytes, void* s
 
 void swe_nh_destroy(swe_nh_ctx* c) {
   if (!c) return;
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->gexec2) hipGraphExecDestroy(c->gexec2);
-  if (c->gexecN) hipGraphExecDestroy(c->gexecN);
-  if (c->gexecT) hipGraphExecDestroy(c->gexecT);
-  if (c->tiles_ev) hipEventDestroy(c->tiles_ev);
-  if (c->tiles_host) hipHostFree(c->tiles_host);
-  if (c->cap) hipStreamDestroy(c->cap);
+  for (hipGraphExec_t g : {c->gexec, c->gexec2, c->gexecN, c->gexecT})
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->tiles_ev) (void)hipEventDestroy(c->tiles_ev);
+  if (c->tiles_host) (void)hipHostFree(c->tiles_host);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
 
@@ -635,7 +632,7 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
   if (!same) {
     for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN, &c->gexecT})
       if (*g) {
-        hipGraphExecDestroy(*g);
+        (void)hipGraphExecDestroy(*g);
         *g = nullptr;
       }
   }
@@ -672,7 +669,7 @@ int swe_nh_step(swe_nh_ctx* c, double* h, double* hu, double* hv, double* hw, do
     if (rc != SWE_NH_OK) {
       for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN, &c->gexecT})
         if (*g) {
-          hipGraphExecDestroy(*g);
+          (void)hipGraphExecDestroy(*g);
           *g = nullptr;
         }
       return rc;
@@ -904,7 +901,7 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* c, const float* params, const double* 
   if (rc) return rc;
   for (hipGraphExec_t* g : {&c->gexec, &c->gexec2, &c->gexecN, &c->gexecT})  // the step must pick up the network
     if (*g) {
-      hipGraphExecDestroy(*g);
+      (void)hipGraphExecDestroy(*g);
       *g = nullptr;
     }
   return SWE_NH_OK;
@@ -984,9 +981,9 @@ int swe_nh_time_stage(swe_nh_ctx* c, int32_t stage, int32_t nreps, double* h, do
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  hipGraphExecDestroy(gx);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(gx);
   if (e != hipSuccess) return fail(c, SWE_NH_EHIP, std::string("time_stage: ") + hipGetErrorString(e));
   *avg_us_host = 1000.0 * ms / (double(nlaunch) * batch);
   return after_launch(c);
