@@ -47,7 +47,18 @@ design notes):
   * hw corrected with Eq. 11 after eliminating (h p)_x through Eq. 10:
     P_b = 3 p / 2 - rho d_x (hu - hu~) / (4 dt) + (4 + d_x^2) phi / 4, node by
     node.
-  * Global model only (every element non-hydrostatic), as in Sec. 4.
+  * The adaptive model (Sec. 5) on elements: an element is non-hydrostatic
+    when the criterion exceeds k_nh at one of its two nodes (strictly), the
+    derivative criteria taking the element's P1 slope; the set is widened by
+    e elements on each side (Sec. 5.2); |w| and |w_x| may treat the first
+    step as global (Sec. 5.1.2, for initial data at rest; off for the
+    solitary wave, whose initial w is not zero).  The LDG system is the global one's rows of the
+    marked elements' node unknowns with the others fixed at the zero
+    non-hydrostatic state, p = 0 and hu = hu~ (the zero Dirichlet condition
+    of Sec. 5.2): across a face into an unmarked element the alternating
+    flux takes p from the right (0 at a segment's right end) and hu from the
+    left (hu~ at its left end).  Unmarked elements keep the predictor's
+    state.  Every element marked is the global model exactly.
 """
 from __future__ import annotations
 
@@ -259,3 +270,89 @@ def run(Q, d_static, body, t0, dt, nsteps, dx, g=G, rho=RHO):
         Q, p = step(Q, d_static, body, t, dt, dx, g, rho)
         t += dt
     return Q, p, t
+
+
+# criteria of Sec. 5.1 (the same numbering as the finite-volume oracle)
+CRIT_ETA_D, CRIT_ETA_X, CRIT_U, CRIT_U_X, CRIT_W, CRIT_W_X, CRIT_GLOBAL, CRIT_NONE = range(8)
+
+
+def element_indicator(Qt, d_static, body, t1, dx, crit):
+    """per element the criterion of Sec. 5.1 on the predictor state: the
+    larger of its two node values (|eta/d|, |u|, |w|), or the magnitude of
+    the element's P1 slope (|eta_x|, |u_x|, |w_x|)"""
+    n = Qt.shape[1]
+    d = bottom(d_static, body, node_x(n, dx), t1)[0]
+    h, m, k = Qt
+    if crit == CRIT_ETA_D:
+        return np.abs((h - d) / d).max(axis=1)
+    if crit == CRIT_U:
+        return np.abs(m / h).max(axis=1)
+    if crit == CRIT_W:
+        return np.abs(k / h).max(axis=1)
+    f = {CRIT_ETA_X: h - d, CRIT_U_X: m / h, CRIT_W_X: k / h}[crit]
+    return np.abs((f[:, 1] - f[:, 0]) / dx)
+
+
+def element_mask(Qt, d_static, body, t1, dx, crit, k_nh, enlarge, first_step, first_global=True):
+    """non-hydrostatic elements (bool [n]): criterion > k_nh, widened by
+    enlarge elements on each side"""
+    n = Qt.shape[1]
+    if crit == CRIT_GLOBAL or (crit in (CRIT_W, CRIT_W_X) and first_step and first_global):
+        return np.ones(n, dtype=bool)
+    if crit == CRIT_NONE:
+        return np.zeros(n, dtype=bool)
+    raw = element_indicator(Qt, d_static, body, t1, dx, crit) > k_nh
+    out = raw.copy()
+    for e in range(1, enlarge + 1):
+        out[e:] |= raw[:-e]
+        out[:-e] |= raw[e:]
+    return out
+
+
+def ldg_solve_masked(c, q_tilde, mask, dx):
+    """(p, q) node values [n, 2]: the LDG system on the marked elements with
+    p = 0 and q = q_tilde on the others"""
+    n = mask.shape[0]
+    A = ldg_matrix(c["s11"], c["s12"], c["s21"], c["s22"], dx).tocsr()
+    b = ldg_rhs(c["f1"], c["f2"], dx)
+    node = np.repeat(mask, 2)
+    inner = np.concatenate([node, node])
+    z = np.concatenate([np.zeros(2 * n), q_tilde.ravel()])
+    if inner.any():
+        I = np.flatnonzero(inner)
+        E = np.flatnonzero(~inner)
+        rhs = b[I] - A[I][:, E] @ z[E]
+        z[I] = spla.spsolve(A[I][:, I].tocsc(), rhs)
+    return z[:2 * n].reshape(n, 2), z[2 * n:].reshape(n, 2)
+
+
+def step_adaptive(Q, d_static, body, t, dt, dx, crit, k_nh=1e-3, enlarge=0, first_step=False,
+                  first_global=True, g=G, rho=RHO):
+    """one step of the adaptive model: predictor, element mask, LDG solve on
+    the marked elements, correction there.  Returns (Q^{n+1}, p, mask)"""
+    Qt = predict(Q, d_static, body, t, dt, dx, g)
+    mask = element_mask(Qt, d_static, body, t + dt, dx, crit, k_nh, enlarge, first_step,
+                        first_global)
+    if not mask.any():
+        return Qt, np.zeros(Qt.shape[1:]), mask
+    c = nh_coefficients(Qt, d_static, body, t + dt, dt, dx, g, rho)
+    p, q = ldg_solve_masked(c, Qt[1], mask, dx)
+    Pb = 1.5 * p - rho * c["d_x"] * (q - Qt[1]) / (4.0 * dt) + c["al"] * c["phi"] / 4.0
+    Qn = np.stack([Qt[0], q, Qt[2] + dt / rho * Pb])
+    Qn[:, ~mask] = Qt[:, ~mask]
+    return Qn, p, mask
+
+
+def run_adaptive(Q, d_static, body, t0, dt, nsteps, dx, crit, k_nh=1e-3, enlarge=0,
+                 first_global=True, g=G, rho=RHO):
+    """nsteps adaptive steps; returns (Q, p, t, marked elements per step)"""
+    t = t0
+    p = np.zeros(Q.shape[1:])
+    counts = []
+    for s in range(nsteps):
+        Q, p, mask = step_adaptive(Q, d_static, body, t, dt, dx, crit, k_nh, enlarge, s == 0,
+                                   first_global, g, rho)
+        counts.append(int(mask.sum()))
+        t += dt
+    return Q, p, t, counts
+
