@@ -341,7 +341,7 @@ int swe_nh_set_warm_start_net(swe_nh_ctx* ctx, const float* params, const double
 int swe_nh_time_stage(swe_nh_ctx* ctx, int32_t stage, int32_t nreps, double* h, double* hu,
                       double* hv, double* hw, double* p, double* avg_us_host);
 
-/* ---- The paper's own 1D discretisation (global model, one channel) ----
+/* ---- The paper's own 1D discretisation (one channel; global or adaptive) ----
  * Sec. 3.1 Eqs. 6-9: RKDG with nodal P1 elements (consistent mass, element
  * integrals of the flux and of the bed source g h d_x by three-point Gauss
  * quadrature, Rusanov flux at the faces, mirror states at the walls, Heun
@@ -359,14 +359,33 @@ typedef struct {
   double g, rho;
   double d_static;     /* flat static depth (m), > 0 */
   swe_nh_body body;    /* moving bottom (kind SWE_NH_BODY_NONE: flat bottom) */
+  /* The adaptive model (Sec. 5) on elements.  adaptive = 0 (a zeroed tail):
+   * the global model, the fields below ignored.  adaptive = 1: an element is
+   * non-hydrostatic when the criterion crit (SWE_NH_CRIT_*) on the
+   * predictor's node values exceeds k_nh at one of its two nodes (strictly;
+   * |eta/d|, |u| = |hu / h|, |w| = |hw / h|), the derivative criteria taking
+   * the magnitude of the element's P1 slope; the set is widened by enlarge
+   * elements on each side (Sec. 5.2, 0 .. SWE_NH_DG_MAX_ENLARGE).  With
+   * first_global, |w| and |w_x| mark every element in the first step of the
+   * call (Sec. 5.1.2, for water initially at rest).  The LDG system is solved
+   * on the marked elements with the other elements' unknowns fixed at p = 0
+   * and hu = hu~ (the zero Dirichlet condition of the non-hydrostatic part,
+   * Sec. 5); the unmarked elements keep the predictor's state and p = 0.
+   * marked: optional (NULL) device int32 [nsteps], the number of marked
+   * elements of each step. */
+  int32_t adaptive, crit, enlarge, first_global;
+  double k_nh;
+  int32_t* marked;
 } swe_nh_dg1d_config;
+#define SWE_NH_DG_MAX_ENLARGE 64
 
 /* Advance nsteps steps of dt from time t0 in one launch on stream (one
  * workgroup holds the channel).  h, hu, hw: device [n][2] node values,
  * element-major (node j of element i at 2 i + j), Q^n on entry and Q^{n+1}
  * on return; p: device [n][2], receives the NH pressure of the last step;
  * status: a device int32 the call uses as scratch.  Synchronises the stream.
- * Returns SWE_NH_EINVAL (bad sizes or null pointers), SWE_NH_EDRY (a node
+ * Returns SWE_NH_EINVAL (bad sizes, criterion or enlargement, or null
+ * pointers), SWE_NH_EDRY (a node
  * depth <= 0 entered a predictor stage), SWE_NH_ENAN (non-finite result) or
  * SWE_NH_EHIP. */
 int swe_nh_dg1d_run(const swe_nh_dg1d_config* cfg, double t0, int32_t nsteps, double* h,

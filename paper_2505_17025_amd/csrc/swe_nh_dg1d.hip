@@ -3,7 +3,8 @@
 // for the hydrostatic predictor (Sec. 3.1, Eqs. 6-9), the local DG (LDG) P1
 // solution of the elliptic system of Eqs. 14-15 with the alternating
 // ("flip-flop") flux of Eqs. 16-17 (Sec. 3.2), and the correction of
-// Eqs. 10-11; global model (every element non-hydrostatic), reflective walls.
+// Eqs. 10-11; the global model or the adaptive one of Sec. 5 on elements,
+// reflective walls.
 //
 // The paper's setups have a few hundred elements, so one workgroup holds a
 // whole channel: thread i owns element i (its node values in registers;
@@ -33,6 +34,13 @@
 // (q1_{k-1}, p0_k) at the n - 1 interior faces then satisfy a block
 // tridiagonal system with 2 x 2 blocks, solved by parallel cyclic reduction
 // in LDS, and each element recovers its four unknowns.
+//
+// Adaptive model: an element outside the non-hydrostatic set publishes its
+// fixed values instead of a solved block (q1 = hu~ at its right node, p0 = 0
+// at its left node, no couplings), so the interface system carries them as
+// identity rows and a marked neighbour's rows see exactly the zero Dirichlet
+// datum of the restricted system; the element then keeps the predictor's
+// state.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -52,6 +60,9 @@ struct DgArgs {
   Chan body;
   double *h, *hu, *hw, *p;
   int* status;
+  int adaptive, crit, enlarge, first_global;
+  double k_nh;
+  int* marked;
 };
 
 template <int NTD>
@@ -69,6 +80,7 @@ struct DgSmem {
     } r;
   } u;
   int status;
+  unsigned char raw[NTD];  // criterion exceeded (adaptive model)
 };
 
 __device__ __forceinline__ void phys_flux(double g, double h, double m, double k, double (&F)[3]) {
@@ -211,7 +223,57 @@ __device__ __forceinline__ void mul2(const double (&a)[4], const double (&b)[4],
   r[3] = a[2] * b[1] + a[3] * b[3];
 }
 
+// the element's criterion of Sec. 5.1 on the predictor's node values: the
+// larger node value of |eta/d|, |u| or |w|, or the magnitude of the P1 slope
+// of eta, u or w; d0, d1 the depths at the nodes at t^{n+1}
+__device__ __forceinline__ double element_indicator(int crit, const double (&Qt)[3][2], double d0,
+                                                    double d1, double dx) {
+  const double h0 = Qt[0][0], h1 = Qt[0][1];
+  switch (crit) {
+    case SWE_NH_CRIT_ETA_D:
+      return fmax(fabs((h0 - d0) / d0), fabs((h1 - d1) / d1));
+    case SWE_NH_CRIT_U:
+      return fmax(fabs(Qt[1][0] / h0), fabs(Qt[1][1] / h1));
+    case SWE_NH_CRIT_W:
+      return fmax(fabs(Qt[2][0] / h0), fabs(Qt[2][1] / h1));
+    case SWE_NH_CRIT_ETA_X:
+      return fabs(((h1 - d1) - (h0 - d0)) / dx);
+    case SWE_NH_CRIT_U_X:
+      return fabs((Qt[1][1] / h1 - Qt[1][0] / h0) / dx);
+    default:  // SWE_NH_CRIT_W_X
+      return fabs((Qt[2][1] / h1 - Qt[2][0] / h0) / dx);
+  }
+}
+
+// whether element i is non-hydrostatic in this step (all threads call: the
+// barriers are the workgroup's); thread 0 records the count
 template <int NTD>
+__device__ bool element_marked(DgSmem<NTD>& S, const DgArgs& A, int i, bool on, int step,
+                               const double (&Qt)[3][2], double d0, double d1) {
+  const int crit = A.crit;
+  bool nh;
+  if (crit == SWE_NH_CRIT_GLOBAL ||
+      (A.first_global && step == 0 && (crit == SWE_NH_CRIT_W || crit == SWE_NH_CRIT_W_X))) {
+    nh = on;
+  } else if (crit == SWE_NH_CRIT_NONE) {
+    nh = false;
+  } else {
+    if (on) S.raw[i] = element_indicator(crit, Qt, d0, d1, A.dx) > A.k_nh;
+    __syncthreads();
+    nh = false;
+    if (on) {
+      const int lo = max(0, i - A.enlarge), hi = min(A.n - 1, i + A.enlarge);
+      for (int k = lo; k <= hi; k++) nh = nh || S.raw[k];
+    }
+    __syncthreads();  // raw is rewritten in the next step
+  }
+  const int cnt = __syncthreads_count(nh);
+  if (i == 0 && A.marked) A.marked[step] = cnt;
+  return nh;
+}
+
+// ADAPT: the adaptive model (the global model's kernel carries none of it)
+template <int NTD, bool ADAPT>
 __global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
   __shared__ DgSmem<NTD> S;
   const int i = threadIdx.x, n = A.n;
@@ -289,7 +351,17 @@ __global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
     }
     if (i > 0) rh[2][1] = 1.0;      // the row of q0 holds - q1_{i-1}
     if (i + 1 < n) rh[1][2] = -1.0;  // the row of p1 holds + p0_{i+1}
-    if (on) solve4(Bm, rh);
+    const bool nh = ADAPT ? element_marked(S, A, i, on, step, Qt, b10.d, b11.d) : on;
+    if (on && nh) {
+      solve4(Bm, rh);
+    } else if (ADAPT) {
+      // fixed unknowns: p = 0, q = hu~ (no couplings)
+      for (int r = 0; r < 4; r++) {
+        rh[r][0] = r < 2 ? 0.0 : Qt[1][r - 2];
+        rh[r][1] = 0.0;
+        rh[r][2] = 0.0;
+      }
+    }
     // u = g + a q1_{i-1} + b p0_{i+1}; the interface rows need the q1
     // components of the left neighbour
     if (on) {
@@ -394,15 +466,17 @@ __global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
     double U[4];
     for (int r = 0; r < 4; r++) U[r] = rh[r][0] + rh[r][1] * ql + rh[r][2] * pr;
     __syncthreads();
-    // ---- correction (Eqs. 10-11): hu = q, hw from the bottom pressure ----
+    // ---- correction (Eqs. 10-11): hu = q, hw from the bottom pressure;
+    // the hydrostatic elements keep the predictor's state ----
     for (int k = 0; k < 2; k++) {
       const double pk = U[k], qk = U[2 + k];
       const double Pb = 1.5 * pk - rho * bn[k].dx_ * (qk - Qt[1][k]) / (4.0 * dt) +
                         al[k] * phi[k] / 4.0;
+      const bool keep = ADAPT && !nh;
       Q[0][k] = Qt[0][k];
-      Q[1][k] = qk;
-      Q[2][k] = Qt[2][k] + dt / rho * Pb;
-      P[k] = pk;
+      Q[1][k] = keep ? Qt[1][k] : qk;
+      Q[2][k] = keep ? Qt[2][k] : Qt[2][k] + dt / rho * Pb;
+      P[k] = keep ? 0.0 : pk;
     }
   }
   if (on) {
@@ -431,6 +505,9 @@ extern "C" int swe_nh_dg1d_run(const swe_nh_dg1d_config* c, double t0, int32_t n
       c->n > SWE_NH_DG_MAX_ELEMS || !(c->dx > 0.0) || !(c->dt > 0.0) || !(c->g > 0.0) ||
       !(c->rho > 0.0) || !(c->d_static > 0.0))
     return SWE_NH_EINVAL;
+  if (c->adaptive && (c->crit < SWE_NH_CRIT_ETA_D || c->crit > SWE_NH_CRIT_NONE ||
+                      c->enlarge < 0 || c->enlarge > SWE_NH_DG_MAX_ENLARGE || !(c->k_nh >= 0.0)))
+    return SWE_NH_EINVAL;
   if (nsteps == 0) return SWE_NH_OK;
   DgArgs A;
   A.n = c->n;
@@ -458,12 +535,21 @@ extern "C" int swe_nh_dg1d_run(const swe_nh_dg1d_config* c, double t0, int32_t n
   A.hw = hw;
   A.p = p;
   A.status = status;
+  A.adaptive = c->adaptive ? 1 : 0;
+  A.crit = c->crit;
+  A.enlarge = c->enlarge;
+  A.first_global = c->first_global;
+  A.k_nh = c->k_nh;
+  A.marked = c->adaptive ? c->marked : nullptr;
   hipStream_t s = (hipStream_t)stream;
-  if (c->n <= NTD_SMALL)
-    hipLaunchKernelGGL(k_dg1d_run<NTD_SMALL>, dim3(1), dim3(NTD_SMALL), 0, s, A);
+  const bool small = c->n <= NTD_SMALL;
+  void (*kern)(DgArgs);
+  if (small)
+    kern = A.adaptive ? k_dg1d_run<NTD_SMALL, true> : k_dg1d_run<NTD_SMALL, false>;
   else
-    hipLaunchKernelGGL(k_dg1d_run<SWE_NH_DG_MAX_ELEMS>, dim3(1), dim3(SWE_NH_DG_MAX_ELEMS), 0, s,
-                       A);
+    kern = A.adaptive ? k_dg1d_run<SWE_NH_DG_MAX_ELEMS, true>
+                      : k_dg1d_run<SWE_NH_DG_MAX_ELEMS, false>;
+  hipLaunchKernelGGL(kern, dim3(1), dim3(small ? NTD_SMALL : SWE_NH_DG_MAX_ELEMS), 0, s, A);
   if (hipGetLastError() != hipSuccess) return SWE_NH_EHIP;
   int bits = 0;
   if (hipMemcpyAsync(&bits, status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -42,7 +42,10 @@ class swe_nh_config(C.Structure):
 
 class swe_nh_dg1d_config(C.Structure):
     _fields_ = [("n", C.c_int32), ("dx", C.c_double), ("dt", C.c_double), ("g", C.c_double),
-                ("rho", C.c_double), ("d_static", C.c_double), ("body", swe_nh_body)]
+                ("rho", C.c_double), ("d_static", C.c_double), ("body", swe_nh_body),
+                ("adaptive", C.c_int32), ("crit", C.c_int32), ("enlarge", C.c_int32),
+                ("first_global", C.c_int32), ("k_nh", C.c_double),
+                ("marked", C.POINTER(C.c_int32))]
 
 
 class swe_nh_stats(C.Structure):
@@ -118,6 +121,7 @@ EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_l
             "swe_nh_dg1d_run"]
 NOALLOC_MAX_PIXELS = 131072
 DG_MAX_ELEMS = 1024
+DG_MAX_ENLARGE = 64
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -300,12 +304,22 @@ def cnn_forward_noalloc(params, x, n, h, w, out):
                                               _ptr(out), C.c_void_p(stream)))
 
 
-def dg1d_run(n, dx, dt, d_static, body, t0, nsteps, h, hu, hw, p, status, g=9.81, rho=1000.0):
+def dg1d_run(n, dx, dt, d_static, body, t0, nsteps, h, hu, hw, p, status, g=9.81, rho=1000.0,
+             crit=None, k_nh=1e-3, enlarge=0, first_global=False, marked=None):
     """swe_nh_dg1d_run on the current stream: h, hu, hw, p device [n, 2]
-    (FP64), status a device int32 scratch word; returns the status code"""
+    (FP64), status a device int32 scratch word; crit None: the global model,
+    else the adaptive model with that criterion (marked: optional device
+    int32 [nsteps] of per-step counts); returns the status code"""
     cfg = swe_nh_dg1d_config()
     cfg.n, cfg.dx, cfg.dt, cfg.g, cfg.rho, cfg.d_static = int(n), dx, dt, g, rho, d_static
     cfg.body = body_struct(body)
+    if crit is not None:
+        cfg.adaptive, cfg.crit, cfg.enlarge = 1, int(crit), int(enlarge)
+        cfg.first_global, cfg.k_nh = int(bool(first_global)), float(k_nh)
+        if marked is not None:
+            if marked.dtype != torch.int32 or marked.numel() < int(nsteps):
+                raise ValueError("marked must be a device int32 tensor of at least nsteps")
+            cfg.marked = C.cast(_ptr(marked), C.POINTER(C.c_int32))
     stream = torch.cuda.current_stream(h.device).cuda_stream
     return int(LIB.swe_nh_dg1d_run(C.byref(cfg), float(t0), int(nsteps), _ptr(h), _ptr(hu),
                                    _ptr(hw), _ptr(p), _ptr(status), C.c_void_p(stream)))

@@ -43,3 +43,29 @@ def test_workspace_query_rejects_bad_config():
     cfg = B.swe_nh_config()
     cfg.dim = 3
     assert B.LIB.swe_nh_workspace_bytes(ctypes.byref(cfg)) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_binding_structures_match_the_header_layout(tmp_path):
+    """every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct of the same name"""
+    import subprocess
+    from paper_2505_17025_amd import swe_nh as B
+    structs = [B.swe_nh_body, B.swe_nh_config, B.swe_nh_dg1d_config, B.swe_nh_stats]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "swe_nh.h"', "int main(void) {"]
+    want = []
+    for T in structs:
+        lines.append(f'  printf("%zu\\n", sizeof({T.__name__}));')
+        want.append(ctypes.sizeof(T))
+        for name, *_ in T._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({T.__name__}, {name}));')
+            want.append(getattr(T, name).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want
