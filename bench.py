@@ -748,6 +748,37 @@ def run_dg1d(B, torch, S, reps):
                   "paper": dict(zip(tab["columns"], tab[key][cname]))}
             adaptive.append(ar)
             log(json.dumps(ar))
+    # batches of independent solitary channels (one workgroup each): the
+    # paper's setup, 200 elements at dx = 4 m, dt = 0.1 s, amplitudes drawn
+    # in [0.5, 2] m, half of the channels adaptive (|eta/d|, enlargement 1)
+    batch = []
+    rng = np.random.default_rng(2505)
+    for nch in (256, 512, 2048):
+        amps = rng.uniform(0.5, 2.0, size=nch)
+        Qs = [S.dg_solitary_state(n, dx, float(am), d, st["x0_over_L"] * L) for am in amps]
+        cat = lambda k: f(np.concatenate([q[k] for q in Qs]))
+        cfgs = [B.dg1d_config(n, dx, dt, d, S.Body(),
+                              **(dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1) if c % 2 else {}))
+                for c in range(nch)]
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        times = []
+        for r in range(reps + 1):
+            h, hu, hw = cat(0), cat(1), cat(2)
+            p = torch.zeros_like(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc = B.dg1d_run_batch(cfgs, 0.0, nsteps, h, hu, hw, p, status)
+            el = time.perf_counter() - t0
+            if rc != B.OK:
+                raise RuntimeError(f"dg1d batch {nch}: status {rc}")
+            if r > 0:
+                times.append(el)
+        g_s = float(np.median(times))
+        br = {"channels": nch, "elements_per_channel": n, "steps": nsteps,
+              "gpu_ms_per_launch": 1e3 * g_s, "us_per_step": 1e6 * g_s / nsteps,
+              "element_steps_per_s": nch * n * nsteps / g_s}
+        batch.append(br)
+        log(json.dumps(br))
     return {"metric": METRIC, "value": tot_es / tot_s, "unit": "element-steps/s", "n_gpus": 1,
             "steps": reps, "warmup": 1,
             "ms_per_step": 1e3 * tot_s / sum(r["steps"] for r in rows),
@@ -762,7 +793,7 @@ def run_dg1d(B, torch, S, reps):
             "roofline": None,
             "cpu_baseline": {"value": tot_es / cpu_s, "unit": "element-steps/s", "cores": 1,
                              "kind": "oracle", "sample": "the same two runs, once each"},
-            "extra": {"setups": rows, "adaptive_solitary": adaptive,
+            "extra": {"setups": rows, "adaptive_solitary": adaptive, "batches": batch,
                       "note": "a few hundred elements fill one workgroup of one compute unit: "
                               "the run is bound by the workgroup's barrier latency (27-29 "
                               "barriers per step, 16-18 of them in the interface system's "

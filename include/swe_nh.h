@@ -391,6 +391,23 @@ typedef struct {
 int swe_nh_dg1d_run(const swe_nh_dg1d_config* cfg, double t0, int32_t nsteps, double* h,
                     double* hu, double* hw, double* p, int32_t* status, void* stream);
 
+/* A batch of independent channels in one launch, one workgroup per channel
+ * (the same discretisation and arithmetic as swe_nh_dg1d_run, each channel
+ * with its own config, global or adaptive).  cfgs: host array [nch],
+ * 1 <= nch <= SWE_NH_DG_MAX_BATCH.  h, hu, hw, p: device arrays of all
+ * channels' node values packed in channel order, element-major: channel c's
+ * element i node j at 2 (E_c + i) + j with E_c the elements of the channels
+ * before c.  Every channel advances nsteps steps of its own dt from t0.
+ * status: a device int32 scratch word, the OR of every channel's status.
+ * Allocates and frees a small device argument table (nch entries of about
+ * 200 bytes), synchronises the stream.  Returns SWE_NH_EINVAL (any config
+ * invalid, bad nch, null pointers), SWE_NH_EDRY or SWE_NH_ENAN (for any
+ * channel), or SWE_NH_EHIP. */
+#define SWE_NH_DG_MAX_BATCH 65536
+int swe_nh_dg1d_run_batch(const swe_nh_dg1d_config* cfgs, int32_t nch, double t0, int32_t nsteps,
+                          double* h, double* hu, double* hw, double* p, int32_t* status,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,10 +8,11 @@
 //
 // The paper's setups have a few hundred elements, so one workgroup holds a
 // whole channel: thread i owns element i (its node values in registers;
-// channels of at most 512 elements run on 512 threads, whose register budget
-// holds nearly the whole step), neighbours' values pass through LDS, and a
-// launch runs many steps with nothing but workgroup barriers between the
-// phases.
+// channels of at most 256 or 512 elements run on 256 or 512 threads, whose
+// register budget holds nearly the whole step), neighbours' values pass
+// through LDS, and a launch runs many steps with nothing but workgroup
+// barriers between the phases.  A batch of independent channels runs one
+// workgroup per channel, which is how the method fills the chip.
 //
 // Discretisation (as the FP64 reference of the same method):
 //   * nodal Lagrange P1 on [i dx, (i + 1) dx], nodes at the element ends;
@@ -44,6 +45,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "swe_nh.h"
 #include "swe_nh_common.h"
 
@@ -53,6 +56,9 @@ namespace {
 // threads of the workgroup, one per element: 512 (no register spills) or
 // SWE_NH_DG_MAX_ELEMS
 constexpr int NTD_SMALL = 512;
+// channels of at most 256 elements: two such workgroups fit on a compute unit
+// where one of 512 threads (8 wavefronts of 256 VGPRs) fills it
+constexpr int NTD_TINY = 256;
 
 struct DgArgs {
   int n, nsteps;
@@ -272,10 +278,10 @@ __device__ bool element_marked(DgSmem<NTD>& S, const DgArgs& A, int i, bool on, 
   return nh;
 }
 
-// ADAPT: the adaptive model (the global model's kernel carries none of it)
+// a whole run of one channel on this workgroup; ADAPT: the adaptive model
+// (the global model's kernel carries none of it)
 template <int NTD, bool ADAPT>
-__global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
-  __shared__ DgSmem<NTD> S;
+__device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
   const int i = threadIdx.x, n = A.n;
   const bool on = i < n;
   const double dx = A.dx, dt = A.dt, g = A.g, rho = A.rho;
@@ -491,7 +497,25 @@ __global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
     }
   }
   __syncthreads();
-  if (i == 0) *A.status = S.status;
+  if (i == 0 && S.status) atomicOr(A.status, S.status);
+}
+
+// two wavefronts per SIMD at least: a 256-thread workgroup gets the same
+// register budget as the 512-thread one, so that two share a compute unit
+constexpr int dg_min_waves(int ntd) { return ntd / 256 > 2 ? ntd / 256 : 2; }
+
+template <int NTD, bool ADAPT>
+__global__ void __launch_bounds__(NTD, dg_min_waves(NTD)) k_dg1d_run(DgArgs A) {
+  __shared__ DgSmem<NTD> S;
+  dg1d_channel<NTD, ADAPT>(S, A);
+}
+
+// one workgroup per channel of a batch
+template <int NTD, bool ADAPT>
+__global__ void __launch_bounds__(NTD, dg_min_waves(NTD)) k_dg1d_batch(const DgArgs* __restrict__ As) {
+  __shared__ DgSmem<NTD> S;
+  const DgArgs A = As[blockIdx.x];
+  dg1d_channel<NTD, ADAPT>(S, A);
 }
 
 }  // namespace
@@ -499,16 +523,21 @@ __global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
 
 using namespace swenh;
 
-extern "C" int swe_nh_dg1d_run(const swe_nh_dg1d_config* c, double t0, int32_t nsteps, double* h,
-                               double* hu, double* hw, double* p, int32_t* status, void* stream) {
-  if (!c || !h || !hu || !hw || !p || !status || nsteps < 0 || c->n < 1 ||
-      c->n > SWE_NH_DG_MAX_ELEMS || !(c->dx > 0.0) || !(c->dt > 0.0) || !(c->g > 0.0) ||
-      !(c->rho > 0.0) || !(c->d_static > 0.0))
-    return SWE_NH_EINVAL;
-  if (c->adaptive && (c->crit < SWE_NH_CRIT_ETA_D || c->crit > SWE_NH_CRIT_NONE ||
-                      c->enlarge < 0 || c->enlarge > SWE_NH_DG_MAX_ENLARGE || !(c->k_nh >= 0.0)))
-    return SWE_NH_EINVAL;
-  if (nsteps == 0) return SWE_NH_OK;
+namespace {
+bool dg_config_ok(const swe_nh_dg1d_config* c) {
+  if (!c || c->n < 1 || c->n > SWE_NH_DG_MAX_ELEMS || !(c->dx > 0.0) || !(c->dt > 0.0) ||
+      !(c->g > 0.0) || !(c->rho > 0.0) || !(c->d_static > 0.0))
+    return false;
+  return !c->adaptive || (c->crit >= SWE_NH_CRIT_ETA_D && c->crit <= SWE_NH_CRIT_NONE &&
+                          c->enlarge >= 0 && c->enlarge <= SWE_NH_DG_MAX_ENLARGE &&
+                          c->k_nh >= 0.0);
+}
+
+// the kernel arguments of one channel whose node values start at h, hu, hw, p;
+// in a kernel with the adaptive model, a channel of the global model takes
+// the criterion that marks every element
+DgArgs dg_args(const swe_nh_dg1d_config* c, double t0, int nsteps, double* h, double* hu,
+               double* hw, double* p, int32_t* status) {
   DgArgs A;
   A.n = c->n;
   A.nsteps = nsteps;
@@ -536,21 +565,21 @@ extern "C" int swe_nh_dg1d_run(const swe_nh_dg1d_config* c, double t0, int32_t n
   A.p = p;
   A.status = status;
   A.adaptive = c->adaptive ? 1 : 0;
-  A.crit = c->crit;
-  A.enlarge = c->enlarge;
-  A.first_global = c->first_global;
-  A.k_nh = c->k_nh;
+  A.crit = c->adaptive ? c->crit : SWE_NH_CRIT_GLOBAL;
+  A.enlarge = c->adaptive ? c->enlarge : 0;
+  A.first_global = c->adaptive ? c->first_global : 0;
+  A.k_nh = c->adaptive ? c->k_nh : 0.0;
   A.marked = c->adaptive ? c->marked : nullptr;
-  hipStream_t s = (hipStream_t)stream;
-  const bool small = c->n <= NTD_SMALL;
-  void (*kern)(DgArgs);
-  if (small)
-    kern = A.adaptive ? k_dg1d_run<NTD_SMALL, true> : k_dg1d_run<NTD_SMALL, false>;
-  else
-    kern = A.adaptive ? k_dg1d_run<SWE_NH_DG_MAX_ELEMS, true>
-                      : k_dg1d_run<SWE_NH_DG_MAX_ELEMS, false>;
-  hipLaunchKernelGGL(kern, dim3(1), dim3(small ? NTD_SMALL : SWE_NH_DG_MAX_ELEMS), 0, s, A);
-  if (hipGetLastError() != hipSuccess) return SWE_NH_EHIP;
+  return A;
+}
+
+// threads of the workgroup that runs channels of at most n elements
+int dg_threads(int n) {
+  return n <= NTD_TINY ? NTD_TINY : (n <= NTD_SMALL ? NTD_SMALL : SWE_NH_DG_MAX_ELEMS);
+}
+
+// waits for the stream and maps the status bits
+int dg_finish(int32_t* status, hipStream_t s) {
   int bits = 0;
   if (hipMemcpyAsync(&bits, status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -558,4 +587,74 @@ extern "C" int swe_nh_dg1d_run(const swe_nh_dg1d_config* c, double t0, int32_t n
   if (bits & ST_DRY) return SWE_NH_EDRY;  // a dry node also makes the values non-finite
   if (bits & ST_NAN) return SWE_NH_ENAN;
   return SWE_NH_OK;
+}
+}  // namespace
+
+extern "C" int swe_nh_dg1d_run(const swe_nh_dg1d_config* c, double t0, int32_t nsteps, double* h,
+                               double* hu, double* hw, double* p, int32_t* status, void* stream) {
+  if (!dg_config_ok(c) || !h || !hu || !hw || !p || !status || nsteps < 0) return SWE_NH_EINVAL;
+  if (nsteps == 0) return SWE_NH_OK;
+  const DgArgs A = dg_args(c, t0, nsteps, h, hu, hw, p, status);
+  hipStream_t s = (hipStream_t)stream;
+  const int nt = dg_threads(c->n);
+  void (*kern)(DgArgs);
+  if (nt == NTD_TINY)
+    kern = A.adaptive ? k_dg1d_run<NTD_TINY, true> : k_dg1d_run<NTD_TINY, false>;
+  else if (nt == NTD_SMALL)
+    kern = A.adaptive ? k_dg1d_run<NTD_SMALL, true> : k_dg1d_run<NTD_SMALL, false>;
+  else
+    kern = A.adaptive ? k_dg1d_run<SWE_NH_DG_MAX_ELEMS, true>
+                      : k_dg1d_run<SWE_NH_DG_MAX_ELEMS, false>;
+  if (hipMemsetAsync(status, 0, sizeof(int32_t), s) != hipSuccess) return SWE_NH_EHIP;
+  hipLaunchKernelGGL(kern, dim3(1), dim3(nt), 0, s, A);
+  if (hipGetLastError() != hipSuccess) return SWE_NH_EHIP;
+  return dg_finish(status, s);
+}
+
+extern "C" int swe_nh_dg1d_run_batch(const swe_nh_dg1d_config* cfgs, int32_t nch, double t0,
+                                     int32_t nsteps, double* h, double* hu, double* hw, double* p,
+                                     int32_t* status, void* stream) {
+  if (!cfgs || nch < 1 || nch > SWE_NH_DG_MAX_BATCH || !h || !hu || !hw || !p || !status ||
+      nsteps < 0)
+    return SWE_NH_EINVAL;
+  int nmax = 0;
+  bool adapt = false;
+  for (int c = 0; c < nch; c++) {
+    if (!dg_config_ok(&cfgs[c])) return SWE_NH_EINVAL;
+    nmax = cfgs[c].n > nmax ? cfgs[c].n : nmax;
+    adapt = adapt || cfgs[c].adaptive;
+  }
+  if (nsteps == 0) return SWE_NH_OK;
+  std::vector<DgArgs> host(nch);
+  int64_t e0 = 0;  // first element of the channel
+  for (int c = 0; c < nch; c++) {
+    const int64_t o = 2 * e0;
+    host[c] = dg_args(&cfgs[c], t0, nsteps, h + o, hu + o, hw + o, p + o, status);
+    e0 += cfgs[c].n;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  DgArgs* dev = nullptr;
+  if (hipMalloc((void**)&dev, sizeof(DgArgs) * (size_t)nch) != hipSuccess) return SWE_NH_EHIP;
+  int rc = SWE_NH_OK;
+  if (hipMemcpyAsync(dev, host.data(), sizeof(DgArgs) * (size_t)nch, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemsetAsync(status, 0, sizeof(int32_t), s) != hipSuccess) {
+    rc = SWE_NH_EHIP;
+  } else {
+    const int nt = dg_threads(nmax);
+    void (*kern)(const DgArgs*);
+    if (nt == NTD_TINY)
+      kern = adapt ? k_dg1d_batch<NTD_TINY, true> : k_dg1d_batch<NTD_TINY, false>;
+    else if (nt == NTD_SMALL)
+      kern = adapt ? k_dg1d_batch<NTD_SMALL, true> : k_dg1d_batch<NTD_SMALL, false>;
+    else
+      kern = adapt ? k_dg1d_batch<SWE_NH_DG_MAX_ELEMS, true>
+                   : k_dg1d_batch<SWE_NH_DG_MAX_ELEMS, false>;
+    hipLaunchKernelGGL(kern, dim3(nch), dim3(nt), 0, s, (const DgArgs*)dev);
+    rc = hipGetLastError() != hipSuccess ? SWE_NH_EHIP : dg_finish(status, s);
+  }
+  // the host copy is pageable: the stream has finished with both buffers
+  if (rc == SWE_NH_EHIP) (void)hipStreamSynchronize(s);
+  (void)hipFree(dev);
+  return rc;
 }

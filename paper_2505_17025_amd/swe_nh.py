@@ -100,11 +100,13 @@ def _load():
     lib.swe_nh_set_warm_start_net.argtypes = [vp, vp, C.POINTER(dbl), dbl]
     lib.swe_nh_dg1d_run.argtypes = [C.POINTER(swe_nh_dg1d_config), dbl, i32, vp, vp, vp, vp, vp,
                                     vp]
+    lib.swe_nh_dg1d_run_batch.argtypes = [C.POINTER(swe_nh_dg1d_config), i32, dbl, i32, vp, vp, vp,
+                                          vp, vp, vp]
     for name in ("swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
                  "swe_nh_cnn_mse", "swe_nh_cnn_bce", "swe_nh_cnn_adam",
                  "swe_nh_features", "swe_nh_set_warm_start_net", "swe_nh_time_stage", "swe_nh_init", "swe_nh_set_time", "swe_nh_get_time", "swe_nh_step",
                  "swe_nh_sync_stats", "swe_nh_predict", "swe_nh_mask", "swe_nh_solve_pressure",
-                 "swe_nh_correct", "swe_nh_dg1d_run"):
+                 "swe_nh_correct", "swe_nh_dg1d_run", "swe_nh_dg1d_run_batch"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -118,10 +120,11 @@ EXPORTED = ["swe_nh_workspace_bytes", "swe_nh_init", "swe_nh_destroy", "swe_nh_l
             "swe_nh_cnn_forward", "swe_nh_cnn_forward_noalloc", "swe_nh_cnn_backward",
             "swe_nh_cnn_mse", "swe_nh_cnn_bce", "swe_nh_cnn_adam", "swe_nh_features",
             "swe_nh_set_warm_start_net",
-            "swe_nh_dg1d_run"]
+            "swe_nh_dg1d_run", "swe_nh_dg1d_run_batch"]
 NOALLOC_MAX_PIXELS = 131072
 DG_MAX_ELEMS = 1024
 DG_MAX_ENLARGE = 64
+DG_MAX_BATCH = 65536
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -304,12 +307,11 @@ def cnn_forward_noalloc(params, x, n, h, w, out):
                                               _ptr(out), C.c_void_p(stream)))
 
 
-def dg1d_run(n, dx, dt, d_static, body, t0, nsteps, h, hu, hw, p, status, g=9.81, rho=1000.0,
-             crit=None, k_nh=1e-3, enlarge=0, first_global=False, marked=None):
-    """swe_nh_dg1d_run on the current stream: h, hu, hw, p device [n, 2]
-    (FP64), status a device int32 scratch word; crit None: the global model,
-    else the adaptive model with that criterion (marked: optional device
-    int32 [nsteps] of per-step counts); returns the status code"""
+def dg1d_config(n, dx, dt, d_static, body, g=9.81, rho=1000.0, crit=None, k_nh=1e-3, enlarge=0,
+                first_global=False, marked=None, nsteps=None):
+    """a swe_nh_dg1d_config: crit None is the global model, else the adaptive
+    model with that criterion (marked: optional device int32 tensor of at
+    least nsteps per-step counts)"""
     cfg = swe_nh_dg1d_config()
     cfg.n, cfg.dx, cfg.dt, cfg.g, cfg.rho, cfg.d_static = int(n), dx, dt, g, rho, d_static
     cfg.body = body_struct(body)
@@ -317,12 +319,39 @@ def dg1d_run(n, dx, dt, d_static, body, t0, nsteps, h, hu, hw, p, status, g=9.81
         cfg.adaptive, cfg.crit, cfg.enlarge = 1, int(crit), int(enlarge)
         cfg.first_global, cfg.k_nh = int(bool(first_global)), float(k_nh)
         if marked is not None:
-            if marked.dtype != torch.int32 or marked.numel() < int(nsteps):
+            if marked.dtype != torch.int32 or nsteps is None or marked.numel() < int(nsteps):
                 raise ValueError("marked must be a device int32 tensor of at least nsteps")
             cfg.marked = C.cast(_ptr(marked), C.POINTER(C.c_int32))
+    return cfg
+
+
+def dg1d_run(n, dx, dt, d_static, body, t0, nsteps, h, hu, hw, p, status, g=9.81, rho=1000.0,
+             crit=None, k_nh=1e-3, enlarge=0, first_global=False, marked=None):
+    """swe_nh_dg1d_run on the current stream: h, hu, hw, p device [n, 2]
+    (FP64), status a device int32 scratch word; crit None: the global model,
+    else the adaptive model with that criterion (marked: optional device
+    int32 [nsteps] of per-step counts); returns the status code"""
+    cfg = dg1d_config(n, dx, dt, d_static, body, g, rho, crit, k_nh, enlarge, first_global,
+                      marked, nsteps)
     stream = torch.cuda.current_stream(h.device).cuda_stream
     return int(LIB.swe_nh_dg1d_run(C.byref(cfg), float(t0), int(nsteps), _ptr(h), _ptr(hu),
                                    _ptr(hw), _ptr(p), _ptr(status), C.c_void_p(stream)))
+
+
+def dg1d_run_batch(cfgs, t0, nsteps, h, hu, hw, p, status):
+    """swe_nh_dg1d_run_batch on the current stream: cfgs a list of
+    swe_nh_dg1d_config (dg1d_config), h, hu, hw, p device FP64 tensors of all
+    channels' node values packed in channel order ([sum n, 2]); returns the
+    status code"""
+    arr = (swe_nh_dg1d_config * len(cfgs))(*cfgs)
+    tot = sum(int(c.n) for c in cfgs)
+    for t in (h, hu, hw, p):
+        if t.dtype != torch.float64 or t.numel() < 2 * tot:
+            raise ValueError("node arrays must be FP64 device tensors of 2 x total elements")
+    stream = torch.cuda.current_stream(h.device).cuda_stream
+    return int(LIB.swe_nh_dg1d_run_batch(arr, len(cfgs), float(t0), int(nsteps), _ptr(h),
+                                         _ptr(hu), _ptr(hw), _ptr(p), _ptr(status),
+                                         C.c_void_p(stream)))
 
 
 class Net:
