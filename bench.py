@@ -83,7 +83,8 @@ def pmc_traffic(kernel_file, src_files, tile=None):
         t = re.search(r"tile1d:\s*(\d+)", txt)
         if not t or int(t.group(1)) != int(tile):
             return None
-    m = re.search(r"sources_sha256:\s*([0-9a-f]+)", txt)
+    # "sources_sha256 (the files, in order): <hex>" or "sources_sha256: <hex>"
+    m = re.search(r"sources_sha256(?:\s*\([^)]*\))?:\s*([0-9a-f]{64})", txt)
     if not m or m.group(1) != sources_sha256(src_files):
         return None
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)

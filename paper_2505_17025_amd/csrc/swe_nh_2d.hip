@@ -325,6 +325,17 @@ __device__ void stage2d(P2& S, const double* d, const G2& G, int i0, int j0, dou
   }
 }
 
+// The workgroups of a launch go to the 8 XCDs in turn (workgroup b to XCD
+// b % 8), each with its own L2.  Tile of workgroup b such that every XCD
+// walks one contiguous band of the row-major tiles: the neighbours whose
+// windows overlap a tile's (the next tile along x, the tile row above) are
+// then read through the same L2.  A bijection of [0, n) for any n.
+__device__ __forceinline__ int xcd_band_tile(int b, int n) {
+  constexpr int NX = 8;
+  const int x = b % NX, k = b / NX, per = n / NX, rem = n % NX;
+  return x * per + min(x, rem) + k;
+}
+
 __global__ void __launch_bounds__(NTP) k_pred2d(G2 G, const double* __restrict__ h,
                                                 const double* __restrict__ hu,
                                                 const double* __restrict__ hv,
@@ -336,7 +347,8 @@ __global__ void __launch_bounds__(NTP) k_pred2d(G2 G, const double* __restrict__
   __shared__ P2 S;
   __shared__ int sflags;
   const Chan c = G.ch[0];
-  const int i0 = (blockIdx.x % G.tiles_x) * TX2, j0 = (blockIdx.x / G.tiles_x) * TY2;
+  const int tb = xcd_band_tile(blockIdx.x, gridDim.x);
+  const int i0 = (tb % G.tiles_x) * TX2, j0 = (tb / G.tiles_x) * TY2;
   const int wi0 = i0 - H2, wj0 = j0 - H2;
   const double t0 = t_in[0];
   double dt;
