@@ -796,8 +796,8 @@ def run_dg1d(B, torch, S, reps):
                              "kind": "oracle", "sample": "the same two runs, once each"},
             "extra": {"setups": rows, "adaptive_solitary": adaptive, "batches": batch,
                       "note": "a few hundred elements fill one workgroup of one compute unit: "
-                              "the run is bound by the workgroup's barrier latency (27-29 "
-                              "barriers per step, 16-18 of them in the interface system's "
+                              "the run is bound by the workgroup's barrier latency (19-23 "
+                              "barriers per step, 8-9 of them in the interface system's "
                               "cyclic reduction); the adaptive model solves the same interface "
                               "system with identity rows outside the marked set, so it saves "
                               "no time here (the paper's time ratios are of a CPU code whose "

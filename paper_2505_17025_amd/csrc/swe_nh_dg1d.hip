@@ -83,7 +83,7 @@ struct DgSmem {
     } c;
     struct {
       double A[4][NTD], B[4][NTD], C[4][NTD], d[2][NTD];  // interface rows, 2 x 2 row-major
-    } r;
+    } r[NTD <= 512 ? 2 : 1];  // two buffers (one barrier per reduction level) where LDS allows
   } u;
   int status;
   unsigned char raw[NTD];  // criterion exceeded (adaptive model)
@@ -392,19 +392,22 @@ __device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
       dr[1] = rh[0][0];
     }
     __syncthreads();
-    auto put = [&]() {
+    constexpr bool TWO = NTD <= 512;  // the level reads one buffer and writes the other
+    int cur = 0;
+    auto put = [&](int bf) {
       if (!row) return;
       for (int e = 0; e < 4; e++) {
-        S.u.r.A[e][j] = Ar[e];
-        S.u.r.B[e][j] = Br[e];
-        S.u.r.C[e][j] = Cr[e];
+        S.u.r[bf].A[e][j] = Ar[e];
+        S.u.r[bf].B[e][j] = Br[e];
+        S.u.r[bf].C[e][j] = Cr[e];
       }
-      S.u.r.d[0][j] = dr[0];
-      S.u.r.d[1][j] = dr[1];
+      S.u.r[bf].d[0][j] = dr[0];
+      S.u.r[bf].d[1][j] = dr[1];
     };
-    put();
+    put(0);
     __syncthreads();
     for (int s = 1; s < m; s *= 2) {
+      const auto& R = S.u.r[cur];
       double An[4], Bn[4] = {Br[0], Br[1], Br[2], Br[3]}, Cn[4], dn[2] = {dr[0], dr[1]};
       if (row) {
         double al_[4] = {0.0, 0.0, 0.0, 0.0}, ga_[4] = {0.0, 0.0, 0.0, 0.0};
@@ -412,32 +415,32 @@ __device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
         if (j - s >= 0) {
           double Bm_[4], Bi[4], Cm[4];
           for (int e = 0; e < 4; e++) {
-            Bm_[e] = S.u.r.B[e][j - s];
-            Am[e] = S.u.r.A[e][j - s];
-            Cm[e] = S.u.r.C[e][j - s];
+            Bm_[e] = R.B[e][j - s];
+            Am[e] = R.A[e][j - s];
+            Cm[e] = R.C[e][j - s];
           }
           inv2(Bm_, Bi);
           mul2(Ar, Bi, al_);
           double t[4];
           mul2(al_, Cm, t);
           for (int e = 0; e < 4; e++) Bn[e] -= t[e];
-          dn[0] -= al_[0] * S.u.r.d[0][j - s] + al_[1] * S.u.r.d[1][j - s];
-          dn[1] -= al_[2] * S.u.r.d[0][j - s] + al_[3] * S.u.r.d[1][j - s];
+          dn[0] -= al_[0] * R.d[0][j - s] + al_[1] * R.d[1][j - s];
+          dn[1] -= al_[2] * R.d[0][j - s] + al_[3] * R.d[1][j - s];
         }
         if (j + s < m) {
           double Bp[4], Bi[4], Ap[4];
           for (int e = 0; e < 4; e++) {
-            Bp[e] = S.u.r.B[e][j + s];
-            Ap[e] = S.u.r.A[e][j + s];
-            Cp[e] = S.u.r.C[e][j + s];
+            Bp[e] = R.B[e][j + s];
+            Ap[e] = R.A[e][j + s];
+            Cp[e] = R.C[e][j + s];
           }
           inv2(Bp, Bi);
           mul2(Cr, Bi, ga_);
           double t[4];
           mul2(ga_, Ap, t);
           for (int e = 0; e < 4; e++) Bn[e] -= t[e];
-          dn[0] -= ga_[0] * S.u.r.d[0][j + s] + ga_[1] * S.u.r.d[1][j + s];
-          dn[1] -= ga_[2] * S.u.r.d[0][j + s] + ga_[3] * S.u.r.d[1][j + s];
+          dn[0] -= ga_[0] * R.d[0][j + s] + ga_[1] * R.d[1][j + s];
+          dn[1] -= ga_[2] * R.d[0][j + s] + ga_[3] * R.d[1][j + s];
         }
         double t[4];
         mul2(al_, Am, t);
@@ -445,7 +448,7 @@ __device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
         mul2(ga_, Cp, t);
         for (int e = 0; e < 4; e++) Cn[e] = -t[e];
       }
-      __syncthreads();
+      if (!TWO) __syncthreads();  // one buffer: every read of this level first
       if (row) {
         for (int e = 0; e < 4; e++) {
           Ar[e] = An[e];
@@ -455,7 +458,8 @@ __device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
         dr[0] = dn[0];
         dr[1] = dn[1];
       }
-      put();
+      if (TWO) cur ^= 1;
+      put(cur);
       __syncthreads();
     }
     // every row is decoupled: (x_k, y_k) = B^-1 d, published through d
@@ -463,12 +467,12 @@ __device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
       double Bi[4];
       inv2(Br, Bi);
       const double xk = Bi[0] * dr[0] + Bi[1] * dr[1], yk = Bi[2] * dr[0] + Bi[3] * dr[1];
-      S.u.r.d[0][j] = xk;
-      S.u.r.d[1][j] = yk;
+      S.u.r[cur].d[0][j] = xk;
+      S.u.r[cur].d[1][j] = yk;
     }
     __syncthreads();
-    const double ql = (on && i >= 1) ? S.u.r.d[0][i - 1] : 0.0;     // q1_{i-1} = x_i
-    const double pr = (on && i + 1 < n) ? S.u.r.d[1][i] : 0.0;      // p0_{i+1} = y_{i+1}
+    const double ql = (on && i >= 1) ? S.u.r[cur].d[0][i - 1] : 0.0;  // q1_{i-1} = x_i
+    const double pr = (on && i + 1 < n) ? S.u.r[cur].d[1][i] : 0.0;   // p0_{i+1} = y_{i+1}
     double U[4];
     for (int r = 0; r < 4; r++) U[r] = rh[r][0] + rh[r][1] * ql + rh[r][2] * pr;
     __syncthreads();
