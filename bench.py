@@ -51,6 +51,9 @@ def parse():
                              "learned2d", "paper1d", "dg1d", "copycal"])
     ap.add_argument("--tile1d", type=int, default=0,
                     help="1D cells per tile (32..512); 0: pick with the autotuner")
+    ap.add_argument("--train-seeds", type=int, default=4,
+                    help="learned2d: runs whose snapshots train the network (15 snapshots, "
+                         "240 crops each; 4 by default, 200 for about 48k crops)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     return ap.parse_args()
@@ -592,7 +595,8 @@ def main():
     elif args.workload == "learned2d":
         steps = args.steps or 20
         warmup = args.warmup if args.warmup is not None else 30
-        print(json.dumps(run_learned(B, torch, S, steps, warmup)), flush=True)
+        print(json.dumps(run_learned(B, torch, S, steps, warmup, train_seeds=args.train_seeds)),
+              flush=True)
     elif args.workload == "shelf2d":
         steps = args.steps or 50
         warmup = args.warmup if args.warmup is not None else 40
@@ -600,17 +604,21 @@ def main():
         print(json.dumps(res), flush=True)
 
 
-def run_learned(B, torch, S, steps, warmup, n=1024, dx=4.0):
-    """learned warm start: train on the solver's own runs (seeds 17027-17030),
-    then time full steps of a held-out seed with the zero guess, the previous
-    step's pressure and the network's guess at the same tolerance"""
+def run_learned(B, torch, S, steps, warmup, n=1024, dx=4.0, train_seeds=4):
+    """learned warm start: train on the solver's own runs (seeds 17027 onwards,
+    train_seeds of them, never the held-out 17099), then time full steps of
+    the held-out seed with the zero guess, the previous step's pressure and
+    the network's guess at the same tolerance"""
     from paper_2505_17025_amd import warm_start as W
     mk = lambda s: S.warm_start_case_2d(s, n=n, dx=dx)
     t0 = time.perf_counter()
     sc = W.estimate_scales(mk(17027), 60, 20)
-    X, P, M = W.dataset([17027, 17028, 17029, 17030], sc, nsteps=150, every=10, crops_per=16,
-                        make_case=mk)
-    params, ps, losses = W.train(X, P, M, iters=2000, batch=16, lr=2e-3, log_every=200)
+    if not 1 <= train_seeds <= 400:
+        raise ValueError("--train-seeds: 1 .. 400")
+    seeds = [s for s in range(17027, 17028 + train_seeds) if s != 17099][:train_seeds]
+    X, P, M = W.dataset(seeds, sc, nsteps=150, every=10, crops_per=16, make_case=mk)
+    iters = 2000 if train_seeds <= 4 else 200 * train_seeds  # about 13 epochs beyond 4 runs
+    params, ps, losses = W.train(X, P, M, iters=iters, batch=16, lr=2e-3, log_every=iters // 10)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log("trained in", round(t_train, 1), "s on", tuple(X.shape), "losses", losses)
