@@ -168,3 +168,27 @@ def test_batch_argument_checks(B):
                             st) == B.EINVAL
     assert B.dg1d_run_batch([], 0.0, 5, h, z, z.clone(), z.clone(), st) == B.EINVAL
     assert torch.all(h == 3.0)
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_batch_of_one_is_the_single_run_bit_for_bit(B, adaptive):
+    """a batch of one channel runs the same kernel variant as the single-
+    channel call (same thread count, same model): the same bits"""
+    kw = dict(crit=S.CRIT_ETA_D, k_nh=1e-3, enlarge=1) if adaptive else {}
+    ch = channel("solitary", 200, 11) + (kw,)
+    rc, got = run_batch(B, [ch], 60)
+    assert rc == B.OK
+    Qs, ps, ms = run_single(B, ch, 60)
+    Qb, pb, mb = got[0]
+    assert np.array_equal(Qb, Qs) and np.array_equal(pb, ps) and mb == ms
+
+
+def test_batch_reports_a_dry_channel(B):
+    """a node depth <= 0 in one channel of a batch gives EDRY for the call"""
+    chans = [channel("rough", 32, 21) + ({},), channel("rough", 32, 22) + ({},),
+             channel("rough", 32, 23) + ({},)]
+    Q = chans[1][5].copy()
+    Q[0][5, 1] = -0.1
+    chans[1] = chans[1][:5] + (Q, {})
+    rc, _ = run_batch(B, chans, 2)
+    assert rc == B.EDRY
