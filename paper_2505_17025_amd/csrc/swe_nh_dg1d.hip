@@ -504,12 +504,14 @@ __device__ __forceinline__ void dg1d_channel(DgSmem<NTD>& S, const DgArgs& A) {
   if (i == 0 && S.status) atomicOr(A.status, S.status);
 }
 
-// two wavefronts per SIMD at least: a 256-thread workgroup gets the same
-// register budget as the 512-thread one, so that two share a compute unit
+// batches: two wavefronts per SIMD at least, so that two 256-thread
+// workgroups share a compute unit (the register budget of the 512-thread one)
 constexpr int dg_min_waves(int ntd) { return ntd / 256 > 2 ? ntd / 256 : 2; }
 
+// one channel per launch: the workgroup has its compute unit to itself, so
+// its registers are bounded by its own size only
 template <int NTD, bool ADAPT>
-__global__ void __launch_bounds__(NTD, dg_min_waves(NTD)) k_dg1d_run(DgArgs A) {
+__global__ void __launch_bounds__(NTD) k_dg1d_run(DgArgs A) {
   __shared__ DgSmem<NTD> S;
   dg1d_channel<NTD, ADAPT>(S, A);
 }
